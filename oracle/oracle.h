@@ -1,0 +1,125 @@
+/*
+ * FP64 CPU oracle for the MPM Lite implicit step — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The product path (the HIP library) never links,
+ * includes or calls anything here; the two share no code.
+ *
+ * Everything is plain, slow and written straight from the paper:
+ *   - particle -> cell-centre unload (Sec. 3.1, 3.2; Alg. 2),
+ *   - centre -> node gather and node -> centre sampling (Sec. 3.3),
+ *   - the rotation-free stretch reference and its reconstruction from the
+ *     resampled Kirchhoff stress (Sec. 4.2, 4.3, App. C),
+ *   - the incremental potential on the voxel hex mesh (Sec. 4.2, Alg. 3),
+ *     minimised by a projected Newton method with Jacobi-PCG,
+ *   - load back to particles (Sec. 3.1, Alg. 4).
+ *
+ * Grid convention (dense): N^3 cells, (N+1)^3 nodes, origin 0, spacing dx.
+ *   node (i,j,k)  -> index (i*(N+1)+j)*(N+1)+k,  position (i,j,k)*dx
+ *   cell (i,j,k)  -> index (i*N+j)*N+k,          centre ((i,j,k)+1/2)*dx
+ * Matrices are row-major 3x3 (9 doubles); G_ab = dv_a/dx_b.
+ * All pointers are host pointers owned by the caller.
+ * Functions return 0 on success, a negative code on error.
+ */
+#ifndef MPM_ORACLE_H
+#define MPM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_NEOHOOKEAN = 0, OR_FIXED_COROTATED = 1, OR_HENCKY = 2 };
+enum { OR_PLASTIC_NONE = 0, OR_PLASTIC_VON_MISES = 1, OR_PLASTIC_DRUCKER_PRAGER = 2 };
+enum { OR_BC_STICKY_BOX = 0, OR_BC_MOVING_BOX = 1 };
+
+enum {
+  OR_OK = 0,
+  OR_ERR_ARG = -1,
+  OR_ERR_DOMAIN = -2,        /* stress outside the invertible range of the model */
+  OR_ERR_NOT_CONVERGED = -3,
+  OR_ERR_LINESEARCH = -4,
+  OR_ERR_OUTSIDE = -5        /* a particle's stencil leaves the grid */
+};
+
+typedef struct {
+  int32_t model;     /* OR_NEOHOOKEAN, OR_FIXED_COROTATED, OR_HENCKY */
+  int32_t plastic;   /* OR_PLASTIC_* */
+  double mu, lambda;
+  double yield_stress;   /* von Mises: Kirchhoff yield stress */
+  double friction_deg;   /* Drucker-Prager friction angle (degrees) */
+} or_material;
+
+typedef struct {
+  int32_t n;   /* cells per axis */
+  double dx;
+} or_grid;
+
+typedef struct {
+  int32_t kind;              /* OR_BC_* */
+  double lo[3], hi[3];       /* box at time 0 (inclusive) */
+  double velocity[3];        /* prescribed velocity (MOVING_BOX; STICKY_BOX uses 0) */
+} or_bc;
+
+typedef struct {
+  double newton_rtol, pcg_rtol, armijo_c;
+  int32_t max_newton, max_pcg, max_ls;
+} or_solver_opts;
+
+typedef struct {
+  int32_t newton_iters, pcg_iters_total, ls_halvings;
+  double g0_norm, g_norm, energy;
+} or_solver_stats;
+
+/* ---- constitutive models (per call: one material point) ---- */
+double or_psi(const or_material* mat, const double F[9]);
+int or_piola(const or_material* mat, const double F[9], double P[9]);
+int or_tau(const or_material* mat, const double F[9], double tau[9]);
+int or_dpdf(const or_material* mat, const double F[9], double A[81]);
+int or_stretch(const or_material* mat, const double tau[9], double S[9]);
+int or_svd3(const double F[9], double U[9], double sig[3], double V[9]);
+int or_sym_eigen(int32_t n, const double* A, double* w, double* Q);
+int or_project_psd(int32_t n, double* A);
+int or_cardano_largest(double p, double q, double* m);
+int or_plastic_project(const or_material* mat, double F[9], double* eps_acc);
+
+/* ---- grid stages ---- */
+int or_unload(const or_grid* g, int64_t np, const double* x, const double* v,
+              const double* G, const double* F, const double* m, const double* V,
+              const int32_t* mat, int32_t nmat, const or_material* mats,
+              double* mc, double* vc, double* Gc, double* Vck, double* tauck,
+              double* mi, double* vi);
+int or_node_bcs(const or_grid* g, const double* mi, int32_t nbc, const or_bc* bcs,
+                double time, uint8_t* fixed, double* vfix);
+int or_reconstruct(const or_grid* g, int32_t nmat, const or_material* mats,
+                   const double* Vck, const double* tauck, double* Sck);
+int or_energy_grad(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+                   const double* mi, const double* vhat, const uint8_t* fixed,
+                   const double* Vck, const double* Sck, const double* v,
+                   double* energy, double* grad);
+int or_tangent(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+               const double* Vck, const double* Sck, const double* v, int32_t project,
+               double* Abar);
+int or_hv(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,
+          const double* Abar, const double* u, double* Hu);
+int or_explicit_force(const or_grid* g, int32_t nmat, const double* Vck,
+                      const double* tauck, double* f);
+int or_solve(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+             const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
+             const double* Vck, const double* Sck, const or_solver_opts* opts,
+             double* v, or_solver_stats* stats);
+int or_node_to_centre(const or_grid* g, const double* mc, const double* vnode,
+                      double* vc, double* Gc);
+int or_load(const or_grid* g, double dt, const double* mc, const double* vnode,
+            int64_t np, const int32_t* mat, const or_material* mats,
+            double* x, double* v, double* G, double* F, double* eps_acc);
+int or_step(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+            const double gravity[3], int32_t nbc, const or_bc* bcs, double time,
+            const or_solver_opts* opts, int64_t np, double* x, double* v, double* G,
+            double* F, const double* m, const double* V, const int32_t* mat,
+            double* eps_acc, or_solver_stats* stats, double* vnode_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

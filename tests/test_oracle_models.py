@@ -1,0 +1,268 @@
+"""Pins of the oracle's per-point routines (constitutive models, stretch
+inverses, Cardano, eigen/SVD, PSD projection, plasticity) against closed
+forms, library routines and finite differences.  CPU only."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import oracle as O
+
+MODELS = [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY]
+RNG = np.random.default_rng(1234)
+
+
+def rand_rot(rng):
+    Q, R = np.linalg.qr(rng.normal(size=(3, 3)))
+    Q = Q * np.sign(np.diag(R))
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def rand_F(rng, lo=0.7, hi=1.4):
+    return rand_rot(rng) @ np.diag(rng.uniform(lo, hi, 3)) @ rand_rot(rng).T
+
+
+def mat(model, E=1e5, nu=0.3, **kw):
+    return O.Material(model, E, nu, **kw)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_piola_is_energy_gradient(model):
+    """P(F) = d psi / dF, central differences on the energy (h = 1e-6)."""
+    m = mat(model)
+    rng = np.random.default_rng(1 + model)
+    for _ in range(5):
+        F = rand_F(rng)
+        P, rc = O.piola(m, F)
+        assert rc == 0
+        fd = np.zeros((3, 3))
+        h = 1e-6
+        for a in range(3):
+            for b in range(3):
+                E = np.zeros((3, 3))
+                E[a, b] = h
+                fd[a, b] = (O.psi(m, F + E) - O.psi(m, F - E)) / (2 * h)
+        assert np.linalg.norm(fd - P) <= 1e-7 * np.linalg.norm(P) + 1e-9
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_tangent_is_piola_derivative(model):
+    """dP/dF against central differences of P."""
+    m = mat(model)
+    rng = np.random.default_rng(10 + model)
+    for _ in range(5):
+        F = rand_F(rng)
+        A, rc = O.dpdf(m, F)
+        assert rc == 0
+        fd = np.zeros((9, 9))
+        h = 1e-6
+        for e in range(9):
+            E = np.zeros(9)
+            E[e] = h
+            Pp, _ = O.piola(m, F.reshape(9) + E)
+            Pm, _ = O.piola(m, F.reshape(9) - E)
+            fd[:, e] = (Pp - Pm).reshape(9) / (2 * h)
+        assert np.linalg.norm(fd - A) <= 1e-7 * np.linalg.norm(A)
+        # a Hessian of a scalar energy is symmetric
+        assert np.linalg.norm(A - A.T) <= 1e-10 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_tangent_near_repeated_stretches(model):
+    """Equal and nearly equal singular values keep the tangent finite and
+    equal to the finite-difference derivative."""
+    m = mat(model)
+    rng = np.random.default_rng(20 + model)
+    U, V = rand_rot(rng), rand_rot(rng)
+    for s in ([1.1, 1.1, 0.9], [1.0, 1.0, 1.0], [1.05, 1.05 + 1e-9, 0.95]):
+        F = U @ np.diag(s) @ V.T
+        A, rc = O.dpdf(m, F)
+        assert rc == 0 and np.all(np.isfinite(A))
+        fd = np.zeros((9, 9))
+        h = 1e-6
+        for e in range(9):
+            E = np.zeros(9)
+            E[e] = h
+            fd[:, e] = (O.piola(m, F.reshape(9) + E)[0] - O.piola(m, F.reshape(9) - E)[0]).reshape(9) / (2 * h)
+        assert np.linalg.norm(fd - A) <= 1e-6 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_spectral_kirchhoff_map(model):
+    """tau_i = sigma_i d psi_hat / d sigma_i (Sec. 4.3, spectral map), with
+    psi_hat differentiated numerically on diagonal F."""
+    m = mat(model)
+    rng = np.random.default_rng(30 + model)
+    for _ in range(5):
+        s = rng.uniform(0.7, 1.4, 3)
+        T, rc = O.tau(m, np.diag(s))
+        assert rc == 0
+        h = 1e-6
+        for i in range(3):
+            sp, sm = s.copy(), s.copy()
+            sp[i] += h
+            sm[i] -= h
+            dpsi = (O.psi(m, np.diag(sp)) - O.psi(m, np.diag(sm))) / (2 * h)
+            assert abs(s[i] * dpsi - T[i, i]) <= 1e-7 * max(1.0, abs(T[i, i]))
+        assert np.abs(T - np.diag(np.diag(T))).max() <= 1e-9 * np.abs(T).max()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_stretch_round_trip(model):
+    """Random F = U diag(s) V^T -> tau(F) -> rotation-free base must equal the
+    left stretch sqrtm(F F^T) = U diag(s) U^T (Sec. 4.2-4.3), for the
+    closed-form Hencky inverse, the split-NH cubic and the fixed-corotated
+    scalar solve.  scipy's sqrtm is the independent reference."""
+    m = mat(model, E=1e6, nu=0.35)
+    rng = np.random.default_rng(40 + model)
+    for _ in range(20):
+        U, V = rand_rot(rng), rand_rot(rng)
+        s = rng.uniform(0.6, 1.8, 3)
+        F = U @ np.diag(s) @ V.T
+        T, rc = O.tau(m, F)
+        S, rc2 = O.stretch(m, T)
+        assert rc == 0 and rc2 == 0
+        ref = np.real(scipy.linalg.sqrtm(F @ F.T))
+        assert np.linalg.norm(S - ref) <= 1e-11 * np.linalg.norm(ref)
+        # P(S) S^T = tau (the defining relation of the base)
+        P, _ = O.piola(m, S)
+        assert np.linalg.norm(P @ S.T - T) <= 1e-9 * max(1.0, np.linalg.norm(T))
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_stretch_special_cases(model):
+    m = mat(model, E=1e5, nu=0.3)
+    S, rc = O.stretch(m, np.zeros((3, 3)))
+    assert rc == 0 and np.allclose(S, np.eye(3), atol=1e-14)
+    mu, lam = O.lame(1e5, 0.3)
+    t = 0.02 * mu
+    S, rc = O.stretch(m, t * np.eye(3))
+    assert rc == 0
+    if model == O.NEOHOOKEAN:
+        kappa = 2 * mu / 3 + lam
+        J = np.sqrt(1 + 2 * t / kappa)
+        assert np.allclose(S, J ** (1 / 3) * np.eye(3), rtol=1e-14)
+    elif model == O.HENCKY:
+        assert np.allclose(S, np.exp(t / (2 * mu + 3 * lam)) * np.eye(3), rtol=1e-14)
+    else:
+        s = S[0, 0]
+        J = s ** 3
+        # isotropic fixed-corotated: tau = 2 mu s (s - 1) + lambda J (J - 1)
+        assert abs(2 * mu * s * (s - 1) + lam * J * (J - 1) - t) <= 1e-10 * mu
+
+
+def test_nh_domain_flag():
+    """Extreme tension tr(tau)/3 <= -kappa/2 has no Neo-Hookean preimage."""
+    m = mat(O.NEOHOOKEAN)
+    mu, lam = O.lame(1e5, 0.3)
+    kappa = 2 * mu / 3 + lam
+    S, rc = O.stretch(m, -0.6 * kappa * np.eye(3))
+    assert rc == O.ERR_DOMAIN
+
+
+def test_cardano_largest_root_matches_numpy_roots():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        d = rng.normal(size=3)
+        d -= d.mean()  # deviatoric offsets sum to zero, so p <= 0
+        J2 = rng.uniform(0.3, 3.0)
+        p = d[0] * d[1] + d[1] * d[2] + d[2] * d[0]
+        q = d[0] * d[1] * d[2] - J2
+        roots = np.roots([1.0, 0.0, p, q])
+        real = roots[np.abs(roots.imag) < 1e-9].real
+        m = O.cardano_largest(p, q)
+        assert abs(m - real.max()) <= 1e-10 * max(1.0, abs(m))
+        # the largest root is the admissible branch: all beta_i = m + d_i > 0
+        assert np.all(m + d > 0)
+
+
+def test_cardano_near_isotropic_residual():
+    """Nearly spherical stress (offsets ~1e-3..1e-8) must keep the cubic's
+    residual at rounding level: the printed sum of cube roots cancels there."""
+    rng = np.random.default_rng(55)
+    for scale in (1e-2, 1e-4, 1e-6, 1e-8):
+        for _ in range(50):
+            d = scale * rng.normal(size=3)
+            d -= d.mean()
+            J2 = rng.uniform(0.5, 2.0)
+            p = d[0] * d[1] + d[1] * d[2] + d[2] * d[0]
+            q = d[0] * d[1] * d[2] - J2
+            m = O.cardano_largest(p, q)
+            # residual of prod(m + d_i) - J^2, relative to J^2
+            assert abs(np.prod(m + d) - J2) <= 4e-16 * J2 * 8
+
+
+def test_svd_and_eigen_against_numpy():
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        F = rng.normal(size=(3, 3))
+        U, s, V = O.svd3(F)
+        assert np.allclose(U @ np.diag(s) @ V.T, F, atol=1e-12)
+        assert np.allclose(U.T @ U, np.eye(3), atol=1e-12) and np.linalg.det(U) > 0
+        assert np.allclose(V.T @ V, np.eye(3), atol=1e-12) and np.linalg.det(V) > 0
+        assert np.allclose(np.sort(np.abs(s)), np.sort(np.linalg.svd(F, compute_uv=False)), atol=1e-12)
+        assert np.sign(s[2]) == np.sign(np.linalg.det(F))
+        A = rng.normal(size=(9, 9))
+        A = A + A.T
+        w, Q = O.sym_eigen(A)
+        assert np.allclose(np.sort(w), np.linalg.eigvalsh(A), atol=1e-12)
+        assert np.allclose(Q @ np.diag(w) @ Q.T, A, atol=1e-12)
+
+
+def test_psd_projection_matches_eigh_clamp():
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        A = rng.normal(size=(9, 9))
+        A = A + A.T
+        w, Q = np.linalg.eigh(A)
+        ref = (Q * np.maximum(w, 0)) @ Q.T
+        assert np.allclose(O.project_psd(A), ref, atol=1e-12)
+
+
+def henky_strain(F):
+    U, s, V = np.linalg.svd(F)
+    return np.log(s)
+
+
+def test_von_mises_projection():
+    mu, lam = O.lame(7e7, 0.3)
+    m = mat(O.FIXED_COROTATED, E=7e7, nu=0.3, plastic=O.PLASTIC_VON_MISES, yield_stress=1e5)
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        F = rand_F(rng, 0.98, 1.02)
+        e0 = henky_strain(F)
+        Fp, dg, rc = O.plastic_project(m, F)
+        assert rc == 0
+        e1 = henky_strain(Fp)
+        assert abs(e1.sum() - e0.sum()) <= 1e-12          # volume preserved
+        dev = e1 - e1.mean()
+        assert 2 * mu * np.linalg.norm(dev) <= 1e5 * (1 + 1e-9)
+        if 2 * mu * np.linalg.norm(e0 - e0.mean()) > 1e5:
+            assert abs(2 * mu * np.linalg.norm(dev) - 1e5) <= 1e-6 * 1e5   # on the surface
+            assert dg > 0
+        else:
+            assert np.allclose(Fp, F, atol=1e-14) and dg == 0
+    # inside the yield surface: identity
+    F = np.diag([1.0 + 1e-5, 1.0, 1.0])
+    Fp, dg, _ = O.plastic_project(m, F)
+    assert np.allclose(Fp, F, atol=1e-15) and dg == 0
+
+
+def test_drucker_prager_projection():
+    m = mat(O.HENCKY, E=1e6, nu=0.3, plastic=O.PLASTIC_DRUCKER_PRAGER, friction_deg=30.0)
+    mu, lam = O.lame(1e6, 0.3)
+    sphi = np.sin(np.radians(30.0))
+    af = np.sqrt(2 / 3) * 2 * sphi / (3 - sphi)
+    rng = np.random.default_rng(9)
+    for _ in range(30):
+        F = rand_F(rng, 0.9, 1.1)
+        Fp, dg, rc = O.plastic_project(m, F)
+        e = henky_strain(Fp)
+        tr = e.sum()
+        if henky_strain(F).sum() > 0:
+            assert np.allclose(e, 0, atol=1e-12)          # tip
+        else:
+            # on or inside the cone: |dev e| + (3 lam + 2 mu)/(2 mu) tr e af <= 0
+            cone = np.linalg.norm(e - e.mean()) + (3 * lam + 2 * mu) / (2 * mu) * tr * af
+            assert cone <= 1e-10

@@ -1,0 +1,200 @@
+/*
+ * mpmlite.h — C-ABI of the MI355X (gfx950) implementation of the MPM Lite
+ * implicit step: linear-kernel particle <-> quadrature resampling and the
+ * particle-free incremental-potential Newton solve on the voxel hex mesh.
+ *
+ * The problem statement follows Alg. 1 of the paper: particle state
+ * (x, v, F, G, m, V, material) in, the same state at n+1 out; the mesh is
+ * implied by (dx, origin, dims) and rebuilt every step (the grid is
+ * transient, Sec. 6).  Sub-steps are exported for testing and measurement.
+ *
+ * Conventions
+ *   - Units SI.  Nodes at origin + i*dx, i in [0, dims]; cells (quadrature
+ *     points) at origin + (c + 1/2)*dx, c in [0, dims-1].  dims must be
+ *     multiples of 4 (the library tiles cells in 4x4x4 blocks).
+ *   - Matrices row-major 3x3; G_ab = dv_a/dx_b.
+ *   - Particle arrays are DEVICE pointers, SoA per field, particle-major:
+ *     x, v [n][3]; F, G [n][3][3]; m, V0, plastic [n]; mat [n] (int32).
+ *     All double precision.  The caller owns them; the library never frees
+ *     or reallocates them.
+ *   - "Dense" grid vectors used by the sub-step entry points are DEVICE
+ *     arrays over ALL nodes (dims+1)^3 (or cells dims^3), index
+ *     (i*(Ny) + j)*(Nz) + k with i the x index, component-interleaved
+ *     ([node][3] for vectors).  Values at inactive nodes are ignored on
+ *     input and written as 0 on output.
+ *   - All device work is ordered on the stream given to mpl_create.  Calls
+ *     synchronise that stream only to read solver control scalars (norms,
+ *     energies, iteration flags) back to the host.
+ *   - The context owns its grid scratch (hipMalloc, grown on demand, reused
+ *     across steps, freed by mpl_destroy).
+ *
+ * Errors: every call returns an mpl_status; 0 is success.  No exception
+ * crosses the ABI.  mpl_last_error() returns a per-context message.
+ */
+#ifndef MPMLITE_H
+#define MPMLITE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPL_MAX_MATERIALS 4
+
+typedef int32_t mpl_status;
+enum {
+  MPL_OK = 0,
+  MPL_ERR_INVALID_ARG = -1,
+  MPL_ERR_HIP = -2,
+  MPL_ERR_OOM = -3,
+  MPL_ERR_NOT_CONVERGED = -4,  /* Newton hit max_newton (state is the last iterate) */
+  MPL_ERR_LINESEARCH = -5,     /* no step length passed the line search */
+  MPL_ERR_NONFINITE = -6,      /* NaN/Inf in a solver quantity */
+  MPL_ERR_DOMAIN = -7,         /* stress outside a model's invertible range, or a
+                                  particle stencil leaving the grid */
+  MPL_ERR_STATE = -8           /* sub-step called before the step it depends on */
+};
+
+/* Constitutive models (Sec. 4.3) and plasticity (applied to particle F). */
+enum { MPL_NEOHOOKEAN = 0, MPL_FIXED_COROTATED = 1, MPL_HENCKY = 2 };
+enum { MPL_PLASTIC_NONE = 0, MPL_PLASTIC_VON_MISES = 1, MPL_PLASTIC_DRUCKER_PRAGER = 2 };
+/* Dirichlet node boxes. */
+enum { MPL_BC_STICKY_BOX = 0, MPL_BC_MOVING_BOX = 1 };
+/* Precision of the stored tangent and of the Hessian-vector product. */
+enum { MPL_F32 = 0, MPL_F64 = 1 };
+/* Preconditioner of the Newton linear systems. */
+enum { MPL_PRECOND_JACOBI = 0, MPL_PRECOND_LEARNED = 2 };
+
+typedef struct {
+  double dx;
+  double origin[3];
+  int32_t dims[3]; /* cells per axis, multiples of 4 */
+} mpl_grid;
+
+typedef struct {
+  int32_t model;        /* MPL_NEOHOOKEAN | MPL_FIXED_COROTATED | MPL_HENCKY */
+  int32_t plastic;      /* MPL_PLASTIC_* */
+  double E, nu, rho;    /* Young's modulus, Poisson ratio, density (rho unused by the step) */
+  double yield_stress;  /* von Mises Kirchhoff yield stress */
+  double friction_deg;  /* Drucker-Prager friction angle */
+} mpl_material;
+
+typedef struct {
+  int32_t hv_precision;   /* MPL_F32 (production) or MPL_F64 (parity) */
+  int32_t precond;        /* MPL_PRECOND_JACOBI or MPL_PRECOND_LEARNED */
+  double newton_rtol;     /* stop when |g_free| <= newton_rtol * |g_free(vhat)| */
+  double pcg_rtol;        /* stop CG when |r| <= pcg_rtol * |b| */
+  int32_t max_newton, max_pcg, max_ls;
+  double armijo_c;        /* sufficient-decrease constant */
+  int32_t pcg_check_every;/* host polls the device convergence flag every k iterations */
+  int32_t time_kernels;   /* 1: time every Hessian-vector product with HIP events */
+} mpl_solver_opts;
+
+typedef struct {
+  int64_t n;
+  double *x, *v, *F, *G, *m, *V0, *plastic;  /* device; plastic may be NULL */
+  int32_t* mat;                               /* device */
+} mpl_particles;
+
+typedef struct {
+  int32_t kind;           /* MPL_BC_STICKY_BOX | MPL_BC_MOVING_BOX */
+  double lo[3], hi[3];    /* box at time 0, inclusive (tolerance 1e-6 dx) */
+  double velocity[3];     /* MOVING_BOX: prescribed velocity; the box moves with it */
+} mpl_bc;
+
+typedef struct {
+  int32_t newton_iters, pcg_iters, ls_halvings, fallbacks;
+  int32_t active_cells, active_nodes, free_dofs, cell_blocks, node_blocks;
+  double g0_norm, g_norm, energy;
+  double hv_ms_total;     /* summed HIP-event time of all Hv launches (time_kernels=1) */
+  int32_t hv_calls;
+  double ms_unload, ms_reconstruct, ms_newton, ms_load;  /* host wall clock per stage */
+  int32_t domain_events;  /* stretch reconstructions clamped (model range) */
+} mpl_stats;
+
+typedef struct mpl_ctx mpl_ctx;
+
+/* Library version string. */
+const char* mpl_version(void);
+
+/* Create a context.  grid, mats (n_mats <= MPL_MAX_MATERIALS) and opts are
+ * copied.  hip_stream is a hipStream_t (NULL = default stream).  On failure
+ * *out is NULL and the status says why. */
+mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
+                      const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out);
+void mpl_destroy(mpl_ctx* ctx);
+const char* mpl_last_error(const mpl_ctx* ctx);
+/* Replace the solver options (e.g. tolerances) of an existing context. */
+mpl_status mpl_set_opts(mpl_ctx* ctx, const mpl_solver_opts* opts);
+
+/* Alg. 1: one implicit time step.  Unload (Alg. 2), Dirichlet sets and
+ * vhat = v^n + dt*gravity on free nodes, stretch reconstruction and the
+ * Newton-PCG minimisation of the incremental potential (Alg. 3), Load with
+ * advection, F update and plastic projection (Alg. 4).  in may alias out;
+ * when they differ and the call fails, out is untouched.  time is the
+ * simulation time at the start of the step (moves MOVING_BOX sets).
+ * stats (host pointer, may be NULL) receives counters and timings. */
+mpl_status mpl_step(mpl_ctx* ctx, const mpl_particles* in, mpl_particles* out, double dt,
+                    const double gravity[3], const mpl_bc* bcs, int32_t n_bcs, double time,
+                    mpl_stats* stats);
+
+/* ---- sub-steps (the same kernels mpl_step runs) ---- */
+
+/* Alg. 2 (Sec. 3.1-3.3): bin particles by dual cell, Kirchhoff stress per
+ * particle, atomics-free coloured particle->centre scatter of m, mv, mG, V_k,
+ * V_k tau_k, normalisation, centre->node gather of m_i and v_i^n, Dirichlet
+ * sets and vhat.  Also resets the Newton iterate to vhat. */
+mpl_status mpl_unload(mpl_ctx* ctx, const mpl_particles* in, double dt, const double gravity[3],
+                      const mpl_bc* bcs, int32_t n_bcs, double time);
+/* Alg. 3 first loop (Sec. 4.3, App. C): S_{c,k} from tau_{c,k} (FP64). */
+mpl_status mpl_reconstruct_stretch(mpl_ctx* ctx);
+/* Incremental potential Phi and its gradient (Sec. 4.2) at the dense node
+ * velocity v (device, [(dims+1)^3][3], FP64) or, if v is NULL, at the
+ * library's current iterate.  energy: host pointer (may be NULL); grad:
+ * device dense array (may be NULL), zero on fixed/massless nodes. */
+mpl_status mpl_energy_grad(mpl_ctx* ctx, const double* v, double* energy, double* grad);
+/* Per-cell projected tangent Abar_c (9x9 symmetric, 45 stored entries) and
+ * the Jacobi diagonal at v (dense device FP64, or NULL = current iterate),
+ * stored in `precision` (MPL_F32 or MPL_F64). */
+mpl_status mpl_build_tangent(mpl_ctx* ctx, const double* v, int32_t precision);
+/* Matrix-free Hessian-vector product Hu = M u + sum_c B_c^T Abar_c B_c u on
+ * free DOFs, with the tangent of the last mpl_build_tangent.  u, Hu: dense
+ * device arrays [(dims+1)^3][3] of float (MPL_F32) or double (MPL_F64). */
+mpl_status mpl_hv(mpl_ctx* ctx, const void* u, void* Hu, int32_t precision);
+/* Jacobi-PCG on H x = b (b, x dense device FP64), tolerance and iteration
+ * cap from the options; iters (host, may be NULL) gets the iteration count
+ * and rel_resid (host, may be NULL) the recurrence residual |r|/|b|. */
+mpl_status mpl_pcg(mpl_ctx* ctx, const double* b, double* x, int32_t* iters, double* rel_resid);
+/* Newton minimisation of Phi from vhat; the solution stays in the context
+ * and is copied to v_out (dense device FP64) if non-NULL. */
+mpl_status mpl_solve(mpl_ctx* ctx, double* v_out, mpl_stats* stats);
+/* Alg. 4: node->centre sampling of v (dense device FP64, or NULL = the
+ * solved velocity), centre->particle interpolation, x += dt v_p,
+ * F <- (I + dt G_p) F, plastic projection.  Uses the binning of the last
+ * unload; in must be the particles passed to it. */
+mpl_status mpl_load(mpl_ctx* ctx, const double* v, const mpl_particles* in, mpl_particles* out,
+                    double dt);
+
+/* Dense export of grid fields (device output, FP64). */
+enum {
+  MPL_FIELD_MASS_C = 0,   /* cells, 1 */
+  MPL_FIELD_VEL_C = 1,    /* cells, 3 (v_c of the unload) */
+  MPL_FIELD_GRAD_C = 2,   /* cells, 9 (G_c of the unload) */
+  MPL_FIELD_VOL_CK = 3,   /* cells, n_mats (material-major: [k][cell]) */
+  MPL_FIELD_TAU_CK = 4,   /* cells, n_mats*9 ([k][cell][9]) */
+  MPL_FIELD_S_CK = 5,     /* cells, n_mats*9 ([k][cell][9]) */
+  MPL_FIELD_ABAR = 6,     /* cells, 81 (full symmetric 9x9) */
+  MPL_FIELD_MASS_I = 7,   /* nodes, 1 */
+  MPL_FIELD_VEL_I = 8,    /* nodes, 3 (v_i^n of the unload) */
+  MPL_FIELD_VHAT = 9,     /* nodes, 3 */
+  MPL_FIELD_FIXED = 10,   /* nodes, 1 (1.0 = Dirichlet) */
+  MPL_FIELD_V = 11,       /* nodes, 3 (current Newton iterate / solution) */
+  MPL_FIELD_DIAG = 12     /* nodes, 3 (Jacobi diagonal) */
+};
+mpl_status mpl_export_field(mpl_ctx* ctx, int32_t field, double* dense_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,68 @@
+// Block geometry shared by the kernels (device side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mpl_internal.h"
+
+namespace mpl {
+
+struct GridDev {
+  int dims[3], cbd[3], nbd[3];
+  double dx, inv_dx, origin[3];
+};
+
+inline GridDev grid_dev(const mpl_ctx* c) {
+  GridDev g;
+  for (int a = 0; a < 3; ++a) {
+    g.dims[a] = c->dims[a];
+    g.cbd[a] = c->cbd[a];
+    g.nbd[a] = c->nbd[a];
+    g.origin[a] = c->origin[a];
+  }
+  g.dx = c->dx;
+  g.inv_dx = c->inv_dx;
+  return g;
+}
+
+__device__ __forceinline__ int local_x(int l) { return l >> 4; }
+__device__ __forceinline__ int local_y(int l) { return (l >> 2) & 3; }
+__device__ __forceinline__ int local_z(int l) { return l & 3; }
+__device__ __forceinline__ int local_index(int x, int y, int z) { return (x * 4 + y) * 4 + z; }
+
+// Corner d of a cell: offsets ((d>>2)&1, (d>>1)&1, d&1); Q1 centre->node
+// gradient grad w = (2 delta - 1)/(4 dx) per component (Sec. 3.3, 3-D).
+__device__ __forceinline__ void corner_grad(int d, double inv4dx, double* gw) {
+  gw[0] = (((d >> 2) & 1) ? 1.0 : -1.0) * inv4dx;
+  gw[1] = (((d >> 1) & 1) ? 1.0 : -1.0) * inv4dx;
+  gw[2] = ((d & 1) ? 1.0 : -1.0) * inv4dx;
+}
+
+// Compact node index of corner d of local cell l in cell block cb.
+__device__ __forceinline__ int corner_node(const int* c_nbr_node, int cb, int l, int d) {
+  int x = local_x(l) + ((d >> 2) & 1), y = local_y(l) + ((d >> 1) & 1), z = local_z(l) + (d & 1);
+  int o = ((x >> 2) * 2 + (y >> 2)) * 2 + (z >> 2);
+  return c_nbr_node[cb * 8 + o] * MPL_BC + local_index(x & 3, y & 3, z & 3);
+}
+
+// Compact cell index of the cell c = node - delta_d around local node l of
+// node block nb, or -1 when that cell block is not active.
+__device__ __forceinline__ int node_cell(const int* n_nbr_cell, int nb, int l, int d) {
+  int x = local_x(l) - ((d >> 2) & 1), y = local_y(l) - ((d >> 1) & 1), z = local_z(l) - (d & 1);
+  int o = ((x < 0) * 2 + (y < 0)) * 2 + (z < 0);
+  int blk = n_nbr_cell[nb * 8 + o];
+  return blk < 0 ? -1 : blk * MPL_BC + local_index(x & 3, y & 3, z & 3);
+}
+
+// Deterministic wavefront sum (butterfly over 64 lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace mpl
+
+// node flag bits
+#define MPL_NODE_ACTIVE 1
+#define MPL_NODE_FIXED 2
+#define MPL_NODE_FREE 4

@@ -1,0 +1,142 @@
+// Internal state of the MI355X implicit-step library.
+//
+// HBM layout (everything per step is rebuilt from the particles):
+//   * cells are tiled in 4x4x4 blocks; only blocks touched by a particle
+//     stencil are allocated ("active cell blocks", compact ids in
+//     lexicographic block order).  Cell field f of cell l (l = (lx*4+ly)*4+lz)
+//     in compact block b lives at f[b*64 + l]; multi-component fields are
+//     component-major ([comp][n_cells]) so one wavefront reads 64 consecutive
+//     values per component;
+//   * nodes are tiled the same way; a node block is active when it holds a
+//     corner of an active cell block (cell block cb has its corners in node
+//     blocks cb + {0,1}^3);
+//   * dense block maps (one int per block of the whole grid) translate block
+//     coordinates to compact ids (-1 = inactive).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mpmlite.h"
+#include "mpl_math.h"
+
+#define MPL_BS 4
+#define MPL_BC 64  // cells (or nodes) per block
+
+// Packed index of the symmetric 9x9 tangent (upper triangle, row-major).
+__host__ __device__ constexpr int sym9(int r, int c) {
+  return (r <= c) ? (r * 9 - r * (r - 1) / 2 + (c - r)) : (c * 9 - c * (c - 1) / 2 + (r - c));
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Device-resident solver scalars (one instance per context).
+struct SolverScalars {
+  double rz, rz_new, rr, pq, alpha, beta, bnorm2, tol2;
+  double red[8];      // generic reduction outputs
+  int32_t done;       // 0 running, 1 converged, 2 breakdown
+  int32_t iters;
+  int32_t err;        // binning / domain error flags
+  int32_t domain_count;
+  int32_t n_cblk, n_nblk;
+  int32_t colour_count[8];
+  int32_t n_active_cells, n_active_nodes, n_free_nodes, pad;
+};
+
+struct mpl_ctx {
+  // grid
+  int dims[3];
+  int cbd[3];   // cell-block grid dims (dims/4)
+  int nbd[3];   // node-block grid dims (dims/4 + 1)
+  double dx, inv_dx, origin[3];
+  // materials and options
+  int nmat = 1;
+  mpl_material mats_in[MPL_MAX_MATERIALS];
+  mpl::MatParams mats[MPL_MAX_MATERIALS];
+  mpl_solver_opts opts;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+
+  // state flags
+  bool unloaded = false, reconstructed = false, tangent_built = false, solved = false;
+  int tangent_precision = MPL_F32;
+  double dt = 0.0;
+  int64_t np = 0;
+  int n_cblk = 0, n_nblk = 0;
+  int colour_count[8] = {0};
+  int colour_offset[9] = {0};
+
+  // binning
+  DevBuf cflag, cmap, nflag, nmap, scan_tmp, ccoord, ncoord, c_nbr_node, n_nbr_cell, colour_list,
+      pcell, pkey, bin_count, bin_start, bin_fill, sorted;
+  // cell fields (FP64 unless noted)
+  DevBuf mc, qc, Gc, Vk, Tk, Sk, Qc, ecell, Abar32, Abar64, Y32, Y64, vcl, Gcl;
+  // node fields
+  DevBuf mi, vn, vhat, flags, v, g, vt, dir, r, x, p32, p64, q32, q64, z, D, partials,
+      dense_tmp32, dense_tmp64;
+  // scalars
+  DevBuf scal;
+  SolverScalars* dscal() const { return (SolverScalars*)scal.p; }
+  SolverScalars hscal;
+
+  // timing
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> hv_events;
+  int hv_event_used = 0;
+  double hv_ms_total = 0.0;
+  int hv_calls = 0;
+  int domain_events = 0;
+
+  size_t ncell_alloc() const { return (size_t)n_cblk * MPL_BC; }
+  size_t nnode_alloc() const { return (size_t)n_nblk * MPL_BC; }
+};
+
+// ---------------------------------------------------------------- helpers
+mpl_status mpl_fail(mpl_ctx* c, mpl_status st, const std::string& msg);
+mpl_status mpl_hip_check(mpl_ctx* c, hipError_t e, const char* what);
+mpl_status mpl_ensure(mpl_ctx* c, DevBuf& b, size_t bytes);
+mpl_status mpl_sync_scalars(mpl_ctx* c);  // copy device scalars to hscal (synchronises)
+
+#define MPL_TRY(expr)                       \
+  do {                                      \
+    mpl_status _st = (expr);                \
+    if (_st != MPL_OK) return _st;          \
+  } while (0)
+#define MPL_HIP(c, expr) MPL_TRY(mpl_hip_check((c), (expr), #expr))
+#define MPL_LAUNCH(c, kern, grid, block, ...)                                     \
+  do {                                                                            \
+    if ((grid) > 0) {                                                             \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, (c)->stream, __VA_ARGS__); \
+      MPL_HIP(c, hipGetLastError());                                              \
+    }                                                                             \
+  } while (0)
+
+template <class T>
+inline T* P(const DevBuf& b) { return (T*)b.p; }
+
+// Exclusive scan of n int32 values (device), total written to *total_dev.
+mpl_status mpl_scan_i32(mpl_ctx* c, const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev);
+
+// Internal stages shared by the entry points.
+mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, const double* gravity,
+                            const mpl_bc* bcs, int n_bcs, double time);
+mpl_status mpl_stage_reconstruct(mpl_ctx* c);
+mpl_status mpl_stage_energy(mpl_ctx* c, const double* v_block, bool want_grad, double* energy,
+                            double* gnorm2);
+mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v_block, int precision);
+mpl_status mpl_stage_hv(mpl_ctx* c, const void* u_block, void* Hu_block, int precision, bool dot);
+mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b_block, double* x_block, int* iters,
+                         double* rel);
+mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st);
+mpl_status mpl_stage_load(mpl_ctx* c, const double* v_block, const mpl_particles* in,
+                          mpl_particles* out, double dt);
+// dense <-> block conversions for node vectors (3 comps) and scalars
+mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, int comps,
+                                    int is_f32);
+mpl_status mpl_block_to_dense_nodes(mpl_ctx* c, const void* block, void* dense, int comps,
+                                    int is_f32);

@@ -1,0 +1,937 @@
+// Integrate, implicit branch (Alg. 3; Sec. 4.2-4.3): stretch reconstruction,
+// incremental potential, projected tangent, matrix-free Hessian-vector
+// product, Jacobi-PCG and the Newton / line-search driver.
+//
+// Precision policy: stretch reconstruction, energy, gradient, SVD/polar and
+// every dot product / norm are FP64; the stored per-cell tangent and the
+// Hessian-vector product run in FP32 (MPL_F32) or FP64 (MPL_F64, parity).
+// CG keeps x and r in FP64, the search direction p and Hp in the Hv precision.
+//
+// Hessian-vector product (the hot loop), two race-free passes:
+//   cells: dG_c = sum_d u_{c+d} (x) grad w_d,  y_c = Abar_c vec(dG_c)   (9 values)
+//   nodes: (Hu)_i = m_i u_i + sum_{c ni i} Y_c grad w_ic, plus a partial u.Hu
+// one wavefront per 4x4x4 block, lane = cell (or node), coalesced
+// component-major loads of the 45 stored tangent entries.
+#include <cmath>
+#include <chrono>
+
+#include "mpl_grid.h"
+
+using namespace mpl;
+
+namespace {
+
+__constant__ MatParams s_mats[MPL_MAX_MATERIALS];
+
+__device__ __forceinline__ bool done_flag(const SolverScalars* s) {
+  return *(volatile const int32_t*)&s->done != 0;
+}
+
+// G_c(v) = sum over the 8 corners of v_i (x) grad w_ic (Sec. 3.3).
+template <class T>
+__device__ __forceinline__ void cell_grad(const T* __restrict__ v, int64_t nnode,
+                                          const int* __restrict__ c_nbr_node, int cb, int l,
+                                          double inv4dx, double* Gm) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Gm[e] = 0.0;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int ni = corner_node(c_nbr_node, cb, l, d);
+    double gw[3];
+    corner_grad(d, inv4dx, gw);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double va = (double)v[a * nnode + ni];
+      Gm[a * 3 + 0] += va * gw[0];
+      Gm[a * 3 + 1] += va * gw[1];
+      Gm[a * 3 + 2] += va * gw[2];
+    }
+  }
+}
+
+__global__ void k_reconstruct(const double* __restrict__ Vk, const double* __restrict__ Tk,
+                              double* __restrict__ Sk, int64_t ncell, int K,
+                              int32_t* __restrict__ domain_count) {
+  int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  for (int k = 0; k < K; ++k) {
+    double S6[6] = {1.0, 1.0, 1.0, 0.0, 0.0, 0.0};
+    if (Vk[k * ncell + ci] != 0.0) {
+      double t6[6], T[9], w[3], Q[9], s[3];
+      for (int j = 0; j < 6; ++j) t6[j] = Tk[(k * 6 + j) * ncell + ci];
+      sym_to_full(t6, T);
+      eig_sym3(T, w, Q);
+      if (stretch_from_principal(s_mats[k], w, s)) atomicAdd(domain_count, 1);
+      double S[9];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          S[i * 3 + j] = Q[i * 3] * s[0] * Q[j * 3] + Q[i * 3 + 1] * s[1] * Q[j * 3 + 1] +
+                         Q[i * 3 + 2] * s[2] * Q[j * 3 + 2];
+      full_to_sym(S, S6);
+    }
+    for (int j = 0; j < 6; ++j) Sk[(k * 6 + j) * ncell + ci] = S6[j];
+  }
+}
+
+// Energy per cell sum_k V psi_k((I + dt G) S_k) and, with want_grad, the
+// stress content Q_c = sum_k V P_k(F_k) S_k^T.
+template <bool WANT_GRAD>
+__global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ v, int64_t nnode,
+                                                     const int* __restrict__ c_nbr_node,
+                                                     const double* __restrict__ Vk,
+                                                     const double* __restrict__ Sk, int64_t ncell,
+                                                     int K, double dt, double inv4dx,
+                                                     double* __restrict__ Qc,
+                                                     double* __restrict__ partial) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  double e = 0.0, Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool any = false;
+  for (int k = 0; k < K; ++k) any = any || (Vk[k * ncell + ci] != 0.0);
+  if (any) {
+    double Gm[9];
+    cell_grad(v, nnode, c_nbr_node, cb, l, inv4dx, Gm);
+    double A[9];
+    for (int i = 0; i < 9; ++i) A[i] = dt * Gm[i];
+    A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
+    for (int k = 0; k < K; ++k) {
+      const double V = Vk[k * ncell + ci];
+      if (V == 0.0) continue;
+      double S6[6], S[9], F[9];
+      for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
+      sym_to_full(S6, S);
+      mul(A, S, F);
+      const double ps = psi(s_mats[k], F);
+      e += V * ps;
+      if (WANT_GRAD && isfinite(ps)) {
+        double Pm[9], PS[9];
+        piola(s_mats[k], F, Pm);
+        mul(Pm, S, PS);  // S symmetric: P S^T = P S
+        for (int i = 0; i < 9; ++i) Q[i] += V * PS[i];
+      }
+    }
+  }
+  if (WANT_GRAD)
+    for (int i = 0; i < 9; ++i) Qc[i * ncell + ci] = Q[i];
+  const double s = wave_sum(e);
+  if (l == 0) partial[cb] = s;
+}
+
+// grad_i = m_i (v_i - vhat_i) + dt sum_c Q_c grad w_ic on free nodes; partial
+// sums of the inertia energy and |grad|^2.
+template <bool WANT_GRAD>
+__global__ __launch_bounds__(64) void k_energy_nodes(const double* __restrict__ v,
+                                                     const double* __restrict__ vhat,
+                                                     const double* __restrict__ mi,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const int* __restrict__ n_nbr_cell,
+                                                     const double* __restrict__ Qc, int64_t ncell,
+                                                     int64_t nnode, double dt, double inv4dx,
+                                                     double* __restrict__ g,
+                                                     double* __restrict__ pe,
+                                                     double* __restrict__ pg) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const double m = mi[ni];
+  double ein = 0.0, gg = 0.0, gr[3] = {0.0, 0.0, 0.0};
+  if (fr) {
+    double dv[3];
+    for (int a = 0; a < 3; ++a) dv[a] = v[a * nnode + ni] - vhat[a * nnode + ni];
+    ein = 0.5 * m * (dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    if (WANT_GRAD) {
+      for (int d = 0; d < 8; ++d) {
+        const int ci = node_cell(n_nbr_cell, nb, l, d);
+        if (ci < 0) continue;
+        double gw[3];
+        corner_grad(d, inv4dx, gw);
+        for (int a = 0; a < 3; ++a)
+          gr[a] += Qc[(a * 3) * ncell + ci] * gw[0] + Qc[(a * 3 + 1) * ncell + ci] * gw[1] +
+                   Qc[(a * 3 + 2) * ncell + ci] * gw[2];
+      }
+      for (int a = 0; a < 3; ++a) gr[a] = m * dv[a] + dt * gr[a];
+      gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+    }
+  }
+  if (WANT_GRAD)
+    for (int a = 0; a < 3; ++a) g[a * nnode + ni] = gr[a];
+  const double se = wave_sum(ein), sg = wave_sum(gg);
+  if (l == 0) {
+    pe[nb] = se;
+    if (WANT_GRAD) pg[nb] = sg;
+  }
+}
+
+// Deterministic reduction of up to 3 partial arrays (fixed order) into
+// scalars, followed by the solver's scalar logic.
+enum { RED_PLAIN = 0, RED_ALPHA = 1, RED_BETA = 2, RED_PCG_INIT = 3 };
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, int na,
+                                                 const double* __restrict__ b, int nb,
+                                                 const double* __restrict__ c, int nc,
+                                                 SolverScalars* __restrict__ s, int slot) {
+  __shared__ double sh[3][1024];
+  const int t = threadIdx.x;
+  if ((MODE == RED_ALPHA || MODE == RED_BETA) && done_flag(s)) return;
+  double va = 0.0, vb = 0.0, vc = 0.0;
+  for (int i = t; i < na; i += 1024) va += a[i];
+  for (int i = t; i < nb; i += 1024) vb += b[i];
+  for (int i = t; i < nc; i += 1024) vc += c[i];
+  sh[0][t] = va;
+  sh[1][t] = vb;
+  sh[2][t] = vc;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) {
+      sh[0][t] += sh[0][t + off];
+      sh[1][t] += sh[1][t + off];
+      sh[2][t] += sh[2][t + off];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double A = sh[0][0], B = sh[1][0], C = sh[2][0];
+  if (MODE == RED_PLAIN) {
+    s->red[slot] = A;
+    s->red[slot + 1] = B;
+    s->red[slot + 2] = C;
+  } else if (MODE == RED_PCG_INIT) {  // A = r.z, B = b.b
+    s->rz = A;
+    s->bnorm2 = B;
+    s->iters = 0;
+    s->done = (B == 0.0) ? 1 : 0;
+  } else if (MODE == RED_ALPHA) {  // A = p.Hp
+    s->pq = A;
+    if (!(A > 0.0) || !isfinite(A)) {
+      s->done = 2;
+      s->alpha = 0.0;
+    } else {
+      s->alpha = s->rz / A;
+    }
+  } else {  // RED_BETA: A = r.z (new), B = r.r
+    s->rz_new = A;
+    s->rr = B;
+    s->iters += 1;
+    if (!isfinite(B)) s->done = 2;
+    else if (B <= s->tol2) s->done = 1;
+    s->beta = A / s->rz;
+    s->rz = A;
+  }
+}
+
+__global__ void k_set_tol(SolverScalars* s, double rtol2) { s->tol2 = rtol2 * s->bnorm2; }
+
+// Per-cell projected tangent (Sec. 4.2 Hessian; projection per material):
+//   Abar_c = dt^2 sum_k V_k sum_modes max(lam, 0) vec(E S_k) vec(E S_k)^T
+// with the analytic eigen-modes E of dP/dF at F_k = (I + dt G_c) S_k.
+template <class T>
+__global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, int64_t nnode,
+                                                const int* __restrict__ c_nbr_node,
+                                                const double* __restrict__ Vk,
+                                                const double* __restrict__ Sk, int64_t ncell,
+                                                int K, double dt, double inv4dx,
+                                                T* __restrict__ Abar, int32_t* __restrict__ err) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  double Ab[45];
+#pragma unroll
+  for (int i = 0; i < 45; ++i) Ab[i] = 0.0;
+  bool any = false;
+  for (int k = 0; k < K; ++k) any = any || (Vk[k * ncell + ci] != 0.0);
+  if (any) {
+    double Gm[9];
+    cell_grad(v, nnode, c_nbr_node, cb, l, inv4dx, Gm);
+    double A[9];
+    for (int i = 0; i < 9; ++i) A[i] = dt * Gm[i];
+    A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
+    for (int k = 0; k < K; ++k) {
+      const double V = Vk[k * ncell + ci];
+      if (V == 0.0) continue;
+      double S6[6], S[9], F[9];
+      for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
+      sym_to_full(S6, S);
+      mul(A, S, F);
+      double U[9], s[3], Vm[9], R[9];
+      if (!principal_frame(F, U, s, Vm, R)) {
+        atomicOr(err, 8);
+        continue;
+      }
+      double dpsi[3], H[3][3], tw[3], fl[3];
+      principal_derivs(s_mats[k], s, dpsi, H, tw, fl);
+      const double coef = dt * dt * V;
+      // scaling modes: eigenpairs of the 3x3 Hessian of psi_hat
+      double Hs[9] = {H[0][0], H[0][1], H[0][2], H[1][0], H[1][1], H[1][2], H[2][0], H[2][1], H[2][2]};
+      double w[3], Qm[9];
+      eig_sym3(Hs, w, Qm);
+      for (int mode = 0; mode < 9; ++mode) {
+        double lam, E[9];
+        if (mode < 3) {
+          lam = w[mode];
+          if (!(lam > 0.0)) continue;
+          // E = U diag(q) V^T
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              E[i * 3 + j] = U[i * 3] * Qm[mode] * Vm[j * 3] + U[i * 3 + 1] * Qm[3 + mode] * Vm[j * 3 + 1] +
+                             U[i * 3 + 2] * Qm[6 + mode] * Vm[j * 3 + 2];
+        } else {
+          const int p = (mode - 3) >> 1, sign = ((mode - 3) & 1) ? -1 : 1;
+          const int pi = (p == 1) ? 1 : 0, pj = (p == 0) ? 1 : 2;
+          lam = (sign > 0) ? tw[p] : fl[p];
+          if (!(lam > 0.0)) continue;
+          // E = (u_i v_j^T +- u_j v_i^T)/sqrt 2
+          const double r2 = 0.70710678118654752440;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+              E[i * 3 + j] = r2 * (U[i * 3 + pi] * Vm[j * 3 + pj] + sign * U[i * 3 + pj] * Vm[j * 3 + pi]);
+        }
+        double W[9];
+        mul(E, S, W);  // vec(E S) is the mode seen in velocity-gradient space
+        const double cl = coef * lam;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          const double wr = cl * W[r];
+#pragma unroll
+          for (int cc = r; cc < 9; ++cc) Ab[sym9(r, cc)] += wr * W[cc];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 45; ++i) Abar[i * ncell + ci] = (T)Ab[i];
+}
+
+// Jacobi diagonal of H at every node: m_i + sum_c sum_{b,b'} Abar[(a,b),(a,b')] gw_b gw_b'.
+template <class T>
+__global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t ncell,
+                                             const double* __restrict__ mi,
+                                             const uint8_t* __restrict__ flags,
+                                             const int* __restrict__ n_nbr_cell, int64_t nnode,
+                                             double inv4dx, double* __restrict__ D) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double dd[3] = {0.0, 0.0, 0.0};
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  if (fr) {
+    for (int d = 0; d < 8; ++d) {
+      const int ci = node_cell(n_nbr_cell, nb, l, d);
+      if (ci < 0) continue;
+      double gw[3];
+      corner_grad(d, inv4dx, gw);
+      for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b)
+          for (int b2 = 0; b2 < 3; ++b2)
+            s += (double)Abar[sym9(a * 3 + b, a * 3 + b2) * ncell + ci] * gw[b] * gw[b2];
+        dd[a] += s;
+      }
+    }
+    for (int a = 0; a < 3; ++a) dd[a] += mi[ni];
+  }
+  for (int a = 0; a < 3; ++a) D[a * nnode + ni] = fr ? dd[a] : 0.0;
+}
+
+// ---------------------------------------------------------------- Hv
+template <class T>
+__global__ __launch_bounds__(64) void k_hv_cells(const T* __restrict__ u, int64_t nnode,
+                                                 const int* __restrict__ c_nbr_node,
+                                                 const T* __restrict__ Abar, int64_t ncell,
+                                                 T inv4dx, T* __restrict__ Y,
+                                                 const SolverScalars* __restrict__ s) {
+  if (s && done_flag(s)) return;
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  T g[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) g[e] = T(0);
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    const int ni = corner_node(c_nbr_node, cb, l, d);
+    const T sx = ((d >> 2) & 1) ? inv4dx : -inv4dx;
+    const T sy = ((d >> 1) & 1) ? inv4dx : -inv4dx;
+    const T sz = (d & 1) ? inv4dx : -inv4dx;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T ua = u[a * nnode + ni];
+      g[a * 3 + 0] += ua * sx;
+      g[a * 3 + 1] += ua * sy;
+      g[a * 3 + 2] += ua * sz;
+    }
+  }
+  T y[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) y[r] = T(0);
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+#pragma unroll
+    for (int c = r; c < 9; ++c) {
+      const T a = Abar[sym9(r, c) * ncell + ci];
+      y[r] += a * g[c];
+      if (c != r) y[c] += a * g[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 9; ++r) Y[r * ncell + ci] = y[r];
+}
+
+template <class T, bool DOT>
+__global__ __launch_bounds__(64) void k_hv_nodes(const T* __restrict__ u,
+                                                 const double* __restrict__ mi,
+                                                 const uint8_t* __restrict__ flags,
+                                                 const int* __restrict__ n_nbr_cell,
+                                                 const T* __restrict__ Y, int64_t ncell,
+                                                 int64_t nnode, T inv4dx, T* __restrict__ Hu,
+                                                 double* __restrict__ partial,
+                                                 const SolverScalars* __restrict__ s) {
+  if (s && done_flag(s)) return;
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  T h[3] = {T(0), T(0), T(0)};
+  double dot = 0.0;
+  if (fr) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int ci = node_cell(n_nbr_cell, nb, l, d);
+      if (ci < 0) continue;
+      const T sx = ((d >> 2) & 1) ? inv4dx : -inv4dx;
+      const T sy = ((d >> 1) & 1) ? inv4dx : -inv4dx;
+      const T sz = (d & 1) ? inv4dx : -inv4dx;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        h[a] += Y[(a * 3) * ncell + ci] * sx + Y[(a * 3 + 1) * ncell + ci] * sy +
+                Y[(a * 3 + 2) * ncell + ci] * sz;
+    }
+    const T m = (T)mi[ni];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T ua = u[a * nnode + ni];
+      h[a] += m * ua;
+      if (DOT) dot += (double)ua * (double)h[a];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Hu[a * nnode + ni] = fr ? h[a] : T(0);
+  if (DOT) {
+    const double sdot = wave_sum(dot);
+    if (l == 0) partial[nb] = sdot;
+  }
+}
+
+// ---------------------------------------------------------------- PCG vectors
+template <class T>
+__global__ __launch_bounds__(64) void k_pcg_init(const double* __restrict__ b,
+                                                 const double* __restrict__ D,
+                                                 const uint8_t* __restrict__ flags, int64_t nnode,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 T* __restrict__ p, double* __restrict__ prz,
+                                                 double* __restrict__ pbb) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  double rz = 0.0, bb = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = a * nnode + ni;
+    const double rv = fr ? b[i] : 0.0;
+    const double zv = fr ? rv / D[i] : 0.0;
+    x[i] = 0.0;
+    r[i] = rv;
+    p[i] = (T)zv;
+    rz += rv * zv;
+    bb += rv * rv;
+  }
+  rz = wave_sum(rz);
+  bb = wave_sum(bb);
+  if (l == 0) {
+    prz[nb] = rz;
+    pbb[nb] = bb;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p, const T* __restrict__ q,
+                                                   const double* __restrict__ D,
+                                                   const uint8_t* __restrict__ flags, int64_t nnode,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ prz,
+                                                   double* __restrict__ prr,
+                                                   const SolverScalars* __restrict__ s) {
+  if (done_flag(s)) return;
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const double alpha = s->alpha;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  double rz = 0.0, rr = 0.0;
+  if (fr) {
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      x[i] += alpha * (double)p[i];
+      const double rv = r[i] - alpha * (double)q[i];
+      r[i] = rv;
+      rz += rv * rv / D[i];
+      rr += rv * rv;
+    }
+  }
+  rz = wave_sum(rz);
+  rr = wave_sum(rr);
+  if (l == 0) {
+    prz[nb] = rz;
+    prr[nb] = rr;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_pcg_direction(const double* __restrict__ r,
+                                                      const double* __restrict__ D,
+                                                      const uint8_t* __restrict__ flags,
+                                                      int64_t nnode, T* __restrict__ p,
+                                                      const SolverScalars* __restrict__ s) {
+  if (done_flag(s)) return;
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const double beta = s->beta;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = a * nnode + ni;
+    p[i] = fr ? (T)(r[i] / D[i] + beta * (double)p[i]) : T(0);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
+                                                 const double* __restrict__ dir, double alpha,
+                                                 const double* __restrict__ g,
+                                                 const uint8_t* __restrict__ flags, int64_t nnode,
+                                                 double* __restrict__ out, double* __restrict__ pdot) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  double dt = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = a * nnode + ni;
+    out[i] = fr ? v[i] + alpha * dir[i] : v[i];
+    if (g) dt += fr ? g[i] * dir[i] : 0.0;
+  }
+  if (pdot) {
+    dt = wave_sum(dt);
+    if (l == 0) pdot[nb] = dt;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_escale(const double* __restrict__ Vk, int64_t ncell, int K,
+                                               double* __restrict__ partial) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) s += Vk[k * ncell + ci] * (s_mats[k].mu + fabs(s_mats[k].lambda));
+  s = wave_sum(s);
+  if (l == 0) partial[cb] = s;
+}
+
+template <class T>
+__global__ void k_mask_free(T* __restrict__ u, const uint8_t* __restrict__ flags, int64_t nnode) {
+  int64_t ni = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ni >= nnode) return;
+  if (!(flags[ni] & MPL_NODE_FREE))
+    for (int a = 0; a < 3; ++a) u[a * nnode + ni] = T(0);
+}
+
+__global__ void k_neg(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = -a[i];
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+// ======================================================================
+static mpl_status upload_mats(mpl_ctx* c) {
+  MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(s_mats), c->mats,
+                                    sizeof(MatParams) * MPL_MAX_MATERIALS, 0,
+                                    hipMemcpyHostToDevice, c->stream));
+  return MPL_OK;
+}
+
+static mpl_status ensure_partials(mpl_ctx* c) {
+  size_t n = std::max(c->n_cblk, c->n_nblk) + 64;
+  return mpl_ensure(c, c->partials, sizeof(double) * 4 * n);
+}
+static double* partial_slot(mpl_ctx* c, int k) {
+  size_t n = std::max(c->n_cblk, c->n_nblk) + 64;
+  return P<double>(c->partials) + k * n;
+}
+
+mpl_status mpl_stage_reconstruct(mpl_ctx* c) {
+  if (!c->unloaded) return mpl_fail(c, MPL_ERR_STATE, "reconstruct before unload");
+  MPL_TRY(upload_mats(c));
+  const int64_t ncell = (int64_t)c->ncell_alloc();
+  MPL_HIP(c, hipMemsetAsync(&c->dscal()->domain_count, 0, sizeof(int32_t), c->stream));
+  MPL_LAUNCH(c, k_reconstruct, (int)((ncell + 127) / 128), 128, P<double>(c->Vk), P<double>(c->Tk),
+             P<double>(c->Sk), ncell, c->nmat, &c->dscal()->domain_count);
+  c->reconstructed = true;
+  return MPL_OK;
+}
+
+// energy (and gradient into c->g) at v (block layout); gnorm2 may be null.
+mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double* energy,
+                            double* gnorm2) {
+  if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "energy before reconstruction");
+  MPL_TRY(upload_mats(c));
+  MPL_TRY(ensure_partials(c));
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  const double inv4dx = 0.25 * c->inv_dx;
+  double* pc = partial_slot(c, 0);
+  double* pe = partial_slot(c, 1);
+  double* pg = partial_slot(c, 2);
+  if (want_grad) {
+    MPL_TRY(mpl_ensure(c, c->Qc, 8 * 9 * ncell));
+    MPL_TRY(mpl_ensure(c, c->g, 8 * 3 * nnode));
+    MPL_LAUNCH(c, k_energy_cells<true>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Qc), pc);
+    MPL_LAUNCH(c, k_energy_nodes<true>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Qc), ncell, nnode, c->dt,
+               inv4dx, P<double>(c->g), pe, pg);
+    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, pc, c->n_cblk, pe, c->n_nblk, pg, c->n_nblk,
+               c->dscal(), 0);
+  } else {
+    MPL_LAUNCH(c, k_energy_cells<false>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, (double*)nullptr, pc);
+    MPL_LAUNCH(c, k_energy_nodes<false>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), (const double*)nullptr, ncell, nnode,
+               c->dt, inv4dx, (double*)nullptr, pe, (double*)nullptr);
+    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, pc, c->n_cblk, pe, c->n_nblk, pe, 0, c->dscal(), 0);
+  }
+  MPL_TRY(mpl_sync_scalars(c));
+  if (energy) *energy = c->hscal.red[0] + c->hscal.red[1];
+  if (gnorm2) *gnorm2 = c->hscal.red[2];
+  return MPL_OK;
+}
+
+mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
+  if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "tangent before reconstruction");
+  MPL_TRY(upload_mats(c));
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  const double inv4dx = 0.25 * c->inv_dx;
+  MPL_TRY(mpl_ensure(c, c->D, 8 * 3 * nnode));
+  if (precision == MPL_F32) {
+    MPL_TRY(mpl_ensure(c, c->Abar32, 4 * 45 * ncell));
+    MPL_LAUNCH(c, k_tangent<float>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
+               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<float>(c->Abar32), &c->dscal()->err);
+    MPL_LAUNCH(c, k_diag<float>, c->n_nblk, 64, P<float>(c->Abar32), ncell, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
+  } else {
+    MPL_TRY(mpl_ensure(c, c->Abar64, 8 * 45 * ncell));
+    MPL_LAUNCH(c, k_tangent<double>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
+               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Abar64), &c->dscal()->err);
+    MPL_LAUNCH(c, k_diag<double>, c->n_nblk, 64, P<double>(c->Abar64), ncell, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
+  }
+  c->tangent_built = true;
+  c->tangent_precision = precision;
+  return MPL_OK;
+}
+
+static hipEvent_t next_event(mpl_ctx* c) {
+  if (c->hv_event_used >= (int)c->hv_events.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->hv_events.push_back(e);
+  }
+  return c->hv_events[c->hv_event_used++];
+}
+
+static mpl_status flush_hv_events(mpl_ctx* c) {
+  if (c->hv_event_used == 0) return MPL_OK;
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i + 1 < c->hv_event_used; i += 2) {
+    float ms = 0.f;
+    MPL_HIP(c, hipEventElapsedTime(&ms, c->hv_events[i], c->hv_events[i + 1]));
+    c->hv_ms_total += ms;
+    c->hv_calls += 1;
+  }
+  c->hv_event_used = 0;
+  return MPL_OK;
+}
+
+// u, Hu in block layout, precision of the stored tangent.
+mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool dot) {
+  if (!c->tangent_built || c->tangent_precision != precision)
+    return mpl_fail(c, MPL_ERR_STATE, "Hv needs a tangent built in the same precision");
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->opts.time_kernels) {
+    if (c->hv_event_used + 2 > 4096) MPL_TRY(flush_hv_events(c));
+    e0 = next_event(c);
+    e1 = next_event(c);
+    if (e0) MPL_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  const SolverScalars* s = dot ? c->dscal() : nullptr;
+  if (precision == MPL_F32) {
+    MPL_TRY(mpl_ensure(c, c->Y32, 4 * 9 * ncell));
+    const float inv4 = (float)(0.25 * c->inv_dx);
+    MPL_LAUNCH(c, k_hv_cells<float>, c->n_cblk, 64, (const float*)u, nnode, P<int>(c->c_nbr_node),
+               P<float>(c->Abar32), ncell, inv4, P<float>(c->Y32), s);
+    if (dot)
+      MPL_LAUNCH(c, (k_hv_nodes<float, true>), c->n_nblk, 64, (const float*)u, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<float>(c->Y32), ncell, nnode, inv4,
+                 (float*)Hu, partial_slot(c, 0), s);
+    else
+      MPL_LAUNCH(c, (k_hv_nodes<float, false>), c->n_nblk, 64, (const float*)u, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<float>(c->Y32), ncell, nnode, inv4,
+                 (float*)Hu, (double*)nullptr, s);
+  } else {
+    MPL_TRY(mpl_ensure(c, c->Y64, 8 * 9 * ncell));
+    const double inv4 = 0.25 * c->inv_dx;
+    MPL_LAUNCH(c, k_hv_cells<double>, c->n_cblk, 64, (const double*)u, nnode, P<int>(c->c_nbr_node),
+               P<double>(c->Abar64), ncell, inv4, P<double>(c->Y64), s);
+    if (dot)
+      MPL_LAUNCH(c, (k_hv_nodes<double, true>), c->n_nblk, 64, (const double*)u, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Y64), ncell, nnode, inv4,
+                 (double*)Hu, partial_slot(c, 0), s);
+    else
+      MPL_LAUNCH(c, (k_hv_nodes<double, false>), c->n_nblk, 64, (const double*)u, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Y64), ncell, nnode, inv4,
+                 (double*)Hu, (double*)nullptr, s);
+  }
+  if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
+  return MPL_OK;
+}
+
+// Jacobi-PCG on H x = b over free DOFs (b, x block layout FP64).
+mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
+  const int prec = c->tangent_precision;
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  SolverScalars* s = c->dscal();
+  double* pa = partial_slot(c, 1);
+  double* pb = partial_slot(c, 2);
+  void* p;
+  void* q;
+  if (prec == MPL_F32) {
+    MPL_TRY(mpl_ensure(c, c->p32, 4 * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->q32, 4 * 3 * nnode));
+    p = c->p32.p;
+    q = c->q32.p;
+    MPL_LAUNCH(c, k_pcg_init<float>, c->n_nblk, 64, b, P<double>(c->D), P<uint8_t>(c->flags), nnode, x,
+               P<double>(c->r), (float*)p, pa, pb);
+  } else {
+    MPL_TRY(mpl_ensure(c, c->p64, 8 * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->q64, 8 * 3 * nnode));
+    p = c->p64.p;
+    q = c->q64.p;
+    MPL_LAUNCH(c, k_pcg_init<double>, c->n_nblk, 64, b, P<double>(c->D), P<uint8_t>(c->flags), nnode,
+               x, P<double>(c->r), (double*)p, pa, pb);
+  }
+  MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
+  MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
+  const int check = std::max(1, c->opts.pcg_check_every);
+  int it = 0;
+  bool finished = false;
+  while (!finished) {
+    for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) {
+      MPL_TRY(mpl_stage_hv(c, p, q, prec, true));
+      MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, partial_slot(c, 0), c->n_nblk, pa, 0, pa, 0, s, 0);
+      if (prec == MPL_F32) {
+        MPL_LAUNCH(c, k_pcg_update<float>, c->n_nblk, 64, (const float*)p, (const float*)q,
+                   P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r), pa, pb, s);
+      } else {
+        MPL_LAUNCH(c, k_pcg_update<double>, c->n_nblk, 64, (const double*)p, (const double*)q,
+                   P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r), pa, pb, s);
+      }
+      MPL_LAUNCH(c, k_reduce<RED_BETA>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
+      if (prec == MPL_F32)
+        MPL_LAUNCH(c, k_pcg_direction<float>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
+                   P<uint8_t>(c->flags), nnode, (float*)p, s);
+      else
+        MPL_LAUNCH(c, k_pcg_direction<double>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
+                   P<uint8_t>(c->flags), nnode, (double*)p, s);
+    }
+    MPL_TRY(mpl_sync_scalars(c));
+    if (c->hscal.done != 0 || it >= c->opts.max_pcg) finished = true;
+  }
+  if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+  if (iters) *iters = c->hscal.iters;
+  if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
+  if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)
+    return mpl_fail(c, MPL_ERR_NONFINITE, "PCG breakdown (p.Hp <= 0 or not finite)");
+  return MPL_OK;
+}
+
+mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
+  if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "solve before reconstruction");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(mpl_ensure(c, c->dir, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->vt, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->g, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->x, 8 * 3 * nnode));
+  MPL_TRY(ensure_partials(c));
+  double* v = P<double>(c->v);
+  // energy rounding scale sum V (mu + |lambda|) for the line-search allowance
+  MPL_LAUNCH(c, k_escale, c->n_cblk, 64, P<double>(c->Vk), (int64_t)c->ncell_alloc(), c->nmat,
+             partial_slot(c, 3));
+  MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, partial_slot(c, 3), c->n_cblk, partial_slot(c, 3), 0,
+             partial_slot(c, 3), 0, c->dscal(), 4);
+  MPL_TRY(mpl_sync_scalars(c));
+  const double escale = c->hscal.red[4];
+  double E = 0.0, gn2 = 0.0;
+  MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+  if (!std::isfinite(E)) return mpl_fail(c, MPL_ERR_DOMAIN, "initial state outside the model domain");
+  const double g0 = std::sqrt(gn2);
+  double gn = g0;
+  int pcg_total = 0, ls_total = 0, it = 0;
+  mpl_status result = MPL_OK;
+  c->hv_ms_total = 0.0;
+  c->hv_calls = 0;
+  for (;; ++it) {
+    if (gn == 0.0 || gn <= c->opts.newton_rtol * g0) break;
+    if (it >= c->opts.max_newton) {
+      result = mpl_fail(c, MPL_ERR_NOT_CONVERGED, "Newton iteration cap reached");
+      break;
+    }
+    MPL_TRY(mpl_stage_tangent(c, v, c->opts.hv_precision));
+    // b = -g
+    MPL_LAUNCH(c, k_neg, (int)((3 * nnode + 255) / 256), 256, P<double>(c->g), P<double>(c->dir),
+               3 * nnode);
+    int iters = 0;
+    double rel = 0.0;
+    MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel));
+    pcg_total += iters;
+    // g . x for the Armijo test
+    MPL_LAUNCH(c, k_axpy_dot, c->n_nblk, 64, v, P<double>(c->x), 0.0, P<double>(c->g),
+               P<uint8_t>(c->flags), nnode, P<double>(c->vt), partial_slot(c, 3));
+    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, partial_slot(c, 3), c->n_nblk, partial_slot(c, 3), 0,
+               partial_slot(c, 3), 0, c->dscal(), 4);
+    MPL_TRY(mpl_sync_scalars(c));
+    const double gtp = c->hscal.red[4];
+    const double allowance = 1e-14 * escale + 1e-13 * std::fabs(E);
+    double alpha = 1.0, Et = 0.0;
+    bool ok = false;
+    int ls = 0;
+    for (; ls <= c->opts.max_ls; ++ls) {
+      MPL_LAUNCH(c, k_axpy_dot, c->n_nblk, 64, v, P<double>(c->x), alpha, (const double*)nullptr,
+                 P<uint8_t>(c->flags), nnode, P<double>(c->vt), (double*)nullptr);
+      MPL_TRY(mpl_stage_energy(c, P<double>(c->vt), false, &Et, nullptr));
+      if (std::isfinite(Et) && Et <= E + c->opts.armijo_c * alpha * gtp + allowance) {
+        ok = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    ls_total += ls;
+    if (!ok) {
+      result = mpl_fail(c, MPL_ERR_LINESEARCH, "no step length passed the line search");
+      break;
+    }
+    MPL_HIP(c, hipMemcpyAsync(v, c->vt.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
+    MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    gn = std::sqrt(gn2);
+    if (!std::isfinite(gn)) {
+      result = mpl_fail(c, MPL_ERR_NONFINITE, "gradient is not finite");
+      break;
+    }
+  }
+  if (st) {
+    st->newton_iters = it;
+    st->pcg_iters = pcg_total;
+    st->ls_halvings = ls_total;
+    st->g0_norm = g0;
+    st->g_norm = gn;
+    st->energy = E;
+    st->hv_ms_total = c->hv_ms_total;
+    st->hv_calls = c->hv_calls;
+  }
+  c->solved = (result == MPL_OK);
+  return result;
+}
+
+// ======================================================================
+extern "C" {
+
+mpl_status mpl_reconstruct_stretch(mpl_ctx* c) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  return mpl_stage_reconstruct(c);
+}
+
+mpl_status mpl_energy_grad(mpl_ctx* c, const double* v, double* energy, double* grad) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "energy before reconstruction");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  const double* vb = P<double>(c->v);
+  if (v) {
+    MPL_TRY(mpl_ensure(c, c->vt, 8 * 3 * nnode));
+    MPL_TRY(mpl_dense_to_block_nodes(c, v, c->vt.p, 3, 0));
+    vb = P<double>(c->vt);
+  }
+  double E = 0.0;
+  MPL_TRY(mpl_stage_energy(c, vb, grad != nullptr, &E, nullptr));
+  if (energy) *energy = E;
+  if (grad) MPL_TRY(mpl_block_to_dense_nodes(c, c->g.p, grad, 3, 0));
+  return MPL_OK;
+}
+
+mpl_status mpl_build_tangent(mpl_ctx* c, const double* v, int32_t precision) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  if (precision != MPL_F32 && precision != MPL_F64) return mpl_fail(c, MPL_ERR_INVALID_ARG, "precision");
+  if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "tangent before reconstruction");
+  const double* vb = P<double>(c->v);
+  if (v) {
+    MPL_TRY(mpl_ensure(c, c->vt, 8 * 3 * (int64_t)c->nnode_alloc()));
+    MPL_TRY(mpl_dense_to_block_nodes(c, v, c->vt.p, 3, 0));
+    vb = P<double>(c->vt);
+  }
+  return mpl_stage_tangent(c, vb, precision);
+}
+
+mpl_status mpl_hv(mpl_ctx* c, const void* u, void* Hu, int32_t precision) {
+  if (!c || !u || !Hu) return MPL_ERR_INVALID_ARG;
+  if (!c->tangent_built || c->tangent_precision != precision)
+    return mpl_fail(c, MPL_ERR_STATE, "mpl_hv needs a tangent built in the same precision");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  const int f32 = precision == MPL_F32;
+  DevBuf& bin = f32 ? c->p32 : c->p64;
+  DevBuf& bout = f32 ? c->q32 : c->q64;
+  MPL_TRY(mpl_ensure(c, bin, (f32 ? 4 : 8) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, bout, (f32 ? 4 : 8) * 3 * nnode));
+  MPL_TRY(mpl_dense_to_block_nodes(c, u, bin.p, 3, f32));
+  if (f32)
+    MPL_LAUNCH(c, k_mask_free<float>, (int)((nnode + 255) / 256), 256, (float*)bin.p,
+               P<uint8_t>(c->flags), nnode);
+  else
+    MPL_LAUNCH(c, k_mask_free<double>, (int)((nnode + 255) / 256), 256, (double*)bin.p,
+               P<uint8_t>(c->flags), nnode);
+  MPL_TRY(mpl_stage_hv(c, bin.p, bout.p, precision, false));
+  MPL_TRY(mpl_block_to_dense_nodes(c, bout.p, Hu, 3, f32));
+  if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+  return MPL_OK;
+}
+
+mpl_status mpl_pcg(mpl_ctx* c, const double* b, double* x, int32_t* iters, double* rel_resid) {
+  if (!c || !b || !x) return MPL_ERR_INVALID_ARG;
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "mpl_pcg needs a tangent");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(mpl_ensure(c, c->dir, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->x, 8 * 3 * nnode));
+  MPL_TRY(mpl_dense_to_block_nodes(c, b, c->dir.p, 3, 0));
+  int it = 0;
+  double rel = 0.0;
+  MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &it, &rel));
+  MPL_TRY(mpl_block_to_dense_nodes(c, c->x.p, x, 3, 0));
+  if (iters) *iters = it;
+  if (rel_resid) *rel_resid = rel;
+  return MPL_OK;
+}
+
+mpl_status mpl_solve(mpl_ctx* c, double* v_out, mpl_stats* st) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  mpl_status s = mpl_stage_solve(c, st);
+  if (v_out) MPL_TRY(mpl_block_to_dense_nodes(c, c->v.p, v_out, 3, 0));
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,521 @@
+// Unload (Alg. 2; Sec. 3.1-3.3): particle binning, Kirchhoff stress per
+// particle, particle -> cell-centre scatter and centre -> node gather.
+//
+// Scatter design (no atomics on floating point, deterministic):
+//   * particles are counting-sorted by their base dual cell b = floor(x/dx - 1/2)
+//     (integer atomics only; each bin is then ordered by particle index);
+//   * one wavefront owns one active 4x4x4 cell block and walks the particles
+//     whose base cell lies in it, 64 at a time.  Lanes holding particles of
+//     the same base cell form contiguous runs; a segmented wavefront scan sums
+//     each run's contribution to each of the 8 target centres b + delta, and
+//     the run's last lane adds it into a 5x5x5 centre tile in LDS (distinct
+//     runs hit distinct centres, so the adds never collide);
+//   * tiles overlap their +x/+y/+z neighbours by one layer, so blocks are
+//     written back in 8 passes by block-coordinate parity: blocks of one
+//     colour touch disjoint centres and read-modify-write them race-free.
+#include <cmath>
+
+#include "mpl_grid.h"
+
+using namespace mpl;
+
+namespace {
+
+struct ParticlesDev {
+  const double *x, *v, *F, *G, *m, *V;
+  const int32_t* mat;
+  int64_t n;
+};
+
+struct BCDev {
+  int n;
+  int kind[16];
+  double lo[16][3], hi[16][3], vel[16][3];
+};
+
+__constant__ MatParams c_mats[MPL_MAX_MATERIALS];
+
+__global__ void k_mark(ParticlesDev P, GridDev g, int32_t* __restrict__ pcell,
+                       int32_t* __restrict__ cflag, int32_t* __restrict__ err) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  int b[3];
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    double xi = (P.x[3 * p + a] - g.origin[a]) / g.dx - 0.5;
+    if (!(xi >= 0.0 && xi < 1e9)) { ok = false; b[a] = 0; continue; }
+    double fb = floor(xi);
+    b[a] = (int)fb;
+    if (b[a] + 1 > g.dims[a] - 1) ok = false;
+  }
+  if (!ok) {
+    atomicOr(err, 1);
+    pcell[p] = -1;
+    return;
+  }
+  pcell[p] = (b[0] * g.dims[1] + b[1]) * g.dims[2] + b[2];
+  for (int d = 0; d < 8; ++d) {
+    int cx = (b[0] + ((d >> 2) & 1)) >> 2, cy = (b[1] + ((d >> 1) & 1)) >> 2, cz = (b[2] + (d & 1)) >> 2;
+    cflag[(cx * g.cbd[1] + cy) * g.cbd[2] + cz] = 1;
+  }
+}
+
+__global__ void k_compact_cells(const int32_t* __restrict__ cflag, const int32_t* __restrict__ scan,
+                                int32_t* __restrict__ cmap, int4* __restrict__ ccoord,
+                                int32_t* __restrict__ nflag, int32_t* __restrict__ colour_list,
+                                int32_t* __restrict__ colour_count, GridDev g, int ndense) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndense) return;
+  if (!cflag[i]) {
+    cmap[i] = -1;
+    return;
+  }
+  int id = scan[i];
+  cmap[i] = id;
+  int bz = i % g.cbd[2], by = (i / g.cbd[2]) % g.cbd[1], bx = i / (g.cbd[1] * g.cbd[2]);
+  int col = ((bx & 1) << 2) | ((by & 1) << 1) | (bz & 1);
+  ccoord[id] = make_int4(bx, by, bz, col);
+  int pos = atomicAdd(&colour_count[col], 1);
+  colour_list[col * ndense + pos] = id;
+  for (int d = 0; d < 8; ++d) {
+    int nx = bx + ((d >> 2) & 1), ny = by + ((d >> 1) & 1), nz = bz + (d & 1);
+    nflag[(nx * g.nbd[1] + ny) * g.nbd[2] + nz] = 1;
+  }
+}
+
+__global__ void k_compact_nodes(const int32_t* __restrict__ nflag, const int32_t* __restrict__ scan,
+                                int32_t* __restrict__ nmap, int4* __restrict__ ncoord, GridDev g,
+                                int ndense) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndense) return;
+  if (!nflag[i]) {
+    nmap[i] = -1;
+    return;
+  }
+  int id = scan[i];
+  nmap[i] = id;
+  int bz = i % g.nbd[2], by = (i / g.nbd[2]) % g.nbd[1], bx = i / (g.nbd[1] * g.nbd[2]);
+  ncoord[id] = make_int4(bx, by, bz, 0);
+}
+
+__global__ void k_neighbours(const int4* __restrict__ ccoord, const int4* __restrict__ ncoord,
+                             const int32_t* __restrict__ cmap, const int32_t* __restrict__ nmap,
+                             int32_t* __restrict__ c_nbr_node, int32_t* __restrict__ n_nbr_cell,
+                             GridDev g, int n_cblk, int n_nblk) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_cblk) {
+    int4 b = ccoord[i];
+    for (int o = 0; o < 8; ++o) {
+      int nx = b.x + ((o >> 2) & 1), ny = b.y + ((o >> 1) & 1), nz = b.z + (o & 1);
+      c_nbr_node[i * 8 + o] = nmap[(nx * g.nbd[1] + ny) * g.nbd[2] + nz];
+    }
+  }
+  if (i < n_nblk) {
+    int4 b = ncoord[i];
+    for (int o = 0; o < 8; ++o) {
+      int cx = b.x - ((o >> 2) & 1), cy = b.y - ((o >> 1) & 1), cz = b.z - (o & 1);
+      int id = -1;
+      if (cx >= 0 && cy >= 0 && cz >= 0 && cx < g.cbd[0] && cy < g.cbd[1] && cz < g.cbd[2])
+        id = cmap[(cx * g.cbd[1] + cy) * g.cbd[2] + cz];
+      n_nbr_cell[i * 8 + o] = id;
+    }
+  }
+}
+
+__global__ void k_keys(const int32_t* __restrict__ pcell, const int32_t* __restrict__ cmap, GridDev g,
+                       int64_t n, int32_t* __restrict__ pkey, int32_t* __restrict__ bin_count) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int c = pcell[p];
+  int bz = c % g.dims[2], by = (c / g.dims[2]) % g.dims[1], bx = c / (g.dims[1] * g.dims[2]);
+  int blk = cmap[((bx >> 2) * g.cbd[1] + (by >> 2)) * g.cbd[2] + (bz >> 2)];
+  int key = blk * MPL_BC + local_index(bx & 3, by & 3, bz & 3);
+  pkey[p] = key;
+  atomicAdd(&bin_count[key], 1);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ pkey, const int32_t* __restrict__ bin_start,
+                          int32_t* __restrict__ bin_fill, int32_t* __restrict__ sorted, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int key = pkey[p];
+  int pos = bin_start[key] + atomicAdd(&bin_fill[key], 1);
+  sorted[pos] = (int32_t)p;
+}
+
+// Order each bin by particle index so that every later sum is reproducible.
+__global__ void k_sort_bins(const int32_t* __restrict__ bin_start, int32_t* __restrict__ sorted,
+                            int nbins) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  int s = bin_start[b], e = bin_start[b + 1];
+  for (int i = s + 1; i < e; ++i) {
+    int v = sorted[i];
+    int j = i - 1;
+    while (j >= s && sorted[j] > v) {
+      sorted[j + 1] = sorted[j];
+      --j;
+    }
+    sorted[j + 1] = v;
+  }
+}
+
+__device__ __forceinline__ double seg_scan(double v, int seg_start, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    double y = __shfl_up(v, off, 64);
+    if (lane - off >= seg_start) v += y;
+  }
+  return v;
+}
+
+// Accumulator slots per centre: 0 mass, 1-3 momentum, 4-12 mass-weighted G,
+// then per material k: 13+7k volume, 14+7k..19+7k V*tau (xx,yy,zz,xy,yz,xz).
+template <int K>
+__global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
+                                            const int32_t* __restrict__ sorted,
+                                            const int32_t* __restrict__ pkey,
+                                            const int32_t* __restrict__ bin_start,
+                                            const int32_t* __restrict__ colour_list,
+                                            const int4* __restrict__ ccoord,
+                                            const int32_t* __restrict__ cmap,
+                                            double* __restrict__ mc, double* __restrict__ qc,
+                                            double* __restrict__ Gc, double* __restrict__ Vk,
+                                            double* __restrict__ Tk, int64_t ncell,
+                                            int32_t* __restrict__ err) {
+  constexpr int NV = 13 + 7 * K;
+  __shared__ double tile[NV][128];
+  const int lane = threadIdx.x;
+  const int cb = colour_list[blockIdx.x];
+  const int4 bc = ccoord[cb];
+  for (int v = 0; v < NV; ++v) {
+    tile[v][lane] = 0.0;
+    tile[v][lane + 64] = 0.0;
+  }
+  __syncthreads();
+  const int s = bin_start[cb * MPL_BC], e = bin_start[cb * MPL_BC + MPL_BC];
+  for (int base = s; base < e; base += 64) {
+    const int idx = base + lane;
+    const bool valid = idx < e;
+    const int p = valid ? sorted[idx] : 0;
+    const int lb = valid ? (pkey[p] - cb * MPL_BC) : (64 + lane);
+    double f[3], xp[3], vp[3], Gp[9], tau[6] = {0, 0, 0, 0, 0, 0}, mp = 0.0, Vp = 0.0;
+    int k = 0;
+    if (valid) {
+      for (int a = 0; a < 3; ++a) {
+        xp[a] = P.x[3 * p + a];
+        vp[a] = P.v[3 * p + a];
+        double xi = (xp[a] - g.origin[a]) / g.dx - 0.5;
+        f[a] = xi - floor(xi);
+      }
+      for (int i = 0; i < 9; ++i) Gp[i] = P.G[9 * p + i];
+      mp = P.m[p];
+      Vp = P.V[p];
+      k = P.mat[p];
+      double F[9];
+      for (int i = 0; i < 9; ++i) F[i] = P.F[9 * p + i];
+      if (k < 0 || k >= K || !kirchhoff(c_mats[k], F, tau)) {
+        atomicOr(err, 2);
+        for (int i = 0; i < 6; ++i) tau[i] = 0.0;
+        if (k < 0 || k >= K) k = 0;
+      }
+    } else {
+      for (int a = 0; a < 3; ++a) f[a] = xp[a] = vp[a] = 0.0;
+      for (int i = 0; i < 9; ++i) Gp[i] = 0.0;
+    }
+    const int prev = __shfl_up(lb, 1, 64);
+    const bool head = (lane == 0) || (prev != lb);
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int seg_start = 63 - __clzll(hm & below);
+    const int next = __shfl_down(lb, 1, 64);
+    const bool tail = (lane == 63) || (next != lb);
+    const int lx = lb >> 4, ly = (lb >> 2) & 3, lz = lb & 3;  // valid lanes only
+    for (int d = 0; d < 8; ++d) {
+      const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+      const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+      const int t = ((lx + dx) * 5 + (ly + dy)) * 5 + (lz + dz);
+      double rc[3];
+      rc[0] = g.origin[0] + ((bc.x * 4 + lx + dx) + 0.5) * g.dx - xp[0];
+      rc[1] = g.origin[1] + ((bc.y * 4 + ly + dy) + 0.5) * g.dx - xp[1];
+      rc[2] = g.origin[2] + ((bc.z * 4 + lz + dz) + 0.5) * g.dx - xp[2];
+      const double wm = valid ? w * mp : 0.0;
+      const double wV = valid ? w * Vp : 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double val;
+        if (v == 0) val = wm;
+        else if (v < 4) {
+          int a = v - 1;
+          val = wm * (vp[a] + (Gp[a * 3] * rc[0] + Gp[a * 3 + 1] * rc[1] + Gp[a * 3 + 2] * rc[2]));
+        } else if (v < 13) val = wm * Gp[v - 4];
+        else {
+          int kk = (v - 13) / 7, j = (v - 13) % 7;
+          val = (kk == k) ? (j == 0 ? wV : wV * tau[j - 1]) : 0.0;
+        }
+        val = seg_scan(val, seg_start, lane);
+        if (tail && valid) tile[v][t] += val;
+      }
+    }
+  }
+  __syncthreads();
+  // write back the 5x5x5 tile (block parity colouring makes this race-free)
+  for (int t = lane; t < 125; t += 64) {
+    if (tile[0][t] == 0.0) {
+      bool any = false;
+      for (int v = 1; v < NV; ++v) any = any || (tile[v][t] != 0.0);
+      if (!any) continue;
+    }
+    const int tx = t / 25, ty = (t / 5) % 5, tz = t % 5;
+    const int gx = bc.x * 4 + tx, gy = bc.y * 4 + ty, gz = bc.z * 4 + tz;
+    if (gx >= g.dims[0] || gy >= g.dims[1] || gz >= g.dims[2]) {
+      atomicOr(err, 4);
+      continue;
+    }
+    const int blk = cmap[((gx >> 2) * g.cbd[1] + (gy >> 2)) * g.cbd[2] + (gz >> 2)];
+    if (blk < 0) {
+      atomicOr(err, 4);
+      continue;
+    }
+    const int64_t ci = (int64_t)blk * MPL_BC + local_index(gx & 3, gy & 3, gz & 3);
+    mc[ci] += tile[0][t];
+    for (int a = 0; a < 3; ++a) qc[a * ncell + ci] += tile[1 + a][t];
+    for (int e2 = 0; e2 < 9; ++e2) Gc[e2 * ncell + ci] += tile[4 + e2][t];
+    for (int kk = 0; kk < K; ++kk) {
+      Vk[kk * ncell + ci] += tile[13 + 7 * kk][t];
+      for (int j = 0; j < 6; ++j) Tk[(kk * 6 + j) * ncell + ci] += tile[14 + 7 * kk + j][t];
+    }
+  }
+}
+
+// Alg. 2 normalisation: v_c = (mv)_c/m_c, G_c = (mG)_c/m_c, tau_{c,k} = (V tau)_{c,k}/V_{c,k}.
+__global__ void k_normalise(double* __restrict__ mc, double* __restrict__ qc, double* __restrict__ Gc,
+                            const double* __restrict__ Vk, double* __restrict__ Tk, int64_t ncell,
+                            int K, int32_t* __restrict__ count) {
+  int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ci >= ncell) return;
+  double m = mc[ci];
+  if (m != 0.0) {
+    for (int a = 0; a < 3; ++a) qc[a * ncell + ci] /= m;
+    for (int e = 0; e < 9; ++e) Gc[e * ncell + ci] /= m;
+    atomicAdd(count, 1);
+  }
+  for (int k = 0; k < K; ++k) {
+    double V = Vk[k * ncell + ci];
+    if (V != 0.0)
+      for (int j = 0; j < 6; ++j) Tk[(k * 6 + j) * ncell + ci] /= V;
+  }
+}
+
+// Sec. 3.3 centre -> node gather with w_ic = 1/8 (race-free: every node
+// gathers from its own 8 cells), then Dirichlet sets and vhat.
+__global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict__ n_nbr_cell,
+                                            const int4* __restrict__ ncoord,
+                                            const double* __restrict__ mc,
+                                            const double* __restrict__ vc,
+                                            const double* __restrict__ Gc, int64_t ncell,
+                                            int64_t nnode, BCDev bcs, double time, double dt,
+                                            double gx, double gy, double gz,
+                                            double* __restrict__ mi, double* __restrict__ vn,
+                                            double* __restrict__ vhat, double* __restrict__ v,
+                                            uint8_t* __restrict__ flags,
+                                            int32_t* __restrict__ counts) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double m = 0.0, q[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < 8; ++d) {
+    int ci = node_cell(n_nbr_cell, nb, l, d);
+    if (ci < 0) continue;
+    double mcc = mc[ci];
+    if (mcc == 0.0) continue;
+    double wm = mcc / 8.0;
+    double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
+    m += wm;
+    for (int a = 0; a < 3; ++a) {
+      double aff = Gc[(a * 3) * ncell + ci] * r[0] + Gc[(a * 3 + 1) * ncell + ci] * r[1] +
+                   Gc[(a * 3 + 2) * ncell + ci] * r[2];
+      q[a] += wm * (vc[a * ncell + ci] + aff);
+    }
+  }
+  double vv[3] = {0.0, 0.0, 0.0};
+  if (m != 0.0)
+    for (int a = 0; a < 3; ++a) vv[a] = q[a] / m;
+  uint8_t fl = 0;
+  double vf[3] = {0.0, 0.0, 0.0};
+  if (m != 0.0) {
+    fl |= MPL_NODE_ACTIVE;
+    int4 bcrd = ncoord[nb];
+    int idx[3] = {bcrd.x * 4 + local_x(l), bcrd.y * 4 + local_y(l), bcrd.z * 4 + local_z(l)};
+    double xn[3];
+    for (int a = 0; a < 3; ++a) xn[a] = g.origin[a] + idx[a] * g.dx;
+    const double eps = 1e-6 * g.dx;
+    for (int b = 0; b < bcs.n; ++b) {
+      bool in = true;
+      for (int a = 0; a < 3; ++a) {
+        double sh = (bcs.kind[b] == MPL_BC_MOVING_BOX) ? bcs.vel[b][a] * time : 0.0;
+        if (xn[a] < bcs.lo[b][a] + sh - eps || xn[a] > bcs.hi[b][a] + sh + eps) in = false;
+      }
+      if (!in) continue;
+      fl |= MPL_NODE_FIXED;
+      for (int a = 0; a < 3; ++a) vf[a] = (bcs.kind[b] == MPL_BC_MOVING_BOX) ? bcs.vel[b][a] : 0.0;
+    }
+    if (!(fl & MPL_NODE_FIXED)) fl |= MPL_NODE_FREE;
+    atomicAdd(&counts[0], 1);
+    if (fl & MPL_NODE_FREE) atomicAdd(&counts[1], 1);
+  }
+  const double grav[3] = {gx, gy, gz};
+  mi[ni] = m;
+  flags[ni] = fl;
+  for (int a = 0; a < 3; ++a) {
+    double vh = (fl & MPL_NODE_FREE) ? vv[a] + dt * grav[a] : ((fl & MPL_NODE_FIXED) ? vf[a] : 0.0);
+    vn[a * nnode + ni] = vv[a];
+    vhat[a * nnode + ni] = vh;
+    v[a * nnode + ni] = vh;
+  }
+}
+
+}  // namespace
+
+mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, const double* gravity,
+                            const mpl_bc* bcs, int n_bcs, double time) {
+  if (!in || in->n < 0 ||
+      (in->n > 0 && (!in->x || !in->v || !in->F || !in->G || !in->m || !in->V0 || !in->mat)))
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "particle arrays missing");
+  if (n_bcs < 0 || n_bcs > 16 || (n_bcs > 0 && !bcs))
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "at most 16 boundary boxes");
+  if (!(dt > 0.0)) return mpl_fail(c, MPL_ERR_INVALID_ARG, "dt must be positive");
+  c->unloaded = c->reconstructed = c->tangent_built = c->solved = false;
+  c->dt = dt;
+  c->np = in->n;
+  const GridDev g = grid_dev(c);
+  const int ncb_dense = c->cbd[0] * c->cbd[1] * c->cbd[2];
+  const int nnb_dense = c->nbd[0] * c->nbd[1] * c->nbd[2];
+  const int64_t np = in->n;
+  ParticlesDev parts{in->x, in->v, in->F, in->G, in->m, in->V0, in->mat, np};
+
+  MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(c_mats), c->mats, sizeof(MatParams) * MPL_MAX_MATERIALS,
+                                    0, hipMemcpyHostToDevice, c->stream));
+  MPL_TRY(mpl_ensure(c, c->cflag, sizeof(int32_t) * ncb_dense));
+  MPL_TRY(mpl_ensure(c, c->cmap, sizeof(int32_t) * (ncb_dense + 1)));
+  MPL_TRY(mpl_ensure(c, c->nflag, sizeof(int32_t) * nnb_dense));
+  MPL_TRY(mpl_ensure(c, c->nmap, sizeof(int32_t) * (nnb_dense + 1)));
+  MPL_TRY(mpl_ensure(c, c->ccoord, sizeof(int4) * ncb_dense));
+  MPL_TRY(mpl_ensure(c, c->ncoord, sizeof(int4) * nnb_dense));
+  MPL_TRY(mpl_ensure(c, c->colour_list, sizeof(int32_t) * 8 * ncb_dense));
+  MPL_TRY(mpl_ensure(c, c->c_nbr_node, sizeof(int32_t) * 8 * ncb_dense));
+  MPL_TRY(mpl_ensure(c, c->n_nbr_cell, sizeof(int32_t) * 8 * nnb_dense));
+  MPL_TRY(mpl_ensure(c, c->pcell, sizeof(int32_t) * (np + 1)));
+  MPL_TRY(mpl_ensure(c, c->pkey, sizeof(int32_t) * (np + 1)));
+  MPL_TRY(mpl_ensure(c, c->sorted, sizeof(int32_t) * (np + 1)));
+  SolverScalars* ds = c->dscal();
+  MPL_HIP(c, hipMemsetAsync(ds, 0, sizeof(SolverScalars), c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->cflag.p, 0, sizeof(int32_t) * ncb_dense, c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->nflag.p, 0, sizeof(int32_t) * nnb_dense, c->stream));
+
+  const int TPB = 256;
+  MPL_LAUNCH(c, k_mark, (int)((np + TPB - 1) / TPB), TPB, parts, g, P<int32_t>(c->pcell),
+             P<int32_t>(c->cflag), &ds->err);
+  // compact cell blocks (cmap doubles as scan output before it is rewritten)
+  MPL_TRY(mpl_ensure(c, c->bin_count, sizeof(int32_t) * (ncb_dense + nnb_dense + 2)));
+  int32_t* scan_c = P<int32_t>(c->bin_count);
+  int32_t* scan_n = scan_c + ncb_dense + 1;
+  MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->cflag), scan_c, ncb_dense, &ds->n_cblk));
+  MPL_LAUNCH(c, k_compact_cells, (ncb_dense + TPB - 1) / TPB, TPB, P<int32_t>(c->cflag), scan_c,
+             P<int32_t>(c->cmap), P<int4>(c->ccoord), P<int32_t>(c->nflag),
+             P<int32_t>(c->colour_list), ds->colour_count, g, ncb_dense);
+  MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->nflag), scan_n, nnb_dense, &ds->n_nblk));
+  MPL_LAUNCH(c, k_compact_nodes, (nnb_dense + TPB - 1) / TPB, TPB, P<int32_t>(c->nflag), scan_n,
+             P<int32_t>(c->nmap), P<int4>(c->ncoord), g, nnb_dense);
+  MPL_TRY(mpl_sync_scalars(c));
+  if (c->hscal.err & 1)
+    return mpl_fail(c, MPL_ERR_DOMAIN, "a particle stencil leaves the grid (or x is not finite)");
+  c->n_cblk = c->hscal.n_cblk;
+  c->n_nblk = c->hscal.n_nblk;
+  c->colour_offset[0] = 0;
+  for (int k = 0; k < 8; ++k) c->colour_count[k] = c->hscal.colour_count[k];
+  const int mx = std::max(c->n_cblk, c->n_nblk);
+  MPL_LAUNCH(c, k_neighbours, (mx + TPB - 1) / TPB, TPB, P<int4>(c->ccoord), P<int4>(c->ncoord),
+             P<int32_t>(c->cmap), P<int32_t>(c->nmap), P<int32_t>(c->c_nbr_node),
+             P<int32_t>(c->n_nbr_cell), g, c->n_cblk, c->n_nblk);
+
+  // per-cell and per-node storage
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  const int K = c->nmat;
+  MPL_TRY(mpl_ensure(c, c->mc, 8 * ncell));
+  MPL_TRY(mpl_ensure(c, c->qc, 8 * 3 * ncell));
+  MPL_TRY(mpl_ensure(c, c->Gc, 8 * 9 * ncell));
+  MPL_TRY(mpl_ensure(c, c->Vk, 8 * K * ncell));
+  MPL_TRY(mpl_ensure(c, c->Tk, 8 * 6 * K * ncell));
+  MPL_TRY(mpl_ensure(c, c->Sk, 8 * 6 * K * ncell));
+  MPL_TRY(mpl_ensure(c, c->mi, 8 * nnode));
+  MPL_TRY(mpl_ensure(c, c->vn, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->vhat, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->v, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->flags, nnode + 64));
+  const int nbins = c->n_cblk * MPL_BC;
+  MPL_TRY(mpl_ensure(c, c->bin_count, sizeof(int32_t) * (nbins + 1)));
+  MPL_TRY(mpl_ensure(c, c->bin_start, sizeof(int32_t) * (nbins + 1)));
+  MPL_TRY(mpl_ensure(c, c->bin_fill, sizeof(int32_t) * (nbins + 1)));
+  MPL_HIP(c, hipMemsetAsync(c->bin_count.p, 0, sizeof(int32_t) * (nbins + 1), c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->bin_fill.p, 0, sizeof(int32_t) * (nbins + 1), c->stream));
+  MPL_LAUNCH(c, k_keys, (int)((np + TPB - 1) / TPB), TPB, P<int32_t>(c->pcell), P<int32_t>(c->cmap), g,
+             np, P<int32_t>(c->pkey), P<int32_t>(c->bin_count));
+  int32_t* bstart = P<int32_t>(c->bin_start);
+  MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->bin_count), bstart, nbins, bstart + nbins));
+  MPL_LAUNCH(c, k_scatter, (int)((np + TPB - 1) / TPB), TPB, P<int32_t>(c->pkey), bstart,
+             P<int32_t>(c->bin_fill), P<int32_t>(c->sorted), np);
+  MPL_LAUNCH(c, k_sort_bins, (nbins + TPB - 1) / TPB, TPB, bstart, P<int32_t>(c->sorted), nbins);
+
+  // P2C: zero accumulators, 8 colour passes
+  MPL_HIP(c, hipMemsetAsync(c->mc.p, 0, 8 * ncell, c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->qc.p, 0, 8 * 3 * ncell, c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->Gc.p, 0, 8 * 9 * ncell, c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->Vk.p, 0, 8 * K * ncell, c->stream));
+  MPL_HIP(c, hipMemsetAsync(c->Tk.p, 0, 8 * 6 * K * ncell, c->stream));
+  for (int col = 0; col < 8; ++col) {
+    const int cnt = c->colour_count[col];
+    const int32_t* list = P<int32_t>(c->colour_list) + (size_t)col * ncb_dense;
+#define MPL_P2C(KK)                                                                              \
+  MPL_LAUNCH(c, k_p2c<KK>, cnt, 64, parts, g, P<int32_t>(c->sorted), P<int32_t>(c->pkey), bstart, list, \
+             P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc),          \
+             P<double>(c->Gc), P<double>(c->Vk), P<double>(c->Tk), ncell, &ds->err)
+    switch (K) {
+      case 1: MPL_P2C(1); break;
+      case 2: MPL_P2C(2); break;
+      case 3: MPL_P2C(3); break;
+      default: MPL_P2C(4); break;
+    }
+#undef MPL_P2C
+  }
+  MPL_LAUNCH(c, k_normalise, (int)((ncell + TPB - 1) / TPB), TPB, P<double>(c->mc), P<double>(c->qc),
+             P<double>(c->Gc), P<double>(c->Vk), P<double>(c->Tk), ncell, K, &ds->n_active_cells);
+
+  BCDev bd{};
+  bd.n = n_bcs;
+  for (int b = 0; b < n_bcs; ++b) {
+    bd.kind[b] = bcs[b].kind;
+    for (int a = 0; a < 3; ++a) {
+      bd.lo[b][a] = bcs[b].lo[a];
+      bd.hi[b][a] = bcs[b].hi[a];
+      bd.vel[b][a] = bcs[b].velocity[a];
+    }
+  }
+  const double gz[3] = {0.0, 0.0, 0.0};
+  const double* gr = gravity ? gravity : gz;
+  MPL_LAUNCH(c, k_c2n, c->n_nblk, 64, g, P<int32_t>(c->n_nbr_cell), P<int4>(c->ncoord),
+             P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, bd, time, dt, gr[0],
+             gr[1], gr[2], P<double>(c->mi), P<double>(c->vn), P<double>(c->vhat), P<double>(c->v),
+             P<uint8_t>(c->flags), &ds->n_active_nodes);
+  MPL_TRY(mpl_sync_scalars(c));
+  if (c->hscal.err & 2) return mpl_fail(c, MPL_ERR_DOMAIN, "particle F outside the model domain (det F <= 0) or bad material id");
+  if (c->hscal.err & 4) return mpl_fail(c, MPL_ERR_HIP, "internal: scatter reached an inactive block");
+  c->unloaded = true;
+  return MPL_OK;
+}
+
+extern "C" mpl_status mpl_unload(mpl_ctx* c, const mpl_particles* in, double dt,
+                                 const double gravity[3], const mpl_bc* bcs, int32_t n_bcs,
+                                 double time) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  return mpl_stage_unload(c, in, dt, gravity, bcs, n_bcs, time);
+}

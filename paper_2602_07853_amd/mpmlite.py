@@ -1,0 +1,279 @@
+"""Thin ctypes binding of ``libmpmlite.so`` (the C-ABI in ``include/mpmlite.h``).
+
+Argument marshalling only: every step of the implicit path runs in the HIP
+kernels of the library.  PyTorch provides device memory and the stream.
+There is no CPU fallback: constructing a :class:`Context` without the built
+library or without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpmlite.so")
+
+F32, F64 = 0, 1
+PRECOND_JACOBI, PRECOND_LEARNED = 0, 2
+NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
+BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
+
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "OOM", -4: "NOT_CONVERGED",
+          -5: "LINESEARCH", -6: "NONFINITE", -7: "DOMAIN", -8: "STATE"}
+
+FIELDS = dict(mass_c=(0, "cell", 1), vel_c=(1, "cell", 3), grad_c=(2, "cell", 9),
+              vol_ck=(3, "cellk", 1), tau_ck=(4, "cellk", 9), s_ck=(5, "cellk", 9),
+              abar=(6, "cell", 81), mass_i=(7, "node", 1), vel_i=(8, "node", 3),
+              vhat=(9, "node", 3), fixed=(10, "node", 1), v=(11, "node", 3), diag=(12, "node", 3))
+
+
+class MplError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mpmlite {STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class _Grid(C.Structure):
+    _fields_ = [("dx", C.c_double), ("origin", C.c_double * 3), ("dims", C.c_int32 * 3)]
+
+
+class _Material(C.Structure):
+    _fields_ = [("model", C.c_int32), ("plastic", C.c_int32), ("E", C.c_double), ("nu", C.c_double),
+                ("rho", C.c_double), ("yield_stress", C.c_double), ("friction_deg", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("hv_precision", C.c_int32), ("precond", C.c_int32), ("newton_rtol", C.c_double),
+                ("pcg_rtol", C.c_double), ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
+                ("max_ls", C.c_int32), ("armijo_c", C.c_double), ("pcg_check_every", C.c_int32),
+                ("time_kernels", C.c_int32)]
+
+
+class _Particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("v", C.c_void_p), ("F", C.c_void_p),
+                ("G", C.c_void_p), ("m", C.c_void_p), ("V0", C.c_void_p), ("plastic", C.c_void_p),
+                ("mat", C.c_void_p)]
+
+
+class _BC(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("velocity", C.c_double * 3)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("pcg_iters", C.c_int32), ("ls_halvings", C.c_int32),
+                ("fallbacks", C.c_int32), ("active_cells", C.c_int32), ("active_nodes", C.c_int32),
+                ("free_dofs", C.c_int32), ("cell_blocks", C.c_int32), ("node_blocks", C.c_int32),
+                ("g0_norm", C.c_double), ("g_norm", C.c_double), ("energy", C.c_double),
+                ("hv_ms_total", C.c_double), ("hv_calls", C.c_int32), ("ms_unload", C.c_double),
+                ("ms_reconstruct", C.c_double), ("ms_newton", C.c_double), ("ms_load", C.c_double),
+                ("domain_events", C.c_int32)]
+
+
+_lib = None
+
+
+def library():
+    """Load the in-tree HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        lib = C.CDLL(LIB_PATH)
+        lib.mpl_version.restype = C.c_char_p
+        lib.mpl_last_error.restype = C.c_char_p
+        lib.mpl_last_error.argtypes = [C.c_void_p]
+        lib.mpl_destroy.argtypes = [C.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _dptr(t: torch.Tensor, dtype) -> int:
+    if t.numel() == 0:
+        return 0
+    if not t.is_cuda:
+        raise ValueError("mpmlite needs device tensors")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} tensor, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _particles(p: dict) -> _Particles:
+    n = p["x"].shape[0]
+    for k, shape in (("x", (n, 3)), ("v", (n, 3)), ("F", (n, 9)), ("G", (n, 9)), ("m", (n,)),
+                     ("V", (n,)), ("mat", (n,))):
+        if tuple(p[k].shape) != shape:
+            raise ValueError(f"particle field {k} has shape {tuple(p[k].shape)}, want {shape}")
+    pl = p.get("plastic")
+    return _Particles(n, _dptr(p["x"], torch.float64), _dptr(p["v"], torch.float64),
+                      _dptr(p["F"], torch.float64), _dptr(p["G"], torch.float64),
+                      _dptr(p["m"], torch.float64), _dptr(p["V"], torch.float64),
+                      _dptr(pl, torch.float64) if pl is not None else None,
+                      _dptr(p["mat"], torch.int32))
+
+
+def _bcs(bcs):
+    arr = (_BC * max(len(bcs), 1))()
+    for i, b in enumerate(bcs):
+        arr[i] = _BC(int(b["kind"]), (C.c_double * 3)(*b["lo"]), (C.c_double * 3)(*b["hi"]),
+                     (C.c_double * 3)(*b.get("velocity", (0.0, 0.0, 0.0))))
+    return arr
+
+
+def particles_to_device(parts: dict, device="cuda") -> dict:
+    """Copy a NumPy particle dict (x, v, G, F, m, V, mat[, eps]) to device tensors."""
+    out = {}
+    for k in ("x", "v", "G", "F", "m", "V"):
+        out[k] = torch.as_tensor(parts[k], dtype=torch.float64).contiguous().to(device)
+    out["mat"] = torch.as_tensor(parts["mat"], dtype=torch.int32).contiguous().to(device)
+    eps = parts.get("eps", parts.get("plastic"))
+    n = out["x"].shape[0]
+    out["plastic"] = (torch.as_tensor(eps, dtype=torch.float64) if eps is not None
+                      else torch.zeros(n, dtype=torch.float64)).contiguous().to(device)
+    return out
+
+
+def default_opts(**kw) -> dict:
+    o = dict(hv_precision=F32, precond=PRECOND_JACOBI, newton_rtol=1e-6, pcg_rtol=1e-6,
+             max_newton=50, max_pcg=20000, max_ls=40, armijo_c=1e-4, pcg_check_every=16,
+             time_kernels=0)
+    o.update(kw)
+    return o
+
+
+class Context:
+    """One simulation grid (dims multiples of 4) with its materials and solver options."""
+
+    def __init__(self, dims, dx, materials, opts=None, origin=(0.0, 0.0, 0.0), stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("mpmlite runs on the GPU only; no device is visible")
+        lib = library()
+        self._lib = lib
+        self.dims = tuple(int(d) for d in dims)
+        self.dx = float(dx)
+        self.nmat = len(materials)
+        g = _Grid(self.dx, (C.c_double * 3)(*origin), (C.c_int32 * 3)(*self.dims))
+        mats = (_Material * len(materials))()
+        for i, m in enumerate(materials):
+            mats[i] = _Material(int(m["model"]), int(m.get("plastic", 0)), float(m["E"]),
+                                float(m["nu"]), float(m.get("rho", 1000.0)),
+                                float(m.get("yield_stress", 0.0)), float(m.get("friction_deg", 0.0)))
+        self.opts = default_opts(**(opts or {}))
+        o = self._copts()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = C.c_void_p()
+        st = lib.mpl_create(C.byref(g), mats, len(materials), C.byref(o),
+                            C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if st != 0:
+            raise MplError(st, "mpl_create failed")
+        self._ctx = ctx
+
+    def _copts(self):
+        o = self.opts
+        return _Opts(int(o["hv_precision"]), int(o["precond"]), float(o["newton_rtol"]),
+                     float(o["pcg_rtol"]), int(o["max_newton"]), int(o["max_pcg"]),
+                     int(o["max_ls"]), float(o["armijo_c"]), int(o["pcg_check_every"]),
+                     int(o["time_kernels"]))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.mpl_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self._lib.mpl_last_error(self._ctx)
+            raise MplError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_opts(self, **kw):
+        self.opts.update(kw)
+        self._check(self._lib.mpl_set_opts(self._ctx, C.byref(self._copts())), "mpl_set_opts")
+
+    # ------------------------------------------------------------ full step
+    def step(self, parts_in: dict, parts_out: dict, dt, gravity=(0.0, 0.0, 0.0), bcs=(), time=0.0):
+        pi, po = _particles(parts_in), _particles(parts_out)
+        st = _Stats()
+        rc = self._lib.mpl_step(self._ctx, C.byref(pi), C.byref(po), C.c_double(dt),
+                                (C.c_double * 3)(*gravity), _bcs(list(bcs)), len(bcs),
+                                C.c_double(time), C.byref(st))
+        stats = {k: getattr(st, k) for k, _ in _Stats._fields_}
+        self._check(rc, "mpl_step")
+        return stats
+
+    # ------------------------------------------------------------ sub-steps
+    def unload(self, parts: dict, dt, gravity=(0.0, 0.0, 0.0), bcs=(), time=0.0):
+        pi = _particles(parts)
+        self._parts_ref = parts
+        self._check(self._lib.mpl_unload(self._ctx, C.byref(pi), C.c_double(dt),
+                                         (C.c_double * 3)(*gravity), _bcs(list(bcs)), len(bcs),
+                                         C.c_double(time)), "mpl_unload")
+
+    def reconstruct(self):
+        self._check(self._lib.mpl_reconstruct_stretch(self._ctx), "mpl_reconstruct_stretch")
+
+    def _node_vec(self, dtype=torch.float64):
+        n1 = [d + 1 for d in self.dims]
+        return torch.zeros((n1[0] * n1[1] * n1[2], 3), dtype=dtype, device="cuda")
+
+    def energy_grad(self, v=None, want_grad=True):
+        E = C.c_double()
+        g = self._node_vec() if want_grad else None
+        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        self._check(self._lib.mpl_energy_grad(self._ctx, vp, C.byref(E),
+                                              C.c_void_p(g.data_ptr()) if g is not None else None),
+                    "mpl_energy_grad")
+        return E.value, g
+
+    def build_tangent(self, v=None, precision=F32):
+        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        self._check(self._lib.mpl_build_tangent(self._ctx, vp, int(precision)), "mpl_build_tangent")
+
+    def hv(self, u: torch.Tensor, precision=F32):
+        dt = torch.float32 if precision == F32 else torch.float64
+        out = self._node_vec(dt)
+        self._check(self._lib.mpl_hv(self._ctx, C.c_void_p(_dptr(u, dt)), C.c_void_p(out.data_ptr()),
+                                     int(precision)), "mpl_hv")
+        return out
+
+    def pcg(self, b: torch.Tensor):
+        x = self._node_vec()
+        it = C.c_int32()
+        rel = C.c_double()
+        self._check(self._lib.mpl_pcg(self._ctx, C.c_void_p(_dptr(b, torch.float64)),
+                                      C.c_void_p(x.data_ptr()), C.byref(it), C.byref(rel)), "mpl_pcg")
+        return x, it.value, rel.value
+
+    def solve(self):
+        v = self._node_vec()
+        st = _Stats()
+        rc = self._lib.mpl_solve(self._ctx, C.c_void_p(v.data_ptr()), C.byref(st))
+        stats = {k: getattr(st, k) for k, _ in _Stats._fields_}
+        self._check(rc, "mpl_solve")
+        return v, stats
+
+    def load(self, parts_in: dict, parts_out: dict, dt, v=None):
+        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        self._check(self._lib.mpl_load(self._ctx, vp, C.byref(_particles(parts_in)),
+                                       C.byref(_particles(parts_out)), C.c_double(dt)), "mpl_load")
+
+    def export(self, name: str) -> torch.Tensor:
+        fid, kind, comps = FIELDS[name]
+        nx, ny, nz = self.dims
+        if kind == "node":
+            shape = ((nx + 1) * (ny + 1) * (nz + 1), comps)
+        elif kind == "cell":
+            shape = (nx * ny * nz, comps)
+        else:
+            shape = (self.nmat, nx * ny * nz, comps)
+        out = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        self._check(self._lib.mpl_export_field(self._ctx, int(fid), C.c_void_p(out.data_ptr())),
+                    "mpl_export_field")
+        return out

@@ -1,0 +1,48 @@
+"""Shared helpers of the GPU parity tests: build the oracle's reference of a
+scene and a HIP context for the same seeded inputs."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2602_07853_amd import scenes
+
+
+def rel(a, b, mask=None):
+    """Norm-wise relative difference |a - b| / |b| (over mask rows if given)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_state(sc, time=0.0):
+    """Unload, Dirichlet sets, vhat and stretch of a scene on the oracle."""
+    g, mats = O.grid_of(sc), O.materials_of(sc)
+    u = O.unload(g, sc.particles, mats)
+    fixed, vfix = O.node_bcs(g, u["mi"], O.bcs_of(sc), time)
+    grav = np.asarray(sc.gravity)
+    act = u["mi"] > 0
+    vhat = np.where(fixed[:, None] > 0, vfix, np.where(act[:, None], u["vi"] + sc.dt * grav, 0.0))
+    S, rc = O.reconstruct(g, mats, u["Vck"], u["tauck"])
+    u.update(fixed=fixed, vhat=vhat, S=S, S_rc=rc, grid=g, mats=mats)
+    return u
+
+
+def gpu_context(sc, precision, **opts):
+    from paper_2602_07853_amd import mpmlite
+    o = dict(hv_precision=precision, newton_rtol=sc.newton_rtol, pcg_rtol=sc.pcg_rtol)
+    o.update(opts)
+    return mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials, opts=o)
+
+
+def small_scenes():
+    return {
+        "nh_strained": scenes.small_block(n=8, lo=2, hi=6, strain=0.08, model=scenes.NEOHOOKEAN),
+        "fcr_two_materials": scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6,
+                                                model=scenes.FIXED_COROTATED, n_mats=2, seed=12),
+        "hencky_ragged": scenes.small_block(n=12, lo=3, hi=8, strain=0.05, model=scenes.HENCKY,
+                                            seed=13, vel_std=0.2),
+    }

@@ -1,0 +1,196 @@
+"""Benchmark: implicit MPM Lite steps per second on one MI355X.
+
+Workload (default): the stiff plastic solid on a 128^3 grid, ~1M active cells,
+~8M particles, fixed-corotated E=7e7 nu=0.3 with von Mises yield 1e5, a
+sticky floor and a plate pressing at 0.2 m/s, dt=1e-3; every step is a full
+Unload -> stretch reconstruction -> Newton-PCG (Jacobi, FP32 Hessian-vector
+products, FP64 reductions) to relative residual 1e-6 -> Load.
+
+Prints ONE JSON line (see the fields below).  ``roofline`` describes the
+Hessian-vector product (the PCG hot loop): algorithmic bytes per product
+(180 B per active cell for the 45 FP32 tangent entries + 28 B per active
+node for u, Hu and m) divided by its average duration, timed with HIP events
+on the library's stream over the timed steps.  ``cpu_baseline`` times the
+FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+HV_BYTES_PER_CELL = 180.0
+HV_BYTES_PER_NODE = 28.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    return ap.parse_args()
+
+
+def make_scene(cfg):
+    from paper_2602_07853_amd import scenes
+    return scenes.CONFIGS[cfg]()
+
+
+def workload_name(sc):
+    return (f"{sc.name}: {sc.n}^3 grid, {sc.occupied_cells} occupied cells, "
+            f"{sc.n_particles} particles, dt={sc.dt}, Newton + Jacobi PCG to rel. resid 1e-6")
+
+
+def cpu_baseline(sc, counts):
+    """Time one call of each oracle stage on the full workload and combine
+    them with this run's per-step Newton / PCG / line-search counts."""
+    from oracle import oracle as O
+    g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+    t = {}
+    t0 = time.perf_counter()
+    u = O.unload(g, sc.particles, mats)
+    t["unload"] = time.perf_counter() - t0
+    fixed, vfix = O.node_bcs(g, u["mi"], bcs, 0.0)
+    act = u["mi"] > 0
+    vhat = np.where(fixed[:, None] > 0, vfix, np.where(act[:, None], u["vi"] + sc.dt * np.asarray(sc.gravity), 0))
+    t0 = time.perf_counter()
+    S, _ = O.reconstruct(g, mats, u["Vck"], u["tauck"])
+    t["reconstruct"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.energy_grad(g, mats, sc.dt, u["mi"], vhat, fixed, u["Vck"], S, vhat)
+    t["energy_grad"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    A, _ = O.tangent(g, mats, sc.dt, u["Vck"], S, vhat, project=True)
+    t["tangent"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.hv(g, u["mc"], u["mi"], fixed, A, vhat)
+    t["hv"] = time.perf_counter() - t0
+    del A
+    t0 = time.perf_counter()
+    O.load(g, sc.dt, u["mc"], vhat, sc.particles, mats)
+    t["load"] = time.perf_counter() - t0
+    newton, pcg, ls = counts
+    step_s = (t["unload"] + t["reconstruct"] + t["load"] + (newton + 1) * t["energy_grad"] +
+              ls * t["energy_grad"] + newton * t["tangent"] + pcg * t["hv"] * 1.2)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sample = ("one call of each FP64 oracle stage on the full workload "
+              f"(unload {t['unload']:.1f}s, reconstruct {t['reconstruct']:.1f}s, energy+grad "
+              f"{t['energy_grad']:.2f}s, tangent {t['tangent']:.1f}s, Hv {t['hv']:.2f}s, load "
+              f"{t['load']:.1f}s), combined with this run's per-step counts (newton {newton:.2f}, "
+              f"pcg {pcg:.1f} with 20% for vector ops, line-search trials {ls:.2f}); OpenMP over cells")
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": sample}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded "
+              f"across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2602_07853_amd import mpmlite
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    sc = make_scene(args.config)
+    prec = mpmlite.F32 if args.precision == "f32" else mpmlite.F64
+    ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                          opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
+                                    pcg_check_every=16, time_kernels=1))
+    parts = mpmlite.particles_to_device(sc.particles)
+    print(f"[bench] {workload_name(sc)}", file=sys.stderr, flush=True)
+    step_idx = 0
+
+    def one_step():
+        nonlocal step_idx
+        st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, step_idx * sc.dt)
+        step_idx += 1
+        return st
+
+    for w in range(args.warmup):
+        st = one_step()
+        print(f"[bench] warmup {w} {json.dumps(st)}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    hv_ms, hv_calls, newton, pcg, ls = 0.0, 0, 0, 0, 0
+    cells = nodes = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st = one_step()
+        hv_ms += st["hv_ms_total"]
+        hv_calls += st["hv_calls"]
+        newton += st["newton_iters"]
+        pcg += st["pcg_iters"]
+        ls += st["ls_halvings"]
+        cells, nodes = st["active_cells"], st["active_nodes"]
+        print(f"[bench] step {k} newton {st['newton_iters']} pcg {st['pcg_iters']} "
+              f"ls {st['ls_halvings']} g {st['g_norm']:.3e}/{st['g0_norm']:.3e} "
+              f"ms unload {st['ms_unload']:.1f} newton {st['ms_newton']:.1f} load {st['ms_load']:.1f}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps_per_s = args.steps / elapsed
+    hv_avg_ms = hv_ms / max(hv_calls, 1)
+    hv_bytes = HV_BYTES_PER_CELL * cells + HV_BYTES_PER_NODE * nodes
+    if prec == mpmlite.F64:
+        hv_bytes *= 2.0
+    achieved = hv_bytes / (hv_avg_ms * 1e-3) / 1e9 if hv_calls else 0.0
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == sc.name and tj.get("kernel_version") == ctx_version():
+                traffic = tj.get("bytes_per_hv")
+        except Exception:
+            traffic = None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "Hessian-vector product (k_hv_cells + k_hv_nodes)",
+            "bytes_per_launch": hv_bytes, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
+    counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
+    base = None
+    if not args.no_cpu_baseline and args.config in (1, 2, 3):
+        base = cpu_baseline(sc, counts)
+    line = {
+        "metric": "implicit steps/s @1M cells to resid 1e-6 (plain Jacobi PCG); Hv HBM GB/s",
+        "value": round(steps_per_s, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == mpmlite.F32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(sc), "preconditioner": "jacobi",
+                   "active_cells": cells, "active_nodes": nodes,
+                   "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
+                   "hv_precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def ctx_version():
+    from paper_2602_07853_amd import mpmlite
+    return mpmlite.library().mpl_version().decode()
+
+
+if __name__ == "__main__":
+    main()

@@ -7,10 +7,10 @@ Unload -> stretch reconstruction -> Newton-PCG (Jacobi, FP32 Hessian-vector
 products, FP64 reductions) to relative residual 1e-6 -> Load.
 
 Prints ONE JSON line (see the fields below).  ``roofline`` describes the
-Hessian-vector product (the PCG hot loop): algorithmic bytes per product
-(180 B per active cell for the 45 FP32 tangent entries + 28 B per active
-node for u, Hu and m) divided by its average duration, timed with HIP events
-on the library's stream over the timed steps.  ``cpu_baseline`` times the
+fused Hessian-vector product kernel (the PCG hot loop): algorithmic bytes
+per launch (180 B per active cell for the 45 FP32 tangent entries + 24 B per
+active node for reading p and writing K p once) divided by its average
+duration, timed with HIP events on the library's stream over the timed steps.  ``cpu_baseline`` times the
 FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-HV_BYTES_PER_CELL = 180.0
-HV_BYTES_PER_NODE = 28.0
+HV_BYTES_PER_CELL = 180.0   # 45 FP32 tangent entries
+HV_BYTES_PER_NODE = 24.0    # p read once (12 B) + K p written once (12 B)
 
 
 def parse():
@@ -158,7 +158,7 @@ def main():
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "Hessian-vector product (k_hv_cells + k_hv_nodes)",
+            "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
             "bytes_per_launch": hv_bytes, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     base = None

@@ -7,11 +7,9 @@
 // Hessian-vector product run in FP32 (MPL_F32) or FP64 (MPL_F64, parity).
 // CG keeps x and r in FP64, the search direction p and Hp in the Hv precision.
 //
-// Hessian-vector product (the hot loop), two race-free passes:
-//   cells: dG_c = sum_d u_{c+d} (x) grad w_d,  y_c = Abar_c vec(dG_c)   (9 values)
-//   nodes: (Hu)_i = m_i u_i + sum_{c ni i} Y_c grad w_ic, plus a partial u.Hu
-// one wavefront per 4x4x4 block, lane = cell (or node), coalesced
-// component-major loads of the 45 stored tangent entries.
+// Hessian-vector product (the hot loop): one fused pass per 4x4x4 cell block
+// (see k_hv_fused) with coalesced component-major loads of the 45 stored
+// tangent entries; the CG update kernel assembles the node result.
 #include <cmath>
 #include <chrono>
 
@@ -200,13 +198,14 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, i
     s->bnorm2 = B;
     s->iters = 0;
     s->done = (B == 0.0) ? 1 : 0;
-  } else if (MODE == RED_ALPHA) {  // A = p.Hp
-    s->pq = A;
-    if (!(A > 0.0) || !isfinite(A)) {
+  } else if (MODE == RED_ALPHA) {  // A = p^T K p (cells), B = p^T M p (nodes)
+    const double pq = A + B;
+    s->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
       s->done = 2;
       s->alpha = 0.0;
     } else {
-      s->alpha = s->rz / A;
+      s->alpha = s->rz / pq;
     }
   } else {  // RED_BETA: A = r.z (new), B = r.r
     s->rz_new = A;
@@ -331,30 +330,73 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t
 }
 
 // ---------------------------------------------------------------- Hv
-template <class T>
-__global__ __launch_bounds__(64) void k_hv_cells(const T* __restrict__ u, int64_t nnode,
+// Fused Hessian-vector product, one wavefront per active cell block:
+//   1. stage the 5x5x5 node tile of p (the 2x2x2 corners of all 64 cells) in LDS;
+//   2. per cell: dG = sum_d p_{c+d} (x) grad w_d,  y = Abar_c vec(dG),
+//      and the cell's share y . vec(dG) of p^T K p;
+//   3. put y in LDS; every tile node gathers y_c grad w over its in-block
+//      cells in a fixed corner order (race-free, deterministic);
+//   4. write the block's own 4x4x4 nodes and its 61 halo nodes (+x/+y/+z
+//      faces, which belong to the next node blocks) exactly once.
+// The halo pieces are summed into their owner node by the CG update kernel
+// (or by k_hv_combine for a stand-alone product), so no node is ever
+// written by two workgroups and no atomics are needed.
+// Workgroups are mapped XCD-major (consecutive blocks on one XCD) so that
+// neighbouring blocks share p tile lines in the same L2.
+__device__ __forceinline__ int xcd_block(int wg, int n) {
+  const int per = (n + 7) >> 3;
+  return (wg & 7) * per + (wg >> 3);
+}
+
+// halo slot -> tile coordinates (see the owner-side decoding in halo_slot)
+__device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
+  if (l < 16) { tx = 4; ty = l >> 2; tz = l & 3; }
+  else if (l < 32) { int k = l - 16; tx = k >> 2; ty = 4; tz = k & 3; }
+  else if (l < 48) { int k = l - 32; tx = k >> 2; ty = k & 3; tz = 4; }
+  else if (l < 52) { tx = 4; ty = 4; tz = l - 48; }
+  else if (l < 56) { tx = 4; ty = l - 52; tz = 4; }
+  else if (l < 60) { tx = l - 56; ty = 4; tz = 4; }
+  else { tx = 4; ty = 4; tz = 4; }
+}
+
+template <class T, bool DOT>
+__global__ __launch_bounds__(64) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
                                                  const T* __restrict__ Abar, int64_t ncell,
-                                                 T inv4dx, T* __restrict__ Y,
+                                                 int n_cblk, T inv4dx, T* __restrict__ Hown,
+                                                 T* __restrict__ Hhalo,
+                                                 double* __restrict__ partial,
                                                  const SolverScalars* __restrict__ s) {
   if (s && done_flag(s)) return;
-  const int cb = blockIdx.x, l = threadIdx.x;
+  const int cb = xcd_block(blockIdx.x, n_cblk);
+  if (cb >= n_cblk) return;
+  const int l = threadIdx.x;
+  __shared__ T tp[3][128];
+  __shared__ T ys[9][64];
+  for (int t = l; t < 125; t += 64) {
+    const int tx = t / 25, ty = (t / 5) % 5, tz = t % 5;
+    const int o = ((tx >> 2) * 2 + (ty >> 2)) * 2 + (tz >> 2);
+    const int64_t ni = (int64_t)c_nbr_node[cb * 8 + o] * MPL_BC + local_index(tx & 3, ty & 3, tz & 3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tp[a][t] = p[a * nnode + ni];
+  }
+  __syncthreads();
   const int64_t ci = (int64_t)cb * MPL_BC + l;
+  const int lx = l >> 4, ly = (l >> 2) & 3, lz = l & 3;
   T g[9];
 #pragma unroll
   for (int e = 0; e < 9; ++e) g[e] = T(0);
 #pragma unroll
   for (int d = 0; d < 8; ++d) {
-    const int ni = corner_node(c_nbr_node, cb, l, d);
-    const T sx = ((d >> 2) & 1) ? inv4dx : -inv4dx;
-    const T sy = ((d >> 1) & 1) ? inv4dx : -inv4dx;
-    const T sz = (d & 1) ? inv4dx : -inv4dx;
+    const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+    const int t = ((lx + dx) * 5 + (ly + dy)) * 5 + (lz + dz);
+    const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const T ua = u[a * nnode + ni];
-      g[a * 3 + 0] += ua * sx;
-      g[a * 3 + 1] += ua * sy;
-      g[a * 3 + 2] += ua * sz;
+      const T pa = tp[a][t];
+      g[a * 3 + 0] += pa * sx;
+      g[a * 3 + 1] += pa * sy;
+      g[a * 3 + 2] += pa * sz;
     }
   }
   T y[9];
@@ -369,86 +411,147 @@ __global__ __launch_bounds__(64) void k_hv_cells(const T* __restrict__ u, int64_
       if (c != r) y[c] += a * g[r];
     }
   }
+  double dot = 0.0;
+  if (DOT) {
 #pragma unroll
-  for (int r = 0; r < 9; ++r) Y[r * ncell + ci] = y[r];
+    for (int r = 0; r < 9; ++r) dot += (double)y[r] * (double)g[r];
+  }
+#pragma unroll
+  for (int r = 0; r < 9; ++r) ys[r][l] = y[r];
+  __syncthreads();
+  // Gather: tile node t sums y_c grad w over its in-block cells c = t - d,
+  // in corner order d = 0..7.  Round 0: the lane's own node; round 1: halo.
+  for (int round = 0; round < 2; ++round) {
+    int tx, ty, tz;
+    if (round == 0) {
+      tx = lx; ty = ly; tz = lz;
+    } else {
+      if (l >= 61) break;
+      halo_tile(l, tx, ty, tz);
+    }
+    T h[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+      const int cx = tx - dx, cy = ty - dy, cz = tz - dz;
+      if (cx < 0 || cy < 0 || cz < 0 || cx > 3 || cy > 3 || cz > 3) continue;
+      const int cl = local_index(cx, cy, cz);
+      const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) h[a] += ys[a * 3][cl] * sx + ys[a * 3 + 1][cl] * sy + ys[a * 3 + 2][cl] * sz;
+    }
+    T* out = (round == 0) ? Hown : Hhalo;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a * ncell + ci] = h[a];
+  }
+  if (DOT) {
+    const double sdot = wave_sum(dot);
+    if (l == 0) partial[cb] = sdot;
+  }
 }
 
-template <class T, bool DOT>
-__global__ __launch_bounds__(64) void k_hv_nodes(const T* __restrict__ u,
-                                                 const double* __restrict__ mi,
-                                                 const uint8_t* __restrict__ flags,
-                                                 const int* __restrict__ n_nbr_cell,
-                                                 const T* __restrict__ Y, int64_t ncell,
-                                                 int64_t nnode, T inv4dx, T* __restrict__ Hu,
-                                                 double* __restrict__ partial,
-                                                 const SolverScalars* __restrict__ s) {
-  if (s && done_flag(s)) return;
+// Assemble (K p)_i for local node l of node block nb: the own partial of the
+// cell block with the same coordinates plus the halo pieces of the cell
+// blocks at -x, -y, -z (faces, edges, corner), summed in a fixed order.
+template <class T>
+__device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* __restrict__ Hhalo,
+                                          const int* __restrict__ n_nbr_cell, int64_t ncell,
+                                          int nb, int l, T* h) {
+  const int lx = l >> 4, ly = (l >> 2) & 3, lz = l & 3;
+  h[0] = h[1] = h[2] = T(0);
+  const int* nbr = n_nbr_cell + nb * 8;
+  int src = nbr[0];
+  if (src >= 0) {
+    const int64_t i = (int64_t)src * MPL_BC + l;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) h[a] += Hown[a * ncell + i];
+  }
+  // (offset index o = (ox*2+oy)*2+oz, required zero local coords, halo slot)
+  int o[7], slot[7];
+  bool need[7];
+  o[0] = 4; need[0] = lx == 0; slot[0] = ly * 4 + lz;
+  o[1] = 2; need[1] = ly == 0; slot[1] = 16 + lx * 4 + lz;
+  o[2] = 1; need[2] = lz == 0; slot[2] = 32 + lx * 4 + ly;
+  o[3] = 6; need[3] = lx == 0 && ly == 0; slot[3] = 48 + lz;
+  o[4] = 5; need[4] = lx == 0 && lz == 0; slot[4] = 52 + ly;
+  o[5] = 3; need[5] = ly == 0 && lz == 0; slot[5] = 56 + lx;
+  o[6] = 7; need[6] = lx == 0 && ly == 0 && lz == 0; slot[6] = 60;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    if (!need[k]) continue;
+    src = nbr[o[k]];
+    if (src < 0) continue;
+    const int64_t i = (int64_t)src * MPL_BC + slot[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) h[a] += Hhalo[a * ncell + i];
+  }
+}
+
+// Stand-alone product: Hu = M u + K u on free nodes.
+template <class T>
+__global__ __launch_bounds__(64) void k_hv_combine(const T* __restrict__ u,
+                                                   const double* __restrict__ mi,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const int* __restrict__ n_nbr_cell,
+                                                   const T* __restrict__ Hown,
+                                                   const T* __restrict__ Hhalo, int64_t ncell,
+                                                   int64_t nnode, T* __restrict__ Hu) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   const bool fr = flags[ni] & MPL_NODE_FREE;
-  T h[3] = {T(0), T(0), T(0)};
-  double dot = 0.0;
-  if (fr) {
+  T h[3];
+  gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+  const T m = (T)mi[ni];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      const int ci = node_cell(n_nbr_cell, nb, l, d);
-      if (ci < 0) continue;
-      const T sx = ((d >> 2) & 1) ? inv4dx : -inv4dx;
-      const T sy = ((d >> 1) & 1) ? inv4dx : -inv4dx;
-      const T sz = (d & 1) ? inv4dx : -inv4dx;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        h[a] += Y[(a * 3) * ncell + ci] * sx + Y[(a * 3 + 1) * ncell + ci] * sy +
-                Y[(a * 3 + 2) * ncell + ci] * sz;
-    }
-    const T m = (T)mi[ni];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T ua = u[a * nnode + ni];
-      h[a] += m * ua;
-      if (DOT) dot += (double)ua * (double)h[a];
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) Hu[a * nnode + ni] = fr ? h[a] : T(0);
-  if (DOT) {
-    const double sdot = wave_sum(dot);
-    if (l == 0) partial[nb] = sdot;
-  }
+  for (int a = 0; a < 3; ++a) Hu[a * nnode + ni] = fr ? h[a] + m * u[a * nnode + ni] : T(0);
 }
 
 // ---------------------------------------------------------------- PCG vectors
+// x = 0, r = b, p = D^{-1} r; partials r.z, b.b and p^T M p.
 template <class T>
 __global__ __launch_bounds__(64) void k_pcg_init(const double* __restrict__ b,
                                                  const double* __restrict__ D,
+                                                 const double* __restrict__ mi,
                                                  const uint8_t* __restrict__ flags, int64_t nnode,
                                                  double* __restrict__ x, double* __restrict__ r,
                                                  T* __restrict__ p, double* __restrict__ prz,
-                                                 double* __restrict__ pbb) {
+                                                 double* __restrict__ pbb,
+                                                 double* __restrict__ pmm) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   const bool fr = flags[ni] & MPL_NODE_FREE;
-  double rz = 0.0, bb = 0.0;
+  const double m = mi[ni];
+  double rz = 0.0, bb = 0.0, mm = 0.0;
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
     const double rv = fr ? b[i] : 0.0;
     const double zv = fr ? rv / D[i] : 0.0;
+    const T pv = (T)zv;
     x[i] = 0.0;
     r[i] = rv;
-    p[i] = (T)zv;
+    p[i] = pv;
     rz += rv * zv;
     bb += rv * rv;
+    mm += m * (double)pv * (double)pv;
   }
   rz = wave_sum(rz);
   bb = wave_sum(bb);
+  mm = wave_sum(mm);
   if (l == 0) {
     prz[nb] = rz;
     pbb[nb] = bb;
+    pmm[nb] = mm;
   }
 }
 
+// q = M p + K p (assembled from the fused product's pieces), x += alpha p,
+// r -= alpha q; partials of r.z (z = D^{-1} r) and r.r.
 template <class T>
-__global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p, const T* __restrict__ q,
+__global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p,
+                                                   const T* __restrict__ Hown,
+                                                   const T* __restrict__ Hhalo,
+                                                   const int* __restrict__ n_nbr_cell,
+                                                   int64_t ncell, const double* __restrict__ mi,
                                                    const double* __restrict__ D,
                                                    const uint8_t* __restrict__ flags, int64_t nnode,
                                                    double* __restrict__ x, double* __restrict__ r,
@@ -462,10 +565,15 @@ __global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p, cons
   const bool fr = flags[ni] & MPL_NODE_FREE;
   double rz = 0.0, rr = 0.0;
   if (fr) {
+    T h[3];
+    gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    const T m = (T)mi[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      x[i] += alpha * (double)p[i];
-      const double rv = r[i] - alpha * (double)q[i];
+      const T pv = p[i];
+      const double q = (double)(h[a] + m * pv);
+      x[i] += alpha * (double)pv;
+      const double rv = r[i] - alpha * q;
       r[i] = rv;
       rz += rv * rv / D[i];
       rr += rv * rv;
@@ -479,21 +587,30 @@ __global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p, cons
   }
 }
 
+// p = D^{-1} r + beta p; partial p^T M p for the next p^T H p.
 template <class T>
 __global__ __launch_bounds__(64) void k_pcg_direction(const double* __restrict__ r,
                                                       const double* __restrict__ D,
+                                                      const double* __restrict__ mi,
                                                       const uint8_t* __restrict__ flags,
                                                       int64_t nnode, T* __restrict__ p,
+                                                      double* __restrict__ pmm,
                                                       const SolverScalars* __restrict__ s) {
   if (done_flag(s)) return;
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   const double beta = s->beta;
   const bool fr = flags[ni] & MPL_NODE_FREE;
+  const double m = mi[ni];
+  double mm = 0.0;
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
-    p[i] = fr ? (T)(r[i] / D[i] + beta * (double)p[i]) : T(0);
+    const T pv = fr ? (T)(r[i] / D[i] + beta * (double)p[i]) : T(0);
+    p[i] = pv;
+    mm += m * (double)pv * (double)pv;
   }
+  mm = wave_sum(mm);
+  if (l == 0) pmm[nb] = mm;
 }
 
 __global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
@@ -656,12 +773,23 @@ static mpl_status flush_hv_events(mpl_ctx* c) {
   return MPL_OK;
 }
 
-// u, Hu in block layout, precision of the stored tangent.
-mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool dot) {
-  if (!c->tangent_built || c->tangent_precision != precision)
-    return mpl_fail(c, MPL_ERR_STATE, "Hv needs a tangent built in the same precision");
+template <class T> static DevBuf& abar_buf(mpl_ctx* c) { return c->Abar32; }
+template <> DevBuf& abar_buf<double>(mpl_ctx* c) { return c->Abar64; }
+template <class T> static DevBuf& pieces_buf(mpl_ctx* c) { return c->Y32; }
+template <> DevBuf& pieces_buf<double>(mpl_ctx* c) { return c->Y64; }
+template <class T> static DevBuf& pvec_buf(mpl_ctx* c) { return c->p32; }
+template <> DevBuf& pvec_buf<double>(mpl_ctx* c) { return c->p64; }
+
+// The fused cell-block product: own and halo node pieces of K p (and, with
+// dot, the per-block partial sums of p^T K p), timed with HIP events when
+// time_kernels is set.
+template <class T>
+static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
-  MPL_TRY(ensure_partials(c));
+  DevBuf& pieces = pieces_buf<T>(c);
+  MPL_TRY(mpl_ensure(c, pieces, sizeof(T) * 6 * ncell));
+  T* Hown = P<T>(pieces);
+  T* Hhalo = Hown + 3 * ncell;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.time_kernels) {
     if (c->hv_event_used + 2 > 4096) MPL_TRY(flush_hv_events(c));
@@ -669,65 +797,65 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
     e1 = next_event(c);
     if (e0) MPL_HIP(c, hipEventRecord(e0, c->stream));
   }
-  const SolverScalars* s = dot ? c->dscal() : nullptr;
-  if (precision == MPL_F32) {
-    MPL_TRY(mpl_ensure(c, c->Y32, 4 * 9 * ncell));
-    const float inv4 = (float)(0.25 * c->inv_dx);
-    MPL_LAUNCH(c, k_hv_cells<float>, c->n_cblk, 64, (const float*)u, nnode, P<int>(c->c_nbr_node),
-               P<float>(c->Abar32), ncell, inv4, P<float>(c->Y32), s);
-    if (dot)
-      MPL_LAUNCH(c, (k_hv_nodes<float, true>), c->n_nblk, 64, (const float*)u, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<float>(c->Y32), ncell, nnode, inv4,
-                 (float*)Hu, partial_slot(c, 0), s);
-    else
-      MPL_LAUNCH(c, (k_hv_nodes<float, false>), c->n_nblk, 64, (const float*)u, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<float>(c->Y32), ncell, nnode, inv4,
-                 (float*)Hu, (double*)nullptr, s);
-  } else {
-    MPL_TRY(mpl_ensure(c, c->Y64, 8 * 9 * ncell));
-    const double inv4 = 0.25 * c->inv_dx;
-    MPL_LAUNCH(c, k_hv_cells<double>, c->n_cblk, 64, (const double*)u, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Abar64), ncell, inv4, P<double>(c->Y64), s);
-    if (dot)
-      MPL_LAUNCH(c, (k_hv_nodes<double, true>), c->n_nblk, 64, (const double*)u, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Y64), ncell, nnode, inv4,
-                 (double*)Hu, partial_slot(c, 0), s);
-    else
-      MPL_LAUNCH(c, (k_hv_nodes<double, false>), c->n_nblk, 64, (const double*)u, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Y64), ncell, nnode, inv4,
-                 (double*)Hu, (double*)nullptr, s);
-  }
+  const T inv4 = (T)(0.25 * c->inv_dx);
+  const int grid = ((c->n_cblk + 7) / 8) * 8;
+  if (dot)
+    MPL_LAUNCH(c, (k_hv_fused<T, true>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
+               P<T>(abar_buf<T>(c)), ncell, c->n_cblk, inv4, Hown, Hhalo, partial_slot(c, 0),
+               (const SolverScalars*)c->dscal());
+  else
+    MPL_LAUNCH(c, (k_hv_fused<T, false>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
+               P<T>(abar_buf<T>(c)), ncell, c->n_cblk, inv4, Hown, Hhalo, (double*)nullptr,
+               (const SolverScalars*)nullptr);
   if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
   return MPL_OK;
 }
 
-// Jacobi-PCG on H x = b over free DOFs (b, x block layout FP64).
-mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
-  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
-  const int prec = c->tangent_precision;
-  const int64_t nnode = (int64_t)c->nnode_alloc();
+// u, Hu in block layout, precision of the stored tangent.
+mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool dot) {
+  if (!c->tangent_built || c->tangent_precision != precision)
+    return mpl_fail(c, MPL_ERR_STATE, "Hv needs a tangent built in the same precision");
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  if (precision == MPL_F32) {
+    MPL_TRY(hv_pieces<float>(c, (const float*)u, dot));
+    const float* Hown = P<float>(c->Y32);
+    MPL_LAUNCH(c, k_hv_combine<float>, c->n_nblk, 64, (const float*)u, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode,
+               (float*)Hu);
+  } else {
+    MPL_TRY(hv_pieces<double>(c, (const double*)u, dot));
+    const double* Hown = P<double>(c->Y64);
+    MPL_LAUNCH(c, k_hv_combine<double>, c->n_nblk, 64, (const double*)u, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode,
+               (double*)Hu);
+  }
+  return MPL_OK;
+}
+
+// Jacobi-PCG on H x = b over free DOFs (b, x block layout FP64).  Per
+// iteration: fused product (p^T K p partials), alpha, update (x, r and the
+// assembled Hp), beta / convergence, new direction (p^T M p partials).
+// Iterations past convergence are no-ops on the device, so the host polls
+// the done flag only every pcg_check_every iterations.
+template <class T>
+static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(ensure_partials(c));
   MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  DevBuf& pb_ = pvec_buf<T>(c);
+  MPL_TRY(mpl_ensure(c, pb_, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, pieces_buf<T>(c), sizeof(T) * 6 * ncell));
+  T* p = P<T>(pb_);
+  const T* Hown = P<T>(pieces_buf<T>(c));
+  const T* Hhalo = Hown + 3 * ncell;
   SolverScalars* s = c->dscal();
+  double* pk = partial_slot(c, 0);
   double* pa = partial_slot(c, 1);
   double* pb = partial_slot(c, 2);
-  void* p;
-  void* q;
-  if (prec == MPL_F32) {
-    MPL_TRY(mpl_ensure(c, c->p32, 4 * 3 * nnode));
-    MPL_TRY(mpl_ensure(c, c->q32, 4 * 3 * nnode));
-    p = c->p32.p;
-    q = c->q32.p;
-    MPL_LAUNCH(c, k_pcg_init<float>, c->n_nblk, 64, b, P<double>(c->D), P<uint8_t>(c->flags), nnode, x,
-               P<double>(c->r), (float*)p, pa, pb);
-  } else {
-    MPL_TRY(mpl_ensure(c, c->p64, 8 * 3 * nnode));
-    MPL_TRY(mpl_ensure(c, c->q64, 8 * 3 * nnode));
-    p = c->p64.p;
-    q = c->q64.p;
-    MPL_LAUNCH(c, k_pcg_init<double>, c->n_nblk, 64, b, P<double>(c->D), P<uint8_t>(c->flags), nnode,
-               x, P<double>(c->r), (double*)p, pa, pb);
-  }
+  double* pm = partial_slot(c, 3);
+  MPL_LAUNCH(c, k_pcg_init<T>, c->n_nblk, 64, b, P<double>(c->D), P<double>(c->mi),
+             P<uint8_t>(c->flags), nnode, x, P<double>(c->r), p, pa, pb, pm);
   MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
   MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
   const int check = std::max(1, c->opts.pcg_check_every);
@@ -735,22 +863,14 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
   bool finished = false;
   while (!finished) {
     for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) {
-      MPL_TRY(mpl_stage_hv(c, p, q, prec, true));
-      MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, partial_slot(c, 0), c->n_nblk, pa, 0, pa, 0, s, 0);
-      if (prec == MPL_F32) {
-        MPL_LAUNCH(c, k_pcg_update<float>, c->n_nblk, 64, (const float*)p, (const float*)q,
-                   P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r), pa, pb, s);
-      } else {
-        MPL_LAUNCH(c, k_pcg_update<double>, c->n_nblk, 64, (const double*)p, (const double*)q,
-                   P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r), pa, pb, s);
-      }
+      MPL_TRY(hv_pieces<T>(c, p, true));
+      MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, c->n_nblk, pm, 0, s, 0);
+      MPL_LAUNCH(c, k_pcg_update<T>, c->n_nblk, 64, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+                 P<double>(c->mi), P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r),
+                 pa, pb, s);
       MPL_LAUNCH(c, k_reduce<RED_BETA>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
-      if (prec == MPL_F32)
-        MPL_LAUNCH(c, k_pcg_direction<float>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
-                   P<uint8_t>(c->flags), nnode, (float*)p, s);
-      else
-        MPL_LAUNCH(c, k_pcg_direction<double>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
-                   P<uint8_t>(c->flags), nnode, (double*)p, s);
+      MPL_LAUNCH(c, k_pcg_direction<T>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
+                 P<double>(c->mi), P<uint8_t>(c->flags), nnode, p, pm, s);
     }
     MPL_TRY(mpl_sync_scalars(c));
     if (c->hscal.done != 0 || it >= c->opts.max_pcg) finished = true;
@@ -761,6 +881,12 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
   if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)
     return mpl_fail(c, MPL_ERR_NONFINITE, "PCG breakdown (p.Hp <= 0 or not finite)");
   return MPL_OK;
+}
+
+mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
+  if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel);
+  return pcg_impl<double>(c, b, x, iters, rel);
 }
 
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {

@@ -190,9 +190,70 @@ enum {
   MPL_FIELD_VHAT = 9,     /* nodes, 3 */
   MPL_FIELD_FIXED = 10,   /* nodes, 1 (1.0 = Dirichlet) */
   MPL_FIELD_V = 11,       /* nodes, 3 (current Newton iterate / solution) */
-  MPL_FIELD_DIAG = 12     /* nodes, 3 (Jacobi diagonal) */
+  MPL_FIELD_DIAG = 12     /* nodes, 3 (inverse Jacobi diagonal; 0 on fixed/massless nodes) */
 };
 mpl_status mpl_export_field(mpl_ctx* ctx, int32_t field, double* dense_out);
+
+/* ---- learned preconditioner ----
+ *
+ * The paper solves the Newton systems with plain PCG (Alg. 3); this library
+ * adds an optional learned preconditioner for them.  A 4-level 3-D U-Net
+ * (channels 16/32/64/128; two 3x3x3 convolutions with ReLU per level and
+ * side, 2x2x2 stride-2 convolutions down, 2x2x2 stride-2 transposed
+ * convolutions up, skip concatenation, a final 1x1x1 convolution) runs on a
+ * dense box over all grid nodes (each axis padded up to a multiple of 8),
+ * with BF16 weights and activations and FP32 accumulation.  Input channels
+ * of node i (free nodes; zero elsewhere): D_i^{-1/2} r_i / s (3), the log of
+ * the node's mean diagonal over the free-node mean (1), 1 (1), 11 zero
+ * channels.  Output channels 0-2 = o_i; the preconditioned residual is
+ *   z_i = D_i^{-1} r_i + s D_i^{-1/2} o_i,   s^2 = sum_free D^{-1} r^2 / (free DOFs),
+ * with D the Jacobi diagonal.  Zero weights therefore give Jacobi.  Solves
+ * with precond = MPL_PRECOND_LEARNED use flexible CG (Polak-Ribiere beta) and
+ * switch to Jacobi for the rest of the solve when z.r <= 0, on NaN/Inf, or
+ * when |r| drops by less than 10% over 10 iterations (mpl_stats.fallbacks).
+ *
+ * Parameters are a flat FP32 vector: for each layer in execution order
+ * (enc0a enc0b down0 enc1a enc1b down1 enc2a enc2b down2 bota botb up2 dec2a
+ * dec2b up1 dec1a dec1b up0 dec0a dec0b out) W[tap][in][out] then bias[out],
+ * taps enumerated with the last spatial axis fastest.  Host pointers below
+ * are marked; all tensors are device pointers otherwise. */
+
+/* Number of FP32 parameters (*n, host). */
+mpl_status mpl_precond_param_count(mpl_ctx* ctx, int64_t* n);
+/* Copy n FP32 parameters from HOST memory; resets the optimiser state. */
+mpl_status mpl_precond_set_weights(mpl_ctx* ctx, const float* params_host, int64_t n);
+/* Copy the current FP32 parameters to HOST memory. */
+mpl_status mpl_precond_get_weights(mpl_ctx* ctx, float* params_host, int64_t n);
+/* Network forward on a dense box: x [X][Y][Z][16] FP32, dims = {X, Y, Z}
+ * (host, multiples of 8); y [X][Y][Z][16] FP32 (BF16-rounded values). */
+mpl_status mpl_nn_forward(mpl_ctx* ctx, const float* x, const int32_t dims[3], float* y);
+/* Parameter gradient (FP32, flat, device) of <dy, network(x)>. */
+mpl_status mpl_nn_backward(mpl_ctx* ctx, const float* x, const int32_t dims[3], const float* dy,
+                           float* grad);
+/* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the masked relative L2
+ * loss |m (y - t)|^2 / |m t|^2 over output channels 0-2: x [X][Y][Z][16],
+ * t [X][Y][Z][3], mask [X][Y][Z] (FP32, device).  *loss (host, may be NULL)
+ * receives the loss before the step. */
+mpl_status mpl_precond_train_step(mpl_ctx* ctx, const float* x, const float* t, const float* mask,
+                                  const int32_t dims[3], float lr, float* loss);
+/* z = learned preconditioner applied to r at the Jacobi diagonal of the last
+ * mpl_build_tangent (r, z dense device FP64 node vectors). */
+mpl_status mpl_precond_apply(mpl_ctx* ctx, const double* r, double* z);
+/* Allocate room for `capacity` training pairs on the current grid's box
+ * (weights must be set first; 48 bytes per box voxel and pair) and empty
+ * the store. */
+mpl_status mpl_precond_reserve(mpl_ctx* ctx, int32_t capacity);
+/* Collection mode for later mpl_solve / mpl_step calls (every = 0 turns it
+ * off): while the store has room, every Newton system is solved to rtol
+ * with Jacobi PCG, that solution is the Newton direction, and the same
+ * iteration is repeated to store (features of r_k, target
+ * D^{1/2}(x* - x_k - D^{-1} r_k)/s, free mask) every `every` iterations. */
+mpl_status mpl_precond_collect(mpl_ctx* ctx, int32_t every, double rtol);
+/* Number of stored training pairs (*n, host). */
+mpl_status mpl_precond_sample_count(mpl_ctx* ctx, int32_t* n);
+/* n_steps Adam steps on the stored pairs, visited in a pseudo-random order
+ * fixed by seed; losses (host, may be NULL) gets each step's loss. */
+mpl_status mpl_precond_train(mpl_ctx* ctx, int32_t n_steps, float lr, uint32_t seed, float* losses);
 
 #ifdef __cplusplus
 }

@@ -1099,6 +1099,42 @@ int or_explicit_force(const or_grid* gg, int32_t nmat, const double* Vck,
 // allowance) and the model's feasibility (Phi = +inf outside the domain).
 //   stop Newton when |g_free| <= newton_rtol * |g_free(vhat)|,
 //   stop CG when |b - H x| <= pcg_rtol * |b| (both 2-norms over free DOFs).
+// Diagonal of H = M + sum_c B_c^T Abar_c B_c on free DOFs (0 elsewhere):
+// entry (i, a) = m_i + sum over the cells c around node i of
+// sum_{b, b'} Abar_c[(a, b), (a, b')] dw_ic/dx_b dw_ic/dx_b'.
+int or_jacobi_diag(const or_grid* gg, const double* mc, const double* mi, const uint8_t* fixed,
+                   const double* Abar, double* D) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nn = g.nn();
+  std::fill(D, D + 3 * nn, 0.0);
+  for (int i = 0; i < g.n; ++i)
+    for (int j = 0; j < g.n; ++j)
+      for (int kk = 0; kk < g.n; ++kk) {
+        int64_t c = g.cell(i, j, kk);
+        if (mc[c] == 0.0) continue;
+        const double* Ac = Abar + 81 * c;
+        for (int d = 0; d < 8; ++d) {
+          int o[3];
+          corner(d, o);
+          int64_t nidx = g.node(i + o[0], j + o[1], kk + o[2]);
+          double gw[3];
+          grad_w(d, g.dx, gw);
+          for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < 3; ++b)
+              for (int b2 = 0; b2 < 3; ++b2) s += Ac[(a * 3 + b) * 9 + (a * 3 + b2)] * gw[b] * gw[b2];
+            D[3 * nidx + a] += s;
+          }
+        }
+      }
+  for (int64_t nidx = 0; nidx < nn; ++nidx)
+    for (int a = 0; a < 3; ++a) {
+      bool freed = mi[nidx] != 0.0 && !fixed[nidx];
+      D[3 * nidx + a] = freed ? D[3 * nidx + a] + mi[nidx] : 0.0;
+    }
+  return OR_OK;
+}
+
 int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
              const double* Vck, const double* Sck, const or_solver_opts* opts,
@@ -1130,32 +1166,7 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
     if (it >= opts->max_newton) { result = OR_ERR_NOT_CONVERGED; break; }
     or_tangent(gg, nmat, mats, dt, Vck, Sck, v, 1, Abar.data());
     // Jacobi preconditioner: diagonal of H.
-    std::fill(D.begin(), D.end(), 0.0);
-    for (int i = 0; i < g.n; ++i)
-      for (int j = 0; j < g.n; ++j)
-        for (int kk = 0; kk < g.n; ++kk) {
-          int64_t c = g.cell(i, j, kk);
-          if (mc[c] == 0.0) continue;
-          const double* Ac = Abar.data() + 81 * c;
-          for (int d = 0; d < 8; ++d) {
-            int o[3];
-            corner(d, o);
-            int64_t nidx = g.node(i + o[0], j + o[1], kk + o[2]);
-            double gw[3];
-            grad_w(d, g.dx, gw);
-            for (int a = 0; a < 3; ++a) {
-              double s = 0.0;
-              for (int b = 0; b < 3; ++b)
-                for (int b2 = 0; b2 < 3; ++b2) s += Ac[(a * 3 + b) * 9 + (a * 3 + b2)] * gw[b] * gw[b2];
-              D[3 * nidx + a] += s;
-            }
-          }
-        }
-    for (int64_t nidx = 0; nidx < nn; ++nidx)
-      for (int a = 0; a < 3; ++a) {
-        bool freed = mi[nidx] != 0.0 && !fixed[nidx];
-        D[3 * nidx + a] = freed ? D[3 * nidx + a] + mi[nidx] : 0.0;
-      }
+    or_jacobi_diag(gg, mc, mi, fixed, Abar.data(), D.data());
     // CG on H x = -g
     for (int64_t i = 0; i < nd; ++i) {
       x[i] = 0.0;

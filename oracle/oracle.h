@@ -104,6 +104,8 @@ int or_hv(const or_grid* g, const double* mc, const double* mi, const uint8_t* f
           const double* Abar, const double* u, double* Hu);
 int or_explicit_force(const or_grid* g, int32_t nmat, const double* Vck,
                       const double* tauck, double* f);
+int or_jacobi_diag(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,
+                   const double* Abar, double* D);
 int or_solve(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
              const double* Vck, const double* Sck, const or_solver_opts* opts,

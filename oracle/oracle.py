@@ -264,6 +264,15 @@ def hv(grid: Grid, mc, mi, fixed, Abar, u):
     return Hu
 
 
+def jacobi_diag(grid: Grid, mc, mi, fixed, Abar):
+    """Diagonal of the Newton matrix H on free DOFs (0 elsewhere), [nnode, 3]."""
+    D = np.zeros((grid.nnode, 3))
+    lib().or_jacobi_diag(C.byref(grid.c()), _p(_f64(mc)), _p(_f64(mi)),
+                         _p(np.ascontiguousarray(fixed, dtype=np.uint8), C.c_uint8), _p(_f64(Abar)),
+                         _p(D))
+    return D
+
+
 def explicit_force(grid: Grid, Vck, tauck):
     f = np.zeros((grid.nnode, 3))
     K = np.asarray(Vck).shape[0]

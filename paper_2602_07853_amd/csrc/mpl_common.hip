@@ -2,9 +2,11 @@
 // conversions.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "mpl_grid.h"
+#include "mpl_nn.h"
 
 using namespace mpl;
 
@@ -249,6 +251,8 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->dx = grid->dx;
   c->inv_dx = 1.0 / grid->dx;
   c->stream = (hipStream_t)hip_stream;
+  const char* ng = std::getenv("MPL_NO_GRAPHS");
+  c->graphs_enabled = !(ng && ng[0] == '1');
   mpl_status st = derive_materials(c, mats, n_mats);
   if (st == MPL_OK) st = check_opts(c, opts);
   if (st == MPL_OK) st = mpl_ensure(c, c->scal, sizeof(SolverScalars));
@@ -272,8 +276,13 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
                    &c->Y64, &c->vcl, &c->Gcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
-                   &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal};
+                   &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar};
   for (DevBuf* b : all) free_buf(*b);
+  nn_destroy(c);
+  for (GraphCache& gc : c->pcg_cache) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+  }
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);

@@ -34,11 +34,27 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
+struct NNState;
+
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[16] = {};
+  int keyn[6] = {0, 0, 0, 0, 0, 0};
+  int events = 0;
+};
 
 // Device-resident solver scalars (one instance per context).
 struct SolverScalars {
   double rz, rz_new, rr, pq, alpha, beta, bnorm2, tol2;
   double red[8];      // generic reduction outputs
+  // flexible CG with the learned preconditioner
+  double s2;          // sum over free DOFs of Dinv r^2 (network input scale)
+  double rr_mark;     // r.r at the last stagnation checkpoint
+  int32_t fallback;   // 1: switched to Jacobi
+  int32_t fb_new;     // 1: switched in this iteration (restart the direction)
+  int32_t nn_off;     // 1: skip the network (converged or fallen back)
+  int32_t fallbacks;  // number of switches (0 or 1 per solve)
   int32_t done;       // 0 running, 1 converged, 2 breakdown
   int32_t iters;
   int32_t err;        // binning / domain error flags
@@ -83,6 +99,19 @@ struct mpl_ctx {
   DevBuf scal;
   SolverScalars* dscal() const { return (SolverScalars*)scal.p; }
   SolverScalars hscal;
+
+  // captured PCG iteration chunks (replayed while the key matches); one
+  // cache per iteration kind (Jacobi, learned)
+  bool graphs_enabled = true;
+  GraphCache pcg_cache[2];
+  // training-pair collection during Newton solves (0 = off)
+  int collect_every = 0;
+  double collect_rtol = 1e-10;
+  DevBuf xstar;
+  int fallbacks_total = 0;
+
+  // learned preconditioner (allocated on first use)
+  NNState* nn = nullptr;
 
   // timing
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -133,6 +162,7 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u_block, void* Hu_block, int pre
 mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b_block, double* x_block, int* iters,
                          double* rel);
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st);
+mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* r_block, double* z_block);
 mpl_status mpl_stage_load(mpl_ctx* c, const double* v_block, const mpl_particles* in,
                           mpl_particles* out, double dt);
 // dense <-> block conversions for node vectors (3 comps) and scalars

@@ -1,0 +1,58 @@
+// Learned preconditioner network state (see mpl_nn.hip for the design).
+//
+// Parameter layout (FP32, flat): for each of the 21 layers in execution
+// order (enc0a, enc0b, down0, enc1a, enc1b, down1, enc2a, enc2b, down2,
+// bota, botb, up2, dec2a, dec2b, up1, dec1a, dec1b, up0, dec0a, dec0b, out)
+// the weight W[tap][in channel][out channel] followed by the bias[out channel];
+// taps of a k x k x k kernel are enumerated with the last axis fastest.
+#pragma once
+#include "mpl_internal.h"
+
+#define NN_LAYERS 21
+#define NN_WGRAD_CHUNK 4096
+
+struct NNSampleStore;
+struct NNState {
+  DevBuf params, grad, adam_m, adam_v, wsw, act, gact, wpart, lpart, tmp;
+  DevBuf dref;  // device scalar: mean diagonal over free nodes
+  NNSampleStore* store = nullptr;
+  // device flag: when nonzero the forward kernels return at once (set by the
+  // solver once its iteration has converged or fallen back to Jacobi)
+  const int32_t* skip = nullptr;
+  size_t sw_fwd_off[NN_LAYERS] = {}, sw_bwd_off[NN_LAYERS] = {};
+  int box[3] = {0, 0, 0};
+  size_t t_in = 0, t_out = 0, t_cat[3] = {0, 0, 0}, t_lay[NN_LAYERS] = {};
+  size_t act_elems = 0;
+  int64_t adam_t = 0;
+  bool ready = false;
+};
+
+int64_t nn_param_count();
+NNState* nn_state(mpl_ctx* c);
+void nn_destroy(mpl_ctx* c);
+mpl_status nn_forward(mpl_ctx* c, NNState& nn);
+mpl_status nn_backward(mpl_ctx* c, NNState& nn);
+
+// ---- the network as a preconditioner on the solver grid ----
+double nn_inv_free_dofs(mpl_ctx* c);
+// The box covers all grid nodes (voxel (i,j,k) = node (i,j,k)), each axis
+// padded to a multiple of 8.  Input channels: 0-2 = sqrt(Dinv) r / s,
+// 3 = log(Dmean_i / Dref), 4 = 1 on free nodes; output channels 0-2 = o,
+// and the preconditioner is z = Dinv r + s sqrt(Dinv) o on free nodes, with
+// s^2 = sum_free Dinv r^2 / (free DOFs).
+struct NNSampleStore {
+  DevBuf feat;    // [n][voxels][16] bf16
+  DevBuf target;  // [n][voxels][3] f32
+  DevBuf mask;    // [n][voxels] f32
+  int count = 0, capacity = 0;
+  int64_t voxels = 0;
+};
+mpl_status nn_prepare_box(mpl_ctx* c, bool train);
+mpl_status nn_set_dref(mpl_ctx* c, const double* Dinv);
+// stage features of r into the network input; s2 = device scalar sum Dinv r^2
+mpl_status nn_stage_features(mpl_ctx* c, const double* r, const double* Dinv, const double* s2);
+// record a training pair from (r, e = xstar - x): features of r, target
+// sqrt(D)(e - Dinv r)/s, mask of free nodes
+mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const double* xstar,
+                            const double* Dinv, const double* s2);
+NNSampleStore& nn_samples(mpl_ctx* c);

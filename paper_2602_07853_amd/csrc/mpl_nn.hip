@@ -1,0 +1,1106 @@
+// Learned preconditioner: a 4-level 3-D U-Net (channels 16/32/64/128, two
+// 3x3x3 convolutions per level and side, 2x2x2 stride-2 down/up sampling,
+// skip concatenation, ReLU) on a dense box over the grid nodes, with BF16
+// activations and weights and FP32 accumulation on MFMA
+// (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam.
+//
+// Tensors are channels-last views (ptr, ldc): channel c of voxel v is at
+// ptr[v*ldc + c], voxel v = (i*Y + j)*Z + k.  Skip concatenation is a
+// layout choice: the encoder writes its output into the upper channel half
+// of the decoder's input tensor and the up-sampling layer into the lower
+// half, so no copy is made.
+//
+// GEMM orientation (all convolutions): D[m = out channel][n = voxel] +=
+// A[m][k] B[k][n] with k enumerating (tap, in channel), in channel fastest.
+// A is the weight, pre-swizzled so that every lane loads its 8 bf16 with one
+// 16-byte load; B is 8 consecutive channels of one voxel (16 bytes); each
+// lane of D holds 4 consecutive output channels of one voxel.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mpl_grid.h"
+#include "mpl_nn.h"
+
+using namespace mpl;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct Dims3 {
+  int x, y, z;
+};
+
+// ---------------------------------------------------------------- gather conv
+// y[v, o] = act(b[o] + sum_{t, i} x[s v + t - p, i] W[t, i, o]) (+ y if accum)
+// One wavefront computes VT tiles of 16 consecutive output voxels x all CT*16
+// output channels.  Wsw: [kstep][CT][64 lanes][8] bf16.
+template <int CT, int VT>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, int ldx, Dims3 din,
+                                              const uint16_t* __restrict__ Wsw, int nk, int Ci,
+                                              int ktaps, int ks, int stride, int pad,
+                                              const float* __restrict__ bias,
+                                              uint16_t* __restrict__ y, int ldy, Dims3 dout,
+                                              int relu, int accum, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nvox = (int64_t)dout.x * dout.y * dout.z;
+  const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * (VT * 16);
+  if (vbase >= nvox) return;
+  int vi[VT][3];
+  bool vok[VT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    const int64_t v = vbase + t * 16 + (lane & 15);
+    vok[t] = v < nvox;
+    const int64_t vv = vok[t] ? v : 0;
+    vi[t][2] = (int)(vv % dout.z);
+    vi[t][1] = (int)((vv / dout.z) % dout.y);
+    vi[t][0] = (int)(vv / ((int64_t)dout.z * dout.y));
+  }
+  f32x4 acc[VT][CT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ksub = (lane >> 4) * 8;
+  for (int kstep = 0; kstep < nk; ++kstep) {
+    const int kk = kstep * 32 + ksub;
+    const int tap = kk / Ci, c0 = kk - tap * Ci;
+    const int tx = tap / (ks * ks), ty = (tap / ks) % ks, tz = tap % ks;
+    bf16x8 bop[VT];
+#pragma unroll
+    for (int t = 0; t < VT; ++t) {
+      const int ix = vi[t][0] * stride + tx - pad, iy = vi[t][1] * stride + ty - pad,
+                iz = vi[t][2] * stride + tz - pad;
+      uint4 raw = make_uint4(0, 0, 0, 0);
+      if (tap < ktaps && vok[t] && ix >= 0 && iy >= 0 && iz >= 0 && ix < din.x && iy < din.y &&
+          iz < din.z) {
+        const int64_t src = (((int64_t)ix * din.y + iy) * din.z + iz) * ldx + c0;
+        raw = *reinterpret_cast<const uint4*>(x + src);
+      }
+      bop[t] = __builtin_bit_cast(bf16x8, raw);
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const uint4 wr = *reinterpret_cast<const uint4*>(Wsw + (((int64_t)kstep * CT + c) * 64 + lane) * 8);
+      const bf16x8 aop = __builtin_bit_cast(bf16x8, wr);
+#pragma unroll
+      for (int t = 0; t < VT; ++t)
+        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[t], acc[t][c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    if (!vok[t]) continue;
+    const int64_t v = vbase + t * 16 + (lane & 15);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int o0 = c * 16 + (lane >> 4) * 4;
+      uint16_t* dst = y + v * ldy + o0;
+      float r[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float val = acc[t][c][e] + (bias ? bias[o0 + e] : 0.f);
+        if (accum) val += bf2f(dst[e]);
+        if (relu) val = fmaxf(val, 0.f);
+        r[e] = val;
+      }
+      const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                      (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+      *reinterpret_cast<uint2*>(dst) = packed;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- up conv
+// y[2 v + t, o] = act(b[o] + sum_i x[v, i] W[t, i, o]) (+ y if accum); the
+// tap t is blockIdx.y so that all 16 voxels of an MFMA share the weight.
+// Wsw: [t][kstep][CT][64][8].
+template <int CT, int VT>
+__global__ __launch_bounds__(256) void k_up(const uint16_t* __restrict__ x, int ldx, Dims3 din,
+                                            const uint16_t* __restrict__ Wsw, int nk,
+                                            const float* __restrict__ bias,
+                                            uint16_t* __restrict__ y, int ldy, int relu,
+                                            int accum, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tap = blockIdx.y;
+  const int tx = tap >> 2, ty = (tap >> 1) & 1, tz = tap & 1;
+  const int64_t nvox = (int64_t)din.x * din.y * din.z;
+  const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * (VT * 16);
+  if (vbase >= nvox) return;
+  f32x4 acc[VT][CT];
+#pragma unroll
+  for (int t = 0; t < VT; ++t)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ksub = (lane >> 4) * 8;
+  for (int kstep = 0; kstep < nk; ++kstep) {
+    bf16x8 bop[VT];
+#pragma unroll
+    for (int t = 0; t < VT; ++t) {
+      const int64_t v = vbase + t * 16 + (lane & 15);
+      uint4 raw = make_uint4(0, 0, 0, 0);
+      if (v < nvox) raw = *reinterpret_cast<const uint4*>(x + v * ldx + kstep * 32 + ksub);
+      bop[t] = __builtin_bit_cast(bf16x8, raw);
+    }
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const uint4 wr = *reinterpret_cast<const uint4*>(
+          Wsw + ((((int64_t)tap * nk + kstep) * CT + c) * 64 + lane) * 8);
+      const bf16x8 aop = __builtin_bit_cast(bf16x8, wr);
+#pragma unroll
+      for (int t = 0; t < VT; ++t)
+        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[t], acc[t][c], 0, 0, 0);
+    }
+  }
+  const Dims3 dout{2 * din.x, 2 * din.y, 2 * din.z};
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    const int64_t v = vbase + t * 16 + (lane & 15);
+    if (v >= nvox) continue;
+    const int k = (int)(v % din.z), j = (int)((v / din.z) % din.y), i = (int)(v / ((int64_t)din.z * din.y));
+    const int64_t u = (((int64_t)(2 * i + tx) * dout.y + (2 * j + ty)) * dout.z + (2 * k + tz));
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int o0 = c * 16 + (lane >> 4) * 4;
+      uint16_t* dst = y + u * ldy + o0;
+      float r[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float val = acc[t][c][e] + (bias ? bias[o0 + e] : 0.f);
+        if (accum) val += bf2f(dst[e]);
+        if (relu) val = fmaxf(val, 0.f);
+        r[e] = val;
+      }
+      const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                      (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+      *reinterpret_cast<uint2*>(dst) = packed;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- wgrad
+// Partial weight gradient of one (tap, in-channel tile, out-channel tile)
+// over a chunk of output voxels:
+//   gather conv: dW[t, i, o] += sum_u x[s u + t - p, i] dy[u, o]
+//   up conv:     dW[t, i, o] += sum_v x[v, i] dy[2 v + t, o]
+// D[m = i][n = o] with the voxel sum as the MFMA K dimension.
+__global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ x, int ldx, Dims3 din,
+                                              const uint16_t* __restrict__ dy, int ldy,
+                                              Dims3 dout, int Ci, int Co, int ks, int stride,
+                                              int pad, int is_up, int chunk,
+                                              float* __restrict__ part) {
+  const int lane = threadIdx.x;
+  const int CiT = Ci / 16, CoT = Co / 16;
+  const int job = blockIdx.y;
+  const int ot = job % CoT, it = (job / CoT) % CiT, tap = job / (CoT * CiT);
+  const int tx = tap / (ks * ks), ty = (tap / ks) % ks, tz = tap % ks;
+  // the voxels summed over: output voxels u (gather) or input voxels v (up)
+  const Dims3 vd = is_up ? din : dout;
+  const int64_t nv = (int64_t)vd.x * vd.y * vd.z;
+  const int64_t v0 = (int64_t)blockIdx.x * chunk;
+  const int64_t v1 = (v0 + chunk < nv) ? v0 + chunk : nv;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int ci = it * 16 + (lane & 15), co = ot * 16 + (lane & 15);
+  for (int64_t vb = v0; vb < v1; vb += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t v = vb + (lane >> 4) * 8 + e;
+      float xa = 0.f, gb = 0.f;
+      if (v < v1) {
+        const int k = (int)(v % vd.z), j = (int)((v / vd.z) % vd.y), i = (int)(v / ((int64_t)vd.z * vd.y));
+        if (is_up) {
+          xa = bf2f(x[v * ldx + ci]);
+          const int64_t u = (((int64_t)(2 * i + tx) * dout.y + (2 * j + ty)) * dout.z + (2 * k + tz));
+          gb = bf2f(dy[u * ldy + co]);
+        } else {
+          const int ix = i * stride + tx - pad, iy = j * stride + ty - pad, iz = k * stride + tz - pad;
+          if (ix >= 0 && iy >= 0 && iz >= 0 && ix < din.x && iy < din.y && iz < din.z)
+            xa = bf2f(x[(((int64_t)ix * din.y + iy) * din.z + iz) * ldx + ci]);
+          gb = bf2f(dy[v * ldy + co]);
+        }
+      }
+      a[e] = (__bf16)xa;
+      b[e] = (__bf16)gb;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  // lane holds D[i = (lane>>4)*4 + e][o = lane & 15]
+  float* dst = part + ((int64_t)blockIdx.x * gridDim.y + job) * 256;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) dst[((lane >> 4) * 4 + e) * 16 + (lane & 15)] = acc[e];
+}
+
+// dW[t][i][o] (flat, added to grad) = sum over chunks of the partial tiles.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int njobs, int Ci,
+                               int Co, float* __restrict__ gW) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)njobs * 256;
+  if (idx >= total) return;
+  const int job = (int)(idx / 256), e = (int)(idx % 256);
+  const int CiT = Ci / 16, CoT = Co / 16;
+  const int ot = job % CoT, it = (job / CoT) % CiT, tap = job / (CoT * CiT);
+  const int i = it * 16 + e / 16, o = ot * 16 + e % 16;
+  float s = 0.f;
+  for (int c = 0; c < nchunks; ++c) s += part[((int64_t)c * njobs + job) * 256 + e];
+  gW[((int64_t)tap * Ci + i) * Co + o] += s;
+}
+
+// db[o] += sum_u dy[u, o] (one workgroup per output channel, fixed order).
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int ldy,
+                                                   int64_t nvox, float* __restrict__ gb) {
+  __shared__ float sh[256];
+  const int o = blockIdx.x;
+  float s = 0.f;
+  for (int64_t v = threadIdx.x; v < nvox; v += 256) s += bf2f(dy[v * ldy + o]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gb[o] += sh[0];
+}
+
+// g <- g * (y > 0) over C channels of strided views.
+__global__ void k_relu_bwd(uint16_t* __restrict__ g, int ldg, const uint16_t* __restrict__ y, int ldy,
+                           int C, int64_t nvox) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nvox * C) return;
+  const int64_t v = idx / C;
+  const int c = (int)(idx % C);
+  if (!(bf2f(y[v * ldy + c]) > 0.f)) g[v * ldg + c] = 0;
+}
+
+// Swizzle FP32 weights into the MFMA A-operand layout.
+//   mode 0 (forward):      A[m = o][k = (t, i)] = W[t][i][o]
+//   mode 1 (conv dgrad):   A[m = i][k = (t', o)] = W[T-1-t'][i][o]   (flipped taps)
+//   mode 2 (transposed):   A[m = i][k = (t, o)]  = W[t][i][o]
+// per_tap: the K dimension restarts at every tap (up-type layers).
+__global__ void k_swizzle(const float* __restrict__ W, int T, int Ci, int Co, int mode, int per_tap,
+                          int nk, int CT, uint16_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)nk * CT * 64 * 8;
+  const int64_t total = per * (per_tap ? T : 1);
+  if (idx >= total) return;
+  const int tap_blk = per_tap ? (int)(idx / per) : 0;
+  int64_t r = idx % per;
+  const int e = (int)(r % 8);
+  r /= 8;
+  const int lane = (int)(r % 64);
+  r /= 64;
+  const int ct = (int)(r % CT);
+  const int kstep = (int)(r / CT);
+  const int m = ct * 16 + (lane & 15);
+  const int k = kstep * 32 + (lane >> 4) * 8 + e;
+  const int Kin = (mode == 0) ? Ci : Co;  // channels along K
+  const int M = (mode == 0) ? Co : Ci;
+  float val = 0.f;
+  const int tap = per_tap ? tap_blk : k / Kin;
+  const int kc = per_tap ? k : k % Kin;
+  if (m < M && tap < T && kc < Kin) {
+    if (mode == 0) val = W[((int64_t)tap * Ci + kc) * Co + m];
+    else if (mode == 1) val = W[((int64_t)(T - 1 - tap) * Ci + m) * Co + kc];
+    else val = W[((int64_t)tap * Ci + m) * Co + kc];
+  }
+  out[idx] = f2bf(val);
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  if (!isfinite(gi)) return;
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = f2bf(a[i]);
+}
+__global__ void k_bf16_to_f32(const uint16_t* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = bf2f(a[i]);
+}
+
+// Masked relative L2 loss on channels 0..2 and its gradient w.r.t. y:
+//   L = |m (y - t)|^2 / |m t|^2,   dL/dy = 2 m^2 (y - t) / |m t|^2.
+// Pass 1: partial sums of numerator and denominator per workgroup.
+__global__ __launch_bounds__(256) void k_loss_partial(const uint16_t* __restrict__ y, int ldy,
+                                                      const float* __restrict__ t,
+                                                      const float* __restrict__ mask, int64_t nvox,
+                                                      double* __restrict__ part) {
+  __shared__ double sn[256], sd[256];
+  double num = 0.0, den = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * 256) {
+    const float mv = mask[v];
+    for (int c = 0; c < 3; ++c) {
+      const double d = (double)(bf2f(y[v * ldy + c]) - t[v * 3 + c]) * mv;
+      const double tt = (double)t[v * 3 + c] * mv;
+      num += d * d;
+      den += tt * tt;
+    }
+  }
+  sn[threadIdx.x] = num;
+  sd[threadIdx.x] = den;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      sn[threadIdx.x] += sn[threadIdx.x + off];
+      sd[threadIdx.x] += sd[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sn[0];
+    part[2 * blockIdx.x + 1] = sd[0];
+  }
+}
+__global__ void k_loss_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < n; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  out[0] = a;
+  out[1] = b;
+  out[2] = b > 0.0 ? a / b : 0.0;
+}
+__global__ void k_loss_grad(const uint16_t* __restrict__ y, int ldy, const float* __restrict__ t,
+                            const float* __restrict__ mask, int64_t nvox,
+                            const double* __restrict__ sums, uint16_t* __restrict__ g, int ldg) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvox) return;
+  const double den = sums[1];
+  const float mv = mask[v];
+  for (int c = 0; c < ldg; ++c) {
+    float val = 0.f;
+    if (c < 3 && den > 0.0) val = (float)(2.0 * mv * mv * (bf2f(y[v * ldy + c]) - t[v * 3 + c]) / den);
+    g[v * ldg + c] = f2bf(val);
+  }
+}
+
+}  // namespace
+
+// ======================================================================
+// Layer table (shared with the parameter layout documented in mpl_nn.h).
+namespace {
+struct Spec {
+  const char* name;
+  int up;       // 1: 2x2x2 stride-2 transposed convolution
+  int k, s, p;  // gather conv kernel size, stride, padding
+  int ci, co, relu, level_in, level_out;
+};
+const Spec kSpec[NN_LAYERS] = {
+    {"enc0a", 0, 3, 1, 1, 16, 16, 1, 0, 0},   {"enc0b", 0, 3, 1, 1, 16, 16, 1, 0, 0},
+    {"down0", 0, 2, 2, 0, 16, 32, 1, 0, 1},   {"enc1a", 0, 3, 1, 1, 32, 32, 1, 1, 1},
+    {"enc1b", 0, 3, 1, 1, 32, 32, 1, 1, 1},   {"down1", 0, 2, 2, 0, 32, 64, 1, 1, 2},
+    {"enc2a", 0, 3, 1, 1, 64, 64, 1, 2, 2},   {"enc2b", 0, 3, 1, 1, 64, 64, 1, 2, 2},
+    {"down2", 0, 2, 2, 0, 64, 128, 1, 2, 3},  {"bota", 0, 3, 1, 1, 128, 128, 1, 3, 3},
+    {"botb", 0, 3, 1, 1, 128, 128, 1, 3, 3},  {"up2", 1, 2, 2, 0, 128, 64, 1, 3, 2},
+    {"dec2a", 0, 3, 1, 1, 128, 64, 1, 2, 2},  {"dec2b", 0, 3, 1, 1, 64, 64, 1, 2, 2},
+    {"up1", 1, 2, 2, 0, 64, 32, 1, 2, 1},     {"dec1a", 0, 3, 1, 1, 64, 32, 1, 1, 1},
+    {"dec1b", 0, 3, 1, 1, 32, 32, 1, 1, 1},   {"up0", 1, 2, 2, 0, 32, 16, 1, 1, 0},
+    {"dec0a", 0, 3, 1, 1, 32, 16, 1, 0, 0},   {"dec0b", 0, 3, 1, 1, 16, 16, 1, 0, 0},
+    {"out", 0, 1, 1, 0, 16, 16, 0, 0, 0}};
+
+int taps_of(const Spec& s) { return s.k * s.k * s.k; }
+}  // namespace
+
+int64_t nn_param_count() {
+  int64_t n = 0;
+  for (int l = 0; l < NN_LAYERS; ++l) n += (int64_t)taps_of(kSpec[l]) * kSpec[l].ci * kSpec[l].co + kSpec[l].co;
+  return n;
+}
+
+static int64_t w_offset(int layer) {
+  int64_t n = 0;
+  for (int l = 0; l < layer; ++l) n += (int64_t)taps_of(kSpec[l]) * kSpec[l].ci * kSpec[l].co + kSpec[l].co;
+  return n;
+}
+
+static mpl_status nn_alloc(mpl_ctx* c, NNState& nn) {
+  const int64_t np = nn_param_count();
+  MPL_TRY(mpl_ensure(c, nn.params, 4 * np));
+  MPL_TRY(mpl_ensure(c, nn.grad, 4 * np));
+  MPL_TRY(mpl_ensure(c, nn.adam_m, 4 * np));
+  MPL_TRY(mpl_ensure(c, nn.adam_v, 4 * np));
+  // swizzled weights: forward and backward copies per layer
+  size_t sw = 0;
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const Spec& s = kSpec[l];
+    const int T = taps_of(s);
+    const size_t kf = s.up ? (size_t)T * ((s.ci + 31) / 32) * (s.co / 16) : ((size_t)(T * s.ci + 31) / 32) * (s.co / 16);
+    const size_t kb = s.up ? ((size_t)(T * s.co + 31) / 32) * (s.ci / 16) : (size_t)(T + 1) * ((s.co + 31) / 32) * (s.ci / 16);
+    nn.sw_fwd_off[l] = sw;
+    sw += kf * 64 * 8;
+    nn.sw_bwd_off[l] = sw;
+    sw += kb * 64 * 8;
+  }
+  MPL_TRY(mpl_ensure(c, nn.wsw, 2 * sw + 256));
+  return MPL_OK;
+}
+
+// Upload FP32 parameters, build the swizzled BF16 copies.
+static mpl_status nn_refresh(mpl_ctx* c, NNState& nn) {
+  const float* P = (const float*)nn.params.p;
+  uint16_t* sw = (uint16_t*)nn.wsw.p;
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const Spec& s = kSpec[l];
+    const int T = taps_of(s);
+    const float* W = P + w_offset(l);
+    if (s.up) {
+      const int nk = (s.ci + 31) / 32, CT = s.co / 16;
+      const int64_t tot = (int64_t)T * nk * CT * 512;
+      MPL_LAUNCH(c, k_swizzle, (int)((tot + 255) / 256), 256, W, T, s.ci, s.co, 0, 1, nk, CT,
+                 sw + nn.sw_fwd_off[l]);
+      // dgrad of an up layer is a 2x2x2 stride-2 gather conv with A[m=i][k=(t,o)]
+      const int nkb = (T * s.co + 31) / 32, CTb = s.ci / 16;
+      const int64_t totb = (int64_t)nkb * CTb * 512;
+      MPL_LAUNCH(c, k_swizzle, (int)((totb + 255) / 256), 256, W, T, s.ci, s.co, 2, 0, nkb, CTb,
+                 sw + nn.sw_bwd_off[l]);
+    } else {
+      const int nk = (T * s.ci + 31) / 32, CT = s.co / 16;
+      const int64_t tot = (int64_t)nk * CT * 512;
+      MPL_LAUNCH(c, k_swizzle, (int)((tot + 255) / 256), 256, W, T, s.ci, s.co, 0, 0, nk, CT,
+                 sw + nn.sw_fwd_off[l]);
+      if (s.k == 2) {
+        // dgrad of a stride-2 down conv is an up-type layer with A[m=i][k=(t,o)], K per tap
+        const int nkb = (s.co + 31) / 32, CTb = s.ci / 16;
+        const int64_t totb = (int64_t)T * nkb * CTb * 512;
+        MPL_LAUNCH(c, k_swizzle, (int)((totb + 255) / 256), 256, W, T, s.ci, s.co, 2, 1, nkb, CTb,
+                   sw + nn.sw_bwd_off[l]);
+      } else {
+        const int nkb = (T * s.co + 31) / 32, CTb = s.ci / 16;
+        const int64_t totb = (int64_t)nkb * CTb * 512;
+        MPL_LAUNCH(c, k_swizzle, (int)((totb + 255) / 256), 256, W, T, s.ci, s.co, 1, 0, nkb, CTb,
+                   sw + nn.sw_bwd_off[l]);
+      }
+    }
+  }
+  nn.ready = true;
+  return MPL_OK;
+}
+
+// Activation buffers for a box of dims (multiples of 8).
+static mpl_status nn_buffers(mpl_ctx* c, NNState& nn, const int* dims, bool train) {
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] <= 0 || dims[a] % 8 != 0) return mpl_fail(c, MPL_ERR_INVALID_ARG, "network box dims must be multiples of 8");
+  for (int a = 0; a < 3; ++a) nn.box[a] = dims[a];
+  int64_t V[4];
+  for (int L = 0; L < 4; ++L) V[L] = (int64_t)(dims[0] >> L) * (dims[1] >> L) * (dims[2] >> L);
+  // one tensor per layer output, except the skip outputs (upper half of the
+  // level's concatenation tensor) and the up-sampling outputs (lower half)
+  const int C[4] = {16, 32, 64, 128};
+  size_t off = 0;
+  auto place = [&](size_t& o, int64_t n) {
+    o = off;
+    off += (size_t)((n + 63) / 64) * 64;
+  };
+  place(nn.t_in, V[0] * 16);
+  for (int L = 0; L < 3; ++L) place(nn.t_cat[L], V[L] * 2 * C[L]);
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const Spec& s = kSpec[l];
+    const std::string n = s.name;
+    if (n == "enc0b" || n == "enc1b" || n == "enc2b" || s.up) continue;
+    place(nn.t_lay[l], V[s.level_out] * s.co);
+  }
+  nn.t_out = nn.t_lay[NN_LAYERS - 1];
+  nn.act_elems = off;
+  MPL_TRY(mpl_ensure(c, nn.act, 2 * off + 256));
+  if (train) {
+    MPL_TRY(mpl_ensure(c, nn.gact, 2 * off + 256));
+    // wgrad partials: worst layer
+    size_t worst = 0;
+    for (int l = 0; l < NN_LAYERS; ++l) {
+      const Spec& s = kSpec[l];
+      const int64_t nv = s.up ? V[s.level_in] : V[s.level_out];
+      const int64_t chunks = (nv + NN_WGRAD_CHUNK - 1) / NN_WGRAD_CHUNK;
+      const size_t jobs = (size_t)taps_of(s) * (s.ci / 16) * (s.co / 16);
+      worst = std::max(worst, (size_t)chunks * jobs * 256);
+    }
+    MPL_TRY(mpl_ensure(c, nn.wpart, 4 * worst + 256));
+    MPL_TRY(mpl_ensure(c, nn.lpart, 8 * 2 * 1024 + 64));
+  }
+  return MPL_OK;
+}
+
+struct View {
+  uint16_t* p;
+  int ld;
+};
+
+// Input and output views of layer l in the activation arena A (the same
+// offsets address the gradient arena).
+static View out_view(const NNState& nn, uint16_t* A, int l) {
+  const int C[4] = {16, 32, 64, 128};
+  const Spec& s = kSpec[l];
+  const std::string n = s.name;
+  if (n == "enc0b") return View{A + nn.t_cat[0] + C[0], 2 * C[0]};
+  if (n == "enc1b") return View{A + nn.t_cat[1] + C[1], 2 * C[1]};
+  if (n == "enc2b") return View{A + nn.t_cat[2] + C[2], 2 * C[2]};
+  if (s.up) return View{A + nn.t_cat[s.level_out], 2 * C[s.level_out]};
+  return View{A + nn.t_lay[l], s.co};
+}
+static void layer_views(const NNState& nn, uint16_t* A, int l, View& in, View& out) {
+  const int C[4] = {16, 32, 64, 128};
+  const Spec& s = kSpec[l];
+  const std::string n = s.name;
+  out = out_view(nn, A, l);
+  if (l == 0) in = View{A + nn.t_in, 16};
+  else if (n == "down0") in = out_view(nn, A, 1);
+  else if (n == "down1") in = out_view(nn, A, 4);
+  else if (n == "down2") in = out_view(nn, A, 7);
+  else if (n == "dec2a") in = View{A + nn.t_cat[2], 2 * C[2]};
+  else if (n == "dec1a") in = View{A + nn.t_cat[1], 2 * C[1]};
+  else if (n == "dec0a") in = View{A + nn.t_cat[0], 2 * C[0]};
+  else in = out_view(nn, A, l - 1);
+}
+
+static Dims3 level_dims(const NNState& nn, int L) {
+  return Dims3{nn.box[0] >> L, nn.box[1] >> L, nn.box[2] >> L};
+}
+
+template <int CT>
+static mpl_status launch_conv_ct(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk, int Ci,
+                                 int T, int ks, int s, int p, const float* bias, View out,
+                                 Dims3 dout, int relu, int accum, const int32_t* skip) {
+  constexpr int VT = (CT <= 1) ? 4 : (CT <= 2 ? 2 : 1);
+  const int64_t nv = (int64_t)dout.x * dout.y * dout.z;
+  const int64_t per_wg = 4 * VT * 16;
+  MPL_LAUNCH(c, (k_conv<CT, VT>), (int)((nv + per_wg - 1) / per_wg), 256, in.p, in.ld, din, wsw, nk,
+             Ci, T, ks, s, p, bias, out.p, out.ld, dout, relu, accum, skip);
+  return MPL_OK;
+}
+static mpl_status launch_conv(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk, int Ci,
+                              int Co, int T, int ks, int s, int p, const float* bias, View out,
+                              Dims3 dout, int relu, int accum, const int32_t* skip = nullptr) {
+  switch (Co / 16) {
+    case 1: return launch_conv_ct<1>(c, in, din, wsw, nk, Ci, T, ks, s, p, bias, out, dout, relu, accum, skip);
+    case 2: return launch_conv_ct<2>(c, in, din, wsw, nk, Ci, T, ks, s, p, bias, out, dout, relu, accum, skip);
+    case 4: return launch_conv_ct<4>(c, in, din, wsw, nk, Ci, T, ks, s, p, bias, out, dout, relu, accum, skip);
+    case 8: return launch_conv_ct<8>(c, in, din, wsw, nk, Ci, T, ks, s, p, bias, out, dout, relu, accum, skip);
+  }
+  return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
+}
+template <int CT>
+static mpl_status launch_up_ct(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk,
+                               const float* bias, View out, int relu, int accum, const int32_t* skip) {
+  constexpr int VT = (CT <= 1) ? 4 : (CT <= 2 ? 2 : 1);
+  const int64_t nv = (int64_t)din.x * din.y * din.z;
+  const int64_t per_wg = 4 * VT * 16;
+  hipLaunchKernelGGL((k_up<CT, VT>), dim3((unsigned)((nv + per_wg - 1) / per_wg), 8), dim3(256), 0,
+                     c->stream, in.p, in.ld, din, wsw, nk, bias, out.p, out.ld, relu, accum, skip);
+  MPL_HIP(c, hipGetLastError());
+  return MPL_OK;
+}
+static mpl_status launch_up(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk, int Co,
+                            const float* bias, View out, int relu, int accum,
+                            const int32_t* skip = nullptr) {
+  switch (Co / 16) {
+    case 1: return launch_up_ct<1>(c, in, din, wsw, nk, bias, out, relu, accum, skip);
+    case 2: return launch_up_ct<2>(c, in, din, wsw, nk, bias, out, relu, accum, skip);
+    case 4: return launch_up_ct<4>(c, in, din, wsw, nk, bias, out, relu, accum, skip);
+    case 8: return launch_up_ct<8>(c, in, din, wsw, nk, bias, out, relu, accum, skip);
+  }
+  return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
+}
+
+// Forward pass on the tensors already staged in nn.act (input at t_in).
+mpl_status nn_forward(mpl_ctx* c, NNState& nn) {
+  uint16_t* A = (uint16_t*)nn.act.p;
+  const uint16_t* sw = (const uint16_t*)nn.wsw.p;
+  const float* P = (const float*)nn.params.p;
+  for (int l = 0; l < NN_LAYERS; ++l) {
+    const Spec& s = kSpec[l];
+    const int T = taps_of(s);
+    View in, out;
+    layer_views(nn, A, l, in, out);
+    const float* bias = P + w_offset(l) + (int64_t)T * s.ci * s.co;
+    const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
+    if (s.up) {
+      MPL_TRY(launch_up(c, in, din, sw + nn.sw_fwd_off[l], (s.ci + 31) / 32, s.co, bias, out, s.relu, 0,
+                        nn.skip));
+    } else {
+      MPL_TRY(launch_conv(c, in, din, sw + nn.sw_fwd_off[l], (T * s.ci + 31) / 32, s.ci, s.co, T, s.k,
+                          s.s, s.p, bias, out, dout, s.relu, 0, nn.skip));
+    }
+  }
+  return MPL_OK;
+}
+
+// Backward pass: the gradient w.r.t. the output must be staged at
+// gact[t_out]; parameter gradients are ADDED into nn.grad.
+mpl_status nn_backward(mpl_ctx* c, NNState& nn) {
+  uint16_t* A = (uint16_t*)nn.act.p;
+  uint16_t* G = (uint16_t*)nn.gact.p;
+  const uint16_t* sw = (const uint16_t*)nn.wsw.p;
+  float* grad = (float*)nn.grad.p;
+  float* part = (float*)nn.wpart.p;
+  for (int l = NN_LAYERS - 1; l >= 0; --l) {
+    const Spec& s = kSpec[l];
+    const int T = taps_of(s);
+    View in, out, gin, gout;
+    layer_views(nn, A, l, in, out);
+    layer_views(nn, G, l, gin, gout);
+    const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
+    const int64_t nvo = (int64_t)dout.x * dout.y * dout.z;
+    if (s.relu)
+      MPL_LAUNCH(c, k_relu_bwd, (int)((nvo * s.co + 255) / 256), 256, gout.p, gout.ld, out.p, out.ld,
+                 s.co, nvo);
+    // parameter gradients
+    float* gW = grad + w_offset(l);
+    float* gb = gW + (int64_t)T * s.ci * s.co;
+    {
+      const int64_t nv = s.up ? (int64_t)din.x * din.y * din.z : nvo;
+      const int chunks = (int)((nv + NN_WGRAD_CHUNK - 1) / NN_WGRAD_CHUNK);
+      const int jobs = T * (s.ci / 16) * (s.co / 16);
+      hipLaunchKernelGGL(k_wgrad, dim3(chunks, jobs), dim3(64), 0, c->stream, in.p, in.ld, din,
+                         gout.p, gout.ld, dout, s.ci, s.co, s.up ? 2 : s.k, s.up ? 2 : s.s,
+                         s.up ? 0 : s.p, s.up, NN_WGRAD_CHUNK, part);
+      MPL_HIP(c, hipGetLastError());
+      MPL_LAUNCH(c, k_wgrad_reduce, (jobs * 256 + 255) / 256, 256, part, chunks, jobs, s.ci, s.co, gW);
+      MPL_LAUNCH(c, k_bias_grad, s.co, 256, gout.p, gout.ld, nvo, gb);
+    }
+    if (l == 0) break;  // no gradient w.r.t. the network input
+    // gradient w.r.t. the layer input; the down layers' input is a skip
+    // tensor whose gradient already holds the decoder's share: accumulate.
+    const int accum = (s.k == 2 && !s.up) ? 1 : 0;
+    if (s.up) {
+      // dgrad of a transposed conv: 2x2x2 stride-2 gather conv, K = (t, o)
+      MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, 2, 2,
+                          0, nullptr, gin, din, 0, accum));
+    } else if (s.k == 2) {
+      MPL_TRY(launch_up(c, gout, dout, sw + nn.sw_bwd_off[l], (s.co + 31) / 32, s.ci, nullptr, gin, 0,
+                        accum));
+    } else {
+      MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, s.k,
+                          1, s.p, nullptr, gin, din, 0, accum));
+    }
+  }
+  return MPL_OK;
+}
+
+NNState* nn_state(mpl_ctx* c) {
+  if (!c->nn) c->nn = new NNState();
+  return c->nn;
+}
+
+void nn_destroy(mpl_ctx* c) {
+  if (!c->nn) return;
+  NNState& nn = *c->nn;
+  DevBuf* all[] = {&nn.params, &nn.grad, &nn.adam_m, &nn.adam_v, &nn.wsw, &nn.act, &nn.gact,
+                   &nn.wpart, &nn.lpart, &nn.tmp, &nn.dref};
+  for (DevBuf* b : all)
+    if (b->p) (void)hipFree(b->p);
+  if (nn.store) {
+    DevBuf* st[] = {&nn.store->feat, &nn.store->target, &nn.store->mask};
+    for (DevBuf* b : st)
+      if (b->p) (void)hipFree(b->p);
+    delete nn.store;
+  }
+  delete c->nn;
+  c->nn = nullptr;
+}
+
+mpl_status nn_stage_input_f32(mpl_ctx* c, NNState& nn, const float* x) {
+  const int64_t n = (int64_t)nn.box[0] * nn.box[1] * nn.box[2] * 16;
+  MPL_LAUNCH(c, k_f32_to_bf16, (int)((n + 255) / 256), 256, x, (uint16_t*)nn.act.p + nn.t_in, n);
+  return MPL_OK;
+}
+
+// ======================================================================
+extern "C" {
+
+mpl_status mpl_precond_param_count(mpl_ctx* c, int64_t* n) {
+  if (!c || !n) return MPL_ERR_INVALID_ARG;
+  *n = nn_param_count();
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_set_weights(mpl_ctx* c, const float* params, int64_t n) {
+  if (!c || !params || n != nn_param_count()) return MPL_ERR_INVALID_ARG;
+  NNState& nn = *nn_state(c);
+  MPL_TRY(nn_alloc(c, nn));
+  MPL_HIP(c, hipMemcpyAsync(nn.params.p, params, 4 * n, hipMemcpyHostToDevice, c->stream));
+  MPL_HIP(c, hipMemsetAsync(nn.adam_m.p, 0, 4 * n, c->stream));
+  MPL_HIP(c, hipMemsetAsync(nn.adam_v.p, 0, 4 * n, c->stream));
+  nn.adam_t = 0;
+  MPL_TRY(nn_refresh(c, nn));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_get_weights(mpl_ctx* c, float* params, int64_t n) {
+  if (!c || !params || n != nn_param_count()) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
+  MPL_HIP(c, hipMemcpyAsync(params, c->nn->params.p, 4 * n, hipMemcpyDeviceToHost, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_nn_forward(mpl_ctx* c, const float* x, const int32_t dims[3], float* y) {
+  if (!c || !x || !y || !dims) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
+  NNState& nn = *c->nn;
+  int d[3] = {dims[0], dims[1], dims[2]};
+  MPL_TRY(nn_buffers(c, nn, d, false));
+  MPL_HIP(c, hipMemsetAsync(nn.act.p, 0, 2 * nn.act_elems, c->stream));
+  MPL_TRY(nn_stage_input_f32(c, nn, x));
+  MPL_TRY(nn_forward(c, nn));
+  const int64_t n = (int64_t)d[0] * d[1] * d[2] * 16;
+  MPL_LAUNCH(c, k_bf16_to_f32, (int)((n + 255) / 256), 256, (const uint16_t*)nn.act.p + nn.t_out, y, n);
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_nn_backward(mpl_ctx* c, const float* x, const int32_t dims[3], const float* dy,
+                           float* grad) {
+  if (!c || !x || !dy || !grad || !dims) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
+  NNState& nn = *c->nn;
+  int d[3] = {dims[0], dims[1], dims[2]};
+  MPL_TRY(nn_buffers(c, nn, d, true));
+  MPL_HIP(c, hipMemsetAsync(nn.act.p, 0, 2 * nn.act_elems, c->stream));
+  MPL_HIP(c, hipMemsetAsync(nn.gact.p, 0, 2 * nn.act_elems, c->stream));
+  MPL_TRY(nn_stage_input_f32(c, nn, x));
+  MPL_TRY(nn_forward(c, nn));
+  const int64_t n = (int64_t)d[0] * d[1] * d[2] * 16;
+  MPL_LAUNCH(c, k_f32_to_bf16, (int)((n + 255) / 256), 256, dy, (uint16_t*)nn.gact.p + nn.t_out, n);
+  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * nn_param_count(), c->stream));
+  MPL_TRY(nn_backward(c, nn));
+  MPL_HIP(c, hipMemcpyAsync(grad, nn.grad.p, 4 * nn_param_count(), hipMemcpyDeviceToDevice, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+// One Adam step on the masked relative L2 loss of one sample (device
+// tensors: x [X][Y][Z][16] FP32 features, t [X][Y][Z][3] FP32 targets,
+// mask [X][Y][Z] FP32).  loss (host, may be NULL) gets the loss before the step.
+mpl_status mpl_precond_train_step(mpl_ctx* c, const float* x, const float* t, const float* mask,
+                                  const int32_t dims[3], float lr, float* loss) {
+  if (!c || !x || !t || !mask || !dims) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
+  NNState& nn = *c->nn;
+  int d[3] = {dims[0], dims[1], dims[2]};
+  MPL_TRY(nn_buffers(c, nn, d, true));
+  const int64_t nvox = (int64_t)d[0] * d[1] * d[2];
+  MPL_HIP(c, hipMemsetAsync(nn.gact.p, 0, 2 * nn.act_elems, c->stream));
+  MPL_TRY(nn_stage_input_f32(c, nn, x));
+  MPL_TRY(nn_forward(c, nn));
+  const uint16_t* y = (const uint16_t*)nn.act.p + nn.t_out;
+  double* lp = (double*)nn.lpart.p;
+  const int nwg = 1024;
+  MPL_LAUNCH(c, k_loss_partial, nwg, 256, y, 16, t, mask, nvox, lp + 8);
+  MPL_LAUNCH(c, k_loss_final, 1, 1, lp + 8, nwg, lp);
+  MPL_LAUNCH(c, k_loss_grad, (int)((nvox + 255) / 256), 256, y, 16, t, mask, nvox, lp,
+             (uint16_t*)nn.gact.p + nn.t_out, 16);
+  const int64_t np = nn_param_count();
+  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
+  MPL_TRY(nn_backward(c, nn));
+  nn.adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);
+  MPL_LAUNCH(c, k_adam, (int)((np + 255) / 256), 256, (float*)nn.params.p, (const float*)nn.grad.p,
+             (float*)nn.adam_m.p, (float*)nn.adam_v.p, np, lr, b1, b2, 1e-8f, c1, c2);
+  MPL_TRY(nn_refresh(c, nn));
+  if (loss) {
+    double h[3];
+    MPL_HIP(c, hipMemcpyAsync(h, lp, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    MPL_HIP(c, hipStreamSynchronize(c->stream));
+    *loss = (float)h[2];
+  }
+  return MPL_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// The network on the solver grid.
+namespace {
+
+__global__ __launch_bounds__(64) void k_dref_partial(const double* __restrict__ Dinv,
+                                                     const uint8_t* __restrict__ flags, int64_t nnode,
+                                                     double* __restrict__ part) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double s = 0.0, n = 0.0;
+  if (flags[ni] & MPL_NODE_FREE) {
+    for (int a = 0; a < 3; ++a) s += 1.0 / Dinv[a * nnode + ni];
+    s /= 3.0;
+    n = 1.0;
+  }
+  s = wave_sum(s);
+  n = wave_sum(n);
+  if (l == 0) {
+    part[2 * nb] = s;
+    part[2 * nb + 1] = n;
+  }
+}
+__global__ void k_dref_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0, m = 0.0;
+  for (int i = 0; i < n; ++i) {
+    s += part[2 * i];
+    m += part[2 * i + 1];
+  }
+  out[0] = m > 0.0 ? s / m : 1.0;
+}
+
+struct Box3 {
+  int d[3];
+};
+
+// Map box voxel (i, j, k) (= grid node) to its compact node index, -1 when
+// its node block is inactive.
+__device__ __forceinline__ int64_t voxel_node(int i, int j, int k, const int32_t* __restrict__ nmap,
+                                              Box3 nbd) {
+  const int bx = i >> 2, by = j >> 2, bz = k >> 2;
+  if (bx >= nbd.d[0] || by >= nbd.d[1] || bz >= nbd.d[2]) return -1;
+  const int id = nmap[((int64_t)bx * nbd.d[1] + by) * nbd.d[2] + bz];
+  if (id < 0) return -1;
+  return (int64_t)id * MPL_BC + (((i & 3) * 4 + (j & 3)) * 4 + (k & 3));
+}
+
+// Network input for node vector r, one thread per box voxel (every voxel
+// written, zeros off the free nodes): [voxel][16] bf16.
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ r,
+                                                  const double* __restrict__ Dinv,
+                                                  const uint8_t* __restrict__ flags,
+                                                  const int32_t* __restrict__ nmap, Box3 nbd,
+                                                  int64_t nnode, Box3 box,
+                                                  const double* __restrict__ s2, double inv_nfree,
+                                                  const double* __restrict__ dref,
+                                                  uint16_t* __restrict__ feat) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = (int64_t)box.d[0] * box.d[1] * box.d[2];
+  if (v >= nv) return;
+  const int k = (int)(v % box.d[2]), j = (int)((v / box.d[2]) % box.d[1]),
+            i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
+  const int64_t ni = voxel_node(i, j, k, nmap, nbd);
+  float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  if (ni >= 0 && (flags[ni] & MPL_NODE_FREE)) {
+    const double sc = sqrt(fmax(s2[0] * inv_nfree, 1e-300));
+    double dm = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double di = Dinv[a * nnode + ni];
+      f[a] = (float)(sqrt(di) * r[a * nnode + ni] / sc);
+      dm += 1.0 / di;
+    }
+    f[3] = (float)log(dm / 3.0 / dref[0]);
+    f[4] = 1.f;
+  }
+  uint16_t* dst = feat + v * 16;
+  uint4 lo, hi = make_uint4(0, 0, 0, 0);
+  lo.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+  lo.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+  lo.z = (uint32_t)f2bf(f[4]);
+  lo.w = 0;
+  reinterpret_cast<uint4*>(dst)[0] = lo;
+  reinterpret_cast<uint4*>(dst)[1] = hi;
+}
+
+__global__ __launch_bounds__(256) void k_record(const double* __restrict__ r, const double* __restrict__ x,
+                                                const double* __restrict__ xstar,
+                                                const double* __restrict__ Dinv,
+                                                const uint8_t* __restrict__ flags,
+                                                const int32_t* __restrict__ nmap, Box3 nbd,
+                                                int64_t nnode, Box3 box, const double* __restrict__ s2,
+                                                double inv_nfree, float* __restrict__ target,
+                                                float* __restrict__ mask) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = (int64_t)box.d[0] * box.d[1] * box.d[2];
+  if (v >= nv) return;
+  const int k = (int)(v % box.d[2]), j = (int)((v / box.d[2]) % box.d[1]),
+            i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
+  const int64_t ni = voxel_node(i, j, k, nmap, nbd);
+  const bool fr = ni >= 0 && (flags[ni] & MPL_NODE_FREE);
+  const double sc = sqrt(fmax(s2[0] * inv_nfree, 1e-300));
+  for (int a = 0; a < 3; ++a) {
+    double t = 0.0;
+    if (fr) {
+      const int64_t q = a * nnode + ni;
+      const double di = Dinv[q];
+      const double e = xstar[q] - x[q];
+      t = (e - di * r[q]) / (sqrt(di) * sc);
+    }
+    target[v * 3 + a] = (float)t;
+  }
+  mask[v] = fr ? 1.f : 0.f;
+}
+
+}  // namespace
+
+NNSampleStore& nn_samples(mpl_ctx* c) {
+  NNState& nn = *nn_state(c);
+  if (!nn.store) nn.store = new NNSampleStore();
+  return *nn.store;
+}
+
+mpl_status nn_prepare_box(mpl_ctx* c, bool train) {
+  NNState& nn = *nn_state(c);
+  if (!nn.ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
+  int d[3];
+  for (int a = 0; a < 3; ++a) d[a] = ((c->dims[a] + 1 + 7) / 8) * 8;
+  MPL_TRY(nn_buffers(c, nn, d, train));
+  MPL_TRY(mpl_ensure(c, nn.dref, 64));
+  return MPL_OK;
+}
+
+mpl_status nn_set_dref(mpl_ctx* c, const double* Dinv) {
+  NNState& nn = *nn_state(c);
+  MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * 2 * (c->n_nblk + 64)));
+  MPL_TRY(mpl_ensure(c, nn.dref, 64));
+  MPL_LAUNCH(c, k_dref_partial, c->n_nblk, 64, Dinv, P<uint8_t>(c->flags), (int64_t)c->nnode_alloc(),
+             P<double>(nn.tmp));
+  MPL_LAUNCH(c, k_dref_final, 1, 1, P<double>(nn.tmp), c->n_nblk, P<double>(nn.dref));
+  return MPL_OK;
+}
+
+double nn_inv_free_dofs(mpl_ctx* c) {
+  const double n = 3.0 * std::max(1, c->hscal.n_free_nodes);
+  return 1.0 / n;
+}
+static double inv_nfree(mpl_ctx* c) { return nn_inv_free_dofs(c); }
+
+mpl_status nn_stage_features(mpl_ctx* c, const double* r, const double* Dinv, const double* s2) {
+  NNState& nn = *nn_state(c);
+  const int64_t nv = (int64_t)nn.box[0] * nn.box[1] * nn.box[2];
+  uint16_t* feat = (uint16_t*)nn.act.p + nn.t_in;
+  Box3 b{{nn.box[0], nn.box[1], nn.box[2]}}, nbd{{c->nbd[0], c->nbd[1], c->nbd[2]}};
+  MPL_LAUNCH(c, k_features, (int)((nv + 255) / 256), 256, r, Dinv, P<uint8_t>(c->flags),
+             P<int32_t>(c->nmap), nbd, (int64_t)c->nnode_alloc(), b, s2, inv_nfree(c),
+             P<double>(nn.dref), feat);
+  return MPL_OK;
+}
+
+mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const double* xstar,
+                            const double* Dinv, const double* s2) {
+  NNState& nn = *nn_state(c);
+  NNSampleStore& st = nn_samples(c);
+  const int64_t nv = (int64_t)nn.box[0] * nn.box[1] * nn.box[2];
+  if (st.voxels != nv) {
+    st.voxels = nv;
+    st.count = 0;
+  }
+  if (st.count >= st.capacity) return mpl_fail(c, MPL_ERR_OOM, "training sample store is full");
+  MPL_TRY(nn_stage_features(c, r, Dinv, s2));
+  uint16_t* feat = P<uint16_t>(st.feat) + (int64_t)st.count * nv * 16;
+  MPL_HIP(c, hipMemcpyAsync(feat, (uint16_t*)nn.act.p + nn.t_in, 2 * nv * 16, hipMemcpyDeviceToDevice,
+                            c->stream));
+  float* tgt = P<float>(st.target) + (int64_t)st.count * nv * 3;
+  float* msk = P<float>(st.mask) + (int64_t)st.count * nv;
+  Box3 b{{nn.box[0], nn.box[1], nn.box[2]}}, nbd{{c->nbd[0], c->nbd[1], c->nbd[2]}};
+  MPL_LAUNCH(c, k_record, (int)((nv + 255) / 256), 256, r, x, xstar, Dinv, P<uint8_t>(c->flags),
+             P<int32_t>(c->nmap), nbd, (int64_t)c->nnode_alloc(), b, s2, inv_nfree(c), tgt, msk);
+  st.count += 1;
+  return MPL_OK;
+}
+
+// one Adam step on a staged bf16 sample
+static mpl_status nn_train_on(mpl_ctx* c, NNState& nn, const uint16_t* feat, const float* t,
+                              const float* mask, float lr, double* loss_dev) {
+  const int64_t nvox = (int64_t)nn.box[0] * nn.box[1] * nn.box[2];
+  MPL_HIP(c, hipMemcpyAsync((uint16_t*)nn.act.p + nn.t_in, feat, 2 * nvox * 16, hipMemcpyDeviceToDevice,
+                            c->stream));
+  MPL_TRY(nn_forward(c, nn));
+  const uint16_t* y = (const uint16_t*)nn.act.p + nn.t_out;
+  double* lp = (double*)nn.lpart.p;
+  MPL_LAUNCH(c, k_loss_partial, 1024, 256, y, 16, t, mask, nvox, lp + 8);
+  MPL_LAUNCH(c, k_loss_final, 1, 1, lp + 8, 1024, loss_dev);
+  MPL_LAUNCH(c, k_loss_grad, (int)((nvox + 255) / 256), 256, y, 16, t, mask, nvox, loss_dev,
+             (uint16_t*)nn.gact.p + nn.t_out, 16);
+  const int64_t np = nn_param_count();
+  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
+  MPL_TRY(nn_backward(c, nn));
+  nn.adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);
+  MPL_LAUNCH(c, k_adam, (int)((np + 255) / 256), 256, (float*)nn.params.p, (const float*)nn.grad.p,
+             (float*)nn.adam_m.p, (float*)nn.adam_v.p, np, lr, b1, b2, 1e-8f, c1, c2);
+  MPL_TRY(nn_refresh(c, nn));
+  return MPL_OK;
+}
+
+extern "C" {
+
+mpl_status mpl_precond_reserve(mpl_ctx* c, int32_t capacity) {
+  if (!c || capacity < 0) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "set network weights first");
+  MPL_TRY(nn_prepare_box(c, true));
+  NNSampleStore& st = nn_samples(c);
+  NNState& nn = *c->nn;
+  const int64_t nv = (int64_t)nn.box[0] * nn.box[1] * nn.box[2];
+  MPL_TRY(mpl_ensure(c, st.feat, (size_t)2 * nv * 16 * std::max(capacity, 1)));
+  MPL_TRY(mpl_ensure(c, st.target, (size_t)4 * nv * 3 * std::max(capacity, 1)));
+  MPL_TRY(mpl_ensure(c, st.mask, (size_t)4 * nv * std::max(capacity, 1)));
+  st.capacity = capacity;
+  st.count = 0;
+  st.voxels = nv;
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_collect(mpl_ctx* c, int32_t every, double rtol) {
+  if (!c || every < 0 || !(rtol > 0.0)) return MPL_ERR_INVALID_ARG;
+  c->collect_every = every;
+  c->collect_rtol = rtol;
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_sample_count(mpl_ctx* c, int32_t* n) {
+  if (!c || !n) return MPL_ERR_INVALID_ARG;
+  *n = (c->nn && c->nn->store) ? c->nn->store->count : 0;
+  return MPL_OK;
+}
+
+// Train on the stored samples: n_steps Adam steps cycling through the
+// samples in a fixed pseudo-random order; losses[i] (host, may be NULL)
+// receives the loss of step i before its update.
+mpl_status mpl_precond_train(mpl_ctx* c, int32_t n_steps, float lr, uint32_t seed, float* losses) {
+  if (!c || n_steps < 0) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready || !c->nn->store || c->nn->store->count == 0)
+    return mpl_fail(c, MPL_ERR_STATE, "no training samples");
+  NNState& nn = *c->nn;
+  MPL_TRY(nn_prepare_box(c, true));
+  NNSampleStore& st = *nn.store;
+  const int64_t nv = st.voxels;
+  MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * 4 * (n_steps + 64) + 4096));
+  double* lossd = P<double>(nn.tmp);
+  uint32_t rs = seed * 2654435761u + 12345u;
+  for (int it = 0; it < n_steps; ++it) {
+    rs = rs * 1664525u + 1013904223u;
+    const int k = (int)((rs >> 8) % (uint32_t)st.count);
+    MPL_TRY(nn_train_on(c, nn, P<uint16_t>(st.feat) + (int64_t)k * nv * 16,
+                        P<float>(st.target) + (int64_t)k * nv * 3, P<float>(st.mask) + (int64_t)k * nv,
+                        lr, lossd + 4 * it));
+  }
+  if (losses && n_steps > 0) {
+    std::vector<double> h(4 * n_steps);
+    MPL_HIP(c, hipMemcpyAsync(h.data(), lossd, sizeof(double) * 4 * n_steps, hipMemcpyDeviceToHost, c->stream));
+    MPL_HIP(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n_steps; ++i) losses[i] = (float)h[4 * i + 2];
+  }
+  return MPL_OK;
+}
+
+}  // extern "C"

@@ -12,8 +12,10 @@
 // tangent entries; the CG update kernel assembles the node result.
 #include <cmath>
 #include <chrono>
+#include <functional>
 
 #include "mpl_grid.h"
+#include "mpl_nn.h"
 
 using namespace mpl;
 
@@ -162,33 +164,55 @@ __global__ __launch_bounds__(64) void k_energy_nodes(const double* __restrict__ 
 
 // Deterministic reduction of up to 3 partial arrays (fixed order) into
 // scalars, followed by the solver's scalar logic.
-enum { RED_PLAIN = 0, RED_ALPHA = 1, RED_BETA = 2, RED_PCG_INIT = 3 };
+enum {
+  RED_PLAIN = 0,
+  RED_ALPHA = 1,
+  RED_BETA = 2,
+  RED_PCG_INIT = 3,
+  RED_FINIT = 4,   // flexible CG: A = b.b, B = sum Dinv b^2
+  RED_FCHECK = 5,  // flexible CG: A = r.r, B = sum Dinv r^2 (convergence, stagnation)
+  RED_FBETA = 6    // flexible CG: A = z.r, B = z.q (Polak-Ribiere beta or fallback)
+};
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, int na,
                                                  const double* __restrict__ b, int nb,
                                                  const double* __restrict__ c, int nc,
                                                  SolverScalars* __restrict__ s, int slot) {
-  __shared__ double sh[3][1024];
+  __shared__ double sh[3][16];
   const int t = threadIdx.x;
-  if ((MODE == RED_ALPHA || MODE == RED_BETA) && done_flag(s)) return;
-  double va = 0.0, vb = 0.0, vc = 0.0;
-  for (int i = t; i < na; i += 1024) va += a[i];
-  for (int i = t; i < nb; i += 1024) vb += b[i];
-  for (int i = t; i < nc; i += 1024) vc += c[i];
-  sh[0][t] = va;
-  sh[1][t] = vb;
-  sh[2][t] = vc;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off) {
-      sh[0][t] += sh[0][t + off];
-      sh[1][t] += sh[1][t + off];
-      sh[2][t] += sh[2][t + off];
-    }
-    __syncthreads();
+  if ((MODE == RED_ALPHA || MODE == RED_BETA || MODE == RED_FCHECK || MODE == RED_FBETA) &&
+      done_flag(s))
+    return;
+  // four independent strided streams per array keep several loads in flight
+  double va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, vc[4] = {0, 0, 0, 0};
+  for (int i = t; i < na; i += 4096)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + 1024 * k < na) va[k] += a[i + 1024 * k];
+  for (int i = t; i < nb; i += 4096)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + 1024 * k < nb) vb[k] += b[i + 1024 * k];
+  for (int i = t; i < nc; i += 4096)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + 1024 * k < nc) vc[k] += c[i + 1024 * k];
+  const double ra = wave_sum((va[0] + va[1]) + (va[2] + va[3]));
+  const double rb = wave_sum((vb[0] + vb[1]) + (vb[2] + vb[3]));
+  const double rc = wave_sum((vc[0] + vc[1]) + (vc[2] + vc[3]));
+  if ((t & 63) == 0) {
+    sh[0][t >> 6] = ra;
+    sh[1][t >> 6] = rb;
+    sh[2][t >> 6] = rc;
   }
+  __syncthreads();
   if (t != 0) return;
-  const double A = sh[0][0], B = sh[1][0], C = sh[2][0];
+  double A = 0.0, B = 0.0, C = 0.0;
+  for (int w = 0; w < 16; ++w) {
+    A += sh[0][w];
+    B += sh[1][w];
+    C += sh[2][w];
+  }
   if (MODE == RED_PLAIN) {
     s->red[slot] = A;
     s->red[slot + 1] = B;
@@ -203,11 +227,12 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, i
     s->pq = pq;
     if (!(pq > 0.0) || !isfinite(pq)) {
       s->done = 2;
+      s->nn_off = 1;
       s->alpha = 0.0;
     } else {
       s->alpha = s->rz / pq;
     }
-  } else {  // RED_BETA: A = r.z (new), B = r.r
+  } else if (MODE == RED_BETA) {  // A = r.z (new), B = r.r
     s->rz_new = A;
     s->rr = B;
     s->iters += 1;
@@ -215,6 +240,52 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, i
     else if (B <= s->tol2) s->done = 1;
     s->beta = A / s->rz;
     s->rz = A;
+  } else if (MODE == RED_FINIT) {
+    s->bnorm2 = A;
+    s->rr = A;
+    s->rr_mark = A;
+    s->s2 = B;
+    s->iters = 0;
+    s->done = (A == 0.0) ? 1 : 0;
+    s->fallback = 0;
+    s->fb_new = 0;
+    s->fallbacks = 0;
+    s->nn_off = s->done;
+  } else if (MODE == RED_FCHECK) {
+    s->rr = A;
+    s->s2 = B;
+    s->iters += 1;
+    if (!isfinite(A)) s->done = 2;
+    else if (A <= s->tol2) s->done = 1;
+    // stagnation: less than 10% drop of |r| over the last 10 iterations
+    if (s->done == 0 && s->fallback == 0 && s->iters % 10 == 0) {
+      if (A > 0.81 * s->rr_mark) {
+        s->fallback = 1;
+        s->fb_new = 1;
+        s->fallbacks += 1;
+      }
+      s->rr_mark = A;
+    }
+    s->nn_off = (s->done != 0 || s->fallback != 0) ? 1 : 0;
+  } else {  // RED_FBETA
+    if (s->fallback) {
+      // Jacobi from here on: z = Dinv r, z.r = s2; restart on the switch
+      s->beta = s->fb_new ? 0.0 : s->s2 / s->rz;
+      s->rz = s->s2;
+      s->fb_new = 0;
+    } else if (!(A > 0.0) || !isfinite(A) || !isfinite(B)) {
+      // the network output is not a descent direction: switch to Jacobi
+      s->fallback = 1;
+      s->fallbacks += 1;
+      s->nn_off = 1;
+      s->beta = 0.0;
+      s->rz = s->s2;
+    } else {
+      // flexible (Polak-Ribiere) beta = z_new.(r_new - r_old) / z_old.r_old
+      // with r_new - r_old = -alpha q
+      s->beta = (s->iters == 0) ? 0.0 : -s->alpha * B / s->rz;
+      s->rz = A;
+    }
   }
 }
 
@@ -299,7 +370,8 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
   for (int i = 0; i < 45; ++i) Abar[i * ncell + ci] = (T)Ab[i];
 }
 
-// Jacobi diagonal of H at every node: m_i + sum_c sum_{b,b'} Abar[(a,b),(a,b')] gw_b gw_b'.
+// Inverse Jacobi diagonal of H at every node, 1 / (m_i + sum_c sum_{b,b'}
+// Abar[(a,b),(a,b')] gw_b gw_b'), and 0 on fixed / massless nodes.
 template <class T>
 __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t ncell,
                                              const double* __restrict__ mi,
@@ -326,7 +398,7 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t
     }
     for (int a = 0; a < 3; ++a) dd[a] += mi[ni];
   }
-  for (int a = 0; a < 3; ++a) D[a * nnode + ni] = fr ? dd[a] : 0.0;
+  for (int a = 0; a < 3; ++a) D[a * nnode + ni] = fr ? 1.0 / dd[a] : 0.0;
 }
 
 // ---------------------------------------------------------------- Hv
@@ -507,110 +579,273 @@ __global__ __launch_bounds__(64) void k_hv_combine(const T* __restrict__ u,
 }
 
 // ---------------------------------------------------------------- PCG vectors
-// x = 0, r = b, p = D^{-1} r; partials r.z, b.b and p^T M p.
+// Node-vector kernels run 4 node blocks (4 wavefronts) per workgroup and
+// emit one partial sum per workgroup (waves combined in a fixed order).
+// Dinv holds the inverse Jacobi diagonal (0 on non-free nodes).
+__device__ __forceinline__ double block4_sum(double v, double* sh) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// x = 0, r = b, p = Dinv r; partials r.z, b.b and p^T M p.
 template <class T>
-__global__ __launch_bounds__(64) void k_pcg_init(const double* __restrict__ b,
-                                                 const double* __restrict__ D,
-                                                 const double* __restrict__ mi,
-                                                 const uint8_t* __restrict__ flags, int64_t nnode,
-                                                 double* __restrict__ x, double* __restrict__ r,
-                                                 T* __restrict__ p, double* __restrict__ prz,
-                                                 double* __restrict__ pbb,
-                                                 double* __restrict__ pmm) {
-  const int nb = blockIdx.x, l = threadIdx.x;
-  const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
-  const double m = mi[ni];
+__global__ __launch_bounds__(256) void k_pcg_init(const double* __restrict__ b,
+                                                  const double* __restrict__ Dinv,
+                                                  const double* __restrict__ mi,
+                                                  const uint8_t* __restrict__ flags, int64_t nnode,
+                                                  int n_nblk, double* __restrict__ x,
+                                                  double* __restrict__ r, T* __restrict__ p,
+                                                  double* __restrict__ prz, double* __restrict__ pbb,
+                                                  double* __restrict__ pmm) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   double rz = 0.0, bb = 0.0, mm = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    const int64_t i = a * nnode + ni;
-    const double rv = fr ? b[i] : 0.0;
-    const double zv = fr ? rv / D[i] : 0.0;
-    const T pv = (T)zv;
-    x[i] = 0.0;
-    r[i] = rv;
-    p[i] = pv;
-    rz += rv * zv;
-    bb += rv * rv;
-    mm += m * (double)pv * (double)pv;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const double m = mi[ni];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const double rv = fr ? b[i] : 0.0;
+      const double zv = rv * Dinv[i];
+      const T pv = (T)zv;
+      x[i] = 0.0;
+      r[i] = rv;
+      p[i] = pv;
+      rz += rv * zv;
+      bb += rv * rv;
+      mm += m * (double)pv * (double)pv;
+    }
   }
-  rz = wave_sum(rz);
-  bb = wave_sum(bb);
-  mm = wave_sum(mm);
-  if (l == 0) {
-    prz[nb] = rz;
-    pbb[nb] = bb;
-    pmm[nb] = mm;
+  rz = block4_sum(rz, sh);
+  bb = block4_sum(bb, sh);
+  mm = block4_sum(mm, sh);
+  if (threadIdx.x == 0) {
+    prz[blockIdx.x] = rz;
+    pbb[blockIdx.x] = bb;
+    pmm[blockIdx.x] = mm;
   }
 }
 
 // q = M p + K p (assembled from the fused product's pieces), x += alpha p,
-// r -= alpha q; partials of r.z (z = D^{-1} r) and r.r.
+// r -= alpha q; partials of r.z (z = Dinv r) and r.r.
 template <class T>
-__global__ __launch_bounds__(64) void k_pcg_update(const T* __restrict__ p,
-                                                   const T* __restrict__ Hown,
-                                                   const T* __restrict__ Hhalo,
-                                                   const int* __restrict__ n_nbr_cell,
-                                                   int64_t ncell, const double* __restrict__ mi,
-                                                   const double* __restrict__ D,
-                                                   const uint8_t* __restrict__ flags, int64_t nnode,
-                                                   double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ prz,
-                                                   double* __restrict__ prr,
-                                                   const SolverScalars* __restrict__ s) {
+__global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
+                                                    const T* __restrict__ Hown,
+                                                    const T* __restrict__ Hhalo,
+                                                    const int* __restrict__ n_nbr_cell,
+                                                    int64_t ncell, const double* __restrict__ mi,
+                                                    const double* __restrict__ Dinv,
+                                                    const uint8_t* __restrict__ flags, int64_t nnode,
+                                                    int n_nblk, double* __restrict__ x,
+                                                    double* __restrict__ r, double* __restrict__ prz,
+                                                    double* __restrict__ prr,
+                                                    const SolverScalars* __restrict__ s,
+                                                    T* __restrict__ qout) {
   if (done_flag(s)) return;
-  const int nb = blockIdx.x, l = threadIdx.x;
-  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   const double alpha = s->alpha;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
   double rz = 0.0, rr = 0.0;
-  if (fr) {
-    T h[3];
-    gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
-    const T m = (T)mi[ni];
-    for (int a = 0; a < 3; ++a) {
-      const int64_t i = a * nnode + ni;
-      const T pv = p[i];
-      const double q = (double)(h[a] + m * pv);
-      x[i] += alpha * (double)pv;
-      const double rv = r[i] - alpha * q;
-      r[i] = rv;
-      rz += rv * rv / D[i];
-      rr += rv * rv;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    if (flags[ni] & MPL_NODE_FREE) {
+      T h[3];
+      gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+      const T m = (T)mi[ni];
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        const T pv = p[i];
+        const T qt = h[a] + m * pv;
+        const double q = (double)qt;
+        if (qout) qout[i] = qt;
+        x[i] += alpha * (double)pv;
+        const double rv = r[i] - alpha * q;
+        r[i] = rv;
+        rz += rv * rv * Dinv[i];
+        rr += rv * rv;
+      }
     }
   }
-  rz = wave_sum(rz);
-  rr = wave_sum(rr);
-  if (l == 0) {
-    prz[nb] = rz;
-    prr[nb] = rr;
+  rz = block4_sum(rz, sh);
+  rr = block4_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    prz[blockIdx.x] = rz;
+    prr[blockIdx.x] = rr;
   }
 }
 
-// p = D^{-1} r + beta p; partial p^T M p for the next p^T H p.
+// p = Dinv r + beta p; partial p^T M p for the next p^T H p.
 template <class T>
-__global__ __launch_bounds__(64) void k_pcg_direction(const double* __restrict__ r,
-                                                      const double* __restrict__ D,
-                                                      const double* __restrict__ mi,
-                                                      const uint8_t* __restrict__ flags,
-                                                      int64_t nnode, T* __restrict__ p,
-                                                      double* __restrict__ pmm,
-                                                      const SolverScalars* __restrict__ s) {
+__global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict__ r,
+                                                       const double* __restrict__ Dinv,
+                                                       const double* __restrict__ mi,
+                                                       const uint8_t* __restrict__ flags,
+                                                       int64_t nnode, int n_nblk,
+                                                       T* __restrict__ p, double* __restrict__ pmm,
+                                                       const SolverScalars* __restrict__ s) {
   if (done_flag(s)) return;
-  const int nb = blockIdx.x, l = threadIdx.x;
-  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   const double beta = s->beta;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
-  const double m = mi[ni];
   double mm = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    const int64_t i = a * nnode + ni;
-    const T pv = fr ? (T)(r[i] / D[i] + beta * (double)p[i]) : T(0);
-    p[i] = pv;
-    mm += m * (double)pv * (double)pv;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const double m = mi[ni];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const T pv = fr ? (T)(r[i] * Dinv[i] + beta * (double)p[i]) : T(0);
+      p[i] = pv;
+      mm += m * (double)pv * (double)pv;
+    }
   }
-  mm = wave_sum(mm);
-  if (l == 0) pmm[nb] = mm;
+  mm = block4_sum(mm, sh);
+  if (threadIdx.x == 0) pmm[blockIdx.x] = mm;
+}
+
+// ---- flexible CG with the learned preconditioner ----
+// The preconditioned residual is z = Dinv r + s sqrt(Dinv) o on free nodes,
+// o the network output (bf16, 16 channels per box voxel, voxel = node), s^2 =
+// s2 / (free DOFs); after a fallback z = Dinv r.
+struct NetOut {
+  const uint16_t* o;
+  int bx, by, bz;
+  double inv_nfree;
+};
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ __forceinline__ void learned_z(const NetOut& net, int4 bc, int l, const double* r,
+                                          const double* Dinv, int64_t nnode, int64_t ni, double sc,
+                                          bool jacobi, double z[3]) {
+  const int i = bc.x * 4 + local_x(l), j = bc.y * 4 + local_y(l), k = bc.z * 4 + local_z(l);
+  const bool in = !jacobi && i < net.bx && j < net.by && k < net.bz;
+  const int64_t v = in ? ((int64_t)i * net.by + j) * net.bz + k : 0;
+  for (int a = 0; a < 3; ++a) {
+    const double di = Dinv[a * nnode + ni];
+    z[a] = di * r[a * nnode + ni];
+    if (in) z[a] += sc * sqrt(di) * (double)bf16_to_f32(net.o[v * 16 + a]);
+  }
+}
+
+// x = 0, r = b on free nodes; partials b.b and sum Dinv b^2.
+__global__ __launch_bounds__(256) void k_fpcg_init(const double* __restrict__ b,
+                                                   const double* __restrict__ Dinv,
+                                                   const uint8_t* __restrict__ flags, int64_t nnode,
+                                                   int n_nblk, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ pbb,
+                                                   double* __restrict__ ps2) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  double bb = 0.0, s2 = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const double rv = fr ? b[i] : 0.0;
+      x[i] = 0.0;
+      r[i] = rv;
+      bb += rv * rv;
+      s2 += rv * rv * Dinv[i];
+    }
+  }
+  bb = block4_sum(bb, sh);
+  s2 = block4_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    pbb[blockIdx.x] = bb;
+    ps2[blockIdx.x] = s2;
+  }
+}
+
+// partials z.r and z.q (q may be null: first iteration)
+template <class T>
+__global__ __launch_bounds__(256) void k_fpcg_dots(const double* __restrict__ r,
+                                                   const T* __restrict__ q,
+                                                   const double* __restrict__ Dinv,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const int4* __restrict__ ncoord, int64_t nnode,
+                                                   int n_nblk, NetOut net, double* __restrict__ pzr,
+                                                   double* __restrict__ pzq,
+                                                   const SolverScalars* __restrict__ s) {
+  if (done_flag(s) || s->fallback) return;
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  const double sc = sqrt(fmax(s->s2 * net.inv_nfree, 1e-300));
+  double zr = 0.0, zq = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    if (flags[ni] & MPL_NODE_FREE) {
+      double z[3];
+      learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, false, z);
+      for (int a = 0; a < 3; ++a) {
+        zr += z[a] * r[a * nnode + ni];
+        if (q) zq += z[a] * (double)q[a * nnode + ni];
+      }
+    }
+  }
+  zr = block4_sum(zr, sh);
+  zq = block4_sum(zq, sh);
+  if (threadIdx.x == 0) {
+    pzr[blockIdx.x] = zr;
+    pzq[blockIdx.x] = zq;
+  }
+}
+
+// p = z + beta p; partial p^T M p.
+template <class T>
+__global__ __launch_bounds__(256) void k_fpcg_direction(const double* __restrict__ r,
+                                                        const double* __restrict__ Dinv,
+                                                        const double* __restrict__ mi,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const int4* __restrict__ ncoord,
+                                                        int64_t nnode, int n_nblk, NetOut net,
+                                                        T* __restrict__ p, double* __restrict__ pmm,
+                                                        const SolverScalars* __restrict__ s) {
+  if (done_flag(s)) return;
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  const double beta = s->beta;
+  const bool jacobi = s->fallback != 0;
+  const double sc = sqrt(fmax(s->s2 * net.inv_nfree, 1e-300));
+  double mm = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const double m = mi[ni];
+    double z[3] = {0.0, 0.0, 0.0};
+    if (fr) learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, jacobi, z);
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const T pv = fr ? (T)(z[a] + beta * (double)p[i]) : T(0);
+      p[i] = pv;
+      mm += m * (double)pv * (double)pv;
+    }
+  }
+  mm = block4_sum(mm, sh);
+  if (threadIdx.x == 0) pmm[blockIdx.x] = mm;
+}
+
+// z = learned preconditioner applied to r (block layout, FP64 output).
+__global__ __launch_bounds__(256) void k_precond_z(const double* __restrict__ r,
+                                                   const double* __restrict__ Dinv,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const int4* __restrict__ ncoord, int64_t nnode,
+                                                   int n_nblk, NetOut net,
+                                                   const SolverScalars* __restrict__ s,
+                                                   double* __restrict__ z) {
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (nb >= n_nblk) return;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double zz[3] = {0.0, 0.0, 0.0};
+  if (flags[ni] & MPL_NODE_FREE)
+    learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(s->s2 * net.inv_nfree, 1e-300)), false,
+              zz);
+  for (int a = 0; a < 3; ++a) z[a * nnode + ni] = zz[a];
 }
 
 __global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
@@ -833,13 +1068,82 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
   return MPL_OK;
 }
 
+// Runs PCG iterations in chunks of `check` until the device flag reports
+// convergence or breakdown or max_pcg iterations have been launched.  A
+// chunk is captured into a HIP graph once and replayed while the buffers and
+// sizes it was captured with (key, keyn) are unchanged; iterations past
+// convergence are device-side no-ops, so replaying a whole chunk is exact.
+// Without graph support the chunk is launched eagerly.  hook (may be null)
+// runs on the host after every chunk that leaves the iteration running,
+// with the iteration count.
+static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[16], const int keyn[6],
+                             int check, const std::function<mpl_status()>& launch_iteration,
+                             const std::function<mpl_status(int)>* hook) {
+  bool use_graph = c->graphs_enabled;
+  if (use_graph) {
+    bool same = gc.exec != nullptr;
+    for (int i = 0; i < 16 && same; ++i) same = gc.key[i] == key[i];
+    for (int i = 0; i < 6 && same; ++i) same = gc.keyn[i] == keyn[i];
+    if (same && c->opts.time_kernels && gc.events != 2 * check) same = false;
+    if (same && !c->opts.time_kernels && gc.events != 0) same = false;
+    if (!same) {
+      if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+      if (gc.graph) (void)hipGraphDestroy(gc.graph);
+      gc.exec = nullptr;
+      gc.graph = nullptr;
+      if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+      bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      mpl_status lst = MPL_OK;
+      if (ok) {
+        for (int k = 0; k < check && lst == MPL_OK; ++k) lst = launch_iteration();
+        hipGraph_t g = nullptr;
+        ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && lst == MPL_OK && g != nullptr;
+        if (ok) ok = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g && !ok) (void)hipGraphDestroy(g);
+        if (ok) gc.graph = g;
+      }
+      (void)hipGetLastError();
+      gc.events = ok ? c->hv_event_used : 0;
+      c->hv_event_used = 0;
+      if (!ok) {
+        gc.exec = nullptr;
+        c->graphs_enabled = false;
+        use_graph = false;
+      } else {
+        for (int i = 0; i < 16; ++i) gc.key[i] = key[i];
+        for (int i = 0; i < 6; ++i) gc.keyn[i] = keyn[i];
+      }
+    }
+  }
+  int it = 0;
+  for (;;) {
+    if (use_graph && it + check <= c->opts.max_pcg) {
+      MPL_HIP(c, hipGraphLaunch(gc.exec, c->stream));
+      it += check;
+      MPL_TRY(mpl_sync_scalars(c));
+      if (c->opts.time_kernels) {
+        c->hv_event_used = gc.events;
+        MPL_TRY(flush_hv_events(c));
+      }
+    } else {
+      for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) MPL_TRY(launch_iteration());
+      MPL_TRY(mpl_sync_scalars(c));
+    }
+    if (c->hscal.done != 0 || it >= c->opts.max_pcg) break;
+    if (hook) MPL_TRY((*hook)(it));
+  }
+  if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+  return MPL_OK;
+}
+
 // Jacobi-PCG on H x = b over free DOFs (b, x block layout FP64).  Per
 // iteration: fused product (p^T K p partials), alpha, update (x, r and the
 // assembled Hp), beta / convergence, new direction (p^T M p partials).
 // Iterations past convergence are no-ops on the device, so the host polls
 // the done flag only every pcg_check_every iterations.
 template <class T>
-static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
+                           const std::function<mpl_status(int)>* hook = nullptr) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(ensure_partials(c));
   MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
@@ -854,28 +1158,28 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
   double* pa = partial_slot(c, 1);
   double* pb = partial_slot(c, 2);
   double* pm = partial_slot(c, 3);
-  MPL_LAUNCH(c, k_pcg_init<T>, c->n_nblk, 64, b, P<double>(c->D), P<double>(c->mi),
-             P<uint8_t>(c->flags), nnode, x, P<double>(c->r), p, pa, pb, pm);
-  MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
+  const int nwg = (c->n_nblk + 3) / 4;
+  MPL_LAUNCH(c, k_pcg_init<T>, nwg, 256, b, P<double>(c->D), P<double>(c->mi), P<uint8_t>(c->flags),
+             nnode, c->n_nblk, x, P<double>(c->r), p, pa, pb, pm);
+  MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
   MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
   const int check = std::max(1, c->opts.pcg_check_every);
-  int it = 0;
-  bool finished = false;
-  while (!finished) {
-    for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) {
-      MPL_TRY(hv_pieces<T>(c, p, true));
-      MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, c->n_nblk, pm, 0, s, 0);
-      MPL_LAUNCH(c, k_pcg_update<T>, c->n_nblk, 64, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-                 P<double>(c->mi), P<double>(c->D), P<uint8_t>(c->flags), nnode, x, P<double>(c->r),
-                 pa, pb, s);
-      MPL_LAUNCH(c, k_reduce<RED_BETA>, 1, 1024, pa, c->n_nblk, pb, c->n_nblk, pb, 0, s, 0);
-      MPL_LAUNCH(c, k_pcg_direction<T>, c->n_nblk, 64, P<double>(c->r), P<double>(c->D),
-                 P<double>(c->mi), P<uint8_t>(c->flags), nnode, p, pm, s);
-    }
-    MPL_TRY(mpl_sync_scalars(c));
-    if (c->hscal.done != 0 || it >= c->opts.max_pcg) finished = true;
-  }
-  if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+  auto launch_iteration = [&]() -> mpl_status {
+    MPL_TRY(hv_pieces<T>(c, p, true));
+    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, nwg, pm, 0, s, 0);
+    MPL_LAUNCH(c, k_pcg_update<T>, nwg, 256, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+               P<double>(c->mi), P<double>(c->D), P<uint8_t>(c->flags), nnode, c->n_nblk, x,
+               P<double>(c->r), pa, pb, s, (T*)nullptr);
+    MPL_LAUNCH(c, k_reduce<RED_BETA>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+    MPL_LAUNCH(c, k_pcg_direction<T>, nwg, 256, P<double>(c->r), P<double>(c->D), P<double>(c->mi),
+               P<uint8_t>(c->flags), nnode, c->n_nblk, p, pm, s);
+    return MPL_OK;
+  };
+  const void* key[16] = {x,           p,           c->r.p,          c->D.p,
+                         abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
+                         c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p};
+  const int keyn[6] = {c->n_cblk, c->n_nblk, check, 0, 0, 0};
+  MPL_TRY(run_chunks(c, c->pcg_cache[0], key, keyn, check, launch_iteration, hook));
   if (iters) *iters = c->hscal.iters;
   if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
   if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)
@@ -883,8 +1187,152 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
   return MPL_OK;
 }
 
+// Flexible CG preconditioned by the network (Polak-Ribiere beta, so that a
+// preconditioner that varies from iteration to iteration still yields a
+// descent method), falling back to Jacobi when z.r <= 0, on NaN/Inf, or when
+// |r| drops by less than 10% over 10 iterations.  Per iteration: fused
+// product, alpha, update (x, r, q = Hp stored), convergence/stagnation
+// check, network input, network forward, z.r and z.q, beta, new direction.
+template <class T>
+static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
+  NNState& nn = *c->nn;
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  DevBuf& pb_ = pvec_buf<T>(c);
+  DevBuf& qb_ = (sizeof(T) == 4) ? c->q32 : c->q64;
+  MPL_TRY(mpl_ensure(c, pb_, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, qb_, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, pieces_buf<T>(c), sizeof(T) * 6 * ncell));
+  MPL_TRY(nn_prepare_box(c, false));
+  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  T* p = P<T>(pb_);
+  T* q = P<T>(qb_);
+  const T* Hown = P<T>(pieces_buf<T>(c));
+  const T* Hhalo = Hown + 3 * ncell;
+  SolverScalars* s = c->dscal();
+  const double* s2 = &s->s2;
+  nn.skip = &s->nn_off;
+  double* pk = partial_slot(c, 0);
+  double* pa = partial_slot(c, 1);
+  double* pb = partial_slot(c, 2);
+  double* pm = partial_slot(c, 3);
+  const int nwg = (c->n_nblk + 3) / 4;
+  const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
+                   nn_inv_free_dofs(c)};
+  const double* r = P<double>(c->r);
+  const double* D = P<double>(c->D);
+  auto precondition = [&](const T* qv) -> mpl_status {
+    MPL_TRY(nn_stage_features(c, r, D, s2));
+    MPL_TRY(nn_forward(c, nn));
+    MPL_LAUNCH(c, k_fpcg_dots<T>, nwg, 256, r, qv, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
+               c->n_nblk, net, pa, pb, s);
+    MPL_LAUNCH(c, k_reduce<RED_FBETA>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+    MPL_LAUNCH(c, k_fpcg_direction<T>, nwg, 256, r, D, P<double>(c->mi), P<uint8_t>(c->flags),
+               P<int4>(c->ncoord), nnode, c->n_nblk, net, p, pm, s);
+    return MPL_OK;
+  };
+  MPL_LAUNCH(c, k_fpcg_init, nwg, 256, b, D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r),
+             pa, pb);
+  MPL_LAUNCH(c, k_reduce<RED_FINIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+  MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
+  mpl_status st = precondition((const T*)nullptr);
+  const int check = std::max(1, c->opts.pcg_check_every);
+  auto launch_iteration = [&]() -> mpl_status {
+    MPL_TRY(hv_pieces<T>(c, p, true));
+    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, nwg, pm, 0, s, 0);
+    MPL_LAUNCH(c, k_pcg_update<T>, nwg, 256, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+               P<double>(c->mi), D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa, pb,
+               s, q);
+    // pa = sum Dinv r^2, pb = r.r
+    MPL_LAUNCH(c, k_reduce<RED_FCHECK>, 1, 1024, pb, nwg, pa, nwg, pa, 0, s, 0);
+    return precondition(q);
+  };
+  if (st == MPL_OK) {
+    const void* key[16] = {x,           p,           c->r.p,          c->D.p,
+                           abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
+                           c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
+                           q,           nn.act.p,    nn.wsw.p,        c->ncoord.p};
+    const int keyn[6] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2]};
+    st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, nullptr);
+  }
+  nn.skip = nullptr;
+  MPL_TRY(st);
+  c->fallbacks_total += c->hscal.fallbacks;
+  if (iters) *iters = c->hscal.iters;
+  if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
+  if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)
+    return mpl_fail(c, MPL_ERR_NONFINITE, "PCG breakdown (p.Hp <= 0 or not finite)");
+  return MPL_OK;
+}
+
+// Training pairs for the learned preconditioner: solve H x* = b to
+// collect_rtol with Jacobi PCG, then run the same (deterministic) iteration
+// again and record (r_k, x* - x_k) every collect_every iterations until the
+// sample store is full.  x* is left in c->xstar.
+template <class T>
+static mpl_status collect_pairs(mpl_ctx* c, const double* b, int* iters) {
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(mpl_ensure(c, c->xstar, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->x, 8 * 3 * nnode));
+  MPL_TRY(nn_prepare_box(c, true));
+  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  const mpl_solver_opts saved = c->opts;
+  c->opts.pcg_rtol = c->collect_rtol;
+  c->opts.pcg_check_every = c->collect_every;
+  double rel = 0.0;
+  mpl_status st = pcg_impl<T>(c, b, P<double>(c->xstar), iters, &rel);
+  NNSampleStore& store = nn_samples(c);
+  std::function<mpl_status(int)> hook = [&](int) -> mpl_status {
+    if (store.count >= store.capacity) return MPL_OK;
+    return nn_record_sample(c, P<double>(c->r), P<double>(c->x), P<double>(c->xstar), P<double>(c->D),
+                            &c->dscal()->rz);
+  };
+  if (st == MPL_OK && store.count < store.capacity) {
+    // stop the replay once the store is full or the exact solve's length is reached
+    c->opts.max_pcg = std::max(1, std::min(c->opts.max_pcg, *iters));
+    st = pcg_impl<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook);
+  }
+  c->opts = saved;
+  return st;
+}
+
+// z = P(r) with the learned preconditioner at the current tangent's
+// diagonal (block layout, FP64).  Uses the solver's r, x and scalars as scratch.
+mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* rin, double* z) {
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "preconditioner before tangent");
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
+  NNState& nn = *c->nn;
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->x, 8 * 3 * nnode));
+  MPL_TRY(nn_prepare_box(c, false));
+  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  SolverScalars* s = c->dscal();
+  const int nwg = (c->n_nblk + 3) / 4;
+  double* pa = partial_slot(c, 1);
+  double* pb = partial_slot(c, 2);
+  MPL_LAUNCH(c, k_fpcg_init, nwg, 256, rin, P<double>(c->D), P<uint8_t>(c->flags), nnode, c->n_nblk,
+             P<double>(c->x), P<double>(c->r), pa, pb);
+  MPL_LAUNCH(c, k_reduce<RED_FINIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+  MPL_TRY(nn_stage_features(c, P<double>(c->r), P<double>(c->D), &s->s2));
+  nn.skip = nullptr;
+  MPL_TRY(nn_forward(c, nn));
+  const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
+                   nn_inv_free_dofs(c)};
+  MPL_LAUNCH(c, k_precond_z, nwg, 256, P<double>(c->r), P<double>(c->D), P<uint8_t>(c->flags),
+             P<int4>(c->ncoord), nnode, c->n_nblk, net, s, z);
+  return MPL_OK;
+}
+
 mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
   if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
+  if (c->opts.precond == MPL_PRECOND_LEARNED) {
+    if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel);
+    return pcg_learned<double>(c, b, x, iters, rel);
+  }
   if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel);
   return pcg_impl<double>(c, b, x, iters, rel);
 }
@@ -914,6 +1362,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   mpl_status result = MPL_OK;
   c->hv_ms_total = 0.0;
   c->hv_calls = 0;
+  c->fallbacks_total = 0;
   for (;; ++it) {
     if (gn == 0.0 || gn <= c->opts.newton_rtol * g0) break;
     if (it >= c->opts.max_newton) {
@@ -926,7 +1375,14 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
                3 * nnode);
     int iters = 0;
     double rel = 0.0;
-    MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel));
+    if (c->collect_every > 0 && c->nn && c->nn->store && c->nn->store->count < c->nn->store->capacity) {
+      // collection mode: the exact solution is the Newton direction
+      if (c->tangent_precision == MPL_F32) MPL_TRY(collect_pairs<float>(c, P<double>(c->dir), &iters));
+      else MPL_TRY(collect_pairs<double>(c, P<double>(c->dir), &iters));
+      MPL_HIP(c, hipMemcpyAsync(c->x.p, c->xstar.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel));
+    }
     pcg_total += iters;
     // g . x for the Armijo test
     MPL_LAUNCH(c, k_axpy_dot, c->n_nblk, 64, v, P<double>(c->x), 0.0, P<double>(c->g),
@@ -971,6 +1427,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     st->energy = E;
     st->hv_ms_total = c->hv_ms_total;
     st->hv_calls = c->hv_calls;
+    st->fallbacks = c->fallbacks_total;
   }
   c->solved = (result == MPL_OK);
   return result;
@@ -1034,6 +1491,18 @@ mpl_status mpl_hv(mpl_ctx* c, const void* u, void* Hu, int32_t precision) {
   MPL_TRY(mpl_stage_hv(c, bin.p, bout.p, precision, false));
   MPL_TRY(mpl_block_to_dense_nodes(c, bout.p, Hu, 3, f32));
   if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_apply(mpl_ctx* c, const double* r, double* z) {
+  if (!c || !r || !z) return MPL_ERR_INVALID_ARG;
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(mpl_ensure(c, c->dir, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->vt, 8 * 3 * nnode));
+  MPL_TRY(mpl_dense_to_block_nodes(c, r, c->dir.p, 3, 0));
+  MPL_TRY(mpl_stage_precond_apply(c, P<double>(c->dir), P<double>(c->vt)));
+  MPL_TRY(mpl_block_to_dense_nodes(c, c->vt.p, z, 3, 0));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
   return MPL_OK;
 }
 

@@ -277,3 +277,75 @@ class Context:
         self._check(self._lib.mpl_export_field(self._ctx, int(fid), C.c_void_p(out.data_ptr())),
                     "mpl_export_field")
         return out
+
+    # ------------------------------------------------------------ learned preconditioner
+    def precond_param_count(self) -> int:
+        n = C.c_int64()
+        self._check(self._lib.mpl_precond_param_count(self._ctx, C.byref(n)), "mpl_precond_param_count")
+        return n.value
+
+    def precond_set_weights(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self._lib.mpl_precond_set_weights(self._ctx, p.ctypes.data_as(C.c_void_p),
+                                                      C.c_int64(p.size)), "mpl_precond_set_weights")
+
+    def precond_get_weights(self):
+        import numpy as np
+        p = np.zeros(self.precond_param_count(), dtype=np.float32)
+        self._check(self._lib.mpl_precond_get_weights(self._ctx, p.ctypes.data_as(C.c_void_p),
+                                                      C.c_int64(p.size)), "mpl_precond_get_weights")
+        return p
+
+    def nn_forward(self, x: torch.Tensor):
+        """Network forward on a dense box x [X, Y, Z, 16] (FP32 device)."""
+        dims = (C.c_int32 * 3)(*x.shape[:3])
+        y = torch.zeros_like(x)
+        self._check(self._lib.mpl_nn_forward(self._ctx, C.c_void_p(_dptr(x, torch.float32)), dims,
+                                             C.c_void_p(y.data_ptr())), "mpl_nn_forward")
+        return y
+
+    def nn_backward(self, x: torch.Tensor, dy: torch.Tensor):
+        """Parameter gradient of <dy, network(x)> (FP32 device, flat)."""
+        dims = (C.c_int32 * 3)(*x.shape[:3])
+        g = torch.zeros(self.precond_param_count(), dtype=torch.float32, device="cuda")
+        self._check(self._lib.mpl_nn_backward(self._ctx, C.c_void_p(_dptr(x, torch.float32)), dims,
+                                              C.c_void_p(_dptr(dy, torch.float32)),
+                                              C.c_void_p(g.data_ptr())), "mpl_nn_backward")
+        return g
+
+    def precond_train_step(self, x, t, mask, lr):
+        dims = (C.c_int32 * 3)(*x.shape[:3])
+        loss = C.c_float()
+        self._check(self._lib.mpl_precond_train_step(
+            self._ctx, C.c_void_p(_dptr(x, torch.float32)), C.c_void_p(_dptr(t, torch.float32)),
+            C.c_void_p(_dptr(mask, torch.float32)), dims, C.c_float(lr), C.byref(loss)),
+            "mpl_precond_train_step")
+        return loss.value
+
+    def precond_apply(self, r: torch.Tensor) -> torch.Tensor:
+        """z = learned preconditioner applied to the dense node vector r."""
+        z = self._node_vec()
+        self._check(self._lib.mpl_precond_apply(self._ctx, C.c_void_p(_dptr(r, torch.float64)),
+                                                C.c_void_p(z.data_ptr())), "mpl_precond_apply")
+        return z
+
+    def precond_reserve(self, capacity: int):
+        self._check(self._lib.mpl_precond_reserve(self._ctx, C.c_int32(capacity)), "mpl_precond_reserve")
+
+    def precond_collect(self, every: int, rtol: float = 1e-10):
+        self._check(self._lib.mpl_precond_collect(self._ctx, C.c_int32(every), C.c_double(rtol)),
+                    "mpl_precond_collect")
+
+    def precond_sample_count(self) -> int:
+        n = C.c_int32()
+        self._check(self._lib.mpl_precond_sample_count(self._ctx, C.byref(n)), "mpl_precond_sample_count")
+        return n.value
+
+    def precond_train(self, n_steps: int, lr: float, seed: int = 0):
+        import numpy as np
+        losses = np.zeros(max(n_steps, 1), dtype=np.float32)
+        self._check(self._lib.mpl_precond_train(self._ctx, C.c_int32(n_steps), C.c_float(lr),
+                                                C.c_uint32(seed), losses.ctypes.data_as(C.c_void_p)),
+                    "mpl_precond_train")
+        return losses[:n_steps]

@@ -22,7 +22,11 @@ def test_header_declares_the_boundary():
     names = declared()
     for required in ("mpl_create", "mpl_destroy", "mpl_step", "mpl_unload", "mpl_reconstruct_stretch",
                      "mpl_energy_grad", "mpl_build_tangent", "mpl_hv", "mpl_pcg", "mpl_solve",
-                     "mpl_load", "mpl_last_error", "mpl_export_field"):
+                     "mpl_load", "mpl_last_error", "mpl_export_field", "mpl_precond_param_count",
+                     "mpl_precond_set_weights", "mpl_precond_get_weights", "mpl_nn_forward",
+                     "mpl_nn_backward", "mpl_precond_train_step", "mpl_precond_apply",
+                     "mpl_precond_reserve", "mpl_precond_collect", "mpl_precond_sample_count",
+                     "mpl_precond_train"):
         assert required in names
 
 
@@ -34,6 +38,8 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (mpl_\w+)", out))
     assert set(declared()) <= exported
+    # and nothing is exported that the header does not document
+    assert exported <= set(declared()), sorted(exported - set(declared()))
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

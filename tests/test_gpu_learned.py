@@ -1,0 +1,145 @@
+"""GPU tests of the learned preconditioner on the solver grid, through the
+C-ABI: its application against the oracle (oracle/precond.py with the BF16
+precision model of the network), flexible CG reaching the FP64 true
+residual, the Jacobi fallback, and pair collection + training."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from oracle import precond as PC
+from oracle import unet as U
+from paper_2602_07853_amd import scenes
+from tests.parity_util import gpu_context, oracle_state, rel
+
+pytestmark = pytest.mark.gpu
+
+LEARNED = 2
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def system():
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=41)
+    print(f"[learned] scene n={sc.n} particles={sc.n_particles}", flush=True)
+    ref = oracle_state(sc)
+    ctx = gpu_context(sc, 1)
+    parts = mpmlite.particles_to_device(sc.particles)
+    ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+    ctx.reconstruct()
+    v = ref["vhat"]
+    ctx.build_tangent(torch.tensor(v, device="cuda"), 1)
+    A, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
+    D = O.jacobi_diag(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A)
+    return sc, ref, ctx, parts, A, D
+
+
+def test_zero_weights_apply_is_jacobi(system):
+    sc, ref, ctx, _, A, D = system
+    ctx.precond_set_weights(np.zeros(ctx.precond_param_count(), np.float32))
+    r = np.random.default_rng(1).normal(size=D.shape) * (D > 0)
+    z = host(ctx.precond_apply(torch.tensor(r, device="cuda")))
+    fr = D > 0
+    assert rel(z[fr], r[fr] / D[fr]) <= 1e-12
+    assert np.all(z[~fr] == 0.0)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_apply_matches_oracle_network(system, seed):
+    sc, ref, ctx, _, A, D = system
+    params = U.bf16(U.init_params(seed=seed, scale=0.5))
+    ctx.precond_set_weights(params)
+    r = np.random.default_rng(seed).normal(size=D.shape) * (D > 0)
+    z = host(ctx.precond_apply(torch.tensor(r, device="cuda")))
+    zo = PC.apply(params, sc.n, r, D, rnd=U.bf16)
+    fr = D > 0
+    jac = np.where(fr, r / np.where(fr, D, 1.0), 0.0)
+    # the Jacobi part is exact; the network part carries BF16 storage error
+    e = rel(z - jac, zo - jac)
+    print(f"[learned] seed {seed} network-part rel err {e:.2e}", flush=True)
+    assert e <= 3e-2
+    assert rel(z, zo) <= 1e-2
+
+
+def test_flexible_cg_reaches_true_residual(system):
+    sc, ref, ctx, _, A, D = system
+    ctx.precond_set_weights(U.init_params(seed=5, scale=0.3).astype(np.float32))
+    ctx.set_opts(precond=LEARNED, pcg_rtol=1e-10, max_pcg=4000)
+    try:
+        free = ((ref["mi"] > 0) & (ref["fixed"] == 0))[:, None]
+        b = np.random.default_rng(6).normal(size=D.shape) * free
+        x, iters, relres = ctx.pcg(torch.tensor(b, device="cuda"))
+        res = b - O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, host(x))
+        print(f"[learned] flexible CG iters {iters} recurrence {relres:.2e} "
+              f"true {np.linalg.norm(res) / np.linalg.norm(b):.2e}", flush=True)
+        assert iters > 0 and relres <= 1e-10
+        assert np.linalg.norm(res) <= 1e-9 * np.linalg.norm(b)
+    finally:
+        ctx.set_opts(precond=0, pcg_rtol=sc.pcg_rtol)
+
+
+def test_nan_weights_fall_back_to_jacobi():
+    """A network producing NaN trips the z.r test at once: every Newton
+    system falls back, and the Newton solution is the Jacobi one."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=42)
+    parts = mpmlite.particles_to_device(sc.particles)
+    sols = {}
+    for precond in (0, LEARNED):
+        ctx = gpu_context(sc, 1, newton_rtol=1e-12, pcg_rtol=1e-12, precond=precond)
+        if precond == LEARNED:
+            w = np.zeros(ctx.precond_param_count(), np.float32)
+            w[:] = np.nan
+            ctx.precond_set_weights(w)
+        ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        print(f"[learned] precond {precond} stats {st}", flush=True)
+        sols[precond] = (host(v), st)
+    (v0, s0), (v1, s1) = sols[0], sols[LEARNED]
+    assert s0["fallbacks"] == 0
+    assert s1["fallbacks"] == s1["newton_iters"] > 0
+    assert rel(v1, v0) <= 1e-10
+
+
+def test_zero_weights_flexible_cg_matches_jacobi_iterations():
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=43)
+    parts = mpmlite.particles_to_device(sc.particles)
+    its = {}
+    for precond in (0, LEARNED):
+        ctx = gpu_context(sc, 1, precond=precond)
+        if precond == LEARNED:
+            ctx.precond_set_weights(np.zeros(ctx.precond_param_count(), np.float32))
+        ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        its[precond] = st
+    assert its[LEARNED]["fallbacks"] == 0
+    assert abs(its[LEARNED]["pcg_iters"] - its[0]["pcg_iters"]) <= max(2, its[0]["pcg_iters"] // 20)
+
+
+def test_collect_pairs_and_train():
+    """Pairs recorded during Newton solves satisfy their definition, and
+    training on them lowers the loss."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.config1()
+    parts = mpmlite.particles_to_device(sc.particles)
+    out = {k: v.clone() for k, v in parts.items()}
+    ctx = gpu_context(sc, 0)
+    ctx.precond_set_weights(U.init_params(seed=8, scale=0.2).astype(np.float32))
+    ctx.precond_reserve(24)
+    ctx.precond_collect(every=4, rtol=1e-10)
+    st = ctx.step(parts, out, sc.dt, sc.gravity, sc.bcs, 0.0)
+    n = ctx.precond_sample_count()
+    print(f"[learned] collected {n} pairs, step stats {st}", flush=True)
+    assert 0 < n <= 24
+    losses = ctx.precond_train(120, 1e-3, seed=1)
+    print(f"[learned] losses first {losses[:5]} last {losses[-5:]}", flush=True)
+    assert np.all(np.isfinite(losses))
+    assert losses[-20:].mean() < 0.9 * losses[:20].mean()

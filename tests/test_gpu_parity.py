@@ -225,3 +225,21 @@ def test_particle_outside_grid_is_rejected():
         ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
     assert e.value.status == -7
     assert np.array_equal(host(dp["x"]), before)  # state untouched on failure
+
+
+def test_graph_replay_matches_eager_launches(monkeypatch):
+    """The PCG loop replays a captured chunk of iterations many times (with
+    host synchronisation between replays); the result must be bit-identical
+    to launching the same kernels eagerly."""
+    from paper_2602_07853_amd import mpmlite
+    sc = SCENES["fcr_two_materials"]
+    outs = []
+    for no_graph in ("0", "1"):
+        monkeypatch.setenv("MPL_NO_GRAPHS", no_graph)
+        ctx = gpu_context(sc, 0, pcg_check_every=4)
+        dp = mpmlite.particles_to_device(sc.particles)
+        st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+        assert st["pcg_iters"] > 8  # several replays of the 4-iteration chunk
+        outs.append({k: host(v) for k, v in dp.items()})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k

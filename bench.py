@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    ap.add_argument("--learned-steps", type=int, default=2,
+                    help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
+    ap.add_argument("--learned-train-steps", type=int, default=2,
+                    help="untimed Jacobi steps with online network training before that leg")
     return ap.parse_args()
 
 
@@ -121,6 +125,7 @@ def main():
         step_idx += 1
         return st
 
+    parts0 = {k: v.clone() for k, v in parts.items()} if args.learned_steps > 0 else None
     for w in range(args.warmup):
         st = one_step()
         print(f"[bench] warmup {w} {json.dumps(st)}", file=sys.stderr, flush=True)
@@ -161,11 +166,14 @@ def main():
             "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
             "bytes_per_launch": hv_bytes, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
+    learned = None
+    if args.learned_steps > 0:
+        learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts)
     base = None
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
         base = cpu_baseline(sc, counts)
     line = {
-        "metric": "implicit steps/s @1M cells to resid 1e-6 (plain Jacobi PCG); Hv HBM GB/s",
+        "metric": "implicit steps/s @1M cells to resid 1e-6, learned vs plain PCG; Hv HBM GB/s",
         "value": round(steps_per_s, 4),
         "unit": "steps/s",
         "n_gpus": 1,
@@ -183,8 +191,54 @@ def main():
                    "hv_precision": args.precision},
         "roofline": roof,
         "cpu_baseline": base,
+        "learned": learned,
     }
     print(json.dumps(line), flush=True)
+
+
+def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
+    """The same workload from its initial state with the learned preconditioner
+    (flexible CG, Jacobi fallback): the network starts as the zero map (i.e.
+    Jacobi), is trained online on the energy-norm loss during
+    ``learned_train_steps`` untimed Jacobi steps, then ``learned_steps`` steps
+    are timed with the learned preconditioner and no training."""
+    import torch
+    from paper_2602_07853_amd import precond_train
+    ctx.precond_set_weights(precond_train.init_weights(0))
+    ctx.set_opts(time_kernels=0, precond=0)
+    ctx.precond_online(64, 1, 1e-3)
+    t = 0.0
+    for k in range(args.learned_train_steps):
+        st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        n, loss = ctx.precond_online_stats()
+        print(f"[bench] learned-leg training step {k}: pcg {st['pcg_iters']} train steps {n} "
+              f"mean loss {loss:.4f}", file=sys.stderr, flush=True)
+    ctx.precond_online(0, 0, 0.0)
+    ctx.set_opts(precond=2)
+    torch.cuda.synchronize()
+    newton = pcg = fb = 0
+    t0 = time.perf_counter()
+    for k in range(args.learned_steps):
+        st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        newton += st["newton_iters"]
+        pcg += st["pcg_iters"]
+        fb += st["fallbacks"]
+        print(f"[bench] learned step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} "
+              f"fallbacks {st['fallbacks']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_opts(precond=0)
+    n = args.learned_steps
+    sps = n / el
+    return {"steps_per_s": round(sps, 4), "steps": n, "ms_per_step": round(1e3 * el / n, 3),
+            "newton_per_step": round(newton / n, 3), "pcg_per_step": round(pcg / n, 2),
+            "fallbacks_per_step": round(fb / n, 3),
+            "vs_plain": round(sps / plain_steps_per_s, 4),
+            "plain_pcg_per_step": round(plain_counts[1], 2),
+            "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "
+                        "from the workload's initial state, 1 Adam step per 64 CG iterations"}
 
 
 def ctx_version():

@@ -249,6 +249,19 @@ mpl_status mpl_precond_reserve(mpl_ctx* ctx, int32_t capacity);
  * iteration is repeated to store (features of r_k, target
  * D^{1/2}(x* - x_k - D^{-1} r_k)/s, free mask) every `every` iterations. */
 mpl_status mpl_precond_collect(mpl_ctx* ctx, int32_t every, double rtol);
+/* Online training for later mpl_pcg / mpl_solve / mpl_step calls (every = 0
+ * turns it off; weights must be set): inside each linear solve, at the first
+ * convergence poll and then every `every` iterations, `steps` Adam steps
+ * (learning rate lr) on the energy-norm loss of the solver's current
+ * residual r under the current Newton matrix H:
+ *   L(z) = (z^T H z / 2 - z^T r) / (r^T D^{-1} r),  z = preconditioner(r),
+ * minimised by z = H^{-1} r.  The solve itself is unchanged (its vectors and
+ * scalars are not touched); the network changes between its iterations. */
+mpl_status mpl_precond_online(mpl_ctx* ctx, int32_t every, int32_t steps, float lr);
+/* Online training counters (host pointers, may be NULL): total steps taken,
+ * and the mean loss of the network before each training burst since the
+ * last call (then reset). */
+mpl_status mpl_precond_online_stats(mpl_ctx* ctx, int64_t* steps_done, double* mean_loss);
 /* Number of stored training pairs (*n, host). */
 mpl_status mpl_precond_sample_count(mpl_ctx* ctx, int32_t* n);
 /* n_steps Adam steps on the stored pairs, visited in a pseudo-random order

@@ -276,7 +276,8 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
                    &c->Y64, &c->vcl, &c->Gcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
-                   &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar};
+                   &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
+                   &c->ogr};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

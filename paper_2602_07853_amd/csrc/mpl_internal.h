@@ -109,6 +109,14 @@ struct mpl_ctx {
   double collect_rtol = 1e-10;
   DevBuf xstar;
   int fallbacks_total = 0;
+  // online training of the learned preconditioner during Newton solves
+  // (energy-norm loss on the solver's own residuals; 0 = off)
+  int online_every = 0, online_steps = 0;
+  float online_lr = 0.f;
+  int64_t online_done = 0;     // training steps taken
+  double online_loss_sum = 0;  // sum of first-step losses since the last read
+  int64_t online_loss_n = 0;
+  DevBuf ozt, ohz, ogr;
 
   // learned preconditioner (allocated on first use)
   NNState* nn = nullptr;

@@ -32,6 +32,7 @@ NNState* nn_state(mpl_ctx* c);
 void nn_destroy(mpl_ctx* c);
 mpl_status nn_forward(mpl_ctx* c, NNState& nn);
 mpl_status nn_backward(mpl_ctx* c, NNState& nn);
+mpl_status nn_backward_update(mpl_ctx* c, NNState& nn, float lr);
 
 // ---- the network as a preconditioner on the solver grid ----
 double nn_inv_free_dofs(mpl_ctx* c);
@@ -56,3 +57,5 @@ mpl_status nn_stage_features(mpl_ctx* c, const double* r, const double* Dinv, co
 mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const double* xstar,
                             const double* Dinv, const double* s2);
 NNSampleStore& nn_samples(mpl_ctx* c);
+// stage the network's output gradient from a node vector (block layout)
+mpl_status nn_stage_output_grad(mpl_ctx* c, const double* g);

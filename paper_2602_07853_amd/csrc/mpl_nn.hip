@@ -949,6 +949,31 @@ __global__ __launch_bounds__(256) void k_record(const double* __restrict__ r, co
   mask[v] = fr ? 1.f : 0.f;
 }
 
+// Output gradient of the network from a node vector g (3 comps, block
+// layout): gact[t_out][voxel][a] = g_a at the voxel's node (free nodes), all
+// other channels and voxels 0.
+__global__ __launch_bounds__(256) void k_out_grad(const double* __restrict__ g,
+                                                  const uint8_t* __restrict__ flags,
+                                                  const int32_t* __restrict__ nmap, Box3 nbd,
+                                                  int64_t nnode, Box3 box, uint16_t* __restrict__ gout) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nv = (int64_t)box.d[0] * box.d[1] * box.d[2];
+  if (v >= nv) return;
+  const int k = (int)(v % box.d[2]), j = (int)((v / box.d[2]) % box.d[1]),
+            i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
+  const int64_t ni = voxel_node(i, j, k, nmap, nbd);
+  float f[3] = {0.f, 0.f, 0.f};
+  if (ni >= 0 && (flags[ni] & MPL_NODE_FREE))
+    for (int a = 0; a < 3; ++a) f[a] = (float)g[a * nnode + ni];
+  uint4 lo, hi = make_uint4(0, 0, 0, 0);
+  lo.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+  lo.y = (uint32_t)f2bf(f[2]);
+  lo.z = 0;
+  lo.w = 0;
+  reinterpret_cast<uint4*>(gout + v * 16)[0] = lo;
+  reinterpret_cast<uint4*>(gout + v * 16)[1] = hi;
+}
+
 }  // namespace
 
 NNSampleStore& nn_samples(mpl_ctx* c) {
@@ -994,6 +1019,15 @@ mpl_status nn_stage_features(mpl_ctx* c, const double* r, const double* Dinv, co
   return MPL_OK;
 }
 
+mpl_status nn_stage_output_grad(mpl_ctx* c, const double* g) {
+  NNState& nn = *nn_state(c);
+  const int64_t nv = (int64_t)nn.box[0] * nn.box[1] * nn.box[2];
+  Box3 b{{nn.box[0], nn.box[1], nn.box[2]}}, nbd{{c->nbd[0], c->nbd[1], c->nbd[2]}};
+  MPL_LAUNCH(c, k_out_grad, (int)((nv + 255) / 256), 256, g, P<uint8_t>(c->flags), P<int32_t>(c->nmap),
+             nbd, (int64_t)c->nnode_alloc(), b, (uint16_t*)nn.gact.p + nn.t_out);
+  return MPL_OK;
+}
+
 mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const double* xstar,
                             const double* Dinv, const double* s2) {
   NNState& nn = *nn_state(c);
@@ -1017,6 +1051,22 @@ mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const 
   return MPL_OK;
 }
 
+// Parameter gradient of the loss whose output gradient is staged at
+// gact[t_out] (activations of the same input in act), then one Adam step
+// and the refresh of the swizzled BF16 weights.
+mpl_status nn_backward_update(mpl_ctx* c, NNState& nn, float lr) {
+  const int64_t np = nn_param_count();
+  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
+  MPL_TRY(nn_backward(c, nn));
+  nn.adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);
+  MPL_LAUNCH(c, k_adam, (int)((np + 255) / 256), 256, (float*)nn.params.p, (const float*)nn.grad.p,
+             (float*)nn.adam_m.p, (float*)nn.adam_v.p, np, lr, b1, b2, 1e-8f, c1, c2);
+  MPL_TRY(nn_refresh(c, nn));
+  return MPL_OK;
+}
+
 // one Adam step on a staged bf16 sample
 static mpl_status nn_train_on(mpl_ctx* c, NNState& nn, const uint16_t* feat, const float* t,
                               const float* mask, float lr, double* loss_dev) {
@@ -1030,16 +1080,7 @@ static mpl_status nn_train_on(mpl_ctx* c, NNState& nn, const uint16_t* feat, con
   MPL_LAUNCH(c, k_loss_final, 1, 1, lp + 8, 1024, loss_dev);
   MPL_LAUNCH(c, k_loss_grad, (int)((nvox + 255) / 256), 256, y, 16, t, mask, nvox, loss_dev,
              (uint16_t*)nn.gact.p + nn.t_out, 16);
-  const int64_t np = nn_param_count();
-  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
-  MPL_TRY(nn_backward(c, nn));
-  nn.adam_t += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);
-  MPL_LAUNCH(c, k_adam, (int)((np + 255) / 256), 256, (float*)nn.params.p, (const float*)nn.grad.p,
-             (float*)nn.adam_m.p, (float*)nn.adam_v.p, np, lr, b1, b2, 1e-8f, c1, c2);
-  MPL_TRY(nn_refresh(c, nn));
-  return MPL_OK;
+  return nn_backward_update(c, nn, lr);
 }
 
 extern "C" {
@@ -1064,6 +1105,24 @@ mpl_status mpl_precond_collect(mpl_ctx* c, int32_t every, double rtol) {
   if (!c || every < 0 || !(rtol > 0.0)) return MPL_ERR_INVALID_ARG;
   c->collect_every = every;
   c->collect_rtol = rtol;
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_online(mpl_ctx* c, int32_t every, int32_t steps, float lr) {
+  if (!c || every < 0 || steps < 0 || !(lr >= 0.f)) return MPL_ERR_INVALID_ARG;
+  if (every > 0 && (!c->nn || !c->nn->ready)) return mpl_fail(c, MPL_ERR_STATE, "set network weights first");
+  c->online_every = every;
+  c->online_steps = steps;
+  c->online_lr = lr;
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_online_stats(mpl_ctx* c, int64_t* steps_done, double* mean_loss) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  if (steps_done) *steps_done = c->online_done;
+  if (mean_loss) *mean_loss = c->online_loss_n ? c->online_loss_sum / (double)c->online_loss_n : 0.0;
+  c->online_loss_sum = 0.0;
+  c->online_loss_n = 0;
   return MPL_OK;
 }
 

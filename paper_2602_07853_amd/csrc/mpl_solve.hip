@@ -848,6 +848,98 @@ __global__ __launch_bounds__(256) void k_precond_z(const double* __restrict__ r,
   for (int a = 0; a < 3; ++a) z[a * nnode + ni] = zz[a];
 }
 
+// ---- online training of the learned preconditioner ----
+// Energy-norm loss on the solver's residual r:
+//   L(z) = (1/2 z^T H z - z^T r) / (r^T Dinv r),
+// minimised by z = H^{-1} r; L - L(H^{-1} r) is half the squared H-norm
+// error of z over r^T Dinv r.  With z = Dinv r + s sqrt(Dinv) o:
+//   dL/do = s sqrt(Dinv) (H z - r) / (r^T Dinv r).
+__global__ __launch_bounds__(256) void k_online_rdr(const double* __restrict__ r,
+                                                    const double* __restrict__ Dinv,
+                                                    const uint8_t* __restrict__ flags, int64_t nnode,
+                                                    int n_nblk, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  double acc = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    if (flags[ni] & MPL_NODE_FREE)
+      for (int a = 0; a < 3; ++a) {
+        const double rv = r[a * nnode + ni];
+        acc += rv * rv * Dinv[a * nnode + ni];
+      }
+  }
+  acc = block4_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_online_z(const double* __restrict__ r,
+                                                  const double* __restrict__ Dinv,
+                                                  const uint8_t* __restrict__ flags,
+                                                  const int4* __restrict__ ncoord, int64_t nnode,
+                                                  int n_nblk, NetOut net, const double* __restrict__ rdr,
+                                                  T* __restrict__ z) {
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (nb >= n_nblk) return;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double zz[3] = {0.0, 0.0, 0.0};
+  if (flags[ni] & MPL_NODE_FREE)
+    learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(rdr[0] * net.inv_nfree, 1e-300)), false,
+              zz);
+  for (int a = 0; a < 3; ++a) z[a * nnode + ni] = (T)zz[a];
+}
+
+// partials z.Hz and z.r
+template <class T>
+__global__ __launch_bounds__(256) void k_online_dots(const double* __restrict__ r,
+                                                     const T* __restrict__ z,
+                                                     const T* __restrict__ hz,
+                                                     const uint8_t* __restrict__ flags, int64_t nnode,
+                                                     int n_nblk, double* __restrict__ pzhz,
+                                                     double* __restrict__ pzr) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  double a1 = 0.0, a2 = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    if (flags[ni] & MPL_NODE_FREE)
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        a1 += (double)z[i] * (double)hz[i];
+        a2 += (double)z[i] * r[i];
+      }
+  }
+  a1 = block4_sum(a1, sh);
+  a2 = block4_sum(a2, sh);
+  if (threadIdx.x == 0) {
+    pzhz[blockIdx.x] = a1;
+    pzr[blockIdx.x] = a2;
+  }
+}
+
+// node-layout output gradient s sqrt(Dinv) (Hz - r) / rdr; loss into *loss
+template <class T>
+__global__ __launch_bounds__(256) void k_online_grad(const double* __restrict__ r,
+                                                     const T* __restrict__ hz,
+                                                     const double* __restrict__ Dinv,
+                                                     const uint8_t* __restrict__ flags, int64_t nnode,
+                                                     int n_nblk, double inv_nfree,
+                                                     const double* __restrict__ red,
+                                                     double* __restrict__ g, double* __restrict__ loss) {
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  const double rdr = red[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *loss = rdr > 0.0 ? (0.5 * red[1] - red[2]) / rdr : 0.0;
+  if (nb >= n_nblk) return;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const double sc = sqrt(fmax(rdr * inv_nfree, 1e-300));
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = a * nnode + ni;
+    g[i] = (fr && rdr > 0.0) ? sc * sqrt(Dinv[i]) * ((double)hz[i] - r[i]) / rdr : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
                                                  const double* __restrict__ dir, double alpha,
                                                  const double* __restrict__ g,
@@ -909,7 +1001,7 @@ static mpl_status upload_mats(mpl_ctx* c) {
 
 static mpl_status ensure_partials(mpl_ctx* c) {
   size_t n = std::max(c->n_cblk, c->n_nblk) + 64;
-  return mpl_ensure(c, c->partials, sizeof(double) * 4 * n);
+  return mpl_ensure(c, c->partials, sizeof(double) * 8 * n);
 }
 static double* partial_slot(mpl_ctx* c, int k) {
   size_t n = std::max(c->n_cblk, c->n_nblk) + 64;
@@ -1194,7 +1286,8 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
 // product, alpha, update (x, r, q = Hp stored), convergence/stagnation
 // check, network input, network forward, z.r and z.q, beta, new direction.
 template <class T>
-static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
+                              const std::function<mpl_status(int)>* hook = nullptr) {
   if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
   NNState& nn = *c->nn;
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
@@ -1255,7 +1348,7 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                            q,           nn.act.p,    nn.wsw.p,        c->ncoord.p};
     const int keyn[6] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2]};
-    st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, nullptr);
+    st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, hook);
   }
   nn.skip = nullptr;
   MPL_TRY(st);
@@ -1267,10 +1360,80 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
   return MPL_OK;
 }
 
+// Online training: `steps` Adam steps of the network on the energy-norm
+// loss of the current residual c->r under the current tangent.  Runs
+// between PCG chunks; touches neither the iteration's vectors nor its
+// control scalars (its reductions use red[0..3] and partial slots 4-6).
+template <class T>
+static mpl_status online_train(mpl_ctx* c) {
+  NNState& nn = *c->nn;
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(nn_prepare_box(c, true));
+  MPL_TRY(mpl_ensure(c, c->ozt, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->ohz, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->ogr, sizeof(double) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * (c->online_steps + 64) + 2 * sizeof(double) * (c->n_nblk + 64)));
+  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  const int32_t* saved_skip = nn.skip;
+  const int saved_tk = c->opts.time_kernels;
+  nn.skip = nullptr;
+  c->opts.time_kernels = 0;
+  SolverScalars* s = c->dscal();
+  const int nwg = (c->n_nblk + 3) / 4;
+  double* p4 = partial_slot(c, 4);
+  double* p5 = partial_slot(c, 5);
+  const double* r = P<double>(c->r);
+  const double* D = P<double>(c->D);
+  T* z = P<T>(c->ozt);
+  T* hz = P<T>(c->ohz);
+  // losses go after the dref partials in nn.tmp
+  double* losses = P<double>(nn.tmp) + 2 * (c->n_nblk + 64);
+  const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
+                   nn_inv_free_dofs(c)};
+  mpl_status st = MPL_OK;
+  auto run = [&]() -> mpl_status {
+    MPL_LAUNCH(c, k_online_rdr, nwg, 256, r, D, P<uint8_t>(c->flags), nnode, c->n_nblk, p4);
+    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p4, 0, p4, 0, s, 0);
+    for (int k = 0; k < c->online_steps; ++k) {
+      MPL_TRY(nn_stage_features(c, r, D, &s->red[0]));
+      MPL_TRY(nn_forward(c, nn));
+      MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
+                 c->n_nblk, net, &s->red[0], z);
+      MPL_TRY(hv_pieces<T>(c, z, false));
+      const T* Hown = P<T>(pieces_buf<T>(c));
+      MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
+                 P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
+      MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,
+                 c->n_nblk, p4, p5);
+      MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p5, nwg, p5, 0, s, 1);
+      MPL_LAUNCH(c, k_online_grad<T>, nwg, 256, r, (const T*)hz, D, P<uint8_t>(c->flags), nnode, c->n_nblk,
+                 nn_inv_free_dofs(c), (const double*)&s->red[0], P<double>(c->ogr), losses + k);
+      MPL_TRY(nn_stage_output_grad(c, P<double>(c->ogr)));
+      MPL_TRY(nn_backward_update(c, nn, c->online_lr));
+    }
+    return MPL_OK;
+  };
+  st = run();
+  nn.skip = saved_skip;
+  c->opts.time_kernels = saved_tk;
+  MPL_TRY(st);
+  double first = 0.0;
+  MPL_HIP(c, hipMemcpyAsync(&first, losses, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  c->online_done += c->online_steps;
+  if (std::isfinite(first)) {
+    c->online_loss_sum += first;
+    c->online_loss_n += 1;
+  }
+  return MPL_OK;
+}
+
 // Training pairs for the learned preconditioner: solve H x* = b to
-// collect_rtol with Jacobi PCG, then run the same (deterministic) iteration
-// again and record (r_k, x* - x_k) every collect_every iterations until the
-// sample store is full.  x* is left in c->xstar.
+// collect_rtol with Jacobi PCG, then run the solver's own iteration (Jacobi
+// PCG, or flexible CG with the current network when the learned
+// preconditioner is selected, so that later pairs follow the residuals the
+// trained solver meets) and record (r_k, x* - x_k) every collect_every
+// iterations until the sample store is full.  x* is left in c->xstar.
 template <class T>
 static mpl_status collect_pairs(mpl_ctx* c, const double* b, int* iters) {
   const int64_t nnode = (int64_t)c->nnode_alloc();
@@ -1284,15 +1447,18 @@ static mpl_status collect_pairs(mpl_ctx* c, const double* b, int* iters) {
   double rel = 0.0;
   mpl_status st = pcg_impl<T>(c, b, P<double>(c->xstar), iters, &rel);
   NNSampleStore& store = nn_samples(c);
+  const bool learned = saved.precond == MPL_PRECOND_LEARNED;
+  // sum Dinv r^2 of the current residual: r.z in Jacobi PCG, s2 in flexible CG
+  const double* s2 = learned ? &c->dscal()->s2 : &c->dscal()->rz;
   std::function<mpl_status(int)> hook = [&](int) -> mpl_status {
     if (store.count >= store.capacity) return MPL_OK;
-    return nn_record_sample(c, P<double>(c->r), P<double>(c->x), P<double>(c->xstar), P<double>(c->D),
-                            &c->dscal()->rz);
+    return nn_record_sample(c, P<double>(c->r), P<double>(c->x), P<double>(c->xstar), P<double>(c->D), s2);
   };
   if (st == MPL_OK && store.count < store.capacity) {
-    // stop the replay once the store is full or the exact solve's length is reached
+    // stop the replay at the exact solve's length
     c->opts.max_pcg = std::max(1, std::min(c->opts.max_pcg, *iters));
-    st = pcg_impl<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook);
+    st = learned ? pcg_learned<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook)
+                 : pcg_impl<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook);
   }
   c->opts = saved;
   return st;
@@ -1329,12 +1495,22 @@ mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* rin, double* z) {
 
 mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
   if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
+  // online training of the network at the first chunk boundary and then
+  // every online_every iterations
+  const bool online = c->online_every > 0 && c->online_steps > 0 && c->nn && c->nn->ready;
+  int last = -1;
+  std::function<mpl_status(int)> hook = [&](int it) -> mpl_status {
+    if (last >= 0 && it - last < c->online_every) return MPL_OK;
+    last = it;
+    return c->tangent_precision == MPL_F32 ? online_train<float>(c) : online_train<double>(c);
+  };
+  const std::function<mpl_status(int)>* h = online ? &hook : nullptr;
   if (c->opts.precond == MPL_PRECOND_LEARNED) {
-    if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel);
-    return pcg_learned<double>(c, b, x, iters, rel);
+    if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel, h);
+    return pcg_learned<double>(c, b, x, iters, rel, h);
   }
-  if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel);
-  return pcg_impl<double>(c, b, x, iters, rel);
+  if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel, h);
+  return pcg_impl<double>(c, b, x, iters, rel, h);
 }
 
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {

@@ -349,3 +349,14 @@ class Context:
                                                 C.c_uint32(seed), losses.ctypes.data_as(C.c_void_p)),
                     "mpl_precond_train")
         return losses[:n_steps]
+
+    def precond_online(self, every: int, steps: int = 1, lr: float = 1e-3):
+        self._check(self._lib.mpl_precond_online(self._ctx, C.c_int32(every), C.c_int32(steps),
+                                                 C.c_float(lr)), "mpl_precond_online")
+
+    def precond_online_stats(self):
+        n = C.c_int64()
+        loss = C.c_double()
+        self._check(self._lib.mpl_precond_online_stats(self._ctx, C.byref(n), C.byref(loss)),
+                    "mpl_precond_online_stats")
+        return n.value, loss.value

@@ -1,0 +1,117 @@
+"""Training driver of the learned preconditioner (the network and its
+training run in the library: pair collection during Newton solves, BF16
+MFMA forward/backward, Adam on FP32 master weights; this module only
+sequences the calls and stores the weights).
+
+    python -m paper_2602_07853_amd.precond_train --config 3 --out weights.npy
+
+collects (residual, error) pairs from the Jacobi-PCG solves of the first
+``--collect-steps`` implicit steps of the scene and trains on them.
+"""
+from __future__ import annotations
+
+import argparse
+import sys
+import time
+
+import numpy as np
+
+# (name, kernel taps, in channels, out channels) in execution order; the
+# flat parameter vector holds W[tap][in][out] then bias[out] per layer.
+CH = (16, 32, 64, 128)
+LAYERS = [("enc0a", 27, 16, 16), ("enc0b", 27, 16, 16), ("down0", 8, 16, 32),
+          ("enc1a", 27, 32, 32), ("enc1b", 27, 32, 32), ("down1", 8, 32, 64),
+          ("enc2a", 27, 64, 64), ("enc2b", 27, 64, 64), ("down2", 8, 64, 128),
+          ("bota", 27, 128, 128), ("botb", 27, 128, 128), ("up2", 8, 128, 64),
+          ("dec2a", 27, 128, 64), ("dec2b", 27, 64, 64), ("up1", 8, 64, 32),
+          ("dec1a", 27, 64, 32), ("dec1b", 27, 32, 32), ("up0", 8, 32, 16),
+          ("dec0a", 27, 32, 16), ("dec0b", 27, 16, 16), ("out", 1, 16, 16)]
+UP = {"up2", "up1", "up0"}
+
+
+def param_count() -> int:
+    return sum(t * ci * co + co for _, t, ci, co in LAYERS)
+
+
+def init_weights(seed: int = 0, out_scale: float = 0.0) -> np.ndarray:
+    """He-normal weights, zero biases; the output layer scaled by out_scale
+    (0 = the network starts as the zero map, i.e. as Jacobi)."""
+    rng = np.random.default_rng(seed)
+    w = []
+    for name, t, ci, co in LAYERS:
+        fan_in = ci if name in UP else t * ci
+        W = rng.normal(0.0, np.sqrt(2.0 / fan_in), t * ci * co)
+        if name == "out":
+            W *= out_scale
+        w += [W, np.zeros(co)]
+    return np.concatenate(w).astype(np.float32)
+
+
+def save_weights(path: str, w: np.ndarray):
+    np.save(path, np.asarray(w, dtype=np.float32), allow_pickle=False)
+
+
+def load_weights(path: str) -> np.ndarray:
+    w = np.load(path, allow_pickle=False)
+    if w.dtype != np.float32 or w.ndim != 1 or w.size != param_count():
+        raise ValueError(f"{path}: expected {param_count()} float32 parameters")
+    return w
+
+
+def collect(ctx, sc, parts, steps: int, every: int, capacity: int, t0: float = 0.0, log=print):
+    """Run `steps` implicit steps of the scene from `parts` (advanced in
+    place) with pair collection on; returns the number of stored pairs."""
+    ctx.precond_reserve(capacity)
+    ctx.precond_collect(every, 1e-10)
+    try:
+        for k in range(steps):
+            st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t0 + k * sc.dt)
+            log(f"[train] collect step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} "
+                f"pairs {ctx.precond_sample_count()}")
+    finally:
+        ctx.precond_collect(0, 1e-10)
+    return ctx.precond_sample_count()
+
+
+def train(ctx, n_steps: int, lr: float, seed: int = 0, chunk: int = 50, log=print):
+    """n_steps Adam steps on the stored pairs (learning rate halved for the
+    last third); returns the per-step losses."""
+    losses = []
+    done = 0
+    t = time.perf_counter()
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        rate = lr if done < 2 * n_steps // 3 else 0.5 * lr
+        losses.append(ctx.precond_train(k, rate, seed=seed + done))
+        done += k
+        log(f"[train] {done}/{n_steps} steps, loss {losses[-1][-k:].mean():.4f} "
+            f"({time.perf_counter() - t:.1f}s)")
+    return np.concatenate(losses) if losses else np.zeros(0)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--collect-steps", type=int, default=3)
+    ap.add_argument("--every", type=int, default=20)
+    ap.add_argument("--capacity", type=int, default=120)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    from paper_2602_07853_amd import mpmlite, scenes
+    sc = scenes.CONFIGS[a.config]()
+    ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                          opts=dict(hv_precision=mpmlite.F32, newton_rtol=1e-6, pcg_rtol=1e-6))
+    ctx.precond_set_weights(init_weights(a.seed))
+    parts = mpmlite.particles_to_device(sc.particles)
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    n = collect(ctx, sc, parts, a.collect_steps, a.every, a.capacity, log=log)
+    log(f"[train] {n} pairs")
+    train(ctx, a.train_steps, a.lr, a.seed, log=log)
+    save_weights(a.out, ctx.precond_get_weights())
+
+
+if __name__ == "__main__":
+    main()

@@ -26,7 +26,7 @@ def test_header_declares_the_boundary():
                      "mpl_precond_set_weights", "mpl_precond_get_weights", "mpl_nn_forward",
                      "mpl_nn_backward", "mpl_precond_train_step", "mpl_precond_apply",
                      "mpl_precond_reserve", "mpl_precond_collect", "mpl_precond_sample_count",
-                     "mpl_precond_train"):
+                     "mpl_precond_train", "mpl_precond_online", "mpl_precond_online_stats"):
         assert required in names
 
 

@@ -53,6 +53,24 @@ __device__ __forceinline__ int node_cell(const int* n_nbr_cell, int nb, int l, i
   return blk < 0 ? -1 : blk * MPL_BC + local_index(x & 3, y & 3, z & 3);
 }
 
+// Slot of local cell l of cell block cb in the compact block-major tangent
+// storage: entry e of the cell lives at base + e*n + rank.
+struct TanSlot {
+  int64_t base;
+  int n, rank;
+  bool active;
+};
+__device__ __forceinline__ TanSlot tan_slot(const uint64_t* __restrict__ cmask,
+                                            const int32_t* __restrict__ coff, int cb, int l) {
+  const uint64_t m = cmask[cb];
+  TanSlot t;
+  t.active = (m >> l) & 1ull;
+  t.n = __popcll(m);
+  t.rank = __popcll(m & ((1ull << l) - 1ull));
+  t.base = 45ll * coff[cb];
+  return t;
+}
+
 // Deterministic wavefront sum (butterfly over 64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

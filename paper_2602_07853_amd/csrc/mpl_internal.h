@@ -39,7 +39,7 @@ struct NNState;
 struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const void* key[16] = {};
+  const void* key[20] = {};
   int keyn[6] = {0, 0, 0, 0, 0, 0};
   int events = 0;
 };
@@ -61,7 +61,8 @@ struct SolverScalars {
   int32_t domain_count;
   int32_t n_cblk, n_nblk;
   int32_t colour_count[8];
-  int32_t n_active_cells, n_active_nodes, n_free_nodes, pad;
+  int32_t n_active_cells, n_active_nodes, n_free_nodes;
+  int32_t n_tan_cells;  // cells that carry a tangent (some V_{c,k} != 0)
 };
 
 struct mpl_ctx {
@@ -92,6 +93,10 @@ struct mpl_ctx {
       pcell, pkey, bin_count, bin_start, bin_fill, sorted;
   // cell fields (FP64 unless noted)
   DevBuf mc, qc, Gc, Vk, Tk, Sk, Qc, ecell, Abar32, Abar64, Y32, Y64, vcl, Gcl;
+  // tangent storage: only cells with some V_{c,k} != 0, block-major
+  // (Abar[45*coff[cb] + e*count(cb) + rank]), with a 64-bit active mask per
+  // cell block (see tan_slot in mpl_grid.h)
+  DevBuf cmask, ccnt, coff;
   // node fields
   DevBuf mi, vn, vhat, flags, v, g, vt, dir, r, x, p32, p64, q32, q64, z, D, partials,
       dense_tmp32, dense_tmp64;

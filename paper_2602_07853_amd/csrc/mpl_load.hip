@@ -112,7 +112,8 @@ __global__ void k_export_cells(const T* __restrict__ src, int comps, int64_t com
         (double)src[a * comp_stride + (int64_t)b * MPL_BC + l];
 }
 
-__global__ void k_export_abar32(const float* __restrict__ Ab, int64_t ncell,
+__global__ void k_export_abar32(const float* __restrict__ Ab, const uint64_t* __restrict__ cmask,
+                                const int32_t* __restrict__ coff,
                                 const int4* __restrict__ ccoord, int n_cblk, int nx, int ny, int nz,
                                 double* __restrict__ dense) {
   const int b = blockIdx.x, l = threadIdx.x;
@@ -120,11 +121,14 @@ __global__ void k_export_abar32(const float* __restrict__ Ab, int64_t ncell,
   const int4 bc = ccoord[b];
   const int i = bc.x * 4 + local_x(l), j = bc.y * 4 + local_y(l), k = bc.z * 4 + local_z(l);
   const int64_t di = ((int64_t)i * ny + j) * nz + k;
-  const int64_t ci = (int64_t)b * MPL_BC + l;
+  const TanSlot ts = tan_slot(cmask, coff, b, l);
+  if (!ts.active) return;
   for (int r = 0; r < 9; ++r)
-    for (int c = 0; c < 9; ++c) dense[di * 81 + r * 9 + c] = (double)Ab[sym9(r, c) * ncell + ci];
+    for (int c = 0; c < 9; ++c)
+      dense[di * 81 + r * 9 + c] = (double)Ab[ts.base + (int64_t)sym9(r, c) * ts.n + ts.rank];
 }
-__global__ void k_export_abar64(const double* __restrict__ Ab, int64_t ncell,
+__global__ void k_export_abar64(const double* __restrict__ Ab, const uint64_t* __restrict__ cmask,
+                                const int32_t* __restrict__ coff,
                                 const int4* __restrict__ ccoord, int n_cblk, int nx, int ny, int nz,
                                 double* __restrict__ dense) {
   const int b = blockIdx.x, l = threadIdx.x;
@@ -132,9 +136,10 @@ __global__ void k_export_abar64(const double* __restrict__ Ab, int64_t ncell,
   const int4 bc = ccoord[b];
   const int i = bc.x * 4 + local_x(l), j = bc.y * 4 + local_y(l), k = bc.z * 4 + local_z(l);
   const int64_t di = ((int64_t)i * ny + j) * nz + k;
-  const int64_t ci = (int64_t)b * MPL_BC + l;
+  const TanSlot ts = tan_slot(cmask, coff, b, l);
+  if (!ts.active) return;
   for (int r = 0; r < 9; ++r)
-    for (int c = 0; c < 9; ++c) dense[di * 81 + r * 9 + c] = Ab[sym9(r, c) * ncell + ci];
+    for (int c = 0; c < 9; ++c) dense[di * 81 + r * 9 + c] = Ab[ts.base + (int64_t)sym9(r, c) * ts.n + ts.rank];
 }
 
 // symmetric 6 -> full 9 for tau / S exports
@@ -291,11 +296,11 @@ mpl_status mpl_export_field(mpl_ctx* c, int32_t field, double* dense) {
       if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "tangent not built");
       MPL_TRY(zero(81 * ncd));
       if (c->tangent_precision == MPL_F32)
-        MPL_LAUNCH(c, k_export_abar32, c->n_cblk, 64, P<float>(c->Abar32), ncell, cc, c->n_cblk, nx,
-                   ny, nz, dense);
+        MPL_LAUNCH(c, k_export_abar32, c->n_cblk, 64, P<float>(c->Abar32), P<uint64_t>(c->cmask),
+                   P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);
       else
-        MPL_LAUNCH(c, k_export_abar64, c->n_cblk, 64, P<double>(c->Abar64), ncell, cc, c->n_cblk, nx,
-                   ny, nz, dense);
+        MPL_LAUNCH(c, k_export_abar64, c->n_cblk, 64, P<double>(c->Abar64), P<uint64_t>(c->cmask),
+                   P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);
       break;
     case MPL_FIELD_MASS_I:
       MPL_TRY(mpl_block_to_dense_nodes(c, c->mi.p, dense, 1, 0));

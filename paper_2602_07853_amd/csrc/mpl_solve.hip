@@ -300,9 +300,13 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
                                                 const double* __restrict__ Vk,
                                                 const double* __restrict__ Sk, int64_t ncell,
                                                 int K, double dt, double inv4dx,
+                                                const uint64_t* __restrict__ cmask,
+                                                const int32_t* __restrict__ coff,
                                                 T* __restrict__ Abar, int32_t* __restrict__ err) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
+  const TanSlot ts = tan_slot(cmask, coff, cb, l);
+  if (!ts.active) return;
   double Ab[45];
 #pragma unroll
   for (int i = 0; i < 45; ++i) Ab[i] = 0.0;
@@ -367,13 +371,15 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
     }
   }
 #pragma unroll
-  for (int i = 0; i < 45; ++i) Abar[i * ncell + ci] = (T)Ab[i];
+  for (int i = 0; i < 45; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)Ab[i];
 }
 
 // Inverse Jacobi diagonal of H at every node, 1 / (m_i + sum_c sum_{b,b'}
 // Abar[(a,b),(a,b')] gw_b gw_b'), and 0 on fixed / massless nodes.
 template <class T>
-__global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t ncell,
+__global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
+                                             const uint64_t* __restrict__ cmask,
+                                             const int32_t* __restrict__ coff,
                                              const double* __restrict__ mi,
                                              const uint8_t* __restrict__ flags,
                                              const int* __restrict__ n_nbr_cell, int64_t nnode,
@@ -386,13 +392,16 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar, int64_t
     for (int d = 0; d < 8; ++d) {
       const int ci = node_cell(n_nbr_cell, nb, l, d);
       if (ci < 0) continue;
+      const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63);
+      if (!ts.active) continue;
       double gw[3];
       corner_grad(d, inv4dx, gw);
       for (int a = 0; a < 3; ++a) {
         double s = 0.0;
         for (int b = 0; b < 3; ++b)
           for (int b2 = 0; b2 < 3; ++b2)
-            s += (double)Abar[sym9(a * 3 + b, a * 3 + b2) * ncell + ci] * gw[b] * gw[b2];
+            s += (double)Abar[ts.base + (int64_t)sym9(a * 3 + b, a * 3 + b2) * ts.n + ts.rank] * gw[b] *
+                 gw[b2];
         dd[a] += s;
       }
     }
@@ -434,7 +443,9 @@ __device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
 template <class T, bool DOT>
 __global__ __launch_bounds__(64) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
-                                                 const T* __restrict__ Abar, int64_t ncell,
+                                                 const T* __restrict__ Abar,
+                                                 const uint64_t* __restrict__ cmask,
+                                                 const int32_t* __restrict__ coff, int64_t ncell,
                                                  int n_cblk, T inv4dx, T* __restrict__ Hown,
                                                  T* __restrict__ Hhalo,
                                                  double* __restrict__ partial,
@@ -474,13 +485,17 @@ __global__ __launch_bounds__(64) void k_hv_fused(const T* __restrict__ p, int64_
   T y[9];
 #pragma unroll
   for (int r = 0; r < 9; ++r) y[r] = T(0);
+  const TanSlot ts = tan_slot(cmask, coff, cb, l);
+  if (ts.active) {
+    const T* A = Abar + ts.base + ts.rank;
 #pragma unroll
-  for (int r = 0; r < 9; ++r) {
+    for (int r = 0; r < 9; ++r) {
 #pragma unroll
-    for (int c = r; c < 9; ++c) {
-      const T a = Abar[sym9(r, c) * ncell + ci];
-      y[r] += a * g[c];
-      if (c != r) y[c] += a * g[r];
+      for (int c = r; c < 9; ++c) {
+        const T a = A[(int64_t)sym9(r, c) * ts.n];
+        y[r] += a * g[c];
+        if (c != r) y[c] += a * g[r];
+      }
     }
   }
   double dot = 0.0;
@@ -1060,17 +1075,22 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   const double inv4dx = 0.25 * c->inv_dx;
   MPL_TRY(mpl_ensure(c, c->D, 8 * 3 * nnode));
+  const int64_t ntan = (int64_t)c->hscal.n_tan_cells + 64;
+  const uint64_t* cm = P<uint64_t>(c->cmask);
+  const int32_t* co = P<int32_t>(c->coff);
   if (precision == MPL_F32) {
-    MPL_TRY(mpl_ensure(c, c->Abar32, 4 * 45 * ncell));
+    MPL_TRY(mpl_ensure(c, c->Abar32, 4 * 45 * ntan));
     MPL_LAUNCH(c, k_tangent<float>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
-               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<float>(c->Abar32), &c->dscal()->err);
-    MPL_LAUNCH(c, k_diag<float>, c->n_nblk, 64, P<float>(c->Abar32), ncell, P<double>(c->mi),
+               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<float>(c->Abar32),
+               &c->dscal()->err);
+    MPL_LAUNCH(c, k_diag<float>, c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
   } else {
-    MPL_TRY(mpl_ensure(c, c->Abar64, 8 * 45 * ncell));
+    MPL_TRY(mpl_ensure(c, c->Abar64, 8 * 45 * ntan));
     MPL_LAUNCH(c, k_tangent<double>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
-               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Abar64), &c->dscal()->err);
-    MPL_LAUNCH(c, k_diag<double>, c->n_nblk, 64, P<double>(c->Abar64), ncell, P<double>(c->mi),
+               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<double>(c->Abar64),
+               &c->dscal()->err);
+    MPL_LAUNCH(c, k_diag<double>, c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
   }
   c->tangent_built = true;
@@ -1128,12 +1148,12 @@ static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot) {
   const int grid = ((c->n_cblk + 7) / 8) * 8;
   if (dot)
     MPL_LAUNCH(c, (k_hv_fused<T, true>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
-               P<T>(abar_buf<T>(c)), ncell, c->n_cblk, inv4, Hown, Hhalo, partial_slot(c, 0),
-               (const SolverScalars*)c->dscal());
+               P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
+               Hown, Hhalo, partial_slot(c, 0), (const SolverScalars*)c->dscal());
   else
     MPL_LAUNCH(c, (k_hv_fused<T, false>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
-               P<T>(abar_buf<T>(c)), ncell, c->n_cblk, inv4, Hown, Hhalo, (double*)nullptr,
-               (const SolverScalars*)nullptr);
+               P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
+               Hown, Hhalo, (double*)nullptr, (const SolverScalars*)nullptr);
   if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
   return MPL_OK;
 }
@@ -1168,13 +1188,13 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
 // Without graph support the chunk is launched eagerly.  hook (may be null)
 // runs on the host after every chunk that leaves the iteration running,
 // with the iteration count.
-static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[16], const int keyn[6],
+static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[20], const int keyn[6],
                              int check, const std::function<mpl_status()>& launch_iteration,
                              const std::function<mpl_status(int)>* hook) {
   bool use_graph = c->graphs_enabled;
   if (use_graph) {
     bool same = gc.exec != nullptr;
-    for (int i = 0; i < 16 && same; ++i) same = gc.key[i] == key[i];
+    for (int i = 0; i < 20 && same; ++i) same = gc.key[i] == key[i];
     for (int i = 0; i < 6 && same; ++i) same = gc.keyn[i] == keyn[i];
     if (same && c->opts.time_kernels && gc.events != 2 * check) same = false;
     if (same && !c->opts.time_kernels && gc.events != 0) same = false;
@@ -1202,7 +1222,7 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[1
         c->graphs_enabled = false;
         use_graph = false;
       } else {
-        for (int i = 0; i < 16; ++i) gc.key[i] = key[i];
+        for (int i = 0; i < 20; ++i) gc.key[i] = key[i];
         for (int i = 0; i < 6; ++i) gc.keyn[i] = keyn[i];
       }
     }
@@ -1267,9 +1287,10 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                P<uint8_t>(c->flags), nnode, c->n_nblk, p, pm, s);
     return MPL_OK;
   };
-  const void* key[16] = {x,           p,           c->r.p,          c->D.p,
+  const void* key[20] = {x,           p,           c->r.p,          c->D.p,
                          abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
-                         c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p};
+                         c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
+                         c->cmask.p,  c->coff.p};
   const int keyn[6] = {c->n_cblk, c->n_nblk, check, 0, 0, 0};
   MPL_TRY(run_chunks(c, c->pcg_cache[0], key, keyn, check, launch_iteration, hook));
   if (iters) *iters = c->hscal.iters;
@@ -1343,10 +1364,11 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
     return precondition(q);
   };
   if (st == MPL_OK) {
-    const void* key[16] = {x,           p,           c->r.p,          c->D.p,
+    const void* key[20] = {x,           p,           c->r.p,          c->D.p,
                            abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
-                           q,           nn.act.p,    nn.wsw.p,        c->ncoord.p};
+                           q,           nn.act.p,    nn.wsw.p,        c->ncoord.p,
+                           c->cmask.p,  c->coff.p,   nn.params.p,     c->nmap.p};
     const int keyn[6] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2]};
     st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, hook);
   }

@@ -307,6 +307,22 @@ __global__ void k_normalise(double* __restrict__ mc, double* __restrict__ qc, do
   }
 }
 
+// Tangent-carrying cells (some V_{c,k} != 0) per cell block: 64-bit mask
+// and count, for the compact tangent storage.
+__global__ __launch_bounds__(64) void k_cell_mask(const double* __restrict__ Vk, int64_t ncell, int K,
+                                                  uint64_t* __restrict__ cmask,
+                                                  int32_t* __restrict__ ccnt) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  bool act = false;
+  for (int k = 0; k < K; ++k) act = act || (Vk[k * ncell + ci] != 0.0);
+  const uint64_t m = __ballot(act);
+  if (l == 0) {
+    cmask[cb] = m;
+    ccnt[cb] = __popcll(m);
+  }
+}
+
 // Sec. 3.3 centre -> node gather with w_ic = 1/8 (race-free: every node
 // gathers from its own 8 cells), then Dirichlet sets and vhat.
 __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict__ n_nbr_cell,
@@ -489,6 +505,12 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   }
   MPL_LAUNCH(c, k_normalise, (int)((ncell + TPB - 1) / TPB), TPB, P<double>(c->mc), P<double>(c->qc),
              P<double>(c->Gc), P<double>(c->Vk), P<double>(c->Tk), ncell, K, &ds->n_active_cells);
+  MPL_TRY(mpl_ensure(c, c->cmask, sizeof(uint64_t) * (c->n_cblk + 1)));
+  MPL_TRY(mpl_ensure(c, c->ccnt, sizeof(int32_t) * (c->n_cblk + 1)));
+  MPL_TRY(mpl_ensure(c, c->coff, sizeof(int32_t) * (c->n_cblk + 1)));
+  MPL_LAUNCH(c, k_cell_mask, c->n_cblk, 64, P<double>(c->Vk), ncell, K, P<uint64_t>(c->cmask),
+             P<int32_t>(c->ccnt));
+  MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->ccnt), P<int32_t>(c->coff), c->n_cblk, &ds->n_tan_cells));
 
   BCDev bd{};
   bd.n = n_bcs;

@@ -230,7 +230,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.2 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.3 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -277,7 +277,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Y64, &c->vcl, &c->Gcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
-                   &c->ogr, &c->cmask, &c->ccnt, &c->coff};
+                   &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

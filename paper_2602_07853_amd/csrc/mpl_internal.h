@@ -39,7 +39,7 @@ struct NNState;
 struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const void* key[20] = {};
+  const void* key[24] = {};
   int keyn[6] = {0, 0, 0, 0, 0, 0};
   int events = 0;
 };
@@ -98,6 +98,9 @@ struct mpl_ctx {
   // cell block (see tan_slot in mpl_grid.h)
   DevBuf cmask, ccnt, coff;
   // node fields
+  // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
+  // (read by the CG vector kernels)
+  DevBuf Dt, mt;
   DevBuf mi, vn, vhat, flags, v, g, vt, dir, r, x, p32, p64, q32, q64, z, D, partials,
       dense_tmp32, dense_tmp64;
   // scalars

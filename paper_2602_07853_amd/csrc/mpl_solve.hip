@@ -183,23 +183,28 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, i
   if ((MODE == RED_ALPHA || MODE == RED_BETA || MODE == RED_FCHECK || MODE == RED_FBETA) &&
       done_flag(s))
     return;
-  // four independent strided streams per array keep several loads in flight
-  double va[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0}, vc[4] = {0, 0, 0, 0};
-  for (int i = t; i < na; i += 4096)
+  // every thread issues all its loads (up to 8 per array) before using any,
+  // so arrays of up to 8192 partials cost one memory round trip
+  double va[8], vb[8], vc[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + 1024 * k < na) va[k] += a[i + 1024 * k];
-  for (int i = t; i < nb; i += 4096)
+  for (int k = 0; k < 8; ++k) {
+    const int i = t + 1024 * k;
+    va[k] = i < na ? a[i] : 0.0;
+    vb[k] = i < nb ? b[i] : 0.0;
+    vc[k] = i < nc ? c[i] : 0.0;
+  }
+  for (int i = t + 8192; i < na; i += 1024) va[0] += a[i];
+  for (int i = t + 8192; i < nb; i += 1024) vb[0] += b[i];
+  for (int i = t + 8192; i < nc; i += 1024) vc[0] += c[i];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + 1024 * k < nb) vb[k] += b[i + 1024 * k];
-  for (int i = t; i < nc; i += 4096)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + 1024 * k < nc) vc[k] += c[i + 1024 * k];
-  const double ra = wave_sum((va[0] + va[1]) + (va[2] + va[3]));
-  const double rb = wave_sum((vb[0] + vb[1]) + (vb[2] + vb[3]));
-  const double rc = wave_sum((vc[0] + vc[1]) + (vc[2] + vc[3]));
+  for (int k = 1; k < 8; ++k) {
+    va[0] += va[k];
+    vb[0] += vb[k];
+    vc[0] += vc[k];
+  }
+  const double ra = wave_sum(va[0]);
+  const double rb = wave_sum(vb[0]);
+  const double rc = wave_sum(vc[0]);
   if ((t & 63) == 0) {
     sh[0][t >> 6] = ra;
     sh[1][t >> 6] = rb;
@@ -383,7 +388,8 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
                                              const double* __restrict__ mi,
                                              const uint8_t* __restrict__ flags,
                                              const int* __restrict__ n_nbr_cell, int64_t nnode,
-                                             double inv4dx, double* __restrict__ D) {
+                                             double inv4dx, double* __restrict__ D,
+                                             T* __restrict__ Dt, T* __restrict__ mt) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double dd[3] = {0.0, 0.0, 0.0};
@@ -407,7 +413,12 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
     }
     for (int a = 0; a < 3; ++a) dd[a] += mi[ni];
   }
-  for (int a = 0; a < 3; ++a) D[a * nnode + ni] = fr ? 1.0 / dd[a] : 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double di = fr ? 1.0 / dd[a] : 0.0;
+    D[a * nnode + ni] = di;
+    Dt[a * nnode + ni] = (T)di;
+  }
+  mt[ni] = (T)mi[ni];
 }
 
 // ---------------------------------------------------------------- Hv
@@ -441,7 +452,7 @@ __device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
 }
 
 template <class T, bool DOT>
-__global__ __launch_bounds__(64) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
+__global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
                                                  const T* __restrict__ Abar,
                                                  const uint64_t* __restrict__ cmask,
@@ -451,89 +462,103 @@ __global__ __launch_bounds__(64) void k_hv_fused(const T* __restrict__ p, int64_
                                                  double* __restrict__ partial,
                                                  const SolverScalars* __restrict__ s) {
   if (s && done_flag(s)) return;
-  const int cb = xcd_block(blockIdx.x, n_cblk);
-  if (cb >= n_cblk) return;
-  const int l = threadIdx.x;
-  __shared__ T tp[3][128];
-  __shared__ T ys[9][64];
-  for (int t = l; t < 125; t += 64) {
-    const int tx = t / 25, ty = (t / 5) % 5, tz = t % 5;
-    const int o = ((tx >> 2) * 2 + (ty >> 2)) * 2 + (tz >> 2);
-    const int64_t ni = (int64_t)c_nbr_node[cb * 8 + o] * MPL_BC + local_index(tx & 3, ty & 3, tz & 3);
+  // four cell blocks per workgroup, one per wavefront
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int grp = xcd_block(blockIdx.x, (n_cblk + 3) >> 2);
+  const int cb = grp * 4 + w;
+  const bool valid = cb < n_cblk;
+  __shared__ T tp_all[4][3][128];
+  __shared__ T ys_all[4][9][64];
+  __shared__ double dsum[4];
+  T(*tp)[128] = tp_all[w];
+  T(*ys)[64] = ys_all[w];
+  if (valid) {
+    for (int t = l; t < 125; t += 64) {
+      const int tx = t / 25, ty = (t / 5) % 5, tz = t % 5;
+      const int o = ((tx >> 2) * 2 + (ty >> 2)) * 2 + (tz >> 2);
+      const int64_t ni = (int64_t)c_nbr_node[cb * 8 + o] * MPL_BC + local_index(tx & 3, ty & 3, tz & 3);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) tp[a][t] = p[a * nnode + ni];
+      for (int a = 0; a < 3; ++a) tp[a][t] = p[a * nnode + ni];
+    }
   }
   __syncthreads();
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   const int lx = l >> 4, ly = (l >> 2) & 3, lz = l & 3;
-  T g[9];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) g[e] = T(0);
-#pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
-    const int t = ((lx + dx) * 5 + (ly + dy)) * 5 + (lz + dz);
-    const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T pa = tp[a][t];
-      g[a * 3 + 0] += pa * sx;
-      g[a * 3 + 1] += pa * sy;
-      g[a * 3 + 2] += pa * sz;
-    }
-  }
-  T y[9];
-#pragma unroll
-  for (int r = 0; r < 9; ++r) y[r] = T(0);
-  const TanSlot ts = tan_slot(cmask, coff, cb, l);
-  if (ts.active) {
-    const T* A = Abar + ts.base + ts.rank;
-#pragma unroll
-    for (int r = 0; r < 9; ++r) {
-#pragma unroll
-      for (int c = r; c < 9; ++c) {
-        const T a = A[(int64_t)sym9(r, c) * ts.n];
-        y[r] += a * g[c];
-        if (c != r) y[c] += a * g[r];
-      }
-    }
-  }
   double dot = 0.0;
-  if (DOT) {
+  if (valid) {
+    T g[9];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) dot += (double)y[r] * (double)g[r];
-  }
-#pragma unroll
-  for (int r = 0; r < 9; ++r) ys[r][l] = y[r];
-  __syncthreads();
-  // Gather: tile node t sums y_c grad w over its in-block cells c = t - d,
-  // in corner order d = 0..7.  Round 0: the lane's own node; round 1: halo.
-  for (int round = 0; round < 2; ++round) {
-    int tx, ty, tz;
-    if (round == 0) {
-      tx = lx; ty = ly; tz = lz;
-    } else {
-      if (l >= 61) break;
-      halo_tile(l, tx, ty, tz);
-    }
-    T h[3] = {T(0), T(0), T(0)};
+    for (int e = 0; e < 9; ++e) g[e] = T(0);
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
       const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
-      const int cx = tx - dx, cy = ty - dy, cz = tz - dz;
-      if (cx < 0 || cy < 0 || cz < 0 || cx > 3 || cy > 3 || cz > 3) continue;
-      const int cl = local_index(cx, cy, cz);
+      const int t = ((lx + dx) * 5 + (ly + dy)) * 5 + (lz + dz);
       const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) h[a] += ys[a * 3][cl] * sx + ys[a * 3 + 1][cl] * sy + ys[a * 3 + 2][cl] * sz;
+      for (int a = 0; a < 3; ++a) {
+        const T pa = tp[a][t];
+        g[a * 3 + 0] += pa * sx;
+        g[a * 3 + 1] += pa * sy;
+        g[a * 3 + 2] += pa * sz;
+      }
     }
-    T* out = (round == 0) ? Hown : Hhalo;
+    T y[9];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) out[a * ncell + ci] = h[a];
+    for (int r = 0; r < 9; ++r) y[r] = T(0);
+    const TanSlot ts = tan_slot(cmask, coff, cb, l);
+    if (ts.active) {
+      const T* A = Abar + ts.base + ts.rank;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+#pragma unroll
+        for (int c = r; c < 9; ++c) {
+          const T a = A[(int64_t)sym9(r, c) * ts.n];
+          y[r] += a * g[c];
+          if (c != r) y[c] += a * g[r];
+        }
+      }
+    }
+    if (DOT) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) dot += (double)y[r] * (double)g[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) ys[r][l] = y[r];
+  }
+  __syncthreads();
+  // Gather: tile node t sums y_c grad w over its in-block cells c = t - d,
+  // in corner order d = 0..7.  Round 0: the lane's own node; round 1: halo.
+  if (valid) {
+    for (int round = 0; round < 2; ++round) {
+      int tx, ty, tz;
+      if (round == 0) {
+        tx = lx; ty = ly; tz = lz;
+      } else {
+        if (l >= 61) break;
+        halo_tile(l, tx, ty, tz);
+      }
+      T h[3] = {T(0), T(0), T(0)};
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+        const int cx = tx - dx, cy = ty - dy, cz = tz - dz;
+        if (cx < 0 || cy < 0 || cz < 0 || cx > 3 || cy > 3 || cz > 3) continue;
+        const int cl = local_index(cx, cy, cz);
+        const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[a] += ys[a * 3][cl] * sx + ys[a * 3 + 1][cl] * sy + ys[a * 3 + 2][cl] * sz;
+      }
+      T* out = (round == 0) ? Hown : Hhalo;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) out[a * ncell + ci] = h[a];
+    }
   }
   if (DOT) {
+    // one partial per group of four blocks (waves summed in a fixed order)
     const double sdot = wave_sum(dot);
-    if (l == 0) partial[cb] = sdot;
+    if (l == 0) dsum[w] = sdot;
+    __syncthreads();
+    if (threadIdx.x == 0 && grp * 4 < n_cblk) partial[grp] = (dsum[0] + dsum[1]) + (dsum[2] + dsum[3]);
   }
 }
 
@@ -609,8 +634,8 @@ __device__ __forceinline__ double block4_sum(double v, double* sh) {
 // x = 0, r = b, p = Dinv r; partials r.z, b.b and p^T M p.
 template <class T>
 __global__ __launch_bounds__(256) void k_pcg_init(const double* __restrict__ b,
-                                                  const double* __restrict__ Dinv,
-                                                  const double* __restrict__ mi,
+                                                  const T* __restrict__ Dinv,
+                                                  const T* __restrict__ mi,
                                                   const uint8_t* __restrict__ flags, int64_t nnode,
                                                   int n_nblk, double* __restrict__ x,
                                                   double* __restrict__ r, T* __restrict__ p,
@@ -622,11 +647,11 @@ __global__ __launch_bounds__(256) void k_pcg_init(const double* __restrict__ b,
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     const bool fr = flags[ni] & MPL_NODE_FREE;
-    const double m = mi[ni];
+    const double m = (double)mi[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
       const double rv = fr ? b[i] : 0.0;
-      const double zv = rv * Dinv[i];
+      const double zv = rv * (double)Dinv[i];
       const T pv = (T)zv;
       x[i] = 0.0;
       r[i] = rv;
@@ -653,8 +678,8 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
                                                     const T* __restrict__ Hown,
                                                     const T* __restrict__ Hhalo,
                                                     const int* __restrict__ n_nbr_cell,
-                                                    int64_t ncell, const double* __restrict__ mi,
-                                                    const double* __restrict__ Dinv,
+                                                    int64_t ncell, const T* __restrict__ mi,
+                                                    const T* __restrict__ Dinv,
                                                     const uint8_t* __restrict__ flags, int64_t nnode,
                                                     int n_nblk, double* __restrict__ x,
                                                     double* __restrict__ r, double* __restrict__ prz,
@@ -671,7 +696,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
     if (flags[ni] & MPL_NODE_FREE) {
       T h[3];
       gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
-      const T m = (T)mi[ni];
+      const T m = mi[ni];
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
         const T pv = p[i];
@@ -681,7 +706,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
         x[i] += alpha * (double)pv;
         const double rv = r[i] - alpha * q;
         r[i] = rv;
-        rz += rv * rv * Dinv[i];
+        rz += rv * rv * (double)Dinv[i];
         rr += rv * rv;
       }
     }
@@ -697,8 +722,8 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
 // p = Dinv r + beta p; partial p^T M p for the next p^T H p.
 template <class T>
 __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict__ r,
-                                                       const double* __restrict__ Dinv,
-                                                       const double* __restrict__ mi,
+                                                       const T* __restrict__ Dinv,
+                                                       const T* __restrict__ mi,
                                                        const uint8_t* __restrict__ flags,
                                                        int64_t nnode, int n_nblk,
                                                        T* __restrict__ p, double* __restrict__ pmm,
@@ -711,10 +736,10 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     const bool fr = flags[ni] & MPL_NODE_FREE;
-    const double m = mi[ni];
+    const double m = (double)mi[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const T pv = fr ? (T)(r[i] * Dinv[i] + beta * (double)p[i]) : T(0);
+      const T pv = fr ? (T)(r[i] * (double)Dinv[i] + beta * (double)p[i]) : T(0);
       p[i] = pv;
       mm += m * (double)pv * (double)pv;
     }
@@ -1083,15 +1108,21 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     MPL_LAUNCH(c, k_tangent<float>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
                P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<float>(c->Abar32),
                &c->dscal()->err);
+    MPL_TRY(mpl_ensure(c, c->Dt, 4 * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->mt, 4 * nnode));
     MPL_LAUNCH(c, k_diag<float>, c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
+               P<float>(c->Dt), P<float>(c->mt));
   } else {
     MPL_TRY(mpl_ensure(c, c->Abar64, 8 * 45 * ntan));
     MPL_LAUNCH(c, k_tangent<double>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
                P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<double>(c->Abar64),
                &c->dscal()->err);
+    MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
     MPL_LAUNCH(c, k_diag<double>, c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
-               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D));
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
+               P<double>(c->Dt), P<double>(c->mt));
   }
   c->tangent_built = true;
   c->tangent_precision = precision;
@@ -1145,13 +1176,13 @@ static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot) {
     if (e0) MPL_HIP(c, hipEventRecord(e0, c->stream));
   }
   const T inv4 = (T)(0.25 * c->inv_dx);
-  const int grid = ((c->n_cblk + 7) / 8) * 8;
+  const int grid = (((c->n_cblk + 3) / 4 + 7) / 8) * 8;
   if (dot)
-    MPL_LAUNCH(c, (k_hv_fused<T, true>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
+    MPL_LAUNCH(c, (k_hv_fused<T, true>), grid, 256, p, nnode, P<int>(c->c_nbr_node),
                P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
                Hown, Hhalo, partial_slot(c, 0), (const SolverScalars*)c->dscal());
   else
-    MPL_LAUNCH(c, (k_hv_fused<T, false>), grid, 64, p, nnode, P<int>(c->c_nbr_node),
+    MPL_LAUNCH(c, (k_hv_fused<T, false>), grid, 256, p, nnode, P<int>(c->c_nbr_node),
                P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
                Hown, Hhalo, (double*)nullptr, (const SolverScalars*)nullptr);
   if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
@@ -1188,13 +1219,13 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
 // Without graph support the chunk is launched eagerly.  hook (may be null)
 // runs on the host after every chunk that leaves the iteration running,
 // with the iteration count.
-static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[20], const int keyn[6],
+static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[24], const int keyn[6],
                              int check, const std::function<mpl_status()>& launch_iteration,
                              const std::function<mpl_status(int)>* hook) {
   bool use_graph = c->graphs_enabled;
   if (use_graph) {
     bool same = gc.exec != nullptr;
-    for (int i = 0; i < 20 && same; ++i) same = gc.key[i] == key[i];
+    for (int i = 0; i < 24 && same; ++i) same = gc.key[i] == key[i];
     for (int i = 0; i < 6 && same; ++i) same = gc.keyn[i] == keyn[i];
     if (same && c->opts.time_kernels && gc.events != 2 * check) same = false;
     if (same && !c->opts.time_kernels && gc.events != 0) same = false;
@@ -1222,7 +1253,7 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
         c->graphs_enabled = false;
         use_graph = false;
       } else {
-        for (int i = 0; i < 20; ++i) gc.key[i] = key[i];
+        for (int i = 0; i < 24; ++i) gc.key[i] = key[i];
         for (int i = 0; i < 6; ++i) gc.keyn[i] = keyn[i];
       }
     }
@@ -1271,24 +1302,24 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
   double* pb = partial_slot(c, 2);
   double* pm = partial_slot(c, 3);
   const int nwg = (c->n_nblk + 3) / 4;
-  MPL_LAUNCH(c, k_pcg_init<T>, nwg, 256, b, P<double>(c->D), P<double>(c->mi), P<uint8_t>(c->flags),
+  MPL_LAUNCH(c, k_pcg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags),
              nnode, c->n_nblk, x, P<double>(c->r), p, pa, pb, pm);
   MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
   MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
   const int check = std::max(1, c->opts.pcg_check_every);
   auto launch_iteration = [&]() -> mpl_status {
     MPL_TRY(hv_pieces<T>(c, p, true));
-    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, nwg, pm, 0, s, 0);
+    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, (c->n_cblk + 3) / 4, pm, nwg, pm, 0, s, 0);
     MPL_LAUNCH(c, k_pcg_update<T>, nwg, 256, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-               P<double>(c->mi), P<double>(c->D), P<uint8_t>(c->flags), nnode, c->n_nblk, x,
+               P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x,
                P<double>(c->r), pa, pb, s, (T*)nullptr);
     MPL_LAUNCH(c, k_reduce<RED_BETA>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
-    MPL_LAUNCH(c, k_pcg_direction<T>, nwg, 256, P<double>(c->r), P<double>(c->D), P<double>(c->mi),
+    MPL_LAUNCH(c, k_pcg_direction<T>, nwg, 256, P<double>(c->r), P<T>(c->Dt), P<T>(c->mt),
                P<uint8_t>(c->flags), nnode, c->n_nblk, p, pm, s);
     return MPL_OK;
   };
-  const void* key[20] = {x,           p,           c->r.p,          c->D.p,
-                         abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
+  const void* key[24] = {x,           p,           c->r.p,          c->Dt.p,
+                         abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                          c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                          c->cmask.p,  c->coff.p};
   const int keyn[6] = {c->n_cblk, c->n_nblk, check, 0, 0, 0};
@@ -1355,20 +1386,21 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
   const int check = std::max(1, c->opts.pcg_check_every);
   auto launch_iteration = [&]() -> mpl_status {
     MPL_TRY(hv_pieces<T>(c, p, true));
-    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, c->n_cblk, pm, nwg, pm, 0, s, 0);
+    MPL_LAUNCH(c, k_reduce<RED_ALPHA>, 1, 1024, pk, (c->n_cblk + 3) / 4, pm, nwg, pm, 0, s, 0);
     MPL_LAUNCH(c, k_pcg_update<T>, nwg, 256, p, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-               P<double>(c->mi), D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa, pb,
+               P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa, pb,
                s, q);
     // pa = sum Dinv r^2, pb = r.r
     MPL_LAUNCH(c, k_reduce<RED_FCHECK>, 1, 1024, pb, nwg, pa, nwg, pa, 0, s, 0);
     return precondition(q);
   };
   if (st == MPL_OK) {
-    const void* key[20] = {x,           p,           c->r.p,          c->D.p,
+    const void* key[24] = {x,           p,           c->r.p,          c->D.p,
                            abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mi.p,
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                            q,           nn.act.p,    nn.wsw.p,        c->ncoord.p,
-                           c->cmask.p,  c->coff.p,   nn.params.p,     c->nmap.p};
+                           c->cmask.p,  c->coff.p,   nn.params.p,     c->nmap.p,
+                           c->Dt.p,     c->mt.p};
     const int keyn[6] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2]};
     st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, hook);
   }

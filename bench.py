@@ -8,9 +8,11 @@ products, FP64 reductions) to relative residual 1e-6 -> Load.
 
 Prints ONE JSON line (see the fields below).  ``roofline`` describes the
 fused Hessian-vector product kernel (the PCG hot loop): algorithmic bytes
-per launch (180 B per active cell for the 45 FP32 tangent entries + 24 B per
-active node for reading p and writing K p once) divided by its average
-duration, timed with HIP events on the library's stream over the timed steps.  ``cpu_baseline`` times the
+per launch as the library reports them (the stored tangent values one
+product reads per tangent-carrying cell -- 30 FP32 values = 120 B in the
+single-material factored form, 45 = 180 B dense -- plus 24 B per active node
+for reading p and writing K p once) divided by its average duration, timed
+with HIP events on the library's stream over the timed steps.  ``cpu_baseline`` times the
 FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,8 +29,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-HV_BYTES_PER_CELL = 180.0   # 45 FP32 tangent entries
-HV_BYTES_PER_NODE = 24.0    # p read once (12 B) + K p written once (12 B)
 
 
 def parse():
@@ -132,6 +132,8 @@ def main():
     torch.cuda.synchronize()
     hv_ms, hv_calls, newton, pcg, ls = 0.0, 0, 0, 0, 0
     cells = nodes = 0
+    hv_bytes = 0.0
+    tan_entries = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         st = one_step()
@@ -141,6 +143,7 @@ def main():
         pcg += st["pcg_iters"]
         ls += st["ls_halvings"]
         cells, nodes = st["active_cells"], st["active_nodes"]
+        hv_bytes, tan_entries = st["hv_model_bytes"], st["tangent_entries"]
         print(f"[bench] step {k} newton {st['newton_iters']} pcg {st['pcg_iters']} "
               f"ls {st['ls_halvings']} g {st['g_norm']:.3e}/{st['g0_norm']:.3e} "
               f"ms unload {st['ms_unload']:.1f} newton {st['ms_newton']:.1f} load {st['ms_load']:.1f}",
@@ -149,9 +152,6 @@ def main():
     elapsed = time.perf_counter() - t0
     steps_per_s = args.steps / elapsed
     hv_avg_ms = hv_ms / max(hv_calls, 1)
-    hv_bytes = HV_BYTES_PER_CELL * cells + HV_BYTES_PER_NODE * nodes
-    if prec == mpmlite.F64:
-        hv_bytes *= 2.0
     achieved = hv_bytes / (hv_avg_ms * 1e-3) / 1e9 if hv_calls else 0.0
     traffic = None
     if os.path.exists(args.traffic_json):
@@ -164,7 +164,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
-            "bytes_per_launch": hv_bytes, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
+            "bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     learned = None
     if args.learned_steps > 0:

@@ -230,7 +230,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.3 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.4 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -253,6 +253,8 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->stream = (hipStream_t)hip_stream;
   const char* ng = std::getenv("MPL_NO_GRAPHS");
   c->graphs_enabled = !(ng && ng[0] == '1');
+  const char* dt = std::getenv("MPL_DENSE_TANGENT");
+  c->factored_enabled = !(dt && dt[0] == '1');
   mpl_status st = derive_materials(c, mats, n_mats);
   if (st == MPL_OK) st = check_opts(c, opts);
   if (st == MPL_OK) st = mpl_ensure(c, c->scal, sizeof(SolverScalars));

@@ -54,22 +54,36 @@ __device__ __forceinline__ int node_cell(const int* n_nbr_cell, int nb, int l, i
 }
 
 // Slot of local cell l of cell block cb in the compact block-major tangent
-// storage: entry e of the cell lives at base + e*n + rank.
+// storage of `stride` entries per cell: entry e lives at base + e*n + rank.
 struct TanSlot {
   int64_t base;
   int n, rank;
   bool active;
 };
 __device__ __forceinline__ TanSlot tan_slot(const uint64_t* __restrict__ cmask,
-                                            const int32_t* __restrict__ coff, int cb, int l) {
+                                            const int32_t* __restrict__ coff, int cb, int l,
+                                            int stride) {
   const uint64_t m = cmask[cb];
   TanSlot t;
   t.active = (m >> l) & 1ull;
   t.n = __popcll(m);
   t.rank = __popcll(m & ((1ull << l) - 1ull));
-  t.base = 45ll * coff[cb];
+  t.base = (int64_t)stride * coff[cb];
   return t;
 }
+
+// Factored single-material FP32 tangent (42 entries per cell):
+//   0-8   U (row-major), the left singular vectors of F = (I + dt G) S
+//   9-17  M = S V (row-major)
+//   18-23 A3, the projected scaling block (00 01 02 11 12 22)
+//   24-29 (a_p, b_p) of the twist/flip pairs p = (0,1), (1,2), (0,2)
+//   30-41 Q_a(s): the cell's Jacobi-diagonal contribution for component a
+//         and corner sign pattern s (see k_tangent)
+// so that Abar vec(g) = vec(U yhat M^T) with Ghat = U^T g M,
+// diag(yhat) = A3 diag(Ghat) and, for pair (i,j), yhat_ij = a Ghat_ij + b Ghat_ji,
+// yhat_ji = b Ghat_ij + a Ghat_ji.
+#define MPL_TAN_DENSE 45
+#define MPL_TAN_FACT 42
 
 // Deterministic wavefront sum (butterfly over 64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {

@@ -40,7 +40,7 @@ struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void* key[24] = {};
-  int keyn[6] = {0, 0, 0, 0, 0, 0};
+  int keyn[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int events = 0;
 };
 
@@ -82,6 +82,8 @@ struct mpl_ctx {
   // state flags
   bool unloaded = false, reconstructed = false, tangent_built = false, solved = false;
   int tangent_precision = MPL_F32;
+  bool tan_factored = false;     // the stored FP32 tangent is in factored form
+  bool factored_enabled = true;  // MPL_DENSE_TANGENT=1 in the environment turns it off
   double dt = 0.0;
   int64_t np = 0;
   int n_cblk = 0, n_nblk = 0;

@@ -121,7 +121,7 @@ __global__ void k_export_abar32(const float* __restrict__ Ab, const uint64_t* __
   const int4 bc = ccoord[b];
   const int i = bc.x * 4 + local_x(l), j = bc.y * 4 + local_y(l), k = bc.z * 4 + local_z(l);
   const int64_t di = ((int64_t)i * ny + j) * nz + k;
-  const TanSlot ts = tan_slot(cmask, coff, b, l);
+  const TanSlot ts = tan_slot(cmask, coff, b, l, MPL_TAN_DENSE);
   if (!ts.active) return;
   for (int r = 0; r < 9; ++r)
     for (int c = 0; c < 9; ++c)
@@ -136,10 +136,57 @@ __global__ void k_export_abar64(const double* __restrict__ Ab, const uint64_t* _
   const int4 bc = ccoord[b];
   const int i = bc.x * 4 + local_x(l), j = bc.y * 4 + local_y(l), k = bc.z * 4 + local_z(l);
   const int64_t di = ((int64_t)i * ny + j) * nz + k;
-  const TanSlot ts = tan_slot(cmask, coff, b, l);
+  const TanSlot ts = tan_slot(cmask, coff, b, l, MPL_TAN_DENSE);
   if (!ts.active) return;
   for (int r = 0; r < 9; ++r)
     for (int c = 0; c < 9; ++c) dense[di * 81 + r * 9 + c] = Ab[ts.base + (int64_t)sym9(r, c) * ts.n + ts.rank];
+}
+
+// Factored FP32 tangent -> dense 9x9: column c is the factored product
+// applied to the unit velocity gradient e_c (FP64 arithmetic on the stored
+// FP32 factors).
+__global__ void k_export_abar_fact(const float* __restrict__ Ab, const uint64_t* __restrict__ cmask,
+                                   const int32_t* __restrict__ coff, const int4* __restrict__ ccoord,
+                                   int n_cblk, int nx, int ny, int nz, double* __restrict__ dense) {
+  const int b = blockIdx.x, l = threadIdx.x;
+  if (b >= n_cblk) return;
+  const int4 bc = ccoord[b];
+  const int i0 = bc.x * 4 + local_x(l), j0 = bc.y * 4 + local_y(l), k0 = bc.z * 4 + local_z(l);
+  const int64_t di = ((int64_t)i0 * ny + j0) * nz + k0;
+  const TanSlot ts = tan_slot(cmask, coff, b, l, MPL_TAN_FACT);
+  if (!ts.active) return;
+  double f[30];
+  for (int e = 0; e < 30; ++e) f[e] = (double)Ab[ts.base + (int64_t)e * ts.n + ts.rank];
+  const double* U = f;
+  const double* M = f + 9;
+  const double* A3 = f + 18;
+  const double* pc = f + 24;
+  for (int col = 0; col < 9; ++col) {
+    double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    g[col] = 1.0;
+    double t1[9], gh[9], yh[9], t2[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) t1[i * 3 + j] = U[i] * g[j] + U[3 + i] * g[3 + j] + U[6 + i] * g[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        gh[i * 3 + j] = t1[i * 3] * M[j] + t1[i * 3 + 1] * M[3 + j] + t1[i * 3 + 2] * M[6 + j];
+    yh[0] = A3[0] * gh[0] + A3[1] * gh[4] + A3[2] * gh[8];
+    yh[4] = A3[1] * gh[0] + A3[3] * gh[4] + A3[4] * gh[8];
+    yh[8] = A3[2] * gh[0] + A3[4] * gh[4] + A3[5] * gh[8];
+    yh[1] = pc[0] * gh[1] + pc[1] * gh[3];
+    yh[3] = pc[1] * gh[1] + pc[0] * gh[3];
+    yh[5] = pc[2] * gh[5] + pc[3] * gh[7];
+    yh[7] = pc[3] * gh[5] + pc[2] * gh[7];
+    yh[2] = pc[4] * gh[2] + pc[5] * gh[6];
+    yh[6] = pc[5] * gh[2] + pc[4] * gh[6];
+    for (int a = 0; a < 3; ++a)
+      for (int j = 0; j < 3; ++j)
+        t2[a * 3 + j] = U[a * 3] * yh[j] + U[a * 3 + 1] * yh[3 + j] + U[a * 3 + 2] * yh[6 + j];
+    for (int a = 0; a < 3; ++a)
+      for (int bb = 0; bb < 3; ++bb)
+        dense[di * 81 + (a * 3 + bb) * 9 + col] =
+            t2[a * 3] * M[bb * 3] + t2[a * 3 + 1] * M[bb * 3 + 1] + t2[a * 3 + 2] * M[bb * 3 + 2];
+  }
 }
 
 // symmetric 6 -> full 9 for tau / S exports
@@ -240,6 +287,12 @@ mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, dou
   st.cell_blocks = c->n_cblk;
   st.node_blocks = c->n_nblk;
   st.domain_events = c->hscal.domain_count;
+  {
+    const int elem = c->tangent_precision == MPL_F32 ? 4 : 8;
+    st.tangent_entries = c->tan_factored ? 30 : 45;
+    st.hv_model_bytes = (double)st.tangent_entries * elem * c->hscal.n_tan_cells +
+                        6.0 * elem * c->hscal.n_active_nodes;
+  }
   st.ms_unload = t1 - t0;
   st.ms_reconstruct = t2 - t1;
   st.ms_newton = t3 - t2;
@@ -295,7 +348,10 @@ mpl_status mpl_export_field(mpl_ctx* c, int32_t field, double* dense) {
     case MPL_FIELD_ABAR:
       if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "tangent not built");
       MPL_TRY(zero(81 * ncd));
-      if (c->tangent_precision == MPL_F32)
+      if (c->tangent_precision == MPL_F32 && c->tan_factored)
+        MPL_LAUNCH(c, k_export_abar_fact, c->n_cblk, 64, P<float>(c->Abar32), P<uint64_t>(c->cmask),
+                   P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);
+      else if (c->tangent_precision == MPL_F32)
         MPL_LAUNCH(c, k_export_abar32, c->n_cblk, 64, P<float>(c->Abar32), P<uint64_t>(c->cmask),
                    P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);
       else

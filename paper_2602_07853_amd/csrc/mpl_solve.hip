@@ -299,7 +299,11 @@ __global__ void k_set_tol(SolverScalars* s, double rtol2) { s->tol2 = rtol2 * s-
 // Per-cell projected tangent (Sec. 4.2 Hessian; projection per material):
 //   Abar_c = dt^2 sum_k V_k sum_modes max(lam, 0) vec(E S_k) vec(E S_k)^T
 // with the analytic eigen-modes E of dP/dF at F_k = (I + dt G_c) S_k.
-template <class T>
+// FACT (single material, FP32): the modes are E = U e V^T with e diagonal
+// (scaling) or a twist/flip pair, so vec(E S) = vec(U e M^T) with M = S V,
+// and the cell stores U, M, the projected scaling block and the pair
+// coefficients (the layout before MPL_TAN_FACT) instead of the 45 entries.
+template <class T, bool FACT>
 __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, int64_t nnode,
                                                 const int* __restrict__ c_nbr_node,
                                                 const double* __restrict__ Vk,
@@ -310,11 +314,14 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
                                                 T* __restrict__ Abar, int32_t* __restrict__ err) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
-  const TanSlot ts = tan_slot(cmask, coff, cb, l);
+  const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
   if (!ts.active) return;
   double Ab[45];
 #pragma unroll
   for (int i = 0; i < 45; ++i) Ab[i] = 0.0;
+  double fac[30];
+#pragma unroll
+  for (int i = 0; i < 30; ++i) fac[i] = 0.0;
   bool any = false;
   for (int k = 0; k < K; ++k) any = any || (Vk[k * ncell + ci] != 0.0);
   if (any) {
@@ -342,6 +349,26 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       double Hs[9] = {H[0][0], H[0][1], H[0][2], H[1][0], H[1][1], H[1][2], H[2][0], H[2][1], H[2][2]};
       double w[3], Qm[9];
       eig_sym3(Hs, w, Qm);
+      if (FACT) {
+        double M[9];
+        mul(S, Vm, M);
+        for (int i = 0; i < 9; ++i) {
+          fac[i] = U[i];
+          fac[9 + i] = M[i];
+        }
+        const int sy[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+        for (int e = 0; e < 6; ++e) {
+          double acc = 0.0;
+          for (int m = 0; m < 3; ++m)
+            if (w[m] > 0.0) acc += coef * w[m] * Qm[sy[e][0] * 3 + m] * Qm[sy[e][1] * 3 + m];
+          fac[18 + e] = acc;
+        }
+        for (int pp = 0; pp < 3; ++pp) {
+          const double lt = tw[pp] > 0.0 ? tw[pp] : 0.0, lf = fl[pp] > 0.0 ? fl[pp] : 0.0;
+          fac[24 + 2 * pp] = 0.5 * coef * (lt + lf);
+          fac[25 + 2 * pp] = 0.5 * coef * (lt - lf);
+        }
+      }
       for (int mode = 0; mode < 9; ++mode) {
         double lam, E[9];
         if (mode < 3) {
@@ -375,13 +402,30 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       }
     }
   }
+  if (FACT) {
 #pragma unroll
-  for (int i = 0; i < 45; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)Ab[i];
+    for (int i = 0; i < 30; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
+    // Jacobi-diagonal contributions Q_a(s) = sum_{b,b'} Abar[(a,b),(a,b')]
+    // sig_b sig_b' / (4 dx)^2 for the corner signs sig = (+1, sy, sz),
+    // s = 2 (sy < 0) + (sz < 0) (a corner and its opposite share the value)
+    const double g2 = inv4dx * inv4dx;
+    for (int a = 0; a < 3; ++a)
+      for (int sidx = 0; sidx < 4; ++sidx) {
+        const double sg[3] = {1.0, (sidx & 2) ? -1.0 : 1.0, (sidx & 1) ? -1.0 : 1.0};
+        double q = 0.0;
+        for (int b = 0; b < 3; ++b)
+          for (int b2 = 0; b2 < 3; ++b2) q += Ab[sym9(a * 3 + b, a * 3 + b2)] * sg[b] * sg[b2];
+        Abar[ts.base + (int64_t)(30 + a * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 45; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)Ab[i];
+  }
 }
 
 // Inverse Jacobi diagonal of H at every node, 1 / (m_i + sum_c sum_{b,b'}
 // Abar[(a,b),(a,b')] gw_b gw_b'), and 0 on fixed / massless nodes.
-template <class T>
+template <class T, bool FACT>
 __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
                                              const uint64_t* __restrict__ cmask,
                                              const int32_t* __restrict__ coff,
@@ -398,8 +442,17 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
     for (int d = 0; d < 8; ++d) {
       const int ci = node_cell(n_nbr_cell, nb, l, d);
       if (ci < 0) continue;
-      const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63);
+      const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
       if (!ts.active) continue;
+      if (FACT) {
+        // sign pattern of the node as corner d of that cell, canonical sx = +1
+        const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+        const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
+        const int sidx = sy * 2 + sz;
+        for (int a = 0; a < 3; ++a)
+          dd[a] += (double)Abar[ts.base + (int64_t)(30 + a * 4 + sidx) * ts.n + ts.rank];
+        continue;
+      }
       double gw[3];
       corner_grad(d, inv4dx, gw);
       for (int a = 0; a < 3; ++a) {
@@ -451,7 +504,7 @@ __device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
   else { tx = 4; ty = 4; tz = 4; }
 }
 
-template <class T, bool DOT>
+template <class T, bool DOT, bool FACT>
 __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
                                                  const T* __restrict__ Abar,
@@ -505,16 +558,65 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
     T y[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) y[r] = T(0);
-    const TanSlot ts = tan_slot(cmask, coff, cb, l);
+    const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
     if (ts.active) {
       const T* A = Abar + ts.base + ts.rank;
+      if (FACT) {
+        T U[9], M[9], A3[6], pc[6];
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
+        for (int e = 0; e < 9; ++e) {
+          U[e] = A[(int64_t)e * ts.n];
+          M[e] = A[(int64_t)(9 + e) * ts.n];
+        }
 #pragma unroll
-        for (int c = r; c < 9; ++c) {
-          const T a = A[(int64_t)sym9(r, c) * ts.n];
-          y[r] += a * g[c];
-          if (c != r) y[c] += a * g[r];
+        for (int e = 0; e < 6; ++e) {
+          A3[e] = A[(int64_t)(18 + e) * ts.n];
+          pc[e] = A[(int64_t)(24 + e) * ts.n];
+        }
+        // Ghat = U^T g M
+        T t1[9], gh[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            t1[i * 3 + j] = U[i] * g[j] + U[3 + i] * g[3 + j] + U[6 + i] * g[6 + j];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            gh[i * 3 + j] = t1[i * 3] * M[j] + t1[i * 3 + 1] * M[3 + j] + t1[i * 3 + 2] * M[6 + j];
+        T yh[9];
+        yh[0] = A3[0] * gh[0] + A3[1] * gh[4] + A3[2] * gh[8];
+        yh[4] = A3[1] * gh[0] + A3[3] * gh[4] + A3[4] * gh[8];
+        yh[8] = A3[2] * gh[0] + A3[4] * gh[4] + A3[5] * gh[8];
+        // pairs (0,1), (1,2), (0,2)
+        yh[1] = pc[0] * gh[1] + pc[1] * gh[3];
+        yh[3] = pc[1] * gh[1] + pc[0] * gh[3];
+        yh[5] = pc[2] * gh[5] + pc[3] * gh[7];
+        yh[7] = pc[3] * gh[5] + pc[2] * gh[7];
+        yh[2] = pc[4] * gh[2] + pc[5] * gh[6];
+        yh[6] = pc[5] * gh[2] + pc[4] * gh[6];
+        // y = U yhat M^T
+        T t2[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            t2[a * 3 + j] = U[a * 3] * yh[j] + U[a * 3 + 1] * yh[3 + j] + U[a * 3 + 2] * yh[6 + j];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            y[a * 3 + b] = t2[a * 3] * M[b * 3] + t2[a * 3 + 1] * M[b * 3 + 1] + t2[a * 3 + 2] * M[b * 3 + 2];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+#pragma unroll
+          for (int c = r; c < 9; ++c) {
+            const T a = A[(int64_t)sym9(r, c) * ts.n];
+            y[r] += a * g[c];
+            if (c != r) y[c] += a * g[r];
+          }
         }
       }
     }
@@ -1103,24 +1205,37 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   const int64_t ntan = (int64_t)c->hscal.n_tan_cells + 64;
   const uint64_t* cm = P<uint64_t>(c->cmask);
   const int32_t* co = P<int32_t>(c->coff);
+  // the single-material FP32 tangent is stored factored (42 entries per
+  // cell instead of 45, 30 of them read by the Hessian-vector product)
+  const bool fact = precision == MPL_F32 && c->nmat == 1 && c->factored_enabled;
+  c->tan_factored = fact;
   if (precision == MPL_F32) {
-    MPL_TRY(mpl_ensure(c, c->Abar32, 4 * 45 * ntan));
-    MPL_LAUNCH(c, k_tangent<float>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
-               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<float>(c->Abar32),
-               &c->dscal()->err);
+    MPL_TRY(mpl_ensure(c, c->Abar32, 4 * (fact ? MPL_TAN_FACT : MPL_TAN_DENSE) * ntan));
     MPL_TRY(mpl_ensure(c, c->Dt, 4 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 4 * nnode));
-    MPL_LAUNCH(c, k_diag<float>, c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
-               P<float>(c->Dt), P<float>(c->mt));
+    if (fact) {
+      MPL_LAUNCH(c, (k_tangent<float, true>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+                 P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+                 P<float>(c->Abar32), &c->dscal()->err);
+      MPL_LAUNCH(c, (k_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
+                 P<float>(c->Dt), P<float>(c->mt));
+    } else {
+      MPL_LAUNCH(c, (k_tangent<float, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+                 P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+                 P<float>(c->Abar32), &c->dscal()->err);
+      MPL_LAUNCH(c, (k_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
+                 P<float>(c->Dt), P<float>(c->mt));
+    }
   } else {
-    MPL_TRY(mpl_ensure(c, c->Abar64, 8 * 45 * ntan));
-    MPL_LAUNCH(c, k_tangent<double>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
-               P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co, P<double>(c->Abar64),
-               &c->dscal()->err);
+    MPL_TRY(mpl_ensure(c, c->Abar64, 8 * MPL_TAN_DENSE * ntan));
+    MPL_LAUNCH(c, (k_tangent<double, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+               P<double>(c->Abar64), &c->dscal()->err);
     MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
-    MPL_LAUNCH(c, k_diag<double>, c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
+    MPL_LAUNCH(c, (k_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                P<double>(c->Dt), P<double>(c->mt));
   }
@@ -1177,14 +1292,16 @@ static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot) {
   }
   const T inv4 = (T)(0.25 * c->inv_dx);
   const int grid = (((c->n_cblk + 3) / 4 + 7) / 8) * 8;
-  if (dot)
-    MPL_LAUNCH(c, (k_hv_fused<T, true>), grid, 256, p, nnode, P<int>(c->c_nbr_node),
-               P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
-               Hown, Hhalo, partial_slot(c, 0), (const SolverScalars*)c->dscal());
-  else
-    MPL_LAUNCH(c, (k_hv_fused<T, false>), grid, 256, p, nnode, P<int>(c->c_nbr_node),
-               P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4,
-               Hown, Hhalo, (double*)nullptr, (const SolverScalars*)nullptr);
+#define MPL_HV_LAUNCH(DOT, FACT, PART, SCAL)                                                       \
+  MPL_LAUNCH(c, (k_hv_fused<T, DOT, FACT>), grid, 256, p, nnode, P<int>(c->c_nbr_node),          \
+             P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4, \
+             Hown, Hhalo, PART, SCAL)
+  const bool fact = c->tan_factored;
+  if (dot && fact) MPL_HV_LAUNCH(true, true, partial_slot(c, 0), (const SolverScalars*)c->dscal());
+  else if (dot) MPL_HV_LAUNCH(true, false, partial_slot(c, 0), (const SolverScalars*)c->dscal());
+  else if (fact) MPL_HV_LAUNCH(false, true, (double*)nullptr, (const SolverScalars*)nullptr);
+  else MPL_HV_LAUNCH(false, false, (double*)nullptr, (const SolverScalars*)nullptr);
+#undef MPL_HV_LAUNCH
   if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
   return MPL_OK;
 }
@@ -1219,14 +1336,14 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
 // Without graph support the chunk is launched eagerly.  hook (may be null)
 // runs on the host after every chunk that leaves the iteration running,
 // with the iteration count.
-static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[24], const int keyn[6],
+static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[24], const int keyn[8],
                              int check, const std::function<mpl_status()>& launch_iteration,
                              const std::function<mpl_status(int)>* hook) {
   bool use_graph = c->graphs_enabled;
   if (use_graph) {
     bool same = gc.exec != nullptr;
     for (int i = 0; i < 24 && same; ++i) same = gc.key[i] == key[i];
-    for (int i = 0; i < 6 && same; ++i) same = gc.keyn[i] == keyn[i];
+    for (int i = 0; i < 8 && same; ++i) same = gc.keyn[i] == keyn[i];
     if (same && c->opts.time_kernels && gc.events != 2 * check) same = false;
     if (same && !c->opts.time_kernels && gc.events != 0) same = false;
     if (!same) {
@@ -1254,7 +1371,7 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
         use_graph = false;
       } else {
         for (int i = 0; i < 24; ++i) gc.key[i] = key[i];
-        for (int i = 0; i < 6; ++i) gc.keyn[i] = keyn[i];
+        for (int i = 0; i < 8; ++i) gc.keyn[i] = keyn[i];
       }
     }
   }
@@ -1322,7 +1439,7 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                          abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                          c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                          c->cmask.p,  c->coff.p};
-  const int keyn[6] = {c->n_cblk, c->n_nblk, check, 0, 0, 0};
+  const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 0};
   MPL_TRY(run_chunks(c, c->pcg_cache[0], key, keyn, check, launch_iteration, hook));
   if (iters) *iters = c->hscal.iters;
   if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
@@ -1401,7 +1518,7 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
                            q,           nn.act.p,    nn.wsw.p,        c->ncoord.p,
                            c->cmask.p,  c->coff.p,   nn.params.p,     c->nmap.p,
                            c->Dt.p,     c->mt.p};
-    const int keyn[6] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2]};
+    const int keyn[8] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2], (int)c->tan_factored, 1};
     st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, hook);
   }
   nn.skip = nullptr;

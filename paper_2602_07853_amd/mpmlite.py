@@ -69,7 +69,8 @@ class _Stats(C.Structure):
                 ("g0_norm", C.c_double), ("g_norm", C.c_double), ("energy", C.c_double),
                 ("hv_ms_total", C.c_double), ("hv_calls", C.c_int32), ("ms_unload", C.c_double),
                 ("ms_reconstruct", C.c_double), ("ms_newton", C.c_double), ("ms_load", C.c_double),
-                ("domain_events", C.c_int32)]
+                ("domain_events", C.c_int32), ("tangent_entries", C.c_int32),
+                ("hv_model_bytes", C.c_double)]
 
 
 _lib = None

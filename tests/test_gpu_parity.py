@@ -86,7 +86,13 @@ def test_tangent_and_hv(state, precision):
     ctx.build_tangent(torch.tensor(v, device="cuda"), precision)
     A = host(ctx.export("abar"))
     Ao, rc = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
-    assert rel(A, Ao) <= (1e-10 if precision == 1 else 2e-7)
+    # FP32 storage: the 45 entries (several materials) round once (2e-7); the
+    # single-material factored form (U, S V, projected blocks) rounds its
+    # factors and is expanded for the export (2e-6)
+    if precision == 1:
+        assert rel(A, Ao) <= 1e-10
+    else:
+        assert rel(A, Ao) <= (2e-7 if len(sc.materials) > 1 else 2e-6)
     dt = torch.float64 if precision == 1 else torch.float32
     for trial in range(3):
         u = rng.normal(size=ref["vhat"].shape)

@@ -230,7 +230,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.4 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.5 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -255,6 +255,8 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->graphs_enabled = !(ng && ng[0] == '1');
   const char* dt = std::getenv("MPL_DENSE_TANGENT");
   c->factored_enabled = !(dt && dt[0] == '1');
+  const char* cgc = std::getenv("MPL_CG_CLASSIC");
+  c->cg_single = !(cgc && cgc[0] == '1');
   mpl_status st = derive_materials(c, mats, n_mats);
   if (st == MPL_OK) st = check_opts(c, opts);
   if (st == MPL_OK) st = mpl_ensure(c, c->scal, sizeof(SolverScalars));
@@ -279,7 +281,8 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Y64, &c->vcl, &c->Gcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
-                   &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt};
+                   &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
+                   &c->cg_u, &c->cg_s};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

@@ -111,9 +111,9 @@ struct mpl_ctx {
   SolverScalars hscal;
 
   // captured PCG iteration chunks (replayed while the key matches); one
-  // cache per iteration kind (Jacobi, learned)
+  // cache per iteration kind (Jacobi, learned, single-reduction Jacobi)
   bool graphs_enabled = true;
-  GraphCache pcg_cache[2];
+  GraphCache pcg_cache[3];
   // training-pair collection during Newton solves (0 = off)
   int collect_every = 0;
   double collect_rtol = 1e-10;
@@ -126,7 +126,10 @@ struct mpl_ctx {
   int64_t online_done = 0;     // training steps taken
   double online_loss_sum = 0;  // sum of first-step losses since the last read
   int64_t online_loss_n = 0;
-  DevBuf ozt, ohz, ogr;
+  DevBuf ozt, ohz, ogr, opieces;
+  // single-reduction CG: u = Dinv r and s = running H p (tangent precision)
+  DevBuf cg_u, cg_s;
+  bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop
 
   // learned preconditioner (allocated on first use)
   NNState* nn = nullptr;

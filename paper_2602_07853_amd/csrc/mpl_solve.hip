@@ -850,6 +850,203 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
   if (threadIdx.x == 0) pmm[blockIdx.x] = mm;
 }
 
+// ---- single-reduction CG (Chronopoulos & Gear) ----
+// Mathematically the Jacobi-preconditioned CG above, rearranged so that one
+// global reduction per iteration yields both step lengths:
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u = Dinv r,  w = H u (next product),
+//   gamma = r.u,  delta = u.w,  beta = gamma / gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old).
+// s carries H p without a second product.  Per iteration: this vector
+// kernel, the fused product of u (with its u^T K u partials), one reduction.
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, const T* __restrict__ Dinv,
+                                                 const T* __restrict__ mi, const uint8_t* __restrict__ flags,
+                                                 int64_t nnode, int n_nblk, double* __restrict__ x,
+                                                 double* __restrict__ r, T* __restrict__ u,
+                                                 T* __restrict__ p, T* __restrict__ sv,
+                                                 double* __restrict__ pg, double* __restrict__ pbb,
+                                                 double* __restrict__ pmu, SolverScalars* __restrict__ s) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  // the first product (next launch) must run even if the previous solve
+  // left the done flag set; the reduction after it sets the flag again
+  if (blockIdx.x == 0 && threadIdx.x == 0) s->done = 0;
+  double g = 0.0, bb = 0.0, mu = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const double m = (double)mi[ni];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const double rv = fr ? b[i] : 0.0;
+      const T uv = (T)(rv * (double)Dinv[i]);
+      x[i] = 0.0;
+      r[i] = rv;
+      u[i] = uv;
+      p[i] = T(0);
+      sv[i] = T(0);
+      g += rv * (double)uv;
+      bb += rv * rv;
+      mu += m * (double)uv * (double)uv;
+    }
+  }
+  g = block4_sum(g, sh);
+  bb = block4_sum(bb, sh);
+  mu = block4_sum(mu, sh);
+  if (threadIdx.x == 0) {
+    pg[blockIdx.x] = g;
+    pbb[blockIdx.x] = bb;
+    pmu[blockIdx.x] = mu;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restrict__ p, T* __restrict__ sv,
+                                                 const T* __restrict__ Hown, const T* __restrict__ Hhalo,
+                                                 const int* __restrict__ n_nbr_cell, int64_t ncell,
+                                                 const T* __restrict__ mi, const T* __restrict__ Dinv,
+                                                 const uint8_t* __restrict__ flags, int64_t nnode,
+                                                 int n_nblk, double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ pg, double* __restrict__ prr,
+                                                 double* __restrict__ pmu,
+                                                 const SolverScalars* __restrict__ s) {
+  if (done_flag(s)) return;
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  const double alpha = s->alpha, beta = s->beta;
+  double g = 0.0, rr = 0.0, mu = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    if (flags[ni] & MPL_NODE_FREE) {
+      // all loads of the node first (three components), then the arithmetic
+      // and the stores, so that every load is in flight at once
+      T uv[3], pv[3], svv[3], dv[3];
+      double xv[3], rv[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        uv[a] = u[i];
+        pv[a] = p[i];
+        svv[a] = sv[i];
+        dv[a] = Dinv[i];
+        xv[a] = x[i];
+        rv[a] = r[i];
+      }
+      const T m = mi[ni];
+      T h[3];
+      gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        const T w = h[a] + m * uv[a];  // (H u)_i
+        const T pn = (T)((double)uv[a] + beta * (double)pv[a]);
+        const T sn = (T)((double)w + beta * (double)svv[a]);
+        const double rn = rv[a] - alpha * (double)sn;
+        const T un = (T)(rn * (double)dv[a]);
+        p[i] = pn;
+        sv[i] = sn;
+        x[i] = xv[a] + alpha * (double)pn;
+        r[i] = rn;
+        u[i] = un;
+        g += rn * (double)un;
+        rr += rn * rn;
+        mu += (double)m * (double)un * (double)un;
+      }
+    }
+  }
+  g = block4_sum(g, sh);
+  rr = block4_sum(rr, sh);
+  mu = block4_sum(mu, sh);
+  if (threadIdx.x == 0) {
+    pg[blockIdx.x] = g;
+    prr[blockIdx.x] = rr;
+    pmu[blockIdx.x] = mu;
+  }
+}
+
+// Reduction of the four partial arrays of one single-reduction CG
+// iteration (fixed order), then its scalar logic.  INIT: A = r.u, B = b.b,
+// C = u^T M u, D = u^T K u.  STEP: A = r.u, B = r.r, C, D as in INIT.
+template <bool INIT>
+__global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a,
+                                                    const double* __restrict__ b,
+                                                    const double* __restrict__ c, int n,
+                                                    const double* __restrict__ d, int nd,
+                                                    SolverScalars* __restrict__ s) {
+  __shared__ double sh[4][16];
+  const int t = threadIdx.x;
+  if (!INIT && done_flag(s)) return;
+  double v[4][8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int i = t + 1024 * k;
+    v[0][k] = i < n ? a[i] : 0.0;
+    v[1][k] = i < n ? b[i] : 0.0;
+    v[2][k] = i < n ? c[i] : 0.0;
+    v[3][k] = i < nd ? d[i] : 0.0;
+  }
+  for (int i = t + 8192; i < n; i += 1024) {
+    v[0][0] += a[i];
+    v[1][0] += b[i];
+    v[2][0] += c[i];
+  }
+  for (int i = t + 8192; i < nd; i += 1024) v[3][0] += d[i];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[q][0] += v[q][k];
+    const double w = wave_sum(v[q][0]);
+    if ((t & 63) == 0) sh[q][t >> 6] = w;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double A = 0.0, B = 0.0, C = 0.0, D = 0.0;
+  for (int w = 0; w < 16; ++w) {
+    A += sh[0][w];
+    B += sh[1][w];
+    C += sh[2][w];
+    D += sh[3][w];
+  }
+  const double delta = C + D;
+  if (INIT) {
+    s->bnorm2 = B;
+    s->rr = B;
+    s->rz = A;
+    s->iters = 0;
+    s->beta = 0.0;
+    s->done = (B == 0.0) ? 1 : 0;
+    if (s->done == 0) {
+      if (!(delta > 0.0) || !isfinite(delta)) {
+        s->done = 2;
+        s->alpha = 0.0;
+      } else {
+        s->alpha = A / delta;
+      }
+    }
+    return;
+  }
+  s->iters += 1;
+  s->rr = B;
+  if (!isfinite(B)) {
+    s->done = 2;
+    return;
+  }
+  if (B <= s->tol2) {
+    s->done = 1;
+    return;
+  }
+  const double beta = A / s->rz;
+  const double denom = delta - beta * A / s->alpha;
+  if (!(denom > 0.0) || !isfinite(denom)) {
+    s->done = 2;
+    return;
+  }
+  s->beta = beta;
+  s->alpha = A / denom;
+  s->rz = A;
+}
+
 // ---- flexible CG with the learned preconditioner ----
 // The preconditioned residual is z = Dinv r + s sqrt(Dinv) o on free nodes,
 // o the network output (bf16, 16 channels per box voxel, voxel = node), s^2 =
@@ -1277,11 +1474,14 @@ template <> DevBuf& pvec_buf<double>(mpl_ctx* c) { return c->p64; }
 // dot, the per-block partial sums of p^T K p), timed with HIP events when
 // time_kernels is set.
 template <class T>
-static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot) {
+static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot, T* out = nullptr) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
-  DevBuf& pieces = pieces_buf<T>(c);
-  MPL_TRY(mpl_ensure(c, pieces, sizeof(T) * 6 * ncell));
-  T* Hown = P<T>(pieces);
+  if (!out) {
+    DevBuf& pieces = pieces_buf<T>(c);
+    MPL_TRY(mpl_ensure(c, pieces, sizeof(T) * 6 * ncell));
+    out = P<T>(pieces);
+  }
+  T* Hown = out;
   T* Hhalo = Hown + 3 * ncell;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->opts.time_kernels) {
@@ -1419,6 +1619,39 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
   double* pb = partial_slot(c, 2);
   double* pm = partial_slot(c, 3);
   const int nwg = (c->n_nblk + 3) / 4;
+  if (c->cg_single) {
+    // single-reduction form (see k_cg_step)
+    MPL_TRY(mpl_ensure(c, c->cg_u, sizeof(T) * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->cg_s, sizeof(T) * 3 * nnode));
+    T* u = P<T>(c->cg_u);
+    T* sv = P<T>(c->cg_s);
+    const int ngrp = (c->n_cblk + 3) / 4;
+    MPL_LAUNCH(c, k_cg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode,
+               c->n_nblk, x, P<double>(c->r), u, p, sv, pa, pb, pm, s);
+    MPL_TRY(hv_pieces<T>(c, u, true));
+    MPL_LAUNCH(c, k_reduce_cg<true>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
+    MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
+    const int check = std::max(1, c->opts.pcg_check_every);
+    auto launch_iteration = [&]() -> mpl_status {
+      MPL_LAUNCH(c, k_cg_step<T>, nwg, 256, u, p, sv, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+                 P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa,
+                 pb, pm, s);
+      MPL_TRY(hv_pieces<T>(c, u, true));
+      MPL_LAUNCH(c, k_reduce_cg<false>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
+      return MPL_OK;
+    };
+    const void* key[24] = {x,           p,           c->r.p,          c->Dt.p,
+                           abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
+                           c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
+                           c->cmask.p,  c->coff.p,   u,               sv};
+    const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 2};
+    MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration, hook));
+    if (iters) *iters = c->hscal.iters;
+    if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
+    if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)
+      return mpl_fail(c, MPL_ERR_NONFINITE, "PCG breakdown (u.Hu <= 0 or not finite)");
+    return MPL_OK;
+  }
   MPL_LAUNCH(c, k_pcg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags),
              nnode, c->n_nblk, x, P<double>(c->r), p, pa, pb, pm);
   MPL_LAUNCH(c, k_reduce<RED_PCG_INIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
@@ -1543,6 +1776,7 @@ static mpl_status online_train(mpl_ctx* c) {
   MPL_TRY(mpl_ensure(c, c->ozt, sizeof(T) * 3 * nnode));
   MPL_TRY(mpl_ensure(c, c->ohz, sizeof(T) * 3 * nnode));
   MPL_TRY(mpl_ensure(c, c->ogr, sizeof(double) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->opieces, sizeof(T) * 6 * ncell));
   MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * (c->online_steps + 64) + 2 * sizeof(double) * (c->n_nblk + 64)));
   MPL_TRY(nn_set_dref(c, P<double>(c->D)));
   const int32_t* saved_skip = nn.skip;
@@ -1570,8 +1804,8 @@ static mpl_status online_train(mpl_ctx* c) {
       MPL_TRY(nn_forward(c, nn));
       MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
                  c->n_nblk, net, &s->red[0], z);
-      MPL_TRY(hv_pieces<T>(c, z, false));
-      const T* Hown = P<T>(pieces_buf<T>(c));
+      MPL_TRY(hv_pieces<T>(c, z, false, P<T>(c->opieces)));
+      const T* Hown = P<T>(c->opieces);
       MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
                  P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
       MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,

@@ -249,3 +249,22 @@ def test_graph_replay_matches_eager_launches(monkeypatch):
         outs.append({k: host(v) for k, v in dp.items()})
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_classic_two_reduction_cg_matches(monkeypatch):
+    """The two-reduction Jacobi CG loop (MPL_CG_CLASSIC=1) and the default
+    single-reduction loop are the same method: same minimiser to 1e-10."""
+    sc = SCENES["fcr_two_materials"]
+    sols = []
+    for classic in ("0", "1"):
+        monkeypatch.setenv("MPL_CG_CLASSIC", classic)
+        ctx, parts = run_unload(sc, 0)
+        ctx.set_opts(newton_rtol=1e-12, pcg_rtol=1e-7)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        print(f"[parity] classic={classic} {st['newton_iters']} newton, {st['pcg_iters']} pcg", flush=True)
+        sols.append((host(v), st))
+    (v0, s0), (v1, s1) = sols
+    assert s0["g_norm"] <= 1e-12 * s0["g0_norm"] and s1["g_norm"] <= 1e-12 * s1["g0_norm"]
+    assert rel(v0, v1) <= 1e-10
+    assert abs(s0["pcg_iters"] - s1["pcg_iters"]) <= max(3, s1["pcg_iters"] // 20)

@@ -211,9 +211,9 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
     for k in range(args.learned_train_steps):
         st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
         t += sc.dt
-        n, loss = ctx.precond_online_stats()
+        n, loss, ref = ctx.precond_online_stats()
         print(f"[bench] learned-leg training step {k}: pcg {st['pcg_iters']} train steps {n} "
-              f"mean loss {loss:.4f}", file=sys.stderr, flush=True)
+              f"mean loss {loss:.4f} (Jacobi {ref:.4f})", file=sys.stderr, flush=True)
     ctx.precond_online(0, 0, 0.0)
     ctx.set_opts(precond=2)
     torch.cuda.synchronize()

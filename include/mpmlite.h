@@ -264,9 +264,12 @@ mpl_status mpl_precond_collect(mpl_ctx* ctx, int32_t every, double rtol);
  * scalars are not touched); the network changes between its iterations. */
 mpl_status mpl_precond_online(mpl_ctx* ctx, int32_t every, int32_t steps, float lr);
 /* Online training counters (host pointers, may be NULL): total steps taken,
- * and the mean loss of the network before each training burst since the
- * last call (then reset). */
-mpl_status mpl_precond_online_stats(mpl_ctx* ctx, int64_t* steps_done, double* mean_loss);
+ * the mean loss of the network before each training burst since the last
+ * call, and the mean loss of the Jacobi preconditioner z = D^{-1} r on the
+ * same residuals (both then reset).  Lower is better; the network beats
+ * Jacobi on those residuals when its loss is below the Jacobi one. */
+mpl_status mpl_precond_online_stats(mpl_ctx* ctx, int64_t* steps_done, double* mean_loss,
+                                    double* mean_jacobi_loss);
 /* Number of stored training pairs (*n, host). */
 mpl_status mpl_precond_sample_count(mpl_ctx* ctx, int32_t* n);
 /* n_steps Adam steps on the stored pairs, visited in a pseudo-random order

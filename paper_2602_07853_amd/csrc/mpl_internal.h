@@ -125,6 +125,7 @@ struct mpl_ctx {
   float online_lr = 0.f;
   int64_t online_done = 0;     // training steps taken
   double online_loss_sum = 0;  // sum of first-step losses since the last read
+  double online_ref_sum = 0;   // the same losses for the Jacobi preconditioner
   int64_t online_loss_n = 0;
   DevBuf ozt, ohz, ogr, opieces;
   // single-reduction CG: u = Dinv r and s = running H p (tangent precision)

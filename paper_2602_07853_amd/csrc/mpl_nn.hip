@@ -1117,11 +1117,15 @@ mpl_status mpl_precond_online(mpl_ctx* c, int32_t every, int32_t steps, float lr
   return MPL_OK;
 }
 
-mpl_status mpl_precond_online_stats(mpl_ctx* c, int64_t* steps_done, double* mean_loss) {
+mpl_status mpl_precond_online_stats(mpl_ctx* c, int64_t* steps_done, double* mean_loss,
+                                    double* mean_jacobi_loss) {
   if (!c) return MPL_ERR_INVALID_ARG;
   if (steps_done) *steps_done = c->online_done;
   if (mean_loss) *mean_loss = c->online_loss_n ? c->online_loss_sum / (double)c->online_loss_n : 0.0;
+  if (mean_jacobi_loss)
+    *mean_jacobi_loss = c->online_loss_n ? c->online_ref_sum / (double)c->online_loss_n : 0.0;
   c->online_loss_sum = 0.0;
+  c->online_ref_sum = 0.0;
   c->online_loss_n = 0;
   return MPL_OK;
 }

@@ -1218,14 +1218,14 @@ __global__ __launch_bounds__(256) void k_online_z(const double* __restrict__ r,
                                                   const uint8_t* __restrict__ flags,
                                                   const int4* __restrict__ ncoord, int64_t nnode,
                                                   int n_nblk, NetOut net, const double* __restrict__ rdr,
-                                                  T* __restrict__ z) {
+                                                  T* __restrict__ z, int jacobi) {
   const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double zz[3] = {0.0, 0.0, 0.0};
   if (flags[ni] & MPL_NODE_FREE)
-    learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(rdr[0] * net.inv_nfree, 1e-300)), false,
-              zz);
+    learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(rdr[0] * net.inv_nfree, 1e-300)),
+              jacobi != 0, zz);
   for (int a = 0; a < 3; ++a) z[a * nnode + ni] = (T)zz[a];
 }
 
@@ -1796,23 +1796,31 @@ static mpl_status online_train(mpl_ctx* c) {
   const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
                    nn_inv_free_dofs(c)};
   mpl_status st = MPL_OK;
+  // loss of z (network or, with jacobi = 1, z = Dinv r) into *loss, output
+  // gradient into ogr
+  auto loss_of = [&](int jacobi, double* loss) -> mpl_status {
+    MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
+               c->n_nblk, net, &s->red[0], z, jacobi);
+    MPL_TRY(hv_pieces<T>(c, z, false, P<T>(c->opieces)));
+    const T* Hown = P<T>(c->opieces);
+    MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
+               P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
+    MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,
+               c->n_nblk, p4, p5);
+    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p5, nwg, p5, 0, s, 1);
+    MPL_LAUNCH(c, k_online_grad<T>, nwg, 256, r, (const T*)hz, D, P<uint8_t>(c->flags), nnode, c->n_nblk,
+               nn_inv_free_dofs(c), (const double*)&s->red[0], P<double>(c->ogr), loss);
+    return MPL_OK;
+  };
   auto run = [&]() -> mpl_status {
     MPL_LAUNCH(c, k_online_rdr, nwg, 256, r, D, P<uint8_t>(c->flags), nnode, c->n_nblk, p4);
     MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p4, 0, p4, 0, s, 0);
+    // reference: the same loss for the Jacobi preconditioner
+    MPL_TRY(loss_of(1, losses + c->online_steps));
     for (int k = 0; k < c->online_steps; ++k) {
       MPL_TRY(nn_stage_features(c, r, D, &s->red[0]));
       MPL_TRY(nn_forward(c, nn));
-      MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
-                 c->n_nblk, net, &s->red[0], z);
-      MPL_TRY(hv_pieces<T>(c, z, false, P<T>(c->opieces)));
-      const T* Hown = P<T>(c->opieces);
-      MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
-                 P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
-      MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,
-                 c->n_nblk, p4, p5);
-      MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p5, nwg, p5, 0, s, 1);
-      MPL_LAUNCH(c, k_online_grad<T>, nwg, 256, r, (const T*)hz, D, P<uint8_t>(c->flags), nnode, c->n_nblk,
-                 nn_inv_free_dofs(c), (const double*)&s->red[0], P<double>(c->ogr), losses + k);
+      MPL_TRY(loss_of(0, losses + k));
       MPL_TRY(nn_stage_output_grad(c, P<double>(c->ogr)));
       MPL_TRY(nn_backward_update(c, nn, c->online_lr));
     }
@@ -1822,12 +1830,15 @@ static mpl_status online_train(mpl_ctx* c) {
   nn.skip = saved_skip;
   c->opts.time_kernels = saved_tk;
   MPL_TRY(st);
-  double first = 0.0;
+  double first = 0.0, ref = 0.0;
   MPL_HIP(c, hipMemcpyAsync(&first, losses, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MPL_HIP(c, hipMemcpyAsync(&ref, losses + c->online_steps, sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
   MPL_HIP(c, hipStreamSynchronize(c->stream));
   c->online_done += c->online_steps;
-  if (std::isfinite(first)) {
+  if (std::isfinite(first) && std::isfinite(ref)) {
     c->online_loss_sum += first;
+    c->online_ref_sum += ref;
     c->online_loss_n += 1;
   }
   return MPL_OK;

@@ -356,8 +356,10 @@ class Context:
                                                  C.c_float(lr)), "mpl_precond_online")
 
     def precond_online_stats(self):
+        """(training steps so far, mean network loss, mean Jacobi loss) since the last call."""
         n = C.c_int64()
         loss = C.c_double()
-        self._check(self._lib.mpl_precond_online_stats(self._ctx, C.byref(n), C.byref(loss)),
+        ref = C.c_double()
+        self._check(self._lib.mpl_precond_online_stats(self._ctx, C.byref(n), C.byref(loss), C.byref(ref)),
                     "mpl_precond_online_stats")
-        return n.value, loss.value
+        return n.value, loss.value, ref.value

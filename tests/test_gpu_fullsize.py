@@ -1,0 +1,92 @@
+"""GPU parity at the benchmark's full size and launch configuration: the
+128^3 stiff plastic workload (~1.06M active cells, 7.95M particles), FP32
+factored tangent and Hessian-vector product, FP64 elsewhere, against the
+FP64 oracle on the same seeded inputs.  Every stage whose oracle finishes in
+seconds at this size is compared on all outputs: unload fields, stretch
+reconstruction, energy and gradient at vhat, Hessian-vector products (GPU
+tangent + product against the oracle's tangent + product), and Load of an
+oracle-side node velocity field."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2602_07853_amd import scenes
+from tests.parity_util import gpu_context, oracle_state, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.config3()
+    print(f"[fullsize] {sc.name}: {sc.n_particles} particles, {sc.occupied_cells} occupied cells", flush=True)
+    ref = oracle_state(sc)
+    print("[fullsize] oracle unload + reconstruction done", flush=True)
+    ctx = gpu_context(sc, 0)
+    parts = mpmlite.particles_to_device(sc.particles)
+    ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+    ctx.reconstruct()
+    return sc, ref, ctx, parts
+
+
+def test_unload_and_stretch_full_size(full):
+    sc, ref, ctx, _ = full
+    mc = host(ctx.export("mass_c"))[:, 0]
+    assert np.array_equal(mc > 0, ref["mc"] > 0)
+    act = ref["mc"] > 0
+    print(f"[fullsize] active cells {int(act.sum())}", flush=True)
+    assert rel(mc, ref["mc"]) <= 1e-13
+    assert rel(host(ctx.export("vel_c")), ref["vc"], act) <= 1e-12
+    assert rel(host(ctx.export("grad_c")), ref["Gc"], act) <= 1e-12
+    assert rel(host(ctx.export("tau_ck")), ref["tauck"]) <= 1e-12
+    S = host(ctx.export("s_ck"))
+    actk = ref["Vck"] > 0
+    assert rel(S[actk], ref["S"][actk]) <= 1e-10
+    assert rel(host(ctx.export("mass_i"))[:, 0], ref["mi"]) <= 1e-13
+    assert np.array_equal(host(ctx.export("fixed"))[:, 0] > 0, ref["fixed"] > 0)
+    assert rel(host(ctx.export("vhat")), ref["vhat"]) <= 1e-12
+
+
+def test_energy_gradient_and_hv_full_size(full):
+    sc, ref, ctx, _ = full
+    v = ref["vhat"]
+    E, g = ctx.energy_grad(torch.tensor(v, device="cuda"))
+    Eo, go, rc = O.energy_grad(ref["grid"], ref["mats"], sc.dt, ref["mi"], ref["vhat"], ref["fixed"],
+                               ref["Vck"], ref["S"], v)
+    assert rc == 0
+    assert abs(E - Eo) <= 1e-10 * abs(Eo)
+    assert rel(host(g), go) <= 1e-10
+    ctx.build_tangent(torch.tensor(v, device="cuda"), 0)
+    A, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
+    rng = np.random.default_rng(7)
+    for trial in range(2):
+        u = rng.normal(size=v.shape).astype(np.float32)
+        Hu = host(ctx.hv(torch.tensor(u, device="cuda"), 0))
+        Huo = O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, u.astype(np.float64))
+        e = rel(Hu, Huo)
+        print(f"[fullsize] Hv trial {trial} rel err {e:.2e}", flush=True)
+        assert e <= 1e-5
+    del A
+
+
+def test_load_full_size(full):
+    sc, ref, ctx, parts = full
+    rng = np.random.default_rng(8)
+    vnode = ref["vhat"] + 0.05 * rng.normal(size=ref["vhat"].shape) * (ref["mi"] > 0)[:, None]
+    out = {k: torch.empty_like(t) for k, t in parts.items()}
+    ctx.load(parts, out, sc.dt, v=torch.tensor(vnode, device="cuda"))
+    po = O.load(ref["grid"], sc.dt, ref["mc"], vnode, sc.particles, ref["mats"])
+    assert po["rc"] == 0
+    for k in ("x", "v", "G", "F"):
+        e = rel(host(out[k]), po[k])
+        print(f"[fullsize] load {k} rel err {e:.2e}", flush=True)
+        assert e <= 1e-12, k
+    assert np.abs(po["eps"]).max() > 0  # the von Mises projection was active
+    assert rel(host(out["plastic"]), po["eps"]) <= 1e-10

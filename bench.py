@@ -9,7 +9,7 @@ products, FP64 reductions) to relative residual 1e-6 -> Load.
 Prints ONE JSON line (see the fields below).  ``roofline`` describes the
 fused Hessian-vector product kernel (the PCG hot loop): algorithmic bytes
 per launch as the library reports them (the stored tangent values one
-product reads per tangent-carrying cell -- 30 FP32 values = 120 B in the
+product reads per tangent-carrying cell -- 25 FP32 values = 100 B in the
 single-material factored form, 45 = 180 B dense -- plus 24 B per active node
 for reading p and writing K p once) divided by its average duration, timed
 with HIP events on the library's stream over the timed steps.  ``cpu_baseline`` times the
@@ -230,15 +230,41 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.set_opts(precond=0)
+    net = network_rate(ctx, sc)
     n = args.learned_steps
     sps = n / el
     return {"steps_per_s": round(sps, 4), "steps": n, "ms_per_step": round(1e3 * el / n, 3),
             "newton_per_step": round(newton / n, 3), "pcg_per_step": round(pcg / n, 2),
             "fallbacks_per_step": round(fb / n, 3),
             "vs_plain": round(sps / plain_steps_per_s, 4),
+            "network": net,
             "plain_pcg_per_step": round(plain_counts[1], 2),
             "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "
                         "from the workload's initial state, 1 Adam step per 64 CG iterations"}
+
+
+def network_rate(ctx, sc, reps=5):
+    """Time the network forward on the solver's box (all grid nodes, padded
+    to multiples of 8) with events on the library's stream: dense MAC FLOPs
+    per application / average time, against the BF16 dense MFMA peak."""
+    import torch
+    from paper_2602_07853_amd import precond_train
+    b = ((sc.n + 1 + 7) // 8) * 8
+    x = torch.randn((b, b, b, 16), dtype=torch.float32, device="cuda")
+    x[..., 5:] = 0
+    ctx.nn_forward(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.nn_forward(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = precond_train.forward_flops((b, b, b))
+    return {"box": [b, b, b], "ms_per_forward": round(ms, 3), "gflop_per_forward": round(flops / 1e9, 1),
+            "tflops": round(flops / (ms * 1e-3) / 1e12, 1), "peak_tflops": 2500.0,
+            "frac": round(flops / (ms * 1e-3) / 2.5e15, 4),
+            "note": "dense box incl. fp32<->bf16 staging of input and output"}
 
 
 def ctx_version():

@@ -112,7 +112,7 @@ typedef struct {
   double ms_unload, ms_reconstruct, ms_newton, ms_load;  /* host wall clock per stage */
   int32_t domain_events;  /* stretch reconstructions clamped (model range) */
   int32_t tangent_entries;/* stored tangent values read per cell by one Hv: 45 (dense
-                             symmetric 9x9) or 30 (single-material FP32 factored form) */
+                             symmetric 9x9) or 25 (single-material FP32 factored form) */
   double hv_model_bytes;  /* algorithmic bytes of one Hv: tangent_entries values per
                              tangent-carrying cell + 2 x 3 values (u read, Hu written) per
                              active node, in the tangent's precision */

@@ -72,18 +72,55 @@ __device__ __forceinline__ TanSlot tan_slot(const uint64_t* __restrict__ cmask,
   return t;
 }
 
-// Factored single-material FP32 tangent (42 entries per cell):
-//   0-8   U (row-major), the left singular vectors of F = (I + dt G) S
-//   9-17  M = S V (row-major)
-//   18-23 A3, the projected scaling block (00 01 02 11 12 22)
-//   24-29 (a_p, b_p) of the twist/flip pairs p = (0,1), (1,2), (0,2)
-//   30-41 Q_a(s): the cell's Jacobi-diagonal contribution for component a
+// Factored single-material FP32 tangent (37 entries per cell):
+//   0-3   unit quaternion (w, x, y, z) of U, the left singular vectors of
+//         F = (I + dt G) S (a proper rotation)
+//   4-12  M = S V (row-major)
+//   13-18 A3, the projected scaling block (00 01 02 11 12 22)
+//   19-24 (a_p, b_p) of the twist/flip pairs p = (0,1), (1,2), (0,2)
+//   25-36 Q_a(s): the cell's Jacobi-diagonal contribution for component a
 //         and corner sign pattern s (see k_tangent)
 // so that Abar vec(g) = vec(U yhat M^T) with Ghat = U^T g M,
 // diag(yhat) = A3 diag(Ghat) and, for pair (i,j), yhat_ij = a Ghat_ij + b Ghat_ji,
-// yhat_ji = b Ghat_ij + a Ghat_ji.
+// yhat_ji = b Ghat_ij + a Ghat_ji.  A product reads entries 0-24.
 #define MPL_TAN_DENSE 45
-#define MPL_TAN_FACT 42
+#define MPL_TAN_FACT 37
+#define MPL_TAN_FACT_READ 25
+
+// Rotation matrix (row-major) of a unit quaternion (w, x, y, z).
+template <class T>
+__host__ __device__ __forceinline__ void quat_to_rot(T w, T x, T y, T z, T* U) {
+  U[0] = T(1) - T(2) * (y * y + z * z);
+  U[1] = T(2) * (x * y - w * z);
+  U[2] = T(2) * (x * z + w * y);
+  U[3] = T(2) * (x * y + w * z);
+  U[4] = T(1) - T(2) * (x * x + z * z);
+  U[5] = T(2) * (y * z - w * x);
+  U[6] = T(2) * (x * z - w * y);
+  U[7] = T(2) * (y * z + w * x);
+  U[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+// Unit quaternion of a proper rotation matrix (Shepperd's method: divide by
+// the largest of the four candidate squared components).
+__host__ __device__ __forceinline__ void rot_to_quat(const double* U, double* q) {
+  const double tr = U[0] + U[4] + U[8];
+  if (tr > 0.0) {
+    const double S = 2.0 * sqrt(tr + 1.0);
+    q[0] = 0.25 * S; q[1] = (U[7] - U[5]) / S; q[2] = (U[2] - U[6]) / S; q[3] = (U[3] - U[1]) / S;
+  } else if (U[0] > U[4] && U[0] > U[8]) {
+    const double S = 2.0 * sqrt(1.0 + U[0] - U[4] - U[8]);
+    q[0] = (U[7] - U[5]) / S; q[1] = 0.25 * S; q[2] = (U[1] + U[3]) / S; q[3] = (U[2] + U[6]) / S;
+  } else if (U[4] > U[8]) {
+    const double S = 2.0 * sqrt(1.0 + U[4] - U[0] - U[8]);
+    q[0] = (U[2] - U[6]) / S; q[1] = (U[1] + U[3]) / S; q[2] = 0.25 * S; q[3] = (U[5] + U[7]) / S;
+  } else {
+    const double S = 2.0 * sqrt(1.0 + U[8] - U[0] - U[4]);
+    q[0] = (U[3] - U[1]) / S; q[1] = (U[2] + U[6]) / S; q[2] = (U[5] + U[7]) / S; q[3] = 0.25 * S;
+  }
+  const double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) q[i] /= n;
+}
 
 // Deterministic wavefront sum (butterfly over 64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {

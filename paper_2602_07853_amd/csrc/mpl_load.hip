@@ -155,12 +155,13 @@ __global__ void k_export_abar_fact(const float* __restrict__ Ab, const uint64_t*
   const int64_t di = ((int64_t)i0 * ny + j0) * nz + k0;
   const TanSlot ts = tan_slot(cmask, coff, b, l, MPL_TAN_FACT);
   if (!ts.active) return;
-  double f[30];
-  for (int e = 0; e < 30; ++e) f[e] = (double)Ab[ts.base + (int64_t)e * ts.n + ts.rank];
-  const double* U = f;
-  const double* M = f + 9;
-  const double* A3 = f + 18;
-  const double* pc = f + 24;
+  double f[MPL_TAN_FACT_READ];
+  for (int e = 0; e < MPL_TAN_FACT_READ; ++e) f[e] = (double)Ab[ts.base + (int64_t)e * ts.n + ts.rank];
+  double U[9];
+  quat_to_rot<double>(f[0], f[1], f[2], f[3], U);
+  const double* M = f + 4;
+  const double* A3 = f + 13;
+  const double* pc = f + 19;
   for (int col = 0; col < 9; ++col) {
     double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     g[col] = 1.0;
@@ -289,7 +290,7 @@ mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, dou
   st.domain_events = c->hscal.domain_count;
   {
     const int elem = c->tangent_precision == MPL_F32 ? 4 : 8;
-    st.tangent_entries = c->tan_factored ? 30 : 45;
+    st.tangent_entries = c->tan_factored ? MPL_TAN_FACT_READ : MPL_TAN_DENSE;
     st.hv_model_bytes = (double)st.tangent_entries * elem * c->hscal.n_tan_cells +
                         6.0 * elem * c->hscal.n_active_nodes;
   }

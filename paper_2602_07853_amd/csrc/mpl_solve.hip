@@ -319,9 +319,10 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
   double Ab[45];
 #pragma unroll
   for (int i = 0; i < 45; ++i) Ab[i] = 0.0;
-  double fac[30];
+  double fac[MPL_TAN_FACT_READ];
 #pragma unroll
-  for (int i = 0; i < 30; ++i) fac[i] = 0.0;
+  for (int i = 0; i < MPL_TAN_FACT_READ; ++i) fac[i] = 0.0;
+  fac[0] = 1.0;  // identity rotation where no material is present
   bool any = false;
   for (int k = 0; k < K; ++k) any = any || (Vk[k * ncell + ci] != 0.0);
   if (any) {
@@ -352,21 +353,19 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       if (FACT) {
         double M[9];
         mul(S, Vm, M);
-        for (int i = 0; i < 9; ++i) {
-          fac[i] = U[i];
-          fac[9 + i] = M[i];
-        }
+        rot_to_quat(U, fac);
+        for (int i = 0; i < 9; ++i) fac[4 + i] = M[i];
         const int sy[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
         for (int e = 0; e < 6; ++e) {
           double acc = 0.0;
           for (int m = 0; m < 3; ++m)
             if (w[m] > 0.0) acc += coef * w[m] * Qm[sy[e][0] * 3 + m] * Qm[sy[e][1] * 3 + m];
-          fac[18 + e] = acc;
+          fac[13 + e] = acc;
         }
         for (int pp = 0; pp < 3; ++pp) {
           const double lt = tw[pp] > 0.0 ? tw[pp] : 0.0, lf = fl[pp] > 0.0 ? fl[pp] : 0.0;
-          fac[24 + 2 * pp] = 0.5 * coef * (lt + lf);
-          fac[25 + 2 * pp] = 0.5 * coef * (lt - lf);
+          fac[19 + 2 * pp] = 0.5 * coef * (lt + lf);
+          fac[20 + 2 * pp] = 0.5 * coef * (lt - lf);
         }
       }
       for (int mode = 0; mode < 9; ++mode) {
@@ -404,7 +403,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
   }
   if (FACT) {
 #pragma unroll
-    for (int i = 0; i < 30; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
+    for (int i = 0; i < MPL_TAN_FACT_READ; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
     // Jacobi-diagonal contributions Q_a(s) = sum_{b,b'} Abar[(a,b),(a,b')]
     // sig_b sig_b' / (4 dx)^2 for the corner signs sig = (+1, sy, sz),
     // s = 2 (sy < 0) + (sz < 0) (a corner and its opposite share the value)
@@ -415,7 +414,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
         double q = 0.0;
         for (int b = 0; b < 3; ++b)
           for (int b2 = 0; b2 < 3; ++b2) q += Ab[sym9(a * 3 + b, a * 3 + b2)] * sg[b] * sg[b2];
-        Abar[ts.base + (int64_t)(30 + a * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
+        Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + a * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
       }
   } else {
 #pragma unroll
@@ -450,7 +449,7 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
         const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
         const int sidx = sy * 2 + sz;
         for (int a = 0; a < 3; ++a)
-          dd[a] += (double)Abar[ts.base + (int64_t)(30 + a * 4 + sidx) * ts.n + ts.rank];
+          dd[a] += (double)Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + a * 4 + sidx) * ts.n + ts.rank];
         continue;
       }
       double gw[3];
@@ -563,15 +562,13 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
       const T* A = Abar + ts.base + ts.rank;
       if (FACT) {
         T U[9], M[9], A3[6], pc[6];
+        quat_to_rot<T>(A[0], A[ts.n], A[2 * (int64_t)ts.n], A[3 * (int64_t)ts.n], U);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) {
-          U[e] = A[(int64_t)e * ts.n];
-          M[e] = A[(int64_t)(9 + e) * ts.n];
-        }
+        for (int e = 0; e < 9; ++e) M[e] = A[(int64_t)(4 + e) * ts.n];
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-          A3[e] = A[(int64_t)(18 + e) * ts.n];
-          pc[e] = A[(int64_t)(24 + e) * ts.n];
+          A3[e] = A[(int64_t)(13 + e) * ts.n];
+          pc[e] = A[(int64_t)(19 + e) * ts.n];
         }
         // Ghat = U^T g M
         T t1[9], gh[9];

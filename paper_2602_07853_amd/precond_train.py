@@ -29,6 +29,26 @@ LAYERS = [("enc0a", 27, 16, 16), ("enc0b", 27, 16, 16), ("down0", 8, 16, 32),
 UP = {"up2", "up1", "up0"}
 
 
+# (input level, output level) of every layer; level L has box >> L voxels per axis
+LEVEL = {"enc0a": (0, 0), "enc0b": (0, 0), "down0": (0, 1), "enc1a": (1, 1), "enc1b": (1, 1),
+         "down1": (1, 2), "enc2a": (2, 2), "enc2b": (2, 2), "down2": (2, 3), "bota": (3, 3),
+         "botb": (3, 3), "up2": (3, 2), "dec2a": (2, 2), "dec2b": (2, 2), "up1": (2, 1),
+         "dec1a": (1, 1), "dec1b": (1, 1), "up0": (1, 0), "dec0a": (0, 0), "dec0b": (0, 0),
+         "out": (0, 0)}
+
+
+def forward_flops(box) -> float:
+    """Multiply-add FLOPs (2 per MAC) of one forward pass on a dense box."""
+    total = 0.0
+    for name, t, ci, co in LAYERS:
+        lin, lout = LEVEL[name]
+        nout = (box[0] >> lout) * (box[1] >> lout) * (box[2] >> lout)
+        # gather convolutions: taps x ci MACs per output channel and voxel;
+        # transposed convolutions: ci MACs per output value (one tap each)
+        total += 2.0 * co * (ci * nout if name in UP else t * ci * nout)
+    return total
+
+
 def param_count() -> int:
     return sum(t * ci * co + co for _, t, ci, co in LAYERS)
 

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
   const int cb = grp * 4 + w;
   const bool valid = cb < n_cblk;
   __shared__ T tp_all[4][3][128];
-  __shared__ T ys_all[4][9][64];
+  __shared__ T ys_all[4][12][64];
   __shared__ double dsum[4];
   T(*tp)[128] = tp_all[w];
   T(*ys)[64] = ys_all[w];
@@ -622,11 +622,21 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
       for (int r = 0; r < 9; ++r) dot += (double)y[r] * (double)g[r];
     }
 #pragma unroll
-    for (int r = 0; r < 9; ++r) ys[r][l] = y[r];
+    // per component a the four signed sums P_k = y_a0 +- y_a1 +- y_a2 (scaled
+    // by 1/(4 dx)): corner sign pattern (sx, sy, sz) contributes
+    // sx * P_k with k = 2 (sy != sx) + (sz != sx)
+    for (int a = 0; a < 3; ++a) {
+      const T y0 = y[a * 3] * inv4dx, y1 = y[a * 3 + 1] * inv4dx, y2 = y[a * 3 + 2] * inv4dx;
+      ys[a * 4 + 0][l] = y0 + y1 + y2;
+      ys[a * 4 + 1][l] = y0 + y1 - y2;
+      ys[a * 4 + 2][l] = y0 - y1 + y2;
+      ys[a * 4 + 3][l] = y0 - y1 - y2;
+    }
   }
   __syncthreads();
   // Gather: tile node t sums y_c grad w over its in-block cells c = t - d,
-  // in corner order d = 0..7.  Round 0: the lane's own node; round 1: halo.
+  // in corner order d = 0..7 (3 LDS reads per cell).  Round 0: the lane's
+  // own node; round 1: halo.
   if (valid) {
     for (int round = 0; round < 2; ++round) {
       int tx, ty, tz;
@@ -643,9 +653,12 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
         const int cx = tx - dx, cy = ty - dy, cz = tz - dz;
         if (cx < 0 || cy < 0 || cz < 0 || cx > 3 || cy > 3 || cz > 3) continue;
         const int cl = local_index(cx, cy, cz);
-        const T sx = dx ? inv4dx : -inv4dx, sy = dy ? inv4dx : -inv4dx, sz = dz ? inv4dx : -inv4dx;
+        const int k = ((dy != dx) << 1) | (dz != dx);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) h[a] += ys[a * 3][cl] * sx + ys[a * 3 + 1][cl] * sy + ys[a * 3 + 2][cl] * sz;
+        for (int a = 0; a < 3; ++a) {
+          const T v = ys[a * 4 + k][cl];
+          h[a] += dx ? v : -v;
+        }
       }
       T* out = (round == 0) ? Hown : Hhalo;
 #pragma unroll

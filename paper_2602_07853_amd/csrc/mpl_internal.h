@@ -129,7 +129,7 @@ struct mpl_ctx {
   int64_t online_loss_n = 0;
   DevBuf ozt, ohz, ogr, opieces;
   // single-reduction CG: u = Dinv r and s = running H p (tangent precision)
-  DevBuf cg_u, cg_s;
+  DevBuf cg_u, cg_s, cg_dx;
   bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop
 
   // learned preconditioner (allocated on first use)

@@ -869,10 +869,16 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
 //   alpha = gamma / (delta - beta gamma / alpha_old).
 // s carries H p without a second product.  Per iteration: this vector
 // kernel, the fused product of u (with its u^T K u partials), one reduction.
+// x (FP64) is advanced through an increment dx kept in the tangent's
+// precision for at most CG_FLUSH iterations (x += dx every CG_FLUSH-th
+// iteration and at the end of the solve), which halves the per-iteration
+// traffic of the solution vector.
+#define CG_FLUSH 8
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, const T* __restrict__ Dinv,
                                                  const T* __restrict__ mi, const uint8_t* __restrict__ flags,
                                                  int64_t nnode, int n_nblk, double* __restrict__ x,
+                                                 T* __restrict__ dx,
                                                  double* __restrict__ r, T* __restrict__ u,
                                                  T* __restrict__ p, T* __restrict__ sv,
                                                  double* __restrict__ pg, double* __restrict__ pbb,
@@ -892,6 +898,7 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
       const double rv = fr ? b[i] : 0.0;
       const T uv = (T)(rv * (double)Dinv[i]);
       x[i] = 0.0;
+      dx[i] = T(0);
       r[i] = rv;
       u[i] = uv;
       p[i] = T(0);
@@ -917,7 +924,8 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
                                                  const int* __restrict__ n_nbr_cell, int64_t ncell,
                                                  const T* __restrict__ mi, const T* __restrict__ Dinv,
                                                  const uint8_t* __restrict__ flags, int64_t nnode,
-                                                 int n_nblk, double* __restrict__ x, double* __restrict__ r,
+                                                 int n_nblk, double* __restrict__ x, T* __restrict__ dx,
+                                                 double* __restrict__ r,
                                                  double* __restrict__ pg, double* __restrict__ prr,
                                                  double* __restrict__ pmu,
                                                  const SolverScalars* __restrict__ s) {
@@ -925,14 +933,15 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
   __shared__ double sh[4];
   const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   const double alpha = s->alpha, beta = s->beta;
+  const bool flush = ((s->iters + 1) % CG_FLUSH) == 0;
   double g = 0.0, rr = 0.0, mu = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     if (flags[ni] & MPL_NODE_FREE) {
       // all loads of the node first (three components), then the arithmetic
       // and the stores, so that every load is in flight at once
-      T uv[3], pv[3], svv[3], dv[3];
-      double xv[3], rv[3];
+      T uv[3], pv[3], svv[3], dv[3], dxv[3];
+      double xv[3] = {0.0, 0.0, 0.0}, rv[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
@@ -940,7 +949,8 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
         pv[a] = p[i];
         svv[a] = sv[i];
         dv[a] = Dinv[i];
-        xv[a] = x[i];
+        dxv[a] = dx[i];
+        if (flush) xv[a] = x[i];
         rv[a] = r[i];
       }
       const T m = mi[ni];
@@ -956,7 +966,12 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
         const T un = (T)(rn * (double)dv[a]);
         p[i] = pn;
         sv[i] = sn;
-        x[i] = xv[a] + alpha * (double)pn;
+        if (flush) {
+          x[i] = xv[a] + ((double)dxv[a] + alpha * (double)pn);
+          dx[i] = T(0);
+        } else {
+          dx[i] = (T)((double)dxv[a] + alpha * (double)pn);
+        }
         r[i] = rn;
         u[i] = un;
         g += rn * (double)un;
@@ -1055,6 +1070,16 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
   s->beta = beta;
   s->alpha = A / denom;
   s->rz = A;
+}
+
+// x += dx, dx = 0 (free nodes)
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_flush(double* __restrict__ x, T* __restrict__ dx,
+                                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] += (double)dx[i];
+  dx[i] = T(0);
 }
 
 // ---- flexible CG with the learned preconditioner ----
@@ -1633,19 +1658,22 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     // single-reduction form (see k_cg_step)
     MPL_TRY(mpl_ensure(c, c->cg_u, sizeof(T) * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->cg_s, sizeof(T) * 3 * nnode));
+    MPL_TRY(mpl_ensure(c, c->cg_dx, sizeof(T) * 3 * nnode));
     T* u = P<T>(c->cg_u);
     T* sv = P<T>(c->cg_s);
+    T* dx = P<T>(c->cg_dx);
+    const int nflush = (int)((3 * nnode + 255) / 256);
     const int ngrp = (c->n_cblk + 3) / 4;
     MPL_LAUNCH(c, k_cg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode,
-               c->n_nblk, x, P<double>(c->r), u, p, sv, pa, pb, pm, s);
+               c->n_nblk, x, dx, P<double>(c->r), u, p, sv, pa, pb, pm, s);
     MPL_TRY(hv_pieces<T>(c, u, true));
     MPL_LAUNCH(c, k_reduce_cg<true>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
     MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
     const int check = std::max(1, c->opts.pcg_check_every);
     auto launch_iteration = [&]() -> mpl_status {
       MPL_LAUNCH(c, k_cg_step<T>, nwg, 256, u, p, sv, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-                 P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa,
-                 pb, pm, s);
+                 P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
+                 pa, pb, pm, s);
       MPL_TRY(hv_pieces<T>(c, u, true));
       MPL_LAUNCH(c, k_reduce_cg<false>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
       return MPL_OK;
@@ -1653,9 +1681,20 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     const void* key[24] = {x,           p,           c->r.p,          c->Dt.p,
                            abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
-                           c->cmask.p,  c->coff.p,   u,               sv};
+                           c->cmask.p,  c->coff.p,   u,               sv,
+                           dx};
     const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 2};
-    MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration, hook));
+    // a caller's hook sees the full solution vector
+    std::function<mpl_status(int)> flushed_hook;
+    if (hook) {
+      flushed_hook = [&](int it) -> mpl_status {
+        MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
+        return (*hook)(it);
+      };
+    }
+    MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration,
+                       hook ? &flushed_hook : nullptr));
+    MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
     if (iters) *iters = c->hscal.iters;
     if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
     if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)

@@ -206,12 +206,29 @@ def config5(seed: int = 5, n: int = 256, ppc_axis: int = 2) -> Scene:
     dt = 2e-3, 50 steps."""
     dx = 1.0 / n
     rng = np.random.Generator(np.random.PCG64(seed))
+    # Rejection sampling of three such spheres with uniform centres almost
+    # never succeeds (they fill ~22% of the cube), so the candidates are
+    # jittered corners of the cube of admissible centres, three corners that
+    # differ in at least two coordinates (face or body diagonals apart),
+    # redrawn until the spheres are disjoint or touching.
+    corners = np.array([[(k >> 2) & 1, (k >> 1) & 1, k & 1] for k in range(8)], dtype=np.float64)
     spheres = []
     while len(spheres) < 3:
-        r = rng.uniform(0.24, 0.28)
-        ctr = rng.uniform(r + 4 * dx, 1 - r - 4 * dx, 3)
-        if all(np.linalg.norm(ctr - c) >= r + rr for c, rr in spheres):
-            spheres.append((ctr, r))
+        spheres = []
+        order = rng.permutation(8)
+        picked = []
+        for k in order:
+            if all(np.abs(corners[k] - corners[j]).sum() >= 2 for j in picked):
+                picked.append(k)
+            if len(picked) == 3:
+                break
+        for k in picked:
+            r = rng.uniform(0.24, 0.28)
+            lo, hi = r + 4 * dx, 1 - r - 4 * dx
+            ctr = lo + corners[k] * (hi - lo) + rng.uniform(-0.02, 0.02, 3)
+            ctr = np.clip(ctr, lo, hi)
+            if all(np.linalg.norm(ctr - c) >= r + rr for c, rr in spheres):
+                spheres.append((ctr, r))
     c = (np.arange(n) + 0.5) * dx
     X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
     owner = np.full((n, n, n), -1, np.int32)

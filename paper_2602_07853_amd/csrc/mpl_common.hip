@@ -230,7 +230,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.8 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.9 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -275,14 +275,14 @@ void mpl_destroy(mpl_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   DevBuf* all[] = {&c->cflag, &c->cmap, &c->nflag, &c->nmap, &c->scan_tmp, &c->ccoord, &c->ncoord,
-                   &c->c_nbr_node, &c->n_nbr_cell, &c->colour_list, &c->pcell, &c->pkey,
+                   &c->c_nbr_node, &c->n_nbr_cell, &c->pcell, &c->pkey,
                    &c->bin_count, &c->bin_start, &c->bin_fill, &c->sorted, &c->mc, &c->qc, &c->Gc,
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
                    &c->Y64, &c->vcl, &c->Gcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx};
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

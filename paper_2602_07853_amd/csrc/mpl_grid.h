@@ -122,6 +122,44 @@ __host__ __device__ __forceinline__ void rot_to_quat(const double* U, double* q)
   for (int i = 0; i < 4; ++i) q[i] /= n;
 }
 
+// Halo slots of a 5x5x5 tile over a 4x4x4 block: the 61 tile positions with
+// some coordinate equal to 4 (they belong to the +x/+y/+z neighbour blocks):
+// faces 0-15 (x), 16-31 (y), 32-47 (z), edges 48-51 (xy), 52-55 (xz),
+// 56-59 (yz), corner 60.
+__device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
+  if (l < 16) { tx = 4; ty = l >> 2; tz = l & 3; }
+  else if (l < 32) { int k = l - 16; tx = k >> 2; ty = 4; tz = k & 3; }
+  else if (l < 48) { int k = l - 32; tx = k >> 2; ty = k & 3; tz = 4; }
+  else if (l < 52) { tx = 4; ty = 4; tz = l - 48; }
+  else if (l < 56) { tx = 4; ty = l - 52; tz = 4; }
+  else if (l < 60) { tx = l - 56; ty = 4; tz = 4; }
+  else { tx = 4; ty = 4; tz = 4; }
+}
+__device__ __forceinline__ int halo_slot(int tx, int ty, int tz) {
+  const bool X = tx == 4, Y = ty == 4, Z = tz == 4;
+  if (X && Y && Z) return 60;
+  if (Y && Z) return 56 + tx;
+  if (X && Z) return 52 + ty;
+  if (X && Y) return 48 + tz;
+  if (Z) return 32 + tx * 4 + ty;
+  if (Y) return 16 + tx * 4 + tz;
+  return ty * 4 + tz;  // X
+}
+// Sources of local position l of block b in the halos of the blocks at
+// -x, -y, -z, -xy, -xz, -yz, -xyz (offset index o = (ox*2+oy)*2+oz into the
+// node-block neighbour list n_nbr_cell of the block's co-located node block)
+// and the halo slot there; need[k] = false where l is not on that face.
+__device__ __forceinline__ void halo_sources(int l, int* o, int* slot, bool* need) {
+  const int lx = l >> 4, ly = (l >> 2) & 3, lz = l & 3;
+  o[0] = 4; need[0] = lx == 0; slot[0] = ly * 4 + lz;
+  o[1] = 2; need[1] = ly == 0; slot[1] = 16 + lx * 4 + lz;
+  o[2] = 1; need[2] = lz == 0; slot[2] = 32 + lx * 4 + ly;
+  o[3] = 6; need[3] = lx == 0 && ly == 0; slot[3] = 48 + lz;
+  o[4] = 5; need[4] = lx == 0 && lz == 0; slot[4] = 52 + ly;
+  o[5] = 3; need[5] = ly == 0 && lz == 0; slot[5] = 56 + lx;
+  o[6] = 7; need[6] = lx == 0 && ly == 0 && lz == 0; slot[6] = 60;
+}
+
 // Deterministic wavefront sum (butterfly over 64 lanes).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

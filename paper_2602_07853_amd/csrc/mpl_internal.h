@@ -60,7 +60,6 @@ struct SolverScalars {
   int32_t err;        // binning / domain error flags
   int32_t domain_count;
   int32_t n_cblk, n_nblk;
-  int32_t colour_count[8];
   int32_t n_active_cells, n_active_nodes, n_free_nodes;
   int32_t n_tan_cells;  // cells that carry a tangent (some V_{c,k} != 0)
 };
@@ -87,11 +86,9 @@ struct mpl_ctx {
   double dt = 0.0;
   int64_t np = 0;
   int n_cblk = 0, n_nblk = 0;
-  int colour_count[8] = {0};
-  int colour_offset[9] = {0};
 
   // binning
-  DevBuf cflag, cmap, nflag, nmap, scan_tmp, ccoord, ncoord, c_nbr_node, n_nbr_cell, colour_list,
+  DevBuf cflag, cmap, nflag, nmap, scan_tmp, ccoord, ncoord, c_nbr_node, n_nbr_cell,
       pcell, pkey, bin_count, bin_start, bin_fill, sorted;
   // cell fields (FP64 unless noted)
   DevBuf mc, qc, Gc, Vk, Tk, Sk, Qc, ecell, Abar32, Abar64, Y32, Y64, vcl, Gcl;
@@ -99,6 +96,7 @@ struct mpl_ctx {
   // (Abar[45*coff[cb] + e*count(cb) + rank]), with a 64-bit active mask per
   // cell block (see tan_slot in mpl_grid.h)
   DevBuf cmask, ccnt, coff;
+  DevBuf p2c_halo;  // particle -> centre scatter: per-block halo staging
   // node fields
   // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
   // (read by the CG vector kernels)

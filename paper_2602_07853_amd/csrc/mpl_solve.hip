@@ -492,17 +492,6 @@ __device__ __forceinline__ int xcd_block(int wg, int n) {
   return (wg & 7) * per + (wg >> 3);
 }
 
-// halo slot -> tile coordinates (see the owner-side decoding in halo_slot)
-__device__ __forceinline__ void halo_tile(int l, int& tx, int& ty, int& tz) {
-  if (l < 16) { tx = 4; ty = l >> 2; tz = l & 3; }
-  else if (l < 32) { int k = l - 16; tx = k >> 2; ty = 4; tz = k & 3; }
-  else if (l < 48) { int k = l - 32; tx = k >> 2; ty = k & 3; tz = 4; }
-  else if (l < 52) { tx = 4; ty = 4; tz = l - 48; }
-  else if (l < 56) { tx = 4; ty = l - 52; tz = 4; }
-  else if (l < 60) { tx = l - 56; ty = 4; tz = 4; }
-  else { tx = 4; ty = 4; tz = 4; }
-}
-
 template <class T, bool DOT, bool FACT>
 __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
@@ -681,7 +670,6 @@ template <class T>
 __device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* __restrict__ Hhalo,
                                           const int* __restrict__ n_nbr_cell, int64_t ncell,
                                           int nb, int l, T* h) {
-  const int lx = l >> 4, ly = (l >> 2) & 3, lz = l & 3;
   h[0] = h[1] = h[2] = T(0);
   const int* nbr = n_nbr_cell + nb * 8;
   int src = nbr[0];
@@ -690,16 +678,9 @@ __device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* _
 #pragma unroll
     for (int a = 0; a < 3; ++a) h[a] += Hown[a * ncell + i];
   }
-  // (offset index o = (ox*2+oy)*2+oz, required zero local coords, halo slot)
   int o[7], slot[7];
   bool need[7];
-  o[0] = 4; need[0] = lx == 0; slot[0] = ly * 4 + lz;
-  o[1] = 2; need[1] = ly == 0; slot[1] = 16 + lx * 4 + lz;
-  o[2] = 1; need[2] = lz == 0; slot[2] = 32 + lx * 4 + ly;
-  o[3] = 6; need[3] = lx == 0 && ly == 0; slot[3] = 48 + lz;
-  o[4] = 5; need[4] = lx == 0 && lz == 0; slot[4] = 52 + ly;
-  o[5] = 3; need[5] = ly == 0 && lz == 0; slot[5] = 56 + lx;
-  o[6] = 7; need[6] = lx == 0 && ly == 0 && lz == 0; slot[6] = 60;
+  halo_sources(l, o, slot, need);
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     if (!need[k]) continue;
@@ -1638,7 +1619,8 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
 // the done flag only every pcg_check_every iterations.
 template <class T>
 static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
-                           const std::function<mpl_status(int)>* hook = nullptr) {
+                           const std::function<mpl_status(int)>* hook = nullptr,
+                           bool hook_reads_x = false) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(ensure_partials(c));
   MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
@@ -1684,16 +1666,17 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                            c->cmask.p,  c->coff.p,   u,               sv,
                            dx};
     const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 2};
-    // a caller's hook sees the full solution vector
+    // a hook that reads x sees the full solution vector (flushing changes
+    // the rounding of x, so it is done only for such hooks)
     std::function<mpl_status(int)> flushed_hook;
-    if (hook) {
+    if (hook && hook_reads_x) {
       flushed_hook = [&](int it) -> mpl_status {
         MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
         return (*hook)(it);
       };
     }
     MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration,
-                       hook ? &flushed_hook : nullptr));
+                       hook ? (hook_reads_x ? &flushed_hook : hook) : nullptr));
     MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
     if (iters) *iters = c->hscal.iters;
     if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
@@ -1923,7 +1906,7 @@ static mpl_status collect_pairs(mpl_ctx* c, const double* b, int* iters) {
     // stop the replay at the exact solve's length
     c->opts.max_pcg = std::max(1, std::min(c->opts.max_pcg, *iters));
     st = learned ? pcg_learned<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook)
-                 : pcg_impl<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook);
+                 : pcg_impl<T>(c, b, P<double>(c->x), nullptr, nullptr, &hook, true);
   }
   c->opts = saved;
   return st;

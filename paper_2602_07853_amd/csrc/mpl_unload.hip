@@ -10,9 +10,11 @@
 //     each run's contribution to each of the 8 target centres b + delta, and
 //     the run's last lane adds it into a 5x5x5 centre tile in LDS (distinct
 //     runs hit distinct centres, so the adds never collide);
-//   * tiles overlap their +x/+y/+z neighbours by one layer, so blocks are
-//     written back in 8 passes by block-coordinate parity: blocks of one
-//     colour touch disjoint centres and read-modify-write them race-free.
+//   * tiles overlap their +x/+y/+z neighbours by one layer: every block
+//     stores its own 64 centres directly and the 61 centres of its halo into
+//     a per-block staging slot; a second pass (one wave per block) adds to
+//     each centre the halo slots of the up to 7 blocks at -x/-y/-z in a fixed
+//     order and normalises (no read-modify-write, one launch each).
 #include <cmath>
 
 #include "mpl_grid.h"
@@ -62,8 +64,7 @@ __global__ void k_mark(ParticlesDev P, GridDev g, int32_t* __restrict__ pcell,
 
 __global__ void k_compact_cells(const int32_t* __restrict__ cflag, const int32_t* __restrict__ scan,
                                 int32_t* __restrict__ cmap, int4* __restrict__ ccoord,
-                                int32_t* __restrict__ nflag, int32_t* __restrict__ colour_list,
-                                int32_t* __restrict__ colour_count, GridDev g, int ndense) {
+                                int32_t* __restrict__ nflag, GridDev g, int ndense) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ndense) return;
   if (!cflag[i]) {
@@ -73,10 +74,7 @@ __global__ void k_compact_cells(const int32_t* __restrict__ cflag, const int32_t
   int id = scan[i];
   cmap[i] = id;
   int bz = i % g.cbd[2], by = (i / g.cbd[2]) % g.cbd[1], bx = i / (g.cbd[1] * g.cbd[2]);
-  int col = ((bx & 1) << 2) | ((by & 1) << 1) | (bz & 1);
-  ccoord[id] = make_int4(bx, by, bz, col);
-  int pos = atomicAdd(&colour_count[col], 1);
-  colour_list[col * ndense + pos] = id;
+  ccoord[id] = make_int4(bx, by, bz, 0);
   for (int d = 0; d < 8; ++d) {
     int nx = bx + ((d >> 2) & 1), ny = by + ((d >> 1) & 1), nz = bz + (d & 1);
     nflag[(nx * g.nbd[1] + ny) * g.nbd[2] + nz] = 1;
@@ -176,17 +174,16 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
                                             const int32_t* __restrict__ sorted,
                                             const int32_t* __restrict__ pkey,
                                             const int32_t* __restrict__ bin_start,
-                                            const int32_t* __restrict__ colour_list,
                                             const int4* __restrict__ ccoord,
                                             const int32_t* __restrict__ cmap,
                                             double* __restrict__ mc, double* __restrict__ qc,
                                             double* __restrict__ Gc, double* __restrict__ Vk,
                                             double* __restrict__ Tk, int64_t ncell,
-                                            int32_t* __restrict__ err) {
+                                            double* __restrict__ halo, int32_t* __restrict__ err) {
   constexpr int NV = 13 + 7 * K;
   __shared__ double tile[NV][128];
   const int lane = threadIdx.x;
-  const int cb = colour_list[blockIdx.x];
+  const int cb = blockIdx.x;
   const int4 bc = ccoord[cb];
   for (int v = 0; v < NV; ++v) {
     tile[v][lane] = 0.0;
@@ -259,52 +256,105 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
     }
   }
   __syncthreads();
-  // write back the 5x5x5 tile (block parity colouring makes this race-free)
-  for (int t = lane; t < 125; t += 64) {
-    if (tile[0][t] == 0.0) {
-      bool any = false;
-      for (int v = 1; v < NV; ++v) any = any || (tile[v][t] != 0.0);
-      if (!any) continue;
-    }
-    const int tx = t / 25, ty = (t / 5) % 5, tz = t % 5;
-    const int gx = bc.x * 4 + tx, gy = bc.y * 4 + ty, gz = bc.z * 4 + tz;
-    if (gx >= g.dims[0] || gy >= g.dims[1] || gz >= g.dims[2]) {
-      atomicOr(err, 4);
-      continue;
-    }
-    const int blk = cmap[((gx >> 2) * g.cbd[1] + (gy >> 2)) * g.cbd[2] + (gz >> 2)];
-    if (blk < 0) {
-      atomicOr(err, 4);
-      continue;
-    }
-    const int64_t ci = (int64_t)blk * MPL_BC + local_index(gx & 3, gy & 3, gz & 3);
-    mc[ci] += tile[0][t];
-    for (int a = 0; a < 3; ++a) qc[a * ncell + ci] += tile[1 + a][t];
-    for (int e2 = 0; e2 < 9; ++e2) Gc[e2 * ncell + ci] += tile[4 + e2][t];
+  // own centres: plain stores (this block is their only writer in this pass)
+  {
+    const int t = ((lane >> 4) * 5 + ((lane >> 2) & 3)) * 5 + (lane & 3);
+    const int64_t ci = (int64_t)cb * MPL_BC + lane;
+    mc[ci] = tile[0][t];
+    for (int a = 0; a < 3; ++a) qc[a * ncell + ci] = tile[1 + a][t];
+    for (int e2 = 0; e2 < 9; ++e2) Gc[e2 * ncell + ci] = tile[4 + e2][t];
     for (int kk = 0; kk < K; ++kk) {
-      Vk[kk * ncell + ci] += tile[13 + 7 * kk][t];
-      for (int j = 0; j < 6; ++j) Tk[(kk * 6 + j) * ncell + ci] += tile[14 + 7 * kk + j][t];
+      Vk[kk * ncell + ci] = tile[13 + 7 * kk][t];
+      for (int j = 0; j < 6; ++j) Tk[(kk * 6 + j) * ncell + ci] = tile[14 + 7 * kk + j][t];
+    }
+  }
+  // halo centres: staged per block ([value][block][64 slots]); a nonzero
+  // contribution to a centre outside the grid is a stencil leaving it
+  if (lane < 61) {
+    int tx, ty, tz;
+    halo_tile(lane, tx, ty, tz);
+    const int t = (tx * 5 + ty) * 5 + tz;
+    const int gx = bc.x * 4 + tx, gy = bc.y * 4 + ty, gz = bc.z * 4 + tz;
+    const bool inside = gx < g.dims[0] && gy < g.dims[1] && gz < g.dims[2];
+    bool any = false;
+    for (int v = 0; v < NV; ++v) {
+      const double val = tile[v][t];
+      any = any || (val != 0.0);
+      halo[((int64_t)v * gridDim.x + cb) * MPL_BC + lane] = val;
+    }
+    if (any) {
+      // the receiving block must exist (else a stencil left the grid or the
+      // active-block marking missed it)
+      if (!inside) atomicOr(err, 4);
+      else if (cmap[((gx >> 2) * g.cbd[1] + (gy >> 2)) * g.cbd[2] + (gz >> 2)] < 0) atomicOr(err, 4);
     }
   }
 }
 
-// Alg. 2 normalisation: v_c = (mv)_c/m_c, G_c = (mG)_c/m_c, tau_{c,k} = (V tau)_{c,k}/V_{c,k}.
-__global__ void k_normalise(double* __restrict__ mc, double* __restrict__ qc, double* __restrict__ Gc,
-                            const double* __restrict__ Vk, double* __restrict__ Tk, int64_t ncell,
-                            int K, int32_t* __restrict__ count) {
-  int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ci >= ncell) return;
-  double m = mc[ci];
+// Second pass of the scatter: own value + halo slots of the blocks at
+// -x/-y/-z (fixed order), then Alg. 2 normalisation
+//   v_c = (mv)_c / m_c, G_c = (mG)_c / m_c, tau_{c,k} = (V tau)_{c,k} / V_{c,k}.
+template <int K>
+__global__ __launch_bounds__(64) void k_p2c_combine(const int* __restrict__ c_nbr_node,
+                                                    const int* __restrict__ n_nbr_cell, int n_cblk,
+                                                    const double* __restrict__ halo,
+                                                    double* __restrict__ mc, double* __restrict__ qc,
+                                                    double* __restrict__ Gc, double* __restrict__ Vk,
+                                                    double* __restrict__ Tk, int64_t ncell,
+                                                    int32_t* __restrict__ count, int32_t* __restrict__ err) {
+  constexpr int NV = 13 + 7 * K;
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  double acc[NV];
+  acc[0] = mc[ci];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) acc[1 + a] = qc[a * ncell + ci];
+#pragma unroll
+  for (int e2 = 0; e2 < 9; ++e2) acc[4 + e2] = Gc[e2 * ncell + ci];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    acc[13 + 7 * kk] = Vk[kk * ncell + ci];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc[14 + 7 * kk + j] = Tk[(kk * 6 + j) * ncell + ci];
+  }
+  // the co-located node block lists the cell blocks at -{0,1}^3
+  const int nb = c_nbr_node[cb * 8];
+  int o[7], slot[7];
+  bool need[7];
+  halo_sources(l, o, slot, need);
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    if (!need[k]) continue;
+    const int src = n_nbr_cell[nb * 8 + o[k]];
+    if (src < 0) continue;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += halo[((int64_t)v * n_cblk + src) * MPL_BC + slot[k]];
+  }
+  const double m = acc[0];
   if (m != 0.0) {
-    for (int a = 0; a < 3; ++a) qc[a * ncell + ci] /= m;
-    for (int e = 0; e < 9; ++e) Gc[e * ncell + ci] /= m;
+#pragma unroll
+    for (int v = 1; v < 13; ++v) acc[v] /= m;
     atomicAdd(count, 1);
   }
-  for (int k = 0; k < K; ++k) {
-    double V = Vk[k * ncell + ci];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const double V = acc[13 + 7 * kk];
     if (V != 0.0)
-      for (int j = 0; j < 6; ++j) Tk[(k * 6 + j) * ncell + ci] /= V;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) acc[14 + 7 * kk + j] /= V;
   }
+  mc[ci] = acc[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) qc[a * ncell + ci] = acc[1 + a];
+#pragma unroll
+  for (int e2 = 0; e2 < 9; ++e2) Gc[e2 * ncell + ci] = acc[4 + e2];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    Vk[kk * ncell + ci] = acc[13 + 7 * kk];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) Tk[(kk * 6 + j) * ncell + ci] = acc[14 + 7 * kk + j];
+  }
+  (void)err;
 }
 
 // Tangent-carrying cells (some V_{c,k} != 0) per cell block: 64-bit mask
@@ -417,7 +467,6 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   MPL_TRY(mpl_ensure(c, c->nmap, sizeof(int32_t) * (nnb_dense + 1)));
   MPL_TRY(mpl_ensure(c, c->ccoord, sizeof(int4) * ncb_dense));
   MPL_TRY(mpl_ensure(c, c->ncoord, sizeof(int4) * nnb_dense));
-  MPL_TRY(mpl_ensure(c, c->colour_list, sizeof(int32_t) * 8 * ncb_dense));
   MPL_TRY(mpl_ensure(c, c->c_nbr_node, sizeof(int32_t) * 8 * ncb_dense));
   MPL_TRY(mpl_ensure(c, c->n_nbr_cell, sizeof(int32_t) * 8 * nnb_dense));
   MPL_TRY(mpl_ensure(c, c->pcell, sizeof(int32_t) * (np + 1)));
@@ -437,8 +486,7 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   int32_t* scan_n = scan_c + ncb_dense + 1;
   MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->cflag), scan_c, ncb_dense, &ds->n_cblk));
   MPL_LAUNCH(c, k_compact_cells, (ncb_dense + TPB - 1) / TPB, TPB, P<int32_t>(c->cflag), scan_c,
-             P<int32_t>(c->cmap), P<int4>(c->ccoord), P<int32_t>(c->nflag),
-             P<int32_t>(c->colour_list), ds->colour_count, g, ncb_dense);
+             P<int32_t>(c->cmap), P<int4>(c->ccoord), P<int32_t>(c->nflag), g, ncb_dense);
   MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->nflag), scan_n, nnb_dense, &ds->n_nblk));
   MPL_LAUNCH(c, k_compact_nodes, (nnb_dense + TPB - 1) / TPB, TPB, P<int32_t>(c->nflag), scan_n,
              P<int32_t>(c->nmap), P<int4>(c->ncoord), g, nnb_dense);
@@ -447,8 +495,6 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
     return mpl_fail(c, MPL_ERR_DOMAIN, "a particle stencil leaves the grid (or x is not finite)");
   c->n_cblk = c->hscal.n_cblk;
   c->n_nblk = c->hscal.n_nblk;
-  c->colour_offset[0] = 0;
-  for (int k = 0; k < 8; ++k) c->colour_count[k] = c->hscal.colour_count[k];
   const int mx = std::max(c->n_cblk, c->n_nblk);
   MPL_LAUNCH(c, k_neighbours, (mx + TPB - 1) / TPB, TPB, P<int4>(c->ccoord), P<int4>(c->ncoord),
              P<int32_t>(c->cmap), P<int32_t>(c->nmap), P<int32_t>(c->c_nbr_node),
@@ -482,29 +528,23 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
              P<int32_t>(c->bin_fill), P<int32_t>(c->sorted), np);
   MPL_LAUNCH(c, k_sort_bins, (nbins + TPB - 1) / TPB, TPB, bstart, P<int32_t>(c->sorted), nbins);
 
-  // P2C: zero accumulators, 8 colour passes
-  MPL_HIP(c, hipMemsetAsync(c->mc.p, 0, 8 * ncell, c->stream));
-  MPL_HIP(c, hipMemsetAsync(c->qc.p, 0, 8 * 3 * ncell, c->stream));
-  MPL_HIP(c, hipMemsetAsync(c->Gc.p, 0, 8 * 9 * ncell, c->stream));
-  MPL_HIP(c, hipMemsetAsync(c->Vk.p, 0, 8 * K * ncell, c->stream));
-  MPL_HIP(c, hipMemsetAsync(c->Tk.p, 0, 8 * 6 * K * ncell, c->stream));
-  for (int col = 0; col < 8; ++col) {
-    const int cnt = c->colour_count[col];
-    const int32_t* list = P<int32_t>(c->colour_list) + (size_t)col * ncb_dense;
-#define MPL_P2C(KK)                                                                              \
-  MPL_LAUNCH(c, k_p2c<KK>, cnt, 64, parts, g, P<int32_t>(c->sorted), P<int32_t>(c->pkey), bstart, list, \
-             P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc),          \
-             P<double>(c->Gc), P<double>(c->Vk), P<double>(c->Tk), ncell, &ds->err)
-    switch (K) {
-      case 1: MPL_P2C(1); break;
-      case 2: MPL_P2C(2); break;
-      case 3: MPL_P2C(3); break;
-      default: MPL_P2C(4); break;
-    }
-#undef MPL_P2C
+  // P2C: one pass over all active blocks (own centres + staged halos), then
+  // the combine / normalise pass
+  MPL_TRY(mpl_ensure(c, c->p2c_halo, sizeof(double) * (13 + 7 * K) * (size_t)c->n_cblk * MPL_BC + 64));
+#define MPL_P2C(KK)                                                                                     \
+  MPL_LAUNCH(c, k_p2c<KK>, c->n_cblk, 64, parts, g, P<int32_t>(c->sorted), P<int32_t>(c->pkey), bstart, \
+             P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), \
+             P<double>(c->Vk), P<double>(c->Tk), ncell, P<double>(c->p2c_halo), &ds->err);             \
+  MPL_LAUNCH(c, k_p2c_combine<KK>, c->n_cblk, 64, P<int>(c->c_nbr_node), P<int>(c->n_nbr_cell),         \
+             c->n_cblk, P<double>(c->p2c_halo), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc),   \
+             P<double>(c->Vk), P<double>(c->Tk), ncell, &ds->n_active_cells, &ds->err)
+  switch (K) {
+    case 1: MPL_P2C(1); break;
+    case 2: MPL_P2C(2); break;
+    case 3: MPL_P2C(3); break;
+    default: MPL_P2C(4); break;
   }
-  MPL_LAUNCH(c, k_normalise, (int)((ncell + TPB - 1) / TPB), TPB, P<double>(c->mc), P<double>(c->qc),
-             P<double>(c->Gc), P<double>(c->Vk), P<double>(c->Tk), ncell, K, &ds->n_active_cells);
+#undef MPL_P2C
   MPL_TRY(mpl_ensure(c, c->cmask, sizeof(uint64_t) * (c->n_cblk + 1)));
   MPL_TRY(mpl_ensure(c, c->ccnt, sizeof(int32_t) * (c->n_cblk + 1)));
   MPL_TRY(mpl_ensure(c, c->coff, sizeof(int32_t) * (c->n_cblk + 1)));

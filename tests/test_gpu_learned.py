@@ -143,3 +143,33 @@ def test_collect_pairs_and_train():
     print(f"[learned] losses first {losses[:5]} last {losses[-5:]}", flush=True)
     assert np.all(np.isfinite(losses))
     assert losses[-20:].mean() < 0.9 * losses[:20].mean()
+
+
+def test_online_training_leaves_the_solve_unchanged():
+    """Online training runs between CG iterations without touching them: the
+    Newton solution is bitwise the one of a solve without training, the
+    network's weights change, and the losses are finite."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=44)
+    parts = mpmlite.particles_to_device(sc.particles)
+    out = []
+    for online in (False, True):
+        ctx = gpu_context(sc, 0, pcg_check_every=4)
+        w0 = U.init_params(seed=9, scale=0.3).astype(np.float32)
+        ctx.precond_set_weights(w0)
+        if online:
+            ctx.precond_online(every=4, steps=2, lr=1e-3)
+        ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        n, loss, ref = ctx.precond_online_stats()
+        print(f"[learned] online={online} stats {st['pcg_iters']} pcg, train steps {n}, "
+              f"loss {loss:.4f} jacobi {ref:.4f}", flush=True)
+        if online:
+            assert n > 0 and np.isfinite(loss) and np.isfinite(ref)
+            assert not np.array_equal(ctx.precond_get_weights(), w0)
+        else:
+            assert n == 0
+        out.append((host(v), st["pcg_iters"]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]

@@ -260,19 +260,31 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int 
 }
 
 // db[o] += sum_u dy[u, o] (one workgroup per output channel, fixed order).
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int ldy,
-                                                   int64_t nvox, float* __restrict__ gb) {
+// Bias gradient sum_v dy[v, o] in two passes: per chunk of voxels one
+// partial per channel (threads of a workgroup read consecutive channels of
+// the same voxels), then a fixed-order sum over the chunks.
+__global__ __launch_bounds__(256) void k_bias_partial(const uint16_t* __restrict__ dy, int ldy,
+                                                      int64_t nvox, int co, int64_t chunk,
+                                                      float* __restrict__ part) {
   __shared__ float sh[256];
-  const int o = blockIdx.x;
+  const int t = threadIdx.x, c = t % co, v0 = t / co, step = 256 / co;
+  const int64_t beg = (int64_t)blockIdx.x * chunk, end = beg + chunk < nvox ? beg + chunk : nvox;
   float s = 0.f;
-  for (int64_t v = threadIdx.x; v < nvox; v += 256) s += bf2f(dy[v * ldy + o]);
-  sh[threadIdx.x] = s;
+  for (int64_t v = beg + v0; v < end; v += step) s += bf2f(dy[v * ldy + c]);
+  sh[t] = s;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
+  if (t < co) {
+    float acc = 0.f;
+    for (int k = 0; k < step; ++k) acc += sh[t + k * co];
+    part[(int64_t)blockIdx.x * co + t] = acc;
   }
-  if (threadIdx.x == 0) gb[o] += sh[0];
+}
+__global__ void k_bias_reduce(const float* __restrict__ part, int nch, int co, float* __restrict__ gb) {
+  const int c = threadIdx.x;
+  if (c >= co) return;
+  float acc = 0.f;
+  for (int k = 0; k < nch; ++k) acc += part[(int64_t)k * co + c];
+  gb[c] += acc;
 }
 
 // g <- g * (y > 0) over C channels of strided views.
@@ -537,7 +549,8 @@ static mpl_status nn_buffers(mpl_ctx* c, NNState& nn, const int* dims, bool trai
       const int64_t nv = s.up ? V[s.level_in] : V[s.level_out];
       const int64_t chunks = (nv + NN_WGRAD_CHUNK - 1) / NN_WGRAD_CHUNK;
       const size_t jobs = (size_t)taps_of(s) * (s.ci / 16) * (s.co / 16);
-      worst = std::max(worst, (size_t)chunks * jobs * 256);
+      const size_t bias = (size_t)((V[s.level_out] + 4095) / 4096) * s.co;
+      worst = std::max(worst, (size_t)chunks * jobs * 256 + bias);
     }
     MPL_TRY(mpl_ensure(c, nn.wpart, 4 * worst + 256));
     MPL_TRY(mpl_ensure(c, nn.lpart, 8 * 2 * 1024 + 64));
@@ -680,7 +693,13 @@ mpl_status nn_backward(mpl_ctx* c, NNState& nn) {
                          s.up ? 0 : s.p, s.up, NN_WGRAD_CHUNK, part);
       MPL_HIP(c, hipGetLastError());
       MPL_LAUNCH(c, k_wgrad_reduce, (jobs * 256 + 255) / 256, 256, part, chunks, jobs, s.ci, s.co, gW);
-      MPL_LAUNCH(c, k_bias_grad, s.co, 256, gout.p, gout.ld, nvo, gb);
+      {
+        const int64_t chunk = 4096;
+        const int nch = (int)((nvo + chunk - 1) / chunk);
+        float* bpart = part + (size_t)chunks * jobs * 256;  // after the weight-gradient partials
+        MPL_LAUNCH(c, k_bias_partial, nch, 256, gout.p, gout.ld, nvo, s.co, chunk, bpart);
+        MPL_LAUNCH(c, k_bias_reduce, 1, 128, bpart, nch, s.co, gb);
+      }
     }
     if (l == 0) break;  // no gradient w.r.t. the network input
     // gradient w.r.t. the layer input; the down layers' input is a skip
@@ -857,14 +876,29 @@ __global__ __launch_bounds__(64) void k_dref_partial(const double* __restrict__ 
     part[2 * nb + 1] = n;
   }
 }
-__global__ void k_dref_final(const double* __restrict__ part, int n, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(1024) void k_dref_final(const double* __restrict__ part, int n,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[2][16];
+  const int t = threadIdx.x;
   double s = 0.0, m = 0.0;
-  for (int i = 0; i < n; ++i) {
+  for (int i = t; i < n; i += 1024) {
     s += part[2 * i];
     m += part[2 * i + 1];
   }
-  out[0] = m > 0.0 ? s / m : 1.0;
+  s = wave_sum(s);
+  m = wave_sum(m);
+  if ((t & 63) == 0) {
+    sh[0][t >> 6] = s;
+    sh[1][t >> 6] = m;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double S = 0.0, M = 0.0;
+  for (int w = 0; w < 16; ++w) {
+    S += sh[0][w];
+    M += sh[1][w];
+  }
+  out[0] = M > 0.0 ? S / M : 1.0;
 }
 
 struct Box3 {
@@ -998,7 +1032,7 @@ mpl_status nn_set_dref(mpl_ctx* c, const double* Dinv) {
   MPL_TRY(mpl_ensure(c, nn.dref, 64));
   MPL_LAUNCH(c, k_dref_partial, c->n_nblk, 64, Dinv, P<uint8_t>(c->flags), (int64_t)c->nnode_alloc(),
              P<double>(nn.tmp));
-  MPL_LAUNCH(c, k_dref_final, 1, 1, P<double>(nn.tmp), c->n_nblk, P<double>(nn.dref));
+  MPL_LAUNCH(c, k_dref_final, 1, 1024, P<double>(nn.tmp), c->n_nblk, P<double>(nn.dref));
   return MPL_OK;
 }
 

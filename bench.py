@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
+                    help="start each Newton iteration's CG from the previous step's direction")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,
@@ -114,7 +116,7 @@ def main():
     prec = mpmlite.F32 if args.precision == "f32" else mpmlite.F64
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
-                                    pcg_check_every=16, time_kernels=1))
+                                    pcg_check_every=16, time_kernels=1, warm_start=args.warm_start))
     parts = mpmlite.particles_to_device(sc.particles)
     print(f"[bench] {workload_name(sc)}", file=sys.stderr, flush=True)
     step_idx = 0

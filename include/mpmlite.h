@@ -89,6 +89,9 @@ typedef struct {
   double armijo_c;        /* sufficient-decrease constant */
   int32_t pcg_check_every;/* host polls the device convergence flag every k iterations */
   int32_t time_kernels;   /* 1: time every Hessian-vector product with HIP events */
+  int32_t warm_start;     /* 1: start the CG of Newton iteration j from the direction that
+                             iteration j of the previous solve of this context found (the
+                             tolerance stays relative to |b|); 0: start from zero */
 } mpl_solver_opts;
 
 typedef struct {

@@ -220,6 +220,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "hv_precision must be MPL_F32 or MPL_F64");
   if (o->precond != MPL_PRECOND_JACOBI && o->precond != MPL_PRECOND_LEARNED)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->warm_start != 0 && o->warm_start != 1)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "warm_start must be 0 or 1");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
       o->max_ls < 0 || !(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "solver options out of range");
@@ -230,7 +232,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.9.1 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.10 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -282,7 +284,8 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo};
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->warm[0], &c->warm[1],
+                   &c->warm[2], &c->warm[3], &c->warm_x0};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

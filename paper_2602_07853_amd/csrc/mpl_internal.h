@@ -128,6 +128,11 @@ struct mpl_ctx {
   DevBuf ozt, ohz, ogr, opieces;
   // single-reduction CG: u = Dinv r and s = running H p (tangent precision)
   DevBuf cg_u, cg_s, cg_dx;
+  // warm start: the CG solution of Newton iteration j of the previous solve
+  // (dense node layout, FP64), and its block-layout copy for the next solve
+  static constexpr int kWarm = 4;
+  DevBuf warm[kWarm], warm_x0;
+  bool warm_valid[kWarm] = {false, false, false, false};
   bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop
 
   // learned preconditioner (allocated on first use)
@@ -180,7 +185,7 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v_block, bool want_grad, d
 mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v_block, int precision);
 mpl_status mpl_stage_hv(mpl_ctx* c, const void* u_block, void* Hu_block, int precision, bool dot);
 mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b_block, double* x_block, int* iters,
-                         double* rel);
+                         double* rel, const double* x0_block = nullptr);
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st);
 mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* r_block, double* z_block);
 mpl_status mpl_stage_load(mpl_ctx* c, const double* v_block, const mpl_particles* in,

@@ -899,6 +899,68 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
   }
 }
 
+// Warm start: u = x0 in the tangent's precision (free nodes), for the
+// product H x0 that gives the initial residual.
+template <class T>
+__global__ void k_cg_prep(const double* __restrict__ x0, const uint8_t* __restrict__ flags, int64_t nnode,
+                          T* __restrict__ u) {
+  const int64_t ni = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ni >= nnode) return;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  for (int a = 0; a < 3; ++a) u[a * nnode + ni] = fr ? (T)x0[a * nnode + ni] : T(0);
+}
+
+// Warm-start variant of k_cg_init: x = x0, r = b - H x0 (the product's
+// pieces and u = x0 given), then as k_cg_init; the b.b partial stays the
+// tolerance reference.
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__ b,
+                                                      const double* __restrict__ x0,
+                                                      const T* __restrict__ Hown, const T* __restrict__ Hhalo,
+                                                      const int* __restrict__ n_nbr_cell, int64_t ncell,
+                                                      const T* __restrict__ Dinv, const T* __restrict__ mi,
+                                                      const uint8_t* __restrict__ flags, int64_t nnode,
+                                                      int n_nblk, double* __restrict__ x, T* __restrict__ dx,
+                                                      double* __restrict__ r, T* __restrict__ u,
+                                                      T* __restrict__ p, T* __restrict__ sv,
+                                                      double* __restrict__ pg, double* __restrict__ pbb,
+                                                      double* __restrict__ pmu, SolverScalars* __restrict__ s) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s->done = 0;
+  double g = 0.0, bb = 0.0, mu = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const T m = mi[ni];
+    T h[3] = {T(0), T(0), T(0)};
+    if (fr) gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const double bv = fr ? b[i] : 0.0;
+      const double rv = fr ? bv - (double)(h[a] + m * u[i]) : 0.0;
+      const T uv = (T)(rv * (double)Dinv[i]);
+      x[i] = fr ? x0[i] : 0.0;
+      dx[i] = T(0);
+      r[i] = rv;
+      u[i] = uv;
+      p[i] = T(0);
+      sv[i] = T(0);
+      g += rv * (double)uv;
+      bb += bv * bv;
+      mu += (double)m * (double)uv * (double)uv;
+    }
+  }
+  g = block4_sum(g, sh);
+  bb = block4_sum(bb, sh);
+  mu = block4_sum(mu, sh);
+  if (threadIdx.x == 0) {
+    pg[blockIdx.x] = g;
+    pbb[blockIdx.x] = bb;
+    pmu[blockIdx.x] = mu;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restrict__ p, T* __restrict__ sv,
                                                  const T* __restrict__ Hown, const T* __restrict__ Hhalo,
@@ -1620,7 +1682,7 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
 template <class T>
 static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
                            const std::function<mpl_status(int)>* hook = nullptr,
-                           bool hook_reads_x = false) {
+                           bool hook_reads_x = false, const double* x0 = nullptr) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(ensure_partials(c));
   MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
@@ -1646,8 +1708,16 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     T* dx = P<T>(c->cg_dx);
     const int nflush = (int)((3 * nnode + 255) / 256);
     const int ngrp = (c->n_cblk + 3) / 4;
-    MPL_LAUNCH(c, k_cg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode,
-               c->n_nblk, x, dx, P<double>(c->r), u, p, sv, pa, pb, pm, s);
+    if (x0) {
+      MPL_LAUNCH(c, k_cg_prep<T>, (int)((nnode + 255) / 256), 256, x0, P<uint8_t>(c->flags), nnode, u);
+      MPL_TRY(hv_pieces<T>(c, u, false));
+      MPL_LAUNCH(c, k_cg_init_warm<T>, nwg, 256, b, x0, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+                 P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
+                 u, p, sv, pa, pb, pm, s);
+    } else {
+      MPL_LAUNCH(c, k_cg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode,
+                 c->n_nblk, x, dx, P<double>(c->r), u, p, sv, pa, pb, pm, s);
+    }
     MPL_TRY(hv_pieces<T>(c, u, true));
     MPL_LAUNCH(c, k_reduce_cg<true>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
     MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
@@ -1941,7 +2011,8 @@ mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* rin, double* z) {
   return MPL_OK;
 }
 
-mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel) {
+mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
+                         const double* x0) {
   if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "PCG before tangent");
   // online training of the network at the first chunk boundary and then
   // every online_every iterations
@@ -1957,8 +2028,10 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
     if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel, h);
     return pcg_learned<double>(c, b, x, iters, rel, h);
   }
-  if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel, h);
-  return pcg_impl<double>(c, b, x, iters, rel, h);
+  // (a warm start applies to the single-reduction Jacobi loop)
+  if (!c->cg_single) x0 = nullptr;
+  if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel, h, false, x0);
+  return pcg_impl<double>(c, b, x, iters, rel, h, false, x0);
 }
 
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
@@ -2005,7 +2078,22 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       else MPL_TRY(collect_pairs<double>(c, P<double>(c->dir), &iters));
       MPL_HIP(c, hipMemcpyAsync(c->x.p, c->xstar.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
     } else {
-      MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel));
+      const double* x0 = nullptr;
+      const bool warm = c->opts.warm_start && it < mpl_ctx::kWarm;
+      if (warm && c->warm_valid[it]) {
+        MPL_TRY(mpl_ensure(c, c->warm_x0, 8 * 3 * nnode));
+        MPL_TRY(mpl_dense_to_block_nodes(c, c->warm[it].p, c->warm_x0.p, 3, 0));
+        x0 = P<double>(c->warm_x0);
+      }
+      MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel, x0));
+      if (warm) {
+        const int64_t ndense = (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
+        MPL_TRY(mpl_ensure(c, c->warm[it], 8 * 3 * ndense));
+        // nodes outside this solve's active blocks start the next one from 0
+        MPL_HIP(c, hipMemsetAsync(c->warm[it].p, 0, 8 * 3 * ndense, c->stream));
+        MPL_TRY(mpl_block_to_dense_nodes(c, c->x.p, c->warm[it].p, 3, 0));
+        c->warm_valid[it] = true;
+      }
     }
     pcg_total += iters;
     // g . x for the Armijo test

@@ -48,7 +48,7 @@ class _Opts(C.Structure):
     _fields_ = [("hv_precision", C.c_int32), ("precond", C.c_int32), ("newton_rtol", C.c_double),
                 ("pcg_rtol", C.c_double), ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
                 ("max_ls", C.c_int32), ("armijo_c", C.c_double), ("pcg_check_every", C.c_int32),
-                ("time_kernels", C.c_int32)]
+                ("time_kernels", C.c_int32), ("warm_start", C.c_int32)]
 
 
 class _Particles(C.Structure):
@@ -139,7 +139,7 @@ def particles_to_device(parts: dict, device="cuda") -> dict:
 def default_opts(**kw) -> dict:
     o = dict(hv_precision=F32, precond=PRECOND_JACOBI, newton_rtol=1e-6, pcg_rtol=1e-6,
              max_newton=50, max_pcg=20000, max_ls=40, armijo_c=1e-4, pcg_check_every=16,
-             time_kernels=0)
+             time_kernels=0, warm_start=0)
     o.update(kw)
     return o
 
@@ -176,7 +176,7 @@ class Context:
         return _Opts(int(o["hv_precision"]), int(o["precond"]), float(o["newton_rtol"]),
                      float(o["pcg_rtol"]), int(o["max_newton"]), int(o["max_pcg"]),
                      int(o["max_ls"]), float(o["armijo_c"]), int(o["pcg_check_every"]),
-                     int(o["time_kernels"]))
+                     int(o["time_kernels"]), int(o["warm_start"]))
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -268,3 +268,30 @@ def test_classic_two_reduction_cg_matches(monkeypatch):
     assert s0["g_norm"] <= 1e-12 * s0["g0_norm"] and s1["g_norm"] <= 1e-12 * s1["g0_norm"]
     assert rel(v0, v1) <= 1e-10
     assert abs(s0["pcg_iters"] - s1["pcg_iters"]) <= max(3, s1["pcg_iters"] // 20)
+
+
+def test_warm_start_same_minimiser_fewer_iterations():
+    """Starting each Newton iteration's CG from the previous step's direction
+    (warm_start=1) reaches the same minimisers to 1e-10 over two steps of a
+    plastic scene with a moving plate, with no more CG iterations."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=scenes.FIXED_COROTATED, E=7e6, strain=0.0,
+                            plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, seed=32,
+                            vel_std=0.05, gravity=(0.0, 0.0, 0.0))
+    sc.bcs.append(dict(kind=scenes.BC_MOVING_BOX, lo=(-1.0, 9 * sc.dx, -1.0), hi=(2.0, 2.0, 2.0),
+                       velocity=(0.0, -0.5, 0.0)))
+    res = {}
+    for warm in (0, 1):
+        ctx = gpu_context(sc, 0, newton_rtol=1e-12, pcg_rtol=1e-8, warm_start=warm)
+        dp = mpmlite.particles_to_device(sc.particles)
+        its = []
+        for k in range(3):
+            st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, k * sc.dt)
+            its.append(st["pcg_iters"])
+        res[warm] = ({key: host(v) for key, v in dp.items()}, its)
+        print(f"[parity] warm_start={warm} pcg per step {its}", flush=True)
+    (p0, i0), (p1, i1) = res[0], res[1]
+    for key in ("x", "v", "G", "F"):
+        assert rel(p1[key], p0[key]) <= 1e-10, key
+    assert i1[0] == i0[0]          # nothing to start from in the first step
+    assert sum(i1[1:]) <= sum(i0[1:])

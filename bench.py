@@ -147,6 +147,7 @@ def main():
         cells, nodes = st["active_cells"], st["active_nodes"]
         hv_bytes, tan_entries = st["hv_model_bytes"], st["tangent_entries"]
         print(f"[bench] step {k} newton {st['newton_iters']} pcg {st['pcg_iters']} "
+              f"({'/'.join(str(x) for x in st['pcg_per_newton'][:st['newton_iters']])}) "
               f"ls {st['ls_halvings']} g {st['g_norm']:.3e}/{st['g0_norm']:.3e} "
               f"ms unload {st['ms_unload']:.1f} newton {st['ms_newton']:.1f} load {st['ms_load']:.1f}",
               file=sys.stderr, flush=True)

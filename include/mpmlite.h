@@ -119,6 +119,7 @@ typedef struct {
   double hv_model_bytes;  /* algorithmic bytes of one Hv: tangent_entries values per
                              tangent-carrying cell + 2 x 3 values (u read, Hu written) per
                              active node, in the tangent's precision */
+  int32_t pcg_per_newton[8]; /* CG iterations of Newton iterations 0..7 */
 } mpl_stats;
 
 typedef struct mpl_ctx mpl_ctx;

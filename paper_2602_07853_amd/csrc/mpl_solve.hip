@@ -2056,6 +2056,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   const double g0 = std::sqrt(gn2);
   double gn = g0;
   int pcg_total = 0, ls_total = 0, it = 0;
+  int per_newton[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   mpl_status result = MPL_OK;
   c->hv_ms_total = 0.0;
   c->hv_calls = 0;
@@ -2096,6 +2097,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       }
     }
     pcg_total += iters;
+    if (it < 8) per_newton[it] = iters;
     // g . x for the Armijo test
     MPL_LAUNCH(c, k_axpy_dot, c->n_nblk, 64, v, P<double>(c->x), 0.0, P<double>(c->g),
                P<uint8_t>(c->flags), nnode, P<double>(c->vt), partial_slot(c, 3));
@@ -2140,6 +2142,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     st->hv_ms_total = c->hv_ms_total;
     st->hv_calls = c->hv_calls;
     st->fallbacks = c->fallbacks_total;
+    for (int k = 0; k < 8; ++k) st->pcg_per_newton[k] = per_newton[k];
   }
   c->solved = (result == MPL_OK);
   return result;

@@ -70,10 +70,18 @@ class _Stats(C.Structure):
                 ("hv_ms_total", C.c_double), ("hv_calls", C.c_int32), ("ms_unload", C.c_double),
                 ("ms_reconstruct", C.c_double), ("ms_newton", C.c_double), ("ms_load", C.c_double),
                 ("domain_events", C.c_int32), ("tangent_entries", C.c_int32),
-                ("hv_model_bytes", C.c_double)]
+                ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8)]
 
 
 _lib = None
+
+
+def _stats_dict(st) -> dict:
+    out = {}
+    for k, _ in _Stats._fields_:
+        v = getattr(st, k)
+        out[k] = list(v) if k == "pcg_per_newton" else v
+    return out
 
 
 def library():
@@ -205,7 +213,7 @@ class Context:
         rc = self._lib.mpl_step(self._ctx, C.byref(pi), C.byref(po), C.c_double(dt),
                                 (C.c_double * 3)(*gravity), _bcs(list(bcs)), len(bcs),
                                 C.c_double(time), C.byref(st))
-        stats = {k: getattr(st, k) for k, _ in _Stats._fields_}
+        stats = _stats_dict(st)
         self._check(rc, "mpl_step")
         return stats
 
@@ -256,7 +264,7 @@ class Context:
         v = self._node_vec()
         st = _Stats()
         rc = self._lib.mpl_solve(self._ctx, C.c_void_p(v.data_ptr()), C.byref(st))
-        stats = {k: getattr(st, k) for k, _ in _Stats._fields_}
+        stats = _stats_dict(st)
         self._check(rc, "mpl_solve")
         return v, stats
 

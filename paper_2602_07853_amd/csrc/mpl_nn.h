@@ -20,11 +20,14 @@ struct NNState {
   // solver once its iteration has converged or fallen back to Jacobi)
   const int32_t* skip = nullptr;
   size_t sw_fwd_off[NN_LAYERS] = {}, sw_bwd_off[NN_LAYERS] = {};
+  // 3x3x3 layers: weights for the LDS-tiled kernel (forward, data gradient)
+  size_t sw3_fwd_off[NN_LAYERS] = {}, sw3_bwd_off[NN_LAYERS] = {};
   int box[3] = {0, 0, 0};
   size_t t_in = 0, t_out = 0, t_cat[3] = {0, 0, 0}, t_lay[NN_LAYERS] = {};
   size_t act_elems = 0;
   int64_t adam_t = 0;
   bool ready = false;
+  bool lds_conv = true;  // 3x3x3 layers on the LDS-tiled kernel (MPL_NN_DIRECT_CONV=1: direct kernel)
 };
 
 int64_t nn_param_count();

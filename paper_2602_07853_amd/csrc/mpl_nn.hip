@@ -16,6 +16,7 @@
 // 16-byte load; B is 8 consecutive channels of one voxel (16 bytes); each
 // lane of D holds 4 consecutive output channels of one voxel.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -121,6 +122,129 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, in
       *reinterpret_cast<uint2*>(dst) = packed;
     }
   }
+}
+
+// ---------------------------------------------------------------- LDS-tiled 3x3x3 conv
+// 3x3x3 stride-1 pad-1 convolution (forward, and the data gradient with the
+// flipped-tap weights).  A workgroup (4 wavefronts) computes a 4 (x) x 4 (y)
+// x 16 (z) output tile for all CT*16 output channels: wavefront w owns
+// x = x0 + w and the four 16-voxel z-strips y0..y0+3.  The input tile with
+// its one-voxel halo (6 x 6 x 18 voxels) is staged in LDS 16 channels at a
+// time, so every input value is read from memory once per workgroup and
+// chunk instead of once per tap; an MFMA K step covers two taps x the 16
+// channels of the chunk (14 steps per chunk, the last one half empty).
+// Wsw: [chunk][kstep 0..13][CT][64 lanes][8] (swizzle modes 3 and 4).
+template <int CT>
+__global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ x, int ldx, Dims3 d,
+                                                   int Ci, const uint16_t* __restrict__ Wsw, int CTT,
+                                                   const float* __restrict__ bias,
+                                                   uint16_t* __restrict__ y, int ldy, int relu,
+                                                   int accum, const int32_t* __restrict__ skip) {
+  // blockIdx.y selects output channels [16 CT y, 16 CT (y + 1)) of the CTT*16
+  if (skip && *skip) return;
+  constexpr int HX = 6, HY = 6, HZ = 18, NV = HX * HY * HZ;
+  __shared__ uint4 tile[NV * 2];  // [voxel][two halves of 8 channels]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nbx = (d.x + 3) >> 2, nby = (d.y + 3) >> 2;
+  int b = blockIdx.x;
+  const int bz = b / (nbx * nby);
+  b -= bz * nbx * nby;
+  const int by = b / nbx, bx = b - by * nbx;
+  const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+  const int j = lane & 15, g = lane >> 4;
+  f32x4 acc[4][CT];
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[st][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = Ci >> 4;
+  for (int q = 0; q < nchunk; ++q) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NV * 2; idx += 256) {
+      const int h = idx & 1, vv = idx >> 1;
+      const int hz = vv % HZ, hy = (vv / HZ) % HY, hx = vv / (HZ * HY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.x && gy < d.y && gz < d.z)
+        val = *reinterpret_cast<const uint4*>(x + (((int64_t)gx * d.y + gy) * d.z + gz) * ldx + q * 16 + h * 8);
+      tile[idx] = val;
+    }
+    __syncthreads();
+    const uint16_t* Wq = Wsw + (int64_t)q * 14 * CTT * 512;
+    const int ct0 = blockIdx.y * CT;
+    for (int m = 0; m < 14; ++m) {
+      const int tap = 2 * m + (g >> 1);
+      bf16x8 aop[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        aop[c] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(Wq + ((m * CTT + ct0 + c) * 64 + lane) * 8));
+      const bool tv = tap < 27;
+      const int tx = tv ? tap / 9 : 0, ty = tv ? (tap / 3) % 3 : 0, tz = tv ? tap % 3 : 0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int hv = ((w + tx) * HY + (st + ty)) * HZ + (j + tz);
+        const uint4 raw = tv ? tile[hv * 2 + (g & 1)] : make_uint4(0, 0, 0, 0);
+        const bf16x8 bop = __builtin_bit_cast(bf16x8, raw);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          acc[st][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[c], bop, acc[st][c], 0, 0, 0);
+      }
+    }
+  }
+  const int ox = x0 + w, oz = z0 + j;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int oy = y0 + st;
+    if (ox >= d.x || oy >= d.y || oz >= d.z) continue;
+    const int64_t v = ((int64_t)ox * d.y + oy) * d.z + oz;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int o0 = (blockIdx.y * CT + c) * 16 + g * 4;
+      uint16_t* dst = y + v * ldy + o0;
+      float r[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float val = acc[st][c][e] + (bias ? bias[o0 + e] : 0.f);
+        if (accum) val += bf2f(dst[e]);
+        if (relu) val = fmaxf(val, 0.f);
+        r[e] = val;
+      }
+      const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                      (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+      *reinterpret_cast<uint2*>(dst) = packed;
+    }
+  }
+}
+
+// Weights of k_conv3_lds: out[((q*14 + m)*CT + ct)*64 + lane][e] with
+// tap = 2m + (lane>>4 >> 1), input channel 16q + ((lane>>4) & 1)*8 + e and
+// output channel 16ct + (lane & 15);
+//   mode 3 (forward): W[tap][in][out];  mode 4 (data gradient): the input is
+//   the forward output: W[26 - tap][out][in].
+__global__ void k_swizzle3(const float* __restrict__ W, int Ci, int Co, int mode, int CT, int nchunk,
+                           uint16_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nchunk * 14 * CT * 512;
+  if (idx >= total) return;
+  int64_t r = idx;
+  const int e = (int)(r % 8);
+  r /= 8;
+  const int lane = (int)(r % 64);
+  r /= 64;
+  const int ct = (int)(r % CT);
+  r /= CT;
+  const int m = (int)(r % 14);
+  const int q = (int)(r / 14);
+  const int gg = lane >> 4;
+  const int tap = 2 * m + (gg >> 1);
+  const int cin = 16 * q + (gg & 1) * 8 + e, cout = 16 * ct + (lane & 15);
+  float val = 0.f;
+  if (tap < 27) {
+    if (mode == 3) val = W[((int64_t)tap * Ci + cin) * Co + cout];
+    else val = W[((int64_t)(26 - tap) * Ci + cout) * Co + cin];
+  }
+  out[idx] = f2bf(val);
 }
 
 // ---------------------------------------------------------------- up conv
@@ -468,6 +592,13 @@ static mpl_status nn_alloc(mpl_ctx* c, NNState& nn) {
     sw += kf * 64 * 8;
     nn.sw_bwd_off[l] = sw;
     sw += kb * 64 * 8;
+    if (s.k == 3 && !s.up) {
+      const size_t k3 = (size_t)(s.ci / 16) * 14 * (s.co / 16) * 512;
+      nn.sw3_fwd_off[l] = sw;
+      sw += k3;
+      nn.sw3_bwd_off[l] = sw;
+      sw += k3;
+    }
   }
   MPL_TRY(mpl_ensure(c, nn.wsw, 2 * sw + 256));
   return MPL_OK;
@@ -496,6 +627,13 @@ static mpl_status nn_refresh(mpl_ctx* c, NNState& nn) {
       const int64_t tot = (int64_t)nk * CT * 512;
       MPL_LAUNCH(c, k_swizzle, (int)((tot + 255) / 256), 256, W, T, s.ci, s.co, 0, 0, nk, CT,
                  sw + nn.sw_fwd_off[l]);
+      if (s.k == 3) {
+        const int64_t n3 = (int64_t)(s.ci / 16) * 14 * (s.co / 16) * 512;
+        MPL_LAUNCH(c, k_swizzle3, (int)((n3 + 255) / 256), 256, W, s.ci, s.co, 3, s.co / 16, s.ci / 16,
+                   sw + nn.sw3_fwd_off[l]);
+        MPL_LAUNCH(c, k_swizzle3, (int)((n3 + 255) / 256), 256, W, s.ci, s.co, 4, s.ci / 16, s.co / 16,
+                   sw + nn.sw3_bwd_off[l]);
+      }
       if (s.k == 2) {
         // dgrad of a stride-2 down conv is an up-type layer with A[m=i][k=(t,o)], K per tap
         const int nkb = (s.co + 31) / 32, CTb = s.ci / 16;
@@ -617,6 +755,33 @@ static mpl_status launch_conv(mpl_ctx* c, View in, Dims3 din, const uint16_t* ws
   return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
 }
 template <int CT>
+static mpl_status launch_conv3_ct(mpl_ctx* c, View in, Dims3 d, const uint16_t* wsw, int Ci, int CTT,
+                                  const float* bias, View out, int relu, int accum, const int32_t* skip) {
+  const int64_t nwg = (int64_t)((d.x + 3) / 4) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
+  hipLaunchKernelGGL((k_conv3_lds<CT>), dim3((unsigned)nwg, CTT / CT), dim3(256), 0, c->stream, in.p,
+                     in.ld, d, Ci, wsw, CTT, bias, out.p, out.ld, relu, accum, skip);
+  MPL_HIP(c, hipGetLastError());
+  return MPL_OK;
+}
+// 3x3x3 stride-1 convolution with Ci input and Co output channels (multiples
+// of 16).  Small grids split the output channels over workgroups (at most
+// two 16-channel tiles each) so that the coarse levels still fill the GPU.
+static mpl_status launch_conv3(mpl_ctx* c, View in, Dims3 d, const uint16_t* wsw, int Ci, int Co,
+                               const float* bias, View out, int relu, int accum,
+                               const int32_t* skip = nullptr) {
+  const int CTT = Co / 16;
+  const int64_t nwg = (int64_t)((d.x + 3) / 4) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
+  int CT = CTT;
+  while (CT > 2 && nwg * (CTT / CT) < 4096) CT /= 2;
+  switch (CT) {
+    case 1: return launch_conv3_ct<1>(c, in, d, wsw, Ci, CTT, bias, out, relu, accum, skip);
+    case 2: return launch_conv3_ct<2>(c, in, d, wsw, Ci, CTT, bias, out, relu, accum, skip);
+    case 4: return launch_conv3_ct<4>(c, in, d, wsw, Ci, CTT, bias, out, relu, accum, skip);
+    case 8: return launch_conv3_ct<8>(c, in, d, wsw, Ci, CTT, bias, out, relu, accum, skip);
+  }
+  return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
+}
+template <int CT>
 static mpl_status launch_up_ct(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk,
                                const float* bias, View out, int relu, int accum, const int32_t* skip) {
   constexpr int VT = (CT <= 1) ? 4 : (CT <= 2 ? 2 : 1);
@@ -654,6 +819,8 @@ mpl_status nn_forward(mpl_ctx* c, NNState& nn) {
     if (s.up) {
       MPL_TRY(launch_up(c, in, din, sw + nn.sw_fwd_off[l], (s.ci + 31) / 32, s.co, bias, out, s.relu, 0,
                         nn.skip));
+    } else if (s.k == 3 && nn.lds_conv) {
+      MPL_TRY(launch_conv3(c, in, din, sw + nn.sw3_fwd_off[l], s.ci, s.co, bias, out, s.relu, 0, nn.skip));
     } else {
       MPL_TRY(launch_conv(c, in, din, sw + nn.sw_fwd_off[l], (T * s.ci + 31) / 32, s.ci, s.co, T, s.k,
                           s.s, s.p, bias, out, dout, s.relu, 0, nn.skip));
@@ -712,6 +879,8 @@ mpl_status nn_backward(mpl_ctx* c, NNState& nn) {
     } else if (s.k == 2) {
       MPL_TRY(launch_up(c, gout, dout, sw + nn.sw_bwd_off[l], (s.co + 31) / 32, s.ci, nullptr, gin, 0,
                         accum));
+    } else if (s.k == 3 && nn.lds_conv) {
+      MPL_TRY(launch_conv3(c, gout, dout, sw + nn.sw3_bwd_off[l], s.co, s.ci, nullptr, gin, 0, accum));
     } else {
       MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, s.k,
                           1, s.p, nullptr, gin, din, 0, accum));
@@ -721,7 +890,11 @@ mpl_status nn_backward(mpl_ctx* c, NNState& nn) {
 }
 
 NNState* nn_state(mpl_ctx* c) {
-  if (!c->nn) c->nn = new NNState();
+  if (!c->nn) {
+    c->nn = new NNState();
+    const char* dc = std::getenv("MPL_NN_DIRECT_CONV");
+    c->nn->lds_conv = !(dc && dc[0] == '1');
+  }
   return c->nn;
 }
 
@@ -784,7 +957,7 @@ mpl_status mpl_nn_forward(mpl_ctx* c, const float* x, const int32_t dims[3], flo
   NNState& nn = *c->nn;
   int d[3] = {dims[0], dims[1], dims[2]};
   MPL_TRY(nn_buffers(c, nn, d, false));
-  MPL_HIP(c, hipMemsetAsync(nn.act.p, 0, 2 * nn.act_elems, c->stream));
+  // every layer writes all voxels and channels of its output: no clearing
   MPL_TRY(nn_stage_input_f32(c, nn, x));
   MPL_TRY(nn_forward(c, nn));
   const int64_t n = (int64_t)d[0] * d[1] * d[2] * 16;

@@ -164,9 +164,11 @@ def main():
                 traffic = tj.get("bytes_per_hv")
         except Exception:
             traffic = None
+    copy_gbs = copy_bandwidth()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
+            "achievable_copy_gbs": copy_gbs,
             "bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     learned = None
@@ -244,6 +246,24 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
             "plain_pcg_per_step": round(plain_counts[1], 2),
             "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "
                         "from the workload's initial state, 1 Adam step per 64 CG iterations"}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Read + write GB/s of a plain 1 GiB device-to-device copy (context for the
+    roofline: what a streaming kernel reaches on this GPU)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
 
 
 def network_rate(ctx, sc, reps=5):

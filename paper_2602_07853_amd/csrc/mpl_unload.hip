@@ -158,21 +158,21 @@ __global__ void k_sort_bins(const int32_t* __restrict__ bin_start, int32_t* __re
   }
 }
 
-__device__ __forceinline__ double seg_scan(double v, int seg_start, int lane) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    double y = __shfl_up(v, off, 64);
-    if (lane - off >= seg_start) v += y;
-  }
-  return v;
-}
-
 // Accumulator slots per centre: 0 mass, 1-3 momentum, 4-12 mass-weighted G,
 // then per material k: 13+7k volume, 14+7k..19+7k V*tau (xx,yy,zz,xy,yz,xz).
+//
+// One lane per cell of the block: at step i every lane takes the i-th
+// particle of its own cell (bins are sorted by particle index) and adds its
+// weighted values to the 8 centres of the cell in a 5x5x5 LDS tile, corner
+// by corner.  For one corner offset the 64 cells of a block reach 64
+// distinct tile slots, so the read-modify-write of one instruction never
+// collides between lanes; LDS operations of a wave complete in issue order,
+// and a compiler barrier between corners keeps that order in the code.  A
+// lane with no particle at step i adds zeros.  Each slot thus sums its
+// contributions in a fixed order (step, then corner), independent of timing.
 template <int K>
 __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
                                             const int32_t* __restrict__ sorted,
-                                            const int32_t* __restrict__ pkey,
                                             const int32_t* __restrict__ bin_start,
                                             const int4* __restrict__ ccoord,
                                             const int32_t* __restrict__ cmap,
@@ -189,70 +189,67 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
     tile[v][lane] = 0.0;
     tile[v][lane + 64] = 0.0;
   }
+  const int s = bin_start[cb * MPL_BC + lane], e = bin_start[cb * MPL_BC + lane + 1];
+  int nmax = e - s;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) nmax = max(nmax, __shfl_xor(nmax, off, 64));
+  const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
+  const int t0 = (lx * 5 + ly) * 5 + lz;
   __syncthreads();
-  const int s = bin_start[cb * MPL_BC], e = bin_start[cb * MPL_BC + MPL_BC];
-  for (int base = s; base < e; base += 64) {
-    const int idx = base + lane;
-    const bool valid = idx < e;
-    const int p = valid ? sorted[idx] : 0;
-    const int lb = valid ? (pkey[p] - cb * MPL_BC) : (64 + lane);
+  for (int i = 0; i < nmax; ++i) {
+    const bool valid = s + i < e;
     double f[3], xp[3], vp[3], Gp[9], tau[6] = {0, 0, 0, 0, 0, 0}, mp = 0.0, Vp = 0.0;
     int k = 0;
     if (valid) {
+      const int p = sorted[s + i];
       for (int a = 0; a < 3; ++a) {
         xp[a] = P.x[3 * p + a];
         vp[a] = P.v[3 * p + a];
         double xi = (xp[a] - g.origin[a]) / g.dx - 0.5;
         f[a] = xi - floor(xi);
       }
-      for (int i = 0; i < 9; ++i) Gp[i] = P.G[9 * p + i];
+      for (int j = 0; j < 9; ++j) Gp[j] = P.G[9 * p + j];
       mp = P.m[p];
       Vp = P.V[p];
       k = P.mat[p];
       double F[9];
-      for (int i = 0; i < 9; ++i) F[i] = P.F[9 * p + i];
+      for (int j = 0; j < 9; ++j) F[j] = P.F[9 * p + j];
       if (k < 0 || k >= K || !kirchhoff(c_mats[k], F, tau)) {
         atomicOr(err, 2);
-        for (int i = 0; i < 6; ++i) tau[i] = 0.0;
+        for (int j = 0; j < 6; ++j) tau[j] = 0.0;
         if (k < 0 || k >= K) k = 0;
       }
     } else {
       for (int a = 0; a < 3; ++a) f[a] = xp[a] = vp[a] = 0.0;
-      for (int i = 0; i < 9; ++i) Gp[i] = 0.0;
+      for (int j = 0; j < 9; ++j) Gp[j] = 0.0;
     }
-    const int prev = __shfl_up(lb, 1, 64);
-    const bool head = (lane == 0) || (prev != lb);
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long below = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const int seg_start = 63 - __clzll(hm & below);
-    const int next = __shfl_down(lb, 1, 64);
-    const bool tail = (lane == 63) || (next != lb);
-    const int lx = lb >> 4, ly = (lb >> 2) & 3, lz = lb & 3;  // valid lanes only
+    double* const mat_slot = &tile[13 + 7 * k][0];
+#pragma unroll
     for (int d = 0; d < 8; ++d) {
       const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
       const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
-      const int t = ((lx + dx) * 5 + (ly + dy)) * 5 + (lz + dz);
+      const int t = t0 + (dx * 5 + dy) * 5 + dz;
       double rc[3];
       rc[0] = g.origin[0] + ((bc.x * 4 + lx + dx) + 0.5) * g.dx - xp[0];
       rc[1] = g.origin[1] + ((bc.y * 4 + ly + dy) + 0.5) * g.dx - xp[1];
       rc[2] = g.origin[2] + ((bc.z * 4 + lz + dz) + 0.5) * g.dx - xp[2];
       const double wm = valid ? w * mp : 0.0;
       const double wV = valid ? w * Vp : 0.0;
+      double val[20];
+      val[0] = wm;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        double val;
-        if (v == 0) val = wm;
-        else if (v < 4) {
-          int a = v - 1;
-          val = wm * (vp[a] + (Gp[a * 3] * rc[0] + Gp[a * 3 + 1] * rc[1] + Gp[a * 3 + 2] * rc[2]));
-        } else if (v < 13) val = wm * Gp[v - 4];
-        else {
-          int kk = (v - 13) / 7, j = (v - 13) % 7;
-          val = (kk == k) ? (j == 0 ? wV : wV * tau[j - 1]) : 0.0;
-        }
-        val = seg_scan(val, seg_start, lane);
-        if (tail && valid) tile[v][t] += val;
-      }
+      for (int a = 0; a < 3; ++a)
+        val[1 + a] = wm * (vp[a] + (Gp[a * 3] * rc[0] + Gp[a * 3 + 1] * rc[1] + Gp[a * 3 + 2] * rc[2]));
+#pragma unroll
+      for (int j = 0; j < 9; ++j) val[4 + j] = wm * Gp[j];
+      val[13] = wV;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) val[14 + j] = wV * tau[j];
+#pragma unroll
+      for (int v = 0; v < 13; ++v) tile[v][t] += val[v];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) mat_slot[j * 128 + t] += val[13 + j];
+      __asm__ __volatile__("" ::: "memory");
     }
   }
   __syncthreads();
@@ -532,7 +529,7 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   // the combine / normalise pass
   MPL_TRY(mpl_ensure(c, c->p2c_halo, sizeof(double) * (13 + 7 * K) * (size_t)c->n_cblk * MPL_BC + 64));
 #define MPL_P2C(KK)                                                                                     \
-  MPL_LAUNCH(c, k_p2c<KK>, c->n_cblk, 64, parts, g, P<int32_t>(c->sorted), P<int32_t>(c->pkey), bstart, \
+  MPL_LAUNCH(c, k_p2c<KK>, c->n_cblk, 64, parts, g, P<int32_t>(c->sorted), bstart, \
              P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), \
              P<double>(c->Vk), P<double>(c->Tk), ncell, P<double>(c->p2c_halo), &ds->err);             \
   MPL_LAUNCH(c, k_p2c_combine<KK>, c->n_cblk, 64, P<int>(c->c_nbr_node), P<int>(c->n_nbr_cell),         \

@@ -51,6 +51,7 @@ struct SolverScalars {
   // flexible CG with the learned preconditioner
   double s2;          // sum over free DOFs of Dinv r^2 (network input scale)
   double rr_mark;     // r.r at the last stagnation checkpoint
+  double alpha_last;  // single-reduction CG: step length of the last completed iteration
   int32_t fallback;   // 1: switched to Jacobi
   int32_t fb_new;     // 1: switched in this iteration (restart the direction)
   int32_t nn_off;     // 1: skip the network (converged or fallen back)

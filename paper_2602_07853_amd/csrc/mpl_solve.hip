@@ -852,8 +852,13 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
 // kernel, the fused product of u (with its u^T K u partials), one reduction.
 // x (FP64) is advanced through an increment dx kept in the tangent's
 // precision for at most CG_FLUSH iterations (x += dx every CG_FLUSH-th
-// iteration and at the end of the solve), which halves the per-iteration
-// traffic of the solution vector.
+// iteration and at the end of the solve), and dx itself only every second
+// iteration: with p_j = u_j + beta_j p_{j-1},
+//   x_{j+1} = x_{j-1} + alpha_{j-1} p_{j-1} + alpha_j p_j,
+// and iteration j (odd) holds both p_{j-1} (the p it reads) and p_j.  After
+// an even iteration the term alpha_j p_j is pending (the flush adds it).
+// u = Dinv r is stored for the product but not read back by the update,
+// which forms it again from r and Dinv (same rounding).
 #define CG_FLUSH 8
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, const T* __restrict__ Dinv,
@@ -975,24 +980,25 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
   if (done_flag(s)) return;
   __shared__ double sh[4];
   const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
-  const double alpha = s->alpha, beta = s->beta;
-  const bool flush = ((s->iters + 1) % CG_FLUSH) == 0;
+  const double alpha = s->alpha, beta = s->beta, alpha_last = s->alpha_last;
+  const int it = s->iters;
+  const bool odd = (it & 1) != 0;
+  const bool flush = ((it + 1) % CG_FLUSH) == 0;  // odd iterations only (CG_FLUSH even)
   double g = 0.0, rr = 0.0, mu = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     if (flags[ni] & MPL_NODE_FREE) {
       // all loads of the node first (three components), then the arithmetic
       // and the stores, so that every load is in flight at once
-      T uv[3], pv[3], svv[3], dv[3], dxv[3];
+      T pv[3], svv[3], dv[3], dxv[3] = {T(0), T(0), T(0)};
       double xv[3] = {0.0, 0.0, 0.0}, rv[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
-        uv[a] = u[i];
         pv[a] = p[i];
         svv[a] = sv[i];
         dv[a] = Dinv[i];
-        dxv[a] = dx[i];
+        if (odd) dxv[a] = dx[i];
         if (flush) xv[a] = x[i];
         rv[a] = r[i];
       }
@@ -1002,18 +1008,22 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
-        const T w = h[a] + m * uv[a];  // (H u)_i
-        const T pn = (T)((double)uv[a] + beta * (double)pv[a]);
+        const T uv = (T)(rv[a] * (double)dv[a]);  // u_j = Dinv r_j as stored for the product
+        const T w = h[a] + m * uv;                // (H u)_i
+        const T pn = (T)((double)uv + beta * (double)pv[a]);
         const T sn = (T)((double)w + beta * (double)svv[a]);
         const double rn = rv[a] - alpha * (double)sn;
         const T un = (T)(rn * (double)dv[a]);
         p[i] = pn;
         sv[i] = sn;
-        if (flush) {
-          x[i] = xv[a] + ((double)dxv[a] + alpha * (double)pn);
-          dx[i] = T(0);
-        } else {
-          dx[i] = (T)((double)dxv[a] + alpha * (double)pn);
+        if (odd) {
+          const double inc = (double)dxv[a] + (alpha_last * (double)pv[a] + alpha * (double)pn);
+          if (flush) {
+            x[i] = xv[a] + inc;
+            dx[i] = T(0);
+          } else {
+            dx[i] = (T)inc;
+          }
         }
         r[i] = rn;
         u[i] = un;
@@ -1078,6 +1088,7 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
   }
   const double delta = C + D;
   if (INIT) {
+    s->alpha_last = 0.0;
     s->bnorm2 = B;
     s->rr = B;
     s->rz = A;
@@ -1094,6 +1105,7 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
     }
     return;
   }
+  s->alpha_last = s->alpha;  // the step length the completed iteration used
   s->iters += 1;
   s->rr = B;
   if (!isfinite(B)) {
@@ -1115,14 +1127,19 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
   s->rz = A;
 }
 
-// x += dx, dx = 0 (free nodes)
+// x += dx (+ alpha_last p when the last iteration's term is pending, i.e.
+// an odd number of iterations is complete); dx then carries -alpha_last p so
+// that the next (odd) iteration's paired update stays exact.
 template <class T>
 __global__ __launch_bounds__(256) void k_cg_flush(double* __restrict__ x, T* __restrict__ dx,
-                                                  int64_t n) {
+                                                  const T* __restrict__ p, int64_t nnode, int64_t nused,
+                                                  const SolverScalars* __restrict__ s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  x[i] += (double)dx[i];
-  dx[i] = T(0);
+  if (i >= 3 * nnode || i % nnode >= nused) return;
+  const bool pending = (s->iters & 1) != 0;
+  const double q = pending ? s->alpha_last * (double)p[i] : 0.0;
+  x[i] += (double)dx[i] + q;
+  dx[i] = (T)(-q);
 }
 
 // ---- flexible CG with the learned preconditioner ----
@@ -1741,13 +1758,13 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     std::function<mpl_status(int)> flushed_hook;
     if (hook && hook_reads_x) {
       flushed_hook = [&](int it) -> mpl_status {
-        MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
+        MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, p, nnode, (int64_t)c->n_nblk * MPL_BC, s);
         return (*hook)(it);
       };
     }
     MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration,
                        hook ? (hook_reads_x ? &flushed_hook : hook) : nullptr));
-    MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, 3 * nnode);
+    MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, p, nnode, (int64_t)c->n_nblk * MPL_BC, s);
     if (iters) *iters = c->hscal.iters;
     if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
     if (c->hscal.done == 2 && c->hscal.iters == 0 && c->hscal.bnorm2 > 0.0)

@@ -670,26 +670,35 @@ template <class T>
 __device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* __restrict__ Hhalo,
                                           const int* __restrict__ n_nbr_cell, int64_t ncell,
                                           int nb, int l, T* h) {
-  h[0] = h[1] = h[2] = T(0);
+  // every load is issued unconditionally (absent sources read slot 0 and
+  // add zero), so the eight sources cost one memory round trip
   const int* nbr = n_nbr_cell + nb * 8;
-  int src = nbr[0];
-  if (src >= 0) {
-    const int64_t i = (int64_t)src * MPL_BC + l;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) h[a] += Hown[a * ncell + i];
-  }
   int o[7], slot[7];
   bool need[7];
   halo_sources(l, o, slot, need);
+  T v[8][3];
+  bool use[8];
+  {
+    const int src = nbr[0];
+    use[0] = src >= 0;
+    const int64_t i = use[0] ? (int64_t)src * MPL_BC + l : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[0][a] = Hown[a * ncell + i];
+  }
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    if (!need[k]) continue;
-    src = nbr[o[k]];
-    if (src < 0) continue;
-    const int64_t i = (int64_t)src * MPL_BC + slot[k];
+    const int src = nbr[o[k]];
+    use[k + 1] = need[k] && src >= 0;
+    const int64_t i = use[k + 1] ? (int64_t)src * MPL_BC + slot[k] : 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) h[a] += Hhalo[a * ncell + i];
+    for (int a = 0; a < 3; ++a) v[k + 1][a] = Hhalo[a * ncell + i];
   }
+  h[0] = h[1] = h[2] = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (use[k]) h[a] += v[k][a];
 }
 
 // Stand-alone product: Hu = M u + K u on free nodes.
@@ -987,24 +996,26 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
   double g = 0.0, rr = 0.0, mu = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    if (flags[ni] & MPL_NODE_FREE) {
-      // all loads of the node first (three components), then the arithmetic
-      // and the stores, so that every load is in flight at once
-      T pv[3], svv[3], dv[3], dxv[3] = {T(0), T(0), T(0)};
-      double xv[3] = {0.0, 0.0, 0.0}, rv[3];
+    // all loads of the node (three components, the flag, the gathered
+    // pieces) are issued at once, also on nodes that are not free (their
+    // lines are read by the wave anyway); only free nodes store
+    const bool fr = flags[ni] & MPL_NODE_FREE;
+    T pv[3], svv[3], dv[3], dxv[3] = {T(0), T(0), T(0)};
+    double xv[3] = {0.0, 0.0, 0.0}, rv[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int64_t i = a * nnode + ni;
-        pv[a] = p[i];
-        svv[a] = sv[i];
-        dv[a] = Dinv[i];
-        if (odd) dxv[a] = dx[i];
-        if (flush) xv[a] = x[i];
-        rv[a] = r[i];
-      }
-      const T m = mi[ni];
-      T h[3];
-      gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      pv[a] = p[i];
+      svv[a] = sv[i];
+      dv[a] = Dinv[i];
+      if (odd) dxv[a] = dx[i];
+      if (flush) xv[a] = x[i];
+      rv[a] = r[i];
+    }
+    const T m = mi[ni];
+    T h[3];
+    gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    if (fr) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;

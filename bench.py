@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    ap.add_argument("--check-every", type=int, default=16,
+                    help="CG iterations per graph chunk between convergence polls")
+    ap.add_argument("--time-kernels", type=int, default=2, choices=[0, 1, 2],
+                    help="HIP events around Hv launches: 1 every launch, 2 the middle product of "
+                         "every CG chunk, 0 none (no roofline figure)")
     ap.add_argument("--warm-start", type=int, default=1, choices=[0, 1],
                     help="start each Newton iteration's CG from the previous step's direction")
     ap.add_argument("--learned-steps", type=int, default=2,
@@ -116,7 +121,8 @@ def main():
     prec = mpmlite.F32 if args.precision == "f32" else mpmlite.F64
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
-                                    pcg_check_every=16, time_kernels=1, warm_start=args.warm_start))
+                                    pcg_check_every=args.check_every, time_kernels=args.time_kernels,
+                                    warm_start=args.warm_start))
     parts = mpmlite.particles_to_device(sc.particles)
     print(f"[bench] {workload_name(sc)}", file=sys.stderr, flush=True)
     step_idx = 0

@@ -88,7 +88,10 @@ typedef struct {
   int32_t max_newton, max_pcg, max_ls;
   double armijo_c;        /* sufficient-decrease constant */
   int32_t pcg_check_every;/* host polls the device convergence flag every k iterations */
-  int32_t time_kernels;   /* 1: time every Hessian-vector product with HIP events */
+  int32_t time_kernels;   /* HIP events around Hessian-vector products: 0 none; 1 every launch
+                             (CG chunks then run without graphs); 2 one launch per CG chunk
+                             (the chunk's last iteration runs eagerly, the others replay
+                             from a graph) */
   int32_t warm_start;     /* 1: start the CG of Newton iteration j from the direction that
                              iteration j of the previous solve of this context found (the
                              tolerance stays relative to |b|); 0: start from zero */
@@ -110,8 +113,8 @@ typedef struct {
   int32_t newton_iters, pcg_iters, ls_halvings, fallbacks;
   int32_t active_cells, active_nodes, free_dofs, cell_blocks, node_blocks;
   double g0_norm, g_norm, energy;
-  double hv_ms_total;     /* summed HIP-event time of all Hv launches (time_kernels=1) */
-  int32_t hv_calls;
+  double hv_ms_total;     /* summed HIP-event time of the timed Hv launches (time_kernels 1 or 2) */
+  int32_t hv_calls;       /* number of timed Hv launches */
   double ms_unload, ms_reconstruct, ms_newton, ms_load;  /* host wall clock per stage */
   int32_t domain_events;  /* stretch reconstructions clamped (model range) */
   int32_t tangent_entries;/* stored tangent values read per cell by one Hv: 45 (dense
@@ -120,6 +123,7 @@ typedef struct {
                              tangent-carrying cell + 2 x 3 values (u read, Hu written) per
                              active node, in the tangent's precision */
   int32_t pcg_per_newton[8]; /* CG iterations of Newton iterations 0..7 */
+  int32_t graph_replays;  /* CG chunks launched from captured HIP graphs (0: all eager) */
 } mpl_stats;
 
 typedef struct mpl_ctx mpl_ctx;

@@ -220,6 +220,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "hv_precision must be MPL_F32 or MPL_F64");
   if (o->precond != MPL_PRECOND_JACOBI && o->precond != MPL_PRECOND_LEARNED)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->time_kernels < 0 || o->time_kernels > 2)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "time_kernels must be 0, 1 or 2");
   if (o->warm_start != 0 && o->warm_start != 1)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "warm_start must be 0 or 1");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
@@ -232,7 +234,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.10 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.11 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -295,6 +297,7 @@ void mpl_destroy(mpl_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 

@@ -41,7 +41,7 @@ struct GraphCache {
   hipGraphExec_t exec = nullptr;
   const void* key[24] = {};
   int keyn[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int events = 0;
+  int time_mode = 0;  // opts.time_kernels at capture
 };
 
 // Device-resident solver scalars (one instance per context).
@@ -77,6 +77,10 @@ struct mpl_ctx {
   mpl::MatParams mats[MPL_MAX_MATERIALS];
   mpl_solver_opts opts;
   hipStream_t stream = nullptr;
+  // private non-blocking stream used only to capture CG chunks into graphs
+  // (the caller's stream may be the null stream, which cannot be captured);
+  // the graphs are launched on `stream`
+  hipStream_t cap_stream = nullptr;
   std::string last_error;
 
   // state flags
@@ -143,6 +147,10 @@ struct mpl_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> hv_events;
   int hv_event_used = 0;
+  bool hv_sample = false;  // time_kernels 2: this launch is the chunk's timed product
+  int graph_replays = 0;   // chunks launched from graphs since the solve began
+  int pcg_expect = 0;      // Jacobi CG: iterations run before the first convergence poll
+  int last_pcg[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // previous step's CG count per Newton index
   double hv_ms_total = 0.0;
   int hv_calls = 0;
   int domain_events = 0;

@@ -1578,7 +1578,8 @@ template <> DevBuf& pvec_buf<double>(mpl_ctx* c) { return c->p64; }
 
 // The fused cell-block product: own and halo node pieces of K p (and, with
 // dot, the per-block partial sums of p^T K p), timed with HIP events when
-// time_kernels is set.
+// time_kernels is 1 (every launch) or 2 (the product of every CG chunk's
+// last iteration).
 template <class T>
 static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot, T* out = nullptr) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
@@ -1590,7 +1591,7 @@ static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot, T* out = nullptr) 
   T* Hown = out;
   T* Hhalo = Hown + 3 * ncell;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->opts.time_kernels) {
+  if (c->opts.time_kernels == 1 || (c->opts.time_kernels == 2 && c->hv_sample)) {
     if (c->hv_event_used + 2 > 4096) MPL_TRY(flush_hv_events(c));
     e0 = next_event(c);
     e1 = next_event(c);
@@ -1644,33 +1645,44 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
 // with the iteration count.
 static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[24], const int keyn[8],
                              int check, const std::function<mpl_status()>& launch_iteration,
-                             const std::function<mpl_status(int)>* hook) {
-  bool use_graph = c->graphs_enabled;
+                             const std::function<mpl_status(int)>* hook, int expect = 0) {
+  // Events recorded inside a captured graph cannot be timed, so products are
+  // timed on eager launches: time_kernels 1 runs every iteration eagerly;
+  // time_kernels 2 replays check - 1 iterations from the graph and runs the
+  // chunk's last iteration eagerly with events around its product.
+  const bool sample = c->opts.time_kernels == 2;
+  const int ncap = sample ? check - 1 : check;
+  bool use_graph = c->graphs_enabled && c->opts.time_kernels != 1 && ncap > 0;
   if (use_graph) {
     bool same = gc.exec != nullptr;
     for (int i = 0; i < 24 && same; ++i) same = gc.key[i] == key[i];
     for (int i = 0; i < 8 && same; ++i) same = gc.keyn[i] == keyn[i];
-    if (same && c->opts.time_kernels && gc.events != 2 * check) same = false;
-    if (same && !c->opts.time_kernels && gc.events != 0) same = false;
+    if (same && gc.time_mode != c->opts.time_kernels) same = false;
     if (!same) {
       if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
       if (gc.graph) (void)hipGraphDestroy(gc.graph);
       gc.exec = nullptr;
       gc.graph = nullptr;
-      if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
-      bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      // capture on the private stream (nothing runs while capturing)
+      bool ok = c->cap_stream != nullptr ||
+                hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+      const hipStream_t user = c->stream;
+      if (ok) {
+        c->stream = c->cap_stream;
+        ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      }
       mpl_status lst = MPL_OK;
       if (ok) {
-        for (int k = 0; k < check && lst == MPL_OK; ++k) lst = launch_iteration();
+        for (int k = 0; k < ncap && lst == MPL_OK; ++k) lst = launch_iteration();
         hipGraph_t g = nullptr;
         ok = (hipStreamEndCapture(c->stream, &g) == hipSuccess) && lst == MPL_OK && g != nullptr;
         if (ok) ok = hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0) == hipSuccess;
         if (g && !ok) (void)hipGraphDestroy(g);
         if (ok) gc.graph = g;
       }
+      c->stream = user;
       (void)hipGetLastError();
-      gc.events = ok ? c->hv_event_used : 0;
-      c->hv_event_used = 0;
+      gc.time_mode = c->opts.time_kernels;
       if (!ok) {
         gc.exec = nullptr;
         c->graphs_enabled = false;
@@ -1681,20 +1693,33 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
       }
     }
   }
+  // expect: iterations the solve is expected to take at least; chunks that
+  // end before it are queued without a poll (without a hook only: a chunk
+  // past convergence costs only its no-op launches)
+  if (hook) expect = 0;
   int it = 0;
   for (;;) {
     if (use_graph && it + check <= c->opts.max_pcg) {
       MPL_HIP(c, hipGraphLaunch(gc.exec, c->stream));
-      it += check;
-      MPL_TRY(mpl_sync_scalars(c));
-      if (c->opts.time_kernels) {
-        c->hv_event_used = gc.events;
-        MPL_TRY(flush_hv_events(c));
+      c->graph_replays += 1;
+      if (sample) {
+        c->hv_sample = true;
+        const mpl_status lst = launch_iteration();
+        c->hv_sample = false;
+        MPL_TRY(lst);
       }
+      it += check;
     } else {
-      for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) MPL_TRY(launch_iteration());
-      MPL_TRY(mpl_sync_scalars(c));
+      for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) {
+        c->hv_sample = k == check - 1;
+        const mpl_status lst = launch_iteration();
+        c->hv_sample = false;
+        MPL_TRY(lst);
+      }
     }
+    if (it < expect && it < c->opts.max_pcg) continue;
+    MPL_TRY(mpl_sync_scalars(c));
+    if (c->opts.time_kernels) MPL_TRY(flush_hv_events(c));
     if (c->hscal.done != 0 || it >= c->opts.max_pcg) break;
     if (hook) MPL_TRY((*hook)(it));
   }
@@ -1774,7 +1799,7 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
       };
     }
     MPL_TRY(run_chunks(c, c->pcg_cache[2], key, keyn, check, launch_iteration,
-                       hook ? (hook_reads_x ? &flushed_hook : hook) : nullptr));
+                       hook ? (hook_reads_x ? &flushed_hook : hook) : nullptr, c->pcg_expect));
     MPL_LAUNCH(c, k_cg_flush<T>, nflush, 256, x, dx, p, nnode, (int64_t)c->n_nblk * MPL_BC, s);
     if (iters) *iters = c->hscal.iters;
     if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
@@ -2088,6 +2113,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   mpl_status result = MPL_OK;
   c->hv_ms_total = 0.0;
   c->hv_calls = 0;
+  c->graph_replays = 0;
   c->fallbacks_total = 0;
   for (;; ++it) {
     if (gn == 0.0 || gn <= c->opts.newton_rtol * g0) break;
@@ -2114,7 +2140,13 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
         MPL_TRY(mpl_dense_to_block_nodes(c, c->warm[it].p, c->warm_x0.p, 3, 0));
         x0 = P<double>(c->warm_x0);
       }
-      MPL_TRY(mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel, x0));
+      // three quarters of the previous step's count for this Newton index
+      // are run before the first convergence poll
+      c->pcg_expect = it < 8 ? (3 * c->last_pcg[it]) / 4 : 0;
+      const mpl_status pst = mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel, x0);
+      c->pcg_expect = 0;
+      MPL_TRY(pst);
+      if (it < 8) c->last_pcg[it] = iters;
       if (warm) {
         const int64_t ndense = (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
         MPL_TRY(mpl_ensure(c, c->warm[it], 8 * 3 * ndense));
@@ -2169,6 +2201,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     st->energy = E;
     st->hv_ms_total = c->hv_ms_total;
     st->hv_calls = c->hv_calls;
+    st->graph_replays = c->graph_replays;
     st->fallbacks = c->fallbacks_total;
     for (int k = 0; k < 8; ++k) st->pcg_per_newton[k] = per_newton[k];
   }

@@ -70,7 +70,8 @@ class _Stats(C.Structure):
                 ("hv_ms_total", C.c_double), ("hv_calls", C.c_int32), ("ms_unload", C.c_double),
                 ("ms_reconstruct", C.c_double), ("ms_newton", C.c_double), ("ms_load", C.c_double),
                 ("domain_events", C.c_int32), ("tangent_entries", C.c_int32),
-                ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8)]
+                ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8),
+                ("graph_replays", C.c_int32)]
 
 
 _lib = None

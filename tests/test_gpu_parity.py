@@ -295,3 +295,64 @@ def test_warm_start_same_minimiser_fewer_iterations():
         assert rel(p1[key], p0[key]) <= 1e-10, key
     assert i1[0] == i0[0]          # nothing to start from in the first step
     assert sum(i1[1:]) <= sum(i0[1:])
+
+
+def test_sampled_product_timing_changes_nothing():
+    """time_kernels only adds HIP events around products (1: every launch,
+    2: one per CG chunk): the state after a step is bitwise the same as
+    without events, and mode 2 times one product per chunk of 16."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=scenes.FIXED_COROTATED, E=7e6, strain=0.0,
+                            plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, seed=33,
+                            vel_std=0.05, gravity=(0.0, 0.0, 0.0))
+    res = {}
+    for tk in (0, 1, 2):
+        ctx = gpu_context(sc, 0, newton_rtol=1e-10, pcg_rtol=1e-8, time_kernels=tk, pcg_check_every=16)
+        dp = mpmlite.particles_to_device(sc.particles)
+        st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+        res[tk] = ({key: host(v) for key, v in dp.items()}, st)
+        print(f"[parity] time_kernels={tk} pcg {st['pcg_iters']} timed {st['hv_calls']} "
+              f"ms {st['hv_ms_total']:.3f}", flush=True)
+    for tk in (1, 2):
+        for key in ("x", "v", "G", "F"):
+            assert np.array_equal(res[tk][0][key], res[0][0][key]), (tk, key)
+    st0, st1, st2 = res[0][1], res[1][1], res[2][1]
+    assert st0["hv_calls"] == 0
+    assert st1["hv_calls"] >= st1["pcg_iters"]
+    chunks = sum((k + 15) // 16 for k in st2["pcg_per_newton"][:st2["newton_iters"]])
+    assert 0 < st2["hv_calls"] <= chunks + st2["newton_iters"]
+    assert st2["hv_ms_total"] > 0.0
+
+
+@pytest.mark.parametrize("classic", [False, True])
+def test_graph_replays_match_eager_launches(monkeypatch, classic):
+    """CG chunks replayed from HIP graphs (captured on the library's private
+    stream, launched on the caller's) give bitwise the state that eager
+    launches give, over three steps with a chunk of 4 iterations (dozens of
+    replays with host polls and Newton work between them)."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=scenes.FIXED_COROTATED, E=7e6, strain=0.0,
+                            plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, seed=34,
+                            vel_std=0.05, gravity=(0.0, 0.0, 0.0))
+    if classic:
+        monkeypatch.setenv("MPL_CG_CLASSIC", "1")
+    res = {}
+    for eager in (True, False):
+        if eager:
+            monkeypatch.setenv("MPL_NO_GRAPHS", "1")
+        else:
+            monkeypatch.delenv("MPL_NO_GRAPHS", raising=False)
+        ctx = gpu_context(sc, 0, newton_rtol=1e-10, pcg_rtol=1e-8, pcg_check_every=4,
+                          time_kernels=2, warm_start=1)
+        dp = mpmlite.particles_to_device(sc.particles)
+        its = []
+        for k in range(3):
+            st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, k * sc.dt)
+            its.append(st["pcg_iters"])
+            assert (st["graph_replays"] == 0) == eager
+        res[eager] = ({key: host(v) for key, v in dp.items()}, its)
+        print(f"[parity] classic={classic} eager={eager} pcg per step {its} "
+              f"replays {st['graph_replays']}", flush=True)
+    assert res[True][1] == res[False][1]
+    for key in ("x", "v", "G", "F"):
+        assert np.array_equal(res[True][0][key], res[False][0][key]), key

@@ -255,8 +255,8 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->dx = grid->dx;
   c->inv_dx = 1.0 / grid->dx;
   c->stream = (hipStream_t)hip_stream;
-  const char* ng = std::getenv("MPL_NO_GRAPHS");
-  c->graphs_enabled = !(ng && ng[0] == '1');
+  const char* gr = std::getenv("MPL_GRAPHS");
+  c->graphs_enabled = gr && gr[0] == '1';
   const char* dt = std::getenv("MPL_DENSE_TANGENT");
   c->factored_enabled = !(dt && dt[0] == '1');
   const char* cgc = std::getenv("MPL_CG_CLASSIC");
@@ -297,6 +297,8 @@ void mpl_destroy(mpl_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->cap_order)
+    if (e) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }

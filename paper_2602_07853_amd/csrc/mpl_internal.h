@@ -81,6 +81,7 @@ struct mpl_ctx {
   // (the caller's stream may be the null stream, which cannot be captured);
   // the graphs are launched on `stream`
   hipStream_t cap_stream = nullptr;
+  hipEvent_t cap_order[2] = {nullptr, nullptr};  // orders graph launches with `stream`
   std::string last_error;
 
   // state flags
@@ -115,7 +116,7 @@ struct mpl_ctx {
 
   // captured PCG iteration chunks (replayed while the key matches); one
   // cache per iteration kind (Jacobi, learned, single-reduction Jacobi)
-  bool graphs_enabled = true;
+  bool graphs_enabled = false;  // MPL_GRAPHS=1: CG chunks replay from HIP graphs
   GraphCache pcg_cache[3];
   // training-pair collection during Newton solves (0 = off)
   int collect_every = 0;

@@ -1266,7 +1266,10 @@ __global__ __launch_bounds__(256) void k_fpcg_direction(const double* __restrict
     if (fr) learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, jacobi, z);
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const T pv = fr ? (T)(z[a] + beta * (double)p[i]) : T(0);
+      // beta = 0 (first iteration, restart after a fallback) does not read
+      // the previous direction, which may hold anything on the first call
+      const double pold = (beta != 0.0) ? (double)p[i] : 0.0;
+      const T pv = fr ? (T)(z[a] + beta * pold) : T(0);
       p[i] = pv;
       mm += m * (double)pv * (double)pv;
     }
@@ -1666,6 +1669,9 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
       // capture on the private stream (nothing runs while capturing)
       bool ok = c->cap_stream != nullptr ||
                 hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+      for (int i = 0; i < 2 && ok; ++i)
+        ok = c->cap_order[i] != nullptr ||
+             hipEventCreateWithFlags(&c->cap_order[i], hipEventDisableTiming) == hipSuccess;
       const hipStream_t user = c->stream;
       if (ok) {
         c->stream = c->cap_stream;
@@ -1700,7 +1706,13 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
   int it = 0;
   for (;;) {
     if (use_graph && it + check <= c->opts.max_pcg) {
-      MPL_HIP(c, hipGraphLaunch(gc.exec, c->stream));
+      // the replay runs on the private stream, ordered after everything
+      // queued on the caller's stream and before everything queued after it
+      MPL_HIP(c, hipEventRecord(c->cap_order[0], c->stream));
+      MPL_HIP(c, hipStreamWaitEvent(c->cap_stream, c->cap_order[0], 0));
+      MPL_HIP(c, hipGraphLaunch(gc.exec, c->cap_stream));
+      MPL_HIP(c, hipEventRecord(c->cap_order[1], c->cap_stream));
+      MPL_HIP(c, hipStreamWaitEvent(c->stream, c->cap_order[1], 0));
       c->graph_replays += 1;
       if (sample) {
         c->hv_sample = true;

@@ -1,11 +1,13 @@
-"""GPU parity at the benchmark's full size and launch configuration: the
-128^3 stiff plastic workload (~1.06M active cells, 7.95M particles), FP32
-factored tangent and Hessian-vector product, FP64 elsewhere, against the
-FP64 oracle on the same seeded inputs.  Every stage whose oracle finishes in
-seconds at this size is compared on all outputs: unload fields, stretch
-reconstruction, energy and gradient at vhat, Hessian-vector products (GPU
-tangent + product against the oracle's tangent + product), and Load of an
-oracle-side node velocity field."""
+"""GPU parity at full size and in the launch configuration the benchmark
+times, against the FP64 oracle on the same seeded inputs:
+- the 128^3 stiff plastic workload (~1.06M active cells, 7.95M particles,
+  one material: FP32 factored tangent and Hessian-vector product);
+- the 256^3 mixed scene (3.2M occupied cells, 25.5M particles, three
+  materials including Drucker-Prager sand: the dense FP32 tangent).
+FP64 elsewhere.  Every stage whose oracle finishes in seconds at this size is
+compared on all outputs: unload fields, stretch reconstruction, energy and
+gradient at vhat, Hessian-vector products (GPU tangent + product against the
+oracle's tangent + product), and Load of an oracle-side node velocity field."""
 import numpy as np
 import pytest
 
@@ -22,10 +24,10 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module")
-def full():
+@pytest.fixture(scope="module", params=["config3", "config5"])
+def full(request):
     from paper_2602_07853_amd import mpmlite
-    sc = scenes.config3()
+    sc = getattr(scenes, request.param)()
     print(f"[fullsize] {sc.name}: {sc.n_particles} particles, {sc.occupied_cells} occupied cells", flush=True)
     ref = oracle_state(sc)
     print("[fullsize] oracle unload + reconstruction done", flush=True)
@@ -88,5 +90,6 @@ def test_load_full_size(full):
         e = rel(host(out[k]), po[k])
         print(f"[fullsize] load {k} rel err {e:.2e}", flush=True)
         assert e <= 1e-12, k
-    assert np.abs(po["eps"]).max() > 0  # the von Mises projection was active
+    if sc.name.startswith("config3"):
+        assert np.abs(po["eps"]).max() > 0  # the von Mises projection was active
     assert rel(host(out["plastic"]), po["eps"]) <= 1e-10

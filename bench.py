@@ -139,6 +139,7 @@ def main():
         print(f"[bench] warmup {w} {json.dumps(st)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     hv_ms, hv_calls, newton, pcg, ls = 0.0, 0, 0, 0, 0
+    up_ms, up_calls, up_bytes = 0.0, 0, 0.0
     cells = nodes = 0
     hv_bytes = 0.0
     tan_entries = 0
@@ -147,6 +148,9 @@ def main():
         st = one_step()
         hv_ms += st["hv_ms_total"]
         hv_calls += st["hv_calls"]
+        up_ms += st["upd_ms_total"]
+        up_calls += st["upd_calls"]
+        up_bytes = st["upd_model_bytes"]
         newton += st["newton_iters"]
         pcg += st["pcg_iters"]
         ls += st["ls_halvings"]
@@ -176,6 +180,12 @@ def main():
             "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
             "achievable_copy_gbs": copy_gbs,
             "bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
+    up_avg_ms = up_ms / max(up_calls, 1)
+    up_gbs = up_bytes / (up_avg_ms * 1e-3) / 1e9 if up_calls else 0.0
+    update = {"kernel": "k_cg_step (single-reduction CG update + product-piece gather)", "bound": "hbm",
+              "achieved": round(up_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(up_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": up_bytes,
+              "avg_ms": round(up_avg_ms, 5), "launches": up_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     learned = None
     if args.learned_steps > 0:
@@ -201,6 +211,7 @@ def main():
                    "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
                    "hv_precision": args.precision},
         "roofline": roof,
+        "update_kernel": update,
         "cpu_baseline": base,
         "learned": learned,
     }

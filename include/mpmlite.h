@@ -89,9 +89,9 @@ typedef struct {
   double armijo_c;        /* sufficient-decrease constant */
   int32_t pcg_check_every;/* host polls the device convergence flag every k iterations */
   int32_t time_kernels;   /* HIP events around Hessian-vector products: 0 none; 1 every launch
-                             (CG chunks then run without graphs); 2 one launch per CG chunk
-                             (the chunk's last iteration runs eagerly, the others replay
-                             from a graph) */
+                             (CG chunks then run without graphs); 2 one iteration per CG
+                             chunk, its position rotating from chunk to chunk (with graphs:
+                             the chunk's last iteration, run eagerly) */
   int32_t warm_start;     /* 1: start the CG of Newton iteration j from the direction that
                              iteration j of the previous solve of this context found (the
                              tolerance stays relative to |b|); 0: start from zero */
@@ -124,6 +124,12 @@ typedef struct {
                              active node, in the tangent's precision */
   int32_t pcg_per_newton[8]; /* CG iterations of Newton iterations 0..7 */
   int32_t graph_replays;  /* CG chunks launched from captured HIP graphs (0: all eager) */
+  int32_t upd_calls;      /* timed launches of the single-reduction CG update kernel */
+  double upd_ms_total;    /* their summed HIP-event time (time_kernels 1 or 2) */
+  double upd_model_bytes; /* algorithmic bytes of one update launch: 28 e + 55 per free node
+                             (e = 4 or 8 bytes for the tangent's precision): p, s, Dinv, m,
+                             two product pieces and r read, p, s, u, r written, dx every
+                             second and x every eighth iteration */
 } mpl_stats;
 
 typedef struct mpl_ctx mpl_ctx;

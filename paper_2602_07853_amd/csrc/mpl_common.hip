@@ -297,6 +297,7 @@ void mpl_destroy(mpl_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->cap_order)
     if (e) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

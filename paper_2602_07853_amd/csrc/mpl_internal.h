@@ -149,11 +149,17 @@ struct mpl_ctx {
   std::vector<hipEvent_t> hv_events;
   int hv_event_used = 0;
   bool hv_sample = false;  // time_kernels 2: this launch is the chunk's timed product
+  uint32_t sample_rot = 0; // time_kernels 2: rotates the timed iteration over chunks
   int graph_replays = 0;   // chunks launched from graphs since the solve began
   int pcg_expect = 0;      // Jacobi CG: iterations run before the first convergence poll
   int last_pcg[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // previous step's CG count per Newton index
   double hv_ms_total = 0.0;
   int hv_calls = 0;
+  // the same for the single-reduction CG update kernel
+  std::vector<hipEvent_t> up_events;
+  int up_event_used = 0;
+  double up_ms_total = 0.0;
+  int up_calls = 0;
   int domain_events = 0;
 
   size_t ncell_alloc() const { return (size_t)n_cblk * MPL_BC; }

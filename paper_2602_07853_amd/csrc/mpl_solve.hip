@@ -1550,17 +1550,19 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   return MPL_OK;
 }
 
-static hipEvent_t next_event(mpl_ctx* c) {
-  if (c->hv_event_used >= (int)c->hv_events.size()) {
+static hipEvent_t next_event_in(std::vector<hipEvent_t>& pool, int& used) {
+  if (used >= (int)pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    c->hv_events.push_back(e);
+    pool.push_back(e);
   }
-  return c->hv_events[c->hv_event_used++];
+  return pool[used++];
 }
-
+static hipEvent_t next_event(mpl_ctx* c) { return next_event_in(c->hv_events, c->hv_event_used); }
+// Reads the elapsed times of the recorded event pairs (products and CG
+// updates) into the per-solve totals.
 static mpl_status flush_hv_events(mpl_ctx* c) {
-  if (c->hv_event_used == 0) return MPL_OK;
+  if (c->hv_event_used == 0 && c->up_event_used == 0) return MPL_OK;
   MPL_HIP(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i + 1 < c->hv_event_used; i += 2) {
     float ms = 0.f;
@@ -1568,7 +1570,14 @@ static mpl_status flush_hv_events(mpl_ctx* c) {
     c->hv_ms_total += ms;
     c->hv_calls += 1;
   }
+  for (int i = 0; i + 1 < c->up_event_used; i += 2) {
+    float ms = 0.f;
+    MPL_HIP(c, hipEventElapsedTime(&ms, c->up_events[i], c->up_events[i + 1]));
+    c->up_ms_total += ms;
+    c->up_calls += 1;
+  }
   c->hv_event_used = 0;
+  c->up_event_used = 0;
   return MPL_OK;
 }
 
@@ -1581,8 +1590,8 @@ template <> DevBuf& pvec_buf<double>(mpl_ctx* c) { return c->p64; }
 
 // The fused cell-block product: own and halo node pieces of K p (and, with
 // dot, the per-block partial sums of p^T K p), timed with HIP events when
-// time_kernels is 1 (every launch) or 2 (the product of every CG chunk's
-// last iteration).
+// time_kernels is 1 (every launch) or 2 (one iteration's product per CG
+// chunk).
 template <class T>
 static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot, T* out = nullptr) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
@@ -1722,8 +1731,12 @@ static mpl_status run_chunks(mpl_ctx* c, GraphCache& gc, const void* const key[2
       }
       it += check;
     } else {
+      // the timed iteration's position rotates from chunk to chunk so that
+      // the samples cover the update kernel's iteration-dependent work (dx
+      // every second, x every eighth iteration) evenly
+      const int pos = (int)(c->sample_rot++ % (uint32_t)check);
       for (int k = 0; k < check && it < c->opts.max_pcg; ++k, ++it) {
-        c->hv_sample = k == check - 1;
+        c->hv_sample = k == pos;
         const mpl_status lst = launch_iteration();
         c->hv_sample = false;
         MPL_TRY(lst);
@@ -1788,9 +1801,17 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
     const int check = std::max(1, c->opts.pcg_check_every);
     auto launch_iteration = [&]() -> mpl_status {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c->opts.time_kernels == 1 || (c->opts.time_kernels == 2 && c->hv_sample)) {
+        if (c->up_event_used + 2 > 4096) MPL_TRY(flush_hv_events(c));
+        e0 = next_event_in(c->up_events, c->up_event_used);
+        e1 = next_event_in(c->up_events, c->up_event_used);
+        if (e0) MPL_HIP(c, hipEventRecord(e0, c->stream));
+      }
       MPL_LAUNCH(c, k_cg_step<T>, nwg, 256, u, p, sv, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
                  P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
                  pa, pb, pm, s);
+      if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
       MPL_TRY(hv_pieces<T>(c, u, true));
       MPL_LAUNCH(c, k_reduce_cg<false>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
       return MPL_OK;
@@ -2125,6 +2146,8 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   mpl_status result = MPL_OK;
   c->hv_ms_total = 0.0;
   c->hv_calls = 0;
+  c->up_ms_total = 0.0;
+  c->up_calls = 0;
   c->graph_replays = 0;
   c->fallbacks_total = 0;
   for (;; ++it) {
@@ -2213,6 +2236,15 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     st->energy = E;
     st->hv_ms_total = c->hv_ms_total;
     st->hv_calls = c->hv_calls;
+    st->upd_ms_total = c->up_ms_total;
+    st->upd_calls = c->up_calls;
+    // per free node: reads p, s, Dinv, m and the two product pieces (tangent
+    // precision), r (FP64), the flag byte, dx every second and x every eighth
+    // iteration; writes p, s, u, r, dx every second and x every eighth
+    {
+      const double e = c->tangent_precision == MPL_F32 ? 4.0 : 8.0;
+      st->upd_model_bytes = (28.0 * e + 55.0) * c->hscal.n_free_nodes;
+    }
     st->graph_replays = c->graph_replays;
     st->fallbacks = c->fallbacks_total;
     for (int k = 0; k < 8; ++k) st->pcg_per_newton[k] = per_newton[k];

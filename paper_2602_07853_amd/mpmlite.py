@@ -71,7 +71,8 @@ class _Stats(C.Structure):
                 ("ms_reconstruct", C.c_double), ("ms_newton", C.c_double), ("ms_load", C.c_double),
                 ("domain_events", C.c_int32), ("tangent_entries", C.c_int32),
                 ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8),
-                ("graph_replays", C.c_int32)]
+                ("graph_replays", C.c_int32), ("upd_calls", C.c_int32), ("upd_ms_total", C.c_double),
+                ("upd_model_bytes", C.c_double)]
 
 
 _lib = None

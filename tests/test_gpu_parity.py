@@ -304,6 +304,9 @@ def test_sampled_product_timing_changes_nothing():
     chunks = sum((k + 15) // 16 for k in st2["pcg_per_newton"][:st2["newton_iters"]])
     assert 0 < st2["hv_calls"] <= chunks + st2["newton_iters"]
     assert st2["hv_ms_total"] > 0.0
+    # the CG update kernel is timed on the same sampled iterations
+    assert st0["upd_calls"] == 0 and st2["upd_calls"] > 0 and st2["upd_ms_total"] > 0.0
+    assert st2["upd_model_bytes"] > 0.0
 
 
 @pytest.mark.parametrize("classic", [False, True])

@@ -87,7 +87,11 @@ typedef struct {
   double pcg_rtol;        /* stop CG when |r| <= pcg_rtol * |b| */
   int32_t max_newton, max_pcg, max_ls;
   double armijo_c;        /* sufficient-decrease constant */
-  int32_t pcg_check_every;/* host polls the device convergence flag every k iterations */
+  int32_t pcg_check_every;/* host polls the device convergence flag every k iterations (inside
+                             mpl_step/mpl_solve the first poll of Newton iteration j comes after
+                             3/4 of the previous step's count for j; iterations past convergence
+                             are no-ops on the device). MPL_GRAPHS=1 in the environment at
+                             context creation replays the k iterations from a HIP graph */
   int32_t time_kernels;   /* HIP events around Hessian-vector products: 0 none; 1 every launch
                              (CG chunks then run without graphs); 2 one iteration per CG
                              chunk, its position rotating from chunk to chunk (with graphs:

@@ -1066,26 +1066,33 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
   __shared__ double sh[4][16];
   const int t = threadIdx.x;
   if (!INIT && done_flag(s)) return;
-  double v[4][8];
+  // rounds of 8 loads per array and thread, all 32 in flight at once
+  // (indices clamped into range, out-of-range values replaced by zero)
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nm = n > nd ? n : nd;
+  for (int base = t; base < nm; base += 8192) {
+    double v[4][8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int i = t + 1024 * k;
-    v[0][k] = i < n ? a[i] : 0.0;
-    v[1][k] = i < n ? b[i] : 0.0;
-    v[2][k] = i < n ? c[i] : 0.0;
-    v[3][k] = i < nd ? d[i] : 0.0;
+    for (int k = 0; k < 8; ++k) {
+      const int i = base + 1024 * k;
+      const int ia = min(i, n - 1), id = min(i, nd - 1);
+      v[0][k] = (n > 0) ? a[ia] : 0.0;
+      v[1][k] = (n > 0) ? b[ia] : 0.0;
+      v[2][k] = (n > 0) ? c[ia] : 0.0;
+      v[3][k] = (nd > 0) ? d[id] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = base + 1024 * k;
+      acc[0] += i < n ? v[0][k] : 0.0;
+      acc[1] += i < n ? v[1][k] : 0.0;
+      acc[2] += i < n ? v[2][k] : 0.0;
+      acc[3] += i < nd ? v[3][k] : 0.0;
+    }
   }
-  for (int i = t + 8192; i < n; i += 1024) {
-    v[0][0] += a[i];
-    v[1][0] += b[i];
-    v[2][0] += c[i];
-  }
-  for (int i = t + 8192; i < nd; i += 1024) v[3][0] += d[i];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-#pragma unroll
-    for (int k = 1; k < 8; ++k) v[q][0] += v[q][k];
-    const double w = wave_sum(v[q][0]);
+    const double w = wave_sum(acc[q]);
     if ((t & 63) == 0) sh[q][t >> 6] = w;
   }
   __syncthreads();

@@ -98,7 +98,9 @@ typedef struct {
                              the chunk's last iteration, run eagerly) */
   int32_t warm_start;     /* 1: start the CG of Newton iteration j from the direction that
                              iteration j of the previous solve of this context found (the
-                             tolerance stays relative to |b|); 0: start from zero */
+                             tolerance stays relative to |b|); 2: from the linear extrapolation
+                             2 x_{n-1} - x_{n-2} of the last two solves' directions (1 until two
+                             exist); 0: start from zero */
 } mpl_solver_opts;
 
 typedef struct {

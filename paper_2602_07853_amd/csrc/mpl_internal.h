@@ -139,6 +139,12 @@ struct mpl_ctx {
   static constexpr int kWarm = 4;
   DevBuf warm[kWarm], warm_x0;
   bool warm_valid[kWarm] = {false, false, false, false};
+  // warm_start 2 and 3: the solutions of the solves before that, for a
+  // linear (2 x_{n-1} - x_{n-2}) or quadratic (3 x_{n-1} - 3 x_{n-2} + x_{n-3})
+  // extrapolation
+  DevBuf warm_old[kWarm], warm_old2[kWarm];
+  bool warm_old_valid[kWarm] = {false, false, false, false};
+  bool warm_old2_valid[kWarm] = {false, false, false, false};
   bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop
 
   // learned preconditioner (allocated on first use)

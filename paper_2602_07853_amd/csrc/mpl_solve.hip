@@ -2127,6 +2127,20 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
   return pcg_impl<double>(c, b, x, iters, rel, h, false, x0);
 }
 
+namespace {
+// out = 2 x1 - x2 (dense node arrays; out may be x2)
+__global__ void k_extrapolate(const double* x1, const double* x2, double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = 2.0 * x1[i] - x2[i];
+}
+// x3 = 3 x1 - 3 x2 + x3 (dense node arrays)
+__global__ void k_extrapolate2(const double* __restrict__ x1, const double* __restrict__ x2,
+                               double* __restrict__ x3, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x3[i] = 3.0 * (x1[i] - x2[i]) + x3[i];
+}
+}  // namespace
+
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "solve before reconstruction");
   const int64_t nnode = (int64_t)c->nnode_alloc();
@@ -2179,7 +2193,24 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       const bool warm = c->opts.warm_start && it < mpl_ctx::kWarm;
       if (warm && c->warm_valid[it]) {
         MPL_TRY(mpl_ensure(c, c->warm_x0, 8 * 3 * nnode));
-        MPL_TRY(mpl_dense_to_block_nodes(c, c->warm[it].p, c->warm_x0.p, 3, 0));
+        const int64_t nd3 = 3 * (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
+        if (c->opts.warm_start == 3 && c->warm_old2_valid[it]) {
+          // x0 = 3 x_{n-1} - 3 x_{n-2} + x_{n-3} (dense, in the oldest buffer,
+          // which the solution of this solve replaces)
+          MPL_LAUNCH(c, k_extrapolate2, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
+                     P<double>(c->warm_old[it]), P<double>(c->warm_old2[it]), nd3);
+          MPL_TRY(mpl_dense_to_block_nodes(c, c->warm_old2[it].p, c->warm_x0.p, 3, 0));
+        } else if (c->opts.warm_start >= 2 && c->warm_old_valid[it]) {
+          // x0 = 2 x_{n-1} - x_{n-2} (dense, written to a buffer this solve's
+          // bookkeeping replaces)
+          DevBuf& out = c->opts.warm_start == 3 ? c->warm_old2[it] : c->warm_old[it];
+          MPL_TRY(mpl_ensure(c, out, 8 * nd3));
+          MPL_LAUNCH(c, k_extrapolate, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
+                     P<double>(c->warm_old[it]), P<double>(out), nd3);
+          MPL_TRY(mpl_dense_to_block_nodes(c, out.p, c->warm_x0.p, 3, 0));
+        } else {
+          MPL_TRY(mpl_dense_to_block_nodes(c, c->warm[it].p, c->warm_x0.p, 3, 0));
+        }
         x0 = P<double>(c->warm_x0);
       }
       // three quarters of the previous step's count for this Newton index
@@ -2190,6 +2221,16 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       MPL_TRY(pst);
       if (it < 8) c->last_pcg[it] = iters;
       if (warm) {
+        if (c->opts.warm_start == 3) {
+          // rotate: oldest <- older <- old, and the freed buffer takes x
+          std::swap(c->warm_old2[it], c->warm_old[it]);
+          c->warm_old2_valid[it] = c->warm_old_valid[it];
+          std::swap(c->warm[it], c->warm_old[it]);
+          c->warm_old_valid[it] = c->warm_valid[it];
+        } else if (c->opts.warm_start == 2) {
+          std::swap(c->warm[it], c->warm_old[it]);
+          c->warm_old_valid[it] = c->warm_valid[it];
+        }
         const int64_t ndense = (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
         MPL_TRY(mpl_ensure(c, c->warm[it], 8 * 3 * ndense));
         // nodes outside this solve's active blocks start the next one from 0

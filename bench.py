@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--time-kernels", type=int, default=2, choices=[0, 1, 2],
                     help="HIP events around Hv launches: 1 every launch, 2 the middle product of "
                          "every CG chunk, 0 none (no roofline figure)")
-    ap.add_argument("--warm-start", type=int, default=3, choices=[0, 1, 2, 3],
+    ap.add_argument("--warm-start", type=int, default=4, choices=[0, 1, 2, 3, 4],
                     help="start each Newton iteration's CG from the previous step's direction "
-                         "(2, 3: extrapolated linearly / quadratically from the last steps)")
+                         "(2, 3: extrapolated linearly / quadratically from the last steps; 4: the "
+                         "energy-norm best combination of the last three)")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,

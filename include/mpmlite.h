@@ -100,7 +100,11 @@ typedef struct {
                              iteration j of the previous solve of this context found (the
                              tolerance stays relative to |b|); 2: from the linear extrapolation
                              2 x_{n-1} - x_{n-2} of the last two solves' directions (1 until two
-                             exist); 0: start from zero */
+                             exist); 3: the quadratic one 3 x_{n-1} - 3 x_{n-2} + x_{n-3}; 4: the
+                             combination W c of the last (up to) three that minimises the
+                             energy norm of the error, (W^T H W) c = W^T b with the current
+                             tangent (three extra products and one host synchronisation per
+                             solve); 0: start from zero */
 } mpl_solver_opts;
 
 typedef struct {

@@ -222,8 +222,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->time_kernels < 0 || o->time_kernels > 2)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "time_kernels must be 0, 1 or 2");
-  if (o->warm_start < 0 || o->warm_start > 3)
-    return mpl_fail(c, MPL_ERR_INVALID_ARG, "warm_start must be 0, 1, 2 or 3");
+  if (o->warm_start < 0 || o->warm_start > 4)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "warm_start must be 0, 1, 2, 3 or 4");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
       o->max_ls < 0 || !(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "solver options out of range");
@@ -289,7 +289,8 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->warm[0], &c->warm[1],
                    &c->warm[2], &c->warm[3], &c->warm_x0, &c->warm_old[0], &c->warm_old[1],
                    &c->warm_old[2], &c->warm_old[3], &c->warm_old2[0], &c->warm_old2[1],
-                   &c->warm_old2[2], &c->warm_old2[3]};
+                   &c->warm_old2[2], &c->warm_old2[3], &c->gal_w, &c->gal_u, &c->gal_y,
+                   &c->gal_part};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {

@@ -143,6 +143,7 @@ struct mpl_ctx {
   // linear (2 x_{n-1} - x_{n-2}) or quadratic (3 x_{n-1} - 3 x_{n-2} + x_{n-3})
   // extrapolation
   DevBuf warm_old[kWarm], warm_old2[kWarm];
+  DevBuf gal_w, gal_u, gal_y, gal_part;  // warm_start 4: Galerkin start work space
   bool warm_old_valid[kWarm] = {false, false, false, false};
   bool warm_old2_valid[kWarm] = {false, false, false, false};
   bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop

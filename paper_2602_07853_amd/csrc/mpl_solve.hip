@@ -2133,6 +2133,106 @@ __global__ void k_extrapolate(const double* x1, const double* x2, double* out, i
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = 2.0 * x1[i] - x2[i];
 }
+// Galerkin start: per node block, the partial sums over free nodes of
+// w_k . (H w_l) for k <= l (packed row by row) and then of w_k . b, for up to
+// GAL_MAX vectors (block layout, vector k at w + k * 3 nnode).
+#define GAL_MAX 3
+#define GAL_SUMS (GAL_MAX * (GAL_MAX + 1) / 2 + GAL_MAX)
+template <class T>
+__global__ __launch_bounds__(64) void k_gram(const double* __restrict__ w, const T* __restrict__ y,
+                                             const double* __restrict__ b, const uint8_t* __restrict__ flags,
+                                             int64_t nnode, int nv, int n_nblk, double* __restrict__ part) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const int64_t n3 = 3 * nnode;
+  const int ng = nv * (nv + 1) / 2;
+  double acc[GAL_SUMS];
+#pragma unroll
+  for (int q = 0; q < GAL_SUMS; ++q) acc[q] = 0.0;
+  if (fr) {
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      double wv[GAL_MAX], yv[GAL_MAX];
+#pragma unroll
+      for (int k = 0; k < GAL_MAX; ++k) {
+        wv[k] = k < nv ? w[k * n3 + i] : 0.0;
+        yv[k] = k < nv ? (double)y[k * n3 + i] : 0.0;
+      }
+      const double bv = b[i];
+      int q = 0;
+#pragma unroll
+      for (int k = 0; k < GAL_MAX; ++k)
+#pragma unroll
+        for (int m = k; m < GAL_MAX; ++m) {
+          acc[q] += wv[k] * yv[m];
+          ++q;
+        }
+#pragma unroll
+      for (int k = 0; k < GAL_MAX; ++k) acc[q + k] += wv[k] * bv;
+    }
+  }
+  // store the nv-vector layout: pairs (k <= m < nv) row by row, then w_k . b
+  int q = 0, o = 0;
+#pragma unroll
+  for (int k = 0; k < GAL_MAX; ++k)
+#pragma unroll
+    for (int m = k; m < GAL_MAX; ++m) {
+      const double sum = wave_sum(acc[q]);
+      if (k < nv && m < nv) {
+        if (l == 0) part[(int64_t)o * n_nblk + nb] = sum;
+        ++o;
+      }
+      ++q;
+    }
+#pragma unroll
+  for (int k = 0; k < GAL_MAX; ++k) {
+    const double sum = wave_sum(acc[q + k]);
+    if (k < nv && l == 0) part[(int64_t)(ng + k) * n_nblk + nb] = sum;
+  }
+}
+// fixed-order sums of the nq rows of k_gram partials (one 1024-thread workgroup)
+__global__ __launch_bounds__(1024) void k_gram_reduce(const double* __restrict__ part, int n, int nq,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int t = threadIdx.x;
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int i = t; i < n; i += 1024) v += part[(int64_t)q * n + i];
+    v = wave_sum(v);
+    if ((t & 63) == 0) sh[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double r = 0.0;
+      for (int w = 0; w < 16; ++w) r += sh[w];
+      out[q] = r;
+    }
+    __syncthreads();
+  }
+}
+// u = (T) w (block layout, 3 components)
+template <class T>
+__global__ void k_to_prec(const double* __restrict__ w, T* __restrict__ u, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = (T)w[i];
+}
+struct GalCoef {
+  double c[GAL_MAX];
+};
+// x0 = sum_k c_k w_k on free nodes, 0 elsewhere (block layout)
+__global__ __launch_bounds__(64) void k_lincomb(const double* __restrict__ w, GalCoef cf, int nv,
+                                                const uint8_t* __restrict__ flags, int64_t nnode,
+                                                double* __restrict__ x0) {
+  const int64_t ni = (int64_t)blockIdx.x * MPL_BC + threadIdx.x;
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const int64_t n3 = 3 * nnode;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = a * nnode + ni;
+    double v = 0.0;
+    for (int k = 0; k < nv; ++k) v += cf.c[k] * w[k * n3 + i];
+    x0[i] = fr ? v : 0.0;
+  }
+}
 // x3 = 3 x1 - 3 x2 + x3 (dense node arrays)
 __global__ void k_extrapolate2(const double* __restrict__ x1, const double* __restrict__ x2,
                                double* __restrict__ x3, int64_t n) {
@@ -2140,6 +2240,92 @@ __global__ void k_extrapolate2(const double* __restrict__ x1, const double* __re
   if (i < n) x3[i] = 3.0 * (x1[i] - x2[i]) + x3[i];
 }
 }  // namespace
+
+// warm_start 4: the start x0 = W c that minimises the energy norm of the
+// error over the span W of earlier solutions (the last three of this Newton
+// index, newest first; adding the other indices' solutions was measured to
+// cost iterations), from
+// (W^T H W) c = W^T b with H the current tangent.  A vector whose Cholesky
+// pivot falls below 1e-10 of the largest diagonal entry is left out; *used
+// stays false when no vector is left.
+template <class T>
+static mpl_status galerkin_start(mpl_ctx* c, const DevBuf* const* hist, int nv, const double* b,
+                                 double* x0, bool* used) {
+  *used = false;
+  nv = std::min(nv, GAL_MAX);
+  if (nv <= 0) return MPL_OK;
+  const int64_t nnode = (int64_t)c->nnode_alloc(), n3 = 3 * nnode;
+  const int ng = nv * (nv + 1) / 2, nq = ng + nv;
+  MPL_TRY(mpl_ensure(c, c->gal_w, 8 * (size_t)GAL_MAX * n3));
+  MPL_TRY(mpl_ensure(c, c->gal_u, sizeof(T) * n3));
+  MPL_TRY(mpl_ensure(c, c->gal_y, sizeof(T) * (size_t)GAL_MAX * n3));
+  MPL_TRY(mpl_ensure(c, c->gal_part, 8 * ((size_t)GAL_SUMS * c->n_nblk + GAL_SUMS)));
+  double* w = P<double>(c->gal_w);
+  T* y = P<T>(c->gal_y);
+  for (int k = 0; k < nv; ++k) {
+    MPL_TRY(mpl_dense_to_block_nodes(c, hist[k]->p, w + k * n3, 3, 0));
+    MPL_LAUNCH(c, k_to_prec<T>, (int)((n3 + 255) / 256), 256, (const double*)(w + k * n3), P<T>(c->gal_u), n3);
+    MPL_TRY(mpl_stage_hv(c, c->gal_u.p, y + k * n3, c->tangent_precision, false));
+  }
+  double* part = P<double>(c->gal_part);
+  double* sums = part + (size_t)GAL_SUMS * c->n_nblk;
+  MPL_LAUNCH(c, k_gram<T>, c->n_nblk, 64, (const double*)w, (const T*)y, b, P<uint8_t>(c->flags), nnode, nv,
+             c->n_nblk, part);
+  MPL_LAUNCH(c, k_gram_reduce, 1, 1024, (const double*)part, c->n_nblk, nq, sums);
+  double h[GAL_SUMS];
+  MPL_HIP(c, hipMemcpyAsync(h, sums, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  // G_km from the packed upper triangle (the product is symmetric up to
+  // rounding; the upper entry is used for both)
+  double G[GAL_MAX][GAL_MAX];
+  {
+    int q = 0;
+    for (int k = 0; k < nv; ++k)
+      for (int m = k; m < nv; ++m, ++q) G[k][m] = G[m][k] = h[q];
+  }
+  double dmax = 0.0;
+  for (int k = 0; k < nv; ++k)
+    if (std::isfinite(G[k][k])) dmax = std::max(dmax, G[k][k]);
+  if (!(dmax > 0.0)) return MPL_OK;
+  // Cholesky over the kept vectors, in order
+  int keep[GAL_MAX], m = 0;
+  double L[GAL_MAX][GAL_MAX] = {};
+  for (int k = 0; k < nv; ++k) {
+    double row[GAL_MAX];
+    bool ok = true;
+    for (int j = 0; j < m && ok; ++j) {
+      double v = G[k][keep[j]];
+      for (int t = 0; t < j; ++t) v -= row[t] * L[j][t];
+      row[j] = v / L[j][j];
+      ok = std::isfinite(row[j]);
+    }
+    if (!ok) continue;
+    double d = G[k][k];
+    for (int t = 0; t < m; ++t) d -= row[t] * row[t];
+    if (!(d > 1e-10 * dmax) || !std::isfinite(d)) continue;
+    for (int t = 0; t < m; ++t) L[m][t] = row[t];
+    L[m][m] = std::sqrt(d);
+    keep[m++] = k;
+  }
+  if (m == 0) return MPL_OK;
+  double z[GAL_MAX], cm[GAL_MAX];
+  for (int i = 0; i < m; ++i) {
+    double v = h[ng + keep[i]];
+    for (int t = 0; t < i; ++t) v -= L[i][t] * z[t];
+    z[i] = v / L[i][i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double v = z[i];
+    for (int t = i + 1; t < m; ++t) v -= L[t][i] * cm[t];
+    cm[i] = v / L[i][i];
+  }
+  GalCoef cf;
+  for (int k = 0; k < GAL_MAX; ++k) cf.c[k] = 0.0;
+  for (int i = 0; i < m; ++i) cf.c[keep[i]] = cm[i];
+  MPL_LAUNCH(c, k_lincomb, c->n_nblk, 64, (const double*)w, cf, nv, P<uint8_t>(c->flags), nnode, x0);
+  *used = true;
+  return MPL_OK;
+}
 
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "solve before reconstruction");
@@ -2194,7 +2380,22 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       if (warm && c->warm_valid[it]) {
         MPL_TRY(mpl_ensure(c, c->warm_x0, 8 * 3 * nnode));
         const int64_t nd3 = 3 * (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
-        if (c->opts.warm_start == 3 && c->warm_old2_valid[it]) {
+        bool done_x0 = false;
+        if (c->opts.warm_start == 4) {
+          const DevBuf* hist[GAL_MAX];
+          int nv = 0;
+          hist[nv++] = &c->warm[it];
+          if (c->warm_old_valid[it]) {
+            hist[nv++] = &c->warm_old[it];
+            if (c->warm_old2_valid[it]) hist[nv++] = &c->warm_old2[it];
+          }
+          if (c->tangent_precision == MPL_F32)
+            MPL_TRY(galerkin_start<float>(c, hist, nv, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
+          else
+            MPL_TRY(galerkin_start<double>(c, hist, nv, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
+        }
+        if (done_x0) {
+        } else if (c->opts.warm_start == 3 && c->warm_old2_valid[it]) {
           // x0 = 3 x_{n-1} - 3 x_{n-2} + x_{n-3} (dense, in the oldest buffer,
           // which the solution of this solve replaces)
           MPL_LAUNCH(c, k_extrapolate2, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
@@ -2203,7 +2404,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
         } else if (c->opts.warm_start >= 2 && c->warm_old_valid[it]) {
           // x0 = 2 x_{n-1} - x_{n-2} (dense, written to a buffer this solve's
           // bookkeeping replaces)
-          DevBuf& out = c->opts.warm_start == 3 ? c->warm_old2[it] : c->warm_old[it];
+          DevBuf& out = c->opts.warm_start >= 3 ? c->warm_old2[it] : c->warm_old[it];
           MPL_TRY(mpl_ensure(c, out, 8 * nd3));
           MPL_LAUNCH(c, k_extrapolate, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
                      P<double>(c->warm_old[it]), P<double>(out), nd3);
@@ -2221,7 +2422,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       MPL_TRY(pst);
       if (it < 8) c->last_pcg[it] = iters;
       if (warm) {
-        if (c->opts.warm_start == 3) {
+        if (c->opts.warm_start >= 3) {
           // rotate: oldest <- older <- old, and the freed buffer takes x
           std::swap(c->warm_old2[it], c->warm_old[it]);
           c->warm_old2_valid[it] = c->warm_old_valid[it];

@@ -343,10 +343,11 @@ def test_graph_replays_match_eager_launches(monkeypatch, classic):
         assert np.array_equal(res[True][0][key], res[False][0][key]), key
 
 
-@pytest.mark.parametrize("warm", [2, 3])
+@pytest.mark.parametrize("warm", [2, 3, 4])
 def test_extrapolated_warm_start_same_minimiser(warm):
     """Starting CG from the linear (warm_start=2) or quadratic (3)
-    extrapolation of the last steps' directions reaches the same minimisers
+    extrapolation of the last steps' directions, or from their energy-norm
+    best combination under the current tangent (4), reaches the same minimisers
     to 1e-10 as cold starts over five steps of a plastic scene with a moving
     plate.  The iteration counts are printed: on this small scene with random
     velocities the directions change too much from step to step for a warm

@@ -286,10 +286,8 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->warm[0], &c->warm[1],
-                   &c->warm[2], &c->warm[3], &c->warm_x0, &c->warm_old[0], &c->warm_old[1],
-                   &c->warm_old[2], &c->warm_old[3], &c->warm_old2[0], &c->warm_old2[1],
-                   &c->warm_old2[2], &c->warm_old2[3], &c->gal_w, &c->gal_u, &c->gal_y,
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->wtmp, &c->warm_x0, &c->gal_w,
+                   &c->gal_u, &c->gal_y,
                    &c->gal_part};
   for (DevBuf* b : all) free_buf(*b);
   nn_destroy(c);
@@ -299,6 +297,8 @@ void mpl_destroy(mpl_ctx* c) {
   }
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (auto& ring : c->whist)
+    for (DevBuf& b : ring) free_buf(b);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->cap_order)

@@ -134,18 +134,16 @@ struct mpl_ctx {
   DevBuf ozt, ohz, ogr, opieces;
   // single-reduction CG: u = Dinv r and s = running H p (tangent precision)
   DevBuf cg_u, cg_s, cg_dx;
-  // warm start: the CG solution of Newton iteration j of the previous solve
-  // (dense node layout, FP64), and its block-layout copy for the next solve
+  // warm start: the CG solutions of Newton iteration j of the last solves
+  // (dense node arrays, so that they survive the change of active blocks),
+  // in a ring of kHist per Newton index: whist[j][(whead[j] - k) mod len] is
+  // the k-th newest, wcount[j] of them valid
   static constexpr int kWarm = 4;
-  DevBuf warm[kWarm], warm_x0;
-  bool warm_valid[kWarm] = {false, false, false, false};
-  // warm_start 2 and 3: the solutions of the solves before that, for a
-  // linear (2 x_{n-1} - x_{n-2}) or quadratic (3 x_{n-1} - 3 x_{n-2} + x_{n-3})
-  // extrapolation
-  DevBuf warm_old[kWarm], warm_old2[kWarm];
+  static constexpr int kHist = 3;
+  DevBuf whist[kWarm][kHist], wtmp, warm_x0;
+  int whead[kWarm] = {0, 0, 0, 0}, wcount[kWarm] = {0, 0, 0, 0};
+  int whist_len = 0;  // ring length the current warm_start mode uses
   DevBuf gal_w, gal_u, gal_y, gal_part;  // warm_start 4: Galerkin start work space
-  bool warm_old_valid[kWarm] = {false, false, false, false};
-  bool warm_old2_valid[kWarm] = {false, false, false, false};
   bool cg_single = true;  // MPL_CG_CLASSIC=1 in the environment selects the two-reduction loop
 
   // learned preconditioner (allocated on first use)

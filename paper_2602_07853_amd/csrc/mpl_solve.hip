@@ -2128,8 +2128,9 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
 }
 
 namespace {
-// out = 2 x1 - x2 (dense node arrays; out may be x2)
-__global__ void k_extrapolate(const double* x1, const double* x2, double* out, int64_t n) {
+// out = 2 x1 - x2 (dense node arrays)
+__global__ void k_extrapolate(const double* __restrict__ x1, const double* __restrict__ x2,
+                              double* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = 2.0 * x1[i] - x2[i];
 }
@@ -2137,6 +2138,7 @@ __global__ void k_extrapolate(const double* x1, const double* x2, double* out, i
 // w_k . (H w_l) for k <= l (packed row by row) and then of w_k . b, for up to
 // GAL_MAX vectors (block layout, vector k at w + k * 3 nnode).
 #define GAL_MAX 3
+static_assert(GAL_MAX <= mpl_ctx::kHist, "the Galerkin basis comes from the history ring");
 #define GAL_SUMS (GAL_MAX * (GAL_MAX + 1) / 2 + GAL_MAX)
 template <class T>
 __global__ __launch_bounds__(64) void k_gram(const double* __restrict__ w, const T* __restrict__ y,
@@ -2233,18 +2235,18 @@ __global__ __launch_bounds__(64) void k_lincomb(const double* __restrict__ w, Ga
     x0[i] = fr ? v : 0.0;
   }
 }
-// x3 = 3 x1 - 3 x2 + x3 (dense node arrays)
+// out = 3 x1 - 3 x2 + x3 (dense node arrays)
 __global__ void k_extrapolate2(const double* __restrict__ x1, const double* __restrict__ x2,
-                               double* __restrict__ x3, int64_t n) {
+                               const double* __restrict__ x3, double* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x3[i] = 3.0 * (x1[i] - x2[i]) + x3[i];
+  if (i < n) out[i] = 3.0 * (x1[i] - x2[i]) + x3[i];
 }
 }  // namespace
 
 // warm_start 4: the start x0 = W c that minimises the energy norm of the
-// error over the span W of earlier solutions (the last three of this Newton
-// index, newest first; adding the other indices' solutions was measured to
-// cost iterations), from
+// error over the span W of earlier solutions (the last GAL_MAX of this
+// Newton index, newest first; five instead of three gained nothing, adding
+// the other indices' solutions cost iterations), from
 // (W^T H W) c = W^T b with H the current tangent.  A vector whose Cholesky
 // pivot falls below 1e-10 of the largest diagonal entry is left out; *used
 // stays false when no vector is left.
@@ -2377,40 +2379,46 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     } else {
       const double* x0 = nullptr;
       const bool warm = c->opts.warm_start && it < mpl_ctx::kWarm;
-      if (warm && c->warm_valid[it]) {
+      // ring length of the mode: 1 (previous), 2 (linear), 3 (quadratic),
+      // GAL_MAX (Galerkin); a change of mode starts the histories afresh
+      const int wm = c->opts.warm_start;
+      const int len = wm >= 4 ? GAL_MAX : std::max(wm, 1);
+      if (len != c->whist_len) {
+        for (int j = 0; j < mpl_ctx::kWarm; ++j) c->wcount[j] = c->whead[j] = 0;
+        c->whist_len = len;
+      }
+      const int64_t nd3 = 3 * (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
+      auto hist = [&](int k) -> DevBuf& {  // k-th newest solution of this Newton index
+        return c->whist[it][((c->whead[it] - k) % len + len) % len];
+      };
+      if (warm && c->wcount[it] > 0) {
         MPL_TRY(mpl_ensure(c, c->warm_x0, 8 * 3 * nnode));
-        const int64_t nd3 = 3 * (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
+        const int have = c->wcount[it];
         bool done_x0 = false;
-        if (c->opts.warm_start == 4) {
-          const DevBuf* hist[GAL_MAX];
-          int nv = 0;
-          hist[nv++] = &c->warm[it];
-          if (c->warm_old_valid[it]) {
-            hist[nv++] = &c->warm_old[it];
-            if (c->warm_old2_valid[it]) hist[nv++] = &c->warm_old2[it];
-          }
+        if (wm == 4) {
+          const DevBuf* h[GAL_MAX];
+          for (int k = 0; k < have; ++k) h[k] = &hist(k);
           if (c->tangent_precision == MPL_F32)
-            MPL_TRY(galerkin_start<float>(c, hist, nv, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
+            MPL_TRY(galerkin_start<float>(c, h, have, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
           else
-            MPL_TRY(galerkin_start<double>(c, hist, nv, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
+            MPL_TRY(galerkin_start<double>(c, h, have, P<double>(c->dir), P<double>(c->warm_x0), &done_x0));
         }
-        if (done_x0) {
-        } else if (c->opts.warm_start == 3 && c->warm_old2_valid[it]) {
-          // x0 = 3 x_{n-1} - 3 x_{n-2} + x_{n-3} (dense, in the oldest buffer,
-          // which the solution of this solve replaces)
-          MPL_LAUNCH(c, k_extrapolate2, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
-                     P<double>(c->warm_old[it]), P<double>(c->warm_old2[it]), nd3);
-          MPL_TRY(mpl_dense_to_block_nodes(c, c->warm_old2[it].p, c->warm_x0.p, 3, 0));
-        } else if (c->opts.warm_start >= 2 && c->warm_old_valid[it]) {
-          // x0 = 2 x_{n-1} - x_{n-2} (dense, written to a buffer this solve's
-          // bookkeeping replaces)
-          DevBuf& out = c->opts.warm_start >= 3 ? c->warm_old2[it] : c->warm_old[it];
-          MPL_TRY(mpl_ensure(c, out, 8 * nd3));
-          MPL_LAUNCH(c, k_extrapolate, (int)((nd3 + 255) / 256), 256, P<double>(c->warm[it]),
-                     P<double>(c->warm_old[it]), P<double>(out), nd3);
-          MPL_TRY(mpl_dense_to_block_nodes(c, out.p, c->warm_x0.p, 3, 0));
-        } else {
-          MPL_TRY(mpl_dense_to_block_nodes(c, c->warm[it].p, c->warm_x0.p, 3, 0));
+        if (!done_x0) {
+          // polynomial extrapolation of the newest solutions: constant, linear
+          // (2 x_{n-1} - x_{n-2}) or quadratic (3 x_{n-1} - 3 x_{n-2} + x_{n-3})
+          const int order = std::min(have, std::min(std::max(wm, 1), 3));
+          if (order == 1) {
+            MPL_TRY(mpl_dense_to_block_nodes(c, hist(0).p, c->warm_x0.p, 3, 0));
+          } else {
+            MPL_TRY(mpl_ensure(c, c->wtmp, 8 * nd3));
+            if (order == 2)
+              MPL_LAUNCH(c, k_extrapolate, (int)((nd3 + 255) / 256), 256, P<double>(hist(0)),
+                         P<double>(hist(1)), P<double>(c->wtmp), nd3);
+            else
+              MPL_LAUNCH(c, k_extrapolate2, (int)((nd3 + 255) / 256), 256, P<double>(hist(0)),
+                         P<double>(hist(1)), P<double>(hist(2)), P<double>(c->wtmp), nd3);
+            MPL_TRY(mpl_dense_to_block_nodes(c, c->wtmp.p, c->warm_x0.p, 3, 0));
+          }
         }
         x0 = P<double>(c->warm_x0);
       }
@@ -2422,22 +2430,14 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       MPL_TRY(pst);
       if (it < 8) c->last_pcg[it] = iters;
       if (warm) {
-        if (c->opts.warm_start >= 3) {
-          // rotate: oldest <- older <- old, and the freed buffer takes x
-          std::swap(c->warm_old2[it], c->warm_old[it]);
-          c->warm_old2_valid[it] = c->warm_old_valid[it];
-          std::swap(c->warm[it], c->warm_old[it]);
-          c->warm_old_valid[it] = c->warm_valid[it];
-        } else if (c->opts.warm_start == 2) {
-          std::swap(c->warm[it], c->warm_old[it]);
-          c->warm_old_valid[it] = c->warm_valid[it];
-        }
-        const int64_t ndense = (int64_t)(c->dims[0] + 1) * (c->dims[1] + 1) * (c->dims[2] + 1);
-        MPL_TRY(mpl_ensure(c, c->warm[it], 8 * 3 * ndense));
+        // the solution becomes the newest entry of the ring
+        c->whead[it] = (c->whead[it] + 1) % len;
+        DevBuf& dst = c->whist[it][c->whead[it]];
+        MPL_TRY(mpl_ensure(c, dst, 8 * nd3));
         // nodes outside this solve's active blocks start the next one from 0
-        MPL_HIP(c, hipMemsetAsync(c->warm[it].p, 0, 8 * 3 * ndense, c->stream));
-        MPL_TRY(mpl_block_to_dense_nodes(c, c->x.p, c->warm[it].p, 3, 0));
-        c->warm_valid[it] = true;
+        MPL_HIP(c, hipMemsetAsync(dst.p, 0, 8 * nd3, c->stream));
+        MPL_TRY(mpl_block_to_dense_nodes(c, c->x.p, dst.p, 3, 0));
+        c->wcount[it] = std::min(c->wcount[it] + 1, len);
       }
     }
     pcg_total += iters;

@@ -171,9 +171,10 @@ mpl_status mpl_step(mpl_ctx* ctx, const mpl_particles* in, mpl_particles* out, d
 /* ---- sub-steps (the same kernels mpl_step runs) ---- */
 
 /* Alg. 2 (Sec. 3.1-3.3): bin particles by dual cell, Kirchhoff stress per
- * particle, atomics-free coloured particle->centre scatter of m, mv, mG, V_k,
- * V_k tau_k, normalisation, centre->node gather of m_i and v_i^n, Dirichlet
- * sets and vhat.  Also resets the Newton iterate to vhat. */
+ * particle, atomics-free particle->centre scatter of m, mv, mG, V_k, V_k tau_k
+ * (per-block LDS tiles, halo centres staged and combined in a fixed order),
+ * normalisation, centre->node gather of m_i and v_i^n, Dirichlet sets and
+ * vhat.  Also resets the Newton iterate to vhat. */
 mpl_status mpl_unload(mpl_ctx* ctx, const mpl_particles* in, double dt, const double gravity[3],
                       const mpl_bc* bcs, int32_t n_bcs, double time);
 /* Alg. 3 first loop (Sec. 4.3, App. C): S_{c,k} from tau_{c,k} (FP64). */

@@ -4,12 +4,11 @@
 // Scatter design (no atomics on floating point, deterministic):
 //   * particles are counting-sorted by their base dual cell b = floor(x/dx - 1/2)
 //     (integer atomics only; each bin is then ordered by particle index);
-//   * one wavefront owns one active 4x4x4 cell block and walks the particles
-//     whose base cell lies in it, 64 at a time.  Lanes holding particles of
-//     the same base cell form contiguous runs; a segmented wavefront scan sums
-//     each run's contribution to each of the 8 target centres b + delta, and
-//     the run's last lane adds it into a 5x5x5 centre tile in LDS (distinct
-//     runs hit distinct centres, so the adds never collide);
+//   * one wavefront owns one active 4x4x4 cell block, one lane per cell: at
+//     step i every lane takes the i-th particle of its cell and adds its
+//     weighted values to the 8 target centres b + delta in a 5x5x5 centre
+//     tile in LDS, corner by corner (for one corner the 64 cells reach 64
+//     distinct centres, so the adds of one instruction never collide);
 //   * tiles overlap their +x/+y/+z neighbours by one layer: every block
 //     stores its own 64 centres directly and the 61 centres of its halo into
 //     a per-block staging slot; a second pass (one wave per block) adds to

@@ -62,19 +62,44 @@ __global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t
     f[a] = xi - fb;
   }
   double vp[3] = {0, 0, 0}, Gp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // the 8 block lookups first, then the centre values four corners at a
+  // time, all loads of a batch in flight together; the sums run in corner
+  // order (a corner with zero weight or no block adds nothing)
+  double w[8];
+  int64_t ci[8];
+#pragma unroll
   for (int d = 0; d < 8; ++d) {
     const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
-    const double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
-    if (w == 0.0) continue;
+    w[d] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
     const int cx = b[0] + dx, cy = b[1] + dy, cz = b[2] + dz;
-    const int blk = cmap[((cx >> 2) * g.cbd[1] + (cy >> 2)) * g.cbd[2] + (cz >> 2)];
-    if (blk < 0) {
-      atomicOr(err, 16);
-      continue;
+    // a corner outside the grid (possible with zero weight) has no block
+    const bool inside = cx >= 0 && cy >= 0 && cz >= 0 && cx < g.dims[0] && cy < g.dims[1] && cz < g.dims[2];
+    const int blk = inside ? cmap[((cx >> 2) * g.cbd[1] + (cy >> 2)) * g.cbd[2] + (cz >> 2)] : -1;
+    ci[d] = blk < 0 ? -1 : (int64_t)blk * MPL_BC + local_index(cx & 3, cy & 3, cz & 3);
+  }
+#pragma unroll
+  for (int d = 0; d < 8; ++d)
+    if (w[d] != 0.0 && ci[d] < 0) atomicOr(err, 16);
+#pragma unroll
+  for (int h = 0; h < 8; h += 4) {
+    double vv[4][3], GG[4][9];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t c = ci[h + k] < 0 ? 0 : ci[h + k];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vv[k][a] = vcl[a * ncell + c];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) GG[k][e] = Gcl[e * ncell + c];
     }
-    const int64_t ci = (int64_t)blk * MPL_BC + local_index(cx & 3, cy & 3, cz & 3);
-    for (int a = 0; a < 3; ++a) vp[a] += w * vcl[a * ncell + ci];
-    for (int e = 0; e < 9; ++e) Gp[e] += w * Gcl[e * ncell + ci];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int d = h + k;
+      if (w[d] == 0.0 || ci[d] < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vp[a] += w[d] * vv[k][a];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Gp[e] += w[d] * GG[k][e];
+    }
   }
   double F[9], A[9], Fn[9];
   for (int e = 0; e < 9; ++e) {

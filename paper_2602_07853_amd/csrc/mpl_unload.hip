@@ -385,18 +385,27 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double m = 0.0, q[3] = {0.0, 0.0, 0.0};
+  // corner by corner in a fixed order; every cell's values are loaded up
+  // front (an absent cell reads cell 0 and counts for nothing), so the eight
+  // cells cost one memory round trip
+#pragma unroll
   for (int d = 0; d < 8; ++d) {
-    int ci = node_cell(n_nbr_cell, nb, l, d);
-    if (ci < 0) continue;
-    double mcc = mc[ci];
-    if (mcc == 0.0) continue;
-    double wm = mcc / 8.0;
-    double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
+    const int cv = node_cell(n_nbr_cell, nb, l, d);
+    const int64_t ci = cv < 0 ? 0 : cv;
+    const double mcc = mc[ci];
+    double vcc[3], G[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vcc[a] = vc[a * ncell + ci];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) G[e] = Gc[e * ncell + ci];
+    if (cv < 0 || mcc == 0.0) continue;
+    const double wm = mcc / 8.0;
+    const double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
     m += wm;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-      double aff = Gc[(a * 3) * ncell + ci] * r[0] + Gc[(a * 3 + 1) * ncell + ci] * r[1] +
-                   Gc[(a * 3 + 2) * ncell + ci] * r[2];
-      q[a] += wm * (vc[a * ncell + ci] + aff);
+      const double aff = G[a * 3] * r[0] + G[a * 3 + 1] * r[1] + G[a * 3 + 2] * r[2];
+      q[a] += wm * (vcc[a] + aff);
     }
   }
   double vv[3] = {0.0, 0.0, 0.0};

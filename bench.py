@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    ap.add_argument("--ppc-axis", type=int, default=None,
+                    help="particles per cell along each axis (default: the config's, 2 = 8 PPC)")
     ap.add_argument("--check-every", type=int, default=16,
                     help="CG iterations per graph chunk between convergence polls")
     ap.add_argument("--time-kernels", type=int, default=2, choices=[0, 1, 2],
@@ -56,8 +58,12 @@ def parse():
     return ap.parse_args()
 
 
-def make_scene(cfg):
+def make_scene(cfg, ppc_axis=None):
     from paper_2602_07853_amd import scenes
+    if ppc_axis is not None:
+        if cfg not in (2, 3, 5):
+            raise SystemExit("--ppc-axis applies to configs 2, 3 and 5")
+        return scenes.CONFIGS[cfg](ppc_axis=ppc_axis)
     return scenes.CONFIGS[cfg]()
 
 
@@ -119,7 +125,7 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    sc = make_scene(args.config)
+    sc = make_scene(args.config, args.ppc_axis)
     prec = mpmlite.F32 if args.precision == "f32" else mpmlite.F64
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,

@@ -374,3 +374,23 @@ def test_extrapolated_warm_start_same_minimiser(warm):
         assert rel(p1[key], p0[key]) <= 1e-10, key
     assert i1[0] == i0[0]
     assert sum(i1[1:]) <= 1.2 * sum(i0[1:])
+
+
+def test_particle_on_last_cell_centre_is_rejected_like_oracle():
+    """A particle exactly on the centre of the last cell has a zero-weight
+    corner past the grid.  Its stencil still leaves the grid, and both the
+    oracle and the GPU path reject it (the GPU before touching the state)."""
+    from paper_2602_07853_amd import mpmlite, scenes as S
+    sc = S.small_block(n=8, lo=4, hi=7, seed=36)
+    p = {k: v.copy() for k, v in sc.particles.items()}
+    p["x"][0] = [(sc.n - 0.5) * sc.dx] * 3
+    g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+    _, _, _, rc = O.step(g, mats, sc.dt, sc.gravity, bcs, 0.0, O.SolverOpts(1e-8, 1e-8), p)
+    assert rc == -5  # the oracle's "stencil leaves the grid"
+    ctx = gpu_context(sc, 0)
+    dp = mpmlite.particles_to_device(p)
+    before = host(dp["x"]).copy()
+    with pytest.raises(mpmlite.MplError) as e:
+        ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+    assert e.value.status == -7
+    assert np.array_equal(host(dp["x"]), before)

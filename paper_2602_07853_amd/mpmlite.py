@@ -230,6 +230,24 @@ class Context:
     def reconstruct(self):
         self._check(self._lib.mpl_reconstruct_stretch(self._ctx), "mpl_reconstruct_stretch")
 
+    def _check_node_vec(self, t: torch.Tensor, name: str):
+        n1 = [d + 1 for d in self.dims]
+        want = (n1[0] * n1[1] * n1[2], 3)
+        if tuple(t.shape) != want:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, want {want} (dense node vector)")
+        return t
+
+    @staticmethod
+    def _check_box(t: torch.Tensor, name: str, channels, like=None):
+        shape = tuple(t.shape)
+        if like is not None:
+            want = tuple(like.shape[:3]) + ((channels,) if channels else ())
+        else:
+            want = shape[:3] + ((channels,) if channels else ())
+        if shape != want or len(shape[:3]) != 3:
+            raise ValueError(f"{name} has shape {shape}, want {want} ([X, Y, Z(, C)] box)")
+        return t
+
     def _node_vec(self, dtype=torch.float64):
         n1 = [d + 1 for d in self.dims]
         return torch.zeros((n1[0] * n1[1] * n1[2], 3), dtype=dtype, device="cuda")
@@ -237,20 +255,20 @@ class Context:
     def energy_grad(self, v=None, want_grad=True):
         E = C.c_double()
         g = self._node_vec() if want_grad else None
-        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        vp = C.c_void_p(_dptr(self._check_node_vec(v, "v"), torch.float64)) if v is not None else None
         self._check(self._lib.mpl_energy_grad(self._ctx, vp, C.byref(E),
                                               C.c_void_p(g.data_ptr()) if g is not None else None),
                     "mpl_energy_grad")
         return E.value, g
 
     def build_tangent(self, v=None, precision=F32):
-        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        vp = C.c_void_p(_dptr(self._check_node_vec(v, "v"), torch.float64)) if v is not None else None
         self._check(self._lib.mpl_build_tangent(self._ctx, vp, int(precision)), "mpl_build_tangent")
 
     def hv(self, u: torch.Tensor, precision=F32):
         dt = torch.float32 if precision == F32 else torch.float64
         out = self._node_vec(dt)
-        self._check(self._lib.mpl_hv(self._ctx, C.c_void_p(_dptr(u, dt)), C.c_void_p(out.data_ptr()),
+        self._check(self._lib.mpl_hv(self._ctx, C.c_void_p(_dptr(self._check_node_vec(u, "u"), dt)), C.c_void_p(out.data_ptr()),
                                      int(precision)), "mpl_hv")
         return out
 
@@ -258,7 +276,7 @@ class Context:
         x = self._node_vec()
         it = C.c_int32()
         rel = C.c_double()
-        self._check(self._lib.mpl_pcg(self._ctx, C.c_void_p(_dptr(b, torch.float64)),
+        self._check(self._lib.mpl_pcg(self._ctx, C.c_void_p(_dptr(self._check_node_vec(b, "b"), torch.float64)),
                                       C.c_void_p(x.data_ptr()), C.byref(it), C.byref(rel)), "mpl_pcg")
         return x, it.value, rel.value
 
@@ -271,7 +289,7 @@ class Context:
         return v, stats
 
     def load(self, parts_in: dict, parts_out: dict, dt, v=None):
-        vp = C.c_void_p(_dptr(v, torch.float64)) if v is not None else None
+        vp = C.c_void_p(_dptr(self._check_node_vec(v, "v"), torch.float64)) if v is not None else None
         self._check(self._lib.mpl_load(self._ctx, vp, C.byref(_particles(parts_in)),
                                        C.byref(_particles(parts_out)), C.c_double(dt)), "mpl_load")
 
@@ -310,6 +328,7 @@ class Context:
 
     def nn_forward(self, x: torch.Tensor):
         """Network forward on a dense box x [X, Y, Z, 16] (FP32 device)."""
+        self._check_box(x, "x", 16)
         dims = (C.c_int32 * 3)(*x.shape[:3])
         y = torch.zeros_like(x)
         self._check(self._lib.mpl_nn_forward(self._ctx, C.c_void_p(_dptr(x, torch.float32)), dims,
@@ -318,6 +337,8 @@ class Context:
 
     def nn_backward(self, x: torch.Tensor, dy: torch.Tensor):
         """Parameter gradient of <dy, network(x)> (FP32 device, flat)."""
+        self._check_box(x, "x", 16)
+        self._check_box(dy, "dy", 16, like=x)
         dims = (C.c_int32 * 3)(*x.shape[:3])
         g = torch.zeros(self.precond_param_count(), dtype=torch.float32, device="cuda")
         self._check(self._lib.mpl_nn_backward(self._ctx, C.c_void_p(_dptr(x, torch.float32)), dims,
@@ -326,6 +347,9 @@ class Context:
         return g
 
     def precond_train_step(self, x, t, mask, lr):
+        self._check_box(x, "x", 16)
+        self._check_box(t, "t", 3, like=x)
+        self._check_box(mask, "mask", None, like=x)
         dims = (C.c_int32 * 3)(*x.shape[:3])
         loss = C.c_float()
         self._check(self._lib.mpl_precond_train_step(
@@ -337,7 +361,7 @@ class Context:
     def precond_apply(self, r: torch.Tensor) -> torch.Tensor:
         """z = learned preconditioner applied to the dense node vector r."""
         z = self._node_vec()
-        self._check(self._lib.mpl_precond_apply(self._ctx, C.c_void_p(_dptr(r, torch.float64)),
+        self._check(self._lib.mpl_precond_apply(self._ctx, C.c_void_p(_dptr(self._check_node_vec(r, "r"), torch.float64)),
                                                 C.c_void_p(z.data_ptr())), "mpl_precond_apply")
         return z
 

@@ -394,3 +394,24 @@ def test_particle_on_last_cell_centre_is_rejected_like_oracle():
         ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
     assert e.value.status == -7
     assert np.array_equal(host(dp["x"]), before)
+
+
+def test_binding_rejects_mis_shaped_tensors():
+    """The binding checks tensor shapes before any kernel reads them."""
+    from paper_2602_07853_amd import mpmlite
+    sc = SCENES["nh_strained"]
+    ctx, parts = run_unload(sc, 0)
+    ctx.reconstruct()
+    nodes = (sc.n + 1) ** 3
+    with pytest.raises(ValueError):
+        ctx.energy_grad(torch.zeros((nodes - 1, 3), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.pcg(torch.zeros((nodes, 2), dtype=torch.float64, device="cuda"))
+    ctx.precond_set_weights(np.zeros(ctx.precond_param_count(), np.float32))
+    with pytest.raises(ValueError):
+        ctx.nn_forward(torch.zeros((8, 8, 8, 5), dtype=torch.float32, device="cuda"))
+    x = torch.zeros((8, 8, 8, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.precond_train_step(x, torch.zeros((8, 8, 8, 2), device="cuda"),
+                               torch.ones((8, 8, 8), device="cuda"), 1e-3)
+    assert ctx.nn_forward(x).shape == x.shape

@@ -1315,4 +1315,36 @@ int or_step(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
   return or_load(gg, dt, mc.data(), vnew.data(), np, mat, mats, x, v, G, F, eps_acc);
 }
 
+// One explicit step: the Integrate algorithm's explicit branch between the
+// unload and the load.  vhat_i = v_i^n + dt gravity on free nodes (the
+// prescribed velocity on Dirichlet nodes), then v_i^{n+1} = vhat_i + dt f_i / m_i
+// with f_i = -sum_c sum_k V_{c,k} tau_{c,k} grad w_ic (Eq. explicitforce).
+int or_step_explicit(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
+                     const double gravity[3], int32_t nbc, const or_bc* bcs, double time,
+                     int64_t np, double* x, double* v, double* G, double* F, const double* m,
+                     const double* V, const int32_t* mat, double* eps_acc, double* vnode_out) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nc = g.nc(), nn = g.nn();
+  std::vector<double> mc(nc), vc(3 * nc), Gc(9 * nc), Vck(nmat * nc), tauck(9 * nmat * nc),
+      mi(nn), vi(3 * nn), vfix(3 * nn), f(3 * nn), vnew(3 * nn);
+  std::vector<uint8_t> fixed(nn);
+  int rc = or_unload(gg, np, x, v, G, F, m, V, mat, nmat, mats, mc.data(), vc.data(), Gc.data(),
+                     Vck.data(), tauck.data(), mi.data(), vi.data());
+  if (rc != OR_OK && rc != OR_ERR_DOMAIN) return rc;
+  or_node_bcs(gg, mi.data(), nbc, bcs, time, fixed.data(), vfix.data());
+  or_explicit_force(gg, nmat, Vck.data(), tauck.data(), f.data());
+  for (int64_t nidx = 0; nidx < nn; ++nidx)
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = 3 * nidx + a;
+      if (fixed[nidx])
+        vnew[i] = vfix[i];
+      else if (mi[nidx] != 0.0)
+        vnew[i] = vi[i] + dt * gravity[a] + dt * f[i] / mi[nidx];
+      else
+        vnew[i] = 0.0;
+    }
+  if (vnode_out) std::memcpy(vnode_out, vnew.data(), sizeof(double) * 3 * nn);
+  return or_load(gg, dt, mc.data(), vnew.data(), np, mat, mats, x, v, G, F, eps_acc);
+}
+
 }  // extern "C"

@@ -120,6 +120,13 @@ int or_step(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
             const or_solver_opts* opts, int64_t np, double* x, double* v, double* G,
             double* F, const double* m, const double* V, const int32_t* mat,
             double* eps_acc, or_solver_stats* stats, double* vnode_out);
+/* Explicit branch of Integrate (Sec. 4 opening, Eq. explicitforce): unload,
+ * Dirichlet sets, v = vhat + dt f / m on free nodes with f the explicit
+ * internal force, then load.  vnode_out (may be NULL) gets the node velocity. */
+int or_step_explicit(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+                     const double gravity[3], int32_t nbc, const or_bc* bcs, double time,
+                     int64_t np, double* x, double* v, double* G, double* F, const double* m,
+                     const double* V, const int32_t* mat, double* eps_acc, double* vnode_out);
 
 #ifdef __cplusplus
 }

@@ -331,6 +331,26 @@ def step(grid: Grid, mats, dt, gravity, bcs, time, opts: SolverOpts, parts: dict
     return out, stats, vnode, rc
 
 
+def step_explicit(grid: Grid, mats, dt, gravity, bcs, time, parts: dict):
+    """Explicit branch of the Integrate algorithm (Sec. 4 opening, Eq.
+    explicitforce) between unload and load, on a copy of ``parts``; returns
+    (new parts, node velocity, rc)."""
+    out = {k: np.array(v, dtype=np.float64 if k != "mat" else np.int32, copy=True)
+           for k, v in parts.items()}
+    if "eps" not in out:
+        out["eps"] = np.zeros(len(out["m"]))
+    vnode = np.zeros((grid.nnode, 3))
+    arr = (_BC * max(len(bcs), 1))(*[b.c() for b in bcs])
+    grav = (C.c_double * 3)(*gravity)
+    rc = lib().or_step_explicit(C.byref(grid.c()), len(mats), _mats(mats), C.c_double(dt), grav,
+                                len(bcs), arr, C.c_double(time), C.c_int64(len(out["m"])),
+                                _p(out["x"]), _p(out["v"]), _p(out["G"]), _p(out["F"]),
+                                _p(_f64(out["m"])), _p(_f64(out["V"])),
+                                _p(np.ascontiguousarray(out["mat"], dtype=np.int32), C.c_int32),
+                                _p(out["eps"]), _p(vnode))
+    return out, vnode, rc
+
+
 # ---------------------------------------------------------------- scene glue
 def materials_of(scene):
     return [Material(m["model"], m["E"], m["nu"], m["plastic"], m["yield_stress"],

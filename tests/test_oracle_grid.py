@@ -346,3 +346,83 @@ def test_config1_step_runs_and_converges():
     # gravity pulls the mean velocity down by ~dt g
     dv = (out["v"] - sc.particles["v"]).mean(0)
     assert abs(dv[1] + 9.81e-3) <= 2e-4
+
+
+# ---------------------------------------------------------------- explicit branch
+def explicit_prep(model=O.NEOHOOKEAN, strain=0.1, n_mats=2, gravity=(0.0, 0.0, 0.0), bcs=()):
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=strain, model=model, n_mats=n_mats)
+    out, vnode, rc = O.step_explicit(g, mats, sc.dt, gravity, list(bcs), 0.0, sc.particles)
+    assert rc == 0
+    u = O.unload(g, sc.particles, mats)
+    return sc, g, mats, u, out, vnode
+
+
+def test_explicit_step_at_rest_stays_at_rest():
+    """F_p = I (tau = 0), v_p = G_p = 0 and no gravity: no node or particle
+    moves and F_p stays the identity."""
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.0)
+    p = {k: np.array(v, copy=True) for k, v in sc.particles.items()}
+    p["v"][:] = 0.0
+    p["G"][:] = 0.0
+    out, vnode, rc = O.step_explicit(g, mats, sc.dt, (0.0, 0.0, 0.0), [], 0.0, p)
+    assert rc == 0
+    assert np.abs(vnode).max() == 0.0
+    assert np.array_equal(out["x"], p["x"])
+    assert np.abs(out["F"] - np.eye(3).reshape(1, 9)).max() == 0.0
+
+
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY])
+def test_explicit_step_conserves_node_momenta(model):
+    """Without Dirichlet nodes or gravity the internal forces sum to zero
+    (the corner gradients of a cell sum to zero) and exert no torque (the
+    corners reproduce x linearly and tau is symmetric): the node update
+    changes neither the total momentum nor the angular momentum about the
+    origin, while the forces themselves are large."""
+    sc, g, mats, u, out, vnode = explicit_prep(model=model)
+    m = u["mi"][:, None]
+    dv = vnode - u["vi"]
+    dp = (m * dv).sum(0)
+    xn = node_pos(g.n, g.dx)
+    dL = np.cross(xn, m * dv).sum(0)
+    scale = np.abs(m * dv).sum()
+    assert scale > 0
+    assert np.abs(dp).max() <= 1e-13 * scale
+    assert np.abs(dL).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY])
+def test_explicit_velocity_is_minus_gradient_at_rest_over_mass(model):
+    """On free nodes the explicit update equals -grad Phi(0) / m_i: the
+    incremental potential's gradient at v = 0 (the stretch reconstruction's
+    S in place of tau, Eq. rotfree-def) is m_i (0 - vhat_i) - dt f_i."""
+    gravity = (0.0, -9.81, 0.0)
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.1, model=model, n_mats=2)
+    bcs = O.bcs_of(sc)
+    out, vnode, rc = O.step_explicit(g, mats, sc.dt, gravity, bcs, 0.0, sc.particles)
+    assert rc == 0
+    u = O.unload(g, sc.particles, mats)
+    fixed, vfix = O.node_bcs(g, u["mi"], bcs)
+    free = (u["mi"] > 0) & (fixed == 0)
+    vhat = np.where(free[:, None], u["vi"] + sc.dt * np.array(gravity), vfix)
+    S, rc = O.reconstruct(g, mats, u["Vck"], u["tauck"])
+    assert rc == 0
+    zero = np.zeros((g.nnode, 3))
+    _, grad, _ = O.energy_grad(g, mats, sc.dt, u["mi"], vhat, fixed, u["Vck"], S, zero)
+    want = -grad[free] / u["mi"][free, None]
+    assert np.abs(vnode[free] - want).max() <= 1e-10 * np.abs(vnode[free] - vhat[free]).max()
+    assert np.array_equal(vnode[fixed == 1], vfix[fixed == 1])
+    assert np.all(vnode[u["mi"] == 0] == 0.0)
+
+
+def test_explicit_velocity_change_is_linear_in_dt():
+    """With no gravity, v - v^n is dt f / m: doubling dt doubles it (the
+    unload and the force do not depend on dt)."""
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.1)
+    u = O.unload(g, sc.particles, mats)
+    dvs = []
+    for dt in (1e-4, 2e-4):
+        _, vnode, rc = O.step_explicit(g, mats, dt, (0.0, 0.0, 0.0), [], 0.0, sc.particles)
+        assert rc == 0
+        dvs.append(vnode - u["vi"])
+    assert np.abs(dvs[0]).max() > 0
+    assert np.abs(dvs[1] - 2 * dvs[0]).max() <= 1e-12 * np.abs(dvs[1]).max()

@@ -51,6 +51,8 @@ def parse():
                     help="start each Newton iteration's CG from the previous step's direction "
                          "(2, 3: extrapolated linearly / quadratically from the last steps; 4: the "
                          "energy-norm best combination of the last three)")
+    ap.add_argument("--explicit-steps", type=int, default=200,
+                    help="timed steps of the explicit leg (jelly-falling workload, 256^3); 0 = skip")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,
@@ -198,6 +200,9 @@ def main():
     learned = None
     if args.learned_steps > 0:
         learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts)
+    explicit = None
+    if args.explicit_steps > 0:
+        explicit = explicit_leg(args.explicit_steps)
     base = None
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
         base = cpu_baseline(sc, counts)
@@ -222,6 +227,7 @@ def main():
         "update_kernel": update,
         "cpu_baseline": base,
         "learned": learned,
+        "explicit": explicit,
     }
     print(json.dumps(line), flush=True)
 
@@ -271,6 +277,44 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
             "plain_pcg_per_step": round(plain_counts[1], 2),
             "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "
                         "from the workload's initial state, 1 Adam step per 64 CG iterations"}
+
+
+def explicit_leg(nsteps, warmup=3):
+    """The explicit branch of Integrate on the jelly-falling workload (256^3,
+    about 1.1M particles, dt = 6e-5): unload, nodal force and update, load per
+    step, timed on the wall clock between two synchronisations.  The stage
+    split comes from the library's host timers."""
+    import torch
+    from paper_2602_07853_amd import mpmlite, scenes
+    sc = scenes.jelly_falling()
+    ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials, opts=dict(hv_precision=mpmlite.F64))
+    parts = mpmlite.particles_to_device(sc.particles)
+    t = 0.0
+    for _ in range(warmup):
+        ctx.step_explicit(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+    torch.cuda.synchronize()
+    ms = {"unload": 0.0, "integrate": 0.0, "load": 0.0}
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        st = ctx.step_explicit(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        ms["unload"] += st["ms_unload"]
+        ms["integrate"] += st["ms_newton"]
+        ms["load"] += st["ms_load"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {"workload": f"{sc.name}: {sc.n}^3 grid, dx=1/{sc.n}, {sc.n_particles} particles "
+                        f"(8 ppc, {sc.occupied_cells} occupied cells), StVK-Hencky E=5e3 nu=0.4, "
+                        f"dt={sc.dt:g}, gravity, two cubes falling onto a slab",
+            "steps_per_s": round(nsteps / el, 2), "steps": nsteps,
+            "ms_per_step": round(1e3 * el / nsteps, 4),
+            "particles_per_s": round(sc.n_particles * nsteps / el, 1),
+            "active_cells": st["active_cells"], "active_nodes": st["active_nodes"],
+            "ms_stage": {k: round(v / nsteps, 4) for k, v in ms.items()}}
+    print(f"[bench] explicit leg {json.dumps(line)}", file=sys.stderr, flush=True)
+    del ctx, parts
+    return line
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

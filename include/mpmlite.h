@@ -168,6 +168,21 @@ mpl_status mpl_step(mpl_ctx* ctx, const mpl_particles* in, mpl_particles* out, d
                     const double gravity[3], const mpl_bc* bcs, int32_t n_bcs, double time,
                     mpl_stats* stats);
 
+/* Integrate, explicit branch (the explicit case of the Integrate algorithm;
+ * Sec. 4 opening, Eq. explicitforce): one explicit time step.  Unload
+ * (Alg. 2), Dirichlet sets and vhat as in mpl_step; then the internal nodal
+ * force from the unloaded per-centre volumes and Kirchhoff stresses,
+ *   f_i = -sum_c sum_k V_{c,k} tau_{c,k} grad w_ic,
+ * and v_i^{n+1} = vhat_i + dt f_i / m_i on free nodes, the prescribed
+ * velocity on Dirichlet nodes and zero on massless nodes (no stretch
+ * reconstruction, no solve); then Load (Alg. 4).  Arguments, aliasing and
+ * failure behaviour as for mpl_step.  stats (host, may be NULL) gets the
+ * grid counts and the stage times, ms_newton holding the force and node
+ * update; its solver counters are zero. */
+mpl_status mpl_step_explicit(mpl_ctx* ctx, const mpl_particles* in, mpl_particles* out, double dt,
+                             const double gravity[3], const mpl_bc* bcs, int32_t n_bcs, double time,
+                             mpl_stats* stats);
+
 /* ---- sub-steps (the same kernels mpl_step runs) ---- */
 
 /* Alg. 2 (Sec. 3.1-3.3): bin particles by dual cell, Kirchhoff stress per
@@ -199,8 +214,14 @@ mpl_status mpl_pcg(mpl_ctx* ctx, const double* b, double* x, int32_t* iters, dou
 /* Newton minimisation of Phi from vhat; the solution stays in the context
  * and is copied to v_out (dense device FP64) if non-NULL. */
 mpl_status mpl_solve(mpl_ctx* ctx, double* v_out, mpl_stats* stats);
+/* Explicit branch of Integrate after mpl_unload (the force and node update
+ * of mpl_step_explicit).  The new velocity becomes the context's velocity,
+ * so mpl_load with v = NULL moves the particles with it.  v_out, f_out:
+ * dense device FP64 arrays [(dims+1)^3][3] or NULL; f_out gets f_i on every
+ * node with mass (Dirichlet nodes included) and zero elsewhere. */
+mpl_status mpl_integrate_explicit(mpl_ctx* ctx, double* v_out, double* f_out);
 /* Alg. 4: node->centre sampling of v (dense device FP64, or NULL = the
- * solved velocity), centre->particle interpolation, x += dt v_p,
+ * solved or explicitly integrated velocity), centre->particle interpolation, x += dt v_p,
  * F <- (I + dt G_p) F, plastic projection.  Uses the binning of the last
  * unload; in must be the particles passed to it. */
 mpl_status mpl_load(mpl_ctx* ctx, const double* v, const mpl_particles* in, mpl_particles* out,

@@ -219,6 +219,17 @@ class Context:
         self._check(rc, "mpl_step")
         return stats
 
+    def step_explicit(self, parts_in: dict, parts_out: dict, dt, gravity=(0.0, 0.0, 0.0), bcs=(),
+                      time=0.0):
+        pi, po = _particles(parts_in), _particles(parts_out)
+        st = _Stats()
+        rc = self._lib.mpl_step_explicit(self._ctx, C.byref(pi), C.byref(po), C.c_double(dt),
+                                         (C.c_double * 3)(*gravity), _bcs(list(bcs)), len(bcs),
+                                         C.c_double(time), C.byref(st))
+        stats = _stats_dict(st)
+        self._check(rc, "mpl_step_explicit")
+        return stats
+
     # ------------------------------------------------------------ sub-steps
     def unload(self, parts: dict, dt, gravity=(0.0, 0.0, 0.0), bcs=(), time=0.0):
         pi = _particles(parts)
@@ -287,6 +298,14 @@ class Context:
         stats = _stats_dict(st)
         self._check(rc, "mpl_solve")
         return v, stats
+
+    def integrate_explicit(self, want_force=False):
+        v = self._node_vec()
+        f = self._node_vec() if want_force else None
+        self._check(self._lib.mpl_integrate_explicit(self._ctx, C.c_void_p(v.data_ptr()),
+                                                     C.c_void_p(f.data_ptr()) if f is not None else None),
+                    "mpl_integrate_explicit")
+        return (v, f) if want_force else v
 
     def load(self, parts_in: dict, parts_out: dict, dt, v=None):
         vp = C.c_void_p(_dptr(self._check_node_vec(v, "v"), torch.float64)) if v is not None else None

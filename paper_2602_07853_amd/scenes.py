@@ -320,4 +320,29 @@ def spinning_rod(n=32, seed=15, omega=4.0, E=5e3, nu=0.3) -> Scene:
                  newton_rtol=1e-10, pcg_rtol=1e-10, occupied_cells=len(cells))
 
 
+def jelly_falling(seed: int = 6, n: int = 256, ppc_axis: int = 2, speed: float = 1.0) -> Scene:
+    """Explicit workload shaped like the paper's Jelly Falling example: StVK
+    with Hencky strain, E = 5e3, nu = 0.4, rho = 1000, dt = 6e-5, gravity and
+    sticky walls.  A slab of 3/8 n x n/32 x 3/8 n cells rests on the floor and
+    two n/8-cubes fall onto it at ``speed`` m/s; at n = 256 that is 139,264
+    occupied cells and 1,114,112 particles at 8 per cell."""
+    dx = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mats = [material(HENCKY, 5e3, 0.4, 1000.0)]
+    e = n // 8
+    base = box_cells((5 * n // 16, 2, 5 * n // 16), (11 * n // 16, 2 + max(n // 32, 1), 11 * n // 16))
+    c1 = box_cells((23 * n // 64, 5 * n // 32, 23 * n // 64),
+                   (23 * n // 64 + e, 5 * n // 32 + e, 23 * n // 64 + e))
+    c2 = box_cells((33 * n // 64, 15 * n // 64, 33 * n // 64),
+                   (33 * n // 64 + e, 15 * n // 64 + e, 33 * n // 64 + e))
+    cells = np.concatenate([base, c1, c2])
+    x = fill_cells(cells, dx, ppc_axis, rng)
+    p = make_particles(x, np.zeros(len(x), np.int32), mats, dx, ppc_axis ** 3)
+    ppc = ppc_axis ** 3
+    falling = np.repeat(np.arange(len(cells)) >= len(base), ppc)
+    p["v"][falling, 1] = -speed
+    return Scene(f"jelly_falling_{n}", n, dx, 6e-5, 100, (0.0, -9.81, 0.0), mats, wall_bcs(n, dx), p,
+                 occupied_cells=len(cells))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}

@@ -93,3 +93,28 @@ def test_load_full_size(full):
     if sc.name.startswith("config3"):
         assert np.abs(po["eps"]).max() > 0  # the von Mises projection was active
     assert rel(host(out["plastic"]), po["eps"]) <= 1e-10
+
+
+def test_explicit_steps_jelly_full_size():
+    """The explicit workload as the benchmark runs it (256^3, 1.11M particles,
+    the library's launch configuration): two explicit steps on the GPU against
+    the oracle's explicit step, every particle compared."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.jelly_falling()
+    print(f"[fullsize] {sc.name}: {sc.n_particles} particles", flush=True)
+    g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+    ctx = gpu_context(sc, 1)
+    dp = mpmlite.particles_to_device(sc.particles)
+    p = sc.particles
+    t = 0.0
+    for k in range(2):
+        p, vnode, rc = O.step_explicit(g, mats, sc.dt, sc.gravity, bcs, t, p)
+        assert rc == 0
+        ctx.step_explicit(dp, dp, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        print(f"[fullsize] explicit step {k} done", flush=True)
+    pg = {k: host(v) for k, v in dp.items()}
+    for k in ("x", "v", "G", "F"):
+        e = rel(pg[k], p[k])
+        print(f"[fullsize] jelly {k} rel {e:.2e}", flush=True)
+        assert e <= 1e-10, k

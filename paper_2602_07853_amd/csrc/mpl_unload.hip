@@ -330,7 +330,11 @@ __global__ __launch_bounds__(64) void k_p2c_combine(const int* __restrict__ c_nb
   if (m != 0.0) {
 #pragma unroll
     for (int v = 1; v < 13; ++v) acc[v] /= m;
-    atomicAdd(count, 1);
+  }
+  {
+    // occupied-cell count: one atomic per wavefront (the block is one wave)
+    const uint64_t bm = __ballot(m != 0.0);
+    if (l == 0 && bm) atomicAdd(count, (int32_t)__popcll(bm));
   }
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
@@ -431,8 +435,15 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
       for (int a = 0; a < 3; ++a) vf[a] = (bcs.kind[b] == MPL_BC_MOVING_BOX) ? bcs.vel[b][a] : 0.0;
     }
     if (!(fl & MPL_NODE_FIXED)) fl |= MPL_NODE_FREE;
-    atomicAdd(&counts[0], 1);
-    if (fl & MPL_NODE_FREE) atomicAdd(&counts[1], 1);
+  }
+  {
+    // active and free node counts: one atomic per wavefront (the block is
+    // one wave), not one per node on the same two addresses
+    const uint64_t ba = __ballot((fl & MPL_NODE_ACTIVE) != 0), bf = __ballot((fl & MPL_NODE_FREE) != 0);
+    if (l == 0) {
+      if (ba) atomicAdd(&counts[0], (int32_t)__popcll(ba));
+      if (bf) atomicAdd(&counts[1], (int32_t)__popcll(bf));
+    }
   }
   const double grav[3] = {gx, gy, gz};
   mi[ni] = m;

@@ -9,9 +9,10 @@
 // One wavefront per 4x4x4 node block, one lane per node: the lane gathers
 // its 8 surrounding centres in a fixed corner order (no atomics, the same
 // result on every run).  A centre's V and tau are read by its 8 corner
-// nodes, which sit in at most 8 node blocks of neighbouring workgroups, so
-// the re-reads are served by L2; the kernel runs once per step and moves
-// 7K doubles per centre and 57 bytes per node.
+// nodes, which sit in at most 8 node blocks; the XCD-major block mapping
+// keeps those blocks on one XCD so the re-reads are served by its L2.  The
+// kernel runs once per step and moves 7K doubles per centre and 57 bytes
+// per node.
 #include <chrono>
 
 #include "mpl_grid.h"
@@ -23,31 +24,50 @@ namespace {
 __global__ __launch_bounds__(64) void k_explicit_nodes(const double* __restrict__ Vk,
                                                        const double* __restrict__ Tk, int64_t ncell,
                                                        int K, const int* __restrict__ n_nbr_cell,
-                                                       const double* __restrict__ mi,
+                                                       int n_nblk, const double* __restrict__ mi,
                                                        const uint8_t* __restrict__ flags,
                                                        const double* __restrict__ vhat, int64_t nnode,
                                                        double dt, double inv4dx,
                                                        double* __restrict__ v, double* __restrict__ f) {
-  const int nb = blockIdx.x, l = threadIdx.x;
+  const int nb = xcd_block(blockIdx.x, n_nblk), l = threadIdx.x;
+  if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   const uint8_t fl = flags[ni];
   double fr[3] = {0.0, 0.0, 0.0};
   if (fl & MPL_NODE_ACTIVE) {
+    int cis[8];
+    bool ok[8];
+#pragma unroll
     for (int d = 0; d < 8; ++d) {
-      const int ci = node_cell(n_nbr_cell, nb, l, d);
-      if (ci < 0) continue;
-      double gw[3];
-      corner_grad(d, inv4dx, gw);
-      for (int k = 0; k < K; ++k) {
-        const double V = Vk[k * ncell + ci];
-        if (V == 0.0) continue;
-        // symmetric tau stored as (xx, yy, zz, xy, yz, xz)
-        const double* T = Tk + (int64_t)k * 6 * ncell + ci;
-        const double txx = T[0], tyy = T[ncell], tzz = T[2 * ncell], txy = T[3 * ncell],
-                     tyz = T[4 * ncell], txz = T[5 * ncell];
-        fr[0] -= V * (txx * gw[0] + txy * gw[1] + txz * gw[2]);
-        fr[1] -= V * (txy * gw[0] + tyy * gw[1] + tyz * gw[2]);
-        fr[2] -= V * (txz * gw[0] + tyz * gw[1] + tzz * gw[2]);
+      const int cv = node_cell(n_nbr_cell, nb, l, d);
+      ok[d] = cv >= 0;
+      cis[d] = ok[d] ? cv : 0;
+    }
+    for (int k = 0; k < K; ++k) {
+      // corners in a fixed order, two batches of four whose loads are all
+      // issued before any is used; an absent centre reads centre 0 and an
+      // empty one its own zeros, both with V = 0, which subtracts exact zeros
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double V[4], T[4][6];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t ci = cis[4 * h + j];
+          V[j] = Vk[k * ncell + ci];
+          // symmetric tau stored as (xx, yy, zz, xy, yz, xz)
+#pragma unroll
+          for (int e = 0; e < 6; ++e) T[j][e] = Tk[((int64_t)k * 6 + e) * ncell + ci];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int d = 4 * h + j;
+          const double Vc = ok[d] ? V[j] : 0.0;
+          double gw[3];
+          corner_grad(d, inv4dx, gw);
+          fr[0] -= Vc * (T[j][0] * gw[0] + T[j][3] * gw[1] + T[j][5] * gw[2]);
+          fr[1] -= Vc * (T[j][3] * gw[0] + T[j][1] * gw[1] + T[j][4] * gw[2]);
+          fr[2] -= Vc * (T[j][5] * gw[0] + T[j][4] * gw[1] + T[j][2] * gw[2]);
+        }
       }
     }
   }
@@ -71,8 +91,8 @@ mpl_status stage_explicit(mpl_ctx* c, bool want_force) {
   if (!c->unloaded) return mpl_fail(c, MPL_ERR_STATE, "explicit integration before unload");
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   if (want_force) MPL_TRY(mpl_ensure(c, c->g, 8 * 3 * nnode));
-  MPL_LAUNCH(c, k_explicit_nodes, c->n_nblk, 64, P<double>(c->Vk), P<double>(c->Tk), ncell, c->nmat,
-             P<int>(c->n_nbr_cell), P<double>(c->mi), P<uint8_t>(c->flags), P<double>(c->vhat), nnode,
+  MPL_LAUNCH(c, k_explicit_nodes, xcd_grid(c->n_nblk), 64, P<double>(c->Vk), P<double>(c->Tk), ncell,
+             c->nmat, P<int>(c->n_nbr_cell), c->n_nblk, P<double>(c->mi), P<uint8_t>(c->flags), P<double>(c->vhat), nnode,
              c->dt, 0.25 * c->inv_dx, P<double>(c->v), want_force ? P<double>(c->g) : nullptr);
   // the explicit velocity takes the place of a Newton solution: mpl_load
   // with v = NULL moves the particles with it

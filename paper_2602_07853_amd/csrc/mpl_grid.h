@@ -44,6 +44,18 @@ __device__ __forceinline__ int corner_node(const int* c_nbr_node, int cb, int l,
   return c_nbr_node[cb * 8 + o] * MPL_BC + local_index(x & 3, y & 3, z & 3);
 }
 
+// XCD-major workgroup mapping.  The dispatcher deals consecutive workgroups
+// round-robin to the 8 XCDs, each with its own L2; mapping workgroup wg to
+// block (wg mod 8) * ceil(n/8) + wg / 8 gives every XCD a contiguous range of
+// blocks, so neighbouring blocks (which read the same halo lines) share one
+// L2.  A bijection on [0, 8 ceil(n/8)): launch that many workgroups and let
+// those with a result >= n exit.
+__device__ __forceinline__ int xcd_block(int wg, int n) {
+  const int per = (n + 7) >> 3;
+  return (wg & 7) * per + (wg >> 3);
+}
+__host__ __device__ inline int xcd_grid(int n) { return ((n + 7) / 8) * 8; }
+
 // Compact cell index of the cell c = node - delta_d around local node l of
 // node block nb, or -1 when that cell block is not active.
 __device__ __forceinline__ int node_cell(const int* n_nbr_cell, int nb, int l, int d) {

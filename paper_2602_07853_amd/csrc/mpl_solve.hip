@@ -485,12 +485,8 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
 // The halo pieces are summed into their owner node by the CG update kernel
 // (or by k_hv_combine for a stand-alone product), so no node is ever
 // written by two workgroups and no atomics are needed.
-// Workgroups are mapped XCD-major (consecutive blocks on one XCD) so that
-// neighbouring blocks share p tile lines in the same L2.
-__device__ __forceinline__ int xcd_block(int wg, int n) {
-  const int per = (n + 7) >> 3;
-  return (wg & 7) * per + (wg >> 3);
-}
+// Workgroups are mapped XCD-major (xcd_block: consecutive blocks on one XCD)
+// so that neighbouring blocks share p tile lines in the same L2.
 
 template <class T, bool DOT, bool FACT>
 __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64_t nnode,

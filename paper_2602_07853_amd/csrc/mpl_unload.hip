@@ -380,36 +380,46 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
                                             const double* __restrict__ mc,
                                             const double* __restrict__ vc,
                                             const double* __restrict__ Gc, int64_t ncell,
-                                            int64_t nnode, BCDev bcs, double time, double dt,
+                                            int64_t nnode, int n_nblk, BCDev bcs, double time, double dt,
                                             double gx, double gy, double gz,
                                             double* __restrict__ mi, double* __restrict__ vn,
                                             double* __restrict__ vhat, double* __restrict__ v,
                                             uint8_t* __restrict__ flags,
                                             int32_t* __restrict__ counts) {
-  const int nb = blockIdx.x, l = threadIdx.x;
+  const int nb = xcd_block(blockIdx.x, n_nblk), l = threadIdx.x;
+  if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double m = 0.0, q[3] = {0.0, 0.0, 0.0};
-  // corner by corner in a fixed order; every cell's values are loaded up
-  // front (an absent cell reads cell 0 and counts for nothing), so the eight
-  // cells cost one memory round trip
+  // corner by corner in a fixed order, in two batches of four corners whose
+  // loads are all issued before any is used.  An absent centre reads centre
+  // 0 and an empty one its own zeros; both enter with weight 0 and add exact
+  // zeros, so no branch separates the loads from their use.
 #pragma unroll
-  for (int d = 0; d < 8; ++d) {
-    const int cv = node_cell(n_nbr_cell, nb, l, d);
-    const int64_t ci = cv < 0 ? 0 : cv;
-    const double mcc = mc[ci];
-    double vcc[3], G[9];
+  for (int h = 0; h < 2; ++h) {
+    double mcc[4], vcc[4][3], G[4][9];
+    bool ok[4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vcc[a] = vc[a * ncell + ci];
+    for (int j = 0; j < 4; ++j) {
+      const int cv = node_cell(n_nbr_cell, nb, l, 4 * h + j);
+      ok[j] = cv >= 0;
+      const int64_t ci = ok[j] ? cv : 0;
+      mcc[j] = mc[ci];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) G[e] = Gc[e * ncell + ci];
-    if (cv < 0 || mcc == 0.0) continue;
-    const double wm = mcc / 8.0;
-    const double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
-    m += wm;
+      for (int a = 0; a < 3; ++a) vcc[j][a] = vc[a * ncell + ci];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double aff = G[a * 3] * r[0] + G[a * 3 + 1] * r[1] + G[a * 3 + 2] * r[2];
-      q[a] += wm * (vcc[a] + aff);
+      for (int e = 0; e < 9; ++e) G[j][e] = Gc[e * ncell + ci];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = 4 * h + j;
+      const double wm = ok[j] ? mcc[j] / 8.0 : 0.0;
+      const double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
+      m += wm;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double aff = G[j][a * 3] * r[0] + G[j][a * 3 + 1] * r[1] + G[j][a * 3 + 2] * r[2];
+        q[a] += wm * (vcc[j][a] + aff);
+      }
     }
   }
   double vv[3] = {0.0, 0.0, 0.0};
@@ -580,8 +590,8 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   }
   const double gz[3] = {0.0, 0.0, 0.0};
   const double* gr = gravity ? gravity : gz;
-  MPL_LAUNCH(c, k_c2n, c->n_nblk, 64, g, P<int32_t>(c->n_nbr_cell), P<int4>(c->ncoord),
-             P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, bd, time, dt, gr[0],
+  MPL_LAUNCH(c, k_c2n, xcd_grid(c->n_nblk), 64, g, P<int32_t>(c->n_nbr_cell), P<int4>(c->ncoord),
+             P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, c->n_nblk, bd, time, dt, gr[0],
              gr[1], gr[2], P<double>(c->mi), P<double>(c->vn), P<double>(c->vhat), P<double>(c->v),
              P<uint8_t>(c->flags), &ds->n_active_nodes);
   MPL_TRY(mpl_sync_scalars(c));

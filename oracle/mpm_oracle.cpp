@@ -436,6 +436,38 @@ int dpdf_hencky(const or_material* m, const double* F, double* A) {
   return OR_OK;
 }
 
+// J-based water (Sec. 3, Water): psi = kappa/2 (J - 1)^2 with kappa in
+// m->lambda.  P = dpsi/dJ dJ/dF = kappa (J - 1) cof F, and
+// dP[E] = kappa (cof F : E) cof F + kappa (J - 1) d(cof F)[E].
+double psi_water(const or_material* m, const double* F) {
+  double J = m3_det(F);
+  if (!(J > 0.0)) return kInf;
+  return 0.5 * m->lambda * (J - 1.0) * (J - 1.0);
+}
+int piola_water(const or_material* m, const double* F, double* P) {
+  double J = m3_det(F);
+  if (!(J > 0.0)) return OR_ERR_DOMAIN;
+  double C[9];
+  m3_cofactor(F, C);
+  for (int i = 0; i < 9; ++i) P[i] = m->lambda * (J - 1.0) * C[i];
+  return OR_OK;
+}
+int dpdf_water(const or_material* m, const double* F, double* A) {
+  double J = m3_det(F);
+  if (!(J > 0.0)) return OR_ERR_DOMAIN;
+  double C[9];
+  m3_cofactor(F, C);
+  for (int e = 0; e < 9; ++e) {
+    double E[9] = {0};
+    E[e] = 1.0;
+    double dC[9];
+    m3_cofactor_deriv(F, E, dC);
+    double cE = m3_ddot(C, E);
+    for (int i = 0; i < 9; ++i) A[i * 9 + e] = m->lambda * (cE * C[i] + (J - 1.0) * dC[i]);
+  }
+  return OR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Stress -> stretch inverses (Sec. 4.3, App. C).
 // ---------------------------------------------------------------------------
@@ -466,7 +498,20 @@ double cardano_largest(double p, double q) {
 int stretch_from_principal(const or_material* m, const double* t, double* sig) {
   const double mu = m->mu, la = m->lambda;
   int st = OR_OK;
-  if (m->model == OR_HENCKY) {
+  if (m->model == OR_WATER) {
+    // Sec. 3, Water: pressure pi = mean principal stress, pi = kappa J (J - 1)
+    // inverted on J > 0 as J = (1 + sqrt(1 + 4 pi / kappa)) / 2 (below
+    // pi = -kappa/4 there is no root: J = 1/2 and a domain flag), and the
+    // base is isotropic, sigma_i = J^{1/3}.
+    double pi_c = (t[0] + t[1] + t[2]) / 3.0;
+    double r = 1.0 + 4.0 * pi_c / m->lambda;
+    if (r < 0.0) {
+      r = 0.0;
+      st = OR_ERR_DOMAIN;
+    }
+    double J = 0.5 * (1.0 + std::sqrt(r));
+    for (int i = 0; i < 3; ++i) sig[i] = std::cbrt(J);
+  } else if (m->model == OR_HENCKY) {
     // Sec. 4.3.1: s = tr tau/(2mu + 3 lambda), e_i = (tau_i - lambda s)/(2 mu).
     double s = (t[0] + t[1] + t[2]) / (2.0 * mu + 3.0 * la);
     for (int i = 0; i < 3; ++i) sig[i] = std::exp((t[i] - la * s) / (2.0 * mu));
@@ -566,6 +611,7 @@ double psi_any(const or_material* m, const double* F) {
     case OR_NEOHOOKEAN: return psi_nh(m, F);
     case OR_FIXED_COROTATED: return psi_fcr(m, F);
     case OR_HENCKY: return psi_hencky(m, F);
+    case OR_WATER: return psi_water(m, F);
   }
   return kInf;
 }
@@ -574,6 +620,7 @@ int piola_any(const or_material* m, const double* F, double* P) {
     case OR_NEOHOOKEAN: return piola_nh(m, F, P);
     case OR_FIXED_COROTATED: return piola_fcr(m, F, P);
     case OR_HENCKY: return piola_hencky(m, F, P);
+    case OR_WATER: return piola_water(m, F, P);
   }
   return OR_ERR_ARG;
 }
@@ -582,6 +629,7 @@ int dpdf_any(const or_material* m, const double* F, double* A) {
     case OR_NEOHOOKEAN: return dpdf_nh(m, F, A);
     case OR_FIXED_COROTATED: return dpdf_fcr(m, F, A);
     case OR_HENCKY: return dpdf_hencky(m, F, A);
+    case OR_WATER: return dpdf_water(m, F, A);
   }
   return OR_ERR_ARG;
 }
@@ -1278,6 +1326,17 @@ int or_load(const or_grid* gg, double dt, const double* mc, const double* vnode,
     for (int e = 0; e < 9; ++e) G[9 * p + e] = Gp[e];
     double A[9] = {1.0 + dt * Gp[0], dt * Gp[1], dt * Gp[2], dt * Gp[3], 1.0 + dt * Gp[4],
                    dt * Gp[5], dt * Gp[6], dt * Gp[7], 1.0 + dt * Gp[8]};
+    if (mats[mat[p]].model == OR_WATER) {
+      // Sec. 3, Water: J^{n+1} = (1 + dt tr G_p) J^n, carried as F = J^{1/3} I
+      double Jn = (1.0 + dt * (Gp[0] + Gp[4] + Gp[8])) * m3_det(F + 9 * p);
+      if (!(Jn > 0.0)) {
+        status = OR_ERR_DOMAIN;
+        continue;
+      }
+      double c = std::cbrt(Jn);
+      for (int e = 0; e < 9; ++e) F[9 * p + e] = (e % 4 == 0) ? c : 0.0;
+      continue;
+    }
     m3_mul(A, F + 9 * p, F + 9 * p);
     int st = plastic_project(&mats[mat[p]], F + 9 * p, eps_acc ? eps_acc + p : nullptr);
     if (st != OR_OK) status = st;

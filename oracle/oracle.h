@@ -29,7 +29,10 @@
 extern "C" {
 #endif
 
-enum { OR_NEOHOOKEAN = 0, OR_FIXED_COROTATED = 1, OR_HENCKY = 2 };
+/* OR_WATER: J-based inviscid fluid (Sec. 3, Water), psi = kappa/2 (J - 1)^2;
+ * its bulk modulus kappa travels in or_material.lambda (mu unused), and its
+ * particles carry F = J^{1/3} I. */
+enum { OR_NEOHOOKEAN = 0, OR_FIXED_COROTATED = 1, OR_HENCKY = 2, OR_WATER = 3 };
 enum { OR_PLASTIC_NONE = 0, OR_PLASTIC_VON_MISES = 1, OR_PLASTIC_DRUCKER_PRAGER = 2 };
 enum { OR_BC_STICKY_BOX = 0, OR_BC_MOVING_BOX = 1 };
 
@@ -43,7 +46,7 @@ enum {
 };
 
 typedef struct {
-  int32_t model;     /* OR_NEOHOOKEAN, OR_FIXED_COROTATED, OR_HENCKY */
+  int32_t model;     /* OR_NEOHOOKEAN, OR_FIXED_COROTATED, OR_HENCKY, OR_WATER */
   int32_t plastic;   /* OR_PLASTIC_* */
   double mu, lambda;
   double yield_stress;   /* von Mises: Kirchhoff yield stress */

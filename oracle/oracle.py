@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
+NEOHOOKEAN, FIXED_COROTATED, HENCKY, WATER = 0, 1, 2, 3
 PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
 BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
 
@@ -82,7 +82,10 @@ class Material:
     friction_deg: float = 0.0
 
     def c(self) -> _Material:
-        mu, lam = lame(self.E, self.nu)
+        # J-based water (Sec. 3, Water): E is the bulk modulus kappa, carried
+        # in the lambda slot; the table of the paper's examples likewise lists
+        # E in place of kappa for water
+        mu, lam = (0.0, self.E) if self.model == WATER else lame(self.E, self.nu)
         return _Material(self.model, self.plastic, mu, lam, self.yield_stress, self.friction_deg)
 
 

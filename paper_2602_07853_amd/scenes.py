@@ -22,7 +22,7 @@ import math
 
 import numpy as np
 
-NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
+NEOHOOKEAN, FIXED_COROTATED, HENCKY, WATER = 0, 1, 2, 3
 PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
 BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
 

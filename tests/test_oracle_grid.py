@@ -210,7 +210,7 @@ def test_patch_test_regular_lattice():
 def test_gradient_at_rest_velocity_is_explicit_force():
     """P10: at v = 0 (F_c = S_c) the elastic gradient equals -dt times the
     explicit force of Sec. 4, because P(S) S^T = tau (Eq. rotfree-def)."""
-    for model in (O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY):
+    for model in (O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY, O.WATER):
         sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.1, model=model, n_mats=2)
         u = O.unload(g, sc.particles, mats)
         S, rc = O.reconstruct(g, mats, u["Vck"], u["tauck"])
@@ -223,7 +223,7 @@ def test_gradient_at_rest_velocity_is_explicit_force():
         assert np.abs(grad[act] + sc.dt * f[act]).max() <= 1e-10 * np.abs(f).max() * sc.dt
 
 
-@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY])
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY, O.WATER])
 def test_finite_difference_gradient_and_hessian(model):
     """P11: on a small mesh, central differences of Phi match grad . u and
     central differences of grad match the unprojected H u."""
@@ -371,7 +371,7 @@ def test_explicit_step_at_rest_stays_at_rest():
     assert np.abs(out["F"] - np.eye(3).reshape(1, 9)).max() == 0.0
 
 
-@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY])
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY, O.WATER])
 def test_explicit_step_conserves_node_momenta(model):
     """Without Dirichlet nodes or gravity the internal forces sum to zero
     (the corner gradients of a cell sum to zero) and exert no torque (the
@@ -390,7 +390,7 @@ def test_explicit_step_conserves_node_momenta(model):
     assert np.abs(dL).max() <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY])
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.FIXED_COROTATED, O.HENCKY, O.WATER])
 def test_explicit_velocity_is_minus_gradient_at_rest_over_mass(model):
     """On free nodes the explicit update equals -grad Phi(0) / m_i: the
     incremental potential's gradient at v = 0 (the stretch reconstruction's

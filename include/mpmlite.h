@@ -57,7 +57,11 @@ enum {
 };
 
 /* Constitutive models (Sec. 4.3) and plasticity (applied to particle F). */
-enum { MPL_NEOHOOKEAN = 0, MPL_FIXED_COROTATED = 1, MPL_HENCKY = 2 };
+/* MPL_WATER: J-based inviscid fluid (Sec. 3, Water), psi = kappa/2 (J - 1)^2
+ * with the bulk modulus kappa given as E (nu is not used) and no plasticity;
+ * its particles leave each step with F = J^{1/3} I, J updated as
+ * (1 + dt tr G_p) J. */
+enum { MPL_NEOHOOKEAN = 0, MPL_FIXED_COROTATED = 1, MPL_HENCKY = 2, MPL_WATER = 3 };
 enum { MPL_PLASTIC_NONE = 0, MPL_PLASTIC_VON_MISES = 1, MPL_PLASTIC_DRUCKER_PRAGER = 2 };
 /* Dirichlet node boxes. */
 enum { MPL_BC_STICKY_BOX = 0, MPL_BC_MOVING_BOX = 1 };
@@ -73,7 +77,7 @@ typedef struct {
 } mpl_grid;
 
 typedef struct {
-  int32_t model;        /* MPL_NEOHOOKEAN | MPL_FIXED_COROTATED | MPL_HENCKY */
+  int32_t model;        /* MPL_NEOHOOKEAN | MPL_FIXED_COROTATED | MPL_HENCKY | MPL_WATER */
   int32_t plastic;      /* MPL_PLASTIC_* */
   double E, nu, rho;    /* Young's modulus, Poisson ratio, density (rho unused by the step) */
   double yield_stress;  /* von Mises Kirchhoff yield stress */

@@ -196,10 +196,13 @@ static void free_buf(DevBuf& b) {
 static mpl_status derive_materials(mpl_ctx* c, const mpl_material* mats, int n) {
   for (int k = 0; k < n; ++k) {
     const mpl_material& m = mats[k];
-    if (m.model < 0 || m.model > 2 || m.plastic < 0 || m.plastic > 2)
+    if (m.model < 0 || m.model > 3 || m.plastic < 0 || m.plastic > 2)
       return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown material model or plasticity kind");
-    if (!(m.E > 0.0) || !(m.nu > -1.0 && m.nu < 0.5))
+    const bool water = m.model == MPL_WATER;
+    if (!(m.E > 0.0) || (!water && !(m.nu > -1.0 && m.nu < 0.5)))
       return mpl_fail(c, MPL_ERR_INVALID_ARG, "material needs E > 0 and -1 < nu < 0.5");
+    if (water && m.plastic != MPL_PLASTIC_NONE)
+      return mpl_fail(c, MPL_ERR_INVALID_ARG, "water takes no plasticity");
     c->mats_in[k] = m;
     MatParams& p = c->mats[k];
     p.model = m.model;
@@ -207,6 +210,10 @@ static mpl_status derive_materials(mpl_ctx* c, const mpl_material* mats, int n) 
     p.mu = m.E / (2.0 * (1.0 + m.nu));
     p.lambda = m.E * m.nu / ((1.0 + m.nu) * (1.0 - 2.0 * m.nu));
     p.kappa = 2.0 * p.mu / 3.0 + p.lambda;
+    if (water) {  // E is the bulk modulus of the J-based fluid
+      p.mu = p.lambda = 0.0;
+      p.kappa = m.E;
+    }
     p.yield_stress = m.yield_stress;
     double sphi = std::sin(m.friction_deg * M_PI / 180.0);
     p.alpha_f = std::sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi);

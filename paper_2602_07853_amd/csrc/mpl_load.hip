@@ -107,9 +107,19 @@ __global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t
     A[e] = dt * Gp[e];
   }
   A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
-  mul(A, F, Fn);
   const int k = in.mat[p];
-  double dg = plastic_project(l_mats[k], Fn);
+  double dg = 0.0;
+  if (l_mats[k].model == WATER) {
+    // J-based water: J <- (1 + dt tr G_p) J, carried as F = J^{1/3} I
+    const double Jn = (1.0 + dt * (Gp[0] + Gp[4] + Gp[8])) * det(F);
+    if (!(Jn > 0.0)) atomicOr(err, 32);
+    const double c = cbrt(Jn);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Fn[e] = (e % 4 == 0) ? c : 0.0;
+  } else {
+    mul(A, F, Fn);
+    dg = plastic_project(l_mats[k], Fn);
+  }
   const double pl = in.plastic ? in.plastic[p] : 0.0;
   for (int a = 0; a < 3; ++a) {
     out.v[3 * p + a] = vp[a];
@@ -268,6 +278,8 @@ mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const mpl_particles* in, 
              P<double>(c->vcl), P<double>(c->Gcl), ncell, dt, &c->dscal()->err);
   MPL_TRY(mpl_sync_scalars(c));
   if (c->hscal.err & 16) return mpl_fail(c, MPL_ERR_HIP, "internal: load reached an inactive block");
+  if (c->hscal.err & 32)
+    return mpl_fail(c, MPL_ERR_DOMAIN, "a water particle's volume ratio (1 + dt tr G) J is not positive");
   return MPL_OK;
 }
 

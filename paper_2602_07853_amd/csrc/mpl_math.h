@@ -23,12 +23,12 @@
 
 namespace mpl {
 
-enum { NEOHOOKEAN = 0, FIXED_COROTATED = 1, HENCKY = 2 };
+enum { NEOHOOKEAN = 0, FIXED_COROTATED = 1, HENCKY = 2, WATER = 3 };
 enum { PLASTIC_NONE = 0, PLASTIC_VON_MISES = 1, PLASTIC_DRUCKER_PRAGER = 2 };
 
 struct MatParams {
   int model, plastic;
-  double mu, lambda, kappa;   // kappa = 2 mu / 3 + lambda (split Neo-Hookean bulk modulus)
+  double mu, lambda, kappa;   // kappa: split Neo-Hookean 2 mu / 3 + lambda; water: the bulk modulus
   double yield_stress, alpha_f;
 };
 
@@ -194,7 +194,22 @@ MPL_DEV void principal_derivs(const MatParams& m, const double* s, double* d, do
                               double* tw, double* fl) {
   const int pi[3] = {0, 1, 0}, pj[3] = {1, 2, 2};
   const double J = s[0] * s[1] * s[2];
-  if (m.model == FIXED_COROTATED) {
+  if (m.model == WATER) {
+    // psi = kappa/2 (J - 1)^2: d_i = kappa (J - 1) J / s_i,
+    // H_ii = kappa J^2 / s_i^2, H_ij = kappa J (2J - 1) / (s_i s_j); both pair
+    // quotients are closed forms, -+ kappa (J - 1) J / (s_i s_j)
+    const double k = m.kappa;
+    for (int i = 0; i < 3; ++i) {
+      d[i] = k * (J - 1.0) * J / s[i];
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = (i == j) ? k * J * J / (s[i] * s[i]) : k * J * (2.0 * J - 1.0) / (s[i] * s[j]);
+    }
+    for (int p = 0; p < 3; ++p) {
+      const double q = k * (J - 1.0) * J / (s[pi[p]] * s[pj[p]]);
+      tw[p] = -q;
+      fl[p] = q;
+    }
+  } else if (m.model == FIXED_COROTATED) {
     // psi = mu sum (s_i - 1)^2 + lambda/2 (J - 1)^2
     for (int i = 0; i < 3; ++i) {
       double sjk = J / s[i];
@@ -262,6 +277,7 @@ MPL_DEV void principal_derivs(const MatParams& m, const double* s, double* d, do
 MPL_DEV double psi(const MatParams& m, const double* F) {
   const double J = det(F);
   if (!(J > 0.0)) return INFINITY;
+  if (m.model == WATER) return 0.5 * m.kappa * (J - 1.0) * (J - 1.0);
   if (m.model == NEOHOOKEAN) {
     double I = frob2(F);
     return 0.5 * m.mu * (pow(J, -2.0 / 3.0) * I - 3.0) + 0.25 * m.kappa * (J * J - 1.0 - 2.0 * log(J));
@@ -289,6 +305,11 @@ MPL_DEV bool piola(const MatParams& m, const double* F, double* P) {
   if (!(J > 0.0)) return false;
   double C[9];
   cofactor(F, C);
+  if (m.model == WATER) {  // P = kappa (J - 1) cof F
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[i] = m.kappa * (J - 1.0) * C[i];
+    return true;
+  }
   if (m.model == NEOHOOKEAN) {
     // P = mu J^{-2/3} (F - I1/3 F^{-T}) + kappa/2 (J^2 - 1) F^{-T}, F^{-T} = cof F / J
     double c = pow(J, -2.0 / 3.0), I1 = frob2(F), vol = 0.5 * m.kappa * (J * J - 1.0);
@@ -326,6 +347,13 @@ MPL_DEV bool kirchhoff(const MatParams& m, const double* F, double* tau6) {
   const double J = det(F);
   if (!(J > 0.0)) return false;
   double T[9];
+  if (m.model == WATER) {
+    // tau = pi I with the pressure pi = kappa J (J - 1)
+    const double pr = m.kappa * J * (J - 1.0);
+    tau6[0] = tau6[1] = tau6[2] = pr;
+    tau6[3] = tau6[4] = tau6[5] = 0.0;
+    return true;
+  }
   if (m.model == NEOHOOKEAN) {
     // tau = mu J^{-2/3} dev(F F^T) + kappa/2 (J^2 - 1) I
     double B[9];
@@ -388,6 +416,18 @@ MPL_DEV double cubic_largest_root(double p, double q) {
 // Returns 0 on success, 1 when the stress lies outside the model's range
 // (the result is then clamped and flagged).
 MPL_DEV int stretch_from_principal(const MatParams& m, const double* t, double* s) {
+  if (m.model == WATER) {
+    // pressure pi = mean principal stress = kappa J (J - 1), inverted on J > 0:
+    // J = (1 + sqrt(1 + 4 pi / kappa)) / 2 (no root below pi = -kappa/4: J = 1/2,
+    // flagged); isotropic base s_i = J^{1/3}
+    const double pr = (t[0] + t[1] + t[2]) / 3.0;
+    double r = 1.0 + 4.0 * pr / m.kappa;
+    int flag = 0;
+    if (r < 0.0) { r = 0.0; flag = 1; }
+    const double c = cbrt(0.5 * (1.0 + sqrt(r)));
+    s[0] = s[1] = s[2] = c;
+    return flag;
+  }
   if (m.model == HENCKY) {
     double lsum = (t[0] + t[1] + t[2]) / (2.0 * m.mu + 3.0 * m.lambda);
     for (int i = 0; i < 3; ++i) s[i] = exp((t[i] - m.lambda * lsum) / (2.0 * m.mu));

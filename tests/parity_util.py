@@ -45,4 +45,20 @@ def small_scenes():
                                                 model=scenes.FIXED_COROTATED, n_mats=2, seed=12),
         "hencky_ragged": scenes.small_block(n=12, lo=3, hi=8, strain=0.05, model=scenes.HENCKY,
                                             seed=13, vel_std=0.2),
+        "water_block": scenes.small_block(n=12, lo=3, hi=9, strain=0.05, model=scenes.WATER, E=2e5,
+                                          seed=14, vel_std=0.2),
+        "sand_water": sand_water(),
     }
+
+
+def sand_water(n=12, seed=15):
+    """Sand (StVK-Hencky + Drucker-Prager, 30 degrees) and J-based water
+    alternating by cell in one block: two materials share centres at every
+    interface (Sec. 3, Material Mixture), as in the paper's sand-and-water
+    example."""
+    sc = scenes.small_block(n=n, lo=3, hi=9, strain=0.05, model=scenes.HENCKY, E=1e5, seed=seed,
+                            vel_std=0.2, n_mats=2, plastic=scenes.PLASTIC_DRUCKER_PRAGER,
+                            friction_deg=30.0)
+    sc.materials[1] = scenes.material(scenes.WATER, 2e5, 0.0, 1000.0)
+    sc.name = f"sand_water_{n}"
+    return sc

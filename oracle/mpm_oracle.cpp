@@ -1298,18 +1298,18 @@ int or_node_to_centre(const or_grid* gg, const double* mc, const double* vnode,
 // Alg. 4: sample v, G at the centres, interpolate to particles with the same
 // w_cp as the unload (positions x^n), advect, F <- (I + dt G_p) F, then the
 // plastic projection of F (applied after the update, semi-implicitly).
-int or_load(const or_grid* gg, double dt, const double* mc, const double* vnode,
-            int64_t np, const int32_t* mat, const or_material* mats,
-            double* x, double* v, double* G, double* F, double* eps_acc) {
-  Grid g{gg->n, gg->dx};
-  const int64_t nc = g.nc();
-  std::vector<double> vc(3 * nc), Gc(9 * nc);
-  or_node_to_centre(gg, mc, vnode, vc.data(), Gc.data());
+// Alg. 4 for the particles, given the centre fields of the new velocity
+// (vc, Gc) and, for the FLIP/PIC transfer (Sec. 3, Degradation to FLIP/PIC),
+// the centre field dvc of the node velocity increment (NULL for APIC).
+static int load_particles(const Grid& g, double dt, const double* vc, const double* Gc,
+                          const double* dvc, double flip, int64_t np, const int32_t* mat,
+                          const or_material* mats, double* x, double* v, double* G, double* F,
+                          double* eps_acc) {
   int status = OR_OK;
   for (int64_t p = 0; p < np; ++p) {
     Stencil s;
     if (!make_stencil(g, x + 3 * p, &s)) return OR_ERR_OUTSIDE;
-    double vp[3] = {0, 0, 0}, Gp[9] = {0};
+    double vp[3] = {0, 0, 0}, Gp[9] = {0}, dvp[3] = {0, 0, 0};
     for (int d = 0; d < 8; ++d) {
       int o[3];
       corner(d, o);
@@ -1318,9 +1318,13 @@ int or_load(const or_grid* gg, double dt, const double* mc, const double* vnode,
       if (w == 0.0) continue;
       for (int a = 0; a < 3; ++a) vp[a] += w * vc[3 * c + a];
       for (int e = 0; e < 9; ++e) Gp[e] += w * Gc[9 * c + e];
+      if (dvc)
+        for (int a = 0; a < 3; ++a) dvp[a] += w * dvc[3 * c + a];
     }
     for (int a = 0; a < 3; ++a) {
-      v[3 * p + a] = vp[a];
+      // APIC: v_p is the interpolated new velocity.  FLIP/PIC: the PIC
+      // velocity vp advects, the particle keeps flip (v_p + dv_p) + (1 - flip) vp
+      v[3 * p + a] = dvc ? flip * (v[3 * p + a] + dvp[a]) + (1.0 - flip) * vp[a] : vp[a];
       x[3 * p + a] += dt * vp[a];
     }
     for (int e = 0; e < 9; ++e) G[9 * p + e] = Gp[e];
@@ -1342,6 +1346,34 @@ int or_load(const or_grid* gg, double dt, const double* mc, const double* vnode,
     if (st != OR_OK) status = st;
   }
   return status;
+}
+
+int or_load(const or_grid* gg, double dt, const double* mc, const double* vnode,
+            int64_t np, const int32_t* mat, const or_material* mats,
+            double* x, double* v, double* G, double* F, double* eps_acc) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nc = g.nc();
+  std::vector<double> vc(3 * nc), Gc(9 * nc);
+  or_node_to_centre(gg, mc, vnode, vc.data(), Gc.data());
+  return load_particles(g, dt, vc.data(), Gc.data(), nullptr, 0.0, np, mat, mats, x, v, G, F,
+                        eps_acc);
+}
+
+// Load with the FLIP/PIC transfer (Sec. 3, Degradation to FLIP/PIC): the new
+// node velocity and the node increment vnode - vnode_old are both sampled at
+// centres and interpolated to the particles; flip in [0, 1] is the FLIP share.
+int or_load_flip(const or_grid* gg, double dt, const double* mc, const double* vnode,
+                 const double* vnode_old, double flip, int64_t np, const int32_t* mat,
+                 const or_material* mats, double* x, double* v, double* G, double* F,
+                 double* eps_acc) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nc = g.nc(), nn = g.nn();
+  std::vector<double> vc(3 * nc), Gc(9 * nc), dvc(3 * nc), dGc(9 * nc), dv(3 * nn);
+  or_node_to_centre(gg, mc, vnode, vc.data(), Gc.data());
+  for (int64_t i = 0; i < 3 * nn; ++i) dv[i] = vnode[i] - vnode_old[i];
+  or_node_to_centre(gg, mc, dv.data(), dvc.data(), dGc.data());
+  return load_particles(g, dt, vc.data(), Gc.data(), dvc.data(), flip, np, mat, mats, x, v, G, F,
+                        eps_acc);
 }
 
 // Alg. 1: Unload -> Integrate (implicit) -> Load.  External gravity enters

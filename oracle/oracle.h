@@ -118,6 +118,13 @@ int or_node_to_centre(const or_grid* g, const double* mc, const double* vnode,
 int or_load(const or_grid* g, double dt, const double* mc, const double* vnode,
             int64_t np, const int32_t* mat, const or_material* mats,
             double* x, double* v, double* G, double* F, double* eps_acc);
+/* Load with the FLIP/PIC transfer (Sec. 3, Degradation to FLIP/PIC):
+ * v_p <- flip (v_p + dv_p) + (1 - flip) v_PIC with dv the increment
+ * vnode - vnode_old sampled like v; x advects with v_PIC. */
+int or_load_flip(const or_grid* g, double dt, const double* mc, const double* vnode,
+                 const double* vnode_old, double flip, int64_t np, const int32_t* mat,
+                 const or_material* mats, double* x, double* v, double* G, double* F,
+                 double* eps_acc);
 int or_step(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
             const double gravity[3], int32_t nbc, const or_bc* bcs, double time,
             const or_solver_opts* opts, int64_t np, double* x, double* v, double* G,

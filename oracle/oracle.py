@@ -334,6 +334,55 @@ def step(grid: Grid, mats, dt, gravity, bcs, time, opts: SolverOpts, parts: dict
     return out, stats, vnode, rc
 
 
+def load_flip(grid: Grid, dt, mc, vnode, vnode_old, parts: dict, mats, flip):
+    """Load with the FLIP/PIC transfer (Sec. 3, Degradation to FLIP/PIC).
+    Returns a new particle dict (input untouched)."""
+    out = {k: np.array(v, dtype=np.float64 if k != "mat" else np.int32, copy=True)
+           for k, v in parts.items()}
+    if "eps" not in out:
+        out["eps"] = np.zeros(len(out["m"]))
+    mat = np.ascontiguousarray(out["mat"], dtype=np.int32)
+    rc = lib().or_load_flip(C.byref(grid.c()), C.c_double(dt), _p(_f64(mc)), _p(_f64(vnode)),
+                            _p(_f64(vnode_old)), C.c_double(flip), C.c_int64(len(out["m"])),
+                            _p(mat, C.c_int32), _mats(mats), _p(out["x"]), _p(out["v"]),
+                            _p(out["G"]), _p(out["F"]), _p(out["eps"]))
+    out["rc"] = rc
+    return out
+
+
+def step_flip(grid: Grid, mats, dt, gravity, bcs, time, parts: dict, flip, opts=None):
+    """One step with the FLIP/PIC transfer (Sec. 3, Degradation to FLIP/PIC),
+    composed from the pinned stages: the unload without the affine terms (the
+    particles' G does not enter the grid, so centre and node velocities are
+    plain weighted averages), the Dirichlet sets and vhat of Alg. 1, then the
+    implicit solve (``opts``) or, with ``opts`` None, the explicit update of
+    Eq. explicitforce, and the FLIP/PIC load with the unloaded node velocity
+    as v^n.  Returns (new parts, node velocity, rc)."""
+    p0 = dict(parts)
+    p0["G"] = np.zeros_like(np.asarray(parts["G"], dtype=np.float64))
+    u = unload(grid, p0, mats)
+    if u["rc"] not in (OK, ERR_DOMAIN):
+        return None, None, u["rc"]
+    fixed, vfix = node_bcs(grid, u["mi"], bcs, time)
+    act = u["mi"] > 0
+    free = act & (fixed == 0)
+    vhat = np.where(fixed[:, None] > 0, vfix,
+                    np.where(act[:, None], u["vi"] + dt * np.asarray(gravity, dtype=np.float64), 0.0))
+    if opts is None:
+        f = explicit_force(grid, u["Vck"], u["tauck"])
+        vnew = vhat.copy()
+        vnew[free] += dt * f[free] / u["mi"][free, None]
+    else:
+        S, rc = reconstruct(grid, mats, u["Vck"], u["tauck"])
+        if rc not in (OK, ERR_DOMAIN):
+            return None, None, rc
+        vnew, _, rc = solve(grid, mats, dt, u["mc"], u["mi"], vhat, fixed, u["Vck"], S, opts)
+        if rc != OK:
+            return None, None, rc
+    out = load_flip(grid, dt, u["mc"], vnew, u["vi"], parts, mats, flip)
+    return out, vnew, out["rc"]
+
+
 def step_explicit(grid: Grid, mats, dt, gravity, bcs, time, parts: dict):
     """Explicit branch of the Integrate algorithm (Sec. 4 opening, Eq.
     explicitforce) between unload and load, on a copy of ``parts``; returns

@@ -426,3 +426,61 @@ def test_explicit_velocity_change_is_linear_in_dt():
         dvs.append(vnode - u["vi"])
     assert np.abs(dvs[0]).max() > 0
     assert np.abs(dvs[1] - 2 * dvs[0]).max() <= 1e-12 * np.abs(dvs[1]).max()
+
+
+# ---------------------------------------------------------------- FLIP/PIC transfer
+def test_flip_unload_is_plain_averaging():
+    """Without the affine terms (Sec. 3, Degradation to FLIP/PIC) a uniform
+    particle velocity reaches every node with mass unchanged, whatever G_p;
+    the APIC unload of the same particles carries their G into the nodes."""
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.05)
+    p = {k: np.array(v, copy=True) for k, v in sc.particles.items()}
+    v0 = np.array([0.3, -0.2, 0.1])
+    p["v"][:] = v0
+    p["G"] = np.random.default_rng(70).normal(size=p["G"].shape)
+    apic = O.unload(g, p, mats)
+    p0 = dict(p)
+    p0["G"] = np.zeros_like(p["G"])
+    flip = O.unload(g, p0, mats)
+    act = flip["mi"] > 0
+    assert np.abs(flip["vi"][act] - v0).max() <= 1e-14
+    assert np.abs(apic["vi"][act] - v0).max() > 1e-3
+
+
+def test_pic_load_is_the_apic_load_and_flip_adds_increments():
+    """flip = 0 reproduces the APIC load (x, v, G, F); flip = 1 with a uniform
+    node increment c gives v_p^n + c exactly (the weights sum to 1); the
+    result is linear in flip."""
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.05)
+    u = O.unload(g, sc.particles, mats)
+    rng = np.random.default_rng(71)
+    act = (u["mi"] > 0)[:, None]
+    vnew = (u["vi"] + 0.2 * rng.normal(size=u["vi"].shape)) * act
+    ref = O.load(g, sc.dt, u["mc"], vnew, sc.particles, mats)
+    pic = O.load_flip(g, sc.dt, u["mc"], vnew, u["vi"], sc.particles, mats, 0.0)
+    for k in ("x", "v", "G", "F"):
+        assert np.abs(pic[k] - ref[k]).max() <= 1e-14 * max(1.0, np.abs(ref[k]).max()), k
+    c = np.array([0.05, -0.1, 0.2])
+    shifted = (u["vi"] + c) * act
+    fl = O.load_flip(g, sc.dt, u["mc"], shifted, u["vi"], sc.particles, mats, 1.0)
+    assert np.abs(fl["v"] - (sc.particles["v"] + c)).max() <= 1e-14
+    half = O.load_flip(g, sc.dt, u["mc"], vnew, u["vi"], sc.particles, mats, 0.5)
+    one = O.load_flip(g, sc.dt, u["mc"], vnew, u["vi"], sc.particles, mats, 1.0)
+    assert np.abs(half["v"] - 0.5 * (one["v"] + pic["v"])).max() <= 1e-14
+    assert np.array_equal(half["x"], pic["x"])
+
+
+@pytest.mark.parametrize("flip", [0.0, 0.95, 1.0])
+def test_flip_explicit_step_conserves_particle_momentum(flip):
+    """No Dirichlet nodes, no gravity: the internal forces sum to zero, the
+    averaging unload and the gather conserve momentum, and so does the FLIP
+    increment (sum_p m_p dv_p = sum_i m_i dv_i): the particles' total
+    momentum is unchanged by an explicit FLIP/PIC step."""
+    sc, g, mats = scene_small(n=8, lo=2, hi=6, strain=0.1, vel_std=0.2)
+    out, vnode, rc = O.step_flip(g, mats, sc.dt, (0.0, 0.0, 0.0), [], 0.0, sc.particles, flip)
+    assert rc == 0
+    m = sc.particles["m"]
+    p0 = m @ sc.particles["v"]
+    p1 = m @ out["v"]
+    assert np.abs(p1 - p0).max() <= 1e-13 * np.abs(m[:, None] * sc.particles["v"]).sum()
+    assert np.abs(out["v"] - sc.particles["v"]).max() > 1e-6

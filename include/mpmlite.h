@@ -109,7 +109,17 @@ typedef struct {
                              energy norm of the error, (W^T H W) c = W^T b with the current
                              tangent (three extra products and one host synchronisation per
                              solve); 0: start from zero */
+  int32_t transfer;       /* MPL_TRANSFER_APIC: the paper's transfers with the affine terms of
+                             G_p and G_c (default); MPL_TRANSFER_FLIP_PIC: their FLIP/PIC
+                             degradation (Sec. 3, Degradation to FLIP/PIC): G_p does not enter
+                             the grid (centre and node velocities are plain weighted averages),
+                             and the load interpolates the new node velocity (PIC, which also
+                             advects) and the node increment v - v^n (FLIP, added to v_p^n) */
+  double flip_ratio;      /* MPL_TRANSFER_FLIP_PIC: v_p <- flip_ratio v_FLIP + (1 - flip_ratio)
+                             v_PIC, in [0, 1] */
 } mpl_solver_opts;
+
+enum { MPL_TRANSFER_APIC = 0, MPL_TRANSFER_FLIP_PIC = 1 };
 
 typedef struct {
   int64_t n;

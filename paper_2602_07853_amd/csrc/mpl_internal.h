@@ -97,7 +97,7 @@ struct mpl_ctx {
   DevBuf cflag, cmap, nflag, nmap, scan_tmp, ccoord, ncoord, c_nbr_node, n_nbr_cell,
       pcell, pkey, bin_count, bin_start, bin_fill, sorted;
   // cell fields (FP64 unless noted)
-  DevBuf mc, qc, Gc, Vk, Tk, Sk, Qc, ecell, Abar32, Abar64, Y32, Y64, vcl, Gcl;
+  DevBuf mc, qc, Gc, Vk, Tk, Sk, Qc, ecell, Abar32, Abar64, Y32, Y64, vcl, Gcl, dvcl;
   // tangent storage: only cells with some V_{c,k} != 0, block-major
   // (Abar[45*coff[cb] + e*count(cb) + rank]), with a 64-bit active mask per
   // cell block (see tan_slot in mpl_grid.h)

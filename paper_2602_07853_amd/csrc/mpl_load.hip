@@ -21,14 +21,18 @@ struct ParticlesOut {
 
 // v_c = sum_i w_ic v_i (w_ic = 1/8), G_c = sum_i v_i (x) grad w_ic on cells
 // with m_c != 0 (hourglass modes of v_i vanish here, Sec. 6).
+// With vold (the FLIP/PIC transfer) the node increment v - vold is sampled
+// the same way into dvcl.
 __global__ __launch_bounds__(64) void k_n2c(const double* __restrict__ v, int64_t nnode,
                                             const int* __restrict__ c_nbr_node,
                                             const double* __restrict__ mc, int64_t ncell,
                                             double inv4dx, double* __restrict__ vcl,
-                                            double* __restrict__ Gcl) {
+                                            double* __restrict__ Gcl,
+                                            const double* __restrict__ vold,
+                                            double* __restrict__ dvcl) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
-  double vc[3] = {0, 0, 0}, G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double vc[3] = {0, 0, 0}, G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dvc[3] = {0, 0, 0};
   if (mc[ci] != 0.0) {
     for (int d = 0; d < 8; ++d) {
       const int ni = corner_node(c_nbr_node, cb, l, d);
@@ -37,19 +41,25 @@ __global__ __launch_bounds__(64) void k_n2c(const double* __restrict__ v, int64_
       for (int a = 0; a < 3; ++a) {
         const double va = v[a * nnode + ni];
         vc[a] += va / 8.0;
+        if (vold) dvc[a] += (va - vold[a * nnode + ni]) / 8.0;
         for (int b = 0; b < 3; ++b) G[a * 3 + b] += va * gw[b];
       }
     }
   }
   for (int a = 0; a < 3; ++a) vcl[a * ncell + ci] = vc[a];
   for (int e = 0; e < 9; ++e) Gcl[e * ncell + ci] = G[e];
+  if (vold)
+    for (int a = 0; a < 3; ++a) dvcl[a * ncell + ci] = dvc[a];
 }
 
 // v_p = sum_c w_cp v_c, G_p = sum_c w_cp G_c (weights at x^n, as in the
 // unload), x += dt v_p, F <- (I + dt G_p) F, then the plastic projection.
+// FLIP/PIC transfer (dvcl non-null): v_p <- flip (v_p^n + dv_p) + (1 - flip) v_PIC
+// with dv_p interpolated from the centre increments; x advects with v_PIC.
 __global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t* __restrict__ cmap,
                       const double* __restrict__ vcl, const double* __restrict__ Gcl, int64_t ncell,
-                      double dt, int32_t* __restrict__ err) {
+                      double dt, const double* __restrict__ dvcl, double flip,
+                      int32_t* __restrict__ err) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= in.n) return;
   double xp[3], f[3];
@@ -101,6 +111,18 @@ __global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t
       for (int e = 0; e < 9; ++e) Gp[e] += w[d] * GG[k][e];
     }
   }
+  double vnew[3] = {vp[0], vp[1], vp[2]};
+  if (dvcl) {
+    double dvp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      if (w[d] == 0.0 || ci[d] < 0) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dvp[a] += w[d] * dvcl[a * ncell + ci[d]];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vnew[a] = flip * (in.v[3 * p + a] + dvp[a]) + (1.0 - flip) * vp[a];
+  }
   double F[9], A[9], Fn[9];
   for (int e = 0; e < 9; ++e) {
     F[e] = in.F[9 * p + e];
@@ -122,7 +144,7 @@ __global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t
   }
   const double pl = in.plastic ? in.plastic[p] : 0.0;
   for (int a = 0; a < 3; ++a) {
-    out.v[3 * p + a] = vp[a];
+    out.v[3 * p + a] = vnew[a];
     out.x[3 * p + a] = xp[a] + dt * vp[a];
   }
   for (int e = 0; e < 9; ++e) {
@@ -270,12 +292,16 @@ mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const mpl_particles* in, 
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(mpl_ensure(c, c->vcl, 8 * 3 * ncell));
   MPL_TRY(mpl_ensure(c, c->Gcl, 8 * 9 * ncell));
+  const bool flip = c->opts.transfer == MPL_TRANSFER_FLIP_PIC;
+  if (flip) MPL_TRY(mpl_ensure(c, c->dvcl, 8 * 3 * ncell));
   MPL_LAUNCH(c, k_n2c, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->mc), ncell,
-             0.25 * c->inv_dx, P<double>(c->vcl), P<double>(c->Gcl));
+             0.25 * c->inv_dx, P<double>(c->vcl), P<double>(c->Gcl),
+             flip ? P<double>(c->vn) : (const double*)nullptr, flip ? P<double>(c->dvcl) : nullptr);
   ParticlesIn pi{in->x, in->v, in->F, in->G, in->m, in->V0, in->plastic, in->mat, in->n};
   ParticlesOut po{out->x, out->v, out->F, out->G, out->plastic};
   MPL_LAUNCH(c, k_c2p, (int)((in->n + 255) / 256), 256, pi, po, grid_dev(c), P<int32_t>(c->cmap),
-             P<double>(c->vcl), P<double>(c->Gcl), ncell, dt, &c->dscal()->err);
+             P<double>(c->vcl), P<double>(c->Gcl), ncell, dt,
+             flip ? P<double>(c->dvcl) : (const double*)nullptr, c->opts.flip_ratio, &c->dscal()->err);
   MPL_TRY(mpl_sync_scalars(c));
   if (c->hscal.err & 16) return mpl_fail(c, MPL_ERR_HIP, "internal: load reached an inactive block");
   if (c->hscal.err & 32)

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
         double xi = (xp[a] - g.origin[a]) / g.dx - 0.5;
         f[a] = xi - floor(xi);
       }
-      for (int j = 0; j < 9; ++j) Gp[j] = P.G[9 * p + j];
+      for (int j = 0; j < 9; ++j) Gp[j] = P.G ? P.G[9 * p + j] : 0.0;
       mp = P.m[p];
       Vp = P.V[p];
       k = P.mat[p];
@@ -483,7 +483,10 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   const int ncb_dense = c->cbd[0] * c->cbd[1] * c->cbd[2];
   const int nnb_dense = c->nbd[0] * c->nbd[1] * c->nbd[2];
   const int64_t np = in->n;
-  ParticlesDev parts{in->x, in->v, in->F, in->G, in->m, in->V0, in->mat, np};
+  // FLIP/PIC transfer: the particles' G does not enter the grid (a null G
+  // reads as zero), so G_c = 0 and the centre->node affine term vanishes
+  const double* Gin = c->opts.transfer == MPL_TRANSFER_FLIP_PIC ? nullptr : in->G;
+  ParticlesDev parts{in->x, in->v, in->F, Gin, in->m, in->V0, in->mat, np};
 
   MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(c_mats), c->mats, sizeof(MatParams) * MPL_MAX_MATERIALS,
                                     0, hipMemcpyHostToDevice, c->stream));

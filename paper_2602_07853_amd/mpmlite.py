@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmpmlite.so")
 
 F32, F64 = 0, 1
 PRECOND_JACOBI, PRECOND_LEARNED = 0, 2
+TRANSFER_APIC, TRANSFER_FLIP_PIC = 0, 1
 NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
 BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
 
@@ -48,7 +49,8 @@ class _Opts(C.Structure):
     _fields_ = [("hv_precision", C.c_int32), ("precond", C.c_int32), ("newton_rtol", C.c_double),
                 ("pcg_rtol", C.c_double), ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
                 ("max_ls", C.c_int32), ("armijo_c", C.c_double), ("pcg_check_every", C.c_int32),
-                ("time_kernels", C.c_int32), ("warm_start", C.c_int32)]
+                ("time_kernels", C.c_int32), ("warm_start", C.c_int32), ("transfer", C.c_int32),
+                ("flip_ratio", C.c_double)]
 
 
 class _Particles(C.Structure):
@@ -149,7 +151,7 @@ def particles_to_device(parts: dict, device="cuda") -> dict:
 def default_opts(**kw) -> dict:
     o = dict(hv_precision=F32, precond=PRECOND_JACOBI, newton_rtol=1e-6, pcg_rtol=1e-6,
              max_newton=50, max_pcg=20000, max_ls=40, armijo_c=1e-4, pcg_check_every=16,
-             time_kernels=0, warm_start=0)
+             time_kernels=0, warm_start=0, transfer=TRANSFER_APIC, flip_ratio=0.0)
     o.update(kw)
     return o
 
@@ -182,11 +184,10 @@ class Context:
         self._ctx = ctx
 
     def _copts(self):
+        # every struct field by name, so an added option cannot arrive as zero
         o = self.opts
-        return _Opts(int(o["hv_precision"]), int(o["precond"]), float(o["newton_rtol"]),
-                     float(o["pcg_rtol"]), int(o["max_newton"]), int(o["max_pcg"]),
-                     int(o["max_ls"]), float(o["armijo_c"]), int(o["pcg_check_every"]),
-                     int(o["time_kernels"]), int(o["warm_start"]))
+        return _Opts(**{name: (int(o[name]) if ctype is C.c_int32 else float(o[name]))
+                        for name, ctype in _Opts._fields_})
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(64) void k_n2c(const double* __restrict__ v, int64_
 // unload), x += dt v_p, F <- (I + dt G_p) F, then the plastic projection.
 // FLIP/PIC transfer (dvcl non-null): v_p <- flip (v_p^n + dv_p) + (1 - flip) v_PIC
 // with dv_p interpolated from the centre increments; x advects with v_PIC.
-__global__ void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g, const int32_t* __restrict__ cmap,
+__global__ __launch_bounds__(256) void k_c2p(ParticlesIn in, ParticlesOut out, GridDev g,
+                                             const int32_t* __restrict__ cmap,
                       const double* __restrict__ vcl, const double* __restrict__ Gcl, int64_t ncell,
                       double dt, const double* __restrict__ dvcl, double flip,
                       int32_t* __restrict__ err) {

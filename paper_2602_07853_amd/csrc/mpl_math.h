@@ -350,11 +350,9 @@ MPL_DEV bool kirchhoff(const MatParams& m, const double* F, double* tau6) {
   if (m.model == WATER) {
     // tau = pi I with the pressure pi = kappa J (J - 1)
     const double pr = m.kappa * J * (J - 1.0);
-    tau6[0] = tau6[1] = tau6[2] = pr;
-    tau6[3] = tau6[4] = tau6[5] = 0.0;
-    return true;
-  }
-  if (m.model == NEOHOOKEAN) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) T[i] = (i % 4 == 0) ? pr : 0.0;
+  } else if (m.model == NEOHOOKEAN) {
     // tau = mu J^{-2/3} dev(F F^T) + kappa/2 (J^2 - 1) I
     double B[9];
     mul_nt(F, F, B);

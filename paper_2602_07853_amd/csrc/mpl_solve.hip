@@ -49,8 +49,8 @@ __device__ __forceinline__ void cell_grad(const T* __restrict__ v, int64_t nnode
   }
 }
 
-__global__ void k_reconstruct(const double* __restrict__ Vk, const double* __restrict__ Tk,
-                              double* __restrict__ Sk, int64_t ncell, int K,
+__global__ __launch_bounds__(128) void k_reconstruct(const double* __restrict__ Vk, const double* __restrict__ Tk,
+                                                     double* __restrict__ Sk, int64_t ncell, int K,
                               int32_t* __restrict__ domain_count) {
   int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ci >= ncell) return;

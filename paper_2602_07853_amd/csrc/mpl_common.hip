@@ -293,7 +293,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->c_nbr_node, &c->n_nbr_cell, &c->pcell, &c->pkey,
                    &c->bin_count, &c->bin_start, &c->bin_fill, &c->sorted, &c->mc, &c->qc, &c->Gc,
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
-                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
+                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,

@@ -36,6 +36,14 @@ struct DevBuf {
 };
 struct NNState;
 
+// Dirichlet boxes of the current step as the centre->node kernel reads them
+// (a per-context device copy, so that contexts on other streams never share it).
+struct BCDev {
+  int n;
+  int kind[16];
+  double lo[16][3], hi[16][3], vel[16][3];
+};
+
 struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -122,6 +130,9 @@ struct mpl_ctx {
   int collect_every = 0;
   double collect_rtol = 1e-10;
   DevBuf xstar;
+  DevBuf bcbuf;     // device copy of bc_host
+  DevBuf cntbuf;    // per-block active/free counts of the unload
+  BCDev bc_host{};  // host staging of the step's Dirichlet boxes (outlives the async copy)
   int fallbacks_total = 0;
   // online training of the learned preconditioner during Newton solves
   // (energy-norm loss on the solver's own residuals; 0 = off)

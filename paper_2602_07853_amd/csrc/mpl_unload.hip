@@ -28,12 +28,6 @@ struct ParticlesDev {
   int64_t n;
 };
 
-struct BCDev {
-  int n;
-  int kind[16];
-  double lo[16][3], hi[16][3], vel[16][3];
-};
-
 __constant__ MatParams c_mats[MPL_MAX_MATERIALS];
 
 __global__ void k_mark(ParticlesDev P, GridDev g, int32_t* __restrict__ pcell,
@@ -116,6 +110,27 @@ __global__ void k_neighbours(const int4* __restrict__ ccoord, const int4* __rest
         id = cmap[(cx * g.cbd[1] + cy) * g.cbd[2] + cz];
       n_nbr_cell[i * 8 + o] = id;
     }
+  }
+}
+
+// Column sums of a block-major [n][ncols] int32 array (ncols <= 2) by one
+// workgroup in a fixed order, written to out[0..ncols).
+__global__ __launch_bounds__(1024) void k_sum_counts(const int32_t* __restrict__ part, int n, int ncols,
+                                                     int32_t* __restrict__ out) {
+  __shared__ int32_t sh[2][16];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  for (int col = 0; col < ncols; ++col) {
+    int32_t acc = 0;
+    for (int i = t; i < n; i += 1024) acc += part[(int64_t)i * ncols + col];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (l == 0) sh[col][w] = acc;
+  }
+  __syncthreads();
+  if (t < ncols) {
+    int32_t s = 0;
+    for (int k = 0; k < 16; ++k) s += sh[t][k];
+    out[t] = s;
   }
 }
 
@@ -332,9 +347,9 @@ __global__ __launch_bounds__(64) void k_p2c_combine(const int* __restrict__ c_nb
     for (int v = 1; v < 13; ++v) acc[v] /= m;
   }
   {
-    // occupied-cell count: one atomic per wavefront (the block is one wave)
+    // occupied-cell count of the block (one wave), summed by k_sum_counts
     const uint64_t bm = __ballot(m != 0.0);
-    if (l == 0 && bm) atomicAdd(count, (int32_t)__popcll(bm));
+    if (l == 0) count[cb] = (int32_t)__popcll(bm);
   }
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
@@ -374,13 +389,17 @@ __global__ __launch_bounds__(64) void k_cell_mask(const double* __restrict__ Vk,
 }
 
 // Sec. 3.3 centre -> node gather with w_ic = 1/8 (race-free: every node
-// gathers from its own 8 cells), then Dirichlet sets and vhat.
+// gathers from its own 8 cells), then Dirichlet sets and vhat.  One wave per
+// node block (XCD-major); the block's 5x5x5 centre tile goes through LDS so
+// that every centre value is read from memory once per block, not once per
+// corner.
 __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict__ n_nbr_cell,
                                             const int4* __restrict__ ncoord,
                                             const double* __restrict__ mc,
                                             const double* __restrict__ vc,
                                             const double* __restrict__ Gc, int64_t ncell,
-                                            int64_t nnode, int n_nblk, BCDev bcs, double time, double dt,
+                                            int64_t nnode, int n_nblk, const BCDev* __restrict__ bcp,
+                                            double time, double dt,
                                             double gx, double gy, double gz,
                                             double* __restrict__ mi, double* __restrict__ vn,
                                             double* __restrict__ vhat, double* __restrict__ v,
@@ -389,37 +408,40 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
   const int nb = xcd_block(blockIdx.x, n_nblk), l = threadIdx.x;
   if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
+  // the 5x5x5 tile of centres around the block's nodes (cells -1..3 along
+  // each axis, from the block and its -x/-y/-z neighbours) is staged in LDS
+  // once: m, v (3) and G (9) per centre, zeros for absent blocks
+  __shared__ double tile[13][128];
+  for (int t = l; t < 125; t += 64) {
+    const int cx = t / 25 - 1, cy = (t / 5) % 5 - 1, cz = t % 5 - 1;
+    const int o = ((cx < 0) * 2 + (cy < 0)) * 2 + (cz < 0);
+    const int blk = n_nbr_cell[nb * 8 + o];
+    const int64_t ci = (int64_t)(blk < 0 ? 0 : blk) * MPL_BC + local_index(cx & 3, cy & 3, cz & 3);
+    double val[13];
+    val[0] = mc[ci];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) val[1 + a] = vc[a * ncell + ci];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) val[4 + e] = Gc[e * ncell + ci];
+#pragma unroll
+    for (int v2 = 0; v2 < 13; ++v2) tile[v2][t] = blk < 0 ? 0.0 : val[v2];
+  }
+  __syncthreads();
   double m = 0.0, q[3] = {0.0, 0.0, 0.0};
-  // corner by corner in a fixed order, in two batches of four corners whose
-  // loads are all issued before any is used.  An absent centre reads centre
-  // 0 and an empty one its own zeros; both enter with weight 0 and add exact
-  // zeros, so no branch separates the loads from their use.
+  // corner by corner in a fixed order; an absent or empty centre has m = 0,
+  // enters with weight 0 and adds exact zeros
+  const int lx = local_x(l), ly = local_y(l), lz = local_z(l);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    double mcc[4], vcc[4][3], G[4][9];
-    bool ok[4];
+  for (int d = 0; d < 8; ++d) {
+    const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+    const int t = ((lx - dx + 1) * 5 + (ly - dy + 1)) * 5 + (lz - dz + 1);
+    const double wm = tile[0][t] / 8.0;
+    const double r[3] = {(dx - 0.5) * g.dx, (dy - 0.5) * g.dx, (dz - 0.5) * g.dx};
+    m += wm;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cv = node_cell(n_nbr_cell, nb, l, 4 * h + j);
-      ok[j] = cv >= 0;
-      const int64_t ci = ok[j] ? cv : 0;
-      mcc[j] = mc[ci];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) vcc[j][a] = vc[a * ncell + ci];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) G[j][e] = Gc[e * ncell + ci];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int d = 4 * h + j;
-      const double wm = ok[j] ? mcc[j] / 8.0 : 0.0;
-      const double r[3] = {(((d >> 2) & 1) - 0.5) * g.dx, (((d >> 1) & 1) - 0.5) * g.dx, ((d & 1) - 0.5) * g.dx};
-      m += wm;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double aff = G[j][a * 3] * r[0] + G[j][a * 3 + 1] * r[1] + G[j][a * 3 + 2] * r[2];
-        q[a] += wm * (vcc[j][a] + aff);
-      }
+    for (int a = 0; a < 3; ++a) {
+      const double aff = tile[4 + a * 3][t] * r[0] + tile[5 + a * 3][t] * r[1] + tile[6 + a * 3][t] * r[2];
+      q[a] += wm * (tile[1 + a][t] + aff);
     }
   }
   double vv[3] = {0.0, 0.0, 0.0};
@@ -434,6 +456,7 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
     double xn[3];
     for (int a = 0; a < 3; ++a) xn[a] = g.origin[a] + idx[a] * g.dx;
     const double eps = 1e-6 * g.dx;
+    const BCDev& bcs = *bcp;
     for (int b = 0; b < bcs.n; ++b) {
       bool in = true;
       for (int a = 0; a < 3; ++a) {
@@ -447,12 +470,13 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
     if (!(fl & MPL_NODE_FIXED)) fl |= MPL_NODE_FREE;
   }
   {
-    // active and free node counts: one atomic per wavefront (the block is
-    // one wave), not one per node on the same two addresses
+    // active and free node counts of the block (one wave), summed later by
+    // k_sum_counts: device-scope atomics on one address from every wave
+    // serialise at the memory side
     const uint64_t ba = __ballot((fl & MPL_NODE_ACTIVE) != 0), bf = __ballot((fl & MPL_NODE_FREE) != 0);
     if (l == 0) {
-      if (ba) atomicAdd(&counts[0], (int32_t)__popcll(ba));
-      if (bf) atomicAdd(&counts[1], (int32_t)__popcll(bf));
+      counts[2 * nb] = (int32_t)__popcll(ba);
+      counts[2 * nb + 1] = (int32_t)__popcll(bf);
     }
   }
   const double grav[3] = {gx, gy, gz};
@@ -560,13 +584,16 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   // P2C: one pass over all active blocks (own centres + staged halos), then
   // the combine / normalise pass
   MPL_TRY(mpl_ensure(c, c->p2c_halo, sizeof(double) * (13 + 7 * K) * (size_t)c->n_cblk * MPL_BC + 64));
+  // per-block counts: n_cblk for the combine pass, then 2 n_nblk for the gather
+  MPL_TRY(mpl_ensure(c, c->cntbuf, sizeof(int32_t) * (2 * (size_t)std::max(c->n_cblk, c->n_nblk) + 64)));
 #define MPL_P2C(KK)                                                                                     \
   MPL_LAUNCH(c, k_p2c<KK>, c->n_cblk, 64, parts, g, P<int32_t>(c->sorted), bstart, \
              P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), \
              P<double>(c->Vk), P<double>(c->Tk), ncell, P<double>(c->p2c_halo), &ds->err);             \
   MPL_LAUNCH(c, k_p2c_combine<KK>, c->n_cblk, 64, P<int>(c->c_nbr_node), P<int>(c->n_nbr_cell),         \
              c->n_cblk, P<double>(c->p2c_halo), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc),   \
-             P<double>(c->Vk), P<double>(c->Tk), ncell, &ds->n_active_cells, &ds->err)
+             P<double>(c->Vk), P<double>(c->Tk), ncell, P<int32_t>(c->cntbuf), &ds->err);            \
+  MPL_LAUNCH(c, k_sum_counts, 1, 1024, P<int32_t>(c->cntbuf), c->n_cblk, 1, &ds->n_active_cells)
   switch (K) {
     case 1: MPL_P2C(1); break;
     case 2: MPL_P2C(2); break;
@@ -581,7 +608,8 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
              P<int32_t>(c->ccnt));
   MPL_TRY(mpl_scan_i32(c, P<int32_t>(c->ccnt), P<int32_t>(c->coff), c->n_cblk, &ds->n_tan_cells));
 
-  BCDev bd{};
+  BCDev& bd = c->bc_host;
+  bd = BCDev{};
   bd.n = n_bcs;
   for (int b = 0; b < n_bcs; ++b) {
     bd.kind[b] = bcs[b].kind;
@@ -591,12 +619,16 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
       bd.vel[b][a] = bcs[b].velocity[a];
     }
   }
+  MPL_TRY(mpl_ensure(c, c->bcbuf, sizeof(BCDev)));
+  MPL_HIP(c, hipMemcpyAsync(c->bcbuf.p, &bd, sizeof(BCDev), hipMemcpyHostToDevice, c->stream));
   const double gz[3] = {0.0, 0.0, 0.0};
   const double* gr = gravity ? gravity : gz;
   MPL_LAUNCH(c, k_c2n, xcd_grid(c->n_nblk), 64, g, P<int32_t>(c->n_nbr_cell), P<int4>(c->ncoord),
-             P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, c->n_nblk, bd, time, dt, gr[0],
+             P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, c->n_nblk, P<BCDev>(c->bcbuf), time, dt, gr[0],
              gr[1], gr[2], P<double>(c->mi), P<double>(c->vn), P<double>(c->vhat), P<double>(c->v),
-             P<uint8_t>(c->flags), &ds->n_active_nodes);
+             P<uint8_t>(c->flags), P<int32_t>(c->cntbuf));
+  // n_active_nodes and n_free_nodes are adjacent in SolverScalars
+  MPL_LAUNCH(c, k_sum_counts, 1, 1024, P<int32_t>(c->cntbuf), c->n_nblk, 2, &ds->n_active_nodes);
   MPL_TRY(mpl_sync_scalars(c));
   if (c->hscal.err & 2) return mpl_fail(c, MPL_ERR_DOMAIN, "particle F outside the model domain (det F <= 0) or bad material id");
   if (c->hscal.err & 4) return mpl_fail(c, MPL_ERR_HIP, "internal: scatter reached an inactive block");

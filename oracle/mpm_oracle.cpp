@@ -1142,6 +1142,41 @@ int or_explicit_force(const or_grid* gg, int32_t nmat, const double* Vck,
   return OR_OK;
 }
 
+int or_plastic_base(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
+                    const double* Vck, const double* S0, const double* v, double* Seff) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nc = g.nc();
+  int status = OR_OK;
+#pragma omp parallel for schedule(static) reduction(min : status)
+  for (int64_t c = 0; c < nc; ++c) {
+    int i = (int)(c / ((int64_t)g.n * g.n)), j = (int)((c / g.n) % g.n), kk = (int)(c % g.n);
+    bool need = false;
+    for (int k = 0; k < nmat; ++k)
+      need = need || (Vck[k * nc + c] != 0.0 && mats[k].plastic != OR_PLASTIC_NONE);
+    double A[9], Ai[9];
+    if (need) {
+      double Gm[9];
+      cell_velocity_gradient(g, i, j, kk, v, Gm);
+      for (int e = 0; e < 9; ++e) A[e] = dt * Gm[e];
+      A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
+      if (!m3_inverse(A, Ai)) need = false, status = std::min(status, (int)OR_ERR_DOMAIN);
+    }
+    for (int k = 0; k < nmat; ++k) {
+      const double* S = S0 + (k * nc + c) * 9;
+      double* Se = Seff + (k * nc + c) * 9;
+      for (int e = 0; e < 9; ++e) Se[e] = S[e];
+      if (!need || Vck[k * nc + c] == 0.0 || mats[k].plastic == OR_PLASTIC_NONE) continue;
+      double F[9];
+      m3_mul(A, S, F);
+      double inc = 0.0;
+      int st = plastic_project(&mats[k], F, &inc);
+      if (st != OR_OK) { status = std::min(status, st); continue; }
+      if (inc > 0.0) m3_mul(Ai, F, Se);
+    }
+  }
+  return status;
+}
+
 // Newton's method on Phi with the projected Hessian, Jacobi-preconditioned CG
 // for each linear system and Armijo backtracking (halving, with a rounding
 // allowance) and the model's feasibility (Phi = +inf outside the domain).
@@ -1185,15 +1220,25 @@ int or_jacobi_diag(const or_grid* gg, const double* mc, const double* mi, const 
 
 int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
-             const double* Vck, const double* Sck, const or_solver_opts* opts,
+             const double* Vck, const double* S0, const or_solver_opts* opts,
              double* v, or_solver_stats* stats) {
   Grid g{gg->n, gg->dx};
   const int64_t nc = g.nc(), nn = g.nn(), nd = 3 * nn;
   std::vector<double> grad(nd), Abar(81 * nc), p(nd), r(nd), z(nd), q(nd), x(nd), D(nd),
       vt(nd), dir(nd);
   for (int64_t i = 0; i < nd; ++i) v[i] = vhat[i];
+  // the base the energy uses: S0, or with fixed-point plasticity the
+  // return-mapped base of the current iterate (re-projected after every step)
+  std::vector<double> Seff(S0, S0 + 9 * (size_t)nmat * nc);
+  const double* Sck = Seff.data();
+  auto reproject = [&]() {
+    return opts->fixed_point_plasticity
+               ? or_plastic_base(gg, nmat, mats, dt, Vck, S0, v, Seff.data())
+               : (int)OR_OK;
+  };
   or_solver_stats st{};
   double E;
+  if (int rp = reproject(); rp != OR_OK) return rp;
   int rc = or_energy_grad(gg, nmat, mats, dt, mi, vhat, fixed, Vck, Sck, v, &E, grad.data());
   if (rc != OR_OK) return rc;
   auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
@@ -1264,6 +1309,7 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
     st.newton_iters = it + 1;
     if (!ok) { result = OR_ERR_LINESEARCH; break; }
     for (int64_t i = 0; i < nd; ++i) v[i] = vt[i];
+    if (int rp = reproject(); rp != OR_OK) { result = rp; break; }
     or_energy_grad(gg, nmat, mats, dt, mi, vhat, fixed, Vck, Sck, v, &E, grad.data());
     gn = std::sqrt(dot(grad, grad));
   }

@@ -67,6 +67,10 @@ typedef struct {
 typedef struct {
   double newton_rtol, pcg_rtol, armijo_c;
   int32_t max_newton, max_pcg, max_ls;
+  /* 1: fixed-point plasticity inside Newton (Sec. 7, Fixed-Point Plasticity):
+   * at every Newton iterate the plastic centres' trial F is return-mapped and
+   * the iteration's energy uses the resulting base (or_plastic_base) */
+  int32_t fixed_point_plasticity;
 } or_solver_opts;
 
 typedef struct {
@@ -105,6 +109,13 @@ int or_tangent(const or_grid* g, int32_t nmat, const or_material* mats, double d
                double* Abar);
 int or_hv(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,
           const double* Abar, const double* u, double* Hu);
+/* Fixed-point plasticity base (Sec. 7, Fixed-Point Plasticity): for every
+ * centre and material with plasticity, F = (I + dt G_c(v)) S0 is return-mapped
+ * (the particles' projection) to F_E and Seff = (I + dt G_c(v))^{-1} F_E; where
+ * nothing yields, and for materials without plasticity, Seff = S0.  S0, Seff:
+ * [nmat][ncell][9]. */
+int or_plastic_base(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
+                    const double* Vck, const double* S0, const double* v, double* Seff);
 int or_explicit_force(const or_grid* g, int32_t nmat, const double* Vck,
                       const double* tauck, double* f);
 int or_jacobi_diag(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,

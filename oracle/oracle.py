@@ -43,7 +43,8 @@ class _BC(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("armijo_c", C.c_double),
-                ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("max_ls", C.c_int32)]
+                ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("max_ls", C.c_int32),
+                ("fixed_point_plasticity", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -109,10 +110,11 @@ class SolverOpts:
     max_newton: int = 50
     max_pcg: int = 20000
     max_ls: int = 40
+    fixed_point_plasticity: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.newton_rtol, self.pcg_rtol, self.armijo_c, self.max_newton,
-                     self.max_pcg, self.max_ls)
+                     self.max_pcg, self.max_ls, self.fixed_point_plasticity)
 
 
 def _p(a: np.ndarray, ctype=C.c_double):
@@ -274,6 +276,16 @@ def jacobi_diag(grid: Grid, mc, mi, fixed, Abar):
                          _p(np.ascontiguousarray(fixed, dtype=np.uint8), C.c_uint8), _p(_f64(Abar)),
                          _p(D))
     return D
+
+
+def plastic_base(grid: Grid, mats, dt, Vck, S0, v):
+    """Fixed-point plasticity base at node velocity v (Sec. 7, Fixed-Point
+    Plasticity): the return-mapped (I + dt G_c(v)) S0, mapped back by
+    (I + dt G_c(v))^{-1}, where a plastic centre yields; S0 elsewhere."""
+    Se = np.zeros((len(mats), grid.ncell, 9))
+    rc = lib().or_plastic_base(C.byref(grid.c()), len(mats), _mats(mats), C.c_double(dt),
+                               _p(_f64(Vck)), _p(_f64(S0)), _p(_f64(v)), _p(Se))
+    return Se, rc
 
 
 def explicit_force(grid: Grid, Vck, tauck):

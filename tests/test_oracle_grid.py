@@ -484,3 +484,86 @@ def test_flip_explicit_step_conserves_particle_momentum(flip):
     p1 = m @ out["v"]
     assert np.abs(p1 - p0).max() <= 1e-13 * np.abs(m[:, None] * sc.particles["v"]).sum()
     assert np.abs(out["v"] - sc.particles["v"]).max() > 1e-6
+
+
+# ---------------------------------------------------------------- fixed-point plasticity
+def plate_scene(plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, friction_deg=0.0, model=None):
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=model if model is not None else scenes.FIXED_COROTATED,
+                            E=7e6, strain=0.0, plastic=plastic, yield_stress=yield_stress,
+                            friction_deg=friction_deg, seed=31, vel_std=0.05, gravity=(0.0, 0.0, 0.0))
+    sc.bcs.append(dict(kind=scenes.BC_MOVING_BOX, lo=(-1.0, 9 * sc.dx, -1.0), hi=(2.0, 2.0, 2.0),
+                       velocity=(0.0, -0.5, 0.0)))
+    g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+    u = O.unload(g, sc.particles, mats)
+    fixed, vfix = O.node_bcs(g, u["mi"], bcs, 0.0)
+    act = u["mi"] > 0
+    vhat = np.where(fixed[:, None] > 0, vfix, np.where(act[:, None], u["vi"], 0.0))
+    S, rc = O.reconstruct(g, mats, u["Vck"], u["tauck"])
+    assert rc == 0
+    return sc, g, mats, u, fixed, vhat, S
+
+
+def hencky_strains(g, sc, u, v, Sb):
+    """Principal Hencky strains of the elastic F = (I + dt G_c(v)) S at every
+    centre with volume (numpy SVD)."""
+    _, Gc = O.node_to_centre(g, u["mc"], v)
+    cells = np.nonzero(u["Vck"][0] > 0)[0]
+    A = np.eye(3)[None] + sc.dt * Gc[cells].reshape(-1, 3, 3)
+    F = A @ Sb[0, cells].reshape(-1, 3, 3)
+    return np.log(np.linalg.svd(F, compute_uv=False))
+
+
+def test_fixed_point_without_yield_is_the_plain_solve():
+    """Where no centre yields the return mapping changes nothing, so the
+    fixed-point solve takes exactly the plain solve's steps."""
+    sc, g, mats, u, fixed, vhat, S = plate_scene(yield_stress=1e12)
+    runs = []
+    for fp in (0, 1):
+        v, st, rc = O.solve(g, mats, sc.dt, u["mc"], u["mi"], vhat, fixed, u["Vck"], S,
+                            O.SolverOpts(1e-10, 1e-10, fixed_point_plasticity=fp))
+        assert rc == 0
+        runs.append((v, st))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
+
+
+def test_fixed_point_von_mises_ends_on_the_yield_surface():
+    """Sec. 7, Fixed-Point Plasticity, von Mises: at the converged velocity
+    every centre's elastic state, (I + dt G_c(v)) times the return-mapped
+    base, satisfies 2 mu |dev e| <= yield stress; the plain solve (plasticity
+    only at the particles after it) leaves many centres far outside."""
+    sc, g, mats, u, fixed, vhat, S = plate_scene()
+    mu, _ = O.lame(7e6, 0.3)
+    out = {}
+    for fp in (0, 1):
+        v, st, rc = O.solve(g, mats, sc.dt, u["mc"], u["mi"], vhat, fixed, u["Vck"], S,
+                            O.SolverOpts(1e-10, 1e-10, fixed_point_plasticity=fp))
+        assert rc == 0
+        Sb = O.plastic_base(g, mats, sc.dt, u["Vck"], S, v)[0] if fp else S
+        e = hencky_strains(g, sc, u, v, Sb)
+        dev = e - e.mean(1, keepdims=True)
+        out[fp] = 2 * mu * np.linalg.norm(dev, axis=1) / 2e3
+    assert out[1].max() <= 1 + 1e-8
+    assert np.mean(out[1] > 1 - 1e-8) > 0.1          # many centres sit on the surface
+    assert np.mean(out[0] > 1.5) > 0.1                # the plain solve overshoots
+
+
+def test_fixed_point_drucker_prager_ends_inside_the_cone():
+    """Drucker-Prager (30 degrees) on the same loading: at the converged
+    velocity every centre's elastic Hencky strain satisfies the cone condition
+    |dev e| + (3 lambda + 2 mu)/(2 mu) tr(e) alpha <= 0 or sits at the tip."""
+    sc, g, mats, u, fixed, vhat, S = plate_scene(plastic=scenes.PLASTIC_DRUCKER_PRAGER, yield_stress=0.0,
+                                                 friction_deg=30.0, model=scenes.HENCKY)
+    mu, lam = O.lame(7e6, 0.3)
+    sphi = np.sin(np.radians(30.0))
+    alpha = np.sqrt(2 / 3) * 2 * sphi / (3 - sphi)
+    v, st, rc = O.solve(g, mats, sc.dt, u["mc"], u["mi"], vhat, fixed, u["Vck"], S,
+                        O.SolverOpts(1e-8, 1e-10, fixed_point_plasticity=1))
+    assert rc == 0
+    Sb = O.plastic_base(g, mats, sc.dt, u["Vck"], S, v)[0]
+    e = hencky_strains(g, sc, u, v, Sb)
+    tr = e.sum(1)
+    nd = np.linalg.norm(e - tr[:, None] / 3, axis=1)
+    cone = nd + (3 * lam + 2 * mu) / (2 * mu) * tr * alpha
+    tip = np.linalg.norm(e, axis=1) <= 1e-12
+    assert np.all((cone <= 1e-9) | tip)

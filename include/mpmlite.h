@@ -117,7 +117,17 @@ typedef struct {
                              advects) and the node increment v - v^n (FLIP, added to v_p^n) */
   double flip_ratio;      /* MPL_TRANSFER_FLIP_PIC: v_p <- flip_ratio v_FLIP + (1 - flip_ratio)
                              v_PIC, in [0, 1] */
+  int32_t plasticity;     /* MPL_PLASTICITY_AFTER_SOLVE: the plastic projection acts on the
+                             particles' F in the load only (default); MPL_PLASTICITY_FIXED_POINT:
+                             in addition, at every Newton iterate v the plastic centres' trial
+                             F = (I + dt G_c(v)) S_c is return-mapped to F_E and that Newton
+                             iteration's energy, gradient and tangent use the base
+                             (I + dt G_c(v))^{-1} F_E (Sec. 7, Fixed-Point Plasticity); CG then
+                             solves for the elastic response only.  Converges linearly, so it
+                             needs more Newton iterations */
 } mpl_solver_opts;
+
+enum { MPL_PLASTICITY_AFTER_SOLVE = 0, MPL_PLASTICITY_FIXED_POINT = 1 };
 
 enum { MPL_TRANSFER_APIC = 0, MPL_TRANSFER_FLIP_PIC = 1 };
 

@@ -235,6 +235,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "transfer must be MPL_TRANSFER_APIC or MPL_TRANSFER_FLIP_PIC");
   if (!(o->flip_ratio >= 0.0 && o->flip_ratio <= 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "flip_ratio must lie in [0, 1]");
+  if (o->plasticity != MPL_PLASTICITY_AFTER_SOLVE && o->plasticity != MPL_PLASTICITY_FIXED_POINT)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "plasticity must be MPL_PLASTICITY_AFTER_SOLVE or _FIXED_POINT");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
       o->max_ls < 0 || !(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "solver options out of range");
@@ -293,7 +295,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->c_nbr_node, &c->n_nbr_cell, &c->pcell, &c->pkey,
                    &c->bin_count, &c->bin_start, &c->bin_fill, &c->sorted, &c->mc, &c->qc, &c->Gc,
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
-                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
+                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->Seff, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,

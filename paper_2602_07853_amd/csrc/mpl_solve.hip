@@ -79,7 +79,8 @@ template <bool WANT_GRAD>
 __global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ v, int64_t nnode,
                                                      const int* __restrict__ c_nbr_node,
                                                      const double* __restrict__ Vk,
-                                                     const double* __restrict__ Sk, int64_t ncell,
+                                                     const double* __restrict__ Sk,
+                                                     const double* __restrict__ Sg, int64_t ncell,
                                                      int K, double dt, double inv4dx,
                                                      double* __restrict__ Qc,
                                                      double* __restrict__ partial) {
@@ -98,15 +99,19 @@ __global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ 
       const double V = Vk[k * ncell + ci];
       if (V == 0.0) continue;
       double S6[6], S[9], F[9];
-      for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
-      sym_to_full(S6, S);
+      if (Sg) {  // general base (fixed-point plasticity), 9 entries
+        for (int e = 0; e < 9; ++e) S[e] = Sg[(k * 9 + e) * ncell + ci];
+      } else {
+        for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
+        sym_to_full(S6, S);
+      }
       mul(A, S, F);
       const double ps = psi(s_mats[k], F);
       e += V * ps;
       if (WANT_GRAD && isfinite(ps)) {
         double Pm[9], PS[9];
         piola(s_mats[k], F, Pm);
-        mul(Pm, S, PS);  // S symmetric: P S^T = P S
+        mul_nt(Pm, S, PS);  // P S^T (S need not be symmetric)
         for (int i = 0; i < 9; ++i) Q[i] += V * PS[i];
       }
     }
@@ -115,6 +120,55 @@ __global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ 
     for (int i = 0; i < 9; ++i) Qc[i * ncell + ci] = Q[i];
   const double s = wave_sum(e);
   if (l == 0) partial[cb] = s;
+}
+
+// Fixed-point plasticity base (Sec. 7, Fixed-Point Plasticity): for every
+// centre and material with plasticity, the trial F = (I + dt G_c(v)) S is
+// return-mapped (the particles' projection) to F_E and the base becomes
+// (I + dt G_c(v))^{-1} F_E; where nothing yields, and for materials without
+// plasticity, the reconstructed S itself (9 entries per centre and material).
+__global__ __launch_bounds__(64) void k_plastic_base(const double* __restrict__ v, int64_t nnode,
+                                                     const int* __restrict__ c_nbr_node,
+                                                     const double* __restrict__ Vk,
+                                                     const double* __restrict__ Sk, int64_t ncell,
+                                                     int K, double dt, double inv4dx,
+                                                     double* __restrict__ Seff,
+                                                     int32_t* __restrict__ err) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  bool need = false;
+  for (int k = 0; k < K; ++k)
+    need = need || (Vk[k * ncell + ci] != 0.0 && s_mats[k].plastic != PLASTIC_NONE);
+  double A[9], Ai[9];
+  if (need) {
+    double Gm[9];
+    cell_grad(v, nnode, c_nbr_node, cb, l, inv4dx, Gm);
+    for (int i = 0; i < 9; ++i) A[i] = dt * Gm[i];
+    A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
+    double C[9];
+    cofactor(A, C);  // C = det(A) A^{-T}
+    const double d = det(A);
+    if (!(d != 0.0) || !isfinite(d)) {
+      need = false;
+      atomicOr(err, 8);
+    } else {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Ai[i * 3 + j] = C[j * 3 + i] / d;
+    }
+  }
+  for (int k = 0; k < K; ++k) {
+    double S6[6], S[9];
+    for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
+    sym_to_full(S6, S);
+    double Se[9];
+    for (int e = 0; e < 9; ++e) Se[e] = S[e];
+    if (need && Vk[k * ncell + ci] != 0.0 && s_mats[k].plastic != PLASTIC_NONE) {
+      double F[9];
+      mul(A, S, F);
+      if (plastic_project(s_mats[k], F) > 0.0) mul(Ai, F, Se);
+    }
+    for (int e = 0; e < 9; ++e) Seff[(k * 9 + e) * ncell + ci] = Se[e];
+  }
 }
 
 // grad_i = m_i (v_i - vhat_i) + dt sum_c Q_c grad w_ic on free nodes; partial
@@ -307,7 +361,8 @@ template <class T, bool FACT>
 __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, int64_t nnode,
                                                 const int* __restrict__ c_nbr_node,
                                                 const double* __restrict__ Vk,
-                                                const double* __restrict__ Sk, int64_t ncell,
+                                                const double* __restrict__ Sk,
+                                                const double* __restrict__ Sg, int64_t ncell,
                                                 int K, double dt, double inv4dx,
                                                 const uint64_t* __restrict__ cmask,
                                                 const int32_t* __restrict__ coff,
@@ -335,8 +390,12 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       const double V = Vk[k * ncell + ci];
       if (V == 0.0) continue;
       double S6[6], S[9], F[9];
-      for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
-      sym_to_full(S6, S);
+      if (Sg) {  // general base (fixed-point plasticity), 9 entries
+        for (int e = 0; e < 9; ++e) S[e] = Sg[(k * 9 + e) * ncell + ci];
+      } else {
+        for (int j = 0; j < 6; ++j) S6[j] = Sk[(k * 6 + j) * ncell + ci];
+        sym_to_full(S6, S);
+      }
       mul(A, S, F);
       double U[9], s[3], Vm[9], R[9];
       if (!principal_frame(F, U, s, Vm, R)) {
@@ -1459,6 +1518,22 @@ static double* partial_slot(mpl_ctx* c, int k) {
   return P<double>(c->partials) + k * n;
 }
 
+// The base the energy and tangent kernels read: the return-mapped one under
+// fixed-point plasticity, else the symmetric stretch (null).
+static const double* sgen(mpl_ctx* c) { return c->s_general ? P<double>(c->Seff) : nullptr; }
+
+// Fixed-point plasticity: the base at the node velocity v (block layout).
+static mpl_status plastic_base(mpl_ctx* c, const double* v) {
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(upload_mats(c));
+  MPL_TRY(mpl_ensure(c, c->Seff, sizeof(double) * 9 * c->nmat * ncell));
+  MPL_LAUNCH(c, k_plastic_base, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
+             P<double>(c->Sk), ncell, c->nmat, c->dt, 0.25 * c->inv_dx, P<double>(c->Seff),
+             &c->dscal()->err);
+  c->s_general = true;
+  return MPL_OK;
+}
+
 mpl_status mpl_stage_reconstruct(mpl_ctx* c) {
   if (!c->unloaded) return mpl_fail(c, MPL_ERR_STATE, "reconstruct before unload");
   MPL_TRY(upload_mats(c));
@@ -1467,6 +1542,7 @@ mpl_status mpl_stage_reconstruct(mpl_ctx* c) {
   MPL_LAUNCH(c, k_reconstruct, (int)((ncell + 127) / 128), 128, P<double>(c->Vk), P<double>(c->Tk),
              P<double>(c->Sk), ncell, c->nmat, &c->dscal()->domain_count);
   c->reconstructed = true;
+  c->s_general = false;
   return MPL_OK;
 }
 
@@ -1485,7 +1561,7 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
     MPL_TRY(mpl_ensure(c, c->Qc, 8 * 9 * ncell));
     MPL_TRY(mpl_ensure(c, c->g, 8 * 3 * nnode));
     MPL_LAUNCH(c, k_energy_cells<true>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Qc), pc);
+               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Qc), pc);
     MPL_LAUNCH(c, k_energy_nodes<true>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Qc), ncell, nnode, c->dt,
                inv4dx, P<double>(c->g), pe, pg);
@@ -1493,7 +1569,7 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
                c->dscal(), 0);
   } else {
     MPL_LAUNCH(c, k_energy_cells<false>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, (double*)nullptr, pc);
+               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, (double*)nullptr, pc);
     MPL_LAUNCH(c, k_energy_nodes<false>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), (const double*)nullptr, ncell, nnode,
                c->dt, inv4dx, (double*)nullptr, pe, (double*)nullptr);
@@ -1524,14 +1600,14 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     MPL_TRY(mpl_ensure(c, c->mt, 4 * nnode));
     if (fact) {
       MPL_LAUNCH(c, (k_tangent<float, true>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-                 P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+                 P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
                  P<float>(c->Abar32), &c->dscal()->err);
       MPL_LAUNCH(c, (k_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                  P<float>(c->Dt), P<float>(c->mt));
     } else {
       MPL_LAUNCH(c, (k_tangent<float, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-                 P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+                 P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
                  P<float>(c->Abar32), &c->dscal()->err);
       MPL_LAUNCH(c, (k_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
@@ -1540,7 +1616,7 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   } else {
     MPL_TRY(mpl_ensure(c, c->Abar64, 8 * MPL_TAN_DENSE * ntan));
     MPL_LAUNCH(c, (k_tangent<double, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Vk), P<double>(c->Sk), ncell, c->nmat, c->dt, inv4dx, cm, co,
+               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
                P<double>(c->Abar64), &c->dscal()->err);
     MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
@@ -2342,6 +2418,8 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   MPL_TRY(mpl_sync_scalars(c));
   const double escale = c->hscal.red[4];
   double E = 0.0, gn2 = 0.0;
+  const bool fixed_point = c->opts.plasticity == MPL_PLASTICITY_FIXED_POINT;
+  if (fixed_point) MPL_TRY(plastic_base(c, v));
   MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
   if (!std::isfinite(E)) return mpl_fail(c, MPL_ERR_DOMAIN, "initial state outside the model domain");
   const double g0 = std::sqrt(gn2);
@@ -2465,6 +2543,8 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       break;
     }
     MPL_HIP(c, hipMemcpyAsync(v, c->vt.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
+    // fixed-point plasticity: re-project at the new iterate before its energy
+    if (fixed_point) MPL_TRY(plastic_base(c, v));
     MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
     gn = std::sqrt(gn2);
     if (!std::isfinite(gn)) {

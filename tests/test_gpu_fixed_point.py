@@ -1,0 +1,102 @@
+"""GPU tests of fixed-point plasticity inside Newton (Sec. 7, Fixed-Point
+Plasticity) through the C-ABI, against the oracle's fixed-point solve and
+step on the same seeded inputs."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2602_07853_amd import scenes
+from tests.parity_util import gpu_context, oracle_state, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def plate(plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, friction_deg=0.0, model=scenes.FIXED_COROTATED):
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=model, E=7e6, strain=0.0, plastic=plastic,
+                            yield_stress=yield_stress, friction_deg=friction_deg, seed=31, vel_std=0.05,
+                            gravity=(0.0, 0.0, 0.0))
+    sc.bcs.append(dict(kind=scenes.BC_MOVING_BOX, lo=(-1.0, 9 * sc.dx, -1.0), hi=(2.0, 2.0, 2.0),
+                       velocity=(0.0, -0.5, 0.0)))
+    return sc
+
+
+def solve_both(sc, precision, rtol=1e-10, newton_rtol=None):
+    from paper_2602_07853_amd import mpmlite
+    nrtol = rtol if newton_rtol is None else newton_rtol
+    ref = oracle_state(sc)
+    v_or, st_or, rc = O.solve(ref["grid"], ref["mats"], sc.dt, ref["mc"], ref["mi"], ref["vhat"],
+                              ref["fixed"], ref["Vck"], ref["S"],
+                              O.SolverOpts(nrtol, rtol, fixed_point_plasticity=1))
+    assert rc == 0
+    ctx = gpu_context(sc, precision, newton_rtol=nrtol, pcg_rtol=rtol if precision == 1 else 1e-6,
+                      plasticity=mpmlite.PLASTICITY_FIXED_POINT)
+    parts = mpmlite.particles_to_device(sc.particles)
+    ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+    ctx.reconstruct()
+    v, st = ctx.solve()
+    return host(v), st, v_or, st_or
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_fixed_point_von_mises_solve_matches_oracle(precision):
+    v, st, v_or, st_or = solve_both(plate(), precision)
+    e = rel(v, v_or)
+    print(f"[fixed-point] VM precision {precision}: gpu newton {st['newton_iters']} pcg {st['pcg_iters']}, "
+          f"oracle newton {st_or['newton_iters']}; v rel {e:.2e}", flush=True)
+    if precision == 1:
+        assert st["newton_iters"] == st_or["newton_iters"]
+    assert e <= 1e-9
+
+
+def test_fixed_point_drucker_prager_solve_matches_oracle():
+    """The sand's fixed point contracts slowly (about 0.7 per iteration on
+    this loading): Newton to 1e-7 takes 38 iterations on both sides."""
+    sc = plate(plastic=scenes.PLASTIC_DRUCKER_PRAGER, yield_stress=0.0, friction_deg=30.0, model=scenes.HENCKY)
+    v, st, v_or, st_or = solve_both(sc, 1, rtol=1e-10, newton_rtol=1e-7)
+    e = rel(v, v_or)
+    print(f"[fixed-point] DP: gpu newton {st['newton_iters']}, oracle {st_or['newton_iters']}; v rel {e:.2e}",
+          flush=True)
+    assert st["newton_iters"] == st_or["newton_iters"]
+    assert e <= 1e-9
+
+
+def test_fixed_point_without_yield_is_the_plain_solve():
+    from paper_2602_07853_amd import mpmlite
+    sc = plate(yield_stress=1e12)
+    parts = mpmlite.particles_to_device(sc.particles)
+    out = []
+    for mode in (mpmlite.PLASTICITY_AFTER_SOLVE, mpmlite.PLASTICITY_FIXED_POINT):
+        ctx = gpu_context(sc, 1, newton_rtol=1e-10, pcg_rtol=1e-10, plasticity=mode)
+        ctx.unload(parts, sc.dt, sc.gravity, sc.bcs, 0.0)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        out.append((host(v), st["newton_iters"], st["pcg_iters"]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:]
+
+
+def test_fixed_point_steps_match_oracle():
+    from paper_2602_07853_amd import mpmlite
+    sc = plate()
+    g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+    rtol = 1e-10
+    ctx = gpu_context(sc, 1, newton_rtol=rtol, pcg_rtol=rtol, plasticity=mpmlite.PLASTICITY_FIXED_POINT)
+    dp = mpmlite.particles_to_device(sc.particles)
+    p = sc.particles
+    t = 0.0
+    for _ in range(2):
+        p, st_or, _, rc = O.step(g, mats, sc.dt, sc.gravity, bcs, t,
+                                 O.SolverOpts(rtol, rtol, fixed_point_plasticity=1), p)
+        assert rc == 0
+        ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+    pg = {k: host(v) for k, v in dp.items()}
+    for k in ("x", "v", "G", "F"):
+        assert rel(pg[k], p[k]) <= 1e-9, k
+    assert rel(pg["plastic"], p["eps"]) <= 1e-7

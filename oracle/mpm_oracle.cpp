@@ -1177,6 +1177,71 @@ int or_plastic_base(const or_grid* gg, int32_t nmat, const or_material* mats, do
   return status;
 }
 
+// Vertex block descent (Sec. 5, VBD) on Phi: see or_solver_opts.vbd_sweeps.
+static int vbd_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
+                     const double* mi, const double* vhat, const uint8_t* fixed,
+                     const double* Vck, const double* Sck, int sweeps, double* v,
+                     or_solver_stats* stats) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nc = g.nc(), nn = g.nn();
+  std::vector<double> grad(3 * nn), Abar(81 * nc);
+  for (int64_t i = 0; i < 3 * nn; ++i) v[i] = vhat[i];
+  double E = 0.0;
+  int rc = or_energy_grad(gg, nmat, mats, dt, mi, vhat, fixed, Vck, Sck, v, &E, grad.data());
+  if (rc != OR_OK) return rc;
+  auto gnorm = [&]() {
+    double s = 0.0;
+    for (int64_t i = 0; i < 3 * nn; ++i) s += grad[i] * grad[i];
+    return std::sqrt(s);
+  };
+  or_solver_stats st{};
+  st.g0_norm = gnorm();
+  for (int sw = 0; sw < sweeps; ++sw) {
+    for (int color = 0; color < 8; ++color) {
+      rc = or_energy_grad(gg, nmat, mats, dt, mi, vhat, fixed, Vck, Sck, v, &E, grad.data());
+      if (rc != OR_OK) return rc;
+      rc = or_tangent(gg, nmat, mats, dt, Vck, Sck, v, 1, Abar.data());
+      if (rc != OR_OK) return rc;
+      for (int i = 0; i <= g.n; ++i)
+        for (int j = 0; j <= g.n; ++j)
+          for (int k = 0; k <= g.n; ++k) {
+            if ((((i & 1) << 2) | ((j & 1) << 1) | (k & 1)) != color) continue;
+            const int64_t nidx = g.node(i, j, k);
+            if (mi[nidx] == 0.0 || fixed[nidx]) continue;
+            double H[9] = {mi[nidx], 0, 0, 0, mi[nidx], 0, 0, 0, mi[nidx]};
+            // the node is corner d = ((i-ci), (j-cj), (k-ck)) of each adjacent cell
+            for (int d = 0; d < 8; ++d) {
+              int o[3];
+              corner(d, o);
+              const int ci = i - o[0], cj = j - o[1], ck = k - o[2];
+              if (ci < 0 || cj < 0 || ck < 0 || ci >= g.n || cj >= g.n || ck >= g.n) continue;
+              const double* Ac = Abar.data() + 81 * g.cell(ci, cj, ck);
+              double gw[3];
+              grad_w(d, g.dx, gw);
+              for (int a = 0; a < 3; ++a)
+                for (int a2 = 0; a2 < 3; ++a2) {
+                  double s = 0.0;
+                  for (int b = 0; b < 3; ++b)
+                    for (int b2 = 0; b2 < 3; ++b2) s += Ac[(a * 3 + b) * 9 + (a2 * 3 + b2)] * gw[b] * gw[b2];
+                  H[a * 3 + a2] += s;
+                }
+            }
+            double Hi[9];
+            if (!m3_inverse(H, Hi)) return OR_ERR_NOT_CONVERGED;
+            for (int a = 0; a < 3; ++a)
+              v[3 * nidx + a] -= Hi[a * 3] * grad[3 * nidx] + Hi[a * 3 + 1] * grad[3 * nidx + 1] +
+                                 Hi[a * 3 + 2] * grad[3 * nidx + 2];
+          }
+    }
+  }
+  rc = or_energy_grad(gg, nmat, mats, dt, mi, vhat, fixed, Vck, Sck, v, &E, grad.data());
+  st.newton_iters = sweeps;
+  st.g_norm = gnorm();
+  st.energy = E;
+  if (stats) *stats = st;
+  return rc;
+}
+
 // Newton's method on Phi with the projected Hessian, Jacobi-preconditioned CG
 // for each linear system and Armijo backtracking (halving, with a rounding
 // allowance) and the model's feasibility (Phi = +inf outside the domain).
@@ -1222,6 +1287,8 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
              const double* Vck, const double* S0, const or_solver_opts* opts,
              double* v, or_solver_stats* stats) {
+  if (opts->vbd_sweeps > 0)
+    return vbd_solve(gg, nmat, mats, dt, mi, vhat, fixed, Vck, S0, opts->vbd_sweeps, v, stats);
   Grid g{gg->n, gg->dx};
   const int64_t nc = g.nc(), nn = g.nn(), nd = 3 * nn;
   std::vector<double> grad(nd), Abar(81 * nc), p(nd), r(nd), z(nd), q(nd), x(nd), D(nd),

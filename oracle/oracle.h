@@ -71,6 +71,12 @@ typedef struct {
    * at every Newton iterate the plastic centres' trial F is return-mapped and
    * the iteration's energy uses the resulting base (or_plastic_base) */
   int32_t fixed_point_plasticity;
+  /* > 0: instead of Newton-PCG, this many sweeps of vertex block descent
+   * (Sec. 5, VBD): 8 node colours by index parity; per colour the gradient
+   * and projected tangent are evaluated at the current velocity and every
+   * free node of the colour takes v_i -= H_ii^{-1} g_i with the 3x3 node
+   * block H_ii = m_i I + sum_c (its block of Abar_c) */
+  int32_t vbd_sweeps;
 } or_solver_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class _BC(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("armijo_c", C.c_double),
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("max_ls", C.c_int32),
-                ("fixed_point_plasticity", C.c_int32)]
+                ("fixed_point_plasticity", C.c_int32), ("vbd_sweeps", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -111,10 +111,11 @@ class SolverOpts:
     max_pcg: int = 20000
     max_ls: int = 40
     fixed_point_plasticity: int = 0
+    vbd_sweeps: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.newton_rtol, self.pcg_rtol, self.armijo_c, self.max_newton,
-                     self.max_pcg, self.max_ls, self.fixed_point_plasticity)
+                     self.max_pcg, self.max_ls, self.fixed_point_plasticity, self.vbd_sweeps)
 
 
 def _p(a: np.ndarray, ctype=C.c_double):

@@ -125,6 +125,14 @@ typedef struct {
                              (I + dt G_c(v))^{-1} F_E (Sec. 7, Fixed-Point Plasticity); CG then
                              solves for the elastic response only.  Converges linearly, so it
                              needs more Newton iterations */
+  int32_t vbd_sweeps;     /* > 0: instead of Newton-PCG, this many sweeps of vertex block descent
+                             (Sec. 5, VBD) on the same potential: 8 node colours by index parity;
+                             per colour the gradient and the projected FP64 cell tangents are
+                             evaluated at the current velocity and every free node of the colour
+                             takes v_i -= H_ii^{-1} g_i with its 3x3 block H_ii = m_i I + sum over
+                             its cells of their blocks.  Not combined with
+                             MPL_PLASTICITY_FIXED_POINT.  The stats report the sweeps as
+                             newton_iters and no CG iterations */
 } mpl_solver_opts;
 
 enum { MPL_PLASTICITY_AFTER_SOLVE = 0, MPL_PLASTICITY_FIXED_POINT = 1 };

@@ -532,6 +532,58 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
   mt[ni] = (T)mi[ni];
 }
 
+// Vertex block descent (Sec. 5, VBD), one colour: every free node whose index
+// parity is `color` takes v_i -= H_ii^{-1} g_i with H_ii = m_i I + sum over its
+// cells of the node's 3x3 block of the dense FP64 tangent,
+//   H[a][a'] += sum_{b,b'} Abar[(a,b),(a',b')] gw_b gw_b'.
+// No two nodes of one colour share a cell, so the updates are independent.
+__global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Abar,
+                                                  const uint64_t* __restrict__ cmask,
+                                                  const int32_t* __restrict__ coff,
+                                                  const double* __restrict__ mi,
+                                                  const uint8_t* __restrict__ flags,
+                                                  const int* __restrict__ n_nbr_cell,
+                                                  const int4* __restrict__ ncoord, int64_t nnode,
+                                                  double inv4dx, int color,
+                                                  const double* __restrict__ g,
+                                                  double* __restrict__ v, int32_t* __restrict__ err) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const int4 bc = ncoord[nb];
+  const int ix = bc.x * 4 + local_x(l), iy = bc.y * 4 + local_y(l), iz = bc.z * 4 + local_z(l);
+  if ((((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1)) != color) return;
+  if (!(flags[ni] & MPL_NODE_FREE)) return;
+  const double m = mi[ni];
+  double H[9] = {m, 0.0, 0.0, 0.0, m, 0.0, 0.0, 0.0, m};
+  for (int d = 0; d < 8; ++d) {
+    const int ci = node_cell(n_nbr_cell, nb, l, d);
+    if (ci < 0) continue;
+    const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63, MPL_TAN_DENSE);
+    if (!ts.active) continue;
+    double gw[3];
+    corner_grad(d, inv4dx, gw);
+    for (int a = 0; a < 3; ++a)
+      for (int a2 = 0; a2 < 3; ++a2) {
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b)
+          for (int b2 = 0; b2 < 3; ++b2)
+            s += Abar[ts.base + (int64_t)sym9(a * 3 + b, a2 * 3 + b2) * ts.n + ts.rank] * gw[b] * gw[b2];
+        H[a * 3 + a2] += s;
+      }
+  }
+  double C[9];
+  cofactor(H, C);  // C = det(H) H^{-T}; H is symmetric
+  const double dH = det(H);
+  if (!(dH > 0.0) || !isfinite(dH)) {
+    atomicOr(err, 64);
+    return;
+  }
+  double gi[3];
+  for (int a = 0; a < 3; ++a) gi[a] = g[a * nnode + ni];
+  for (int a = 0; a < 3; ++a)
+    v[a * nnode + ni] -= (C[a] * gi[0] + C[3 + a] * gi[1] + C[6 + a] * gi[2]) / dH;
+}
+
 // ---------------------------------------------------------------- Hv
 // Fused Hessian-vector product, one wavefront per active cell block:
 //   1. stage the 5x5x5 node tile of p (the 2x2x2 corners of all 64 cells) in LDS;
@@ -2418,6 +2470,35 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   MPL_TRY(mpl_sync_scalars(c));
   const double escale = c->hscal.red[4];
   double E = 0.0, gn2 = 0.0;
+  if (c->opts.vbd_sweeps > 0) {
+    // vertex block descent instead of Newton-PCG (Sec. 5, VBD)
+    MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    if (!std::isfinite(E)) return mpl_fail(c, MPL_ERR_DOMAIN, "initial state outside the model domain");
+    const double g0v = std::sqrt(gn2);
+    for (int sw = 0; sw < c->opts.vbd_sweeps; ++sw)
+      for (int color = 0; color < 8; ++color) {
+        MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+        MPL_TRY(mpl_stage_tangent(c, v, MPL_F64));
+        MPL_LAUNCH(c, k_vbd_nodes, c->n_nblk, 64, P<double>(c->Abar64), P<uint64_t>(c->cmask),
+                   P<int32_t>(c->coff), P<double>(c->mi), P<uint8_t>(c->flags), P<int>(c->n_nbr_cell),
+                   P<int4>(c->ncoord), nnode, 0.25 * c->inv_dx, color, P<double>(c->g), v,
+                   &c->dscal()->err);
+      }
+    MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    if (c->hscal.err & 64) {
+      c->solved = false;
+      return mpl_fail(c, MPL_ERR_NONFINITE, "a vertex block is not positive definite");
+    }
+    if (st) {
+      *st = mpl_stats{};
+      st->newton_iters = c->opts.vbd_sweeps;
+      st->g0_norm = g0v;
+      st->g_norm = std::sqrt(gn2);
+      st->energy = E;
+    }
+    c->solved = std::isfinite(E);
+    return c->solved ? MPL_OK : mpl_fail(c, MPL_ERR_NONFINITE, "non-finite energy after the sweeps");
+  }
   const bool fixed_point = c->opts.plasticity == MPL_PLASTICITY_FIXED_POINT;
   if (fixed_point) MPL_TRY(plastic_base(c, v));
   MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));

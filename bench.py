@@ -53,6 +53,9 @@ def parse():
                          "energy-norm best combination of the last three)")
     ap.add_argument("--explicit-steps", type=int, default=200,
                     help="timed steps of the explicit leg (jelly-falling workload, 256^3); 0 = skip")
+    ap.add_argument("--vbd-steps", type=int, default=10,
+                    help="timed steps of the VBD-vs-Newton-PCG leg (two-material bar, 64^3); 0 = skip")
+    ap.add_argument("--vbd-sweeps", type=int, default=4)
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,
@@ -204,6 +207,9 @@ def main():
     explicit = None
     if args.explicit_steps > 0:
         explicit = explicit_leg(args.explicit_steps)
+    vbd = None
+    if args.vbd_steps > 0:
+        vbd = vbd_leg(args.vbd_steps, args.vbd_sweeps)
     base = None
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
         base = cpu_baseline(sc, counts)
@@ -229,6 +235,7 @@ def main():
         "cpu_baseline": base,
         "learned": learned,
         "explicit": explicit,
+        "vbd": vbd,
     }
     print(json.dumps(line), flush=True)
 
@@ -316,6 +323,45 @@ def explicit_leg(nsteps, warmup=3):
     print(f"[bench] explicit leg {json.dumps(line)}", file=sys.stderr, flush=True)
     del ctx, parts
     return line
+
+
+def vbd_leg(nsteps, sweeps, warmup=1):
+    """Vertex block descent against Newton-PCG on the same potential (the
+    paper's VBD comparison, a soft-stiff-soft bar): each solver advances the
+    bar from its initial state; steps/s, and the gradient reduction each
+    reaches per step (Newton-PCG to 1e-6, VBD after a fixed sweep count)."""
+    import torch
+    from paper_2602_07853_amd import mpmlite, scenes
+    sc = scenes.two_material_bar()
+    out = {"workload": f"{sc.name}: {sc.n}^3 grid, {sc.n_particles} particles, split NH E=1e4/1e5/1e4, "
+                       f"dt={sc.dt:g}, one end held, the other dragged at 0.5 m/s"}
+    for name, opts in (("newton_pcg", dict(newton_rtol=1e-6, pcg_rtol=1e-6, warm_start=4)),
+                       ("vbd", dict(vbd_sweeps=sweeps))):
+        ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                              opts=dict(hv_precision=mpmlite.F64 if name == "vbd" else mpmlite.F32, **opts))
+        parts = mpmlite.particles_to_device(sc.particles)
+        t = 0.0
+        for _ in range(warmup):
+            ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+            t += sc.dt
+        torch.cuda.synchronize()
+        red = []
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+            t += sc.dt
+            red.append(st["g_norm"] / max(st["g0_norm"], 1e-300))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"steps_per_s": round(nsteps / el, 2), "ms_per_step": round(1e3 * el / nsteps, 3),
+                     "iters_per_step": round(st["newton_iters"], 2), "pcg_per_step": st["pcg_iters"],
+                     "max_grad_reduction": float(f"{max(red):.3e}")}
+        if name == "vbd":
+            out[name]["sweeps"] = sweeps
+        del ctx, parts
+    out["vbd_vs_newton_pcg"] = round(out["vbd"]["steps_per_s"] / out["newton_pcg"]["steps_per_s"], 3)
+    print(f"[bench] vbd leg {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 def copy_bandwidth(nbytes=1 << 30, reps=10):

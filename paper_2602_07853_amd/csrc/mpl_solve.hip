@@ -1617,6 +1617,9 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
     MPL_LAUNCH(c, k_energy_nodes<true>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Qc), ncell, nnode, c->dt,
                inv4dx, P<double>(c->g), pe, pg);
+    // with no scalar wanted (vertex block descent needs the gradient only)
+    // skip the reduction and the host synchronisation
+    if (!energy && !gnorm2) return MPL_OK;
     MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, pc, c->n_cblk, pe, c->n_nblk, pg, c->n_nblk,
                c->dscal(), 0);
   } else {
@@ -2477,7 +2480,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     const double g0v = std::sqrt(gn2);
     for (int sw = 0; sw < c->opts.vbd_sweeps; ++sw)
       for (int color = 0; color < 8; ++color) {
-        MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+        MPL_TRY(mpl_stage_energy(c, v, true, nullptr, nullptr));
         MPL_TRY(mpl_stage_tangent(c, v, MPL_F64));
         MPL_LAUNCH(c, k_vbd_nodes, c->n_nblk, 64, P<double>(c->Abar64), P<uint64_t>(c->cmask),
                    P<int32_t>(c->coff), P<double>(c->mi), P<uint8_t>(c->flags), P<int>(c->n_nbr_cell),

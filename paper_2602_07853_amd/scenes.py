@@ -345,4 +345,32 @@ def jelly_falling(seed: int = 6, n: int = 256, ppc_axis: int = 2, speed: float =
                  occupied_cells=len(cells))
 
 
+def two_material_bar(seed: int = 7, n: int = 64, ppc_axis: int = 2, speed: float = 0.5) -> Scene:
+    """Soft-stiff-soft bar shaped like the paper's VBD comparison: split
+    Neo-Hookean, E = 1e4 at both ends and 1e5 in the middle third, nu = 0.3,
+    rho = 1000, dt = 1e-3, gravity.  The bar runs along z over 48 cells with a
+    16 x 16 section; the nodes of its first 2 cell layers are held and those
+    of its last 2 layers are dragged along +x at ``speed`` m/s (the paper
+    twists the end; the boxes here translate).  At n = 64: 12,288 cells,
+    98,304 particles."""
+    dx = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mats = [material(NEOHOOKEAN, 1e4, 0.3, 1000.0), material(NEOHOOKEAN, 1e5, 0.3, 1000.0)]
+    x0, x1 = 3 * n // 8, 5 * n // 8
+    z0, z1 = n // 8, 7 * n // 8
+    cells = box_cells((x0, x0, z0), (x1, x1, z1))
+    third = (z1 - z0) // 3
+    ids_c = ((cells[:, 2] >= z0 + third) & (cells[:, 2] < z1 - third)).astype(np.int32)
+    x = fill_cells(cells, dx, ppc_axis, rng)
+    ppc = ppc_axis ** 3
+    p = make_particles(x, np.repeat(ids_c, ppc), mats, dx, ppc)
+    big = 10.0
+    bcs = wall_bcs(n, dx) + [
+        dict(kind=BC_STICKY_BOX, lo=(-big, -big, -big), hi=(big, big, (z0 + 2) * dx), velocity=(0.0, 0.0, 0.0)),
+        dict(kind=BC_MOVING_BOX, lo=(-big, -big, (z1 - 2) * dx), hi=(big, big, big), velocity=(speed, 0.0, 0.0)),
+    ]
+    return Scene(f"two_material_bar_{n}", n, dx, 1e-3, 10, (0.0, -9.81, 0.0), mats, bcs, p,
+                 occupied_cells=len(cells))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}

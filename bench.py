@@ -53,6 +53,9 @@ def parse():
                          "energy-norm best combination of the last three)")
     ap.add_argument("--explicit-steps", type=int, default=200,
                     help="timed steps of the explicit leg (jelly-falling workload, 256^3); 0 = skip")
+    ap.add_argument("--plasticity", choices=["after_solve", "fixed_point"], default="after_solve",
+                    help="plastic projection on the particles after the solve, or in addition the "
+                         "fixed point inside Newton")
     ap.add_argument("--vbd-steps", type=int, default=10,
                     help="timed steps of the VBD-vs-Newton-PCG leg (two-material bar, 64^3); 0 = skip")
     ap.add_argument("--vbd-sweeps", type=int, default=4)
@@ -136,7 +139,9 @@ def main():
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
                                     pcg_check_every=args.check_every, time_kernels=args.time_kernels,
-                                    warm_start=args.warm_start))
+                                    warm_start=args.warm_start,
+                                    plasticity=(mpmlite.PLASTICITY_FIXED_POINT if args.plasticity == "fixed_point"
+                                                else mpmlite.PLASTICITY_AFTER_SOLVE)))
     parts = mpmlite.particles_to_device(sc.particles)
     print(f"[bench] {workload_name(sc)}", file=sys.stderr, flush=True)
     step_idx = 0
@@ -229,7 +234,7 @@ def main():
         "config": {"workload": workload_name(sc), "preconditioner": "jacobi",
                    "active_cells": cells, "active_nodes": nodes,
                    "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
-                   "hv_precision": args.precision},
+                   "hv_precision": args.precision, "plasticity": args.plasticity},
         "roofline": roof,
         "update_kernel": update,
         "cpu_baseline": base,

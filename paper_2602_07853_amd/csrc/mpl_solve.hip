@@ -1173,6 +1173,16 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
   __shared__ double sh[4][16];
   const int t = threadIdx.x;
   if (!INIT && done_flag(s)) return;
+  // the scalars the tail needs, loaded before the partial sums so that their
+  // latency overlaps the reduction instead of following the barrier
+  double s_alpha = 0.0, s_rz = 0.0, s_tol2 = 0.0;
+  int s_iters = 0;
+  if (!INIT && t == 0) {
+    s_alpha = s->alpha;
+    s_rz = s->rz;
+    s_tol2 = s->tol2;
+    s_iters = s->iters;
+  }
   // rounds of 8 loads per array and thread, all 32 in flight at once
   // (indices clamped into range, out-of-range values replaced by zero)
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1230,19 +1240,19 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
     }
     return;
   }
-  s->alpha_last = s->alpha;  // the step length the completed iteration used
-  s->iters += 1;
+  s->alpha_last = s_alpha;  // the step length the completed iteration used
+  s->iters = s_iters + 1;
   s->rr = B;
   if (!isfinite(B)) {
     s->done = 2;
     return;
   }
-  if (B <= s->tol2) {
+  if (B <= s_tol2) {
     s->done = 1;
     return;
   }
-  const double beta = A / s->rz;
-  const double denom = delta - beta * A / s->alpha;
+  const double beta = A / s_rz;
+  const double denom = delta - beta * A / s_alpha;
   if (!(denom > 0.0) || !isfinite(denom)) {
     s->done = 2;
     return;

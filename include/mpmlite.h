@@ -180,8 +180,11 @@ typedef struct mpl_ctx mpl_ctx;
 const char* mpl_version(void);
 
 /* Create a context.  grid, mats (n_mats <= MPL_MAX_MATERIALS) and opts are
- * copied.  hip_stream is a hipStream_t (NULL = default stream).  On failure
- * *out is NULL and the status says why. */
+ * copied (the materials also to a device table of the context's own).
+ * hip_stream is a hipStream_t (NULL = default stream).  On failure *out is
+ * NULL and the status says why.  Contexts share no device state, so several
+ * may run at once on one GPU from different host threads and streams; one
+ * context must be used by one host thread at a time. */
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out);
 void mpl_destroy(mpl_ctx* ctx);

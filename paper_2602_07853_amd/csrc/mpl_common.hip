@@ -279,6 +279,12 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   mpl_status st = derive_materials(c, mats, n_mats);
   if (st == MPL_OK) st = check_opts(c, opts);
   if (st == MPL_OK) st = mpl_ensure(c, c->scal, sizeof(SolverScalars));
+  // the context's own device copy of its materials (kernels take its address)
+  if (st == MPL_OK) st = mpl_ensure(c, c->matbuf, sizeof(MatParams) * MPL_MAX_MATERIALS);
+  if (st == MPL_OK && (hipMemcpyAsync(c->matbuf.p, c->mats, sizeof(MatParams) * MPL_MAX_MATERIALS,
+                                      hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+                       hipStreamSynchronize(c->stream) != hipSuccess))
+    st = MPL_ERR_HIP;
   if (st == MPL_OK && hipEventCreate(&c->ev[0]) != hipSuccess) st = MPL_ERR_HIP;
   if (st == MPL_OK && hipEventCreate(&c->ev[1]) != hipSuccess) st = MPL_ERR_HIP;
   if (st != MPL_OK) {
@@ -297,7 +303,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->c_nbr_node, &c->n_nbr_cell, &c->pcell, &c->pkey,
                    &c->bin_count, &c->bin_start, &c->bin_fill, &c->sorted, &c->mc, &c->qc, &c->Gc,
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
-                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->Seff, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
+                   &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->Seff, &c->matbuf, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,

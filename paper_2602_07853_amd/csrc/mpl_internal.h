@@ -132,6 +132,7 @@ struct mpl_ctx {
   DevBuf xstar;
   DevBuf bcbuf;     // device copy of bc_host
   DevBuf cntbuf;    // per-block active/free counts of the unload
+  DevBuf matbuf;    // device copy of mats (MPL_MAX_MATERIALS entries)
   DevBuf Seff;      // fixed-point plasticity: return-mapped base, 9 entries per centre and material
   bool s_general = false;  // energy and tangent read Seff instead of the symmetric stretch
   BCDev bc_host{};  // host staging of the step's Dirichlet boxes (outlives the async copy)

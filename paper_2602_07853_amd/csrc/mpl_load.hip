@@ -8,7 +8,6 @@ using namespace mpl;
 
 namespace {
 
-__constant__ MatParams l_mats[MPL_MAX_MATERIALS];
 
 struct ParticlesIn {
   const double *x, *v, *F, *G, *m, *V, *plastic;
@@ -60,7 +59,8 @@ __global__ __launch_bounds__(256) void k_c2p(ParticlesIn in, ParticlesOut out, G
                                              const int32_t* __restrict__ cmap,
                       const double* __restrict__ vcl, const double* __restrict__ Gcl, int64_t ncell,
                       double dt, const double* __restrict__ dvcl, double flip,
-                      int32_t* __restrict__ err) {
+                      int32_t* __restrict__ err,
+    const MatParams* __restrict__ mats) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= in.n) return;
   double xp[3], f[3];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_c2p(ParticlesIn in, ParticlesOut out, G
   A[0] += 1.0; A[4] += 1.0; A[8] += 1.0;
   const int k = in.mat[p];
   double dg = 0.0;
-  if (l_mats[k].model == WATER) {
+  if (mats[k].model == WATER) {
     // J-based water: J <- (1 + dt tr G_p) J, carried as F = J^{1/3} I
     const double Jn = (1.0 + dt * (Gp[0] + Gp[4] + Gp[8])) * det(F);
     if (!(Jn > 0.0)) atomicOr(err, 32);
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_c2p(ParticlesIn in, ParticlesOut out, G
     for (int e = 0; e < 9; ++e) Fn[e] = (e % 4 == 0) ? c : 0.0;
   } else {
     mul(A, F, Fn);
-    dg = plastic_project(l_mats[k], Fn);
+    dg = plastic_project(mats[k], Fn);
   }
   const double pl = in.plastic ? in.plastic[p] : 0.0;
   for (int a = 0; a < 3; ++a) {
@@ -288,8 +288,6 @@ mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const mpl_particles* in, 
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "load needs the unloaded particle set");
   if (in->n > 0 && (!out->x || !out->v || !out->F || !out->G))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "output particle arrays missing");
-  MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(l_mats), c->mats, sizeof(MatParams) * MPL_MAX_MATERIALS,
-                                    0, hipMemcpyHostToDevice, c->stream));
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(mpl_ensure(c, c->vcl, 8 * 3 * ncell));
   MPL_TRY(mpl_ensure(c, c->Gcl, 8 * 9 * ncell));
@@ -302,7 +300,7 @@ mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const mpl_particles* in, 
   ParticlesOut po{out->x, out->v, out->F, out->G, out->plastic};
   MPL_LAUNCH(c, k_c2p, (int)((in->n + 255) / 256), 256, pi, po, grid_dev(c), P<int32_t>(c->cmap),
              P<double>(c->vcl), P<double>(c->Gcl), ncell, dt,
-             flip ? P<double>(c->dvcl) : (const double*)nullptr, c->opts.flip_ratio, &c->dscal()->err);
+             flip ? P<double>(c->dvcl) : (const double*)nullptr, c->opts.flip_ratio, &c->dscal()->err, P<MatParams>(c->matbuf));
   MPL_TRY(mpl_sync_scalars(c));
   if (c->hscal.err & 16) return mpl_fail(c, MPL_ERR_HIP, "internal: load reached an inactive block");
   if (c->hscal.err & 32)

@@ -21,7 +21,6 @@ using namespace mpl;
 
 namespace {
 
-__constant__ MatParams s_mats[MPL_MAX_MATERIALS];
 
 __device__ __forceinline__ bool done_flag(const SolverScalars* s) {
   return *(volatile const int32_t*)&s->done != 0;
@@ -51,7 +50,8 @@ __device__ __forceinline__ void cell_grad(const T* __restrict__ v, int64_t nnode
 
 __global__ __launch_bounds__(128) void k_reconstruct(const double* __restrict__ Vk, const double* __restrict__ Tk,
                                                      double* __restrict__ Sk, int64_t ncell, int K,
-                              int32_t* __restrict__ domain_count) {
+                              int32_t* __restrict__ domain_count,
+    const MatParams* __restrict__ mats) {
   int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ci >= ncell) return;
   for (int k = 0; k < K; ++k) {
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(128) void k_reconstruct(const double* __restrict__ 
       for (int j = 0; j < 6; ++j) t6[j] = Tk[(k * 6 + j) * ncell + ci];
       sym_to_full(t6, T);
       eig_sym3(T, w, Q);
-      if (stretch_from_principal(s_mats[k], w, s)) atomicAdd(domain_count, 1);
+      if (stretch_from_principal(mats[k], w, s)) atomicAdd(domain_count, 1);
       double S[9];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
@@ -83,7 +83,8 @@ __global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ 
                                                      const double* __restrict__ Sg, int64_t ncell,
                                                      int K, double dt, double inv4dx,
                                                      double* __restrict__ Qc,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial,
+    const MatParams* __restrict__ mats) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   double e = 0.0, Q[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -106,11 +107,11 @@ __global__ __launch_bounds__(64) void k_energy_cells(const double* __restrict__ 
         sym_to_full(S6, S);
       }
       mul(A, S, F);
-      const double ps = psi(s_mats[k], F);
+      const double ps = psi(mats[k], F);
       e += V * ps;
       if (WANT_GRAD && isfinite(ps)) {
         double Pm[9], PS[9];
-        piola(s_mats[k], F, Pm);
+        piola(mats[k], F, Pm);
         mul_nt(Pm, S, PS);  // P S^T (S need not be symmetric)
         for (int i = 0; i < 9; ++i) Q[i] += V * PS[i];
       }
@@ -133,12 +134,13 @@ __global__ __launch_bounds__(64) void k_plastic_base(const double* __restrict__ 
                                                      const double* __restrict__ Sk, int64_t ncell,
                                                      int K, double dt, double inv4dx,
                                                      double* __restrict__ Seff,
-                                                     int32_t* __restrict__ err) {
+                                                     int32_t* __restrict__ err,
+    const MatParams* __restrict__ mats) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   bool need = false;
   for (int k = 0; k < K; ++k)
-    need = need || (Vk[k * ncell + ci] != 0.0 && s_mats[k].plastic != PLASTIC_NONE);
+    need = need || (Vk[k * ncell + ci] != 0.0 && mats[k].plastic != PLASTIC_NONE);
   double A[9], Ai[9];
   if (need) {
     double Gm[9];
@@ -162,10 +164,10 @@ __global__ __launch_bounds__(64) void k_plastic_base(const double* __restrict__ 
     sym_to_full(S6, S);
     double Se[9];
     for (int e = 0; e < 9; ++e) Se[e] = S[e];
-    if (need && Vk[k * ncell + ci] != 0.0 && s_mats[k].plastic != PLASTIC_NONE) {
+    if (need && Vk[k * ncell + ci] != 0.0 && mats[k].plastic != PLASTIC_NONE) {
       double F[9];
       mul(A, S, F);
-      if (plastic_project(s_mats[k], F) > 0.0) mul(Ai, F, Se);
+      if (plastic_project(mats[k], F) > 0.0) mul(Ai, F, Se);
     }
     for (int e = 0; e < 9; ++e) Seff[(k * 9 + e) * ncell + ci] = Se[e];
   }
@@ -366,7 +368,8 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
                                                 int K, double dt, double inv4dx,
                                                 const uint64_t* __restrict__ cmask,
                                                 const int32_t* __restrict__ coff,
-                                                T* __restrict__ Abar, int32_t* __restrict__ err) {
+                                                T* __restrict__ Abar, int32_t* __restrict__ err,
+    const MatParams* __restrict__ mats) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
         continue;
       }
       double dpsi[3], H[3][3], tw[3], fl[3];
-      principal_derivs(s_mats[k], s, dpsi, H, tw, fl);
+      principal_derivs(mats[k], s, dpsi, H, tw, fl);
       const double coef = dt * dt * V;
       // scaling modes: eigenpairs of the 3x3 Hessian of psi_hat
       double Hs[9] = {H[0][0], H[0][1], H[0][2], H[1][0], H[1][1], H[1][2], H[2][0], H[2][1], H[2][2]};
@@ -1533,11 +1536,12 @@ __global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
 }
 
 __global__ __launch_bounds__(64) void k_escale(const double* __restrict__ Vk, int64_t ncell, int K,
-                                               double* __restrict__ partial) {
+                                               double* __restrict__ partial,
+    const MatParams* __restrict__ mats) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   double s = 0.0;
-  for (int k = 0; k < K; ++k) s += Vk[k * ncell + ci] * (s_mats[k].mu + fabs(s_mats[k].lambda));
+  for (int k = 0; k < K; ++k) s += Vk[k * ncell + ci] * (mats[k].mu + fabs(mats[k].lambda));
   s = wave_sum(s);
   if (l == 0) partial[cb] = s;
 }
@@ -1564,12 +1568,9 @@ double now_ms() {
 }  // namespace
 
 // ======================================================================
-static mpl_status upload_mats(mpl_ctx* c) {
-  MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(s_mats), c->mats,
-                                    sizeof(MatParams) * MPL_MAX_MATERIALS, 0,
-                                    hipMemcpyHostToDevice, c->stream));
-  return MPL_OK;
-}
+// The materials live in the context's own device table (copied at creation),
+// so contexts on one GPU never share them.
+static mpl_status upload_mats(mpl_ctx*) { return MPL_OK; }
 
 static mpl_status ensure_partials(mpl_ctx* c) {
   size_t n = std::max(c->n_cblk, c->n_nblk) + 64;
@@ -1591,7 +1592,7 @@ static mpl_status plastic_base(mpl_ctx* c, const double* v) {
   MPL_TRY(mpl_ensure(c, c->Seff, sizeof(double) * 9 * c->nmat * ncell));
   MPL_LAUNCH(c, k_plastic_base, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node), P<double>(c->Vk),
              P<double>(c->Sk), ncell, c->nmat, c->dt, 0.25 * c->inv_dx, P<double>(c->Seff),
-             &c->dscal()->err);
+             &c->dscal()->err, P<MatParams>(c->matbuf));
   c->s_general = true;
   return MPL_OK;
 }
@@ -1602,7 +1603,7 @@ mpl_status mpl_stage_reconstruct(mpl_ctx* c) {
   const int64_t ncell = (int64_t)c->ncell_alloc();
   MPL_HIP(c, hipMemsetAsync(&c->dscal()->domain_count, 0, sizeof(int32_t), c->stream));
   MPL_LAUNCH(c, k_reconstruct, (int)((ncell + 127) / 128), 128, P<double>(c->Vk), P<double>(c->Tk),
-             P<double>(c->Sk), ncell, c->nmat, &c->dscal()->domain_count);
+             P<double>(c->Sk), ncell, c->nmat, &c->dscal()->domain_count, P<MatParams>(c->matbuf));
   c->reconstructed = true;
   c->s_general = false;
   return MPL_OK;
@@ -1623,7 +1624,7 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
     MPL_TRY(mpl_ensure(c, c->Qc, 8 * 9 * ncell));
     MPL_TRY(mpl_ensure(c, c->g, 8 * 3 * nnode));
     MPL_LAUNCH(c, k_energy_cells<true>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Qc), pc);
+               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, P<double>(c->Qc), pc, P<MatParams>(c->matbuf));
     MPL_LAUNCH(c, k_energy_nodes<true>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), P<double>(c->Qc), ncell, nnode, c->dt,
                inv4dx, P<double>(c->g), pe, pg);
@@ -1634,7 +1635,7 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
                c->dscal(), 0);
   } else {
     MPL_LAUNCH(c, k_energy_cells<false>, c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, (double*)nullptr, pc);
+               P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, (double*)nullptr, pc, P<MatParams>(c->matbuf));
     MPL_LAUNCH(c, k_energy_nodes<false>, c->n_nblk, 64, v, P<double>(c->vhat), P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), (const double*)nullptr, ncell, nnode,
                c->dt, inv4dx, (double*)nullptr, pe, (double*)nullptr);
@@ -1666,14 +1667,14 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     if (fact) {
       MPL_LAUNCH(c, (k_tangent<float, true>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                  P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err);
+                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf));
       MPL_LAUNCH(c, (k_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                  P<float>(c->Dt), P<float>(c->mt));
     } else {
       MPL_LAUNCH(c, (k_tangent<float, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                  P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err);
+                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf));
       MPL_LAUNCH(c, (k_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                  P<float>(c->Dt), P<float>(c->mt));
@@ -1682,7 +1683,7 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     MPL_TRY(mpl_ensure(c, c->Abar64, 8 * MPL_TAN_DENSE * ntan));
     MPL_LAUNCH(c, (k_tangent<double, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-               P<double>(c->Abar64), &c->dscal()->err);
+               P<double>(c->Abar64), &c->dscal()->err, P<MatParams>(c->matbuf));
     MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
     MPL_LAUNCH(c, (k_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
@@ -2477,7 +2478,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   double* v = P<double>(c->v);
   // energy rounding scale sum V (mu + |lambda|) for the line-search allowance
   MPL_LAUNCH(c, k_escale, c->n_cblk, 64, P<double>(c->Vk), (int64_t)c->ncell_alloc(), c->nmat,
-             partial_slot(c, 3));
+             partial_slot(c, 3), P<MatParams>(c->matbuf));
   MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, partial_slot(c, 3), c->n_cblk, partial_slot(c, 3), 0,
              partial_slot(c, 3), 0, c->dscal(), 4);
   MPL_TRY(mpl_sync_scalars(c));

@@ -28,7 +28,6 @@ struct ParticlesDev {
   int64_t n;
 };
 
-__constant__ MatParams c_mats[MPL_MAX_MATERIALS];
 
 __global__ void k_mark(ParticlesDev P, GridDev g, int32_t* __restrict__ pcell,
                        int32_t* __restrict__ cflag, int32_t* __restrict__ err) {
@@ -193,7 +192,8 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
                                             double* __restrict__ mc, double* __restrict__ qc,
                                             double* __restrict__ Gc, double* __restrict__ Vk,
                                             double* __restrict__ Tk, int64_t ncell,
-                                            double* __restrict__ halo, int32_t* __restrict__ err) {
+                                            double* __restrict__ halo, int32_t* __restrict__ err,
+    const MatParams* __restrict__ mats) {
   constexpr int NV = 13 + 7 * K;
   __shared__ double tile[NV][128];
   const int lane = threadIdx.x;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(64) void k_p2c(ParticlesDev P, GridDev g,
       k = P.mat[p];
       double F[9];
       for (int j = 0; j < 9; ++j) F[j] = P.F[9 * p + j];
-      if (k < 0 || k >= K || !kirchhoff(c_mats[k], F, tau)) {
+      if (k < 0 || k >= K || !kirchhoff(mats[k], F, tau)) {
         atomicOr(err, 2);
         for (int j = 0; j < 6; ++j) tau[j] = 0.0;
         if (k < 0 || k >= K) k = 0;
@@ -512,8 +512,6 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
   const double* Gin = c->opts.transfer == MPL_TRANSFER_FLIP_PIC ? nullptr : in->G;
   ParticlesDev parts{in->x, in->v, in->F, Gin, in->m, in->V0, in->mat, np};
 
-  MPL_HIP(c, hipMemcpyToSymbolAsync(HIP_SYMBOL(c_mats), c->mats, sizeof(MatParams) * MPL_MAX_MATERIALS,
-                                    0, hipMemcpyHostToDevice, c->stream));
   MPL_TRY(mpl_ensure(c, c->cflag, sizeof(int32_t) * ncb_dense));
   MPL_TRY(mpl_ensure(c, c->cmap, sizeof(int32_t) * (ncb_dense + 1)));
   MPL_TRY(mpl_ensure(c, c->nflag, sizeof(int32_t) * nnb_dense));
@@ -589,7 +587,7 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
 #define MPL_P2C(KK)                                                                                     \
   MPL_LAUNCH(c, k_p2c<KK>, c->n_cblk, 64, parts, g, P<int32_t>(c->sorted), bstart, \
              P<int4>(c->ccoord), P<int32_t>(c->cmap), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), \
-             P<double>(c->Vk), P<double>(c->Tk), ncell, P<double>(c->p2c_halo), &ds->err);             \
+             P<double>(c->Vk), P<double>(c->Tk), ncell, P<double>(c->p2c_halo), &ds->err, P<MatParams>(c->matbuf));             \
   MPL_LAUNCH(c, k_p2c_combine<KK>, c->n_cblk, 64, P<int>(c->c_nbr_node), P<int>(c->n_nbr_cell),         \
              c->n_cblk, P<double>(c->p2c_halo), P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc),   \
              P<double>(c->Vk), P<double>(c->Tk), ncell, P<int32_t>(c->cntbuf), &ds->err);            \

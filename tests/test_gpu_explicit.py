@@ -110,3 +110,32 @@ def test_integrate_explicit_needs_unload():
     ctx = gpu_context(sc, 1)
     with pytest.raises(mpmlite.MplError):
         ctx.integrate_explicit()
+
+
+def test_explicit_step_empty_particle_set():
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=8, lo=2, hi=3)
+    p = {k: v[:0] for k, v in sc.particles.items()}
+    dp = mpmlite.particles_to_device(p)
+    for opts in (dict(), dict(vbd_sweeps=2), dict(plasticity=mpmlite.PLASTICITY_FIXED_POINT),
+                 dict(transfer=mpmlite.TRANSFER_FLIP_PIC, flip_ratio=0.9)):
+        ctx = gpu_context(sc, 0, **opts)
+        st = ctx.step_explicit(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+        assert st["active_cells"] == 0
+        st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+        assert st["active_cells"] == 0 and st["pcg_iters"] == 0
+
+
+def test_explicit_particle_outside_grid_is_rejected():
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=8, lo=2, hi=4)
+    p = dict(sc.particles)
+    p["x"] = p["x"].copy()
+    p["x"][0] = [0.01, 0.5, 0.5]  # stencil would reach cell -1
+    ctx = gpu_context(sc, 0)
+    dp = mpmlite.particles_to_device(p)
+    before = host(dp["x"]).copy()
+    with pytest.raises(mpmlite.MplError) as e:
+        ctx.step_explicit(dp, dp, sc.dt, sc.gravity, sc.bcs, 0.0)
+    assert e.value.status == -7
+    assert np.array_equal(host(dp["x"]), before)

@@ -1242,7 +1242,8 @@ static int vbd_solve(const or_grid* gg, int32_t nmat, const or_material* mats, d
   return rc;
 }
 
-// Newton's method on Phi with the projected Hessian, Jacobi-preconditioned CG
+// Newton's method on Phi with the projected Hessian, Jacobi- or 3x3
+// block-Jacobi-preconditioned CG
 // for each linear system and Armijo backtracking (halving, with a rounding
 // allowance) and the model's feasibility (Phi = +inf outside the domain).
 //   stop Newton when |g_free| <= newton_rtol * |g_free(vhat)|,
@@ -1283,6 +1284,51 @@ int or_jacobi_diag(const or_grid* gg, const double* mc, const double* mi, const 
   return OR_OK;
 }
 
+// 3x3 nodal block-Jacobi preconditioner: the inverse of each free node's
+// diagonal 3x3 block of H = M + sum_c B_c^T Abar_c B_c (the coupling of the
+// node's three velocity components with each other; Jacobi keeps only its
+// diagonal),
+//   H_ii[a][a'] = m_i delta_aa'
+//               + sum_c sum_{b,b'} Abar_c[(a,b),(a',b')] dw_ic/dx_b dw_ic/dx_b',
+// and 0 on fixed and massless nodes.  Binv: [nnode][9], row-major.
+int or_block_jacobi(const or_grid* gg, const double* mc, const double* mi, const uint8_t* fixed,
+                    const double* Abar, double* Binv) {
+  Grid g{gg->n, gg->dx};
+  const int64_t nn = g.nn();
+  std::vector<double> H(9 * nn, 0.0);
+  for (int i = 0; i < g.n; ++i)
+    for (int j = 0; j < g.n; ++j)
+      for (int kk = 0; kk < g.n; ++kk) {
+        int64_t c = g.cell(i, j, kk);
+        if (mc[c] == 0.0) continue;
+        const double* Ac = Abar + 81 * c;
+        for (int d = 0; d < 8; ++d) {
+          int o[3];
+          corner(d, o);
+          int64_t nidx = g.node(i + o[0], j + o[1], kk + o[2]);
+          double gw[3];
+          grad_w(d, g.dx, gw);
+          for (int a = 0; a < 3; ++a)
+            for (int a2 = 0; a2 < 3; ++a2) {
+              double s = 0.0;
+              for (int b = 0; b < 3; ++b)
+                for (int b2 = 0; b2 < 3; ++b2) s += Ac[(a * 3 + b) * 9 + (a2 * 3 + b2)] * gw[b] * gw[b2];
+              H[9 * nidx + 3 * a + a2] += s;
+            }
+        }
+      }
+  int status = OR_OK;
+  for (int64_t nidx = 0; nidx < nn; ++nidx) {
+    double* Bi = Binv + 9 * nidx;
+    std::fill(Bi, Bi + 9, 0.0);
+    if (mi[nidx] == 0.0 || fixed[nidx]) continue;
+    double* Hn = H.data() + 9 * nidx;
+    for (int a = 0; a < 3; ++a) Hn[4 * a] += mi[nidx];
+    if (!m3_inverse(Hn, Bi)) status = OR_ERR_DOMAIN;
+  }
+  return status;
+}
+
 int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
              const double* Vck, const double* S0, const or_solver_opts* opts,
@@ -1292,7 +1338,7 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
   Grid g{gg->n, gg->dx};
   const int64_t nc = g.nc(), nn = g.nn(), nd = 3 * nn;
   std::vector<double> grad(nd), Abar(81 * nc), p(nd), r(nd), z(nd), q(nd), x(nd), D(nd),
-      vt(nd), dir(nd);
+      vt(nd), dir(nd), Binv(opts->block_jacobi ? 9 * nn : 0);
   for (int64_t i = 0; i < nd; ++i) v[i] = vhat[i];
   // the base the energy uses: S0, or with fixed-point plasticity the
   // return-mapped base of the current iterate (re-projected after every step)
@@ -1325,15 +1371,32 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
     if (gn == 0.0 || gn <= opts->newton_rtol * g0) break;
     if (it >= opts->max_newton) { result = OR_ERR_NOT_CONVERGED; break; }
     or_tangent(gg, nmat, mats, dt, Vck, Sck, v, 1, Abar.data());
-    // Jacobi preconditioner: diagonal of H.
+    // preconditioner: the diagonal of H (Jacobi) or its inverted 3x3 node
+    // blocks (block-Jacobi); z = P r
     or_jacobi_diag(gg, mc, mi, fixed, Abar.data(), D.data());
+    if (opts->block_jacobi) {
+      if (int rb = or_block_jacobi(gg, mc, mi, fixed, Abar.data(), Binv.data()); rb != OR_OK) {
+        result = rb;
+        break;
+      }
+    }
+    auto precondition = [&]() {
+      if (opts->block_jacobi) {
+        for (int64_t n = 0; n < nn; ++n)
+          for (int a = 0; a < 3; ++a)
+            z[3 * n + a] = Binv[9 * n + 3 * a] * r[3 * n] + Binv[9 * n + 3 * a + 1] * r[3 * n + 1] +
+                           Binv[9 * n + 3 * a + 2] * r[3 * n + 2];
+      } else {
+        for (int64_t i = 0; i < nd; ++i) z[i] = D[i] > 0.0 ? r[i] / D[i] : 0.0;
+      }
+    };
     // CG on H x = -g
     for (int64_t i = 0; i < nd; ++i) {
       x[i] = 0.0;
       r[i] = -grad[i];
-      z[i] = D[i] > 0.0 ? r[i] / D[i] : 0.0;
-      p[i] = z[i];
     }
+    precondition();
+    for (int64_t i = 0; i < nd; ++i) p[i] = z[i];
     double bn = std::sqrt(dot(r, r));
     double rz = dot(r, z);
     int k = 0;
@@ -1347,7 +1410,7 @@ int or_solve(const or_grid* gg, int32_t nmat, const or_material* mats, double dt
         r[i] -= alpha * q[i];
       }
       if (std::sqrt(dot(r, r)) <= opts->pcg_rtol * bn) { ++k; break; }
-      for (int64_t i = 0; i < nd; ++i) z[i] = D[i] > 0.0 ? r[i] / D[i] : 0.0;
+      precondition();
       double rz2 = dot(r, z);
       double beta = rz2 / rz;
       rz = rz2;

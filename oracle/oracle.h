@@ -77,6 +77,9 @@ typedef struct {
    * free node of the colour takes v_i -= H_ii^{-1} g_i with the 3x3 node
    * block H_ii = m_i I + sum_c (its block of Abar_c) */
   int32_t vbd_sweeps;
+  /* 1: the CG is preconditioned with the inverted 3x3 node blocks of H
+   * (or_block_jacobi) instead of its diagonal */
+  int32_t block_jacobi;
 } or_solver_opts;
 
 typedef struct {
@@ -126,6 +129,8 @@ int or_explicit_force(const or_grid* g, int32_t nmat, const double* Vck,
                       const double* tauck, double* f);
 int or_jacobi_diag(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,
                    const double* Abar, double* D);
+int or_block_jacobi(const or_grid* g, const double* mc, const double* mi, const uint8_t* fixed,
+                    const double* Abar, double* Binv);
 int or_solve(const or_grid* g, int32_t nmat, const or_material* mats, double dt,
              const double* mc, const double* mi, const double* vhat, const uint8_t* fixed,
              const double* Vck, const double* Sck, const or_solver_opts* opts,

@@ -44,7 +44,8 @@ class _BC(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("pcg_rtol", C.c_double), ("armijo_c", C.c_double),
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32), ("max_ls", C.c_int32),
-                ("fixed_point_plasticity", C.c_int32), ("vbd_sweeps", C.c_int32)]
+                ("fixed_point_plasticity", C.c_int32), ("vbd_sweeps", C.c_int32),
+                ("block_jacobi", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -112,10 +113,12 @@ class SolverOpts:
     max_ls: int = 40
     fixed_point_plasticity: int = 0
     vbd_sweeps: int = 0
+    block_jacobi: int = 0
 
     def c(self) -> _Opts:
         return _Opts(self.newton_rtol, self.pcg_rtol, self.armijo_c, self.max_newton,
-                     self.max_pcg, self.max_ls, self.fixed_point_plasticity, self.vbd_sweeps)
+                     self.max_pcg, self.max_ls, self.fixed_point_plasticity, self.vbd_sweeps,
+                     self.block_jacobi)
 
 
 def _p(a: np.ndarray, ctype=C.c_double):
@@ -277,6 +280,16 @@ def jacobi_diag(grid: Grid, mc, mi, fixed, Abar):
                          _p(np.ascontiguousarray(fixed, dtype=np.uint8), C.c_uint8), _p(_f64(Abar)),
                          _p(D))
     return D
+
+
+def block_jacobi(grid: Grid, mc, mi, fixed, Abar):
+    """Inverted 3x3 node blocks of the Newton matrix H on free nodes (0
+    elsewhere), [nnode, 3, 3]."""
+    B = np.zeros((grid.nnode, 3, 3))
+    rc = lib().or_block_jacobi(C.byref(grid.c()), _p(_f64(mc)), _p(_f64(mi)),
+                               _p(np.ascontiguousarray(fixed, dtype=np.uint8), C.c_uint8), _p(_f64(Abar)),
+                               _p(B))
+    return B, rc
 
 
 def plastic_base(grid: Grid, mats, dt, Vck, S0, v):

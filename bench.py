@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--vbd-steps", type=int, default=10,
                     help="timed steps of the VBD-vs-Newton-PCG leg (two-material bar, 64^3); 0 = skip")
     ap.add_argument("--vbd-sweeps", type=int, default=4)
+    ap.add_argument("--bj-steps", type=int, default=5,
+                    help="timed steps of the block-Jacobi leg, after 3 untimed ones (0 = skip the leg)")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,
@@ -162,9 +164,11 @@ def main():
     cells = nodes = 0
     hv_bytes = 0.0
     tan_entries = 0
+    traj = {}   # trajectory step -> (CG iterations, host-timed ms of the step's stages)
     t0 = time.perf_counter()
     for k in range(args.steps):
         st = one_step()
+        traj[args.warmup + k] = (st["pcg_iters"], st["ms_unload"] + st["ms_newton"] + st["ms_load"])
         hv_ms += st["hv_ms_total"]
         hv_calls += st["hv_calls"]
         up_ms += st["upd_ms_total"]
@@ -206,6 +210,9 @@ def main():
               "frac": round(up_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": up_bytes,
               "avg_ms": round(up_avg_ms, 5), "launches": up_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
+    block_jacobi = None
+    if args.bj_steps > 0:
+        block_jacobi = block_jacobi_leg(ctx, sc, args, steps_per_s, counts, traj)
     learned = None
     if args.learned_steps > 0:
         learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts)
@@ -238,11 +245,60 @@ def main():
         "roofline": roof,
         "update_kernel": update,
         "cpu_baseline": base,
+        "block_jacobi": block_jacobi,
         "learned": learned,
         "explicit": explicit,
         "vbd": vbd,
     }
     print(json.dumps(line), flush=True)
+
+
+def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untimed=3):
+    """The same workload from its initial state with the 3x3 nodal
+    block-Jacobi preconditioner in the same single-reduction CG and warm
+    start: ``untimed`` steps (the warm start's history fills up), then
+    ``bj_steps`` timed steps.  The CG count falls along the trajectory, so
+    the comparison with Jacobi is also made over the same trajectory steps
+    of the main run (host stage timers on both sides)."""
+    import torch
+    from paper_2602_07853_amd import mpmlite
+    parts = mpmlite.particles_to_device(sc.particles)
+    ctx.set_opts(time_kernels=0, precond=mpmlite.PRECOND_BLOCK_JACOBI)
+    t = 0.0
+    for k in range(untimed):
+        ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+    torch.cuda.synchronize()
+    newton = pcg = 0
+    host_ms = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.bj_steps):
+        st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        newton += st["newton_iters"]
+        pcg += st["pcg_iters"]
+        host_ms += st["ms_unload"] + st["ms_newton"] + st["ms_load"]
+        print(f"[bench] block-Jacobi step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_opts(precond=mpmlite.PRECOND_JACOBI)
+    n = args.bj_steps
+    sps = n / el
+    out = {"steps_per_s": round(sps, 4), "steps": n, "untimed_steps": untimed,
+           "ms_per_step": round(1e3 * el / n, 3), "newton_per_step": round(newton / n, 3),
+           "pcg_per_step": round(pcg / n, 2), "vs_jacobi": round(sps / plain_steps_per_s, 4),
+           "jacobi_pcg_per_step": round(plain_counts[1], 2), "same_steps": None}
+    window = range(untimed, untimed + n)
+    if all(i in traj for i in window):
+        jp = sum(traj[i][0] for i in window) / n
+        jm = sum(traj[i][1] for i in window) / n
+        bm = host_ms / n
+        out["same_steps"] = {"trajectory_steps": [window.start, window.stop - 1],
+                             "jacobi_pcg_per_step": round(jp, 2), "block_jacobi_pcg_per_step": round(pcg / n, 2),
+                             "jacobi_host_ms": round(jm, 2), "block_jacobi_host_ms": round(bm, 2),
+                             "speed_vs_jacobi": round(jm / bm, 4)}
+    return out
 
 
 def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):

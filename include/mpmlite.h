@@ -67,8 +67,13 @@ enum { MPL_PLASTIC_NONE = 0, MPL_PLASTIC_VON_MISES = 1, MPL_PLASTIC_DRUCKER_PRAG
 enum { MPL_BC_STICKY_BOX = 0, MPL_BC_MOVING_BOX = 1 };
 /* Precision of the stored tangent and of the Hessian-vector product. */
 enum { MPL_F32 = 0, MPL_F64 = 1 };
-/* Preconditioner of the Newton linear systems. */
-enum { MPL_PRECOND_JACOBI = 0, MPL_PRECOND_LEARNED = 2 };
+/* Preconditioner of the Newton linear systems (the preconditioned
+ * matrix-free CG of Sec. 5): the inverse diagonal of H (Jacobi); the
+ * inverses of its 3x3 node blocks H_ii = m_i I + sum_c (node block of
+ * B_c^T Abar_c B_c), which couple a node's three velocity components
+ * (block-Jacobi; single-reduction CG only, MPL_CG_CLASSIC=1 rejects it); or
+ * the learned network (see below). */
+enum { MPL_PRECOND_JACOBI = 0, MPL_PRECOND_BLOCK_JACOBI = 1, MPL_PRECOND_LEARNED = 2 };
 
 typedef struct {
   double dx;
@@ -86,7 +91,7 @@ typedef struct {
 
 typedef struct {
   int32_t hv_precision;   /* MPL_F32 (production) or MPL_F64 (parity) */
-  int32_t precond;        /* MPL_PRECOND_JACOBI or MPL_PRECOND_LEARNED */
+  int32_t precond;        /* MPL_PRECOND_JACOBI, _BLOCK_JACOBI or _LEARNED */
   double newton_rtol;     /* stop when |g_free| <= newton_rtol * |g_free(vhat)| */
   double pcg_rtol;        /* stop CG when |r| <= pcg_rtol * |b| */
   int32_t max_newton, max_pcg, max_ls;
@@ -276,7 +281,10 @@ enum {
   MPL_FIELD_VHAT = 9,     /* nodes, 3 */
   MPL_FIELD_FIXED = 10,   /* nodes, 1 (1.0 = Dirichlet) */
   MPL_FIELD_V = 11,       /* nodes, 3 (current Newton iterate / solution) */
-  MPL_FIELD_DIAG = 12     /* nodes, 3 (inverse Jacobi diagonal; 0 on fixed/massless nodes) */
+  MPL_FIELD_DIAG = 12,    /* nodes, 3 (inverse Jacobi diagonal; 0 on fixed/massless nodes) */
+  MPL_FIELD_BLOCK_DIAG = 13 /* nodes, 9 (inverted 3x3 node block of H, row-major; 0 on
+                             * fixed/massless nodes; needs a tangent built with
+                             * precond = MPL_PRECOND_BLOCK_JACOBI) */
 };
 mpl_status mpl_export_field(mpl_ctx* ctx, int32_t field, double* dense_out);
 

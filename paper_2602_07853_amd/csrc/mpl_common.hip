@@ -225,8 +225,11 @@ static mpl_status derive_materials(mpl_ctx* c, const mpl_material* mats, int n) 
 static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
   if (o->hv_precision != MPL_F32 && o->hv_precision != MPL_F64)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "hv_precision must be MPL_F32 or MPL_F64");
-  if (o->precond != MPL_PRECOND_JACOBI && o->precond != MPL_PRECOND_LEARNED)
+  if (o->precond != MPL_PRECOND_JACOBI && o->precond != MPL_PRECOND_BLOCK_JACOBI &&
+      o->precond != MPL_PRECOND_LEARNED)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->precond == MPL_PRECOND_BLOCK_JACOBI && !c->cg_single)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "block-Jacobi runs in the single-reduction CG only");
   if (o->time_kernels < 0 || o->time_kernels > 2)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "time_kernels must be 0, 1 or 2");
   if (o->warm_start < 0 || o->warm_start > 4)
@@ -305,7 +308,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
                    &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->Seff, &c->matbuf, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
-                   &c->D, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
+                   &c->D, &c->Bj, &c->Bjt, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
                    &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->wtmp, &c->warm_x0, &c->gal_w,
                    &c->gal_u, &c->gal_y,

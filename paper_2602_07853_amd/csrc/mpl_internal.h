@@ -115,6 +115,10 @@ struct mpl_ctx {
   // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
   // (read by the CG vector kernels)
   DevBuf Dt, mt;
+  // Bj, Bjt: inverted 3x3 node blocks of H (xx, yy, zz, xy, yz, xz), FP64
+  // and in the tangent's precision, when block-Jacobi is selected
+  DevBuf Bj, Bjt;
+  bool bj_built = false;  // Bj/Bjt match the current tangent
   DevBuf mi, vn, vhat, flags, v, g, vt, dir, r, x, p32, p64, q32, q64, z, D, partials,
       dense_tmp32, dense_tmp64;
   // scalars

@@ -273,6 +273,15 @@ __global__ void k_flags_to_double(const uint8_t* __restrict__ fl, double* __rest
   if (i < n) out[i] = (fl[i] & MPL_NODE_FIXED) ? 1.0 : 0.0;
 }
 
+// the six stored entries (xx, yy, zz, xy, yz, xz) of symmetric node blocks,
+// component-major, to all nine (row-major), component-major
+__global__ void k_sym6_to_9(const double* __restrict__ b6, double* __restrict__ b9, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int map[9] = {0, 3, 5, 3, 1, 4, 5, 4, 2};
+  for (int e = 0; e < 9; ++e) b9[e * n + i] = b6[map[e] * n + i];
+}
+
 double wall_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch())
@@ -443,6 +452,14 @@ mpl_status mpl_export_field(mpl_ctx* c, int32_t field, double* dense) {
     case MPL_FIELD_DIAG:
       if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "tangent not built");
       MPL_TRY(mpl_block_to_dense_nodes(c, c->D.p, dense, 3, 0));
+      break;
+    case MPL_FIELD_BLOCK_DIAG:
+      if (!c->tangent_built || !c->bj_built)
+        return mpl_fail(c, MPL_ERR_STATE, "block-Jacobi blocks not built (tangent with precond = block-Jacobi)");
+      MPL_TRY(mpl_ensure(c, c->dense_tmp64, 8 * 9 * nnode));
+      MPL_LAUNCH(c, k_sym6_to_9, (int)((nnode + 255) / 256), 256, P<double>(c->Bj), P<double>(c->dense_tmp64),
+                 nnode);
+      MPL_TRY(mpl_block_to_dense_nodes(c, c->dense_tmp64.p, dense, 9, 0));
       break;
     default:
       return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown field");

@@ -466,18 +466,22 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
   if (FACT) {
 #pragma unroll
     for (int i = 0; i < MPL_TAN_FACT_READ; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
-    // Jacobi-diagonal contributions Q_a(s) = sum_{b,b'} Abar[(a,b),(a,b')]
-    // sig_b sig_b' / (4 dx)^2 for the corner signs sig = (+1, sy, sz),
-    // s = 2 (sy < 0) + (sz < 0) (a corner and its opposite share the value)
+    // node-block contributions Q_e(s) = sum_{b,b'} Abar[(a,b),(a',b')]
+    // sig_b sig_b' / (4 dx)^2 for the entries e = (a, a') of the 3x3 block
+    // (xx, yy, zz, xy, yz, xz; the first three are the Jacobi diagonal) and
+    // the corner signs sig = (+1, sy, sz), s = 2 (sy < 0) + (sz < 0) (a corner
+    // and its opposite share the value)
     const double g2 = inv4dx * inv4dx;
-    for (int a = 0; a < 3; ++a)
+    for (int e = 0; e < 6; ++e) {
+      const int a = e < 3 ? e : (e == 5 ? 0 : e - 3), a2 = e < 3 ? e : (e == 5 ? 2 : e - 2);
       for (int sidx = 0; sidx < 4; ++sidx) {
         const double sg[3] = {1.0, (sidx & 2) ? -1.0 : 1.0, (sidx & 1) ? -1.0 : 1.0};
         double q = 0.0;
         for (int b = 0; b < 3; ++b)
-          for (int b2 = 0; b2 < 3; ++b2) q += Ab[sym9(a * 3 + b, a * 3 + b2)] * sg[b] * sg[b2];
-        Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + a * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
+          for (int b2 = 0; b2 < 3; ++b2) q += Ab[sym9(a * 3 + b, a2 * 3 + b2)] * sg[b] * sg[b2];
+        Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + e * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
       }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 45; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)Ab[i];
@@ -533,6 +537,79 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
     Dt[a * nnode + ni] = (T)di;
   }
   mt[ni] = (T)mi[ni];
+}
+
+// pair index of the symmetric 3x3 block entries (xx, yy, zz, xy, yz, xz)
+__host__ __device__ constexpr int blk_a(int e) { return e < 3 ? e : (e == 5 ? 0 : e - 3); }
+__host__ __device__ constexpr int blk_b(int e) { return e < 3 ? e : (e == 5 ? 2 : e - 2); }
+
+// 3x3 block-Jacobi preconditioner: at every free node the inverse of its
+// diagonal block of H,
+//   H_ii[a][a'] = m_i delta_aa' + sum_c sum_{b,b'} Abar[(a,b),(a',b')] gw_b gw_b',
+// stored as its six distinct entries (xx, yy, zz, xy, yz, xz) in FP64 (B)
+// and in the tangent's precision (Bt); 0 on fixed and massless nodes.  The
+// block is m I plus a positive semidefinite sum, so it is invertible
+// whenever m > 0; the inverse is the adjugate over the determinant.
+template <class T, bool FACT>
+__global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
+                                                   const uint64_t* __restrict__ cmask,
+                                                   const int32_t* __restrict__ coff,
+                                                   const double* __restrict__ mi,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const int* __restrict__ n_nbr_cell, int64_t nnode,
+                                                   double inv4dx, double* __restrict__ B,
+                                                   T* __restrict__ Bt) {
+  const int nb = blockIdx.x, l = threadIdx.x;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool fr = flags[ni] & MPL_NODE_FREE;
+  if (fr) {
+    for (int d = 0; d < 8; ++d) {
+      const int ci = node_cell(n_nbr_cell, nb, l, d);
+      if (ci < 0) continue;
+      const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
+      if (!ts.active) continue;
+      if (FACT) {
+        const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
+        const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
+        const int sidx = sy * 2 + sz;
+        for (int e = 0; e < 6; ++e)
+          h[e] += (double)Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + e * 4 + sidx) * ts.n + ts.rank];
+        continue;
+      }
+      double gw[3];
+      corner_grad(d, inv4dx, gw);
+      for (int e = 0; e < 6; ++e) {
+        const int a = blk_a(e), a2 = blk_b(e);
+        double s = 0.0;
+        for (int b = 0; b < 3; ++b)
+          for (int b2 = 0; b2 < 3; ++b2)
+            s += (double)Abar[ts.base + (int64_t)sym9(a * 3 + b, a2 * 3 + b2) * ts.n + ts.rank] * gw[b] *
+                 gw[b2];
+        h[e] += s;
+      }
+    }
+    for (int a = 0; a < 3; ++a) h[a] += mi[ni];
+  }
+  // adjugate of [[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]]
+  const double xx = h[0], yy = h[1], zz = h[2], xy = h[3], yz = h[4], xz = h[5];
+  const double c00 = yy * zz - yz * yz, c11 = xx * zz - xz * xz, c22 = xx * yy - xy * xy;
+  const double c01 = xz * yz - xy * zz, c12 = xy * xz - xx * yz, c02 = xy * yz - yy * xz;
+  const double det = xx * c00 + xy * c01 + xz * c02;
+  const double id = fr ? 1.0 / det : 0.0;
+  const double inv[6] = {c00 * id, c11 * id, c22 * id, c01 * id, c12 * id, c02 * id};
+  for (int e = 0; e < 6; ++e) {
+    B[e * nnode + ni] = inv[e];
+    Bt[e * nnode + ni] = (T)inv[e];
+  }
+}
+
+// z = B r with B a symmetric 3x3 block given by its entries (xx, yy, zz, xy,
+// yz, xz)
+__device__ __forceinline__ void block_apply(const double b[6], const double r[3], double z[3]) {
+  z[0] = b[0] * r[0] + b[3] * r[1] + b[5] * r[2];
+  z[1] = b[3] * r[0] + b[1] * r[1] + b[4] * r[2];
+  z[2] = b[5] * r[0] + b[4] * r[1] + b[2] * r[2];
 }
 
 // Vertex block descent (Sec. 5, VBD), one colour: every free node whose index
@@ -979,7 +1056,9 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
 // u = Dinv r is stored for the product but not read back by the update,
 // which forms it again from r and Dinv (same rounding).
 #define CG_FLUSH 8
-template <class T>
+// BJ: Dinv holds the inverted 3x3 node blocks (block_apply layout, six
+// entries per node) instead of the inverse diagonal, and u = B r.
+template <class T, bool BJ>
 __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, const T* __restrict__ Dinv,
                                                  const T* __restrict__ mi, const uint8_t* __restrict__ flags,
                                                  int64_t nnode, int n_nblk, double* __restrict__ x,
@@ -998,6 +1077,25 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     const bool fr = flags[ni] & MPL_NODE_FREE;
     const double m = (double)mi[ni];
+    if constexpr (BJ) {
+      double rb[3], bk[6], z[3];
+      for (int a = 0; a < 3; ++a) rb[a] = fr ? b[a * nnode + ni] : 0.0;
+      for (int e = 0; e < 6; ++e) bk[e] = (double)Dinv[e * nnode + ni];
+      block_apply(bk, rb, z);
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        const T uv = (T)z[a];
+        x[i] = 0.0;
+        dx[i] = T(0);
+        r[i] = rb[a];
+        u[i] = uv;
+        p[i] = T(0);
+        sv[i] = T(0);
+        g += rb[a] * (double)uv;
+        bb += rb[a] * rb[a];
+        mu += m * (double)uv * (double)uv;
+      }
+    } else
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
       const double rv = fr ? b[i] : 0.0;
@@ -1037,7 +1135,7 @@ __global__ void k_cg_prep(const double* __restrict__ x0, const uint8_t* __restri
 // Warm-start variant of k_cg_init: x = x0, r = b - H x0 (the product's
 // pieces and u = x0 given), then as k_cg_init; the b.b partial stays the
 // tolerance reference.
-template <class T>
+template <class T, bool BJ>
 __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__ b,
                                                       const double* __restrict__ x0,
                                                       const T* __restrict__ Hown, const T* __restrict__ Hhalo,
@@ -1059,6 +1157,29 @@ __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__
     const T m = mi[ni];
     T h[3] = {T(0), T(0), T(0)};
     if (fr) gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    if constexpr (BJ) {
+      double bv[3], rb[3], bk[6], z[3];
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        bv[a] = fr ? b[i] : 0.0;
+        rb[a] = fr ? bv[a] - (double)(h[a] + m * u[i]) : 0.0;
+      }
+      for (int e = 0; e < 6; ++e) bk[e] = (double)Dinv[e * nnode + ni];
+      block_apply(bk, rb, z);
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        const T uv = (T)z[a];
+        x[i] = fr ? x0[i] : 0.0;
+        dx[i] = T(0);
+        r[i] = rb[a];
+        u[i] = uv;
+        p[i] = T(0);
+        sv[i] = T(0);
+        g += rb[a] * (double)uv;
+        bb += bv[a] * bv[a];
+        mu += (double)m * (double)uv * (double)uv;
+      }
+    } else
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
       const double bv = fr ? b[i] : 0.0;
@@ -1085,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__
   }
 }
 
-template <class T>
+template <class T, bool BJ>
 __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restrict__ p, T* __restrict__ sv,
                                                  const T* __restrict__ Hown, const T* __restrict__ Hhalo,
                                                  const int* __restrict__ n_nbr_cell, int64_t ncell,
@@ -1104,6 +1225,64 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
   const bool odd = (it & 1) != 0;
   const bool flush = ((it + 1) % CG_FLUSH) == 0;  // odd iterations only (CG_FLUSH even)
   double g = 0.0, rr = 0.0, mu = 0.0;
+  if constexpr (BJ) {
+    // block-Jacobi: the same recurrence with u = B r (all three components
+    // of r enter each component of u)
+    if (nb < n_nblk) {
+      const int64_t ni = (int64_t)nb * MPL_BC + l;
+      const bool fr = flags[ni] & MPL_NODE_FREE;
+      T pv[3], svv[3], dxv[3] = {T(0), T(0), T(0)};
+      double xv[3] = {0.0, 0.0, 0.0}, rv[3], bk[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int64_t i = a * nnode + ni;
+        pv[a] = p[i];
+        svv[a] = sv[i];
+        if (odd) dxv[a] = dx[i];
+        if (flush) xv[a] = x[i];
+        rv[a] = r[i];
+      }
+#pragma unroll
+      for (int e = 0; e < 6; ++e) bk[e] = (double)Dinv[e * nnode + ni];
+      const T m = mi[ni];
+      T h[3];
+      gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+      if (fr) {
+        double ud[3], rn[3], und[3];
+        block_apply(bk, rv, ud);  // u_j = B r_j as stored for the product
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int64_t i = a * nnode + ni;
+          const T uv = (T)ud[a];
+          const T w = h[a] + m * uv;
+          const T pn = (T)((double)uv + beta * (double)pv[a]);
+          const T sn = (T)((double)w + beta * (double)svv[a]);
+          rn[a] = rv[a] - alpha * (double)sn;
+          p[i] = pn;
+          sv[i] = sn;
+          if (odd) {
+            const double inc = (double)dxv[a] + (alpha_last * (double)pv[a] + alpha * (double)pn);
+            if (flush) {
+              x[i] = xv[a] + inc;
+              dx[i] = T(0);
+            } else {
+              dx[i] = (T)inc;
+            }
+          }
+          r[i] = rn[a];
+        }
+        block_apply(bk, rn, und);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const T un = (T)und[a];
+          u[a * nnode + ni] = un;
+          g += rn[a] * (double)un;
+          rr += rn[a] * rn[a];
+          mu += (double)m * (double)un * (double)un;
+        }
+      }
+    }
+  } else
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     // all loads of the node (three components, the flag, the gathered
@@ -1656,8 +1835,9 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   const int64_t ntan = (int64_t)c->hscal.n_tan_cells + 64;
   const uint64_t* cm = P<uint64_t>(c->cmask);
   const int32_t* co = P<int32_t>(c->coff);
-  // the single-material FP32 tangent is stored factored (42 entries per
-  // cell instead of 45, 30 of them read by the Hessian-vector product)
+  // the single-material FP32 tangent is stored factored (49 entries per
+  // cell, 25 of them read by the Hessian-vector product, 24 node-block sums
+  // read by the Jacobi and block-Jacobi set-up)
   const bool fact = precision == MPL_F32 && c->nmat == 1 && c->factored_enabled;
   c->tan_factored = fact;
   if (precision == MPL_F32) {
@@ -1689,6 +1869,24 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     MPL_LAUNCH(c, (k_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                P<double>(c->Dt), P<double>(c->mt));
+  }
+  c->bj_built = false;
+  if (c->opts.precond == MPL_PRECOND_BLOCK_JACOBI) {
+    MPL_TRY(mpl_ensure(c, c->Bj, 8 * 6 * nnode));
+    if (precision == MPL_F32) {
+      MPL_TRY(mpl_ensure(c, c->Bjt, 4 * 6 * nnode));
+      if (fact)
+        MPL_LAUNCH(c, (k_block_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt));
+      else
+        MPL_LAUNCH(c, (k_block_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt));
+    } else {
+      MPL_TRY(mpl_ensure(c, c->Bjt, 8 * 6 * nnode));
+      MPL_LAUNCH(c, (k_block_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt));
+    }
+    c->bj_built = true;
   }
   c->tangent_built = true;
   c->tangent_precision = precision;
@@ -1931,14 +2129,21 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     T* dx = P<T>(c->cg_dx);
     const int nflush = (int)((3 * nnode + 255) / 256);
     const int ngrp = (c->n_cblk + 3) / 4;
+    // Jacobi (inverse diagonal) or block-Jacobi (inverted node blocks)
+    const bool bj = c->opts.precond == MPL_PRECOND_BLOCK_JACOBI;
+    if (bj && !c->bj_built) return mpl_fail(c, MPL_ERR_STATE, "block-Jacobi blocks not built with the tangent");
+    const T* pre = bj ? P<T>(c->Bjt) : P<T>(c->Dt);
+    auto* kinit = bj ? &k_cg_init<T, true> : &k_cg_init<T, false>;
+    auto* kwarm = bj ? &k_cg_init_warm<T, true> : &k_cg_init_warm<T, false>;
+    auto* kstep = bj ? &k_cg_step<T, true> : &k_cg_step<T, false>;
     if (x0) {
       MPL_LAUNCH(c, k_cg_prep<T>, (int)((nnode + 255) / 256), 256, x0, P<uint8_t>(c->flags), nnode, u);
       MPL_TRY(hv_pieces<T>(c, u, false));
-      MPL_LAUNCH(c, k_cg_init_warm<T>, nwg, 256, b, x0, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-                 P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
+      MPL_LAUNCH(c, kwarm, nwg, 256, b, x0, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+                 pre, P<T>(c->mt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
                  u, p, sv, pa, pb, pm, s);
     } else {
-      MPL_LAUNCH(c, k_cg_init<T>, nwg, 256, b, P<T>(c->Dt), P<T>(c->mt), P<uint8_t>(c->flags), nnode,
+      MPL_LAUNCH(c, kinit, nwg, 256, b, pre, P<T>(c->mt), P<uint8_t>(c->flags), nnode,
                  c->n_nblk, x, dx, P<double>(c->r), u, p, sv, pa, pb, pm, s);
     }
     MPL_TRY(hv_pieces<T>(c, u, true));
@@ -1953,20 +2158,20 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
         e1 = next_event_in(c->up_events, c->up_event_used);
         if (e0) MPL_HIP(c, hipEventRecord(e0, c->stream));
       }
-      MPL_LAUNCH(c, k_cg_step<T>, nwg, 256, u, p, sv, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
-                 P<T>(c->mt), P<T>(c->Dt), P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
+      MPL_LAUNCH(c, kstep, nwg, 256, u, p, sv, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+                 P<T>(c->mt), pre, P<uint8_t>(c->flags), nnode, c->n_nblk, x, dx, P<double>(c->r),
                  pa, pb, pm, s);
       if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
       MPL_TRY(hv_pieces<T>(c, u, true));
       MPL_LAUNCH(c, k_reduce_cg<false>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
       return MPL_OK;
     };
-    const void* key[24] = {x,           p,           c->r.p,          c->Dt.p,
+    const void* key[24] = {x,           p,           c->r.p,          pre,
                            abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                            c->cmask.p,  c->coff.p,   u,               sv,
                            dx};
-    const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 2};
+    const int keyn[8] = {c->n_cblk, c->n_nblk, check, (int)bj, 0, 0, (int)c->tan_factored, 2};
     // a hook that reads x sees the full solution vector (flushing changes
     // the rounding of x, so it is done only for such hooks)
     std::function<mpl_status(int)> flushed_hook;

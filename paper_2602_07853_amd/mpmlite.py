@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmlite.so")
 
 F32, F64 = 0, 1
-PRECOND_JACOBI, PRECOND_LEARNED = 0, 2
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_LEARNED = 0, 1, 2
 TRANSFER_APIC, TRANSFER_FLIP_PIC = 0, 1
 PLASTICITY_AFTER_SOLVE, PLASTICITY_FIXED_POINT = 0, 1
 NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
@@ -28,7 +28,8 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "OOM", -4: "NOT_CONVERGED",
 FIELDS = dict(mass_c=(0, "cell", 1), vel_c=(1, "cell", 3), grad_c=(2, "cell", 9),
               vol_ck=(3, "cellk", 1), tau_ck=(4, "cellk", 9), s_ck=(5, "cellk", 9),
               abar=(6, "cell", 81), mass_i=(7, "node", 1), vel_i=(8, "node", 3),
-              vhat=(9, "node", 3), fixed=(10, "node", 1), v=(11, "node", 3), diag=(12, "node", 3))
+              vhat=(9, "node", 3), fixed=(10, "node", 1), v=(11, "node", 3), diag=(12, "node", 3),
+              block_diag=(13, "node", 9))
 
 
 class MplError(RuntimeError):

@@ -7,7 +7,7 @@ times, against the FP64 oracle on the same seeded inputs:
 FP64 elsewhere.  Every stage whose oracle finishes in seconds at this size is
 compared on all outputs: unload fields, stretch reconstruction, energy and
 gradient at vhat, Hessian-vector products (GPU tangent + product against the
-oracle's tangent + product), and Load of an oracle-side node velocity field."""
+oracle's tangent + product), the 3x3 block-Jacobi blocks, and Load of an oracle-side node velocity field."""
 import numpy as np
 import pytest
 
@@ -65,6 +65,8 @@ def test_energy_gradient_and_hv_full_size(full):
     assert rc == 0
     assert abs(E - Eo) <= 1e-10 * abs(Eo)
     assert rel(host(g), go) <= 1e-10
+    from paper_2602_07853_amd import mpmlite
+    ctx.set_opts(precond=mpmlite.PRECOND_BLOCK_JACOBI)   # the tangent also builds the node blocks
     ctx.build_tangent(torch.tensor(v, device="cuda"), 0)
     A, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
     rng = np.random.default_rng(7)
@@ -75,7 +77,16 @@ def test_energy_gradient_and_hv_full_size(full):
         e = rel(Hu, Huo)
         print(f"[fullsize] Hv trial {trial} rel err {e:.2e}", flush=True)
         assert e <= 1e-5
-    del A
+    # 3x3 block-Jacobi blocks from the FP32 tangent against the oracle's
+    # from its FP64 tangent, on every node
+    B = host(ctx.export("block_diag")).reshape(-1, 3, 3)
+    ctx.set_opts(precond=mpmlite.PRECOND_JACOBI)
+    Bo, rc = O.block_jacobi(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A)
+    assert rc == 0
+    e = rel(B, Bo)
+    print(f"[fullsize] block-Jacobi blocks rel err {e:.2e}", flush=True)
+    assert e <= 1e-5
+    del A, B, Bo
 
 
 def test_load_full_size(full):

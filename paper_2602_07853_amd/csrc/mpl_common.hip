@@ -308,7 +308,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->Vk, &c->Tk, &c->Sk, &c->Qc, &c->ecell, &c->Abar32, &c->Abar64, &c->Y32,
                    &c->Y64, &c->vcl, &c->Gcl, &c->dvcl, &c->bcbuf, &c->cntbuf, &c->Seff, &c->matbuf, &c->mi, &c->vn, &c->vhat, &c->flags, &c->v, &c->g,
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
-                   &c->D, &c->Bj, &c->Bjt, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
+                   &c->D, &c->Bj, &c->Bjt, &c->Aoff, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
                    &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->wtmp, &c->warm_x0, &c->gal_w,
                    &c->gal_u, &c->gal_y,

@@ -84,20 +84,24 @@ __device__ __forceinline__ TanSlot tan_slot(const uint64_t* __restrict__ cmask,
   return t;
 }
 
-// Factored single-material FP32 tangent (49 entries per cell):
+// Factored single-material FP32 tangent (37 entries per cell):
 //   0-3   unit quaternion (w, x, y, z) of U, the left singular vectors of
 //         F = (I + dt G) S (a proper rotation)
 //   4-12  M = S V (row-major)
 //   13-18 A3, the projected scaling block (00 01 02 11 12 22)
 //   19-24 (a_p, b_p) of the twist/flip pairs p = (0,1), (1,2), (0,2)
-//   25-48 Q_e(s): the cell's contribution to entry e = (xx, yy, zz, xy, yz,
-//         xz) of the 3x3 node block of H for corner sign pattern s (see
-//         k_tangent); e < 3 is the Jacobi diagonal
+//   25-36 Q_e(s): the cell's contribution to diagonal entry e = (xx, yy, zz)
+//         of the 3x3 node block of H for corner sign pattern s (see
+//         k_tangent), the Jacobi diagonal; with block-Jacobi the off-diagonal
+//         entries (xy, yz, xz) go to a separate array of MPL_TAN_OFF entries
+//         per cell in the same compact layout, so the product's reads keep
+//         this layout
 // so that Abar vec(g) = vec(U yhat M^T) with Ghat = U^T g M,
 // diag(yhat) = A3 diag(Ghat) and, for pair (i,j), yhat_ij = a Ghat_ij + b Ghat_ji,
 // yhat_ji = b Ghat_ij + a Ghat_ji.  A product reads entries 0-24.
 #define MPL_TAN_DENSE 45
-#define MPL_TAN_FACT 49
+#define MPL_TAN_FACT 37
+#define MPL_TAN_OFF 12
 #define MPL_TAN_FACT_READ 25
 
 // Rotation matrix (row-major) of a unit quaternion (w, x, y, z).

@@ -118,6 +118,7 @@ struct mpl_ctx {
   // Bj, Bjt: inverted 3x3 node blocks of H (xx, yy, zz, xy, yz, xz), FP64
   // and in the tangent's precision, when block-Jacobi is selected
   DevBuf Bj, Bjt;
+  DevBuf Aoff;  // off-diagonal node-block sums of the factored tangent (block-Jacobi only)
   bool bj_built = false;  // Bj/Bjt match the current tangent
   DevBuf mi, vn, vhat, flags, v, g, vt, dir, r, x, p32, p64, q32, q64, z, D, partials,
       dense_tmp32, dense_tmp64;

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
                                                 const uint64_t* __restrict__ cmask,
                                                 const int32_t* __restrict__ coff,
                                                 T* __restrict__ Abar, int32_t* __restrict__ err,
-    const MatParams* __restrict__ mats) {
+    const MatParams* __restrict__ mats, T* __restrict__ Aoff) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
   const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
@@ -468,18 +468,23 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
     for (int i = 0; i < MPL_TAN_FACT_READ; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
     // node-block contributions Q_e(s) = sum_{b,b'} Abar[(a,b),(a',b')]
     // sig_b sig_b' / (4 dx)^2 for the entries e = (a, a') of the 3x3 block
-    // (xx, yy, zz, xy, yz, xz; the first three are the Jacobi diagonal) and
-    // the corner signs sig = (+1, sy, sz), s = 2 (sy < 0) + (sz < 0) (a corner
-    // and its opposite share the value)
+    // (xx, yy, zz, xy, yz, xz; the first three are the Jacobi diagonal, the
+    // others are written to Aoff when it is given) and the corner signs
+    // sig = (+1, sy, sz), s = 2 (sy < 0) + (sz < 0) (a corner and its
+    // opposite share the value)
     const double g2 = inv4dx * inv4dx;
-    for (int e = 0; e < 6; ++e) {
+    const TanSlot to = tan_slot(cmask, coff, cb, l, MPL_TAN_OFF);
+    for (int e = 0; e < (Aoff ? 6 : 3); ++e) {
       const int a = e < 3 ? e : (e == 5 ? 0 : e - 3), a2 = e < 3 ? e : (e == 5 ? 2 : e - 2);
       for (int sidx = 0; sidx < 4; ++sidx) {
         const double sg[3] = {1.0, (sidx & 2) ? -1.0 : 1.0, (sidx & 1) ? -1.0 : 1.0};
         double q = 0.0;
         for (int b = 0; b < 3; ++b)
           for (int b2 = 0; b2 < 3; ++b2) q += Ab[sym9(a * 3 + b, a2 * 3 + b2)] * sg[b] * sg[b2];
-        Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + e * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
+        if (e < 3)
+          Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + e * 4 + sidx) * ts.n + ts.rank] = (T)(q * g2);
+        else
+          Aoff[to.base + (int64_t)((e - 3) * 4 + sidx) * to.n + to.rank] = (T)(q * g2);
       }
     }
   } else {
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
                                                    const uint8_t* __restrict__ flags,
                                                    const int* __restrict__ n_nbr_cell, int64_t nnode,
                                                    double inv4dx, double* __restrict__ B,
-                                                   T* __restrict__ Bt) {
+                                                   T* __restrict__ Bt, const T* __restrict__ Aoff) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -573,8 +578,11 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
         const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
         const int sidx = sy * 2 + sz;
-        for (int e = 0; e < 6; ++e)
+        const TanSlot to = tan_slot(cmask, coff, ci >> 6, ci & 63, MPL_TAN_OFF);
+        for (int e = 0; e < 3; ++e) {
           h[e] += (double)Abar[ts.base + (int64_t)(MPL_TAN_FACT_READ + e * 4 + sidx) * ts.n + ts.rank];
+          h[e + 3] += (double)Aoff[to.base + (int64_t)(e * 4 + sidx) * to.n + to.rank];
+        }
         continue;
       }
       double gw[3];
@@ -1835,11 +1843,15 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   const int64_t ntan = (int64_t)c->hscal.n_tan_cells + 64;
   const uint64_t* cm = P<uint64_t>(c->cmask);
   const int32_t* co = P<int32_t>(c->coff);
-  // the single-material FP32 tangent is stored factored (49 entries per
-  // cell, 25 of them read by the Hessian-vector product, 24 node-block sums
-  // read by the Jacobi and block-Jacobi set-up)
+  // the single-material FP32 tangent is stored factored (37 entries per
+  // cell, 25 of them read by the Hessian-vector product, 12 Jacobi-diagonal
+  // sums); with block-Jacobi its 12 off-diagonal node-block sums per cell go
+  // to Aoff
   const bool fact = precision == MPL_F32 && c->nmat == 1 && c->factored_enabled;
+  const bool bj = c->opts.precond == MPL_PRECOND_BLOCK_JACOBI;
   c->tan_factored = fact;
+  if (fact && bj) MPL_TRY(mpl_ensure(c, c->Aoff, 4 * MPL_TAN_OFF * ntan));
+  float* aoff = fact && bj ? P<float>(c->Aoff) : nullptr;
   if (precision == MPL_F32) {
     MPL_TRY(mpl_ensure(c, c->Abar32, 4 * (fact ? MPL_TAN_FACT : MPL_TAN_DENSE) * ntan));
     MPL_TRY(mpl_ensure(c, c->Dt, 4 * 3 * nnode));
@@ -1847,14 +1859,14 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     if (fact) {
       MPL_LAUNCH(c, (k_tangent<float, true>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                  P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf));
+                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf), aoff);
       MPL_LAUNCH(c, (k_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                  P<float>(c->Dt), P<float>(c->mt));
     } else {
       MPL_LAUNCH(c, (k_tangent<float, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                  P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf));
+                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf), (float*)nullptr);
       MPL_LAUNCH(c, (k_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
                  P<float>(c->Dt), P<float>(c->mt));
@@ -1863,7 +1875,7 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     MPL_TRY(mpl_ensure(c, c->Abar64, 8 * MPL_TAN_DENSE * ntan));
     MPL_LAUNCH(c, (k_tangent<double, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-               P<double>(c->Abar64), &c->dscal()->err, P<MatParams>(c->matbuf));
+               P<double>(c->Abar64), &c->dscal()->err, P<MatParams>(c->matbuf), (double*)nullptr);
     MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
     MPL_LAUNCH(c, (k_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
@@ -1871,20 +1883,20 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
                P<double>(c->Dt), P<double>(c->mt));
   }
   c->bj_built = false;
-  if (c->opts.precond == MPL_PRECOND_BLOCK_JACOBI) {
+  if (bj) {
     MPL_TRY(mpl_ensure(c, c->Bj, 8 * 6 * nnode));
     if (precision == MPL_F32) {
       MPL_TRY(mpl_ensure(c, c->Bjt, 4 * 6 * nnode));
       if (fact)
         MPL_LAUNCH(c, (k_block_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt));
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)aoff);
       else
         MPL_LAUNCH(c, (k_block_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt));
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)nullptr);
     } else {
       MPL_TRY(mpl_ensure(c, c->Bjt, 8 * 6 * nnode));
       MPL_LAUNCH(c, (k_block_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt));
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt), (const double*)nullptr);
     }
     c->bj_built = true;
   }

@@ -473,9 +473,14 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
     // sig = (+1, sy, sz), s = 2 (sy < 0) + (sz < 0) (a corner and its
     // opposite share the value)
     const double g2 = inv4dx * inv4dx;
+    // (fully unrolled: the entry indices into Ab must be compile-time
+    // constants, or Ab leaves registers for scratch memory)
     const TanSlot to = tan_slot(cmask, coff, cb, l, MPL_TAN_OFF);
-    for (int e = 0; e < (Aoff ? 6 : 3); ++e) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      if (e >= 3 && !Aoff) break;
       const int a = e < 3 ? e : (e == 5 ? 0 : e - 3), a2 = e < 3 ? e : (e == 5 ? 2 : e - 2);
+#pragma unroll
       for (int sidx = 0; sidx < 4; ++sidx) {
         const double sg[3] = {1.0, (sidx & 2) ? -1.0 : 1.0, (sidx & 1) ? -1.0 : 1.0};
         double q = 0.0;

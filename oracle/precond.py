@@ -63,3 +63,78 @@ def apply(params, n: int, r, D, rnd=U._ident):
     z = np.zeros_like(r)
     z[fr] = r[fr] / D[fr] + sc * o[fr] / np.sqrt(D[fr])
     return z
+
+
+# ---------------------------------------------------------------- training
+# The learned preconditioner is trained with two losses.  Both are written
+# here from their definitions (FP64, no blocking or reordering):
+#
+#  * the energy-norm loss of a preconditioned residual z for the residual r
+#    of the Newton system H x = b,
+#        L(z) = (z^T H z / 2 - z^T r) / (r^T D^{-1} r),
+#    which is minimised by z = H^{-1} r (L(z) - L(H^{-1} r) is half the
+#    squared H-norm of z - H^{-1} r, over r^T D^{-1} r), and
+#  * the pair loss of oracle/unet.py (masked relative L2) against the pair
+#    target below.
+#
+# Parameters are updated by Adam (Kingma and Ba, 2015): with gradient g at
+# step t (t = 1, 2, ...),
+#    m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+#    p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+
+
+def rdr(r, D):
+    """r^T D^{-1} r over the free DOFs (D > 0)."""
+    fr = _free(D)
+    return float(np.sum(r[fr] ** 2 / D[fr]))
+
+
+def energy_loss(z, r, Hz, D):
+    """L(z) = (z^T H z / 2 - z^T r) / (r^T D^{-1} r) over the free DOFs, with
+    Hz = H z given."""
+    fr = _free(D)
+    den = rdr(r, D)
+    if den <= 0.0:
+        return 0.0
+    return (0.5 * float(np.sum(z[fr] * Hz[fr])) - float(np.sum(z[fr] * r[fr]))) / den
+
+
+def energy_loss_grad_z(r, Hz, D):
+    """dL/dz = (H z - r) / (r^T D^{-1} r) on free DOFs, 0 elsewhere (H is
+    symmetric)."""
+    fr = _free(D)
+    den = rdr(r, D)
+    g = np.zeros_like(r)
+    if den > 0.0:
+        g[fr] = (Hz[fr] - r[fr]) / den
+    return g
+
+
+def energy_loss_grad_o(r, Hz, D):
+    """dL/do for the map z = r / D + s o / sqrt(D) of :func:`apply`:
+    s (H z - r) / (sqrt(D) r^T D^{-1} r) on free DOFs."""
+    fr = _free(D)
+    g = energy_loss_grad_z(r, Hz, D)
+    out = np.zeros_like(r)
+    out[fr] = scale(r, D) * g[fr] / np.sqrt(D[fr])
+    return out
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step at step number t >= 1; returns (p, m, v) updated."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def pair_target(r, x, xstar, D):
+    """Target of a training pair taken at a CG iterate x with residual r of
+    H x = b, x* the solution: the network output o for which the map of
+    :func:`apply` gives z = x* - x (= H^{-1} r), i.e.
+    o = sqrt(D) (x* - x - r / D) / s on free DOFs, 0 elsewhere."""
+    fr = _free(D)
+    t = np.zeros_like(r)
+    t[fr] = np.sqrt(D[fr]) * (xstar[fr] - x[fr] - r[fr] / D[fr]) / scale(r, D)
+    return t

@@ -359,6 +359,42 @@ mpl_status mpl_precond_online(mpl_ctx* ctx, int32_t every, int32_t steps, float 
  * Jacobi on those residuals when its loss is below the Jacobi one. */
 mpl_status mpl_precond_online_stats(mpl_ctx* ctx, int64_t* steps_done, double* mean_loss,
                                     double* mean_jacobi_loss);
+/* Energy-norm loss of the learned preconditioner on a residual, with the
+ * kernels of the online training (mpl_precond_online): r is a dense device
+ * FP64 node vector; with the Jacobi diagonal D of the last
+ * mpl_build_tangent and its Newton matrix H,
+ *   z = D^{-1} r + s D^{-1/2} o,  s^2 = sum_free D^{-1} r^2 / (free DOFs),
+ *   L(z) = (z^T H z / 2 - z^T r) / (r^T D^{-1} r),
+ *   dL/do = s D^{-1/2} (H z - r) / (r^T D^{-1} r)   (free DOFs, 0 elsewhere).
+ * o is the network output o_box [X][Y][Z][16] (device FP32 in the layout of
+ * mpl_nn_forward, channels 0-2 used, values rounded to BF16 as the network
+ * stores them) or, when o_box is NULL, the network's forward on the features
+ * of r.  loss and loss_jacobi (host, may be NULL) receive L(z) and the loss
+ * of the Jacobi preconditioner z = D^{-1} r; grad_o (dense device FP64 node
+ * vector, may be NULL) receives dL/do.  The network's weights are not
+ * changed.  Needs weights and a tangent (MPL_ERR_STATE otherwise). */
+mpl_status mpl_precond_energy_loss(mpl_ctx* ctx, const double* r, const float* o_box, double* loss,
+                                   double* loss_jacobi, double* grad_o);
+/* One Adam step of the network's FP32 parameters with a caller-given
+ * parameter gradient grad (device FP32, mpl_precond_param_count values),
+ * learning rate lr, betas 0.9/0.999, eps 1e-8 and bias correction
+ * (Kingma and Ba, 2015); the step number continues from the previous Adam
+ * steps since mpl_precond_set_weights, which resets the moments. */
+mpl_status mpl_precond_adam_step(mpl_ctx* ctx, const float* grad, float lr);
+/* Append one training pair built from the caller's vectors (dense device
+ * FP64 node vectors): the residual r = b - H x of a CG iterate x and the
+ * solution xstar of H x = b, under the Jacobi diagonal D of the last
+ * mpl_build_tangent; the pair stores the network features of r and the
+ * target sqrt(D) (xstar - x - D^{-1} r) / s (the output for which the map of
+ * mpl_precond_energy_loss gives z = xstar - x).  Needs room in the store
+ * (mpl_precond_reserve; MPL_ERR_OOM when full). */
+mpl_status mpl_precond_record_pair(mpl_ctx* ctx, const double* r, const double* x, const double* xstar);
+/* Copy stored training pair i (0 <= i < mpl_precond_sample_count) to device
+ * FP32 arrays on the network box of the current grid (each axis dims + 1
+ * rounded up to a multiple of 8): feat [X][Y][Z][16] (the BF16 features as
+ * FP32), target [X][Y][Z][3], mask [X][Y][Z] (1 on free nodes).  Any of
+ * the three may be NULL. */
+mpl_status mpl_precond_get_sample(mpl_ctx* ctx, int32_t i, float* feat, float* target, float* mask);
 /* Number of stored training pairs (*n, host). */
 mpl_status mpl_precond_sample_count(mpl_ctx* ctx, int32_t* n);
 /* n_steps Adam steps on the stored pairs, visited in a pseudo-random order

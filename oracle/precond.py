@@ -56,10 +56,16 @@ def features(n: int, r, D):
 def apply(params, n: int, r, D, rnd=U._ident):
     """z = r / D + s o / sqrt(D) on free nodes (``rnd`` as in unet.forward,
     also applied to the stored network input)."""
+    x = rnd(features(n, r, D))
+    return map_output(n, r, D, U.forward(params, x, rnd=rnd))
+
+
+def map_output(n: int, r, D, o_box):
+    """z = r / D + s o / sqrt(D) on free nodes, o = channels 0-2 of the
+    network output box o_box [X, Y, Z, >= 3] at the grid's nodes."""
     fr = _free(D)
     sc = scale(r, D)
-    x = rnd(features(n, r, D))
-    o = U.forward(params, x, rnd=rnd)[:n + 1, :n + 1, :n + 1, :3].reshape(-1, 3)
+    o = np.asarray(o_box)[:n + 1, :n + 1, :n + 1, :3].reshape(-1, 3)
     z = np.zeros_like(r)
     z[fr] = r[fr] / D[fr] + sc * o[fr] / np.sqrt(D[fr])
     return z

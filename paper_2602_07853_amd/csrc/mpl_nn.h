@@ -62,3 +62,9 @@ mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const 
 NNSampleStore& nn_samples(mpl_ctx* c);
 // stage the network's output gradient from a node vector (block layout)
 mpl_status nn_stage_output_grad(mpl_ctx* c, const double* g);
+// stage a caller-given network output (box layout [X][Y][Z][16], FP32,
+// rounded to BF16) in place of the forward's output
+mpl_status nn_stage_output_f32(mpl_ctx* c, const float* o_box);
+// one Adam step with the parameter gradient in nn.grad, then the refresh
+// of the BF16 weight copies
+mpl_status nn_adam_update(mpl_ctx* c, NNState& nn, float lr);

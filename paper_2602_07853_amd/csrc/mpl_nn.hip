@@ -1235,6 +1235,13 @@ mpl_status nn_stage_output_grad(mpl_ctx* c, const double* g) {
   return MPL_OK;
 }
 
+mpl_status nn_stage_output_f32(mpl_ctx* c, const float* o_box) {
+  NNState& nn = *nn_state(c);
+  const int64_t n = (int64_t)nn.box[0] * nn.box[1] * nn.box[2] * 16;
+  MPL_LAUNCH(c, k_f32_to_bf16, (int)((n + 255) / 256), 256, o_box, (uint16_t*)nn.act.p + nn.t_out, n);
+  return MPL_OK;
+}
+
 mpl_status nn_record_sample(mpl_ctx* c, const double* r, const double* x, const double* xstar,
                             const double* Dinv, const double* s2) {
   NNState& nn = *nn_state(c);
@@ -1265,6 +1272,11 @@ mpl_status nn_backward_update(mpl_ctx* c, NNState& nn, float lr) {
   const int64_t np = nn_param_count();
   MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
   MPL_TRY(nn_backward(c, nn));
+  return nn_adam_update(c, nn, lr);
+}
+
+mpl_status nn_adam_update(mpl_ctx* c, NNState& nn, float lr) {
+  const int64_t np = nn_param_count();
   nn.adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);
@@ -1334,6 +1346,35 @@ mpl_status mpl_precond_online_stats(mpl_ctx* c, int64_t* steps_done, double* mea
   c->online_loss_sum = 0.0;
   c->online_ref_sum = 0.0;
   c->online_loss_n = 0;
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_adam_step(mpl_ctx* c, const float* grad, float lr) {
+  if (!c || !grad) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "set network weights first");
+  NNState& nn = *c->nn;
+  MPL_HIP(c, hipMemcpyAsync(nn.grad.p, grad, 4 * nn_param_count(), hipMemcpyDeviceToDevice, c->stream));
+  MPL_TRY(nn_adam_update(c, nn, lr));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_get_sample(mpl_ctx* c, int32_t i, float* feat, float* target, float* mask) {
+  if (!c) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->store) return mpl_fail(c, MPL_ERR_STATE, "no training samples");
+  NNSampleStore& st = *c->nn->store;
+  if (i < 0 || i >= st.count) return mpl_fail(c, MPL_ERR_INVALID_ARG, "sample index out of range");
+  const int64_t nv = st.voxels;
+  if (feat)
+    MPL_LAUNCH(c, k_bf16_to_f32, (int)((nv * 16 + 255) / 256), 256,
+               P<uint16_t>(st.feat) + (int64_t)i * nv * 16, feat, nv * 16);
+  if (target)
+    MPL_HIP(c, hipMemcpyAsync(target, P<float>(st.target) + (int64_t)i * nv * 3, 4 * nv * 3,
+                              hipMemcpyDeviceToDevice, c->stream));
+  if (mask)
+    MPL_HIP(c, hipMemcpyAsync(mask, P<float>(st.mask) + (int64_t)i * nv, 4 * nv, hipMemcpyDeviceToDevice,
+                              c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
   return MPL_OK;
 }
 

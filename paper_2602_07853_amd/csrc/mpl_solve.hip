@@ -2319,6 +2319,63 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
   return MPL_OK;
 }
 
+// Buffers of the energy-norm loss kernels (online training and
+// mpl_precond_energy_loss).
+template <class T>
+static mpl_status online_buffers(mpl_ctx* c, int n_losses) {
+  NNState& nn = *c->nn;
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(nn_prepare_box(c, true));
+  MPL_TRY(ensure_partials(c));
+  MPL_TRY(mpl_ensure(c, c->ozt, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->ohz, sizeof(T) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->ogr, sizeof(double) * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->opieces, sizeof(T) * 6 * ncell));
+  MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * (n_losses + 64) + 2 * sizeof(double) * (c->n_nblk + 64)));
+  return nn_set_dref(c, P<double>(c->D));
+}
+
+// r^T Dinv r of the residual r (block layout) into red[0].
+static mpl_status online_rdr(mpl_ctx* c, const double* r) {
+  const int nwg = (c->n_nblk + 3) / 4;
+  double* p4 = partial_slot(c, 4);
+  MPL_LAUNCH(c, k_online_rdr, nwg, 256, r, P<double>(c->D), P<uint8_t>(c->flags), (int64_t)c->nnode_alloc(),
+             c->n_nblk, p4);
+  MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p4, 0, p4, 0, c->dscal(), 0);
+  return MPL_OK;
+}
+
+// Energy-norm loss of z = preconditioner(r) (the network output staged in
+// the activation arena or, with jacobi = 1, z = Dinv r): z into ozt, H z into
+// ohz, the loss into *loss (device) and dL/do into ogr.  Needs red[0] =
+// r^T Dinv r (online_rdr); uses red[1..3] and partial slots 4-5.
+template <class T>
+static mpl_status online_loss(mpl_ctx* c, const double* r, int jacobi, double* loss) {
+  NNState& nn = *c->nn;
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  SolverScalars* s = c->dscal();
+  const int nwg = (c->n_nblk + 3) / 4;
+  double* p4 = partial_slot(c, 4);
+  double* p5 = partial_slot(c, 5);
+  const double* D = P<double>(c->D);
+  T* z = P<T>(c->ozt);
+  T* hz = P<T>(c->ohz);
+  const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
+                   nn_inv_free_dofs(c)};
+  MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
+             c->n_nblk, net, &s->red[0], z, jacobi);
+  MPL_TRY(hv_pieces<T>(c, z, false, P<T>(c->opieces)));
+  const T* Hown = P<T>(c->opieces);
+  MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
+             P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
+  MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,
+             c->n_nblk, p4, p5);
+  MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p5, nwg, p5, 0, s, 1);
+  MPL_LAUNCH(c, k_online_grad<T>, nwg, 256, r, (const T*)hz, D, P<uint8_t>(c->flags), nnode, c->n_nblk,
+             nn_inv_free_dofs(c), (const double*)&s->red[0], P<double>(c->ogr), loss);
+  return MPL_OK;
+}
+
 // Online training: `steps` Adam steps of the network on the energy-norm
 // loss of the current residual c->r under the current tangent.  Runs
 // between PCG chunks; touches neither the iteration's vectors nor its
@@ -2326,56 +2383,24 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
 template <class T>
 static mpl_status online_train(mpl_ctx* c) {
   NNState& nn = *c->nn;
-  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
-  MPL_TRY(nn_prepare_box(c, true));
-  MPL_TRY(mpl_ensure(c, c->ozt, sizeof(T) * 3 * nnode));
-  MPL_TRY(mpl_ensure(c, c->ohz, sizeof(T) * 3 * nnode));
-  MPL_TRY(mpl_ensure(c, c->ogr, sizeof(double) * 3 * nnode));
-  MPL_TRY(mpl_ensure(c, c->opieces, sizeof(T) * 6 * ncell));
-  MPL_TRY(mpl_ensure(c, nn.tmp, sizeof(double) * (c->online_steps + 64) + 2 * sizeof(double) * (c->n_nblk + 64)));
-  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  MPL_TRY(online_buffers<T>(c, c->online_steps));
   const int32_t* saved_skip = nn.skip;
   const int saved_tk = c->opts.time_kernels;
   nn.skip = nullptr;
   c->opts.time_kernels = 0;
-  SolverScalars* s = c->dscal();
-  const int nwg = (c->n_nblk + 3) / 4;
-  double* p4 = partial_slot(c, 4);
-  double* p5 = partial_slot(c, 5);
   const double* r = P<double>(c->r);
   const double* D = P<double>(c->D);
-  T* z = P<T>(c->ozt);
-  T* hz = P<T>(c->ohz);
   // losses go after the dref partials in nn.tmp
   double* losses = P<double>(nn.tmp) + 2 * (c->n_nblk + 64);
-  const NetOut net{(const uint16_t*)nn.act.p + nn.t_out, nn.box[0], nn.box[1], nn.box[2],
-                   nn_inv_free_dofs(c)};
   mpl_status st = MPL_OK;
-  // loss of z (network or, with jacobi = 1, z = Dinv r) into *loss, output
-  // gradient into ogr
-  auto loss_of = [&](int jacobi, double* loss) -> mpl_status {
-    MPL_LAUNCH(c, k_online_z<T>, nwg, 256, r, D, P<uint8_t>(c->flags), P<int4>(c->ncoord), nnode,
-               c->n_nblk, net, &s->red[0], z, jacobi);
-    MPL_TRY(hv_pieces<T>(c, z, false, P<T>(c->opieces)));
-    const T* Hown = P<T>(c->opieces);
-    MPL_LAUNCH(c, k_hv_combine<T>, c->n_nblk, 64, (const T*)z, P<double>(c->mi), P<uint8_t>(c->flags),
-               P<int>(c->n_nbr_cell), Hown, Hown + 3 * ncell, ncell, nnode, hz);
-    MPL_LAUNCH(c, k_online_dots<T>, nwg, 256, r, (const T*)z, (const T*)hz, P<uint8_t>(c->flags), nnode,
-               c->n_nblk, p4, p5);
-    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p5, nwg, p5, 0, s, 1);
-    MPL_LAUNCH(c, k_online_grad<T>, nwg, 256, r, (const T*)hz, D, P<uint8_t>(c->flags), nnode, c->n_nblk,
-               nn_inv_free_dofs(c), (const double*)&s->red[0], P<double>(c->ogr), loss);
-    return MPL_OK;
-  };
   auto run = [&]() -> mpl_status {
-    MPL_LAUNCH(c, k_online_rdr, nwg, 256, r, D, P<uint8_t>(c->flags), nnode, c->n_nblk, p4);
-    MPL_LAUNCH(c, k_reduce<RED_PLAIN>, 1, 1024, p4, nwg, p4, 0, p4, 0, s, 0);
+    MPL_TRY(online_rdr(c, r));
     // reference: the same loss for the Jacobi preconditioner
-    MPL_TRY(loss_of(1, losses + c->online_steps));
+    MPL_TRY(online_loss<T>(c, r, 1, losses + c->online_steps));
     for (int k = 0; k < c->online_steps; ++k) {
-      MPL_TRY(nn_stage_features(c, r, D, &s->red[0]));
+      MPL_TRY(nn_stage_features(c, r, D, &c->dscal()->red[0]));
       MPL_TRY(nn_forward(c, nn));
-      MPL_TRY(loss_of(0, losses + k));
+      MPL_TRY(online_loss<T>(c, r, 0, losses + k));
       MPL_TRY(nn_stage_output_grad(c, P<double>(c->ogr)));
       MPL_TRY(nn_backward_update(c, nn, c->online_lr));
     }
@@ -2396,6 +2421,41 @@ static mpl_status online_train(mpl_ctx* c) {
     c->online_ref_sum += ref;
     c->online_loss_n += 1;
   }
+  return MPL_OK;
+}
+
+// Energy-norm loss of the learned preconditioner on a given residual r
+// (block layout in c->r): the network output o is the caller's box tensor
+// (FP32, rounded to BF16 like the network's own output) or, when o_box is
+// NULL, the network's forward on the features of r.  Loss and Jacobi loss
+// to the host, dL/do (block layout) in c->ogr.
+template <class T>
+static mpl_status energy_loss_on(mpl_ctx* c, const float* o_box, double* loss, double* loss_jacobi) {
+  NNState& nn = *c->nn;
+  MPL_TRY(online_buffers<T>(c, 2));
+  const int32_t* saved_skip = nn.skip;
+  nn.skip = nullptr;
+  const double* r = P<double>(c->r);
+  double* losses = P<double>(nn.tmp) + 2 * (c->n_nblk + 64);
+  auto run = [&]() -> mpl_status {
+    MPL_TRY(online_rdr(c, r));
+    MPL_TRY(online_loss<T>(c, r, 1, losses + 1));
+    if (o_box) {
+      MPL_TRY(nn_stage_output_f32(c, o_box));
+    } else {
+      MPL_TRY(nn_stage_features(c, r, P<double>(c->D), &c->dscal()->red[0]));
+      MPL_TRY(nn_forward(c, nn));
+    }
+    return online_loss<T>(c, r, 0, losses);
+  };
+  mpl_status st = run();
+  nn.skip = saved_skip;
+  MPL_TRY(st);
+  double h[2] = {0.0, 0.0};
+  MPL_HIP(c, hipMemcpyAsync(h, losses, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = h[0];
+  if (loss_jacobi) *loss_jacobi = h[1];
   return MPL_OK;
 }
 
@@ -2964,6 +3024,44 @@ mpl_status mpl_precond_apply(mpl_ctx* c, const double* r, double* z) {
   MPL_TRY(mpl_dense_to_block_nodes(c, r, c->dir.p, 3, 0));
   MPL_TRY(mpl_stage_precond_apply(c, P<double>(c->dir), P<double>(c->vt)));
   MPL_TRY(mpl_block_to_dense_nodes(c, c->vt.p, z, 3, 0));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_energy_loss(mpl_ctx* c, const double* r, const float* o_box, double* loss,
+                                   double* loss_jacobi, double* grad_o) {
+  if (!c || !r) return MPL_ERR_INVALID_ARG;
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "energy loss needs a tangent");
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  MPL_TRY(mpl_dense_to_block_nodes(c, r, c->r.p, 3, 0));
+  if (c->tangent_precision == MPL_F32) MPL_TRY(energy_loss_on<float>(c, o_box, loss, loss_jacobi));
+  else MPL_TRY(energy_loss_on<double>(c, o_box, loss, loss_jacobi));
+  if (grad_o) MPL_TRY(mpl_block_to_dense_nodes(c, c->ogr.p, grad_o, 3, 0));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  return MPL_OK;
+}
+
+mpl_status mpl_precond_record_pair(mpl_ctx* c, const double* r, const double* x, const double* xstar) {
+  if (!c || !r || !x || !xstar) return MPL_ERR_INVALID_ARG;
+  if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "a training pair needs a tangent");
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  MPL_TRY(ensure_partials(c));
+  MPL_TRY(nn_prepare_box(c, true));
+  NNSampleStore& store = nn_samples(c);
+  if (store.count >= store.capacity) return mpl_fail(c, MPL_ERR_OOM, "training sample store is full (mpl_precond_reserve)");
+  MPL_TRY(mpl_ensure(c, c->r, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->x, 8 * 3 * nnode));
+  MPL_TRY(mpl_ensure(c, c->xstar, 8 * 3 * nnode));
+  MPL_TRY(mpl_dense_to_block_nodes(c, r, c->r.p, 3, 0));
+  MPL_TRY(mpl_dense_to_block_nodes(c, x, c->x.p, 3, 0));
+  MPL_TRY(mpl_dense_to_block_nodes(c, xstar, c->xstar.p, 3, 0));
+  MPL_TRY(nn_set_dref(c, P<double>(c->D)));
+  MPL_TRY(online_rdr(c, P<double>(c->r)));
+  MPL_TRY(nn_record_sample(c, P<double>(c->r), P<double>(c->x), P<double>(c->xstar), P<double>(c->D),
+                           &c->dscal()->red[0]));
   MPL_HIP(c, hipStreamSynchronize(c->stream));
   return MPL_OK;
 }

@@ -408,6 +408,47 @@ class Context:
                     "mpl_precond_train")
         return losses[:n_steps]
 
+    def box_dims(self):
+        """Dims of the network box over the grid's nodes (each axis padded to a multiple of 8)."""
+        return tuple(((d + 1 + 7) // 8) * 8 for d in self.dims)
+
+    def precond_energy_loss(self, r: torch.Tensor, o_box: torch.Tensor = None):
+        """(L(z), Jacobi loss, dL/do) of the energy-norm loss on residual r, with the
+        network output o_box [X, Y, Z, 16] given or (None) computed from r."""
+        loss, ref = C.c_double(), C.c_double()
+        g = self._node_vec()
+        op = None
+        if o_box is not None:
+            if tuple(o_box.shape) != self.box_dims() + (16,):
+                raise ValueError(f"o_box has shape {tuple(o_box.shape)}, want {self.box_dims() + (16,)}")
+            op = C.c_void_p(_dptr(o_box, torch.float32))
+        self._check(self._lib.mpl_precond_energy_loss(
+            self._ctx, C.c_void_p(_dptr(self._check_node_vec(r, "r"), torch.float64)), op,
+            C.byref(loss), C.byref(ref), C.c_void_p(g.data_ptr())), "mpl_precond_energy_loss")
+        return loss.value, ref.value, g
+
+    def precond_adam_step(self, grad: torch.Tensor, lr: float):
+        if tuple(grad.shape) != (self.precond_param_count(),):
+            raise ValueError("grad must hold one value per network parameter")
+        self._check(self._lib.mpl_precond_adam_step(self._ctx, C.c_void_p(_dptr(grad, torch.float32)),
+                                                    C.c_float(lr)), "mpl_precond_adam_step")
+
+    def precond_record_pair(self, r: torch.Tensor, x: torch.Tensor, xstar: torch.Tensor):
+        ptrs = [C.c_void_p(_dptr(self._check_node_vec(t, n), torch.float64))
+                for t, n in ((r, "r"), (x, "x"), (xstar, "xstar"))]
+        self._check(self._lib.mpl_precond_record_pair(self._ctx, *ptrs), "mpl_precond_record_pair")
+
+    def precond_get_sample(self, i: int):
+        """(features [X, Y, Z, 16], target [X, Y, Z, 3], mask [X, Y, Z]) of stored pair i."""
+        X = self.box_dims()
+        f = torch.zeros(X + (16,), dtype=torch.float32, device="cuda")
+        t = torch.zeros(X + (3,), dtype=torch.float32, device="cuda")
+        m = torch.zeros(X, dtype=torch.float32, device="cuda")
+        self._check(self._lib.mpl_precond_get_sample(self._ctx, C.c_int32(i), C.c_void_p(f.data_ptr()),
+                                                     C.c_void_p(t.data_ptr()), C.c_void_p(m.data_ptr())),
+                    "mpl_precond_get_sample")
+        return f, t, m
+
     def precond_online(self, every: int, steps: int = 1, lr: float = 1e-3):
         self._check(self._lib.mpl_precond_online(self._ctx, C.c_int32(every), C.c_int32(steps),
                                                  C.c_float(lr)), "mpl_precond_online")

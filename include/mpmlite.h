@@ -247,6 +247,24 @@ mpl_status mpl_build_tangent(mpl_ctx* ctx, const double* v, int32_t precision);
  * free DOFs, with the tangent of the last mpl_build_tangent.  u, Hu: dense
  * device arrays [(dims+1)^3][3] of float (MPL_F32) or double (MPL_F64). */
 mpl_status mpl_hv(mpl_ctx* ctx, const void* u, void* Hu, int32_t precision);
+/* Allocation-free variant of mpl_hv, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and result as mpl_hv
+ * (the same kernels).  Its block-layout copies of u and Hu and the
+ * product's per-cell pieces are carved from one fixed device array of
+ * MPL_HV_NOALLOC_MAX_BYTES per GPU, held until the process ends, instead of
+ * the context's buffers: 2 x 3 x (active node blocks x 64) + 6 x (active
+ * cell blocks x 64) values of the precision (each part rounded up to 256
+ * bytes) must fit, else MPL_ERR_INVALID_ARG (the 128^3 one-million-cell
+ * workload fits in MPL_F32, not in MPL_F64).  Every call on one GPU shares
+ * that array and leaves its contents there: calls that overlap on one GPU
+ * (other streams, threads or contexts) race.  Enqueues kernels only on the
+ * context's stream (no allocation, no memset, no event, no
+ * synchronisation); the context's device must be current.  The tangent
+ * must have been built (mpl_build_tangent or a solve) beforehand, which is
+ * where the context allocates. */
+#define MPL_HV_NOALLOC_MAX_BYTES (64ll << 20)
+mpl_status mpl_hv_noalloc(mpl_ctx* ctx, const void* u, void* Hu, int32_t precision);
 /* Jacobi-PCG on H x = b (b, x dense device FP64), tolerance and iteration
  * cap from the options; iters (host, may be NULL) gets the iteration count
  * and rel_resid (host, may be NULL) the recurrence residual |r|/|b|. */

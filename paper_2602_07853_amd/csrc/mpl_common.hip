@@ -156,6 +156,10 @@ __global__ void k_block_to_dense(const T* __restrict__ blk, T* __restrict__ dens
   for (int a = 0; a < comps; ++a)
     dense[di * comps + a] = blk[(int64_t)a * nn_block + (int64_t)b * MPL_BC + l];
 }
+__global__ void k_zero_words(uint32_t* __restrict__ a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0u;
+}
 }  // namespace
 
 mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, int comps,
@@ -174,8 +178,10 @@ mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, 
 mpl_status mpl_block_to_dense_nodes(mpl_ctx* c, const void* block, void* dense, int comps,
                                     int is_f32) {
   int nx1 = c->dims[0] + 1, ny1 = c->dims[1] + 1, nz1 = c->dims[2] + 1;
-  size_t bytes = (size_t)nx1 * ny1 * nz1 * comps * (is_f32 ? 4 : 8);
-  MPL_HIP(c, hipMemsetAsync(dense, 0, bytes, c->stream));
+  // cleared by a fill kernel rather than a memset, so that the call can be
+  // captured into a HIP graph
+  const int64_t words = (int64_t)nx1 * ny1 * nz1 * comps * (is_f32 ? 1 : 2);
+  MPL_LAUNCH(c, k_zero_words, (int)((words + 255) / 256), 256, (uint32_t*)dense, words);
   if (is_f32)
     MPL_LAUNCH(c, k_block_to_dense<float>, c->n_nblk, MPL_BC, (const float*)block, (float*)dense,
                P<int4>(c->ncoord), comps, c->n_nblk, nx1, ny1, nz1, (int64_t)c->nnode_alloc());
@@ -273,6 +279,11 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->dx = grid->dx;
   c->inv_dx = 1.0 / grid->dx;
   c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return MPL_ERR_HIP;
+  }
+  mpl_noalloc_attach(c);
   const char* gr = std::getenv("MPL_GRAPHS");
   c->graphs_enabled = gr && gr[0] == '1';
   const char* dt = std::getenv("MPL_DENSE_TANGENT");

@@ -74,6 +74,7 @@ struct SolverScalars {
 };
 
 struct mpl_ctx {
+  int device = 0;  // HIP device current at mpl_create
   // grid
   int dims[3];
   int cbd[3];   // cell-block grid dims (dims/4)
@@ -235,3 +236,13 @@ mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, 
                                     int is_f32);
 mpl_status mpl_block_to_dense_nodes(mpl_ctx* c, const void* block, void* dense, int comps,
                                     int is_f32);
+
+// Allocation-free entry point (mpl_noalloc.hip): fetch the device address of
+// the fixed scratch array for the context's device once per device.
+void mpl_noalloc_attach(mpl_ctx* c);
+// Hessian-vector product on block-layout u into block-layout Hu, with the
+// product's per-cell pieces in a caller-given buffer (6 x cells x values);
+// launches kernels only.
+mpl_status mpl_stage_hv_into(mpl_ctx* c, const void* u, void* Hu, void* pieces, int precision);
+// zero the non-free nodes of a block-layout node vector (3 components)
+mpl_status mpl_mask_free_nodes(mpl_ctx* c, void* u, int is_f32);

@@ -2007,6 +2007,35 @@ mpl_status mpl_stage_hv(mpl_ctx* c, const void* u, void* Hu, int precision, bool
   return MPL_OK;
 }
 
+mpl_status mpl_mask_free_nodes(mpl_ctx* c, void* u, int is_f32) {
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  if (is_f32)
+    MPL_LAUNCH(c, k_mask_free<float>, (int)((nnode + 255) / 256), 256, (float*)u, P<uint8_t>(c->flags), nnode);
+  else
+    MPL_LAUNCH(c, k_mask_free<double>, (int)((nnode + 255) / 256), 256, (double*)u, P<uint8_t>(c->flags), nnode);
+  return MPL_OK;
+}
+
+mpl_status mpl_stage_hv_into(mpl_ctx* c, const void* u, void* Hu, void* pieces, int precision) {
+  if (!c->tangent_built || c->tangent_precision != precision)
+    return mpl_fail(c, MPL_ERR_STATE, "Hv needs a tangent built in the same precision");
+  const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
+  if (precision == MPL_F32) {
+    float* Hown = (float*)pieces;
+    MPL_TRY(hv_pieces<float>(c, (const float*)u, false, Hown));
+    MPL_LAUNCH(c, k_hv_combine<float>, c->n_nblk, 64, (const float*)u, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), (const float*)Hown,
+               (const float*)Hown + 3 * ncell, ncell, nnode, (float*)Hu);
+  } else {
+    double* Hown = (double*)pieces;
+    MPL_TRY(hv_pieces<double>(c, (const double*)u, false, Hown));
+    MPL_LAUNCH(c, k_hv_combine<double>, c->n_nblk, 64, (const double*)u, P<double>(c->mi),
+               P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), (const double*)Hown,
+               (const double*)Hown + 3 * ncell, ncell, nnode, (double*)Hu);
+  }
+  return MPL_OK;
+}
+
 // Runs PCG iterations in chunks of `check` until the device flag reports
 // convergence or breakdown or max_pcg iterations have been launched.  A
 // chunk is captured into a HIP graph once and replayed while the buffers and

@@ -287,6 +287,16 @@ class Context:
                                      int(precision)), "mpl_hv")
         return out
 
+    def hv_noalloc(self, u: torch.Tensor, out: torch.Tensor, precision=F32):
+        """Allocation-free Hu (mpl_hv_noalloc) into the caller's dense tensor ``out``;
+        enqueued on the context's stream, not synchronised."""
+        dt = torch.float32 if precision == F32 else torch.float64
+        self._check_node_vec(out, "out")
+        self._check(self._lib.mpl_hv_noalloc(self._ctx, C.c_void_p(_dptr(self._check_node_vec(u, "u"), dt)),
+                                             C.c_void_p(_dptr(out, dt)), int(precision)),
+                    "mpl_hv_noalloc")
+        return out
+
     def pcg(self, b: torch.Tensor):
         x = self._node_vec()
         it = C.c_int32()

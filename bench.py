@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 5])
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-check", action="store_true",
+                    help="skip the final-error check of one step against the FP64 GPU variant")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
     ap.add_argument("--ppc-axis", type=int, default=None,
                     help="particles per cell along each axis (default: the config's, 2 = 8 PPC)")
@@ -82,46 +84,133 @@ def workload_name(sc):
             f"{sc.n_particles} particles, dt={sc.dt}, Newton + Jacobi PCG to rel. resid 1e-6")
 
 
-def cpu_baseline(sc, counts, reps_hv=60, reps=5):
-    """Time the FP64 oracle's stages on the full workload (unload, reconstruct
-    and load once; energy + gradient and tangent over ``reps`` calls, the Hv
-    over ``reps_hv`` calls, means) and combine them with this run's per-step
-    Newton / PCG / line-search counts.  About 10 s of CPU work."""
+_ORACLE_STEP = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_2602_07853_amd import scenes
+sc = scenes.CONFIGS[int(sys.argv[2])]()
+g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
+t0 = time.perf_counter()
+po, st, v, rc = O.step(g, mats, sc.dt, sc.gravity, bcs, 0.0, O.SolverOpts(1e-6, 1e-6), sc.particles)
+print(json.dumps({"s": time.perf_counter() - t0, "rc": rc, "newton": st["newton_iters"],
+                  "pcg": st["pcg_iters_total"], "particles": sc.n_particles}))
+"""
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def oracle_full_step(cfg, threads):
+    """One whole oracle step (Alg. 1, Newton + Jacobi PCG to 1e-6, FP64) of
+    config ``cfg`` from its initial state, in a child process with
+    ``threads`` OpenMP threads; wall seconds and the oracle's own counts."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", _ORACLE_STEP, ROOT, str(cfg)], env=env,
+                         capture_output=True, text=True, timeout=900, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(sc, cold_counts):
+    """The FP64 oracle on the host cores.
+
+    Measured: (1) one whole oracle step of the 64^3 fixed-corotated workload
+    (885k particles, Newton + Jacobi PCG to 1e-6) on one thread and on all
+    threads; (2) a bounded sample of the 128^3 workload at its initial
+    state: the oracle's unload, reconstruction and load, and its own
+    Newton-PCG solver stopped after one Newton iteration with its CG capped
+    at 10 and at 40 iterations, which gives the cost of one CG iteration
+    (product and vector operations) and of the rest of a Newton iteration
+    (energy, gradient, tangent, line search).  The 128^3 steps/s (``value``)
+    extrapolates the sample to a whole step with the Newton and CG counts of
+    this run's first step, which starts CG from zero like the oracle."""
     from oracle import oracle as O
+    model, ncpu = cpu_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", ncpu))
+    full = {"threads_1": oracle_full_step(2, 1), f"threads_{threads}": oracle_full_step(2, threads)}
     g, mats, bcs = O.grid_of(sc), O.materials_of(sc), O.bcs_of(sc)
     t = {}
 
-    def timed(name, n, fn):
+    def timed(name, fn):
         t0 = time.perf_counter()
-        for _ in range(n):
-            out = fn()
-        t[name] = (time.perf_counter() - t0) / n
+        out = fn()
+        t[name] = time.perf_counter() - t0
         return out
 
-    u = timed("unload", 1, lambda: O.unload(g, sc.particles, mats))
+    u = timed("unload", lambda: O.unload(g, sc.particles, mats))
     fixed, vfix = O.node_bcs(g, u["mi"], bcs, 0.0)
     act = u["mi"] > 0
-    vhat = np.where(fixed[:, None] > 0, vfix, np.where(act[:, None], u["vi"] + sc.dt * np.asarray(sc.gravity), 0))
-    S, _ = timed("reconstruct", 1, lambda: O.reconstruct(g, mats, u["Vck"], u["tauck"]))
-    timed("energy_grad", reps, lambda: O.energy_grad(g, mats, sc.dt, u["mi"], vhat, fixed, u["Vck"], S, vhat))
-    A, _ = timed("tangent", reps, lambda: O.tangent(g, mats, sc.dt, u["Vck"], S, vhat, project=True))
-    timed("hv", reps_hv, lambda: O.hv(g, u["mc"], u["mi"], fixed, A, vhat))
-    del A
-    timed("load", 1, lambda: O.load(g, sc.dt, u["mc"], vhat, sc.particles, mats))
-    newton, pcg, ls = counts
-    step_s = (t["unload"] + t["reconstruct"] + t["load"] + (newton + 1) * t["energy_grad"] +
-              ls * t["energy_grad"] + newton * t["tangent"] + pcg * t["hv"] * 1.2)
-    cpu_s = (t["unload"] + t["reconstruct"] + t["load"] + reps * (t["energy_grad"] + t["tangent"]) +
-             reps_hv * t["hv"])
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    sample = (f"FP64 oracle stages on the full workload, {cpu_s:.1f}s of CPU work: unload "
-              f"{t['unload']:.1f}s, reconstruct {t['reconstruct']:.1f}s and load {t['load']:.1f}s once; "
-              f"energy+grad {t['energy_grad']:.3f}s and tangent {t['tangent']:.3f}s (mean of {reps}); "
-              f"Hv {t['hv']:.4f}s (mean of {reps_hv}); combined with this run's per-step counts "
-              f"(newton {newton:.2f}, pcg {pcg:.1f} with 20% for vector ops, line-search trials "
-              f"{ls:.2f}); OpenMP over cells")
-    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": sample}
+    vhat = np.where(fixed[:, None] > 0, vfix,
+                    np.where(act[:, None], u["vi"] + sc.dt * np.asarray(sc.gravity), 0))
+    S, _ = timed("reconstruct", lambda: O.reconstruct(g, mats, u["Vck"], u["tauck"]))
+    for K in (10, 40):
+        timed(f"solve_{K}", lambda: O.solve(g, mats, sc.dt, u["mc"], u["mi"], vhat, fixed, u["Vck"], S,
+                                            O.SolverOpts(1e-6, 1e-6, max_newton=1, max_pcg=K)))
+    timed("load", lambda: O.load(g, sc.dt, u["mc"], vhat, sc.particles, mats))
+    per_cg = (t["solve_40"] - t["solve_10"]) / 30.0
+    per_newton = max(t["solve_10"] - 10 * per_cg, 0.0)
+    newton, pcg = cold_counts
+    step_s = t["unload"] + t["reconstruct"] + t["load"] + newton * per_newton + pcg * per_cg
+    cpu_s = sum(t.values()) + sum(v["s"] for v in full.values())
+    sample = (f"{cpu_s:.1f}s of CPU work. Measured: whole oracle steps of the 64^3 workload "
+              f"(1 thread {full['threads_1']['s']:.1f}s, {threads} threads "
+              f"{full[f'threads_{threads}']['s']:.1f}s); at 128^3 the oracle's unload "
+              f"{t['unload']:.2f}s, reconstruction {t['reconstruct']:.2f}s, load {t['load']:.2f}s, and "
+              f"its own solver for one Newton iteration: {per_cg * 1e3:.1f} ms per CG iteration "
+              f"(product + vector ops), {per_newton:.2f}s for the rest of the iteration. The 128^3 "
+              f"figure extrapolates these to a whole step with the counts of this run's first step "
+              f"(CG from zero, as in the oracle): {newton} Newton, {pcg} CG iterations")
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "cpu_model": model, "nproc": ncpu,
+            "method": "128^3 value extrapolated from a measured sample; 64^3 steps measured whole",
+            "oracle_step_s_128": round(step_s, 2),
+            "oracle_full_step_64": full}
+
+
+def precision_check(sc, parts, ctx, t):
+    """Final error of one production step (FP32 products, tolerances 1e-6)
+    from the current state, against the FP64 GPU variant of the same step
+    converged to 1e-10 (the variant the parity tests hold to the oracle
+    within 1e-10); the FP64 variant at the production tolerances is given
+    too, to separate the tolerance from the precision."""
+    import torch
+    from paper_2602_07853_amd import mpmlite
+    src = {k: v.clone() for k, v in parts.items()}
+    runs = {}
+    tight = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                            opts=dict(hv_precision=mpmlite.F64, newton_rtol=1e-10, pcg_rtol=1e-10))
+    same = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                           opts=dict(hv_precision=mpmlite.F64, newton_rtol=1e-6, pcg_rtol=1e-6))
+    for name, c in (("f32", ctx), ("f64_tight", tight), ("f64", same)):
+        out = {k: v.clone() for k, v in src.items()}
+        c.step(src, out, sc.dt, sc.gravity, sc.bcs, t)
+        runs[name] = out
+    torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float((a - b).norm() / b.norm().clamp_min(1e-300))
+
+    ref = runs["f64_tight"]
+    res = {}
+    for name in ("f32", "f64"):
+        r = runs[name]
+        res[name] = {"x": rel(r["x"], ref["x"]), "dx": rel(r["x"] - src["x"], ref["x"] - src["x"]),
+                     "v": rel(r["v"], ref["v"]), "F": rel(r["F"], ref["F"]), "G": rel(r["G"], ref["G"])}
+        res[name] = {k: float(f"{v:.3e}") for k, v in res[name].items()}
+    del tight, same
+    return {"reference": "FP64 GPU variant, Newton and CG to 1e-10 (held to the oracle within 1e-10 by the parity tests)",
+            "step": "one step from the state after the timed steps", "production_f32": res["f32"],
+            "f64_same_tolerances": res["f64"]}
 
 
 def main():
@@ -155,8 +244,13 @@ def main():
         return st
 
     parts0 = {k: v.clone() for k, v in parts.items()} if args.learned_steps > 0 else None
+    traj = {}   # trajectory step -> (CG iterations, host-timed ms of the step's stages)
+    first = None
     for w in range(args.warmup):
         st = one_step()
+        traj[w] = (st["pcg_iters"], st["ms_unload"] + st["ms_newton"] + st["ms_load"])
+        if first is None:
+            first = (st["newton_iters"], st["pcg_iters"])
         print(f"[bench] warmup {w} {json.dumps(st)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     hv_ms, hv_calls, newton, pcg, ls = 0.0, 0, 0, 0, 0
@@ -164,11 +258,12 @@ def main():
     cells = nodes = 0
     hv_bytes = 0.0
     tan_entries = 0
-    traj = {}   # trajectory step -> (CG iterations, host-timed ms of the step's stages)
     t0 = time.perf_counter()
     for k in range(args.steps):
         st = one_step()
         traj[args.warmup + k] = (st["pcg_iters"], st["ms_unload"] + st["ms_newton"] + st["ms_load"])
+        if first is None:
+            first = (st["newton_iters"], st["pcg_iters"])
         hv_ms += st["hv_ms_total"]
         hv_calls += st["hv_calls"]
         up_ms += st["upd_ms_total"]
@@ -210,12 +305,16 @@ def main():
               "frac": round(up_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": up_bytes,
               "avg_ms": round(up_avg_ms, 5), "launches": up_calls}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
+    final_error = None
+    if not args.no_precision_check:
+        final_error = precision_check(sc, parts, ctx, step_idx * sc.dt)
+        print(f"[bench] final error {json.dumps(final_error)}", file=sys.stderr, flush=True)
     block_jacobi = None
     if args.bj_steps > 0:
         block_jacobi = block_jacobi_leg(ctx, sc, args, steps_per_s, counts, traj)
     learned = None
     if args.learned_steps > 0:
-        learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts)
+        learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts, traj)
     explicit = None
     if args.explicit_steps > 0:
         explicit = explicit_leg(args.explicit_steps)
@@ -224,7 +323,7 @@ def main():
         vbd = vbd_leg(args.vbd_steps, args.vbd_sweeps)
     base = None
     if not args.no_cpu_baseline and args.config in (1, 2, 3):
-        base = cpu_baseline(sc, counts)
+        base = cpu_baseline(sc, first)
     line = {
         "metric": "implicit steps/s @1M cells to resid 1e-6, learned vs plain PCG; Hv HBM GB/s",
         "value": round(steps_per_s, 4),
@@ -244,6 +343,7 @@ def main():
                    "hv_precision": args.precision, "plasticity": args.plasticity},
         "roofline": roof,
         "update_kernel": update,
+        "final_error": final_error,
         "cpu_baseline": base,
         "block_jacobi": block_jacobi,
         "learned": learned,
@@ -290,23 +390,28 @@ def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untim
            "pcg_per_step": round(pcg / n, 2), "vs_jacobi": round(sps / plain_steps_per_s, 4),
            "jacobi_pcg_per_step": round(plain_counts[1], 2), "same_steps": None}
     window = range(untimed, untimed + n)
-    if all(i in traj for i in window):
-        jp = sum(traj[i][0] for i in window) / n
-        jm = sum(traj[i][1] for i in window) / n
-        bm = host_ms / n
-        out["same_steps"] = {"trajectory_steps": [window.start, window.stop - 1],
-                             "jacobi_pcg_per_step": round(jp, 2), "block_jacobi_pcg_per_step": round(pcg / n, 2),
-                             "jacobi_host_ms": round(jm, 2), "block_jacobi_host_ms": round(bm, 2),
-                             "speed_vs_jacobi": round(jm / bm, 4)}
+    if not all(i in traj for i in window):
+        raise RuntimeError(f"block-Jacobi window {window.start}..{window.stop - 1} lies outside the "
+                           f"main run's {len(traj)} recorded steps; raise --steps or lower --bj-steps")
+    jp = sum(traj[i][0] for i in window) / n
+    jm = sum(traj[i][1] for i in window) / n
+    bm = host_ms / n
+    out["same_steps"] = {"trajectory_steps": [window.start, window.stop - 1],
+                         "jacobi_pcg_per_step": round(jp, 2), "block_jacobi_pcg_per_step": round(pcg / n, 2),
+                         "jacobi_host_ms": round(jm, 2), "block_jacobi_host_ms": round(bm, 2),
+                         "speed_vs_jacobi": round(jm / bm, 4)}
     return out
 
 
-def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
+def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
     """The same workload from its initial state with the learned preconditioner
     (flexible CG, Jacobi fallback): the network starts as the zero map (i.e.
     Jacobi), is trained online on the energy-norm loss during
     ``learned_train_steps`` untimed Jacobi steps, then ``learned_steps`` steps
-    are timed with the learned preconditioner and no training."""
+    are timed with the learned preconditioner and no training.  They are
+    compared with the main Jacobi run over the same trajectory steps (host
+    stage timers on both sides); the flexible CG starts each solve from zero,
+    the Jacobi CG from its warm start."""
     import torch
     from paper_2602_07853_amd import precond_train
     ctx.precond_set_weights(precond_train.init_weights(0))
@@ -323,6 +428,7 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
     ctx.set_opts(precond=2)
     torch.cuda.synchronize()
     newton = pcg = fb = 0
+    host_ms = 0.0
     t0 = time.perf_counter()
     for k in range(args.learned_steps):
         st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
@@ -330,6 +436,7 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
         newton += st["newton_iters"]
         pcg += st["pcg_iters"]
         fb += st["fallbacks"]
+        host_ms += st["ms_unload"] + st["ms_newton"] + st["ms_load"]
         print(f"[bench] learned step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} "
               f"fallbacks {st['fallbacks']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -338,10 +445,21 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts):
     net = network_rate(ctx, sc)
     n = args.learned_steps
     sps = n / el
+    window = range(args.learned_train_steps, args.learned_train_steps + n)
+    if not all(i in traj for i in window):
+        raise RuntimeError(f"learned window {window.start}..{window.stop - 1} lies outside the main "
+                           f"run's {len(traj)} recorded steps; raise --steps or --warmup")
+    jp = sum(traj[i][0] for i in window) / n
+    jm = sum(traj[i][1] for i in window) / n
     return {"steps_per_s": round(sps, 4), "steps": n, "ms_per_step": round(1e3 * el / n, 3),
             "newton_per_step": round(newton / n, 3), "pcg_per_step": round(pcg / n, 2),
             "fallbacks_per_step": round(fb / n, 3),
             "vs_plain": round(sps / plain_steps_per_s, 4),
+            "same_steps": {"trajectory_steps": [window.start, window.stop - 1],
+                           "jacobi_pcg_per_step": round(jp, 2), "learned_pcg_per_step": round(pcg / n, 2),
+                           "jacobi_host_ms": round(jm, 2), "learned_host_ms": round(host_ms / n, 2),
+                           "speed_vs_jacobi": round(jm / (host_ms / n), 4),
+                           "note": "flexible CG starts from zero; the Jacobi CG from its warm start"},
             "network": net,
             "plain_pcg_per_step": round(plain_counts[1], 2),
             "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "

@@ -7,7 +7,8 @@ times, against the FP64 oracle on the same seeded inputs:
 FP64 elsewhere.  Every stage whose oracle finishes in seconds at this size is
 compared on all outputs: unload fields, stretch reconstruction, energy and
 gradient at vhat, Hessian-vector products (GPU tangent + product against the
-oracle's tangent + product), the 3x3 block-Jacobi blocks, and Load of an oracle-side node velocity field."""
+oracle's tangent + product, on random vectors and on the search directions
+of the oracle's own Jacobi-PCG run), the 3x3 block-Jacobi blocks, and Load of an oracle-side node velocity field."""
 import numpy as np
 import pytest
 
@@ -76,6 +77,33 @@ def test_energy_gradient_and_hv_full_size(full):
         Huo = O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, u.astype(np.float64))
         e = rel(Hu, Huo)
         print(f"[fullsize] Hv trial {trial} rel err {e:.2e}", flush=True)
+        assert e <= 1e-5
+    # and on the search directions of a Jacobi-PCG run of the oracle on the
+    # first Newton system H p = -g (its own product and diagonal), recorded
+    # every 6 iterations: smooth, nearly rigid vectors where the per-cell
+    # contributions cancel most
+    D = O.jacobi_diag(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A)
+    Dinv = np.where(D > 0, 1.0 / np.where(D > 0, D, 1.0), 0.0)
+    r = np.where(D > 0, -go, 0.0)
+    z = Dinv * r
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    dirs = []
+    for k in range(25):
+        if k % 6 == 0:
+            dirs.append(p.astype(np.float32))
+        q = O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, p)
+        alpha = rz / float(np.sum(p * q))
+        r -= alpha * q
+        z = Dinv * r
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    for k, u in enumerate(dirs):
+        Hu = host(ctx.hv(torch.tensor(u, device="cuda"), 0))
+        Huo = O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, u.astype(np.float64))
+        e = rel(Hu, Huo)
+        print(f"[fullsize] Hv on CG direction {6 * k} rel err {e:.2e}", flush=True)
         assert e <= 1e-5
     # 3x3 block-Jacobi blocks from the FP32 tangent against the oracle's
     # from its FP64 tangent, on every node

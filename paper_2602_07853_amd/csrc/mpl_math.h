@@ -63,6 +63,27 @@ MPL_DEV double det(const double* A) {
          A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 // cof(A) = det(A) A^{-T}
+// Inverse of the symmetric 3x3 matrix h = (xx, yy, zz, xy, yz, xz) by its
+// adjugate over its determinant, same storage.  Returns false (and inv = 0)
+// unless the determinant is finite and positive (h positive definite when
+// also its leading 1x1 and 2x2 minors are, which a block of an SPD matrix
+// satisfies).
+MPL_DEV bool sym3_inverse(const double h[6], double inv[6]) {
+  const double xx = h[0], yy = h[1], zz = h[2], xy = h[3], yz = h[4], xz = h[5];
+  const double c00 = yy * zz - yz * yz, c11 = xx * zz - xz * xz, c22 = xx * yy - xy * xy;
+  const double c01 = xz * yz - xy * zz, c12 = xy * xz - xx * yz, c02 = xy * yz - yy * xz;
+  const double d = xx * c00 + xy * c01 + xz * c02;
+  const bool ok = d > 0.0 && isfinite(d) && xx > 0.0 && c22 > 0.0;
+  const double id = ok ? 1.0 / d : 0.0;
+  inv[0] = ok ? c00 * id : 0.0;
+  inv[1] = ok ? c11 * id : 0.0;
+  inv[2] = ok ? c22 * id : 0.0;
+  inv[3] = ok ? c01 * id : 0.0;
+  inv[4] = ok ? c12 * id : 0.0;
+  inv[5] = ok ? c02 * id : 0.0;
+  return ok;
+}
+
 MPL_DEV void cofactor(const double* A, double* C) {
   C[0] = A[4] * A[8] - A[5] * A[7];
   C[1] = A[5] * A[6] - A[3] * A[8];

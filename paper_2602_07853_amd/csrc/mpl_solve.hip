@@ -568,7 +568,8 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
                                                    const uint8_t* __restrict__ flags,
                                                    const int* __restrict__ n_nbr_cell, int64_t nnode,
                                                    double inv4dx, double* __restrict__ B,
-                                                   T* __restrict__ Bt, const T* __restrict__ Aoff) {
+                                                   T* __restrict__ Bt, const T* __restrict__ Aoff,
+                                                   int32_t* __restrict__ err) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -604,13 +605,13 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
     }
     for (int a = 0; a < 3; ++a) h[a] += mi[ni];
   }
-  // adjugate of [[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]]
-  const double xx = h[0], yy = h[1], zz = h[2], xy = h[3], yz = h[4], xz = h[5];
-  const double c00 = yy * zz - yz * yz, c11 = xx * zz - xz * xz, c22 = xx * yy - xy * xy;
-  const double c01 = xz * yz - xy * zz, c12 = xy * xz - xx * yz, c02 = xy * yz - yy * xz;
-  const double det = xx * c00 + xy * c01 + xz * c02;
-  const double id = fr ? 1.0 / det : 0.0;
-  const double inv[6] = {c00 * id, c11 * id, c22 * id, c01 * id, c12 * id, c02 * id};
+  // a free node's block is m_i I plus PSD cell blocks: positive definite
+  // unless a value is not finite; anything else is reported (error bit 128)
+  double inv[6];
+  const bool ok = sym3_inverse(h, inv);
+  if (fr && !ok) atomicOr(err, 128);
+  if (!fr || !ok)
+    for (int e = 0; e < 6; ++e) inv[e] = 0.0;
   for (int e = 0; e < 6; ++e) {
     B[e * nnode + ni] = inv[e];
     Bt[e * nnode + ni] = (T)inv[e];
@@ -1894,15 +1895,22 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
       MPL_TRY(mpl_ensure(c, c->Bjt, 4 * 6 * nnode));
       if (fact)
         MPL_LAUNCH(c, (k_block_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)aoff);
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)aoff,
+                   &c->dscal()->err);
       else
         MPL_LAUNCH(c, (k_block_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)nullptr);
+                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)nullptr,
+                   &c->dscal()->err);
     } else {
       MPL_TRY(mpl_ensure(c, c->Bjt, 8 * 6 * nnode));
       MPL_LAUNCH(c, (k_block_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt), (const double*)nullptr);
+                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt), (const double*)nullptr,
+                 &c->dscal()->err);
     }
+    // the node blocks are read by every CG iteration: check them once here
+    MPL_TRY(mpl_sync_scalars(c));
+    if (c->hscal.err & 128)
+      return mpl_fail(c, MPL_ERR_NONFINITE, "a 3x3 node block of the Newton matrix is not positive definite");
     c->bj_built = true;
   }
   c->tangent_built = true;

@@ -15,8 +15,9 @@
  *   - Matrices row-major 3x3; G_ab = dv_a/dx_b.
  *   - Particle arrays are DEVICE pointers, SoA per field, particle-major:
  *     x, v [n][3]; F, G [n][3][3]; m, V0, plastic [n]; mat [n] (int32).
- *     All double precision.  The caller owns them; the library never frees
- *     or reallocates them.
+ *     Double precision, or single precision staged to double (the dtype
+ *     field of mpl_particles).  The caller owns them; the library never
+ *     frees or reallocates them.
  *   - "Dense" grid vectors used by the sub-step entry points are DEVICE
  *     arrays over ALL nodes (dims+1)^3 (or cells dims^3), index
  *     (i*(Ny) + j)*(Nz) + k with i the x index, component-interleaved
@@ -25,8 +26,9 @@
  *   - All device work is ordered on the stream given to mpl_create.  Calls
  *     synchronise that stream only to read solver control scalars (norms,
  *     energies, iteration flags) back to the host.
- *   - The context owns its grid scratch (hipMalloc, grown on demand, reused
- *     across steps, freed by mpl_destroy).
+ *   - The context owns its grid scratch (grown on demand, reused across
+ *     steps, freed by mpl_destroy), from hipMalloc or from the caller's
+ *     allocator callbacks (mpl_create_with_allocator).
  *
  * Errors: every call returns an mpl_status; 0 is success.  No exception
  * crosses the ABI.  mpl_last_error() returns a per-context message.
@@ -34,6 +36,7 @@
 #ifndef MPMLITE_H
 #define MPMLITE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -144,9 +147,16 @@ enum { MPL_PLASTICITY_AFTER_SOLVE = 0, MPL_PLASTICITY_FIXED_POINT = 1 };
 
 enum { MPL_TRANSFER_APIC = 0, MPL_TRANSFER_FLIP_PIC = 1 };
 
+/* Particle state (device arrays, SoA, particle-major, see Conventions).
+ * dtype is the precision of x, v, F, G, m, V0 and plastic: MPL_F64, or
+ * MPL_F32, whose arrays are copied to FP64 staging buffers of the context on
+ * entry and the results (x, v, F, G, plastic) rounded back on success; the
+ * step computes in FP64 either way.  in and out of one call must have the
+ * same dtype. */
 typedef struct {
   int64_t n;
-  double *x, *v, *F, *G, *m, *V0, *plastic;  /* device; plastic may be NULL */
+  int32_t dtype;                              /* MPL_F64 or MPL_F32 */
+  void *x, *v, *F, *G, *m, *V0, *plastic;     /* device; plastic may be NULL */
   int32_t* mat;                               /* device */
 } mpl_particles;
 
@@ -181,6 +191,20 @@ typedef struct {
 
 typedef struct mpl_ctx mpl_ctx;
 
+/* Optional device-memory callbacks for a context's grid scratch, so that
+ * the caller's allocator (for example PyTorch's caching allocator) owns
+ * every buffer the library uses.  alloc returns a device pointer of at
+ * least `bytes` bytes (aligned to 256 bytes) for use on hip_stream, or NULL
+ * on failure (the call then fails with MPL_ERR_OOM); free releases a
+ * pointer alloc returned, with the size it was asked for.  The library
+ * synchronises its stream before it frees a buffer.  user is passed back
+ * unchanged.  Both callbacks must be set. */
+typedef struct {
+  void* (*alloc)(void* user, size_t bytes, void* hip_stream);
+  void (*free)(void* user, void* ptr, size_t bytes, void* hip_stream);
+  void* user;
+} mpl_allocator;
+
 /* Library version string. */
 const char* mpl_version(void);
 
@@ -192,6 +216,11 @@ const char* mpl_version(void);
  * context must be used by one host thread at a time. */
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out);
+/* mpl_create with the context's device memory taken from the caller's
+ * callbacks (allocator may be NULL: hipMalloc/hipFree, as mpl_create). */
+mpl_status mpl_create_with_allocator(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
+                                     const mpl_solver_opts* opts, void* hip_stream,
+                                     const mpl_allocator* allocator, mpl_ctx** out);
 void mpl_destroy(mpl_ctx* ctx);
 const char* mpl_last_error(const mpl_ctx* ctx);
 /* Replace the solver options (e.g. tolerances) of an existing context. */

@@ -1,5 +1,6 @@
 // Context life cycle, error handling, buffers, scans and dense <-> block
 // conversions.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -21,21 +22,43 @@ mpl_status mpl_hip_check(mpl_ctx* c, hipError_t e, const char* what) {
   return mpl_fail(c, e == hipErrorOutOfMemory ? MPL_ERR_OOM : MPL_ERR_HIP, m);
 }
 
+mpl_status mpl_dev_alloc(mpl_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (c->allocator.alloc) {
+    *p = c->allocator.alloc(c->allocator.user, bytes, (void*)c->stream);
+    if (!*p) return mpl_fail(c, MPL_ERR_OOM, "allocator callback failed for " + std::to_string(bytes) + " bytes");
+    if (((uintptr_t)*p & 255) != 0) {
+      c->allocator.free(c->allocator.user, *p, bytes, (void*)c->stream);
+      *p = nullptr;
+      return mpl_fail(c, MPL_ERR_OOM, "allocator callback returned memory not aligned to 256 bytes");
+    }
+    return MPL_OK;
+  }
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return mpl_fail(c, MPL_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return MPL_OK;
+}
+
+void mpl_dev_free(mpl_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (c->allocator.free) c->allocator.free(c->allocator.user, p, bytes, (void*)c->stream);
+  else (void)hipFree(p);
+}
+
 mpl_status mpl_ensure(mpl_ctx* c, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.bytes >= bytes) return MPL_OK;
   if (b.p) {
     MPL_HIP(c, hipStreamSynchronize(c->stream));
-    MPL_HIP(c, hipFree(b.p));
+    mpl_dev_free(c, b.p, b.bytes);
     b.p = nullptr;
     b.bytes = 0;
   }
   size_t want = bytes + bytes / 8;  // grow with headroom
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    b.p = nullptr;
-    return mpl_fail(c, MPL_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
-  }
+  MPL_TRY(mpl_dev_alloc(c, &b.p, want));
   b.bytes = want;
   return MPL_OK;
 }
@@ -192,9 +215,63 @@ mpl_status mpl_block_to_dense_nodes(mpl_ctx* c, const void* block, void* dense, 
   return MPL_OK;
 }
 
+// ---------------------------------------------------------------- particle staging
+namespace {
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+__global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+// components per particle of x, v, F, G, m, V0, plastic
+constexpr int kComps[7] = {3, 3, 9, 9, 1, 1, 1};
+}  // namespace
+
+mpl_status mpl_particles_in(mpl_ctx* c, const mpl_particles* p, Parts64* out) {
+  if (!p || p->n < 0) return mpl_fail(c, MPL_ERR_INVALID_ARG, "particles");
+  out->n = p->n;
+  out->mat = p->mat;
+  void* const src[7] = {p->x, p->v, p->F, p->G, p->m, p->V0, p->plastic};
+  double** dst[7] = {&out->x, &out->v, &out->F, &out->G, &out->m, &out->V0, &out->plastic};
+  if (p->dtype == MPL_F64) {
+    for (int f = 0; f < 7; ++f) *dst[f] = (double*)src[f];
+    return MPL_OK;
+  }
+  if (p->dtype != MPL_F32) return mpl_fail(c, MPL_ERR_INVALID_ARG, "particle dtype must be MPL_F64 or MPL_F32");
+  const int64_t n = p->n;
+  MPL_TRY(mpl_ensure(c, c->pstage, 8 * 27 * (size_t)std::max<int64_t>(n, 1)));
+  double* base = P<double>(c->pstage);
+  int64_t off = 0;
+  for (int f = 0; f < 7; ++f) {
+    const int64_t cnt = n * kComps[f];
+    *dst[f] = nullptr;
+    if (src[f]) {
+      *dst[f] = base + off;
+      MPL_LAUNCH(c, k_f32_to_f64, (int)((cnt + 255) / 256), 256, (const float*)src[f], base + off, cnt);
+    }
+    off += cnt;
+  }
+  return MPL_OK;
+}
+
+mpl_status mpl_particles_out(mpl_ctx* c, const Parts64* staged, const mpl_particles* p) {
+  const int64_t n = staged->n;
+  const double* from[5] = {staged->x, staged->v, staged->F, staged->G, staged->plastic};
+  void* const to[5] = {p->x, p->v, p->F, p->G, p->plastic};
+  const int comps[5] = {3, 3, 9, 9, 1};
+  for (int f = 0; f < 5; ++f) {
+    if (!from[f] || !to[f]) continue;
+    const int64_t cnt = n * comps[f];
+    MPL_LAUNCH(c, k_f64_to_f32, (int)((cnt + 255) / 256), 256, from[f], (float*)to[f], cnt);
+  }
+  return MPL_OK;
+}
+
 // ---------------------------------------------------------------- life cycle
-static void free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+static void free_buf(mpl_ctx* c, DevBuf& b) {
+  mpl_dev_free(c, b.p, b.bytes);
   b.p = nullptr;
   b.bytes = 0;
 }
@@ -262,8 +339,15 @@ const char* mpl_version(void) { return "mpmlite-mi355x 0.15 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
+  return mpl_create_with_allocator(grid, mats, n_mats, opts, hip_stream, nullptr, out);
+}
+
+mpl_status mpl_create_with_allocator(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
+                                     const mpl_solver_opts* opts, void* hip_stream,
+                                     const mpl_allocator* allocator, mpl_ctx** out) {
   if (!out) return MPL_ERR_INVALID_ARG;
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) return MPL_ERR_INVALID_ARG;
   if (!grid || !mats || !opts || n_mats < 1 || n_mats > MPL_MAX_MATERIALS) return MPL_ERR_INVALID_ARG;
   for (int a = 0; a < 3; ++a)
     if (grid->dims[a] < 4 || grid->dims[a] % 4 != 0 || grid->dims[a] > 4096) return MPL_ERR_INVALID_ARG;
@@ -279,6 +363,7 @@ mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_
   c->dx = grid->dx;
   c->inv_dx = 1.0 / grid->dx;
   c->stream = (hipStream_t)hip_stream;
+  if (allocator) c->allocator = *allocator;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return MPL_ERR_HIP;
@@ -321,10 +406,10 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->Bj, &c->Bjt, &c->Aoff, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->wtmp, &c->warm_x0, &c->gal_w,
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->pstage, &c->wtmp, &c->warm_x0, &c->gal_w,
                    &c->gal_u, &c->gal_y,
                    &c->gal_part};
-  for (DevBuf* b : all) free_buf(*b);
+  for (DevBuf* b : all) free_buf(c, *b);
   nn_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {
     if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
@@ -333,7 +418,7 @@ void mpl_destroy(mpl_ctx* c) {
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (auto& ring : c->whist)
-    for (DevBuf& b : ring) free_buf(b);
+    for (DevBuf& b : ring) free_buf(c, b);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->cap_order)

@@ -116,13 +116,19 @@ mpl_status mpl_step_explicit(mpl_ctx* c, const mpl_particles* in, mpl_particles*
                              const double gravity[3], const mpl_bc* bcs, int32_t n_bcs, double time,
                              mpl_stats* stats) {
   if (!c || !in || !out) return MPL_ERR_INVALID_ARG;
+  if (out->dtype != in->dtype) return mpl_fail(c, MPL_ERR_INVALID_ARG, "in and out particle dtypes differ");
   mpl_stats st{};
   const double t0 = wall_ms();
-  MPL_TRY(mpl_stage_unload(c, in, dt, gravity, bcs, n_bcs, time));
+  Parts64 pin, pout;
+  MPL_TRY(mpl_particles_in(c, in, &pin));
+  if (in->dtype == MPL_F32) pout = pin;
+  else MPL_TRY(mpl_particles_in(c, out, &pout));
+  MPL_TRY(mpl_stage_unload(c, &pin, dt, gravity, bcs, n_bcs, time));
   const double t1 = wall_ms();
   MPL_TRY(stage_explicit(c, false));
   const double t2 = wall_ms();
-  MPL_TRY(mpl_stage_load(c, P<double>(c->v), in, out, dt));
+  MPL_TRY(mpl_stage_load(c, P<double>(c->v), &pin, &pout, dt));
+  if (in->dtype == MPL_F32) MPL_TRY(mpl_particles_out(c, &pout, out));
   const double t3 = wall_ms();
   st.active_cells = c->hscal.n_active_cells;
   st.active_nodes = c->hscal.n_active_nodes;

@@ -73,8 +73,16 @@ struct SolverScalars {
   int32_t n_tan_cells;  // cells that carry a tangent (some V_{c,k} != 0)
 };
 
+// FP64 view of the boundary's particle arrays (the kernels' layout).
+struct Parts64 {
+  int64_t n;
+  double *x, *v, *F, *G, *m, *V0, *plastic;
+  int32_t* mat;
+};
+
 struct mpl_ctx {
   int device = 0;  // HIP device current at mpl_create
+  mpl_allocator allocator{};  // caller's device-memory callbacks (alloc NULL: hipMalloc)
   // grid
   int dims[3];
   int cbd[3];   // cell-block grid dims (dims/4)
@@ -112,6 +120,7 @@ struct mpl_ctx {
   // cell block (see tan_slot in mpl_grid.h)
   DevBuf cmask, ccnt, coff;
   DevBuf p2c_halo;  // particle -> centre scatter: per-block halo staging
+  DevBuf pstage;    // FP64 staging of single-precision particle arrays
   // node fields
   // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
   // (read by the CG vector kernels)
@@ -218,7 +227,7 @@ inline T* P(const DevBuf& b) { return (T*)b.p; }
 mpl_status mpl_scan_i32(mpl_ctx* c, const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev);
 
 // Internal stages shared by the entry points.
-mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, const double* gravity,
+mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const double* gravity,
                             const mpl_bc* bcs, int n_bcs, double time);
 mpl_status mpl_stage_reconstruct(mpl_ctx* c);
 mpl_status mpl_stage_energy(mpl_ctx* c, const double* v_block, bool want_grad, double* energy,
@@ -229,8 +238,8 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b_block, double* x_block, int
                          double* rel, const double* x0_block = nullptr);
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st);
 mpl_status mpl_stage_precond_apply(mpl_ctx* c, const double* r_block, double* z_block);
-mpl_status mpl_stage_load(mpl_ctx* c, const double* v_block, const mpl_particles* in,
-                          mpl_particles* out, double dt);
+mpl_status mpl_stage_load(mpl_ctx* c, const double* v_block, const Parts64* in,
+                          const Parts64* out, double dt);
 // dense <-> block conversions for node vectors (3 comps) and scalars
 mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, int comps,
                                     int is_f32);
@@ -246,3 +255,12 @@ void mpl_noalloc_attach(mpl_ctx* c);
 mpl_status mpl_stage_hv_into(mpl_ctx* c, const void* u, void* Hu, void* pieces, int precision);
 // zero the non-free nodes of a block-layout node vector (3 components)
 mpl_status mpl_mask_free_nodes(mpl_ctx* c, void* u, int is_f32);
+// device memory of the context (the caller's allocator or hipMalloc/hipFree)
+mpl_status mpl_dev_alloc(mpl_ctx* c, void** p, size_t bytes);
+void mpl_dev_free(mpl_ctx* c, void* p, size_t bytes);
+// FP64 views of boundary particle arrays: MPL_F64 arrays in place, MPL_F32
+// arrays staged to the context's FP64 buffer (x, v, F, G, m, V0, plastic).
+mpl_status mpl_particles_in(mpl_ctx* c, const mpl_particles* p, Parts64* out);
+// After a successful load into the staging buffer: round x, v, F, G and
+// plastic back into the caller's single-precision arrays.
+mpl_status mpl_particles_out(mpl_ctx* c, const Parts64* staged, const mpl_particles* p);

@@ -290,7 +290,7 @@ double wall_ms() {
 
 }  // namespace
 
-mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const mpl_particles* in, mpl_particles* out,
+mpl_status mpl_stage_load(mpl_ctx* c, const double* v, const Parts64* in, const Parts64* out,
                           double dt) {
   if (!c->unloaded) return mpl_fail(c, MPL_ERR_STATE, "load before unload");
   if (!in || !out || in->n != c->np || out->n != in->n)
@@ -331,16 +331,29 @@ mpl_status mpl_load(mpl_ctx* c, const double* v, const mpl_particles* in, mpl_pa
   } else if (!c->solved) {
     return mpl_fail(c, MPL_ERR_STATE, "load without a velocity needs a solved step");
   }
-  return mpl_stage_load(c, vb, in, out, dt);
+  if (!in || !out) return MPL_ERR_INVALID_ARG;
+  if (out->dtype != in->dtype) return mpl_fail(c, MPL_ERR_INVALID_ARG, "in and out particle dtypes differ");
+  Parts64 pin, pout;
+  MPL_TRY(mpl_particles_in(c, in, &pin));
+  if (in->dtype == MPL_F32) pout = pin;  // load into the staging buffer, then round back
+  else MPL_TRY(mpl_particles_in(c, out, &pout));
+  MPL_TRY(mpl_stage_load(c, vb, &pin, &pout, dt));
+  if (in->dtype == MPL_F32) MPL_TRY(mpl_particles_out(c, &pout, out));
+  return MPL_OK;
 }
 
 mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, double dt,
                     const double gravity[3], const mpl_bc* bcs, int32_t n_bcs, double time,
                     mpl_stats* stats) {
   if (!c || !in || !out) return MPL_ERR_INVALID_ARG;
+  if (out->dtype != in->dtype) return mpl_fail(c, MPL_ERR_INVALID_ARG, "in and out particle dtypes differ");
   mpl_stats st{};
   double t0 = wall_ms();
-  MPL_TRY(mpl_stage_unload(c, in, dt, gravity, bcs, n_bcs, time));
+  Parts64 pin, pout;
+  MPL_TRY(mpl_particles_in(c, in, &pin));
+  if (in->dtype == MPL_F32) pout = pin;
+  else MPL_TRY(mpl_particles_in(c, out, &pout));
+  MPL_TRY(mpl_stage_unload(c, &pin, dt, gravity, bcs, n_bcs, time));
   double t1 = wall_ms();
   MPL_TRY(mpl_stage_reconstruct(c));
   MPL_TRY(mpl_sync_scalars(c));
@@ -351,7 +364,8 @@ mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, dou
     if (stats) *stats = st;
     return s;
   }
-  MPL_TRY(mpl_stage_load(c, P<double>(c->v), in, out, dt));
+  MPL_TRY(mpl_stage_load(c, P<double>(c->v), &pin, &pout, dt));
+  if (in->dtype == MPL_F32) MPL_TRY(mpl_particles_out(c, &pout, out));
   double t4 = wall_ms();
   st.active_cells = c->hscal.n_active_cells;
   st.active_nodes = c->hscal.n_active_nodes;

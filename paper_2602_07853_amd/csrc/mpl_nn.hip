@@ -903,12 +903,10 @@ void nn_destroy(mpl_ctx* c) {
   NNState& nn = *c->nn;
   DevBuf* all[] = {&nn.params, &nn.grad, &nn.adam_m, &nn.adam_v, &nn.wsw, &nn.act, &nn.gact,
                    &nn.wpart, &nn.lpart, &nn.tmp, &nn.dref};
-  for (DevBuf* b : all)
-    if (b->p) (void)hipFree(b->p);
+  for (DevBuf* b : all) mpl_dev_free(c, b->p, b->bytes);
   if (nn.store) {
     DevBuf* st[] = {&nn.store->feat, &nn.store->target, &nn.store->mask};
-    for (DevBuf* b : st)
-      if (b->p) (void)hipFree(b->p);
+    for (DevBuf* b : st) mpl_dev_free(c, b->p, b->bytes);
     delete nn.store;
   }
   delete c->nn;

@@ -492,7 +492,7 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
 
 }  // namespace
 
-mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, const double* gravity,
+mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const double* gravity,
                             const mpl_bc* bcs, int n_bcs, double time) {
   if (!in || in->n < 0 ||
       (in->n > 0 && (!in->x || !in->v || !in->F || !in->G || !in->m || !in->V0 || !in->mat)))
@@ -637,6 +637,8 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const mpl_particles* in, double dt, cons
 extern "C" mpl_status mpl_unload(mpl_ctx* c, const mpl_particles* in, double dt,
                                  const double gravity[3], const mpl_bc* bcs, int32_t n_bcs,
                                  double time) {
-  if (!c) return MPL_ERR_INVALID_ARG;
-  return mpl_stage_unload(c, in, dt, gravity, bcs, n_bcs, time);
+  if (!c || !in) return MPL_ERR_INVALID_ARG;
+  Parts64 pin;
+  MPL_TRY(mpl_particles_in(c, in, &pin));
+  return mpl_stage_unload(c, &pin, dt, gravity, bcs, n_bcs, time);
 }

@@ -56,7 +56,7 @@ class _Opts(C.Structure):
 
 
 class _Particles(C.Structure):
-    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("v", C.c_void_p), ("F", C.c_void_p),
+    _fields_ = [("n", C.c_int64), ("dtype", C.c_int32), ("x", C.c_void_p), ("v", C.c_void_p), ("F", C.c_void_p),
                 ("G", C.c_void_p), ("m", C.c_void_p), ("V0", C.c_void_p), ("plastic", C.c_void_p),
                 ("mat", C.c_void_p)]
 
@@ -77,6 +77,49 @@ class _Stats(C.Structure):
                 ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8),
                 ("graph_replays", C.c_int32), ("upd_calls", C.c_int32), ("upd_ms_total", C.c_double),
                 ("upd_model_bytes", C.c_double)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device-memory callbacks backed by PyTorch's caching allocator, so that
+    PyTorch owns the library's grid scratch (it shows in
+    ``torch.cuda.memory_allocated``)."""
+
+    def __init__(self, device, stream):
+        self.device = device
+        self.stream = stream
+        self.live = {}
+
+        def alloc(user, nbytes, hip_stream):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def free(user, ptr, nbytes, hip_stream):
+            if ptr in self.live:
+                del self.live[ptr]
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass
+
+        self._alloc = _ALLOC_FN(alloc)
+        self._free = _FREE_FN(free)
+        self.c = _Allocator(self._alloc, self._free, None)
+
+    @property
+    def bytes_live(self) -> int:
+        return sum(self.live.values())
 
 
 _lib = None
@@ -122,10 +165,14 @@ def _particles(p: dict) -> _Particles:
         if tuple(p[k].shape) != shape:
             raise ValueError(f"particle field {k} has shape {tuple(p[k].shape)}, want {shape}")
     pl = p.get("plastic")
-    return _Particles(n, _dptr(p["x"], torch.float64), _dptr(p["v"], torch.float64),
-                      _dptr(p["F"], torch.float64), _dptr(p["G"], torch.float64),
-                      _dptr(p["m"], torch.float64), _dptr(p["V"], torch.float64),
-                      _dptr(pl, torch.float64) if pl is not None else None,
+    dt = p["x"].dtype
+    if dt not in (torch.float64, torch.float32):
+        raise ValueError(f"particle arrays must be float64 or float32, got {dt}")
+    return _Particles(n, F64 if dt == torch.float64 else F32,
+                      _dptr(p["x"], dt), _dptr(p["v"], dt),
+                      _dptr(p["F"], dt), _dptr(p["G"], dt),
+                      _dptr(p["m"], dt), _dptr(p["V"], dt),
+                      _dptr(pl, dt) if pl is not None else None,
                       _dptr(p["mat"], torch.int32))
 
 
@@ -137,16 +184,17 @@ def _bcs(bcs):
     return arr
 
 
-def particles_to_device(parts: dict, device="cuda") -> dict:
-    """Copy a NumPy particle dict (x, v, G, F, m, V, mat[, eps]) to device tensors."""
+def particles_to_device(parts: dict, device="cuda", dtype=torch.float64) -> dict:
+    """Copy a NumPy particle dict (x, v, G, F, m, V, mat[, eps]) to device
+    tensors of ``dtype`` (float64, or float32 staged to FP64 by the library)."""
     out = {}
     for k in ("x", "v", "G", "F", "m", "V"):
-        out[k] = torch.as_tensor(parts[k], dtype=torch.float64).contiguous().to(device)
+        out[k] = torch.as_tensor(parts[k], dtype=torch.float64).to(dtype).contiguous().to(device)
     out["mat"] = torch.as_tensor(parts["mat"], dtype=torch.int32).contiguous().to(device)
     eps = parts.get("eps", parts.get("plastic"))
     n = out["x"].shape[0]
     out["plastic"] = (torch.as_tensor(eps, dtype=torch.float64) if eps is not None
-                      else torch.zeros(n, dtype=torch.float64)).contiguous().to(device)
+                      else torch.zeros(n, dtype=torch.float64)).to(dtype).contiguous().to(device)
     return out
 
 
@@ -162,7 +210,8 @@ def default_opts(**kw) -> dict:
 class Context:
     """One simulation grid (dims multiples of 4) with its materials and solver options."""
 
-    def __init__(self, dims, dx, materials, opts=None, origin=(0.0, 0.0, 0.0), stream=None):
+    def __init__(self, dims, dx, materials, opts=None, origin=(0.0, 0.0, 0.0), stream=None,
+                 torch_allocator=True):
         if not torch.cuda.is_available():
             raise RuntimeError("mpmlite runs on the GPU only; no device is visible")
         lib = library()
@@ -180,8 +229,12 @@ class Context:
         o = self._copts()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = C.c_void_p()
-        st = lib.mpl_create(C.byref(g), mats, len(materials), C.byref(o),
-                            C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        # grid scratch from PyTorch's caching allocator (or hipMalloc in the library)
+        self.allocator = TorchAllocator(torch.cuda.current_device(), self.stream) if torch_allocator else None
+        st = lib.mpl_create_with_allocator(C.byref(g), mats, len(materials), C.byref(o),
+                                           C.c_void_p(self.stream.cuda_stream),
+                                           C.byref(self.allocator.c) if self.allocator else None,
+                                           C.byref(ctx))
         if st != 0:
             raise MplError(st, "mpl_create failed")
         self._ctx = ctx

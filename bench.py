@@ -7,13 +7,16 @@ Unload -> stretch reconstruction -> Newton-PCG (Jacobi, FP32 Hessian-vector
 products, FP64 reductions) to relative residual 1e-6 -> Load.
 
 Prints ONE JSON line (see the fields below).  ``roofline`` describes the
-fused Hessian-vector product kernel (the PCG hot loop): algorithmic bytes
-per launch as the library reports them (the stored tangent values one
-product reads per tangent-carrying cell -- 25 FP32 values = 100 B in the
-single-material factored form, 45 = 180 B dense -- plus 24 B per active node
-for reading p and writing K p once) divided by its average duration, timed
-with HIP events on the library's stream over the timed steps.  ``cpu_baseline`` times the
-FP64 CPU oracle on a bounded sample of the same workload.
+kernel with the most time per step, the single-reduction CG update
+(``k_cg_step``): algorithmic bytes per launch (60 B per free DOF) divided by
+its average duration, timed with HIP events on the library's stream over the
+timed steps; ``hv_kernel`` gives the same for the fused Hessian-vector
+product (180 B per tangent-carrying cell + 28 B per active node).  Both also
+carry the library's own count of the bytes its kernels must move (the
+factored tangent reads 25 values per cell).  ``traffic`` is the HBM bytes per
+launch measured by rocprofv3 counters (profiles/cg_traffic.json), when those
+were taken with the current library.  ``cpu_baseline`` times the FP64 CPU
+oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -41,7 +44,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-check", action="store_true",
                     help="skip the final-error check of one step against the FP64 GPU variant")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hv_traffic.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "cg_traffic.json"))
     ap.add_argument("--ppc-axis", type=int, default=None,
                     help="particles per cell along each axis (default: the config's, 2 = 8 PPC)")
     ap.add_argument("--check-every", type=int, default=16,
@@ -282,28 +285,55 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_per_s = args.steps / elapsed
+    # Algorithmic bytes per launch, from the per-unit figures of the design
+    # notes' roofline table (FP32 products):
+    #   CG update (a9): 60 B per free DOF -- r and x in FP64, p, q and the
+    #     Jacobi diagonal in FP32, each read or written once;
+    #   Hessian-vector product (a8): 180 B per tangent-carrying cell (45 FP32
+    #     values of the symmetric 9x9 tangent) + 28 B per active node (u read,
+    #     Hu written, m read).
+    # The library's own count of what its kernels must move (the factored
+    # tangent reads 25 values per cell) is given beside them.
+    free_dofs = st["free_dofs"]
+    elem = 4 if prec == mpmlite.F32 else 8
+    n_tan = int(round((hv_bytes - 6.0 * elem * nodes) / (tan_entries * elem))) if tan_entries else 0
+    hv_alg = (45 * elem * n_tan + 7 * elem * nodes)
+    up_alg = 15 * elem * free_dofs
     hv_avg_ms = hv_ms / max(hv_calls, 1)
-    achieved = hv_bytes / (hv_avg_ms * 1e-3) / 1e9 if hv_calls else 0.0
-    traffic = None
+    up_avg_ms = up_ms / max(up_calls, 1)
+    traffic = {}
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
             if tj.get("workload") == sc.name and tj.get("kernel_version") == ctx_version():
-                traffic = tj.get("bytes_per_hv")
+                traffic = {"hv": tj.get("bytes_per_hv"), "update": tj.get("bytes_per_update")}
         except Exception:
-            traffic = None
+            traffic = {}
     copy_gbs = copy_bandwidth()
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_hv_fused (matrix-free Hessian-vector product)",
-            "achievable_copy_gbs": copy_gbs,
-            "bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries, "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls}
-    up_avg_ms = up_ms / max(up_calls, 1)
-    up_gbs = up_bytes / (up_avg_ms * 1e-3) / 1e9 if up_calls else 0.0
-    update = {"kernel": "k_cg_step (single-reduction CG update + product-piece gather)", "bound": "hbm",
-              "achieved": round(up_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(up_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": up_bytes,
-              "avg_ms": round(up_avg_ms, 5), "launches": up_calls}
+
+    def gbs(nbytes, ms):
+        return nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+
+    up_gbs = gbs(up_alg, up_avg_ms)
+    roof = {"bound": "hbm", "achieved": round(up_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(up_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("update"),
+            "kernel": "k_cg_step (single-reduction CG update with the product-piece gather; the "
+                      "kernel with the most time per step)",
+            "bytes_per_launch": up_alg, "bytes_model": "60 B per free DOF (FP32 products)",
+            "free_dofs": free_dofs, "avg_ms": round(up_avg_ms, 5), "launches": up_calls,
+            "design_bytes_per_launch": up_bytes,
+            "design_frac": round(gbs(up_bytes, up_avg_ms) / HBM_PEAK_GBS, 4),
+            "achievable_copy_gbs": copy_gbs}
+    hv_gbs = gbs(hv_alg, hv_avg_ms)
+    hv_line = {"kernel": "k_hv_fused (matrix-free Hessian-vector product)", "bound": "hbm",
+               "achieved": round(hv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(hv_gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get("hv"),
+               "bytes_per_launch": hv_alg,
+               "bytes_model": "180 B per tangent-carrying cell + 28 B per active node (FP32)",
+               "tangent_cells": n_tan, "active_nodes": nodes,
+               "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls,
+               "design_bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries,
+               "design_frac": round(gbs(hv_bytes, hv_avg_ms) / HBM_PEAK_GBS, 4)}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     final_error = None
     if not args.no_precision_check:
@@ -342,7 +372,7 @@ def main():
                    "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
                    "hv_precision": args.precision, "plasticity": args.plasticity},
         "roofline": roof,
-        "update_kernel": update,
+        "hv_kernel": hv_line,
         "final_error": final_error,
         "cpu_baseline": base,
         "block_jacobi": block_jacobi,

@@ -39,9 +39,13 @@ def main(argv=None):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
+    mi = ctx.export("mass_i")[:, 0]
+    fixed = ctx.export("fixed")[:, 0]
     info = {"workload": sc.name, "pcg_iters": it, "copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+            "kernel_version": mpmlite.library().mpl_version().decode(),
             "active_cells": int(ctx.export("mass_c").gt(0).sum().item()),
-            "active_nodes": int(ctx.export("mass_i").gt(0).sum().item())}
+            "active_nodes": int(mi.gt(0).sum().item()),
+            "free_dofs": 3 * int((mi.gt(0) & fixed.eq(0)).sum().item())}
     print(json.dumps(info), flush=True)
 
 

@@ -371,6 +371,19 @@ mpl_status mpl_nn_forward(mpl_ctx* ctx, const float* x, const int32_t dims[3], f
 /* Parameter gradient (FP32, flat, device) of <dy, network(x)>. */
 mpl_status mpl_nn_backward(mpl_ctx* ctx, const float* x, const int32_t dims[3], const float* dy,
                            float* grad);
+/* One layer of the network on caller tensors, with the kernels of
+ * mpl_nn_forward / mpl_nn_backward: layer index in execution order (see the
+ * parameter layout above), dims = the network box (multiples of 8; the
+ * layer's input and output live at the box >> level of its input and
+ * output).  x [in voxels][Ci] (for the decoders' first layers, the
+ * concatenation [up, skip]) and dy [out voxels][Co] are device FP32, rounded
+ * to BF16 as the network stores them.  y [out voxels][Co] receives the
+ * layer output (after ReLU), dx [in voxels][Ci] the gradient w.r.t. x of
+ * <dy, y> (not for layer 0, whose input is the network input) and dparams
+ * the layer's slice of the parameter gradient (W then bias, FP32); each may
+ * be NULL. */
+mpl_status mpl_nn_layer_grad(mpl_ctx* ctx, int32_t layer, const float* x, const int32_t dims[3],
+                             const float* dy, float* y, float* dx, float* dparams);
 /* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the masked relative L2
  * loss |m (y - t)|^2 / |m t|^2 over output channels 0-2: x [X][Y][Z][16],
  * t [X][Y][Z][3], mask [X][Y][Z] (FP32, device).  *loss (host, may be NULL)

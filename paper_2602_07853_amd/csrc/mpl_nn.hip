@@ -804,27 +804,91 @@ static mpl_status launch_up(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw,
   return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
 }
 
-// Forward pass on the tensors already staged in nn.act (input at t_in).
-mpl_status nn_forward(mpl_ctx* c, NNState& nn) {
+// Forward of layer l on the tensors staged in nn.act.
+static mpl_status nn_forward_layer(mpl_ctx* c, NNState& nn, int l) {
   uint16_t* A = (uint16_t*)nn.act.p;
   const uint16_t* sw = (const uint16_t*)nn.wsw.p;
   const float* P = (const float*)nn.params.p;
-  for (int l = 0; l < NN_LAYERS; ++l) {
-    const Spec& s = kSpec[l];
-    const int T = taps_of(s);
-    View in, out;
-    layer_views(nn, A, l, in, out);
-    const float* bias = P + w_offset(l) + (int64_t)T * s.ci * s.co;
-    const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
-    if (s.up) {
-      MPL_TRY(launch_up(c, in, din, sw + nn.sw_fwd_off[l], (s.ci + 31) / 32, s.co, bias, out, s.relu, 0,
-                        nn.skip));
-    } else if (s.k == 3 && nn.lds_conv) {
-      MPL_TRY(launch_conv3(c, in, din, sw + nn.sw3_fwd_off[l], s.ci, s.co, bias, out, s.relu, 0, nn.skip));
-    } else {
-      MPL_TRY(launch_conv(c, in, din, sw + nn.sw_fwd_off[l], (T * s.ci + 31) / 32, s.ci, s.co, T, s.k,
-                          s.s, s.p, bias, out, dout, s.relu, 0, nn.skip));
+  const Spec& s = kSpec[l];
+  const int T = taps_of(s);
+  View in, out;
+  layer_views(nn, A, l, in, out);
+  const float* bias = P + w_offset(l) + (int64_t)T * s.ci * s.co;
+  const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
+  if (s.up) {
+    MPL_TRY(launch_up(c, in, din, sw + nn.sw_fwd_off[l], (s.ci + 31) / 32, s.co, bias, out, s.relu, 0,
+                      nn.skip));
+  } else if (s.k == 3 && nn.lds_conv) {
+    MPL_TRY(launch_conv3(c, in, din, sw + nn.sw3_fwd_off[l], s.ci, s.co, bias, out, s.relu, 0, nn.skip));
+  } else {
+    MPL_TRY(launch_conv(c, in, din, sw + nn.sw_fwd_off[l], (T * s.ci + 31) / 32, s.ci, s.co, T, s.k,
+                        s.s, s.p, bias, out, dout, s.relu, 0, nn.skip));
+  }
+  return MPL_OK;
+}
+
+// Forward pass on the tensors already staged in nn.act (input at t_in).
+mpl_status nn_forward(mpl_ctx* c, NNState& nn) {
+  for (int l = 0; l < NN_LAYERS; ++l) MPL_TRY(nn_forward_layer(c, nn, l));
+  return MPL_OK;
+}
+
+// Backward of layer l: ReLU mask on its output gradient (staged in nn.gact),
+// parameter gradients ADDED into nn.grad, and (if input_grad and l > 0) the
+// gradient w.r.t. its input, accumulated into a down layer's input view
+// when accum_down (the skip tensor's decoder share is already there).
+static mpl_status nn_backward_layer(mpl_ctx* c, NNState& nn, int l, bool input_grad, bool accum_down) {
+  uint16_t* A = (uint16_t*)nn.act.p;
+  uint16_t* G = (uint16_t*)nn.gact.p;
+  const uint16_t* sw = (const uint16_t*)nn.wsw.p;
+  float* grad = (float*)nn.grad.p;
+  float* part = (float*)nn.wpart.p;
+  const Spec& s = kSpec[l];
+  const int T = taps_of(s);
+  View in, out, gin, gout;
+  layer_views(nn, A, l, in, out);
+  layer_views(nn, G, l, gin, gout);
+  const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
+  const int64_t nvo = (int64_t)dout.x * dout.y * dout.z;
+  if (s.relu)
+    MPL_LAUNCH(c, k_relu_bwd, (int)((nvo * s.co + 255) / 256), 256, gout.p, gout.ld, out.p, out.ld,
+               s.co, nvo);
+  // parameter gradients
+  float* gW = grad + w_offset(l);
+  float* gb = gW + (int64_t)T * s.ci * s.co;
+  {
+    const int64_t nv = s.up ? (int64_t)din.x * din.y * din.z : nvo;
+    const int chunks = (int)((nv + NN_WGRAD_CHUNK - 1) / NN_WGRAD_CHUNK);
+    const int jobs = T * (s.ci / 16) * (s.co / 16);
+    hipLaunchKernelGGL(k_wgrad, dim3(chunks, jobs), dim3(64), 0, c->stream, in.p, in.ld, din,
+                       gout.p, gout.ld, dout, s.ci, s.co, s.up ? 2 : s.k, s.up ? 2 : s.s,
+                       s.up ? 0 : s.p, s.up, NN_WGRAD_CHUNK, part);
+    MPL_HIP(c, hipGetLastError());
+    MPL_LAUNCH(c, k_wgrad_reduce, (jobs * 256 + 255) / 256, 256, part, chunks, jobs, s.ci, s.co, gW);
+    {
+      const int64_t chunk = 4096;
+      const int nch = (int)((nvo + chunk - 1) / chunk);
+      float* bpart = part + (size_t)chunks * jobs * 256;  // after the weight-gradient partials
+      MPL_LAUNCH(c, k_bias_partial, nch, 256, gout.p, gout.ld, nvo, s.co, chunk, bpart);
+      MPL_LAUNCH(c, k_bias_reduce, 1, 128, bpart, nch, s.co, gb);
     }
+  }
+  if (l == 0 || !input_grad) return MPL_OK;  // no gradient w.r.t. the network input
+  // gradient w.r.t. the layer input; the down layers' input is a skip
+  // tensor whose gradient already holds the decoder's share: accumulate.
+  const int accum = (accum_down && s.k == 2 && !s.up) ? 1 : 0;
+  if (s.up) {
+    // dgrad of a transposed conv: 2x2x2 stride-2 gather conv, K = (t, o)
+    MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, 2, 2,
+                        0, nullptr, gin, din, 0, accum));
+  } else if (s.k == 2) {
+    MPL_TRY(launch_up(c, gout, dout, sw + nn.sw_bwd_off[l], (s.co + 31) / 32, s.ci, nullptr, gin, 0,
+                      accum));
+  } else if (s.k == 3 && nn.lds_conv) {
+    MPL_TRY(launch_conv3(c, gout, dout, sw + nn.sw3_bwd_off[l], s.co, s.ci, nullptr, gin, 0, accum));
+  } else {
+    MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, s.k,
+                        1, s.p, nullptr, gin, din, 0, accum));
   }
   return MPL_OK;
 }
@@ -832,60 +896,54 @@ mpl_status nn_forward(mpl_ctx* c, NNState& nn) {
 // Backward pass: the gradient w.r.t. the output must be staged at
 // gact[t_out]; parameter gradients are ADDED into nn.grad.
 mpl_status nn_backward(mpl_ctx* c, NNState& nn) {
+  for (int l = NN_LAYERS - 1; l >= 0; --l) MPL_TRY(nn_backward_layer(c, nn, l, true, true));
+  return MPL_OK;
+}
+
+// One layer on caller tensors: x [in voxels][Ci] into the layer's input
+// view, dy [out voxels][Co] into its output-gradient view (FP32 -> BF16);
+// y, dx read back from the output and input-gradient views (BF16 -> FP32).
+__global__ void k_view_in(const float* __restrict__ src, int64_t nv, int ch, uint16_t* __restrict__ dst,
+                          int ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nv * ch) dst[(i / ch) * ld + i % ch] = f2bf(src[i]);
+}
+__global__ void k_view_out(const uint16_t* __restrict__ src, int ld, int64_t nv, int ch,
+                           float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nv * ch) dst[i] = bf2f(src[(i / ch) * ld + i % ch]);
+}
+
+static mpl_status nn_layer_grad(mpl_ctx* c, int l, const float* x, const int32_t dims[3], const float* dy,
+                                float* y, float* dx, float* dparams) {
+  NNState& nn = *c->nn;
+  const int d[3] = {dims[0], dims[1], dims[2]};
+  MPL_TRY(nn_buffers(c, nn, d, true));
+  const Spec& s = kSpec[l];
+  const int T = taps_of(s);
+  const int32_t* saved_skip = nn.skip;
+  nn.skip = nullptr;
   uint16_t* A = (uint16_t*)nn.act.p;
   uint16_t* G = (uint16_t*)nn.gact.p;
-  const uint16_t* sw = (const uint16_t*)nn.wsw.p;
-  float* grad = (float*)nn.grad.p;
-  float* part = (float*)nn.wpart.p;
-  for (int l = NN_LAYERS - 1; l >= 0; --l) {
-    const Spec& s = kSpec[l];
-    const int T = taps_of(s);
-    View in, out, gin, gout;
-    layer_views(nn, A, l, in, out);
-    layer_views(nn, G, l, gin, gout);
-    const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
-    const int64_t nvo = (int64_t)dout.x * dout.y * dout.z;
-    if (s.relu)
-      MPL_LAUNCH(c, k_relu_bwd, (int)((nvo * s.co + 255) / 256), 256, gout.p, gout.ld, out.p, out.ld,
-                 s.co, nvo);
-    // parameter gradients
-    float* gW = grad + w_offset(l);
-    float* gb = gW + (int64_t)T * s.ci * s.co;
-    {
-      const int64_t nv = s.up ? (int64_t)din.x * din.y * din.z : nvo;
-      const int chunks = (int)((nv + NN_WGRAD_CHUNK - 1) / NN_WGRAD_CHUNK);
-      const int jobs = T * (s.ci / 16) * (s.co / 16);
-      hipLaunchKernelGGL(k_wgrad, dim3(chunks, jobs), dim3(64), 0, c->stream, in.p, in.ld, din,
-                         gout.p, gout.ld, dout, s.ci, s.co, s.up ? 2 : s.k, s.up ? 2 : s.s,
-                         s.up ? 0 : s.p, s.up, NN_WGRAD_CHUNK, part);
-      MPL_HIP(c, hipGetLastError());
-      MPL_LAUNCH(c, k_wgrad_reduce, (jobs * 256 + 255) / 256, 256, part, chunks, jobs, s.ci, s.co, gW);
-      {
-        const int64_t chunk = 4096;
-        const int nch = (int)((nvo + chunk - 1) / chunk);
-        float* bpart = part + (size_t)chunks * jobs * 256;  // after the weight-gradient partials
-        MPL_LAUNCH(c, k_bias_partial, nch, 256, gout.p, gout.ld, nvo, s.co, chunk, bpart);
-        MPL_LAUNCH(c, k_bias_reduce, 1, 128, bpart, nch, s.co, gb);
-      }
-    }
-    if (l == 0) break;  // no gradient w.r.t. the network input
-    // gradient w.r.t. the layer input; the down layers' input is a skip
-    // tensor whose gradient already holds the decoder's share: accumulate.
-    const int accum = (s.k == 2 && !s.up) ? 1 : 0;
-    if (s.up) {
-      // dgrad of a transposed conv: 2x2x2 stride-2 gather conv, K = (t, o)
-      MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, 2, 2,
-                          0, nullptr, gin, din, 0, accum));
-    } else if (s.k == 2) {
-      MPL_TRY(launch_up(c, gout, dout, sw + nn.sw_bwd_off[l], (s.co + 31) / 32, s.ci, nullptr, gin, 0,
-                        accum));
-    } else if (s.k == 3 && nn.lds_conv) {
-      MPL_TRY(launch_conv3(c, gout, dout, sw + nn.sw3_bwd_off[l], s.co, s.ci, nullptr, gin, 0, accum));
-    } else {
-      MPL_TRY(launch_conv(c, gout, dout, sw + nn.sw_bwd_off[l], (T * s.co + 31) / 32, s.co, s.ci, T, s.k,
-                          1, s.p, nullptr, gin, din, 0, accum));
-    }
-  }
+  View in, out, gin, gout;
+  layer_views(nn, A, l, in, out);
+  layer_views(nn, G, l, gin, gout);
+  const Dims3 din = level_dims(nn, s.level_in), dout = level_dims(nn, s.level_out);
+  const int64_t nvi = (int64_t)din.x * din.y * din.z, nvo = (int64_t)dout.x * dout.y * dout.z;
+  MPL_HIP(c, hipMemsetAsync(nn.gact.p, 0, 2 * nn.act_elems, c->stream));
+  MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * nn_param_count(), c->stream));
+  MPL_LAUNCH(c, k_view_in, (int)((nvi * s.ci + 255) / 256), 256, x, nvi, s.ci, in.p, in.ld);
+  MPL_TRY(nn_forward_layer(c, nn, l));
+  MPL_LAUNCH(c, k_view_in, (int)((nvo * s.co + 255) / 256), 256, dy, nvo, s.co, gout.p, gout.ld);
+  mpl_status st = nn_backward_layer(c, nn, l, true, false);
+  nn.skip = saved_skip;
+  MPL_TRY(st);
+  if (y) MPL_LAUNCH(c, k_view_out, (int)((nvo * s.co + 255) / 256), 256, out.p, out.ld, nvo, s.co, y);
+  if (dx && l > 0) MPL_LAUNCH(c, k_view_out, (int)((nvi * s.ci + 255) / 256), 256, gin.p, gin.ld, nvi, s.ci, dx);
+  if (dparams)
+    MPL_HIP(c, hipMemcpyAsync(dparams, (float*)nn.grad.p + w_offset(l),
+                              4 * ((int64_t)T * s.ci * s.co + s.co), hipMemcpyDeviceToDevice, c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
   return MPL_OK;
 }
 
@@ -1345,6 +1403,13 @@ mpl_status mpl_precond_online_stats(mpl_ctx* c, int64_t* steps_done, double* mea
   c->online_ref_sum = 0.0;
   c->online_loss_n = 0;
   return MPL_OK;
+}
+
+mpl_status mpl_nn_layer_grad(mpl_ctx* c, int32_t layer, const float* x, const int32_t dims[3],
+                             const float* dy, float* y, float* dx, float* dparams) {
+  if (!c || !x || !dims || !dy || layer < 0 || layer >= NN_LAYERS) return MPL_ERR_INVALID_ARG;
+  if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "set network weights first");
+  return nn_layer_grad(c, layer, x, dims, dy, y, dx, dparams);
 }
 
 mpl_status mpl_precond_adam_step(mpl_ctx* c, const float* grad, float lr) {

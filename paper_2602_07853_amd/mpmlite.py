@@ -432,6 +432,29 @@ class Context:
                                               C.c_void_p(g.data_ptr())), "mpl_nn_backward")
         return g
 
+    def nn_layer_grad(self, layer: int, x: torch.Tensor, dy: torch.Tensor, box):
+        """One network layer on caller tensors (mpl_nn_layer_grad): x [in voxels, Ci],
+        dy [out voxels, Co] (FP32 device); returns (y, dx, dparams)."""
+        dims = (C.c_int32 * 3)(*box)
+        y = torch.zeros_like(dy)
+        dx = torch.zeros_like(x)
+        n = self._layer_param_counts()[layer]
+        dp = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self._check(self._lib.mpl_nn_layer_grad(self._ctx, C.c_int32(layer), C.c_void_p(_dptr(x, torch.float32)),
+                                                dims, C.c_void_p(_dptr(dy, torch.float32)),
+                                                C.c_void_p(y.data_ptr()), C.c_void_p(dx.data_ptr()),
+                                                C.c_void_p(dp.data_ptr())), "mpl_nn_layer_grad")
+        return y, dx, dp
+
+    @staticmethod
+    def _layer_param_counts():
+        # (k, Ci, Co) of the 21 layers in execution order (include/mpmlite.h)
+        spec = [(3, 16, 16), (3, 16, 16), (2, 16, 32), (3, 32, 32), (3, 32, 32), (2, 32, 64),
+                (3, 64, 64), (3, 64, 64), (2, 64, 128), (3, 128, 128), (3, 128, 128), (2, 128, 64),
+                (3, 128, 64), (3, 64, 64), (2, 64, 32), (3, 64, 32), (3, 32, 32), (2, 32, 16),
+                (3, 32, 16), (3, 16, 16), (1, 16, 16)]
+        return [k ** 3 * ci * co + co for k, ci, co in spec]
+
     def precond_train_step(self, x, t, mask, lr):
         self._check_box(x, "x", 16)
         self._check_box(t, "t", 3, like=x)

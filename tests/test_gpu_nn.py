@@ -9,12 +9,18 @@ is ill-conditioned where many pre-activations sit near zero: on the CPU, a
 1e-4 relative perturbation of the stored activations moves the deep layers'
 weight gradients of a He-initialised network by 1-3%, and BF16 rounding
 moves them by 10-20% (two BF16 computations that round differently differ
-by as much from each other as from FP64).  The tight check therefore uses
-weights in the well-conditioned regime (positive biases keep the ReLUs
+by as much from each other as from FP64).  The whole-network check therefore
+uses weights in the well-conditioned regime (positive biases keep the ReLUs
 active; the same perturbation then moves any layer by < 1%): 5% per layer
-against the FP64 oracle.  The He-initialised ReLU regime is checked for
-direction (cosine > 0.95 per layer) and against the oracle's BF16 precision
-model at 30%."""
+against the FP64 oracle; in the He-initialised ReLU regime the whole-network
+gradient is checked for direction (cosine > 0.95 per layer).
+
+Every layer's kernels are also checked on their own in the He regime
+(mpl_nn_layer_grad): seeded BF16 input and output gradient, He weights, the
+layer's output, input gradient and parameter gradient against the oracle's
+layer in FP64 with BF16 rounding of the stored tensors, within 1e-3 per
+layer; without the depth that compounds roundings the kernels agree to the
+BF16 resolution."""
 import numpy as np
 import pytest
 
@@ -81,15 +87,58 @@ def test_network_gradient_matches_oracle():
 def test_network_gradient_relu_regime():
     params, x, rng = setup(seed=2)
     g, dy = _gradients(params, x, rng)
-    go = U.backward(params, x, dy, rnd=U.bf16)
     g64 = U.backward(params, x, dy)
     lay, _ = U.param_layout()
     for name, (a, b, e) in lay.items():
-        r = rel(g[a:e], go[a:e])
         cos = g[a:e] @ g64[a:e] / (np.linalg.norm(g[a:e]) * np.linalg.norm(g64[a:e]))
-        print(f"[nn] relu-regime grad {name} rel err {r:.3e} cos {cos:.4f}", flush=True)
+        print(f"[nn] relu-regime grad {name} cos {cos:.4f}", flush=True)
         assert cos > 0.95, name
-        assert r <= 0.3, name
+
+
+@pytest.mark.parametrize("layer", range(21))
+def test_layer_kernels_match_oracle_he_regime(layer):
+    """One layer on seeded BF16 tensors with He-initialised BF16 weights and
+    small nonzero biases: output, input gradient and parameter gradient
+    against the oracle's layer (FP64 arithmetic, BF16 rounding of the stored
+    output and input gradient), 1e-3 norm-wise each (measured <= 6e-5)."""
+    box = (16, 16, 24)
+    name, kind, k, s, p, ci, co, act = U.layer_specs()[layer]
+    level_in = {"down0": 0, "down1": 1, "down2": 2, "bota": 3, "botb": 3, "up2": 3, "dec2a": 2, "dec2b": 2,
+                "up1": 2, "dec1a": 1, "dec1b": 1, "up0": 1, "dec0a": 0, "dec0b": 0, "out": 0,
+                "enc0a": 0, "enc0b": 0, "enc1a": 1, "enc1b": 1, "enc2a": 2, "enc2b": 2}[name]
+    din = tuple(d >> level_in for d in box)
+    if kind == "up":
+        dout = tuple(2 * d for d in din)
+    else:
+        dout = tuple((d + 2 * p - k) // s + 1 for d in din)
+    rng = np.random.default_rng(100 + layer)
+    params = U.bf16(U.init_params(seed=layer + 1))
+    lay, _ = U.param_layout()
+    a0, b0, e0 = lay[name]
+    params[b0:e0] = U.bf16(0.05 * rng.normal(size=e0 - b0))
+    W, b = U.unpack(params)[name]
+    x = U.bf16(rng.normal(size=din + (ci,)))
+    dy = U.bf16(rng.normal(size=dout + (co,)))
+    ctx = ctx_small()
+    ctx.precond_set_weights(params)
+    y, dx, dp = (t.cpu().numpy().astype(np.float64) for t in
+                 ctx.nn_layer_grad(layer, torch.tensor(x.reshape(-1, ci), dtype=torch.float32, device="cuda"),
+                                   torch.tensor(dy.reshape(-1, co), dtype=torch.float32, device="cuda"), box))
+    yo = U.conv(x, W, b, k, s, p) if kind == "conv" else U.up(x, W, b)
+    if act:
+        yo = U.relu(yo)
+    yo = U.bf16(yo)
+    g = dy * (yo > 0) if act else dy
+    if kind == "conv":
+        dxo, dWo, dbo = U.conv_backward(x, W, g, k, s, p)
+    else:
+        dxo, dWo, dbo = U.up_backward(x, W, g)
+    dxo = U.bf16(dxo)
+    dpo = np.concatenate([dWo.ravel(), dbo])
+    ey, ep = rel(y.reshape(yo.shape), yo), rel(dp, dpo)
+    ex = rel(dx.reshape(dxo.shape), dxo) if layer > 0 else 0.0
+    print(f"[nn] layer {name}: y {ey:.2e} dx {ex:.2e} dparams {ep:.2e}", flush=True)
+    assert ey <= 1e-3 and ex <= 1e-3 and ep <= 1e-3, name
 
 
 def test_training_steps_reduce_the_loss():

@@ -304,8 +304,8 @@ def main():
     traffic = {}
     if os.path.exists(args.traffic_json):
         try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == sc.name and tj.get("kernel_version") == ctx_version():
+            tj = json.load(open(args.traffic_json)).get(sc.name, {})
+            if tj.get("kernel_version") == ctx_version():
                 traffic = {"hv": tj.get("bytes_per_hv"), "update": tj.get("bytes_per_update")}
         except Exception:
             traffic = {}

@@ -10,7 +10,8 @@ reads for its ``traffic`` fields and prints the tables kept under profiles/).
 printed).  Each counter is scaled by what it reads for the driver's final
 plain device-to-device copy of known size (FETCH_SIZE and WRITE_SIZE are in
 KiB per dispatch), and the per-launch bytes of the fused Hessian-vector
-product and of the CG update kernel are the medians over their launches.
+product and of the CG update kernel are the medians over their launches;
+OUT_JSON keeps one entry per workload.
 
 ``trace``: the kernel dispatches of a ``rocprofv3 --kernel-trace --stats``
 run (its results database), as a Markdown table of the top kernels.
@@ -65,8 +66,14 @@ def counters(fetch_dir, write_dir, info_json, out_json):
         res[f"bytes_per_{label}"] = round(f + w) if f is not None and w is not None else None
     res.update({k: info[k] for k in ("active_cells", "active_nodes", "free_dofs", "tangent_cells")
                 if k in info})
+    # one entry per workload in OUT_JSON
+    allres = {}
+    if os.path.exists(out_json):
+        with open(out_json) as fh:
+            allres = json.load(fh)
+    allres[res["workload"]] = res
     with open(out_json, "w") as fh:
-        json.dump(res, fh, indent=1)
+        json.dump(allres, fh, indent=1)
     print(json.dumps(res, indent=1))
 
 

@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--vbd-sweeps", type=int, default=4)
     ap.add_argument("--bj-steps", type=int, default=5,
                     help="timed steps of the block-Jacobi leg, after 3 untimed ones (0 = skip the leg)")
+    ap.add_argument("--newton-forcing", type=float, default=0.0,
+                    help="inexact Newton forcing term for the main run (0: every CG to 1e-6)")
+    ap.add_argument("--inexact-forcing", type=float, default=0.1,
+                    help="forcing term of the inexact-Newton leg (0 = skip the leg)")
     ap.add_argument("--learned-steps", type=int, default=2,
                     help="timed steps of the learned-preconditioner leg (0 = skip the leg)")
     ap.add_argument("--learned-train-steps", type=int, default=2,
@@ -233,7 +237,7 @@ def main():
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
                                     pcg_check_every=args.check_every, time_kernels=args.time_kernels,
-                                    warm_start=args.warm_start,
+                                    warm_start=args.warm_start, newton_forcing=args.newton_forcing,
                                     plasticity=(mpmlite.PLASTICITY_FIXED_POINT if args.plasticity == "fixed_point"
                                                 else mpmlite.PLASTICITY_AFTER_SOLVE)))
     parts = mpmlite.particles_to_device(sc.particles)
@@ -339,6 +343,9 @@ def main():
     if not args.no_precision_check:
         final_error = precision_check(sc, parts, ctx, step_idx * sc.dt)
         print(f"[bench] final error {json.dumps(final_error)}", file=sys.stderr, flush=True)
+    inexact = None
+    if args.inexact_forcing > 0.0 and args.newton_forcing == 0.0:
+        inexact = inexact_leg(sc, args, steps_per_s, traj, prec)
     block_jacobi = None
     if args.bj_steps > 0:
         block_jacobi = block_jacobi_leg(ctx, sc, args, steps_per_s, counts, traj)
@@ -368,6 +375,7 @@ def main():
         "dtype": "f32+f64" if prec == mpmlite.F32 else "f64",
         "data": "synthetic",
         "config": {"workload": workload_name(sc), "preconditioner": "jacobi",
+                   "newton_forcing": args.newton_forcing,
                    "active_cells": cells, "active_nodes": nodes,
                    "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
                    "hv_precision": args.precision, "plasticity": args.plasticity},
@@ -375,12 +383,57 @@ def main():
         "hv_kernel": hv_line,
         "final_error": final_error,
         "cpu_baseline": base,
+        "inexact_newton": inexact,
         "block_jacobi": block_jacobi,
         "learned": learned,
         "explicit": explicit,
         "vbd": vbd,
     }
     print(json.dumps(line), flush=True)
+
+
+def inexact_leg(sc, args, plain_steps_per_s, traj, prec):
+    """The same workload from its initial state with inexact Newton
+    (Eisenstat-Walker forcing terms, eta_0 = --inexact-forcing): the early
+    Newton systems are solved loosely, Newton still stops at 1e-6.  The same
+    trajectory steps as the main run are timed (warm starts as in the main
+    run), then one more step is compared with the FP64 variant converged to
+    1e-10 like the main run's final error."""
+    import torch
+    from paper_2602_07853_amd import mpmlite
+    ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                          opts=dict(hv_precision=prec, newton_rtol=1e-6, pcg_rtol=1e-6,
+                                    pcg_check_every=args.check_every, warm_start=args.warm_start,
+                                    newton_forcing=args.inexact_forcing))
+    parts = mpmlite.particles_to_device(sc.particles)
+    newton = pcg = 0
+    host_ms = 0.0
+    t = 0.0
+    el = 0.0
+    for k in range(args.warmup + args.steps):
+        if k == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
+        t += sc.dt
+        if k >= args.warmup:
+            newton += st["newton_iters"]
+            pcg += st["pcg_iters"]
+            host_ms += st["ms_unload"] + st["ms_newton"] + st["ms_load"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = args.steps
+    sps = n / el
+    jp = sum(traj[i][0] for i in range(args.warmup, args.warmup + n)) / n
+    err = precision_check(sc, parts, ctx, t)
+    out = {"newton_forcing": args.inexact_forcing, "steps_per_s": round(sps, 4), "steps": n,
+           "ms_per_step": round(1e3 * el / n, 3), "newton_per_step": round(newton / n, 3),
+           "pcg_per_step": round(pcg / n, 2), "vs_exact_newton": round(sps / plain_steps_per_s, 4),
+           "exact_pcg_per_step": round(jp, 2), "trajectory_steps": [args.warmup, args.warmup + n - 1],
+           "final_error": err["production_f32"]}
+    print(f"[bench] inexact Newton leg {json.dumps(out)}", file=sys.stderr, flush=True)
+    del ctx, parts
+    return out
 
 
 def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untimed=3):

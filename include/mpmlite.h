@@ -133,6 +133,13 @@ typedef struct {
                              (I + dt G_c(v))^{-1} F_E (Sec. 7, Fixed-Point Plasticity); CG then
                              solves for the elastic response only.  Converges linearly, so it
                              needs more Newton iterations */
+  double newton_forcing;  /* 0: every Newton system is solved to pcg_rtol (default).  > 0: inexact
+                             Newton with the forcing terms of Eisenstat and Walker (1996, choice 2):
+                             the CG of Newton iteration k stops at max(pcg_rtol, eta_k) |b| with
+                             eta_0 = newton_forcing, eta_k = min(newton_forcing,
+                             0.9 (|g_k| / |g_{k-1}|)^2), raised to 0.9 eta_{k-1}^2 when that exceeds
+                             0.1, and never below 0.5 newton_rtol |g_0| / |g_k| (no solve tighter than
+                             the Newton tolerance needs).  Newton still stops on newton_rtol */
   int32_t vbd_sweeps;     /* > 0: instead of Newton-PCG, this many sweeps of vertex block descent
                              (Sec. 5, VBD) on the same potential: 8 node colours by index parity;
                              per colour the gradient and the projected FP64 cell tangents are

@@ -325,6 +325,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "plasticity must be MPL_PLASTICITY_AFTER_SOLVE or _FIXED_POINT");
   if (o->vbd_sweeps < 0 || (o->vbd_sweeps > 0 && o->plasticity == MPL_PLASTICITY_FIXED_POINT))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "vbd_sweeps must be >= 0 and is not combined with fixed-point plasticity");
+  if (!(o->newton_forcing >= 0.0 && o->newton_forcing < 1.0))
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "newton_forcing must lie in [0, 1)");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
       o->max_ls < 0 || !(o->armijo_c >= 0.0 && o->armijo_c < 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "solver options out of range");

@@ -2847,11 +2847,28 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   c->up_calls = 0;
   c->graph_replays = 0;
   c->fallbacks_total = 0;
+  double gn_prev = gn, eta_prev = c->opts.newton_forcing;
+  const double pcg_rtol = c->opts.pcg_rtol;
   for (;; ++it) {
     if (gn == 0.0 || gn <= c->opts.newton_rtol * g0) break;
     if (it >= c->opts.max_newton) {
       result = mpl_fail(c, MPL_ERR_NOT_CONVERGED, "Newton iteration cap reached");
       break;
+    }
+    // inexact Newton: forcing term of this iteration (Eisenstat-Walker, choice 2)
+    double rtol_k = pcg_rtol;
+    if (c->opts.newton_forcing > 0.0) {
+      double eta = c->opts.newton_forcing;
+      if (it > 0) {
+        const double q = gn / gn_prev;
+        eta = 0.9 * q * q;
+        const double guard = 0.9 * eta_prev * eta_prev;
+        if (guard > 0.1) eta = std::max(eta, guard);
+        eta = std::min(eta, c->opts.newton_forcing);
+      }
+      eta = std::max(eta, 0.5 * c->opts.newton_rtol * g0 / gn);
+      eta_prev = eta;
+      rtol_k = std::max(pcg_rtol, eta);
     }
     MPL_TRY(mpl_stage_tangent(c, v, c->opts.hv_precision));
     // b = -g
@@ -2913,7 +2930,9 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       // three quarters of the previous step's count for this Newton index
       // are run before the first convergence poll
       c->pcg_expect = it < 8 ? (3 * c->last_pcg[it]) / 4 : 0;
+      c->opts.pcg_rtol = rtol_k;
       const mpl_status pst = mpl_stage_pcg(c, P<double>(c->dir), P<double>(c->x), &iters, &rel, x0);
+      c->opts.pcg_rtol = pcg_rtol;
       c->pcg_expect = 0;
       MPL_TRY(pst);
       if (it < 8) c->last_pcg[it] = iters;
@@ -2960,6 +2979,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     // fixed-point plasticity: re-project at the new iterate before its energy
     if (fixed_point) MPL_TRY(plastic_base(c, v));
     MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    gn_prev = gn;
     gn = std::sqrt(gn2);
     if (!std::isfinite(gn)) {
       result = mpl_fail(c, MPL_ERR_NONFINITE, "gradient is not finite");

@@ -453,3 +453,35 @@ def test_two_contexts_on_two_streams_do_not_interfere():
         for k in ("x", "v", "G", "F"):
             assert np.array_equal(together[i][0][k], alone[i][k]), (i, k)
     assert not np.array_equal(alone[0]["v"], alone[1]["v"])
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_inexact_newton_reaches_the_oracle_minimiser(precision):
+    """Inexact Newton (Eisenstat-Walker forcing terms, newton_forcing = 0.1):
+    the early Newton systems are solved loosely, Newton still stops on its
+    own tolerance, so the solve lands on the oracle's minimiser like the
+    exact one, with fewer CG iterations."""
+    sc = SCENES["fcr_two_materials"]
+    ref = oracle_state(sc)
+    v_or, st_or, rc = O.solve(ref["grid"], ref["mats"], sc.dt, ref["mc"], ref["mi"], ref["vhat"],
+                              ref["fixed"], ref["Vck"], ref["S"], O.SolverOpts(1e-12, 1e-12))
+    assert rc == 0
+    out = {}
+    for forcing in (0.0, 0.1):
+        ctx, parts = run_unload(sc, precision)
+        ctx.set_opts(newton_rtol=1e-11, pcg_rtol=1e-11 if precision == 1 else 1e-6, newton_forcing=forcing)
+        ctx.reconstruct()
+        v, st = ctx.solve()
+        print(f"[parity] precision {precision} forcing {forcing}: newton {st['newton_iters']} "
+              f"pcg {st['pcg_iters']} ({st['pcg_per_newton'][:st['newton_iters']]})", flush=True)
+        assert st["g_norm"] <= 1e-11 * st["g0_norm"]
+        assert rel(host(v), v_or) <= 1e-9
+        out[forcing] = st["pcg_iters"]
+    assert out[0.1] < out[0.0]
+
+
+def test_newton_forcing_out_of_range_rejected():
+    from paper_2602_07853_amd import mpmlite
+    sc = SCENES["fcr_two_materials"]
+    with pytest.raises(mpmlite.MplError):
+        gpu_context(sc, 0, newton_forcing=1.5)

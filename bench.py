@@ -300,7 +300,7 @@ def main():
     # tangent reads 25 values per cell) is given beside them.
     free_dofs = st["free_dofs"]
     elem = 4 if prec == mpmlite.F32 else 8
-    n_tan = int(round((hv_bytes - 6.0 * elem * nodes) / (tan_entries * elem))) if tan_entries else 0
+    n_tan = st["tangent_cells"]
     hv_alg = (45 * elem * n_tan + 7 * elem * nodes)
     up_alg = 15 * elem * free_dofs
     hv_avg_ms = hv_ms / max(hv_calls, 1)
@@ -336,7 +336,7 @@ def main():
                "bytes_model": "180 B per tangent-carrying cell + 28 B per active node (FP32)",
                "tangent_cells": n_tan, "active_nodes": nodes,
                "avg_ms": round(hv_avg_ms, 5), "launches": hv_calls,
-               "design_bytes_per_launch": hv_bytes, "tangent_values_per_cell": tan_entries,
+               "design_bytes_per_launch": hv_bytes, "factored_cells": st["factored_cells"],
                "design_frac": round(gbs(hv_bytes, hv_avg_ms) / HBM_PEAK_GBS, 4)}
     counts = (newton / args.steps, pcg / args.steps, ls / args.steps)
     final_error = None

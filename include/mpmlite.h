@@ -183,9 +183,10 @@ typedef struct {
   int32_t domain_events;  /* stretch reconstructions clamped (model range) */
   int32_t tangent_entries;/* stored tangent values read per cell by one Hv: 45 (dense
                              symmetric 9x9) or 25 (single-material FP32 factored form) */
-  double hv_model_bytes;  /* algorithmic bytes of one Hv: tangent_entries values per
-                             tangent-carrying cell + 2 x 3 values (u read, Hu written) per
-                             active node, in the tangent's precision */
+  double hv_model_bytes;  /* bytes one Hv must move by the library's count: 25 values per
+                             factored cell, 45 per dense tangent-carrying cell, + 2 x 3
+                             values (u read, Hu written) per active node, in the tangent's
+                             precision */
   int32_t pcg_per_newton[8]; /* CG iterations of Newton iterations 0..7 */
   int32_t graph_replays;  /* CG chunks launched from captured HIP graphs (0: all eager) */
   int32_t upd_calls;      /* timed launches of the single-reduction CG update kernel */
@@ -194,6 +195,10 @@ typedef struct {
                              (e = 4 or 8 bytes for the tangent's precision): p, s, Dinv, m,
                              two product pieces and r read, p, s, u, r written, dx every
                              second and x every eighth iteration */
+  int32_t tangent_cells;  /* cells that carry a tangent (some V_{c,k} > 0) */
+  int32_t factored_cells; /* of those, cells stored in the factored FP32 layout (25 values read
+                             per product): all with one material, with several materials the
+                             cells of blocks where no cell holds two materials */
 } mpl_stats;
 
 typedef struct mpl_ctx mpl_ctx;

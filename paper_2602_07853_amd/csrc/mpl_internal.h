@@ -71,6 +71,7 @@ struct SolverScalars {
   int32_t n_cblk, n_nblk;
   int32_t n_active_cells, n_active_nodes, n_free_nodes;
   int32_t n_tan_cells;  // cells that carry a tangent (some V_{c,k} != 0)
+  int32_t n_fact_cells; // cells stored in the factored layout (several materials: per-block choice)
 };
 
 // FP64 view of the boundary's particle arrays (the kernels' layout).
@@ -105,6 +106,7 @@ struct mpl_ctx {
   bool unloaded = false, reconstructed = false, tangent_built = false, solved = false;
   int tangent_precision = MPL_F32;
   bool tan_factored = false;     // the stored FP32 tangent is in factored form
+  bool tan_mixed = false;        // several materials in FP32: factored or dense per cell block (cfmt)
   bool factored_enabled = true;  // MPL_DENSE_TANGENT=1 in the environment turns it off
   double dt = 0.0;
   int64_t np = 0;
@@ -121,6 +123,7 @@ struct mpl_ctx {
   DevBuf cmask, ccnt, coff;
   DevBuf p2c_halo;  // particle -> centre scatter: per-block halo staging
   DevBuf pstage;    // FP64 staging of single-precision particle arrays
+  DevBuf cfmt, fcnt; // per cell block: tangent layout (1 factored) and its factored-cell count
   // node fields
   // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
   // (read by the CG vector kernels)

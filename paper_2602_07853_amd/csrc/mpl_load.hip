@@ -203,16 +203,25 @@ __global__ void k_export_abar64(const double* __restrict__ Ab, const uint64_t* _
 // Factored FP32 tangent -> dense 9x9: column c is the factored product
 // applied to the unit velocity gradient e_c (FP64 arithmetic on the stored
 // FP32 factors).
+// With several materials (cfmt given) the blocks use 45 slots per cell and
+// a dense block (cfmt 0) is exported as stored.
 __global__ void k_export_abar_fact(const float* __restrict__ Ab, const uint64_t* __restrict__ cmask,
                                    const int32_t* __restrict__ coff, const int4* __restrict__ ccoord,
-                                   int n_cblk, int nx, int ny, int nz, double* __restrict__ dense) {
+                                   int n_cblk, int nx, int ny, int nz, double* __restrict__ dense,
+                                   const uint8_t* __restrict__ cfmt) {
   const int b = blockIdx.x, l = threadIdx.x;
   if (b >= n_cblk) return;
   const int4 bc = ccoord[b];
   const int i0 = bc.x * 4 + local_x(l), j0 = bc.y * 4 + local_y(l), k0 = bc.z * 4 + local_z(l);
   const int64_t di = ((int64_t)i0 * ny + j0) * nz + k0;
-  const TanSlot ts = tan_slot(cmask, coff, b, l, MPL_TAN_FACT);
+  const TanSlot ts = tan_slot(cmask, coff, b, l, cfmt ? MPL_TAN_DENSE : MPL_TAN_FACT);
   if (!ts.active) return;
+  if (cfmt && cfmt[b] == 0) {
+    for (int r = 0; r < 9; ++r)
+      for (int c2 = 0; c2 < 9; ++c2)
+        dense[di * 81 + r * 9 + c2] = (double)Ab[ts.base + (int64_t)sym9(r, c2) * ts.n + ts.rank];
+    return;
+  }
   double f[MPL_TAN_FACT_READ];
   for (int e = 0; e < MPL_TAN_FACT_READ; ++e) f[e] = (double)Ab[ts.base + (int64_t)e * ts.n + ts.rank];
   double U[9];
@@ -375,8 +384,12 @@ mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, dou
   st.domain_events = c->hscal.domain_count;
   {
     const int elem = c->tangent_precision == MPL_F32 ? 4 : 8;
+    const int32_t nfact = c->tan_factored ? c->hscal.n_tan_cells : (c->tan_mixed ? c->hscal.n_fact_cells : 0);
     st.tangent_entries = c->tan_factored ? MPL_TAN_FACT_READ : MPL_TAN_DENSE;
-    st.hv_model_bytes = (double)st.tangent_entries * elem * c->hscal.n_tan_cells +
+    st.tangent_cells = c->hscal.n_tan_cells;
+    st.factored_cells = nfact;
+    st.hv_model_bytes = (double)elem * (MPL_TAN_FACT_READ * (double)nfact +
+                                        MPL_TAN_DENSE * (double)(c->hscal.n_tan_cells - nfact)) +
                         6.0 * elem * c->hscal.n_active_nodes;
   }
   st.ms_unload = t1 - t0;
@@ -434,9 +447,10 @@ mpl_status mpl_export_field(mpl_ctx* c, int32_t field, double* dense) {
     case MPL_FIELD_ABAR:
       if (!c->tangent_built) return mpl_fail(c, MPL_ERR_STATE, "tangent not built");
       MPL_TRY(zero(81 * ncd));
-      if (c->tangent_precision == MPL_F32 && c->tan_factored)
+      if (c->tangent_precision == MPL_F32 && (c->tan_factored || c->tan_mixed))
         MPL_LAUNCH(c, k_export_abar_fact, c->n_cblk, 64, P<float>(c->Abar32), P<uint64_t>(c->cmask),
-                   P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);
+                   P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense,
+                   c->tan_mixed ? (const uint8_t*)P<uint8_t>(c->cfmt) : (const uint8_t*)nullptr);
       else if (c->tangent_precision == MPL_F32)
         MPL_LAUNCH(c, k_export_abar32, c->n_cblk, 64, P<float>(c->Abar32), P<uint64_t>(c->cmask),
                    P<int32_t>(c->coff), cc, c->n_cblk, nx, ny, nz, dense);

@@ -359,7 +359,7 @@ __global__ void k_set_tol(SolverScalars* s, double rtol2) { s->tol2 = rtol2 * s-
 // (scaling) or a twist/flip pair, so vec(E S) = vec(U e M^T) with M = S V,
 // and the cell stores U, M, the projected scaling block and the pair
 // coefficients (the layout before MPL_TAN_FACT) instead of the 45 entries.
-template <class T, bool FACT>
+template <class T, bool FACT, bool MIX>
 __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, int64_t nnode,
                                                 const int* __restrict__ c_nbr_node,
                                                 const double* __restrict__ Vk,
@@ -369,9 +369,12 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
                                                 const uint64_t* __restrict__ cmask,
                                                 const int32_t* __restrict__ coff,
                                                 T* __restrict__ Abar, int32_t* __restrict__ err,
-    const MatParams* __restrict__ mats, T* __restrict__ Aoff) {
+    const MatParams* __restrict__ mats, T* __restrict__ Aoff, const uint8_t* __restrict__ cfmt) {
   const int cb = blockIdx.x, l = threadIdx.x;
   const int64_t ci = (int64_t)cb * MPL_BC + l;
+  // factored layout for this block: always (FACT), per block (MIX: blocks
+  // whose cells hold at most one material each), or never
+  const bool fb = FACT || (MIX && cfmt[cb] != 0);
   const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
   if (!ts.active) return;
   double Ab[45];
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       double Hs[9] = {H[0][0], H[0][1], H[0][2], H[1][0], H[1][1], H[1][2], H[2][0], H[2][1], H[2][2]};
       double w[3], Qm[9];
       eig_sym3(Hs, w, Qm);
-      if (FACT) {
+      if (fb) {
         double M[9];
         mul(S, Vm, M);
         rot_to_quat(U, fac);
@@ -463,7 +466,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
       }
     }
   }
-  if (FACT) {
+  if (fb) {
 #pragma unroll
     for (int i = 0; i < MPL_TAN_FACT_READ; ++i) Abar[ts.base + (int64_t)i * ts.n + ts.rank] = (T)fac[i];
     // node-block contributions Q_e(s) = sum_{b,b'} Abar[(a,b),(a',b')]
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(64) void k_tangent(const double* __restrict__ v, in
 
 // Inverse Jacobi diagonal of H at every node, 1 / (m_i + sum_c sum_{b,b'}
 // Abar[(a,b),(a,b')] gw_b gw_b'), and 0 on fixed / massless nodes.
-template <class T, bool FACT>
+template <class T, bool FACT, bool MIX>
 __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
                                              const uint64_t* __restrict__ cmask,
                                              const int32_t* __restrict__ coff,
@@ -508,7 +511,8 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
                                              const uint8_t* __restrict__ flags,
                                              const int* __restrict__ n_nbr_cell, int64_t nnode,
                                              double inv4dx, double* __restrict__ D,
-                                             T* __restrict__ Dt, T* __restrict__ mt) {
+                                             T* __restrict__ Dt, T* __restrict__ mt,
+                                             const uint8_t* __restrict__ cfmt) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double dd[3] = {0.0, 0.0, 0.0};
@@ -519,7 +523,7 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
       if (ci < 0) continue;
       const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
       if (!ts.active) continue;
-      if (FACT) {
+      if (FACT || (MIX && cfmt[ci >> 6] != 0)) {
         // sign pattern of the node as corner d of that cell, canonical sx = +1
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
         const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
@@ -560,7 +564,7 @@ __host__ __device__ constexpr int blk_b(int e) { return e < 3 ? e : (e == 5 ? 2 
 // and in the tangent's precision (Bt); 0 on fixed and massless nodes.  The
 // block is m I plus a positive semidefinite sum, so it is invertible
 // whenever m > 0; the inverse is the adjugate over the determinant.
-template <class T, bool FACT>
+template <class T, bool FACT, bool MIX>
 __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
                                                    const uint64_t* __restrict__ cmask,
                                                    const int32_t* __restrict__ coff,
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
                                                    const int* __restrict__ n_nbr_cell, int64_t nnode,
                                                    double inv4dx, double* __restrict__ B,
                                                    T* __restrict__ Bt, const T* __restrict__ Aoff,
-                                                   int32_t* __restrict__ err) {
+                                                   int32_t* __restrict__ err, const uint8_t* __restrict__ cfmt) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
       if (ci < 0) continue;
       const TanSlot ts = tan_slot(cmask, coff, ci >> 6, ci & 63, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
       if (!ts.active) continue;
-      if (FACT) {
+      if (FACT || (MIX && cfmt[ci >> 6] != 0)) {
         const int dx = (d >> 2) & 1, dy = (d >> 1) & 1, dz = d & 1;
         const int sy = dx ? (dy ? 0 : 1) : (dy ? 1 : 0), sz = dx ? (dz ? 0 : 1) : (dz ? 1 : 0);
         const int sidx = sy * 2 + sz;
@@ -693,7 +697,7 @@ __global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Aba
 // Workgroups are mapped XCD-major (xcd_block: consecutive blocks on one XCD)
 // so that neighbouring blocks share p tile lines in the same L2.
 
-template <class T, bool DOT, bool FACT>
+template <class T, bool DOT, bool FACT, bool MIX>
 __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64_t nnode,
                                                  const int* __restrict__ c_nbr_node,
                                                  const T* __restrict__ Abar,
@@ -702,7 +706,8 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
                                                  int n_cblk, T inv4dx, T* __restrict__ Hown,
                                                  T* __restrict__ Hhalo,
                                                  double* __restrict__ partial,
-                                                 const SolverScalars* __restrict__ s) {
+                                                 const SolverScalars* __restrict__ s,
+                                                 const uint8_t* __restrict__ cfmt) {
   if (s && done_flag(s)) return;
   // four cell blocks per workgroup, one per wavefront
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -750,7 +755,8 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
     const TanSlot ts = tan_slot(cmask, coff, cb, l, FACT ? MPL_TAN_FACT : MPL_TAN_DENSE);
     if (ts.active) {
       const T* A = Abar + ts.base + ts.rank;
-      if (FACT) {
+      // wave-uniform: one cell block per wavefront
+      if (FACT || (MIX && cfmt[cb] != 0)) {
         T U[9], M[9], A3[6], pc[6];
         quat_to_rot<T>(A[0], A[ts.n], A[2 * (int64_t)ts.n], A[3 * (int64_t)ts.n], U);
 #pragma unroll
@@ -1840,6 +1846,42 @@ mpl_status mpl_stage_energy(mpl_ctx* c, const double* v, bool want_grad, double*
   return MPL_OK;
 }
 
+// Tangent layout per cell block for several materials in FP32: factored
+// (1) when every cell of the block holds at most one material (V_{c,k} > 0 for
+// at most one k), dense (0) otherwise; part[cb] = the block's factored cells.
+__global__ __launch_bounds__(64) void k_tan_format(const double* __restrict__ Vk, int64_t ncell, int K,
+                                                   const uint64_t* __restrict__ cmask,
+                                                   uint8_t* __restrict__ cfmt, int32_t* __restrict__ part) {
+  const int cb = blockIdx.x, l = threadIdx.x;
+  const int64_t ci = (int64_t)cb * MPL_BC + l;
+  const uint64_t m = cmask[cb];
+  int cnt = 0;
+  if ((m >> l) & 1ull)
+    for (int k = 0; k < K; ++k) cnt += Vk[k * ncell + ci] != 0.0 ? 1 : 0;
+  const bool fact = !__any(cnt > 1);
+  if (l == 0) {
+    cfmt[cb] = fact ? 1 : 0;
+    part[cb] = fact ? __popcll(m) : 0;
+  }
+}
+
+// Sum of n int32 values by one workgroup in a fixed order into *out.
+__global__ __launch_bounds__(1024) void k_sum_i32(const int32_t* __restrict__ a, int n, int32_t* __restrict__ out) {
+  __shared__ int32_t sh[16];
+  const int t = threadIdx.x;
+  int32_t acc = 0;
+  for (int i = t; i < n; i += 1024) acc += a[i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((t & 63) == 0) sh[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    int32_t s = 0;
+    for (int k = 0; k < 16; ++k) s += sh[k];
+    *out = s;
+  }
+}
+
 mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "tangent before reconstruction");
   MPL_TRY(upload_mats(c));
@@ -1849,63 +1891,82 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
   const int64_t ntan = (int64_t)c->hscal.n_tan_cells + 64;
   const uint64_t* cm = P<uint64_t>(c->cmask);
   const int32_t* co = P<int32_t>(c->coff);
-  // the single-material FP32 tangent is stored factored (37 entries per
-  // cell, 25 of them read by the Hessian-vector product, 12 Jacobi-diagonal
-  // sums); with block-Jacobi its 12 off-diagonal node-block sums per cell go
-  // to Aoff
-  const bool fact = precision == MPL_F32 && c->nmat == 1 && c->factored_enabled;
+  // FP32 layouts: with one material the tangent is stored factored (37
+  // entries per cell, 25 of them read by the Hessian-vector product, 12
+  // Jacobi-diagonal sums); with several materials each cell block is
+  // factored when none of its cells holds two materials, dense (45 entries)
+  // otherwise, in blocks of 45 slots per cell.  With block-Jacobi the
+  // factored cells' 12 off-diagonal node-block sums go to Aoff.
+  const bool fp32 = precision == MPL_F32 && c->factored_enabled;
+  const bool fact = fp32 && c->nmat == 1;
+  const bool mixed = fp32 && c->nmat > 1;
   const bool bj = c->opts.precond == MPL_PRECOND_BLOCK_JACOBI;
   c->tan_factored = fact;
-  if (fact && bj) MPL_TRY(mpl_ensure(c, c->Aoff, 4 * MPL_TAN_OFF * ntan));
-  float* aoff = fact && bj ? P<float>(c->Aoff) : nullptr;
+  c->tan_mixed = mixed;
+  const uint8_t* fmt = nullptr;
+  if (mixed) {
+    MPL_TRY(mpl_ensure(c, c->cfmt, (size_t)c->n_cblk + 64));
+    MPL_TRY(mpl_ensure(c, c->fcnt, 4 * ((size_t)c->n_cblk + 64)));
+    MPL_LAUNCH(c, k_tan_format, c->n_cblk, 64, P<double>(c->Vk), ncell, c->nmat, cm, P<uint8_t>(c->cfmt),
+               P<int32_t>(c->fcnt));
+    MPL_LAUNCH(c, k_sum_i32, 1, 1024, P<int32_t>(c->fcnt), c->n_cblk, &c->dscal()->n_fact_cells);
+    fmt = P<uint8_t>(c->cfmt);
+  }
+  if ((fact || mixed) && bj) MPL_TRY(mpl_ensure(c, c->Aoff, 4 * MPL_TAN_OFF * ntan));
+  float* aoff = (fact || mixed) && bj ? P<float>(c->Aoff) : nullptr;
   if (precision == MPL_F32) {
     MPL_TRY(mpl_ensure(c, c->Abar32, 4 * (fact ? MPL_TAN_FACT : MPL_TAN_DENSE) * ntan));
     MPL_TRY(mpl_ensure(c, c->Dt, 4 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 4 * nnode));
+#define MPL_TAN_LAUNCH(FA, MI, AO)                                                                    \
+  MPL_LAUNCH(c, (k_tangent<float, FA, MI>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),           \
+             P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,     \
+             P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf), AO, fmt);               \
+  MPL_LAUNCH(c, (k_diag<float, FA, MI>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi), \
+             P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),            \
+             P<float>(c->Dt), P<float>(c->mt), fmt)
     if (fact) {
-      MPL_LAUNCH(c, (k_tangent<float, true>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-                 P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf), aoff);
-      MPL_LAUNCH(c, (k_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
-                 P<float>(c->Dt), P<float>(c->mt));
+      MPL_TAN_LAUNCH(true, false, aoff);
+    } else if (mixed) {
+      MPL_TAN_LAUNCH(false, true, aoff);
     } else {
-      MPL_LAUNCH(c, (k_tangent<float, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
-                 P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-                 P<float>(c->Abar32), &c->dscal()->err, P<MatParams>(c->matbuf), (float*)nullptr);
-      MPL_LAUNCH(c, (k_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                 P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
-                 P<float>(c->Dt), P<float>(c->mt));
+      MPL_TAN_LAUNCH(false, false, (float*)nullptr);
     }
+#undef MPL_TAN_LAUNCH
   } else {
     MPL_TRY(mpl_ensure(c, c->Abar64, 8 * MPL_TAN_DENSE * ntan));
-    MPL_LAUNCH(c, (k_tangent<double, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
+    MPL_LAUNCH(c, (k_tangent<double, false, false>), c->n_cblk, 64, v, nnode, P<int>(c->c_nbr_node),
                P<double>(c->Vk), P<double>(c->Sk), sgen(c), ncell, c->nmat, c->dt, inv4dx, cm, co,
-               P<double>(c->Abar64), &c->dscal()->err, P<MatParams>(c->matbuf), (double*)nullptr);
+               P<double>(c->Abar64), &c->dscal()->err, P<MatParams>(c->matbuf), (double*)nullptr,
+               (const uint8_t*)nullptr);
     MPL_TRY(mpl_ensure(c, c->Dt, 8 * 3 * nnode));
     MPL_TRY(mpl_ensure(c, c->mt, 8 * nnode));
-    MPL_LAUNCH(c, (k_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
+    MPL_LAUNCH(c, (k_diag<double, false, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
                P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->D),
-               P<double>(c->Dt), P<double>(c->mt));
+               P<double>(c->Dt), P<double>(c->mt), (const uint8_t*)nullptr);
   }
   c->bj_built = false;
   if (bj) {
     MPL_TRY(mpl_ensure(c, c->Bj, 8 * 6 * nnode));
     if (precision == MPL_F32) {
       MPL_TRY(mpl_ensure(c, c->Bjt, 4 * 6 * nnode));
-      if (fact)
-        MPL_LAUNCH(c, (k_block_diag<float, true>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)aoff,
-                   &c->dscal()->err);
-      else
-        MPL_LAUNCH(c, (k_block_diag<float, false>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi),
-                   P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), (const float*)nullptr,
-                   &c->dscal()->err);
+#define MPL_BJ_LAUNCH(FA, MI, AO)                                                                        \
+  MPL_LAUNCH(c, (k_block_diag<float, FA, MI>), c->n_nblk, 64, P<float>(c->Abar32), cm, co, P<double>(c->mi), \
+             P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<float>(c->Bjt), \
+             (const float*)AO, &c->dscal()->err, fmt)
+      if (fact) {
+        MPL_BJ_LAUNCH(true, false, aoff);
+      } else if (mixed) {
+        MPL_BJ_LAUNCH(false, true, aoff);
+      } else {
+        MPL_BJ_LAUNCH(false, false, nullptr);
+      }
+#undef MPL_BJ_LAUNCH
     } else {
       MPL_TRY(mpl_ensure(c, c->Bjt, 8 * 6 * nnode));
-      MPL_LAUNCH(c, (k_block_diag<double, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
+      MPL_LAUNCH(c, (k_block_diag<double, false, false>), c->n_nblk, 64, P<double>(c->Abar64), cm, co, P<double>(c->mi),
                  P<uint8_t>(c->flags), P<int>(c->n_nbr_cell), nnode, inv4dx, P<double>(c->Bj), P<double>(c->Bjt), (const double*)nullptr,
-                 &c->dscal()->err);
+                 &c->dscal()->err, (const uint8_t*)nullptr);
     }
     // the node blocks are read by every CG iteration: check them once here
     MPL_TRY(mpl_sync_scalars(c));
@@ -1979,15 +2040,18 @@ static mpl_status hv_pieces(mpl_ctx* c, const T* p, bool dot, T* out = nullptr) 
   }
   const T inv4 = (T)(0.25 * c->inv_dx);
   const int grid = (((c->n_cblk + 3) / 4 + 7) / 8) * 8;
-#define MPL_HV_LAUNCH(DOT, FACT, PART, SCAL)                                                       \
-  MPL_LAUNCH(c, (k_hv_fused<T, DOT, FACT>), grid, 256, p, nnode, P<int>(c->c_nbr_node),          \
+#define MPL_HV_LAUNCH(DOT, FACT, MIX, PART, SCAL)                                                       \
+  MPL_LAUNCH(c, (k_hv_fused<T, DOT, FACT, MIX>), grid, 256, p, nnode, P<int>(c->c_nbr_node),     \
              P<T>(abar_buf<T>(c)), P<uint64_t>(c->cmask), P<int32_t>(c->coff), ncell, c->n_cblk, inv4, \
-             Hown, Hhalo, PART, SCAL)
+             Hown, Hhalo, PART, SCAL, (const uint8_t*)(MIX ? c->cfmt.p : nullptr))
   const bool fact = c->tan_factored;
-  if (dot && fact) MPL_HV_LAUNCH(true, true, partial_slot(c, 0), (const SolverScalars*)c->dscal());
-  else if (dot) MPL_HV_LAUNCH(true, false, partial_slot(c, 0), (const SolverScalars*)c->dscal());
-  else if (fact) MPL_HV_LAUNCH(false, true, (double*)nullptr, (const SolverScalars*)nullptr);
-  else MPL_HV_LAUNCH(false, false, (double*)nullptr, (const SolverScalars*)nullptr);
+  const bool mixed = c->tan_mixed && sizeof(T) == 4;
+  if (dot && fact) MPL_HV_LAUNCH(true, true, false, partial_slot(c, 0), (const SolverScalars*)c->dscal());
+  else if (dot && mixed) MPL_HV_LAUNCH(true, false, true, partial_slot(c, 0), (const SolverScalars*)c->dscal());
+  else if (dot) MPL_HV_LAUNCH(true, false, false, partial_slot(c, 0), (const SolverScalars*)c->dscal());
+  else if (fact) MPL_HV_LAUNCH(false, true, false, (double*)nullptr, (const SolverScalars*)nullptr);
+  else if (mixed) MPL_HV_LAUNCH(false, false, true, (double*)nullptr, (const SolverScalars*)nullptr);
+  else MPL_HV_LAUNCH(false, false, false, (double*)nullptr, (const SolverScalars*)nullptr);
 #undef MPL_HV_LAUNCH
   if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
   return MPL_OK;
@@ -2225,7 +2289,7 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                            c->cmask.p,  c->coff.p,   u,               sv,
                            dx};
-    const int keyn[8] = {c->n_cblk, c->n_nblk, check, (int)bj, 0, 0, (int)c->tan_factored, 2};
+    const int keyn[8] = {c->n_cblk, c->n_nblk, check, (int)bj, 0, 0, (int)c->tan_factored + 2 * (int)c->tan_mixed, 2};
     // a hook that reads x sees the full solution vector (flushing changes
     // the rounding of x, so it is done only for such hooks)
     std::function<mpl_status(int)> flushed_hook;
@@ -2264,7 +2328,7 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                          abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                          c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                          c->cmask.p,  c->coff.p};
-  const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored, 0};
+  const int keyn[8] = {c->n_cblk, c->n_nblk, check, 0, 0, 0, (int)c->tan_factored + 2 * (int)c->tan_mixed, 0};
   MPL_TRY(run_chunks(c, c->pcg_cache[0], key, keyn, check, launch_iteration, hook));
   if (iters) *iters = c->hscal.iters;
   if (rel) *rel = c->hscal.bnorm2 > 0.0 ? std::sqrt(c->hscal.rr / c->hscal.bnorm2) : 0.0;
@@ -2343,7 +2407,7 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
                            q,           nn.act.p,    nn.wsw.p,        c->ncoord.p,
                            c->cmask.p,  c->coff.p,   nn.params.p,     c->nmap.p,
                            c->Dt.p,     c->mt.p};
-    const int keyn[8] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2], (int)c->tan_factored, 1};
+    const int keyn[8] = {c->n_cblk, c->n_nblk, check, nn.box[0], nn.box[1], nn.box[2], (int)c->tan_factored + 2 * (int)c->tan_mixed, 1};
     st = run_chunks(c, c->pcg_cache[1], key, keyn, check, launch_iteration, hook);
   }
   nn.skip = nullptr;

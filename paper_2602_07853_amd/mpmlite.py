@@ -77,7 +77,7 @@ class _Stats(C.Structure):
                 ("domain_events", C.c_int32), ("tangent_entries", C.c_int32),
                 ("hv_model_bytes", C.c_double), ("pcg_per_newton", C.c_int32 * 8),
                 ("graph_replays", C.c_int32), ("upd_calls", C.c_int32), ("upd_ms_total", C.c_double),
-                ("upd_model_bytes", C.c_double)]
+                ("upd_model_bytes", C.c_double), ("tangent_cells", C.c_int32), ("factored_cells", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)

@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--plasticity", choices=["after_solve", "fixed_point"], default="after_solve",
                     help="plastic projection on the particles after the solve, or in addition the "
                          "fixed point inside Newton")
+    ap.add_argument("--plastic-anderson", type=int, default=0,
+                    help="Anderson depth of the fixed-point plasticity iteration (0 = plain)")
     ap.add_argument("--vbd-steps", type=int, default=10,
                     help="timed steps of the VBD-vs-Newton-PCG leg (two-material bar, 64^3); 0 = skip")
     ap.add_argument("--vbd-sweeps", type=int, default=4)
@@ -239,7 +241,8 @@ def main():
                                     pcg_check_every=args.check_every, time_kernels=args.time_kernels,
                                     warm_start=args.warm_start, newton_forcing=args.newton_forcing,
                                     plasticity=(mpmlite.PLASTICITY_FIXED_POINT if args.plasticity == "fixed_point"
-                                                else mpmlite.PLASTICITY_AFTER_SOLVE)))
+                                                else mpmlite.PLASTICITY_AFTER_SOLVE),
+                                    plastic_anderson=args.plastic_anderson))
     parts = mpmlite.particles_to_device(sc.particles)
     print(f"[bench] {workload_name(sc)}", file=sys.stderr, flush=True)
     step_idx = 0
@@ -378,7 +381,8 @@ def main():
                    "newton_forcing": args.newton_forcing,
                    "active_cells": cells, "active_nodes": nodes,
                    "newton_per_step": round(counts[0], 3), "pcg_per_step": round(counts[1], 2),
-                   "hv_precision": args.precision, "plasticity": args.plasticity},
+                   "hv_precision": args.precision, "plasticity": args.plasticity,
+                   "plastic_anderson": args.plastic_anderson},
         "roofline": roof,
         "hv_kernel": hv_line,
         "final_error": final_error,

@@ -133,6 +133,13 @@ typedef struct {
                              (I + dt G_c(v))^{-1} F_E (Sec. 7, Fixed-Point Plasticity); CG then
                              solves for the elastic response only.  Converges linearly, so it
                              needs more Newton iterations */
+  int32_t plastic_anderson;/* with MPL_PLASTICITY_FIXED_POINT: 0 plain fixed point (default); m in
+                             1..4: Anderson acceleration of the iterates v_k with the last m + 1
+                             Newton updates f_k = v_{k+1} - v_k (after the line search): v_{k+1} =
+                             v_k + f_k - sum_j gamma_j (dv_j + df_j), gamma the least-squares fit of
+                             f_k by the differences df_j; the accelerated iterate is taken when its
+                             gradient (with its own plastic base) is finite and smaller than at v_k,
+                             else the plain update, and the history restarts */
   double newton_forcing;  /* 0: every Newton system is solved to pcg_rtol (default).  > 0: inexact
                              Newton with the forcing terms of Eisenstat and Walker (1996, choice 2):
                              the CG of Newton iteration k stops at max(pcg_rtol, eta_k) |b| with

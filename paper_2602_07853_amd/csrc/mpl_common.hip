@@ -325,6 +325,8 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "plasticity must be MPL_PLASTICITY_AFTER_SOLVE or _FIXED_POINT");
   if (o->vbd_sweeps < 0 || (o->vbd_sweeps > 0 && o->plasticity == MPL_PLASTICITY_FIXED_POINT))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "vbd_sweeps must be >= 0 and is not combined with fixed-point plasticity");
+  if (o->plastic_anderson < 0 || o->plastic_anderson > 4)
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "plastic_anderson must lie in 0..4");
   if (!(o->newton_forcing >= 0.0 && o->newton_forcing < 1.0))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "newton_forcing must lie in [0, 1)");
   if (!(o->newton_rtol > 0.0) || !(o->pcg_rtol > 0.0) || o->max_newton < 0 || o->max_pcg < 1 ||
@@ -408,7 +410,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->Bj, &c->Bjt, &c->Aoff, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->pstage, &c->cfmt, &c->fcnt, &c->wtmp, &c->warm_x0, &c->gal_w,
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->pstage, &c->cfmt, &c->fcnt, &c->aa_tmp, &c->aa_part, &c->wtmp, &c->warm_x0, &c->gal_w,
                    &c->gal_u, &c->gal_y,
                    &c->gal_part};
   for (DevBuf* b : all) free_buf(c, *b);
@@ -421,6 +423,8 @@ void mpl_destroy(mpl_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (auto& ring : c->whist)
     for (DevBuf& b : ring) free_buf(c, b);
+  for (DevBuf& b : c->aa_v) free_buf(c, b);
+  for (DevBuf& b : c->aa_f) free_buf(c, b);
   for (hipEvent_t e : c->hv_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->up_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->cap_order)

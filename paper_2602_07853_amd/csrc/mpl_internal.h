@@ -124,6 +124,11 @@ struct mpl_ctx {
   DevBuf p2c_halo;  // particle -> centre scatter: per-block halo staging
   DevBuf pstage;    // FP64 staging of single-precision particle arrays
   DevBuf cfmt, fcnt; // per cell block: tangent layout (1 factored) and its factored-cell count
+  // Anderson acceleration of fixed-point plasticity: the last iterates v and
+  // Newton updates f (block layout, FP64), oldest first
+  static constexpr int kAA = 5;
+  DevBuf aa_v[kAA], aa_f[kAA], aa_tmp, aa_part;
+  int aa_n = 0;
   // node fields
   // Dt, mt: inverse Jacobi diagonal and mass in the tangent's precision
   // (read by the CG vector kernels)

@@ -1785,6 +1785,73 @@ static double* partial_slot(mpl_ctx* c, int k) {
 static const double* sgen(mpl_ctx* c) { return c->s_general ? P<double>(c->Seff) : nullptr; }
 
 // Fixed-point plasticity: the base at the node velocity v (block layout).
+// ---- Anderson acceleration of fixed-point plasticity ----
+struct AAVecs {
+  const double* p[10];
+};
+struct AACoef {
+  double a[10];
+};
+
+// v_hist = v, f_hist = vt - v (the accepted Newton update), all slots.
+__global__ void k_aa_push(const double* __restrict__ v, const double* __restrict__ vt,
+                          double* __restrict__ vh, double* __restrict__ fh, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  vh[i] = v[i];
+  fh[i] = vt[i] - v[i];
+}
+
+// Partial dot products f_i . f_j (i <= j < nv) over free DOFs, one partial per
+// workgroup of four node blocks: part[pair * nwg + wg].
+__global__ __launch_bounds__(256) void k_aa_gram(AAVecs f, int nv, const uint8_t* __restrict__ flags,
+                                                 int64_t nnode, int n_nblk, double* __restrict__ part, int nwg) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  const int64_t ni = (int64_t)nb * MPL_BC + l;
+  const bool fr = nb < n_nblk && (flags[ni] & MPL_NODE_FREE);
+  double x[5][3];
+  for (int k = 0; k < nv; ++k)
+    for (int a = 0; a < 3; ++a) x[k][a] = fr ? f.p[k][a * nnode + ni] : 0.0;
+  int pair = 0;
+  for (int i = 0; i < nv; ++i)
+    for (int j = i; j < nv; ++j, ++pair) {
+      double d = x[i][0] * x[j][0] + x[i][1] * x[j][1] + x[i][2] * x[j][2];
+      d = block4_sum(d, sh);
+      if (threadIdx.x == 0) part[(int64_t)pair * nwg + blockIdx.x] = d;
+      __syncthreads();
+    }
+}
+
+// out[pair] = sum of that pair's partials, fixed order, one workgroup.
+__global__ __launch_bounds__(1024) void k_aa_reduce(const double* __restrict__ part, int npair, int nwg,
+                                                    double* __restrict__ out) {
+  __shared__ double sh[16];
+  const int t = threadIdx.x;
+  for (int p = 0; p < npair; ++p) {
+    double acc = 0.0;
+    for (int i = t; i < nwg; i += 1024) acc += part[(int64_t)p * nwg + i];
+    acc = wave_sum(acc);
+    if ((t & 63) == 0) sh[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+      double s2 = 0.0;
+      for (int w = 0; w < 16; ++w) s2 += sh[w];
+      out[p] = s2;
+    }
+    __syncthreads();
+  }
+}
+
+// out = sum_k coef_k vec_k over all slots.
+__global__ void k_aa_combine(AAVecs vec, AACoef coef, int nv, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s2 = 0.0;
+  for (int k = 0; k < nv; ++k) s2 += coef.a[k] * vec.p[k][i];
+  out[i] = s2;
+}
+
 static mpl_status plastic_base(mpl_ctx* c, const double* v) {
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
   MPL_TRY(upload_mats(c));
@@ -2850,6 +2917,119 @@ static mpl_status galerkin_start(mpl_ctx* c, const DevBuf* const* hist, int nv, 
   return MPL_OK;
 }
 
+// One Anderson step of the fixed-point plasticity iteration (see the
+// plastic_anderson option): history push, least-squares fit, candidate
+// iterate in aa_tmp with its plastic base, energy and gradient (in c->g).
+// *accepted tells whether the candidate is taken; when it is not, the
+// history restarts from the pair just pushed.
+static mpl_status anderson_step(mpl_ctx* c, const double* v, const double* vt, double gn_k, bool* accepted,
+                                double* E_out, double* gn2_out) {
+  *accepted = false;
+  const int m = c->opts.plastic_anderson;
+  const int64_t nnode = (int64_t)c->nnode_alloc();
+  const int64_t n3 = 3 * nnode;
+  // push: drop the oldest pair when m + 1 are stored
+  if (c->aa_n == m + 1) {
+    DevBuf v0 = c->aa_v[0], f0 = c->aa_f[0];
+    for (int k = 0; k < m; ++k) {
+      c->aa_v[k] = c->aa_v[k + 1];
+      c->aa_f[k] = c->aa_f[k + 1];
+    }
+    c->aa_v[m] = v0;
+    c->aa_f[m] = f0;
+    c->aa_n = m;
+  }
+  const int slot = c->aa_n;
+  MPL_TRY(mpl_ensure(c, c->aa_v[slot], 8 * n3));
+  MPL_TRY(mpl_ensure(c, c->aa_f[slot], 8 * n3));
+  MPL_LAUNCH(c, k_aa_push, (int)((n3 + 255) / 256), 256, v, vt, P<double>(c->aa_v[slot]), P<double>(c->aa_f[slot]), n3);
+  c->aa_n += 1;
+  const int nv = c->aa_n;
+  if (nv < 2) return MPL_OK;
+  // Gram matrix of the stored updates
+  const int nwg = (c->n_nblk + 3) / 4;
+  const int npair = nv * (nv + 1) / 2;
+  MPL_TRY(mpl_ensure(c, c->aa_part, 8 * ((size_t)npair * nwg + 64)));
+  MPL_TRY(mpl_ensure(c, c->aa_tmp, 8 * n3));
+  AAVecs fv{};
+  for (int k = 0; k < nv; ++k) fv.p[k] = P<double>(c->aa_f[k]);
+  MPL_LAUNCH(c, k_aa_gram, nwg, 256, fv, nv, P<uint8_t>(c->flags), nnode, c->n_nblk, P<double>(c->aa_part), nwg);
+  MPL_LAUNCH(c, k_aa_reduce, 1, 1024, P<double>(c->aa_part), npair, nwg, P<double>(c->aa_part) + (size_t)npair * nwg);
+  double g[15];
+  MPL_HIP(c, hipMemcpyAsync(g, P<double>(c->aa_part) + (size_t)npair * nwg, 8 * npair, hipMemcpyDeviceToHost,
+                            c->stream));
+  MPL_HIP(c, hipStreamSynchronize(c->stream));
+  double G[5][5];
+  for (int i = 0, q = 0; i < nv; ++i)
+    for (int j = i; j < nv; ++j, ++q) G[i][j] = G[j][i] = g[q];
+  // normal equations of min |f_k - dF gamma|, dF_j = f_{j+1} - f_j
+  const int h = nv - 1, k = nv - 1;
+  double M[4][4], r[4], tr = 0.0;
+  for (int i = 0; i < h; ++i) {
+    for (int j = 0; j < h; ++j) M[i][j] = G[i + 1][j + 1] - G[i + 1][j] - G[i][j + 1] + G[i][j];
+    r[i] = G[i + 1][k] - G[i][k];
+    tr += M[i][i];
+  }
+  if (!(tr > 0.0) || !std::isfinite(tr)) return MPL_OK;
+  for (int i = 0; i < h; ++i) M[i][i] += 1e-12 * tr / h;
+  // Cholesky solve of the small symmetric positive definite system
+  double L[4][4] = {}, y[4], gam[4];
+  for (int i = 0; i < h; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s2 = M[i][j];
+      for (int q = 0; q < j; ++q) s2 -= L[i][q] * L[j][q];
+      if (i == j) {
+        if (!(s2 > 0.0)) return MPL_OK;
+        L[i][i] = std::sqrt(s2);
+      } else {
+        L[i][j] = s2 / L[j][j];
+      }
+    }
+  }
+  for (int i = 0; i < h; ++i) {
+    double s2 = r[i];
+    for (int q = 0; q < i; ++q) s2 -= L[i][q] * y[q];
+    y[i] = s2 / L[i][i];
+  }
+  for (int i = h - 1; i >= 0; --i) {
+    double s2 = y[i];
+    for (int q = i + 1; q < h; ++q) s2 -= L[q][i] * gam[q];
+    gam[i] = s2 / L[i][i];
+  }
+  // v_new = v_k + f_k - sum_j gamma_j (dv_j + df_j) as a combination of the
+  // stored v and f
+  AAVecs vec{};
+  AACoef co{};
+  for (int i = 0; i < nv; ++i) {
+    vec.p[i] = P<double>(c->aa_v[i]);
+    vec.p[nv + i] = P<double>(c->aa_f[i]);
+  }
+  co.a[k] += 1.0;
+  co.a[nv + k] += 1.0;
+  for (int j = 0; j < h; ++j) {
+    co.a[j + 1] -= gam[j];
+    co.a[j] += gam[j];
+    co.a[nv + j + 1] -= gam[j];
+    co.a[nv + j] += gam[j];
+  }
+  MPL_LAUNCH(c, k_aa_combine, (int)((n3 + 255) / 256), 256, vec, co, 2 * nv, P<double>(c->aa_tmp), n3);
+  MPL_TRY(plastic_base(c, P<double>(c->aa_tmp)));
+  double E = 0.0, gn2 = 0.0;
+  MPL_TRY(mpl_stage_energy(c, P<double>(c->aa_tmp), true, &E, &gn2));
+  if (std::isfinite(E) && std::isfinite(gn2) && std::sqrt(gn2) < gn_k) {
+    *accepted = true;
+    *E_out = E;
+    *gn2_out = gn2;
+    return MPL_OK;
+  }
+  // restart the history from the pair just pushed (buffers swapped, never
+  // shared, so each stays owned by one slot)
+  std::swap(c->aa_v[0], c->aa_v[k]);
+  std::swap(c->aa_f[0], c->aa_f[k]);
+  c->aa_n = 1;
+  return MPL_OK;
+}
+
 mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   if (!c->reconstructed) return mpl_fail(c, MPL_ERR_STATE, "solve before reconstruction");
   const int64_t nnode = (int64_t)c->nnode_alloc();
@@ -2911,6 +3091,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
   c->up_calls = 0;
   c->graph_replays = 0;
   c->fallbacks_total = 0;
+  c->aa_n = 0;  // a new fixed-point iteration
   double gn_prev = gn, eta_prev = c->opts.newton_forcing;
   const double pcg_rtol = c->opts.pcg_rtol;
   for (;; ++it) {
@@ -3039,10 +3220,25 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
       result = mpl_fail(c, MPL_ERR_LINESEARCH, "no step length passed the line search");
       break;
     }
-    MPL_HIP(c, hipMemcpyAsync(v, c->vt.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
-    // fixed-point plasticity: re-project at the new iterate before its energy
-    if (fixed_point) MPL_TRY(plastic_base(c, v));
-    MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    bool accel = false;
+    if (fixed_point && c->opts.plastic_anderson > 0) {
+      // Anderson acceleration: push (v_k, f_k = vt - v_k), fit f_k by the
+      // differences of the stored updates, take the extrapolated iterate if
+      // its gradient (with its own plastic base) is finite and below |g(v_k)|
+      double Eaa = 0.0, gaa2 = 0.0;
+      MPL_TRY(anderson_step(c, v, P<double>(c->vt), gn, &accel, &Eaa, &gaa2));
+      if (accel) {
+        MPL_HIP(c, hipMemcpyAsync(v, c->aa_tmp.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
+        E = Eaa;
+        gn2 = gaa2;
+      }
+    }
+    if (!accel) {
+      MPL_HIP(c, hipMemcpyAsync(v, c->vt.p, 8 * 3 * nnode, hipMemcpyDeviceToDevice, c->stream));
+      // fixed-point plasticity: re-project at the new iterate before its energy
+      if (fixed_point) MPL_TRY(plastic_base(c, v));
+      MPL_TRY(mpl_stage_energy(c, v, true, &E, &gn2));
+    }
     gn_prev = gn;
     gn = std::sqrt(gn2);
     if (!std::isfinite(gn)) {

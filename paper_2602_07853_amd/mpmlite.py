@@ -52,7 +52,8 @@ class _Opts(C.Structure):
                 ("pcg_rtol", C.c_double), ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
                 ("max_ls", C.c_int32), ("armijo_c", C.c_double), ("pcg_check_every", C.c_int32),
                 ("time_kernels", C.c_int32), ("warm_start", C.c_int32), ("transfer", C.c_int32),
-                ("flip_ratio", C.c_double), ("plasticity", C.c_int32), ("newton_forcing", C.c_double),
+                ("flip_ratio", C.c_double), ("plasticity", C.c_int32), ("plastic_anderson", C.c_int32),
+                ("newton_forcing", C.c_double),
                 ("vbd_sweeps", C.c_int32)]
 
 
@@ -203,7 +204,7 @@ def default_opts(**kw) -> dict:
     o = dict(hv_precision=F32, precond=PRECOND_JACOBI, newton_rtol=1e-6, pcg_rtol=1e-6,
              max_newton=50, max_pcg=20000, max_ls=40, armijo_c=1e-4, pcg_check_every=16,
              time_kernels=0, warm_start=0, transfer=TRANSFER_APIC, flip_ratio=0.0,
-             plasticity=PLASTICITY_AFTER_SOLVE, newton_forcing=0.0, vbd_sweeps=0)
+             plasticity=PLASTICITY_AFTER_SOLVE, plastic_anderson=0, newton_forcing=0.0, vbd_sweeps=0)
     o.update(kw)
     return o
 

@@ -159,7 +159,7 @@ def cpu_baseline(sc, cold_counts):
     u = timed("unload", lambda: O.unload(g, sc.particles, mats))
     fixed, vfix = O.node_bcs(g, u["mi"], bcs, 0.0)
     act = u["mi"] > 0
-    vhat = np.where(fixed[:, None] > 0, vfix,
+    vhat = np.where(O.fixed_components(fixed), vfix,
                     np.where(act[:, None], u["vi"] + sc.dt * np.asarray(sc.gravity), 0))
     S, _ = timed("reconstruct", lambda: O.reconstruct(g, mats, u["Vck"], u["tauck"]))
     for K in (10, 40):

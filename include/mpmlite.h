@@ -66,8 +66,21 @@ enum {
  * (1 + dt tr G_p) J. */
 enum { MPL_NEOHOOKEAN = 0, MPL_FIXED_COROTATED = 1, MPL_HENCKY = 2, MPL_WATER = 3 };
 enum { MPL_PLASTIC_NONE = 0, MPL_PLASTIC_VON_MISES = 1, MPL_PLASTIC_DRUCKER_PRAGER = 2 };
-/* Dirichlet node boxes. */
-enum { MPL_BC_STICKY_BOX = 0, MPL_BC_MOVING_BOX = 1 };
+/* Dirichlet node sets.  The paper treats the mesh as FEM nodes, so a
+ * boundary condition is a constraint on node velocities (Sec. 1 and the
+ * Integrate step of Alg. 1, v^{n+1} prescribed on constrained nodes):
+ *   MPL_BC_STICKY_BOX  every active node in the box has v = 0;
+ *   MPL_BC_MOVING_BOX  the box moves with `velocity` (shifted by velocity *
+ *                      time) and every active node in it has v = velocity;
+ *   MPL_BC_SLIP_PLANE  a frictionless wall: the box does not move, and on
+ *                      every active node in it the velocity component along
+ *                      the wall normal is 0 while the two tangential
+ *                      components stay free.  The normal axis is the one
+ *                      nonzero entry of `velocity` (its sign and size do not
+ *                      matter); anything else is MPL_ERR_INVALID_ARG.
+ * A component, once fixed by any box, stays fixed; its value comes from the
+ * last box that fixes it (sticky and moving boxes fix all three). */
+enum { MPL_BC_STICKY_BOX = 0, MPL_BC_MOVING_BOX = 1, MPL_BC_SLIP_PLANE = 2 };
 /* Precision of the stored tangent and of the Hessian-vector product. */
 enum { MPL_F32 = 0, MPL_F64 = 1 };
 /* Preconditioner of the Newton linear systems (the preconditioned
@@ -175,9 +188,10 @@ typedef struct {
 } mpl_particles;
 
 typedef struct {
-  int32_t kind;           /* MPL_BC_STICKY_BOX | MPL_BC_MOVING_BOX */
+  int32_t kind;           /* MPL_BC_STICKY_BOX | MPL_BC_MOVING_BOX | MPL_BC_SLIP_PLANE */
   double lo[3], hi[3];    /* box at time 0, inclusive (tolerance 1e-6 dx) */
-  double velocity[3];     /* MOVING_BOX: prescribed velocity; the box moves with it */
+  double velocity[3];     /* MOVING_BOX: prescribed velocity; the box moves with it;
+                             SLIP_PLANE: the wall normal (one nonzero entry) */
 } mpl_bc;
 
 typedef struct {
@@ -345,7 +359,8 @@ enum {
   MPL_FIELD_MASS_I = 7,   /* nodes, 1 */
   MPL_FIELD_VEL_I = 8,    /* nodes, 3 (v_i^n of the unload) */
   MPL_FIELD_VHAT = 9,     /* nodes, 3 */
-  MPL_FIELD_FIXED = 10,   /* nodes, 1 (1.0 = Dirichlet) */
+  MPL_FIELD_FIXED = 10,   /* nodes, 1: the prescribed velocity components of the
+                             node, bit a for component a (7.0 = all three) */
   MPL_FIELD_V = 11,       /* nodes, 3 (current Newton iterate / solution) */
   MPL_FIELD_DIAG = 12,    /* nodes, 3 (inverse Jacobi diagonal; 0 on fixed/massless nodes) */
   MPL_FIELD_BLOCK_DIAG = 13 /* nodes, 9 (inverted 3x3 node block of H, row-major; 0 on

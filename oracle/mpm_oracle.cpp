@@ -710,6 +710,11 @@ inline void corner(int d, int* o) {
   o[1] = (d >> 1) & 1;
   o[2] = d & 1;
 }
+// Velocity component a of node nidx is a degree of freedom: the node has
+// mass and no boundary condition fixes that component (fixed[] bit a clear).
+inline bool dof_free(const double* mi, const uint8_t* fixed, int64_t nidx, int a) {
+  return mi[nidx] != 0.0 && !((fixed[nidx] >> a) & 1u);
+}
 
 // Particle -> centre stencil (Sec. 3.1): xi = x/dx - 1/2, base b = floor(xi),
 // f = xi - b; the 8 centres b + delta get weight prod_a (delta_a ? f_a : 1 - f_a).
@@ -851,13 +856,28 @@ int or_unload(const or_grid* gg, int64_t np, const double* x, const double* v,
   return status;
 }
 
-// Dirichlet node sets: an active node (m_i > 0) inside a box is fixed to the
-// box velocity (0 for sticky boxes).  A moving box is translated by
-// velocity * time.  Node-in-box uses a tolerance of 1e-6 dx; later boxes win.
+// Dirichlet node sets: an active node (m_i > 0) inside a sticky or moving box
+// has all three velocity components fixed to the box velocity (0 for sticky
+// boxes); a moving box is translated by velocity * time.  Inside a slip plane
+// only the component along the plane's normal axis is fixed, to 0.  fixed[]
+// holds one bit per component; a component stays fixed once a box fixes it,
+// and its value comes from the last box that fixes it.  Node-in-box uses a
+// tolerance of 1e-6 dx.
 int or_node_bcs(const or_grid* gg, const double* mi, int32_t nbc, const or_bc* bcs,
                 double time, uint8_t* fixed, double* vfix) {
   Grid g{gg->n, gg->dx};
   const double eps = 1e-6 * g.dx;
+  std::vector<int> slip_axis(nbc, -1);
+  for (int b = 0; b < nbc; ++b) {
+    if (bcs[b].kind == OR_BC_SLIP_PLANE) {
+      int nz = 0;
+      for (int a = 0; a < 3; ++a)
+        if (bcs[b].velocity[a] != 0.0) { ++nz; slip_axis[b] = a; }
+      if (nz != 1) return OR_ERR_ARG;
+    } else if (bcs[b].kind != OR_BC_STICKY_BOX && bcs[b].kind != OR_BC_MOVING_BOX) {
+      return OR_ERR_ARG;
+    }
+  }
   for (int i = 0; i <= g.n; ++i)
     for (int j = 0; j <= g.n; ++j)
       for (int k = 0; k <= g.n; ++k) {
@@ -874,7 +894,12 @@ int or_node_bcs(const or_grid* gg, const double* mi, int32_t nbc, const or_bc* b
           for (int a = 0; a < 3; ++a)
             if (xn[a] < bcs[b].lo[a] + sh[a] - eps || xn[a] > bcs[b].hi[a] + sh[a] + eps) in = false;
           if (!in) continue;
-          fixed[nidx] = 1;
+          if (bcs[b].kind == OR_BC_SLIP_PLANE) {
+            fixed[nidx] |= (uint8_t)(1u << slip_axis[b]);
+            vfix[3 * nidx + slip_axis[b]] = 0.0;
+            continue;
+          }
+          fixed[nidx] = 7;
           for (int a = 0; a < 3; ++a)
             vfix[3 * nidx + a] = bcs[b].kind == OR_BC_MOVING_BOX ? bcs[b].velocity[a] : 0.0;
         }
@@ -928,8 +953,9 @@ extern "C" {
 // Incremental potential of Sec. 4.2 / Alg. 3 with the rotation-free base:
 //   Phi(v) = sum_free 1/2 m_i |v_i - vhat_i|^2 + sum_{c,k} V_{c,k} psi_k((I + dt G_c(v)) S_{c,k})
 //   grad_i = m_i (v_i - vhat_i) + dt sum_c (sum_k V_{c,k} P_k(F_{c,k}) S_{c,k}^T) grad w_ic
-// (the gradient of Phi, i.e. M(v - vhat) - dt f_int).  Fixed and massless
-// nodes get a zero gradient.  energy = +inf if any F_{c,k} leaves the model's
+// (the gradient of Phi, i.e. M(v - vhat) - dt f_int).  Fixed components and
+// massless nodes get a zero gradient, and the kinetic sum runs over the free
+// components.  energy = +inf if any F_{c,k} leaves the model's
 // domain (det F <= 0 for Neo-Hookean / Hencky).
 int or_energy_grad(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
                    const double* mi, const double* vhat, const uint8_t* fixed,
@@ -967,9 +993,9 @@ int or_energy_grad(const or_grid* gg, int32_t nmat, const or_material* mats, dou
   double E = 0.0;
   for (int64_t c = 0; c < nc; ++c) E += ec[c];
   for (int64_t nidx = 0; nidx < nn; ++nidx) {
-    if (mi[nidx] == 0.0 || fixed[nidx]) continue;
     double s = 0.0;
     for (int a = 0; a < 3; ++a) {
+      if (!dof_free(mi, fixed, nidx, a)) continue;
       double dv = v[3 * nidx + a] - vhat[3 * nidx + a];
       s += dv * dv;
     }
@@ -994,13 +1020,14 @@ int or_energy_grad(const or_grid* gg, int32_t nmat, const or_material* mats, dou
               grad[3 * nidx + a] += dt * (Qc[a * 3 + 0] * gw[0] + Qc[a * 3 + 1] * gw[1] + Qc[a * 3 + 2] * gw[2]);
           }
         }
-    for (int64_t nidx = 0; nidx < nn; ++nidx) {
-      if (mi[nidx] == 0.0 || fixed[nidx]) {
-        for (int a = 0; a < 3; ++a) grad[3 * nidx + a] = 0.0;
-        continue;
+    for (int64_t nidx = 0; nidx < nn; ++nidx)
+      for (int a = 0; a < 3; ++a) {
+        if (!dof_free(mi, fixed, nidx, a)) {
+          grad[3 * nidx + a] = 0.0;
+          continue;
+        }
+        grad[3 * nidx + a] += mi[nidx] * (v[3 * nidx + a] - vhat[3 * nidx + a]);
       }
-      for (int a = 0; a < 3; ++a) grad[3 * nidx + a] += mi[nidx] * (v[3 * nidx + a] - vhat[3 * nidx + a]);
-    }
   }
   return std::isfinite(E) ? OR_OK : OR_ERR_DOMAIN;
 }
@@ -1063,16 +1090,16 @@ int or_tangent(const or_grid* gg, int32_t nmat, const or_material* mats, double 
 
 // Matrix-free product with the Hessian H = M + sum_c B_c^T Abar_c B_c on the
 // free DOFs: dG_c(u) = sum_i u_i (x) grad w_ic, y_c = Abar_c vec(dG_c),
-// (Hu)_i = m_i u_i + sum_c Y_c grad w_ic.  u is read as zero on fixed and
-// massless nodes and Hu is zero there.
+// (Hu)_i = m_i u_i + sum_c Y_c grad w_ic.  u is read as zero on fixed
+// components and massless nodes, and Hu is zero there.
 int or_hv(const or_grid* gg, const double* mc, const double* mi, const uint8_t* fixed,
           const double* Abar, const double* u, double* Hu) {
   Grid g{gg->n, gg->dx};
   const int64_t nc = g.nc(), nn = g.nn();
   std::vector<double> um(3 * nn, 0.0), Y(9 * nc, 0.0);
   for (int64_t nidx = 0; nidx < nn; ++nidx)
-    if (mi[nidx] != 0.0 && !fixed[nidx])
-      for (int a = 0; a < 3; ++a) um[3 * nidx + a] = u[3 * nidx + a];
+    for (int a = 0; a < 3; ++a)
+      if (dof_free(mi, fixed, nidx, a)) um[3 * nidx + a] = u[3 * nidx + a];
 #pragma omp parallel for schedule(static)
   for (int64_t c = 0; c < nc; ++c) {
     if (mc[c] == 0.0) continue;
@@ -1104,13 +1131,9 @@ int or_hv(const or_grid* gg, const double* mc, const double* mi, const uint8_t* 
             Hu[3 * nidx + a] += Yc[a * 3 + 0] * gw[0] + Yc[a * 3 + 1] * gw[1] + Yc[a * 3 + 2] * gw[2];
         }
       }
-  for (int64_t nidx = 0; nidx < nn; ++nidx) {
-    if (mi[nidx] == 0.0 || fixed[nidx]) {
-      for (int a = 0; a < 3; ++a) Hu[3 * nidx + a] = 0.0;
-      continue;
-    }
-    for (int a = 0; a < 3; ++a) Hu[3 * nidx + a] += mi[nidx] * um[3 * nidx + a];
-  }
+  for (int64_t nidx = 0; nidx < nn; ++nidx)
+    for (int a = 0; a < 3; ++a)
+      Hu[3 * nidx + a] = dof_free(mi, fixed, nidx, a) ? Hu[3 * nidx + a] + mi[nidx] * um[3 * nidx + a] : 0.0;
   return OR_OK;
 }
 
@@ -1207,7 +1230,7 @@ static int vbd_solve(const or_grid* gg, int32_t nmat, const or_material* mats, d
           for (int k = 0; k <= g.n; ++k) {
             if ((((i & 1) << 2) | ((j & 1) << 1) | (k & 1)) != color) continue;
             const int64_t nidx = g.node(i, j, k);
-            if (mi[nidx] == 0.0 || fixed[nidx]) continue;
+            if (mi[nidx] == 0.0 || fixed[nidx] == 7) continue;
             double H[9] = {mi[nidx], 0, 0, 0, mi[nidx], 0, 0, 0, mi[nidx]};
             // the node is corner d = ((i-ci), (j-cj), (k-ck)) of each adjacent cell
             for (int d = 0; d < 8; ++d) {
@@ -1226,6 +1249,11 @@ static int vbd_solve(const or_grid* gg, int32_t nmat, const or_material* mats, d
                   H[a * 3 + a2] += s;
                 }
             }
+            // Newton on the free components only (the gradient is 0 on the
+            // fixed ones; their row and column become the identity's)
+            for (int a = 0; a < 3; ++a)
+              if (!dof_free(mi, fixed, nidx, a))
+                for (int a2 = 0; a2 < 3; ++a2) H[3 * a + a2] = H[3 * a2 + a] = (a == a2) ? 1.0 : 0.0;
             double Hi[9];
             if (!m3_inverse(H, Hi)) return OR_ERR_NOT_CONVERGED;
             for (int a = 0; a < 3; ++a)
@@ -1278,8 +1306,7 @@ int or_jacobi_diag(const or_grid* gg, const double* mc, const double* mi, const 
       }
   for (int64_t nidx = 0; nidx < nn; ++nidx)
     for (int a = 0; a < 3; ++a) {
-      bool freed = mi[nidx] != 0.0 && !fixed[nidx];
-      D[3 * nidx + a] = freed ? D[3 * nidx + a] + mi[nidx] : 0.0;
+      D[3 * nidx + a] = dof_free(mi, fixed, nidx, a) ? D[3 * nidx + a] + mi[nidx] : 0.0;
     }
   return OR_OK;
 }
@@ -1290,7 +1317,9 @@ int or_jacobi_diag(const or_grid* gg, const double* mc, const double* mi, const 
 // diagonal),
 //   H_ii[a][a'] = m_i delta_aa'
 //               + sum_c sum_{b,b'} Abar_c[(a,b),(a',b')] dw_ic/dx_b dw_ic/dx_b',
-// and 0 on fixed and massless nodes.  Binv: [nnode][9], row-major.
+// and 0 on massless nodes.  On a node with fixed components the block is that
+// of its free components (the inverse is 0 in the fixed rows and columns).
+// Binv: [nnode][9], row-major.
 int or_block_jacobi(const or_grid* gg, const double* mc, const double* mi, const uint8_t* fixed,
                     const double* Abar, double* Binv) {
   Grid g{gg->n, gg->dx};
@@ -1321,10 +1350,18 @@ int or_block_jacobi(const or_grid* gg, const double* mc, const double* mi, const
   for (int64_t nidx = 0; nidx < nn; ++nidx) {
     double* Bi = Binv + 9 * nidx;
     std::fill(Bi, Bi + 9, 0.0);
-    if (mi[nidx] == 0.0 || fixed[nidx]) continue;
+    if (mi[nidx] == 0.0 || fixed[nidx] == 7) continue;
     double* Hn = H.data() + 9 * nidx;
     for (int a = 0; a < 3; ++a) Hn[4 * a] += mi[nidx];
+    // the block of the free components: a fixed component's row and column
+    // become those of the identity, and its row and column of the inverse 0
+    for (int a = 0; a < 3; ++a)
+      if (!dof_free(mi, fixed, nidx, a))
+        for (int a2 = 0; a2 < 3; ++a2) Hn[3 * a + a2] = Hn[3 * a2 + a] = (a == a2) ? 1.0 : 0.0;
     if (!m3_inverse(Hn, Bi)) status = OR_ERR_DOMAIN;
+    for (int a = 0; a < 3; ++a)
+      if (!dof_free(mi, fixed, nidx, a))
+        for (int a2 = 0; a2 < 3; ++a2) Bi[3 * a + a2] = Bi[3 * a2 + a] = 0.0;
   }
   return status;
 }
@@ -1568,11 +1605,12 @@ int or_step(const or_grid* gg, int32_t nmat, const or_material* mats, double dt,
   int rc = or_unload(gg, np, x, v, G, F, m, V, mat, nmat, mats, mc.data(), vc.data(), Gc.data(),
                      Vck.data(), tauck.data(), mi.data(), vi.data());
   if (rc != OR_OK && rc != OR_ERR_DOMAIN) return rc;
-  or_node_bcs(gg, mi.data(), nbc, bcs, time, fixed.data(), vfix.data());
+  rc = or_node_bcs(gg, mi.data(), nbc, bcs, time, fixed.data(), vfix.data());
+  if (rc != OR_OK) return rc;
   for (int64_t nidx = 0; nidx < nn; ++nidx)
     for (int a = 0; a < 3; ++a)
-      vhat[3 * nidx + a] = fixed[nidx] ? vfix[3 * nidx + a]
-                                        : (mi[nidx] != 0.0 ? vi[3 * nidx + a] + dt * gravity[a] : 0.0);
+      vhat[3 * nidx + a] = ((fixed[nidx] >> a) & 1u) ? vfix[3 * nidx + a]
+                           : (mi[nidx] != 0.0 ? vi[3 * nidx + a] + dt * gravity[a] : 0.0);
   rc = or_reconstruct(gg, nmat, mats, Vck.data(), tauck.data(), Sck.data());
   if (rc != OR_OK && rc != OR_ERR_DOMAIN) return rc;
   rc = or_solve(gg, nmat, mats, dt, mc.data(), mi.data(), vhat.data(), fixed.data(), Vck.data(),
@@ -1598,12 +1636,13 @@ int or_step_explicit(const or_grid* gg, int32_t nmat, const or_material* mats, d
   int rc = or_unload(gg, np, x, v, G, F, m, V, mat, nmat, mats, mc.data(), vc.data(), Gc.data(),
                      Vck.data(), tauck.data(), mi.data(), vi.data());
   if (rc != OR_OK && rc != OR_ERR_DOMAIN) return rc;
-  or_node_bcs(gg, mi.data(), nbc, bcs, time, fixed.data(), vfix.data());
+  rc = or_node_bcs(gg, mi.data(), nbc, bcs, time, fixed.data(), vfix.data());
+  if (rc != OR_OK) return rc;
   or_explicit_force(gg, nmat, Vck.data(), tauck.data(), f.data());
   for (int64_t nidx = 0; nidx < nn; ++nidx)
     for (int a = 0; a < 3; ++a) {
       const int64_t i = 3 * nidx + a;
-      if (fixed[nidx])
+      if ((fixed[nidx] >> a) & 1u)
         vnew[i] = vfix[i];
       else if (mi[nidx] != 0.0)
         vnew[i] = vi[i] + dt * gravity[a] + dt * f[i] / mi[nidx];

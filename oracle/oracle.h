@@ -34,7 +34,11 @@ extern "C" {
  * particles carry F = J^{1/3} I. */
 enum { OR_NEOHOOKEAN = 0, OR_FIXED_COROTATED = 1, OR_HENCKY = 2, OR_WATER = 3 };
 enum { OR_PLASTIC_NONE = 0, OR_PLASTIC_VON_MISES = 1, OR_PLASTIC_DRUCKER_PRAGER = 2 };
-enum { OR_BC_STICKY_BOX = 0, OR_BC_MOVING_BOX = 1 };
+/* OR_BC_SLIP_PLANE: a frictionless wall.  Its box does not move; on the
+ * active nodes inside it the velocity component along the wall normal is
+ * fixed at 0 and the two tangential components stay free.  The normal axis
+ * is the one nonzero entry of `velocity` (the other two must be 0). */
+enum { OR_BC_STICKY_BOX = 0, OR_BC_MOVING_BOX = 1, OR_BC_SLIP_PLANE = 2 };
 
 enum {
   OR_OK = 0,
@@ -61,7 +65,8 @@ typedef struct {
 typedef struct {
   int32_t kind;              /* OR_BC_* */
   double lo[3], hi[3];       /* box at time 0 (inclusive) */
-  double velocity[3];        /* prescribed velocity (MOVING_BOX; STICKY_BOX uses 0) */
+  double velocity[3];        /* prescribed velocity (MOVING_BOX; STICKY_BOX uses 0);
+                                SLIP_PLANE: the wall normal, one nonzero entry */
 } or_bc;
 
 typedef struct {
@@ -105,6 +110,10 @@ int or_unload(const or_grid* g, int64_t np, const double* x, const double* v,
               const int32_t* mat, int32_t nmat, const or_material* mats,
               double* mc, double* vc, double* Gc, double* Vck, double* tauck,
               double* mi, double* vi);
+/* fixed[node]: bit a set when velocity component a of the node is prescribed
+ * (vfix holds its value); a component is a degree of freedom when the node
+ * has mass and its bit is clear.  Every routine below that takes `fixed`
+ * reads it this way. */
 int or_node_bcs(const or_grid* g, const double* mi, int32_t nbc, const or_bc* bcs,
                 double time, uint8_t* fixed, double* vfix);
 int or_reconstruct(const or_grid* g, int32_t nmat, const or_material* mats,

@@ -22,7 +22,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 NEOHOOKEAN, FIXED_COROTATED, HENCKY, WATER = 0, 1, 2, 3
 PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
-BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
+BC_STICKY_BOX, BC_MOVING_BOX, BC_SLIP_PLANE = 0, 1, 2
 
 OK, ERR_ARG, ERR_DOMAIN, ERR_NOT_CONVERGED, ERR_LINESEARCH, ERR_OUTSIDE = 0, -1, -2, -3, -4, -5
 
@@ -232,13 +232,22 @@ def unload(grid: Grid, parts: dict, mats):
 
 
 def node_bcs(grid: Grid, mi, bcs, time=0.0):
+    """Dirichlet sets: fixed [nnode] uint8 with bit a set when velocity
+    component a is prescribed, vfix [nnode, 3] the prescribed values."""
     nn = grid.nnode
     fixed = np.zeros(nn, dtype=np.uint8)
     vfix = np.zeros((nn, 3))
     arr = (_BC * max(len(bcs), 1))(*[b.c() for b in bcs])
-    lib().or_node_bcs(C.byref(grid.c()), _p(_f64(mi)), len(bcs), arr, C.c_double(time),
-                      _p(fixed, C.c_uint8), _p(vfix))
+    rc = lib().or_node_bcs(C.byref(grid.c()), _p(_f64(mi)), len(bcs), arr, C.c_double(time),
+                           _p(fixed, C.c_uint8), _p(vfix))
+    if rc != OK:
+        raise ValueError(f"or_node_bcs: invalid boundary condition (rc {rc})")
     return fixed, vfix
+
+
+def fixed_components(fixed):
+    """[nnode, 3] bool: component a of the node is prescribed."""
+    return ((np.asarray(fixed, dtype=np.uint8)[:, None] >> np.arange(3, dtype=np.uint8)) & 1).astype(bool)
 
 
 def reconstruct(grid: Grid, mats, Vck, tauck):
@@ -391,13 +400,15 @@ def step_flip(grid: Grid, mats, dt, gravity, bcs, time, parts: dict, flip, opts=
         return None, None, u["rc"]
     fixed, vfix = node_bcs(grid, u["mi"], bcs, time)
     act = u["mi"] > 0
-    free = act & (fixed == 0)
-    vhat = np.where(fixed[:, None] > 0, vfix,
+    fx = fixed_components(fixed)
+    free = act[:, None] & ~fx
+    vhat = np.where(fx, vfix,
                     np.where(act[:, None], u["vi"] + dt * np.asarray(gravity, dtype=np.float64), 0.0))
     if opts is None:
         f = explicit_force(grid, u["Vck"], u["tauck"])
         vnew = vhat.copy()
-        vnew[free] += dt * f[free] / u["mi"][free, None]
+        mi3 = np.broadcast_to(u["mi"][:, None], f.shape)
+        vnew[free] += dt * f[free] / mi3[free]
     else:
         S, rc = reconstruct(grid, mats, u["Vck"], u["tauck"])
         if rc not in (OK, ERR_DOMAIN):

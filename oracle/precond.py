@@ -4,13 +4,15 @@ map — TEST INFRASTRUCTURE ONLY (tests, smoke, bench CPU-baseline leg).
 The network runs on a dense box over all grid nodes of an N^3-cell grid:
 voxel (i, j, k) is node (i, j, k), each axis padded from N + 1 up to a
 multiple of 8 (padding voxels are zero).  With D the Jacobi diagonal of the
-Newton matrix (zero off the free DOFs) and r a residual:
+Newton matrix (zero off the free DOFs: massless nodes and the velocity
+components a boundary condition fixes) and r a residual:
 
   s^2     = sum over free DOFs of r^2 / D, divided by the number of free DOFs
-  x[v]    = (r_v / (s sqrt(D_v)) (3 channels), log(mean_a D_v,a / Dref), 1,
-             11 zero channels) on free nodes, 0 elsewhere; Dref = mean over
-             free nodes of mean_a D_v,a
-  z_v     = r_v / D_v + s o_v / sqrt(D_v) on free nodes, 0 elsewhere,
+  x[v]    = (r_v / (s sqrt(D_v)) on its free components, 0 on the fixed ones
+             (3 channels), log(mean of D_v over its free components / Dref),
+             1, 11 zero channels) on nodes with a free DOF, 0 elsewhere;
+             Dref = mean of that per-node mean over those nodes
+  z_v     = r_v / D_v + s o_v / sqrt(D_v) on free DOFs, 0 elsewhere,
 
 o = channels 0-2 of the network output (oracle/unet.py).  Zero weights give
 o = 0, i.e. Jacobi.
@@ -28,25 +30,28 @@ def box_dims(n: int):
 
 
 def _free(D):
-    return np.all(D > 0.0, axis=1)
+    """[nodes, 3] bool: the free DOFs (D > 0)."""
+    return np.asarray(D) > 0.0
 
 
 def scale(r, D):
     fr = _free(D)
     s2 = np.sum(r[fr] ** 2 / D[fr])
-    return np.sqrt(max(s2 / (3.0 * max(int(fr.sum()), 1)), 1e-300))
+    return np.sqrt(max(s2 / max(int(fr.sum()), 1), 1e-300))
 
 
 def features(n: int, r, D):
     """Network input [X, Y, Z, 16] for node vector r [(n+1)^3, 3]."""
     fr = _free(D)
+    nodes = fr.any(axis=1)
     sc = scale(r, D)
-    dmean = np.where(fr, D.mean(axis=1), 1.0)
-    dref = dmean[fr].mean() if fr.any() else 1.0
+    Dsafe = np.where(fr, D, 1.0)
+    dmean = np.where(nodes, np.sum(np.where(fr, D, 0.0), axis=1) / np.maximum(fr.sum(axis=1), 1), 1.0)
+    dref = dmean[nodes].mean() if nodes.any() else 1.0
     f = np.zeros(((n + 1) ** 3, U.IN_CH))
-    f[fr, 0:3] = r[fr] / (sc * np.sqrt(D[fr]))
-    f[fr, 3] = np.log(dmean[fr] / dref)
-    f[fr, 4] = 1.0
+    f[:, 0:3] = np.where(fr, r / (sc * np.sqrt(Dsafe)), 0.0)
+    f[nodes, 3] = np.log(dmean[nodes] / dref)
+    f[nodes, 4] = 1.0
     X = box_dims(n)
     box = np.zeros(X + (U.IN_CH,))
     box[:n + 1, :n + 1, :n + 1] = f.reshape(n + 1, n + 1, n + 1, U.IN_CH)
@@ -54,14 +59,14 @@ def features(n: int, r, D):
 
 
 def apply(params, n: int, r, D, rnd=U._ident):
-    """z = r / D + s o / sqrt(D) on free nodes (``rnd`` as in unet.forward,
+    """z = r / D + s o / sqrt(D) on free DOFs (``rnd`` as in unet.forward,
     also applied to the stored network input)."""
     x = rnd(features(n, r, D))
     return map_output(n, r, D, U.forward(params, x, rnd=rnd))
 
 
 def map_output(n: int, r, D, o_box):
-    """z = r / D + s o / sqrt(D) on free nodes, o = channels 0-2 of the
+    """z = r / D + s o / sqrt(D) on free DOFs, o = channels 0-2 of the
     network output box o_box [X, Y, Z, >= 3] at the grid's nodes."""
     fr = _free(D)
     sc = scale(r, D)

@@ -71,12 +71,11 @@ __global__ __launch_bounds__(64) void k_explicit_nodes(const double* __restrict_
       }
     }
   }
-  const bool free_node = (fl & MPL_NODE_FREE) != 0;
   const double m = mi[ni];
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
     const double vh = vhat[i];
-    v[i] = free_node ? vh + dt * fr[a] / m : vh;
+    v[i] = mpl_free(fl, a) ? vh + dt * fr[a] / m : vh;
     if (f) f[i] = fr[a];
   }
 }
@@ -132,7 +131,7 @@ mpl_status mpl_step_explicit(mpl_ctx* c, const mpl_particles* in, mpl_particles*
   const double t3 = wall_ms();
   st.active_cells = c->hscal.n_active_cells;
   st.active_nodes = c->hscal.n_active_nodes;
-  st.free_dofs = 3 * c->hscal.n_free_nodes;
+  st.free_dofs = c->hscal.n_free_dofs;
   st.cell_blocks = c->n_cblk;
   st.node_blocks = c->n_nblk;
   st.ms_unload = t1 - t0;

@@ -186,7 +186,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 }  // namespace mpl
 
-// node flag bits
+// node flag bits: ACTIVE (the node has mass), FIXED (a boundary condition
+// prescribes at least one velocity component), and MPL_NODE_FREE_X << a
+// (velocity component a is a degree of freedom of the solve)
 #define MPL_NODE_ACTIVE 1
 #define MPL_NODE_FIXED 2
-#define MPL_NODE_FREE 4
+#define MPL_NODE_FREE_X 4
+#define MPL_NODE_FREE_ALL 28
+__host__ __device__ __forceinline__ bool mpl_free(uint8_t fl, int a) { return (fl >> (2 + a)) & 1; }

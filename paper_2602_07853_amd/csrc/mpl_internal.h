@@ -41,6 +41,7 @@ struct NNState;
 struct BCDev {
   int n;
   int kind[16];
+  int axis[16];  // MPL_BC_SLIP_PLANE: the normal axis
   double lo[16][3], hi[16][3], vel[16][3];
 };
 
@@ -69,7 +70,7 @@ struct SolverScalars {
   int32_t err;        // binning / domain error flags
   int32_t domain_count;
   int32_t n_cblk, n_nblk;
-  int32_t n_active_cells, n_active_nodes, n_free_nodes;
+  int32_t n_active_cells, n_active_nodes, n_free_dofs;
   int32_t n_tan_cells;  // cells that carry a tangent (some V_{c,k} != 0)
   int32_t n_fact_cells; // cells stored in the factored layout (several materials: per-block choice)
 };

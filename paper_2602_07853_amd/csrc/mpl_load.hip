@@ -279,7 +279,12 @@ __global__ void k_export_sym(const double* __restrict__ src, int64_t ncell, int 
 __global__ void k_flags_to_double(const uint8_t* __restrict__ fl, double* __restrict__ out,
                                   int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (fl[i] & MPL_NODE_FIXED) ? 1.0 : 0.0;
+  if (i >= n) return;
+  // the prescribed components of an active node, one bit each
+  int bits = 0;
+  if (fl[i] & MPL_NODE_ACTIVE)
+    for (int a = 0; a < 3; ++a) bits |= mpl_free(fl[i], a) ? 0 : (1 << a);
+  out[i] = (double)bits;
 }
 
 // the six stored entries (xx, yy, zz, xy, yz, xz) of symmetric node blocks,
@@ -378,7 +383,7 @@ mpl_status mpl_step(mpl_ctx* c, const mpl_particles* in, mpl_particles* out, dou
   double t4 = wall_ms();
   st.active_cells = c->hscal.n_active_cells;
   st.active_nodes = c->hscal.n_active_nodes;
-  st.free_dofs = 3 * c->hscal.n_free_nodes;
+  st.free_dofs = c->hscal.n_free_dofs;
   st.cell_blocks = c->n_cblk;
   st.node_blocks = c->n_nblk;
   st.domain_events = c->hscal.domain_count;

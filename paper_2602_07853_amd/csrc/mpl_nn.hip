@@ -1092,10 +1092,18 @@ __global__ __launch_bounds__(64) void k_dref_partial(const double* __restrict__ 
                                                      double* __restrict__ part) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
+  // a node with a free component contributes the mean diagonal over its
+  // free components
   double s = 0.0, n = 0.0;
-  if (flags[ni] & MPL_NODE_FREE) {
-    for (int a = 0; a < 3; ++a) s += 1.0 / Dinv[a * nnode + ni];
-    s /= 3.0;
+  const uint8_t fl = flags[ni];
+  if (fl & MPL_NODE_FREE_ALL) {
+    int nf = 0;
+    for (int a = 0; a < 3; ++a)
+      if (mpl_free(fl, a)) {
+        s += 1.0 / Dinv[a * nnode + ni];
+        ++nf;
+      }
+    s /= nf;
     n = 1.0;
   }
   s = wave_sum(s);
@@ -1162,15 +1170,21 @@ __global__ __launch_bounds__(256) void k_features(const double* __restrict__ r,
             i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
   const int64_t ni = voxel_node(i, j, k, nmap, nbd);
   float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-  if (ni >= 0 && (flags[ni] & MPL_NODE_FREE)) {
+  const uint8_t fl = ni >= 0 ? flags[ni] : (uint8_t)0;
+  if (fl & MPL_NODE_FREE_ALL) {
+    // fixed components (Dinv = 0) read as 0; the diagonal channel is the
+    // mean over the free ones
     const double sc = sqrt(fmax(s2[0] * inv_nfree, 1e-300));
     double dm = 0.0;
+    int nf = 0;
     for (int a = 0; a < 3; ++a) {
+      if (!mpl_free(fl, a)) continue;
       const double di = Dinv[a * nnode + ni];
       f[a] = (float)(sqrt(di) * r[a * nnode + ni] / sc);
       dm += 1.0 / di;
+      ++nf;
     }
-    f[3] = (float)log(dm / 3.0 / dref[0]);
+    f[3] = (float)log(dm / nf / dref[0]);
     f[4] = 1.f;
   }
   uint16_t* dst = feat + v * 16;
@@ -1197,11 +1211,12 @@ __global__ __launch_bounds__(256) void k_record(const double* __restrict__ r, co
   const int k = (int)(v % box.d[2]), j = (int)((v / box.d[2]) % box.d[1]),
             i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
   const int64_t ni = voxel_node(i, j, k, nmap, nbd);
-  const bool fr = ni >= 0 && (flags[ni] & MPL_NODE_FREE);
+  const uint8_t fl = ni >= 0 ? flags[ni] : (uint8_t)0;
+  const bool fr = (fl & MPL_NODE_FREE_ALL) != 0;
   const double sc = sqrt(fmax(s2[0] * inv_nfree, 1e-300));
   for (int a = 0; a < 3; ++a) {
     double t = 0.0;
-    if (fr) {
+    if (mpl_free(fl, a)) {
       const int64_t q = a * nnode + ni;
       const double di = Dinv[q];
       const double e = xstar[q] - x[q];
@@ -1226,8 +1241,9 @@ __global__ __launch_bounds__(256) void k_out_grad(const double* __restrict__ g,
             i = (int)(v / ((int64_t)box.d[2] * box.d[1]));
   const int64_t ni = voxel_node(i, j, k, nmap, nbd);
   float f[3] = {0.f, 0.f, 0.f};
-  if (ni >= 0 && (flags[ni] & MPL_NODE_FREE))
-    for (int a = 0; a < 3; ++a) f[a] = (float)g[a * nnode + ni];
+  const uint8_t fl = ni >= 0 ? flags[ni] : (uint8_t)0;
+  for (int a = 0; a < 3; ++a)
+    if (mpl_free(fl, a)) f[a] = (float)g[a * nnode + ni];
   uint4 lo, hi = make_uint4(0, 0, 0, 0);
   lo.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
   lo.y = (uint32_t)f2bf(f[2]);
@@ -1266,7 +1282,7 @@ mpl_status nn_set_dref(mpl_ctx* c, const double* Dinv) {
 }
 
 double nn_inv_free_dofs(mpl_ctx* c) {
-  const double n = 3.0 * std::max(1, c->hscal.n_free_nodes);
+  const double n = std::max(1, c->hscal.n_free_dofs);
   return 1.0 / n;
 }
 static double inv_nfree(mpl_ctx* c) { return nn_inv_free_dofs(c); }

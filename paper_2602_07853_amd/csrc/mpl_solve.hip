@@ -173,8 +173,9 @@ __global__ __launch_bounds__(64) void k_plastic_base(const double* __restrict__ 
   }
 }
 
-// grad_i = m_i (v_i - vhat_i) + dt sum_c Q_c grad w_ic on free nodes; partial
-// sums of the inertia energy and |grad|^2.
+// grad_i = m_i (v_i - vhat_i) + dt sum_c Q_c grad w_ic on the free components
+// (0 on the fixed ones); partial sums of the inertia energy (free components)
+// and |grad|^2.
 template <bool WANT_GRAD>
 __global__ __launch_bounds__(64) void k_energy_nodes(const double* __restrict__ v,
                                                      const double* __restrict__ vhat,
@@ -188,12 +189,14 @@ __global__ __launch_bounds__(64) void k_energy_nodes(const double* __restrict__ 
                                                      double* __restrict__ pg) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
+  const bool fr = (fl & MPL_NODE_FREE_ALL) != 0;
   const double m = mi[ni];
   double ein = 0.0, gg = 0.0, gr[3] = {0.0, 0.0, 0.0};
   if (fr) {
+    // kinetic term and gradient on the free components only
     double dv[3];
-    for (int a = 0; a < 3; ++a) dv[a] = v[a * nnode + ni] - vhat[a * nnode + ni];
+    for (int a = 0; a < 3; ++a) dv[a] = mpl_free(fl, a) ? v[a * nnode + ni] - vhat[a * nnode + ni] : 0.0;
     ein = 0.5 * m * (dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
     if (WANT_GRAD) {
       for (int d = 0; d < 8; ++d) {
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(64) void k_energy_nodes(const double* __restrict__ 
           gr[a] += Qc[(a * 3) * ncell + ci] * gw[0] + Qc[(a * 3 + 1) * ncell + ci] * gw[1] +
                    Qc[(a * 3 + 2) * ncell + ci] * gw[2];
       }
-      for (int a = 0; a < 3; ++a) gr[a] = m * dv[a] + dt * gr[a];
+      for (int a = 0; a < 3; ++a) gr[a] = mpl_free(fl, a) ? m * dv[a] + dt * gr[a] : 0.0;
       gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
     }
   }
@@ -516,7 +519,8 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double dd[3] = {0.0, 0.0, 0.0};
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
+  const bool fr = (fl & MPL_NODE_FREE_ALL) != 0;
   if (fr) {
     for (int d = 0; d < 8; ++d) {
       const int ci = node_cell(n_nbr_cell, nb, l, d);
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(64) void k_diag(const T* __restrict__ Abar,
     for (int a = 0; a < 3; ++a) dd[a] += mi[ni];
   }
   for (int a = 0; a < 3; ++a) {
-    const double di = fr ? 1.0 / dd[a] : 0.0;
+    const double di = mpl_free(fl, a) ? 1.0 / dd[a] : 0.0;
     D[a * nnode + ni] = di;
     Dt[a * nnode + ni] = (T)di;
   }
@@ -577,7 +581,8 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double h[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
+  const bool fr = (fl & MPL_NODE_FREE_ALL) != 0;
   if (fr) {
     for (int d = 0; d < 8; ++d) {
       const int ci = node_cell(n_nbr_cell, nb, l, d);
@@ -608,6 +613,13 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
       }
     }
     for (int a = 0; a < 3; ++a) h[a] += mi[ni];
+    // a node with fixed components takes the block of its free ones: the
+    // fixed rows and columns become those of the identity here and 0 in the
+    // inverse below
+    for (int e = 0; e < 6; ++e) {
+      const int a = blk_a(e), a2 = blk_b(e);
+      if (!mpl_free(fl, a) || !mpl_free(fl, a2)) h[e] = (a == a2) ? 1.0 : 0.0;
+    }
   }
   // a free node's block is m_i I plus PSD cell blocks: positive definite
   // unless a value is not finite; anything else is reported (error bit 128)
@@ -616,6 +628,8 @@ __global__ __launch_bounds__(64) void k_block_diag(const T* __restrict__ Abar,
   if (fr && !ok) atomicOr(err, 128);
   if (!fr || !ok)
     for (int e = 0; e < 6; ++e) inv[e] = 0.0;
+  for (int e = 0; e < 6; ++e)
+    if (!mpl_free(fl, blk_a(e)) || !mpl_free(fl, blk_b(e))) inv[e] = 0.0;
   for (int e = 0; e < 6; ++e) {
     B[e * nnode + ni] = inv[e];
     Bt[e * nnode + ni] = (T)inv[e];
@@ -635,6 +649,8 @@ __device__ __forceinline__ void block_apply(const double b[6], const double r[3]
 // cells of the node's 3x3 block of the dense FP64 tangent,
 //   H[a][a'] += sum_{b,b'} Abar[(a,b),(a',b')] gw_b gw_b'.
 // No two nodes of one colour share a cell, so the updates are independent.
+// On a node with fixed components the step is taken on the free ones (their
+// rows and columns of H; the gradient is 0 on the fixed ones).
 __global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Abar,
                                                   const uint64_t* __restrict__ cmask,
                                                   const int32_t* __restrict__ coff,
@@ -650,7 +666,8 @@ __global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Aba
   const int4 bc = ncoord[nb];
   const int ix = bc.x * 4 + local_x(l), iy = bc.y * 4 + local_y(l), iz = bc.z * 4 + local_z(l);
   if ((((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1)) != color) return;
-  if (!(flags[ni] & MPL_NODE_FREE)) return;
+  const uint8_t fl = flags[ni];
+  if (!(fl & MPL_NODE_FREE_ALL)) return;
   const double m = mi[ni];
   double H[9] = {m, 0.0, 0.0, 0.0, m, 0.0, 0.0, 0.0, m};
   for (int d = 0; d < 8; ++d) {
@@ -669,6 +686,9 @@ __global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Aba
         H[a * 3 + a2] += s;
       }
   }
+  for (int a = 0; a < 3; ++a)
+    if (!mpl_free(fl, a))
+      for (int a2 = 0; a2 < 3; ++a2) H[a * 3 + a2] = H[a2 * 3 + a] = (a == a2) ? 1.0 : 0.0;
   double C[9];
   cofactor(H, C);  // C = det(H) H^{-T}; H is symmetric
   const double dH = det(H);
@@ -677,9 +697,9 @@ __global__ __launch_bounds__(64) void k_vbd_nodes(const double* __restrict__ Aba
     return;
   }
   double gi[3];
-  for (int a = 0; a < 3; ++a) gi[a] = g[a * nnode + ni];
+  for (int a = 0; a < 3; ++a) gi[a] = mpl_free(fl, a) ? g[a * nnode + ni] : 0.0;
   for (int a = 0; a < 3; ++a)
-    v[a * nnode + ni] -= (C[a] * gi[0] + C[3 + a] * gi[1] + C[6 + a] * gi[2]) / dH;
+    if (mpl_free(fl, a)) v[a * nnode + ni] -= (C[a] * gi[0] + C[3 + a] * gi[1] + C[6 + a] * gi[2]) / dH;
 }
 
 // ---------------------------------------------------------------- Hv
@@ -908,7 +928,7 @@ __device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* _
       if (use[k]) h[a] += v[k][a];
 }
 
-// Stand-alone product: Hu = M u + K u on free nodes.
+// Stand-alone product: Hu = M u + K u on the free components (0 elsewhere).
 template <class T>
 __global__ __launch_bounds__(64) void k_hv_combine(const T* __restrict__ u,
                                                    const double* __restrict__ mi,
@@ -919,18 +939,19 @@ __global__ __launch_bounds__(64) void k_hv_combine(const T* __restrict__ u,
                                                    int64_t nnode, T* __restrict__ Hu) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
   T h[3];
   gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
   const T m = (T)mi[ni];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) Hu[a * nnode + ni] = fr ? h[a] + m * u[a * nnode + ni] : T(0);
+  for (int a = 0; a < 3; ++a) Hu[a * nnode + ni] = mpl_free(fl, a) ? h[a] + m * u[a * nnode + ni] : T(0);
 }
 
 // ---------------------------------------------------------------- PCG vectors
 // Node-vector kernels run 4 node blocks (4 wavefronts) per workgroup and
 // emit one partial sum per workgroup (waves combined in a fixed order).
-// Dinv holds the inverse Jacobi diagonal (0 on non-free nodes).
+// Dinv holds the inverse Jacobi diagonal (0 on fixed components and
+// massless nodes); every vector is 0 on those components.
 __device__ __forceinline__ double block4_sum(double v, double* sh) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -955,11 +976,11 @@ __global__ __launch_bounds__(256) void k_pcg_init(const double* __restrict__ b,
   double rz = 0.0, bb = 0.0, mm = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     const double m = (double)mi[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const double rv = fr ? b[i] : 0.0;
+      const double rv = mpl_free(fl, a) ? b[i] : 0.0;
       const double zv = rv * (double)Dinv[i];
       const T pv = (T)zv;
       x[i] = 0.0;
@@ -1002,11 +1023,13 @@ __global__ __launch_bounds__(256) void k_pcg_update(const T* __restrict__ p,
   double rz = 0.0, rr = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    if (flags[ni] & MPL_NODE_FREE) {
+    const uint8_t fl = flags[ni];
+    if (fl & MPL_NODE_FREE_ALL) {
       T h[3];
       gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
       const T m = mi[ni];
       for (int a = 0; a < 3; ++a) {
+        if (!mpl_free(fl, a)) continue;
         const int64_t i = a * nnode + ni;
         const T pv = p[i];
         const T qt = h[a] + m * pv;
@@ -1044,11 +1067,11 @@ __global__ __launch_bounds__(256) void k_pcg_direction(const double* __restrict_
   double mm = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     const double m = (double)mi[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const T pv = fr ? (T)(r[i] * (double)Dinv[i] + beta * (double)p[i]) : T(0);
+      const T pv = mpl_free(fl, a) ? (T)(r[i] * (double)Dinv[i] + beta * (double)p[i]) : T(0);
       p[i] = pv;
       mm += m * (double)pv * (double)pv;
     }
@@ -1095,11 +1118,11 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
   double g = 0.0, bb = 0.0, mu = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     const double m = (double)mi[ni];
     if constexpr (BJ) {
       double rb[3], bk[6], z[3];
-      for (int a = 0; a < 3; ++a) rb[a] = fr ? b[a * nnode + ni] : 0.0;
+      for (int a = 0; a < 3; ++a) rb[a] = mpl_free(fl, a) ? b[a * nnode + ni] : 0.0;
       for (int e = 0; e < 6; ++e) bk[e] = (double)Dinv[e * nnode + ni];
       block_apply(bk, rb, z);
       for (int a = 0; a < 3; ++a) {
@@ -1118,7 +1141,7 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
     } else
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const double rv = fr ? b[i] : 0.0;
+      const double rv = mpl_free(fl, a) ? b[i] : 0.0;
       const T uv = (T)(rv * (double)Dinv[i]);
       x[i] = 0.0;
       dx[i] = T(0);
@@ -1141,15 +1164,15 @@ __global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ b, c
   }
 }
 
-// Warm start: u = x0 in the tangent's precision (free nodes), for the
+// Warm start: u = x0 in the tangent's precision (free components), for the
 // product H x0 that gives the initial residual.
 template <class T>
 __global__ void k_cg_prep(const double* __restrict__ x0, const uint8_t* __restrict__ flags, int64_t nnode,
                           T* __restrict__ u) {
   const int64_t ni = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ni >= nnode) return;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
-  for (int a = 0; a < 3; ++a) u[a * nnode + ni] = fr ? (T)x0[a * nnode + ni] : T(0);
+  const uint8_t fl = flags[ni];
+  for (int a = 0; a < 3; ++a) u[a * nnode + ni] = mpl_free(fl, a) ? (T)x0[a * nnode + ni] : T(0);
 }
 
 // Warm-start variant of k_cg_init: x = x0, r = b - H x0 (the product's
@@ -1173,23 +1196,24 @@ __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__
   double g = 0.0, bb = 0.0, mu = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     const T m = mi[ni];
     T h[3] = {T(0), T(0), T(0)};
-    if (fr) gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    if (fl & MPL_NODE_FREE_ALL) gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
     if constexpr (BJ) {
       double bv[3], rb[3], bk[6], z[3];
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
-        bv[a] = fr ? b[i] : 0.0;
-        rb[a] = fr ? bv[a] - (double)(h[a] + m * u[i]) : 0.0;
+        const bool fa = mpl_free(fl, a);
+        bv[a] = fa ? b[i] : 0.0;
+        rb[a] = fa ? bv[a] - (double)(h[a] + m * u[i]) : 0.0;
       }
       for (int e = 0; e < 6; ++e) bk[e] = (double)Dinv[e * nnode + ni];
       block_apply(bk, rb, z);
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
         const T uv = (T)z[a];
-        x[i] = fr ? x0[i] : 0.0;
+        x[i] = mpl_free(fl, a) ? x0[i] : 0.0;
         dx[i] = T(0);
         r[i] = rb[a];
         u[i] = uv;
@@ -1202,10 +1226,11 @@ __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__
     } else
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const double bv = fr ? b[i] : 0.0;
-      const double rv = fr ? bv - (double)(h[a] + m * u[i]) : 0.0;
+      const bool fa = mpl_free(fl, a);
+      const double bv = fa ? b[i] : 0.0;
+      const double rv = fa ? bv - (double)(h[a] + m * u[i]) : 0.0;
       const T uv = (T)(rv * (double)Dinv[i]);
-      x[i] = fr ? x0[i] : 0.0;
+      x[i] = fa ? x0[i] : 0.0;
       dx[i] = T(0);
       r[i] = rv;
       u[i] = uv;
@@ -1250,7 +1275,7 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
     // of r enter each component of u)
     if (nb < n_nblk) {
       const int64_t ni = (int64_t)nb * MPL_BC + l;
-      const bool fr = flags[ni] & MPL_NODE_FREE;
+      const uint8_t fl = flags[ni];
       T pv[3], svv[3], dxv[3] = {T(0), T(0), T(0)};
       double xv[3] = {0.0, 0.0, 0.0}, rv[3], bk[6];
 #pragma unroll
@@ -1267,12 +1292,14 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
       const T m = mi[ni];
       T h[3];
       gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
-      if (fr) {
+      if (fl & MPL_NODE_FREE_ALL) {
         double ud[3], rn[3], und[3];
         block_apply(bk, rv, ud);  // u_j = B r_j as stored for the product
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const int64_t i = a * nnode + ni;
+          rn[a] = rv[a];
+          if (!mpl_free(fl, a)) continue;  // fixed components stay 0
           const T uv = (T)ud[a];
           const T w = h[a] + m * uv;
           const T pn = (T)((double)uv + beta * (double)pv[a]);
@@ -1307,8 +1334,8 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
     const int64_t ni = (int64_t)nb * MPL_BC + l;
     // all loads of the node (three components, the flag, the gathered
     // pieces) are issued at once, also on nodes that are not free (their
-    // lines are read by the wave anyway); only free nodes store
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    // lines are read by the wave anyway); only free components store
+    const uint8_t fl = flags[ni];
     T pv[3], svv[3], dv[3], dxv[3] = {T(0), T(0), T(0)};
     double xv[3] = {0.0, 0.0, 0.0}, rv[3];
 #pragma unroll
@@ -1324,9 +1351,10 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
     const T m = mi[ni];
     T h[3];
     gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
-    if (fr) {
+    if (fl & MPL_NODE_FREE_ALL) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
+        if (!mpl_free(fl, a)) continue;  // fixed components stay 0
         const int64_t i = a * nnode + ni;
         const T uv = (T)(rv[a] * (double)dv[a]);  // u_j = Dinv r_j as stored for the product
         const T w = h[a] + m * uv;                // (H u)_i
@@ -1503,7 +1531,7 @@ __device__ __forceinline__ void learned_z(const NetOut& net, int4 bc, int l, con
   }
 }
 
-// x = 0, r = b on free nodes; partials b.b and sum Dinv b^2.
+// x = 0, r = b on the free components; partials b.b and sum Dinv b^2.
 __global__ __launch_bounds__(256) void k_fpcg_init(const double* __restrict__ b,
                                                    const double* __restrict__ Dinv,
                                                    const uint8_t* __restrict__ flags, int64_t nnode,
@@ -1515,10 +1543,10 @@ __global__ __launch_bounds__(256) void k_fpcg_init(const double* __restrict__ b,
   double bb = 0.0, s2 = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
-      const double rv = fr ? b[i] : 0.0;
+      const double rv = mpl_free(fl, a) ? b[i] : 0.0;
       x[i] = 0.0;
       r[i] = rv;
       bb += rv * rv;
@@ -1550,7 +1578,7 @@ __global__ __launch_bounds__(256) void k_fpcg_dots(const double* __restrict__ r,
   double zr = 0.0, zq = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    if (flags[ni] & MPL_NODE_FREE) {
+    if (flags[ni] & MPL_NODE_FREE_ALL) {
       double z[3];
       learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, false, z);
       for (int a = 0; a < 3; ++a) {
@@ -1586,16 +1614,16 @@ __global__ __launch_bounds__(256) void k_fpcg_direction(const double* __restrict
   double mm = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    const bool fr = flags[ni] & MPL_NODE_FREE;
+    const uint8_t fl = flags[ni];
     const double m = mi[ni];
     double z[3] = {0.0, 0.0, 0.0};
-    if (fr) learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, jacobi, z);
+    if (fl & MPL_NODE_FREE_ALL) learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sc, jacobi, z);
     for (int a = 0; a < 3; ++a) {
       const int64_t i = a * nnode + ni;
       // beta = 0 (first iteration, restart after a fallback) does not read
       // the previous direction, which may hold anything on the first call
       const double pold = (beta != 0.0) ? (double)p[i] : 0.0;
-      const T pv = fr ? (T)(z[a] + beta * pold) : T(0);
+      const T pv = mpl_free(fl, a) ? (T)(z[a] + beta * pold) : T(0);
       p[i] = pv;
       mm += m * (double)pv * (double)pv;
     }
@@ -1616,7 +1644,7 @@ __global__ __launch_bounds__(256) void k_precond_z(const double* __restrict__ r,
   if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double zz[3] = {0.0, 0.0, 0.0};
-  if (flags[ni] & MPL_NODE_FREE)
+  if (flags[ni] & MPL_NODE_FREE_ALL)
     learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(s->s2 * net.inv_nfree, 1e-300)), false,
               zz);
   for (int a = 0; a < 3; ++a) z[a * nnode + ni] = zz[a];
@@ -1637,7 +1665,7 @@ __global__ __launch_bounds__(256) void k_online_rdr(const double* __restrict__ r
   double acc = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    if (flags[ni] & MPL_NODE_FREE)
+    if (flags[ni] & MPL_NODE_FREE_ALL)
       for (int a = 0; a < 3; ++a) {
         const double rv = r[a * nnode + ni];
         acc += rv * rv * Dinv[a * nnode + ni];
@@ -1658,7 +1686,7 @@ __global__ __launch_bounds__(256) void k_online_z(const double* __restrict__ r,
   if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
   double zz[3] = {0.0, 0.0, 0.0};
-  if (flags[ni] & MPL_NODE_FREE)
+  if (flags[ni] & MPL_NODE_FREE_ALL)
     learned_z(net, ncoord[nb], l, r, Dinv, nnode, ni, sqrt(fmax(rdr[0] * net.inv_nfree, 1e-300)),
               jacobi != 0, zz);
   for (int a = 0; a < 3; ++a) z[a * nnode + ni] = (T)zz[a];
@@ -1677,7 +1705,7 @@ __global__ __launch_bounds__(256) void k_online_dots(const double* __restrict__ 
   double a1 = 0.0, a2 = 0.0;
   if (nb < n_nblk) {
     const int64_t ni = (int64_t)nb * MPL_BC + l;
-    if (flags[ni] & MPL_NODE_FREE)
+    if (flags[ni] & MPL_NODE_FREE_ALL)
       for (int a = 0; a < 3; ++a) {
         const int64_t i = a * nnode + ni;
         a1 += (double)z[i] * (double)hz[i];
@@ -1706,11 +1734,11 @@ __global__ __launch_bounds__(256) void k_online_grad(const double* __restrict__ 
   if (blockIdx.x == 0 && threadIdx.x == 0) *loss = rdr > 0.0 ? (0.5 * red[1] - red[2]) / rdr : 0.0;
   if (nb >= n_nblk) return;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
   const double sc = sqrt(fmax(rdr * inv_nfree, 1e-300));
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
-    g[i] = (fr && rdr > 0.0) ? sc * sqrt(Dinv[i]) * ((double)hz[i] - r[i]) / rdr : 0.0;
+    g[i] = (mpl_free(fl, a) && rdr > 0.0) ? sc * sqrt(Dinv[i]) * ((double)hz[i] - r[i]) / rdr : 0.0;
   }
 }
 
@@ -1721,12 +1749,13 @@ __global__ __launch_bounds__(64) void k_axpy_dot(const double* __restrict__ v,
                                                  double* __restrict__ out, double* __restrict__ pdot) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
   double dt = 0.0;
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
-    out[i] = fr ? v[i] + alpha * dir[i] : v[i];
-    if (g) dt += fr ? g[i] * dir[i] : 0.0;
+    const bool fa = mpl_free(fl, a);
+    out[i] = fa ? v[i] + alpha * dir[i] : v[i];
+    if (g) dt += fa ? g[i] * dir[i] : 0.0;
   }
   if (pdot) {
     dt = wave_sum(dt);
@@ -1749,8 +1778,9 @@ template <class T>
 __global__ void k_mask_free(T* __restrict__ u, const uint8_t* __restrict__ flags, int64_t nnode) {
   int64_t ni = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ni >= nnode) return;
-  if (!(flags[ni] & MPL_NODE_FREE))
-    for (int a = 0; a < 3; ++a) u[a * nnode + ni] = T(0);
+  const uint8_t fl = flags[ni];
+  for (int a = 0; a < 3; ++a)
+    if (!mpl_free(fl, a)) u[a * nnode + ni] = T(0);
 }
 
 __global__ void k_neg(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -1809,10 +1839,10 @@ __global__ __launch_bounds__(256) void k_aa_gram(AAVecs f, int nv, const uint8_t
   __shared__ double sh[4];
   const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = nb < n_nblk && (flags[ni] & MPL_NODE_FREE);
+  const uint8_t fl = nb < n_nblk ? flags[ni] : (uint8_t)0;
   double x[5][3];
   for (int k = 0; k < nv; ++k)
-    for (int a = 0; a < 3; ++a) x[k][a] = fr ? f.p[k][a * nnode + ni] : 0.0;
+    for (int a = 0; a < 3; ++a) x[k][a] = mpl_free(fl, a) ? f.p[k][a * nnode + ni] : 0.0;
   int pair = 0;
   for (int i = 0; i < nv; ++i)
     for (int j = i; j < nv; ++j, ++pair) {
@@ -2722,7 +2752,7 @@ __global__ void k_extrapolate(const double* __restrict__ x1, const double* __res
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = 2.0 * x1[i] - x2[i];
 }
-// Galerkin start: per node block, the partial sums over free nodes of
+// Galerkin start: per node block, the partial sums over free components of
 // w_k . (H w_l) for k <= l (packed row by row) and then of w_k . b, for up to
 // GAL_MAX vectors (block layout, vector k at w + k * 3 nnode).
 #define GAL_MAX 3
@@ -2734,14 +2764,15 @@ __global__ __launch_bounds__(64) void k_gram(const double* __restrict__ w, const
                                              int64_t nnode, int nv, int n_nblk, double* __restrict__ part) {
   const int nb = blockIdx.x, l = threadIdx.x;
   const int64_t ni = (int64_t)nb * MPL_BC + l;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
   const int64_t n3 = 3 * nnode;
   const int ng = nv * (nv + 1) / 2;
   double acc[GAL_SUMS];
 #pragma unroll
   for (int q = 0; q < GAL_SUMS; ++q) acc[q] = 0.0;
-  if (fr) {
+  if (fl & MPL_NODE_FREE_ALL) {
     for (int a = 0; a < 3; ++a) {
+      if (!mpl_free(fl, a)) continue;
       const int64_t i = a * nnode + ni;
       double wv[GAL_MAX], yv[GAL_MAX];
 #pragma unroll
@@ -2809,18 +2840,18 @@ __global__ void k_to_prec(const double* __restrict__ w, T* __restrict__ u, int64
 struct GalCoef {
   double c[GAL_MAX];
 };
-// x0 = sum_k c_k w_k on free nodes, 0 elsewhere (block layout)
+// x0 = sum_k c_k w_k on the free components, 0 elsewhere (block layout)
 __global__ __launch_bounds__(64) void k_lincomb(const double* __restrict__ w, GalCoef cf, int nv,
                                                 const uint8_t* __restrict__ flags, int64_t nnode,
                                                 double* __restrict__ x0) {
   const int64_t ni = (int64_t)blockIdx.x * MPL_BC + threadIdx.x;
-  const bool fr = flags[ni] & MPL_NODE_FREE;
+  const uint8_t fl = flags[ni];
   const int64_t n3 = 3 * nnode;
   for (int a = 0; a < 3; ++a) {
     const int64_t i = a * nnode + ni;
     double v = 0.0;
     for (int k = 0; k < nv; ++k) v += cf.c[k] * w[k * n3 + i];
-    x0[i] = fr ? v : 0.0;
+    x0[i] = mpl_free(fl, a) ? v : 0.0;
   }
 }
 // out = 3 x1 - 3 x2 + x3 (dense node arrays)
@@ -3262,7 +3293,7 @@ mpl_status mpl_stage_solve(mpl_ctx* c, mpl_stats* st) {
     // iteration; writes p, s, u, r, dx every second and x every eighth
     {
       const double e = c->tangent_precision == MPL_F32 ? 4.0 : 8.0;
-      st->upd_model_bytes = (28.0 * e + 55.0) * c->hscal.n_free_nodes;
+      st->upd_model_bytes = (28.0 * e + 55.0) / 3.0 * c->hscal.n_free_dofs;
     }
     st->graph_replays = c->graph_replays;
     st->fallbacks = c->fallbacks_total;

@@ -449,6 +449,7 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
     for (int a = 0; a < 3; ++a) vv[a] = q[a] / m;
   uint8_t fl = 0;
   double vf[3] = {0.0, 0.0, 0.0};
+  int fixmask = 0;  // the prescribed components, one bit each
   if (m != 0.0) {
     fl |= MPL_NODE_ACTIVE;
     int4 bcrd = ncoord[nb];
@@ -464,26 +465,35 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
         if (xn[a] < bcs.lo[b][a] + sh - eps || xn[a] > bcs.hi[b][a] + sh + eps) in = false;
       }
       if (!in) continue;
-      fl |= MPL_NODE_FIXED;
+      if (bcs.kind[b] == MPL_BC_SLIP_PLANE) {
+        // a frictionless wall fixes the normal component only, to 0
+        fixmask |= 1 << bcs.axis[b];
+        vf[bcs.axis[b]] = 0.0;
+        continue;
+      }
+      fixmask = 7;
       for (int a = 0; a < 3; ++a) vf[a] = (bcs.kind[b] == MPL_BC_MOVING_BOX) ? bcs.vel[b][a] : 0.0;
     }
-    if (!(fl & MPL_NODE_FIXED)) fl |= MPL_NODE_FREE;
+    if (fixmask) fl |= MPL_NODE_FIXED;
+    fl |= (uint8_t)(((~fixmask) & 7) << 2);
   }
   {
-    // active and free node counts of the block (one wave), summed later by
-    // k_sum_counts: device-scope atomics on one address from every wave
-    // serialise at the memory side
-    const uint64_t ba = __ballot((fl & MPL_NODE_ACTIVE) != 0), bf = __ballot((fl & MPL_NODE_FREE) != 0);
+    // active node and free component counts of the block (one wave),
+    // summed later by k_sum_counts: device-scope atomics on one address
+    // from every wave serialise at the memory side
+    const uint64_t ba = __ballot((fl & MPL_NODE_ACTIVE) != 0);
+    int nfree = 0;
+    for (int a = 0; a < 3; ++a) nfree += __popcll(__ballot(mpl_free(fl, a)));
     if (l == 0) {
       counts[2 * nb] = (int32_t)__popcll(ba);
-      counts[2 * nb + 1] = (int32_t)__popcll(bf);
+      counts[2 * nb + 1] = nfree;
     }
   }
   const double grav[3] = {gx, gy, gz};
   mi[ni] = m;
   flags[ni] = fl;
   for (int a = 0; a < 3; ++a) {
-    double vh = (fl & MPL_NODE_FREE) ? vv[a] + dt * grav[a] : ((fl & MPL_NODE_FIXED) ? vf[a] : 0.0);
+    double vh = mpl_free(fl, a) ? vv[a] + dt * grav[a] : (((fixmask >> a) & 1) ? vf[a] : 0.0);
     vn[a * nnode + ni] = vv[a];
     vhat[a * nnode + ni] = vh;
     v[a * nnode + ni] = vh;
@@ -500,6 +510,16 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const doub
   if (n_bcs < 0 || n_bcs > 16 || (n_bcs > 0 && !bcs))
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "at most 16 boundary boxes");
   if (!(dt > 0.0)) return mpl_fail(c, MPL_ERR_INVALID_ARG, "dt must be positive");
+  for (int b = 0; b < n_bcs; ++b) {
+    const int k = bcs[b].kind;
+    if (k != MPL_BC_STICKY_BOX && k != MPL_BC_MOVING_BOX && k != MPL_BC_SLIP_PLANE)
+      return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown boundary condition kind");
+    if (k == MPL_BC_SLIP_PLANE) {
+      int nz = 0;
+      for (int a = 0; a < 3; ++a) nz += bcs[b].velocity[a] != 0.0;
+      if (nz != 1) return mpl_fail(c, MPL_ERR_INVALID_ARG, "a slip plane's normal must name one axis");
+    }
+  }
   c->unloaded = c->reconstructed = c->tangent_built = c->solved = false;
   c->dt = dt;
   c->np = in->n;
@@ -611,6 +631,9 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const doub
   bd.n = n_bcs;
   for (int b = 0; b < n_bcs; ++b) {
     bd.kind[b] = bcs[b].kind;
+    bd.axis[b] = 0;
+    for (int a = 0; a < 3; ++a)
+      if (bcs[b].kind == MPL_BC_SLIP_PLANE && bcs[b].velocity[a] != 0.0) bd.axis[b] = a;
     for (int a = 0; a < 3; ++a) {
       bd.lo[b][a] = bcs[b].lo[a];
       bd.hi[b][a] = bcs[b].hi[a];
@@ -625,7 +648,7 @@ mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const doub
              P<double>(c->mc), P<double>(c->qc), P<double>(c->Gc), ncell, nnode, c->n_nblk, P<BCDev>(c->bcbuf), time, dt, gr[0],
              gr[1], gr[2], P<double>(c->mi), P<double>(c->vn), P<double>(c->vhat), P<double>(c->v),
              P<uint8_t>(c->flags), P<int32_t>(c->cntbuf));
-  // n_active_nodes and n_free_nodes are adjacent in SolverScalars
+  // n_active_nodes and n_free_dofs are adjacent in SolverScalars
   MPL_LAUNCH(c, k_sum_counts, 1, 1024, P<int32_t>(c->cntbuf), c->n_nblk, 2, &ds->n_active_nodes);
   MPL_TRY(mpl_sync_scalars(c));
   if (c->hscal.err & 2) return mpl_fail(c, MPL_ERR_DOMAIN, "particle F outside the model domain (det F <= 0) or bad material id");

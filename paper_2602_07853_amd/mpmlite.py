@@ -20,7 +20,7 @@ PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_LEARNED = 0, 1, 2
 TRANSFER_APIC, TRANSFER_FLIP_PIC = 0, 1
 PLASTICITY_AFTER_SOLVE, PLASTICITY_FIXED_POINT = 0, 1
 NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
-BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
+BC_STICKY_BOX, BC_MOVING_BOX, BC_SLIP_PLANE = 0, 1, 2
 
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "OOM", -4: "NOT_CONVERGED",
           -5: "LINESEARCH", -6: "NONFINITE", -7: "DOMAIN", -8: "STATE"}

@@ -11,7 +11,9 @@ Common recipe (unit cube, origin 0, ``dx = 1/N``):
   sub-cell at a uniform random position inside the sub-cell (stratified
   jitter, NumPy PCG64 seeded per scene);
 * ``F_p = I``, ``m_p = rho dx^3 / ppc``, ``V_p = dx^3 / ppc``;
-* sticky walls: every node whose index is <= 1 or >= N-1 on some axis.
+* sticky walls: every node whose index is <= 1 or >= N-1 on some axis
+  (``BC_SLIP_PLANE`` boxes, frictionless walls with their normal in
+  ``velocity``, appear in the test scenes).
 
 Material and model codes match ``include/mpmlite.h``.
 """
@@ -24,7 +26,7 @@ import numpy as np
 
 NEOHOOKEAN, FIXED_COROTATED, HENCKY, WATER = 0, 1, 2, 3
 PLASTIC_NONE, PLASTIC_VON_MISES, PLASTIC_DRUCKER_PRAGER = 0, 1, 2
-BC_STICKY_BOX, BC_MOVING_BOX = 0, 1
+BC_STICKY_BOX, BC_MOVING_BOX, BC_SLIP_PLANE = 0, 1, 2
 
 
 @dataclass
@@ -371,6 +373,33 @@ def two_material_bar(seed: int = 7, n: int = 64, ppc_axis: int = 2, speed: float
     ]
     return Scene(f"two_material_bar_{n}", n, dx, 1e-3, 10, (0.0, -9.81, 0.0), mats, bcs, p,
                  occupied_cells=len(cells))
+
+
+def sand_cone(theta_deg: float, seed: int = 41, n: int = 48, radius: float = 0.3, E: float = 1e6,
+              friction_deg: float = 30.0, ppc_axis: int = 2, dt: float = 2e-3) -> Scene:
+    """A right circular cone of Drucker-Prager sand (Hencky, E = 1e6, nu = 0.3,
+    rho = 2000, friction angle ``friction_deg``) standing on the sticky floor of
+    the unit box: apex over the box centre, base radius ``radius`` at
+    y = 2 dx, flank slope ``theta_deg``; the cells whose centre lies inside
+    the cone are filled.  At rest, gravity, dt = 2e-3 (the sand-pile setting
+    of the paper's fixed-point plasticity comparison).  At n = 48 the 45 and
+    20 degree cones hold 25,120 and 9,120 particles."""
+    dx = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = math.tan(math.radians(theta_deg))
+    y0 = 2 * dx
+    c = (np.arange(n) + 0.5) * dx
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    r = np.hypot(X - 0.5, Z - 0.5)
+    inside = (Y >= y0) & (Y - y0 <= radius * t - r * t)
+    cells = np.argwhere(inside)
+    mats = [material(HENCKY, E, 0.3, 2000.0, PLASTIC_DRUCKER_PRAGER, 0.0, friction_deg)]
+    x = fill_cells(cells, dx, ppc_axis, rng)
+    ppc = ppc_axis ** 3
+    p = make_particles(x, np.zeros(len(x), np.int32), mats, dx, ppc)
+    return Scene(f"sand_cone_{int(round(theta_deg))}deg_{n}", n, dx, dt, 400, (0.0, -9.81, 0.0), mats,
+                 wall_bcs(n, dx), p, newton_rtol=1e-5, pcg_rtol=1e-5, occupied_cells=len(cells),
+                 meta=dict(theta_deg=theta_deg, radius=radius, floor_y=y0))
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 5: config5}

@@ -25,7 +25,7 @@ def oracle_state(sc, time=0.0):
     fixed, vfix = O.node_bcs(g, u["mi"], O.bcs_of(sc), time)
     grav = np.asarray(sc.gravity)
     act = u["mi"] > 0
-    vhat = np.where(fixed[:, None] > 0, vfix, np.where(act[:, None], u["vi"] + sc.dt * grav, 0.0))
+    vhat = np.where(O.fixed_components(fixed), vfix, np.where(act[:, None], u["vi"] + sc.dt * grav, 0.0))
     S, rc = O.reconstruct(g, mats, u["Vck"], u["tauck"])
     u.update(fixed=fixed, vhat=vhat, S=S, S_rc=rc, grid=g, mats=mats)
     return u
@@ -48,7 +48,28 @@ def small_scenes():
         "water_block": scenes.small_block(n=12, lo=3, hi=9, strain=0.05, model=scenes.WATER, E=2e5,
                                           seed=14, vel_std=0.2),
         "sand_water": sand_water(),
+        "slip_walls": slip_walls(),
     }
+
+
+def slip_walls(n=12, seed=16):
+    """A strained fixed-corotated block whose boundary nodes carry every
+    combination of fixed components: a frictionless floor (normal y) under
+    its two lowest node layers, a frictionless side wall (normal x) on its
+    two rightmost node layers, and a sticky back wall on its first z layer
+    (nodes on both slip walls have x and y fixed, nodes on the sticky wall
+    all three)."""
+    sc = scenes.small_block(n=n, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=seed,
+                            vel_std=0.2)
+    dx = sc.dx
+    big = 10.0
+    sc.bcs = scenes.wall_bcs(n, dx) + [
+        dict(kind=scenes.BC_SLIP_PLANE, lo=(-big, -big, -big), hi=(big, 4 * dx, big), velocity=(0.0, 1.0, 0.0)),
+        dict(kind=scenes.BC_SLIP_PLANE, lo=(8 * dx, -big, -big), hi=(big, big, big), velocity=(-1.0, 0.0, 0.0)),
+        dict(kind=scenes.BC_STICKY_BOX, lo=(-big, -big, -big), hi=(big, big, 3 * dx), velocity=(0.0, 0.0, 0.0)),
+    ]
+    sc.name = f"slip_walls_{n}"
+    return sc
 
 
 def sand_water(n=12, seed=15):

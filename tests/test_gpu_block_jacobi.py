@@ -48,9 +48,11 @@ def test_node_blocks_match_oracle(name, precision):
     assert rc == 0
     Bo, rc = O.block_jacobi(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], Ao)
     assert rc == 0
-    free = (ref["mi"] > 0) & (ref["fixed"] == 0)
+    notdof = O.fixed_components(ref["fixed"]) | (ref["mi"] <= 0)[:, None]   # [nodes, 3]
+    free = ~notdof.any(axis=1)   # nodes with every component free
     assert rel(B, Bo) <= (1e-10 if precision == 1 else 1e-5)
-    assert np.all(B[~free] == 0.0)
+    # rows and columns of fixed components and massless nodes are 0
+    assert np.all(B[notdof] == 0.0) and np.all(np.transpose(B, (0, 2, 1))[notdof] == 0.0)
     assert np.allclose(B, np.transpose(B, (0, 2, 1)), rtol=0, atol=0)
     # not a diagonal in disguise: the blocks couple the components
     off = np.abs(Bo[free] - Bo[free] * np.eye(3)).max() / np.abs(Bo[free]).max()
@@ -64,7 +66,7 @@ def test_pcg_residual_with_block_jacobi():
     v = ref["vhat"]
     ctx.build_tangent(torch.tensor(v, device="cuda"), 1)
     Ao, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
-    free = ((ref["mi"] > 0) & (ref["fixed"] == 0))[:, None]
+    free = (ref["mi"] > 0)[:, None] & ~O.fixed_components(ref["fixed"])
     b = np.random.default_rng(43).normal(size=v.shape) * free
     x, iters, relres = ctx.pcg(torch.tensor(b, device="cuda"))
     r = b - O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], Ao, host(x))

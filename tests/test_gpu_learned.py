@@ -12,7 +12,7 @@ from oracle import oracle as O
 from oracle import precond as PC
 from oracle import unet as U
 from paper_2602_07853_amd import scenes
-from tests.parity_util import gpu_context, oracle_state, rel
+from tests.parity_util import gpu_context, oracle_state, rel, slip_walls
 
 pytestmark = pytest.mark.gpu
 
@@ -23,10 +23,15 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module")
-def system():
+@pytest.fixture(scope="module", params=["block", "slip_walls"])
+def system(request):
+    """A strained block in sticky walls, and the block whose boundary nodes
+    carry every combination of fixed components (frictionless walls)."""
     from paper_2602_07853_amd import mpmlite
-    sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=41)
+    if request.param == "block":
+        sc = scenes.small_block(n=12, lo=3, hi=9, strain=0.05, E=1e6, model=scenes.FIXED_COROTATED, seed=41)
+    else:
+        sc = slip_walls()
     print(f"[learned] scene n={sc.n} particles={sc.n_particles}", flush=True)
     ref = oracle_state(sc)
     ctx = gpu_context(sc, 1)
@@ -72,7 +77,7 @@ def test_flexible_cg_reaches_true_residual(system):
     ctx.precond_set_weights(U.init_params(seed=5, scale=0.3).astype(np.float32))
     ctx.set_opts(precond=LEARNED, pcg_rtol=1e-10, max_pcg=4000)
     try:
-        free = ((ref["mi"] > 0) & (ref["fixed"] == 0))[:, None]
+        free = (ref["mi"] > 0)[:, None] & ~O.fixed_components(ref["fixed"])
         b = np.random.default_rng(6).normal(size=D.shape) * free
         x, iters, relres = ctx.pcg(torch.tensor(b, device="cuda"))
         res = b - O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, host(x))

@@ -639,7 +639,7 @@ def test_block_jacobi_cg_is_exact_on_one_free_node():
     sc, g, mats, u, fixed, vhat, S, A = block_jacobi_scene()
     free = np.nonzero((u["mi"] > 0) & (fixed == 0))[0]
     keep = free[np.argmax(u["mi"][free])]
-    fixed1 = np.ones_like(fixed)
+    fixed1 = np.full_like(fixed, 7)  # all three components fixed
     fixed1[keep] = 0
     args = (g, mats, sc.dt, u["mc"], u["mi"], vhat, fixed1, u["Vck"], S)
     vb, stb, rc = O.solve(*args, O.SolverOpts(1e-10, 1e-12, block_jacobi=1))

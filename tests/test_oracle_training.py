@@ -38,19 +38,19 @@ def _system(seed=31, E=1e7):
 
 def _solve(H, D, r, tol=1e-14):
     """x = H^{-1} r on the free DOFs with SciPy's CG (Jacobi preconditioned)."""
-    fr = np.flatnonzero(PC._free(D))
-    n = len(fr)
+    fr = PC._free(D)   # [nodes, 3]: the free DOFs
+    n = int(fr.sum())
 
     def mv(y):
         u = np.zeros(D.shape)
-        u[fr] = y.reshape(-1, 3)
-        return H(u)[fr].ravel()
-    op = spla.LinearOperator((3 * n, 3 * n), matvec=mv)
-    pre = spla.LinearOperator((3 * n, 3 * n), matvec=lambda y: y / D[fr].ravel())
-    sol, info = spla.cg(op, r[fr].ravel(), rtol=tol, atol=0.0, maxiter=20000, M=pre)
+        u[fr] = y
+        return H(u)[fr]
+    op = spla.LinearOperator((n, n), matvec=mv)
+    pre = spla.LinearOperator((n, n), matvec=lambda y: y / D[fr])
+    sol, info = spla.cg(op, r[fr], rtol=tol, atol=0.0, maxiter=20000, M=pre)
     assert info == 0
     x = np.zeros(D.shape)
-    x[fr] = sol.reshape(-1, 3)
+    x[fr] = sol
     return x
 
 

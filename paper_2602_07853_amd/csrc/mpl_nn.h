@@ -22,12 +22,19 @@ struct NNState {
   size_t sw_fwd_off[NN_LAYERS] = {}, sw_bwd_off[NN_LAYERS] = {};
   // 3x3x3 layers: weights for the LDS-tiled kernel (forward, data gradient)
   size_t sw3_fwd_off[NN_LAYERS] = {}, sw3_bwd_off[NN_LAYERS] = {};
+  // 3x3x3 layers with 16 output channels: weights for the register-blocked
+  // kernel (forward when the layer has 16 outputs, data gradient when it has
+  // 16 inputs; 0 = none)
+  size_t sw3rr_fwd_off[NN_LAYERS] = {}, sw3rr_bwd_off[NN_LAYERS] = {};
   int box[3] = {0, 0, 0};
   size_t t_in = 0, t_out = 0, t_cat[3] = {0, 0, 0}, t_lay[NN_LAYERS] = {};
   size_t act_elems = 0;
   int64_t adam_t = 0;
   bool ready = false;
   bool lds_conv = true;  // 3x3x3 layers on the LDS-tiled kernel (MPL_NN_DIRECT_CONV=1: direct kernel)
+  bool rr_conv = true;   // 16-output-channel 3x3x3 layers on the register-blocked kernel (MPL_NN_RR_CONV=0: off)
+  int rr_grid = 0;       // workgroups of the register-blocked kernel (resident on the device at once)
+  int lds_grid[4] = {0, 0, 0, 0};  // the same for the LDS-tiled kernel, CT = 1, 2, 4, 8
 };
 
 int64_t nn_param_count();

@@ -126,14 +126,22 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, in
 
 // ---------------------------------------------------------------- LDS-tiled 3x3x3 conv
 // 3x3x3 stride-1 pad-1 convolution (forward, and the data gradient with the
-// flipped-tap weights).  A workgroup (4 wavefronts) computes a 4 (x) x 4 (y)
-// x 16 (z) output tile for all CT*16 output channels: wavefront w owns
+// flipped-tap weights).  An output tile is 4 (x) x 4 (y) x 16 (z) voxels for
+// CT*16 of the output channels (blockIdx.y selects which); wavefront w owns
 // x = x0 + w and the four 16-voxel z-strips y0..y0+3.  The input tile with
 // its one-voxel halo (6 x 6 x 18 voxels) is staged in LDS 16 channels at a
 // time, so every input value is read from memory once per workgroup and
 // chunk instead of once per tap; an MFMA K step covers two taps x the 16
-// channels of the chunk (14 steps per chunk, the last one half empty).
+// channels of the chunk (14 steps per chunk, the last one half empty), and
+// each B operand read from LDS feeds the CT output-channel tiles.  The
+// workgroups stride over the (tile, chunk) items, and the global loads of the
+// next item are issued before the MFMAs of the current one.
 // Wsw: [chunk][kstep 0..13][CT][64 lanes][8] (swizzle modes 3 and 4).
+namespace lds3 {
+constexpr int HX = 6, HY = 6, HZ = 18, NV = HX * HY * HZ;
+constexpr int PER = (NV * 2 + 255) / 256;
+}  // namespace lds3
+
 template <int CT>
 __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ x, int ldx, Dims3 d,
                                                    int Ci, const uint16_t* __restrict__ Wsw, int CTT,
@@ -141,37 +149,54 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
                                                    uint16_t* __restrict__ y, int ldy, int relu,
                                                    int accum, const int32_t* __restrict__ skip) {
   // blockIdx.y selects output channels [16 CT y, 16 CT (y + 1)) of the CTT*16
+  using namespace lds3;
   if (skip && *skip) return;
-  constexpr int HX = 6, HY = 6, HZ = 18, NV = HX * HY * HZ;
-  __shared__ uint4 tile[NV * 2];  // [voxel][two halves of 8 channels]
+  __shared__ uint4 tile[2 * NV];  // [channel half][voxel]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nbx = (d.x + 3) >> 2, nby = (d.y + 3) >> 2;
-  int b = blockIdx.x;
-  const int bz = b / (nbx * nby);
-  b -= bz * nbx * nby;
-  const int by = b / nbx, bx = b - by * nbx;
-  const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+  const int nbx = (d.x + 3) >> 2, nby = (d.y + 3) >> 2, nbz = (d.z + 15) >> 4;
+  const int ntiles = nbx * nby * nbz;
   const int j = lane & 15, g = lane >> 4;
+  const int nchunk = Ci >> 4;
+  const int ct0 = blockIdx.y * CT;
+  uint4 pre[PER];
+  auto fetch = [&](int t, int q) {
+    const int bz = t / (nbx * nby), rem = t - bz * nbx * nby;
+    const int by = rem / nbx, bx = rem - by * nbx;
+    const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      const int h = idx & 1, vv = idx >> 1;
+      const int hz = vv % HZ, hy = (vv / HZ) % HY, hx = vv / (HZ * HY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      pre[k] = make_uint4(0, 0, 0, 0);
+      if (idx < NV * 2 && gx >= 0 && gy >= 0 && gz >= 0 && gx < d.x && gy < d.y && gz < d.z)
+        pre[k] = *reinterpret_cast<const uint4*>(x + (((int64_t)gx * d.y + gy) * d.z + gz) * ldx + q * 16 + h * 8);
+    }
+  };
   f32x4 acc[4][CT];
 #pragma unroll
   for (int st = 0; st < 4; ++st)
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[st][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nchunk = Ci >> 4;
-  for (int q = 0; q < nchunk; ++q) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NV * 2; idx += 256) {
-      const int h = idx & 1, vv = idx >> 1;
-      const int hz = vv % HZ, hy = (vv / HZ) % HY, hx = vv / (HZ * HY);
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.x && gy < d.y && gz < d.z)
-        val = *reinterpret_cast<const uint4*>(x + (((int64_t)gx * d.y + gy) * d.z + gz) * ldx + q * 16 + h * 8);
-      tile[idx] = val;
+  int t = blockIdx.x, q = 0;
+  if (t >= ntiles) return;
+  fetch(t, 0);
+  while (true) {
+    __syncthreads();  // every wavefront is done reading the previous item's tile
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      if (idx < NV * 2) tile[(idx & 1) * NV + (idx >> 1)] = pre[k];
     }
     __syncthreads();
+    int tn = t, qn = q + 1;
+    if (qn == nchunk) {
+      qn = 0;
+      tn = t + (int)gridDim.x;
+    }
+    if (tn < ntiles) fetch(tn, qn);
     const uint16_t* Wq = Wsw + (int64_t)q * 14 * CTT * 512;
-    const int ct0 = blockIdx.y * CT;
     for (int m = 0; m < 14; ++m) {
       const int tap = 2 * m + (g >> 1);
       bf16x8 aop[CT];
@@ -184,37 +209,226 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         const int hv = ((w + tx) * HY + (st + ty)) * HZ + (j + tz);
-        const uint4 raw = tv ? tile[hv * 2 + (g & 1)] : make_uint4(0, 0, 0, 0);
+        const uint4 raw = tv ? tile[(g & 1) * NV + hv] : make_uint4(0, 0, 0, 0);
         const bf16x8 bop = __builtin_bit_cast(bf16x8, raw);
 #pragma unroll
         for (int c = 0; c < CT; ++c)
           acc[st][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[c], bop, acc[st][c], 0, 0, 0);
       }
     }
-  }
-  const int ox = x0 + w, oz = z0 + j;
+    if (q == nchunk - 1) {
+      const int bz = t / (nbx * nby), rem = t - bz * nbx * nby;
+      const int by = rem / nbx, bx = rem - by * nbx;
+      const int ox = bx * 4 + w, oz = bz * 16 + j;
 #pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const int oy = y0 + st;
-    if (ox >= d.x || oy >= d.y || oz >= d.z) continue;
-    const int64_t v = ((int64_t)ox * d.y + oy) * d.z + oz;
+      for (int st = 0; st < 4; ++st) {
+        const int oy = by * 4 + st;
+        const bool ok = ox < d.x && oy < d.y && oz < d.z;
+        const int64_t v = ((int64_t)ox * d.y + oy) * d.z + oz;
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int o0 = (blockIdx.y * CT + c) * 16 + g * 4;
-      uint16_t* dst = y + v * ldy + o0;
-      float r[4];
+        for (int c = 0; c < CT; ++c) {
+          if (ok) {
+            const int o0 = (ct0 + c) * 16 + g * 4;
+            uint16_t* dst = y + v * ldy + o0;
+            float r[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float val = acc[st][c][e] + (bias ? bias[o0 + e] : 0.f);
-        if (accum) val += bf2f(dst[e]);
-        if (relu) val = fmaxf(val, 0.f);
-        r[e] = val;
+            for (int e = 0; e < 4; ++e) {
+              float val = acc[st][c][e] + (bias ? bias[o0 + e] : 0.f);
+              if (accum) val += bf2f(dst[e]);
+              if (relu) val = fmaxf(val, 0.f);
+              r[e] = val;
+            }
+            const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                            (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+            *reinterpret_cast<uint2*>(dst) = packed;
+          }
+          acc[st][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
       }
-      const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
-                                      (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
-      *reinterpret_cast<uint2*>(dst) = packed;
     }
+    if (tn >= ntiles) break;
+    t = tn;
+    q = qn;
   }
+}
+
+// ---------------------------------------------------------------- register-blocked 3x3x3 conv
+// 3x3x3 stride-1 pad-1 convolution with 16 output channels (the finest level
+// of the network, forward, and the data gradient of its 16-channel layers).
+// With one output-channel tile k_conv3_lds feeds one MFMA per LDS read; here
+// a B operand is reused across the output rows it reaches.  An output tile
+// is 8 (x) x 4 (y) x 16 (z) voxels; wavefront w of the workgroup owns
+// x = x0 + 2w, x0 + 2w + 1 and y = y0 .. y0 + 3, eight 16-voxel z strips.
+// The input tile with its one-voxel halo (10 x 6 x 18 voxels, 16 channels)
+// is staged in LDS per 16-channel chunk.  One MFMA K step covers the z taps
+// 0 and 1 x 16 channels (step 0) or the z tap 2 x 16 channels with 16 zero
+// channels (step 1), so a B operand is one input row (x, y) at two z shifts,
+// and it serves every strip (x - tx, y - ty) of the wavefront: up to six
+// MFMAs per LDS read.  The weights of all nine (tx, ty) pairs and both steps
+// stay in registers for the chunk (for the whole launch when Ci = 16).
+// The workgroups stride over the (tile, chunk) items, and the global loads
+// of the next item are issued before the MFMAs of the current one, so their
+// latency hides behind the arithmetic instead of stalling the workgroup.
+// Wrr: [chunk][tx*3 + ty][step][64 lanes][8] bf16 (swizzle modes 3 and 4).
+namespace rr {
+constexpr int HX = 10, HY = 6, HZ = 18, NV = HX * HY * HZ;
+constexpr int PER = (NV * 2 + 255) / 256;  // staged 16-byte pieces per thread
+}  // namespace rr
+
+__global__ __launch_bounds__(256) void k_conv3_rr(const uint16_t* __restrict__ x, int ldx, Dims3 d,
+                                                  int Ci, const uint16_t* __restrict__ Wrr,
+                                                  const float* __restrict__ bias,
+                                                  uint16_t* __restrict__ y, int ldy, int relu,
+                                                  int accum, const int32_t* __restrict__ skip) {
+  using namespace rr;
+  if (skip && *skip) return;
+  // [channel half][voxel]: the 16 lanes of an MFMA column group read 16
+  // consecutive voxels of one half, 256 contiguous bytes
+  __shared__ uint4 tile[2 * NV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nbx = (d.x + 7) >> 3, nby = (d.y + 3) >> 2, nbz = (d.z + 15) >> 4;
+  const int ntiles = nbx * nby * nbz;
+  const int j = lane & 15, g = lane >> 4;
+  const int nchunk = Ci >> 4;
+  // this lane's LDS position in its wavefront's rows: x row 2w, z = j, the
+  // channel half g & 1; step 0 reads z shift g >> 1, step 1 shift 2 (lanes
+  // g >= 2 of step 1 carry the zero channels)
+  const int lbase = (g & 1) * NV + (2 * w) * HY * HZ + j;
+  const int sh0 = g >> 1;
+  const bool has1 = g < 2;
+  uint4 pre[PER];
+  auto fetch = [&](int t, int q) {
+    const int bz = t / (nbx * nby), rem = t - bz * nbx * nby;
+    const int by = rem / nbx, bx = rem - by * nbx;
+    const int x0 = bx * 8, y0 = by * 4, z0 = bz * 16;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      const int h = idx & 1, vv = idx >> 1;
+      const int hz = vv % HZ, hy = (vv / HZ) % HY, hx = vv / (HZ * HY);
+      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+      pre[k] = make_uint4(0, 0, 0, 0);
+      if (idx < NV * 2 && gx >= 0 && gy >= 0 && gz >= 0 && gx < d.x && gy < d.y && gz < d.z)
+        pre[k] = *reinterpret_cast<const uint4*>(x + (((int64_t)gx * d.y + gy) * d.z + gz) * ldx + q * 16 + h * 8);
+    }
+  };
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int sx = 0; sx < 2; ++sx)
+#pragma unroll
+    for (int sy = 0; sy < 4; ++sy) acc[sx][sy] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the weights of the chunk (loaded once when there is only one)
+  bf16x8 A[9][2];
+  auto loadA = [&](int q) {
+    const uint16_t* Wq = Wrr + (int64_t)q * 18 * 512;
+#pragma unroll
+    for (int tt = 0; tt < 9; ++tt)
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+        A[tt][st] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(Wq + ((tt * 2 + st) * 64 + lane) * 8));
+  };
+  int t = blockIdx.x, q = 0;
+  if (t >= ntiles) return;
+  fetch(t, 0);
+  if (nchunk == 1) loadA(0);
+  while (true) {
+    __syncthreads();  // every wavefront is done reading the previous item's tile
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + 256 * k;
+      if (idx < NV * 2) tile[(idx & 1) * NV + (idx >> 1)] = pre[k];
+    }
+    if (nchunk > 1) loadA(q);
+    __syncthreads();
+    int tn = t, qn = q + 1;
+    if (qn == nchunk) {
+      qn = 0;
+      tn = t + (int)gridDim.x;
+    }
+    if (tn < ntiles) fetch(tn, qn);
+#pragma unroll
+    for (int hx = 0; hx < 4; ++hx)
+#pragma unroll
+      for (int hy = 0; hy < HY; ++hy) {
+        const int row = lbase + (hx * HY + hy) * HZ;
+        const bf16x8 bs[2] = {__builtin_bit_cast(bf16x8, tile[row + sh0]),
+                              __builtin_bit_cast(bf16x8, has1 ? tile[row + 2] : make_uint4(0, 0, 0, 0))};
+        // the two steps in separate passes, so that consecutive MFMAs update
+        // different accumulators
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+          for (int tx = 0; tx < 3; ++tx)
+#pragma unroll
+            for (int ty = 0; ty < 3; ++ty) {
+              const int sx = hx - tx, sy = hy - ty;
+              if (sx < 0 || sx > 1 || sy < 0 || sy > 3) continue;
+              acc[sx][sy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[tx * 3 + ty][st], bs[st], acc[sx][sy], 0, 0, 0);
+            }
+      }
+    if (q == nchunk - 1) {
+      const int bz = t / (nbx * nby), rem = t - bz * nbx * nby;
+      const int by = rem / nbx, bx = rem - by * nbx;
+      const int x0 = bx * 8, y0 = by * 4, oz = bz * 16 + j;
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx)
+#pragma unroll
+        for (int sy = 0; sy < 4; ++sy) {
+          const int ox = x0 + 2 * w + sx, oy = y0 + sy;
+          if (ox < d.x && oy < d.y && oz < d.z) {
+            const int64_t v = ((int64_t)ox * d.y + oy) * d.z + oz;
+            const int o0 = g * 4;
+            uint16_t* dst = y + v * ldy + o0;
+            float r[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              float val = acc[sx][sy][e] + (bias ? bias[o0 + e] : 0.f);
+              if (accum) val += bf2f(dst[e]);
+              if (relu) val = fmaxf(val, 0.f);
+              r[e] = val;
+            }
+            const uint2 packed = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                            (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+            *reinterpret_cast<uint2*>(dst) = packed;
+          }
+          acc[sx][sy] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (tn >= ntiles) break;
+    t = tn;
+    q = qn;
+  }
+}
+
+// Weights of k_conv3_rr: out[((q*9 + tx*3 + ty)*2 + st)*64 + lane][e], output
+// channel lane & 15, group gg = lane >> 4; step 0: z tap gg >> 1, step 1: z
+// tap 2 for gg < 2 and zero for gg >= 2; input channel 16q + (gg & 1)*8 + e;
+//   mode 3 (forward): W[tap][in][out];  mode 4 (data gradient): W[26 - tap][out][in],
+// tap = (tx*3 + ty)*3 + tz.
+__global__ void k_swizzle3rr(const float* __restrict__ W, int Ci, int Co, int mode, int nchunk,
+                             uint16_t* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nchunk * 18 * 512;
+  if (idx >= total) return;
+  int64_t r = idx;
+  const int e = (int)(r % 8);
+  r /= 8;
+  const int lane = (int)(r % 64);
+  r /= 64;
+  const int st = (int)(r % 2);
+  r /= 2;
+  const int txy = (int)(r % 9);
+  const int q = (int)(r / 9);
+  const int gg = lane >> 4;
+  const int tz = st == 0 ? (gg >> 1) : (gg < 2 ? 2 : -1);
+  const int cin = 16 * q + (gg & 1) * 8 + e, cout = lane & 15;
+  float val = 0.f;
+  if (tz >= 0) {
+    const int tap = txy * 3 + tz;
+    if (mode == 3) val = W[((int64_t)tap * Ci + cin) * Co + cout];
+    else val = W[((int64_t)(26 - tap) * Ci + cout) * Co + cin];
+  }
+  out[idx] = f2bf(val);
 }
 
 // Weights of k_conv3_lds: out[((q*14 + m)*CT + ct)*64 + lane][e] with
@@ -598,6 +812,14 @@ static mpl_status nn_alloc(mpl_ctx* c, NNState& nn) {
       sw += k3;
       nn.sw3_bwd_off[l] = sw;
       sw += k3;
+      if (s.co == 16) {
+        nn.sw3rr_fwd_off[l] = sw;
+        sw += (size_t)(s.ci / 16) * 18 * 512;
+      }
+      if (s.ci == 16) {
+        nn.sw3rr_bwd_off[l] = sw;
+        sw += (size_t)(s.co / 16) * 18 * 512;
+      }
     }
   }
   MPL_TRY(mpl_ensure(c, nn.wsw, 2 * sw + 256));
@@ -633,6 +855,16 @@ static mpl_status nn_refresh(mpl_ctx* c, NNState& nn) {
                    sw + nn.sw3_fwd_off[l]);
         MPL_LAUNCH(c, k_swizzle3, (int)((n3 + 255) / 256), 256, W, s.ci, s.co, 4, s.ci / 16, s.co / 16,
                    sw + nn.sw3_bwd_off[l]);
+        if (s.co == 16) {
+          const int64_t nr = (int64_t)(s.ci / 16) * 18 * 512;
+          MPL_LAUNCH(c, k_swizzle3rr, (int)((nr + 255) / 256), 256, W, s.ci, s.co, 3, s.ci / 16,
+                     sw + nn.sw3rr_fwd_off[l]);
+        }
+        if (s.ci == 16) {
+          const int64_t nr = (int64_t)(s.co / 16) * 18 * 512;
+          MPL_LAUNCH(c, k_swizzle3rr, (int)((nr + 255) / 256), 256, W, s.ci, s.co, 4, s.co / 16,
+                     sw + nn.sw3rr_bwd_off[l]);
+        }
       }
       if (s.k == 2) {
         // dgrad of a stride-2 down conv is an up-type layer with A[m=i][k=(t,o)], K per tap
@@ -757,8 +989,20 @@ static mpl_status launch_conv(mpl_ctx* c, View in, Dims3 din, const uint16_t* ws
 template <int CT>
 static mpl_status launch_conv3_ct(mpl_ctx* c, View in, Dims3 d, const uint16_t* wsw, int Ci, int CTT,
                                   const float* bias, View out, int relu, int accum, const int32_t* skip) {
-  const int64_t nwg = (int64_t)((d.x + 3) / 4) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
-  hipLaunchKernelGGL((k_conv3_lds<CT>), dim3((unsigned)nwg, CTT / CT), dim3(256), 0, c->stream, in.p,
+  // as many workgroups as fit on the device at once (they stride over the
+  // tiles), at most one per tile and output-channel group
+  NNState& nn = *nn_state(c);
+  int& resident = nn.lds_grid[CT == 1 ? 0 : (CT == 2 ? 1 : (CT == 4 ? 2 : 3))];
+  if (resident == 0) {
+    int cus = 0, per_cu = 0;
+    MPL_HIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    MPL_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3_lds<CT>, 256, 0));
+    resident = std::max(1, cus) * std::max(1, per_cu);
+  }
+  const int ny = CTT / CT;
+  const int64_t ntiles = (int64_t)((d.x + 3) / 4) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
+  const int nwg = (int)std::min<int64_t>(ntiles, std::max(1, resident / ny));
+  hipLaunchKernelGGL((k_conv3_lds<CT>), dim3((unsigned)nwg, ny), dim3(256), 0, c->stream, in.p,
                      in.ld, d, Ci, wsw, CTT, bias, out.p, out.ld, relu, accum, skip);
   MPL_HIP(c, hipGetLastError());
   return MPL_OK;
@@ -780,6 +1024,27 @@ static mpl_status launch_conv3(mpl_ctx* c, View in, Dims3 d, const uint16_t* wsw
     case 8: return launch_conv3_ct<8>(c, in, d, wsw, Ci, CTT, bias, out, relu, accum, skip);
   }
   return mpl_fail(c, MPL_ERR_INVALID_ARG, "unsupported channel count");
+}
+// 3x3x3 stride-1 convolution with Ci input (a multiple of 16) and 16 output
+// channels on the register-blocked kernel.
+static mpl_status launch_conv3_rr(mpl_ctx* c, View in, Dims3 d, const uint16_t* wrr, int Ci,
+                                  const float* bias, View out, int relu, int accum,
+                                  const int32_t* skip = nullptr) {
+  // as many workgroups as fit on the device at once (they stride over the
+  // tiles), at most one per tile
+  NNState& nn = *nn_state(c);
+  if (nn.rr_grid == 0) {
+    int cus = 0, per_cu = 0;
+    MPL_HIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    MPL_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_conv3_rr, 256, 0));
+    nn.rr_grid = std::max(1, cus) * std::max(1, per_cu);
+  }
+  const int64_t ntiles = (int64_t)((d.x + 7) / 8) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
+  const int nwg = (int)std::min<int64_t>(ntiles, nn.rr_grid);
+  hipLaunchKernelGGL(k_conv3_rr, dim3((unsigned)nwg), dim3(256), 0, c->stream, in.p, in.ld, d, Ci, wrr,
+                     bias, out.p, out.ld, relu, accum, skip);
+  MPL_HIP(c, hipGetLastError());
+  return MPL_OK;
 }
 template <int CT>
 static mpl_status launch_up_ct(mpl_ctx* c, View in, Dims3 din, const uint16_t* wsw, int nk,
@@ -818,6 +1083,8 @@ static mpl_status nn_forward_layer(mpl_ctx* c, NNState& nn, int l) {
   if (s.up) {
     MPL_TRY(launch_up(c, in, din, sw + nn.sw_fwd_off[l], (s.ci + 31) / 32, s.co, bias, out, s.relu, 0,
                       nn.skip));
+  } else if (s.k == 3 && nn.lds_conv && nn.rr_conv && s.co == 16) {
+    MPL_TRY(launch_conv3_rr(c, in, din, sw + nn.sw3rr_fwd_off[l], s.ci, bias, out, s.relu, 0, nn.skip));
   } else if (s.k == 3 && nn.lds_conv) {
     MPL_TRY(launch_conv3(c, in, din, sw + nn.sw3_fwd_off[l], s.ci, s.co, bias, out, s.relu, 0, nn.skip));
   } else {
@@ -884,6 +1151,8 @@ static mpl_status nn_backward_layer(mpl_ctx* c, NNState& nn, int l, bool input_g
   } else if (s.k == 2) {
     MPL_TRY(launch_up(c, gout, dout, sw + nn.sw_bwd_off[l], (s.co + 31) / 32, s.ci, nullptr, gin, 0,
                       accum));
+  } else if (s.k == 3 && nn.lds_conv && nn.rr_conv && s.ci == 16) {
+    MPL_TRY(launch_conv3_rr(c, gout, dout, sw + nn.sw3rr_bwd_off[l], s.co, nullptr, gin, 0, accum));
   } else if (s.k == 3 && nn.lds_conv) {
     MPL_TRY(launch_conv3(c, gout, dout, sw + nn.sw3_bwd_off[l], s.co, s.ci, nullptr, gin, 0, accum));
   } else {
@@ -952,6 +1221,8 @@ NNState* nn_state(mpl_ctx* c) {
     c->nn = new NNState();
     const char* dc = std::getenv("MPL_NN_DIRECT_CONV");
     c->nn->lds_conv = !(dc && dc[0] == '1');
+    const char* rr = std::getenv("MPL_NN_RR_CONV");
+    c->nn->rr_conv = !(rr && rr[0] == '0');
   }
   return c->nn;
 }

@@ -3,6 +3,7 @@ reads for its ``traffic`` fields and prints the tables kept under profiles/).
 
     python3 -m paper_2602_07853_amd.profile_summary counters FETCH_DIR WRITE_DIR INFO_JSON OUT_JSON
     python3 -m paper_2602_07853_amd.profile_summary trace TRACE_DIR
+    python3 -m paper_2602_07853_amd.profile_summary busy PMC_DIR [PMC_DIR ...]
 
 ``counters``: FETCH_DIR and WRITE_DIR hold the results databases of two
 ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
@@ -15,6 +16,10 @@ OUT_JSON keeps one entry per workload.
 
 ``trace``: the kernel dispatches of a ``rocprofv3 --kernel-trace --stats``
 run (its results database), as a Markdown table of the top kernels.
+
+``busy``: every counter of one or more ``rocprofv3 --pmc`` runs (for
+instance VALUBusy, MfmaUtil, SQ_INSTS_VALU), as a Markdown table of the
+median per dispatch of the two CG kernels.
 """
 from __future__ import annotations
 
@@ -93,10 +98,30 @@ def trace(trace_dir, top=25):
               f"{statistics.median(v):.2f} | {100 * sum(v) / total:.1f} |")
 
 
+def busy(dirs):
+    rows = {}
+    for d in dirs:
+        con = _db(d)
+        for name, kname, v in con.execute("select counter_name, kernel_name, value from counters_collection"):
+            for label, match in (("k_hv_fused", "k_hv_fused"), ("k_cg_step", "k_cg_step")):
+                if match in kname:
+                    rows.setdefault(name, {}).setdefault(label, []).append(float(v))
+    print("| counter | `k_hv_fused` (median per dispatch) | `k_cg_step` (median per dispatch) |")
+    print("|---|---:|---:|")
+    for name in sorted(rows):
+        cells = []
+        for label in ("k_hv_fused", "k_cg_step"):
+            v = rows[name].get(label)
+            cells.append(f"{statistics.median(v):.4g}" if v else "-")
+        print(f"| {name} | {cells[0]} | {cells[1]} |")
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "counters" and len(sys.argv) == 6:
         counters(*sys.argv[2:])
     elif len(sys.argv) >= 2 and sys.argv[1] == "trace" and len(sys.argv) == 3:
         trace(sys.argv[2])
+    elif len(sys.argv) >= 3 and sys.argv[1] == "busy":
+        busy(sys.argv[2:])
     else:
         raise SystemExit(__doc__)

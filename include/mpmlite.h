@@ -421,9 +421,11 @@ mpl_status mpl_nn_layer_grad(mpl_ctx* ctx, int32_t layer, const float* x, const 
 /* One Adam step (lr, betas 0.9/0.999, eps 1e-8) on the masked relative L2
  * loss |m (y - t)|^2 / |m t|^2 over output channels 0-2: x [X][Y][Z][16],
  * t [X][Y][Z][3], mask [X][Y][Z] (FP32, device).  *loss (host, may be NULL)
- * receives the loss before the step. */
+ * receives the loss before the step; grads_out (device FP32,
+ * mpl_precond_param_count values, may be NULL) the parameter gradient of
+ * that loss, the one the step applies. */
 mpl_status mpl_precond_train_step(mpl_ctx* ctx, const float* x, const float* t, const float* mask,
-                                  const int32_t dims[3], float lr, float* loss);
+                                  const int32_t dims[3], float lr, float* loss, float* grads_out);
 /* z = learned preconditioner applied to r at the Jacobi diagonal of the last
  * mpl_build_tangent (r, z dense device FP64 node vectors). */
 mpl_status mpl_precond_apply(mpl_ctx* ctx, const double* r, double* z);

@@ -1315,9 +1315,10 @@ mpl_status mpl_nn_backward(mpl_ctx* c, const float* x, const int32_t dims[3], co
 
 // One Adam step on the masked relative L2 loss of one sample (device
 // tensors: x [X][Y][Z][16] FP32 features, t [X][Y][Z][3] FP32 targets,
-// mask [X][Y][Z] FP32).  loss (host, may be NULL) gets the loss before the step.
+// mask [X][Y][Z] FP32).  loss (host, may be NULL) gets the loss before the
+// step, grads_out (device, may be NULL) the parameter gradient it applies.
 mpl_status mpl_precond_train_step(mpl_ctx* c, const float* x, const float* t, const float* mask,
-                                  const int32_t dims[3], float lr, float* loss) {
+                                  const int32_t dims[3], float lr, float* loss, float* grads_out) {
   if (!c || !x || !t || !mask || !dims) return MPL_ERR_INVALID_ARG;
   if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "no network weights");
   NNState& nn = *c->nn;
@@ -1337,6 +1338,8 @@ mpl_status mpl_precond_train_step(mpl_ctx* c, const float* x, const float* t, co
   const int64_t np = nn_param_count();
   MPL_HIP(c, hipMemsetAsync(nn.grad.p, 0, 4 * np, c->stream));
   MPL_TRY(nn_backward(c, nn));
+  if (grads_out)
+    MPL_HIP(c, hipMemcpyAsync(grads_out, nn.grad.p, 4 * np, hipMemcpyDeviceToDevice, c->stream));
   nn.adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)nn.adam_t), c2 = 1.f - powf(b2, (float)nn.adam_t);

@@ -457,15 +457,23 @@ class Context:
                 (3, 32, 16), (3, 16, 16), (1, 16, 16)]
         return [k ** 3 * ci * co + co for k, ci, co in spec]
 
-    def precond_train_step(self, x, t, mask, lr):
+    def precond_train_step(self, x, t, mask, lr, grads_out: torch.Tensor = None):
+        """One Adam step on the pair loss; returns the loss before the step.
+        grads_out (FP32 CUDA, precond_param_count values) receives the
+        parameter gradient the step applies."""
         self._check_box(x, "x", 16)
         self._check_box(t, "t", 3, like=x)
         self._check_box(mask, "mask", None, like=x)
+        if grads_out is not None and (grads_out.dtype != torch.float32 or not grads_out.is_cuda
+                                      or not grads_out.is_contiguous()
+                                      or grads_out.numel() != self.precond_param_count()):
+            raise ValueError("grads_out: contiguous FP32 CUDA tensor of precond_param_count() values")
         dims = (C.c_int32 * 3)(*x.shape[:3])
         loss = C.c_float()
         self._check(self._lib.mpl_precond_train_step(
             self._ctx, C.c_void_p(_dptr(x, torch.float32)), C.c_void_p(_dptr(t, torch.float32)),
-            C.c_void_p(_dptr(mask, torch.float32)), dims, C.c_float(lr), C.byref(loss)),
+            C.c_void_p(_dptr(mask, torch.float32)), dims, C.c_float(lr), C.byref(loss),
+            C.c_void_p(grads_out.data_ptr() if grads_out is not None else None)),
             "mpl_precond_train_step")
         return loss.value
 

@@ -4,9 +4,13 @@ MFMA forward/backward, Adam on FP32 master weights; this module only
 sequences the calls and stores the weights).
 
     python -m paper_2602_07853_amd.precond_train --config 3 --out weights.npy
+    python -m paper_2602_07853_amd.precond_train --configs 2,3 --eval-steps 5 --out weights.npy
 
 collects (residual, error) pairs from the Jacobi-PCG solves of the first
-``--collect-steps`` implicit steps of the scene and trains on them.
+``--collect-steps`` implicit steps of the scene (or of several scenes, the
+corpus of the learned-preconditioner configuration: pairs from the 64^3 and
+128^3 workloads) and trains on them; ``--eval-steps`` then times Jacobi PCG
+and the learned preconditioner over the same trajectory steps.
 """
 from __future__ import annotations
 
@@ -109,28 +113,121 @@ def train(ctx, n_steps: int, lr: float, seed: int = 0, chunk: int = 50, log=prin
     return np.concatenate(losses) if losses else np.zeros(0)
 
 
+def evaluate(sc, weights, warmup: int, steps: int, log=print, warm_start: int = 4) -> dict:
+    """Jacobi PCG against the learned preconditioner over the same trajectory
+    steps of scene `sc`: `warmup` untimed Jacobi steps from the initial
+    state, then `steps` timed steps with each preconditioner from that same
+    state (the Jacobi CG with the given warm start, the flexible CG of the
+    learned preconditioner from zero).  Returns CG iterations and ms per step."""
+    import torch
+    from paper_2602_07853_amd import mpmlite
+    out = {}
+    parts = mpmlite.particles_to_device(sc.particles)
+    ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                          opts=dict(hv_precision=mpmlite.F32, newton_rtol=1e-6, pcg_rtol=1e-6,
+                                    warm_start=warm_start))
+    ctx.precond_set_weights(weights)
+    for k in range(warmup):
+        ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, k * sc.dt)
+    start = {k: v.clone() for k, v in parts.items()}
+    for name, pre in (("jacobi", mpmlite.PRECOND_JACOBI), ("learned", mpmlite.PRECOND_LEARNED)):
+        ctx.set_opts(precond=pre)
+        p = {k: v.clone() for k, v in start.items()}
+        pcg = newton = fb = 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(steps):
+            st = ctx.step(p, p, sc.dt, sc.gravity, sc.bcs, (warmup + k) * sc.dt)
+            pcg += st["pcg_iters"]
+            newton += st["newton_iters"]
+            fb += st["fallbacks"]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / steps
+        out[name] = dict(pcg_per_step=pcg / steps, newton_per_step=newton / steps,
+                         fallbacks_per_step=fb / steps, ms_per_step=round(ms, 2))
+        log(f"[train] eval {name}: {out[name]}")
+    out["trajectory_steps"] = [warmup, warmup + steps - 1]
+    out["learned_vs_jacobi_time"] = round(out["jacobi"]["ms_per_step"] / out["learned"]["ms_per_step"], 4)
+    return out
+
+
+def corpus(configs, collect_steps: int, every: int, capacity: int, train_steps: int, lr: float,
+           seed: int, rounds: int, log=print):
+    """Pairs from the Newton solves of several workloads (one context per
+    grid, each holding its own pairs), trained in rounds: each round takes
+    train_steps / rounds Adam steps on every workload's pairs in turn, the
+    weights handed from context to context (each keeps its own Adam
+    moments).  Returns (weights, pair counts, final losses)."""
+    from paper_2602_07853_amd import mpmlite, scenes
+    w = init_weights(seed)
+    ctxs, counts = [], {}
+    for cfg in configs:
+        sc = scenes.CONFIGS[cfg]()
+        ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                              opts=dict(hv_precision=mpmlite.F32, newton_rtol=1e-6, pcg_rtol=1e-6))
+        ctx.precond_set_weights(w)
+        parts = mpmlite.particles_to_device(sc.particles)
+        counts[sc.name] = collect(ctx, sc, parts, collect_steps, every, capacity, log=log)
+        del parts
+        ctxs.append((sc.name, ctx))
+    per = max(1, train_steps // (rounds * len(ctxs)))
+    losses = {}
+    for r in range(rounds):
+        for name, ctx in ctxs:
+            ctx.precond_set_weights(w)
+            l = ctx.precond_train(per, lr if r < (2 * rounds) // 3 else 0.5 * lr, seed=seed + r)
+            w = ctx.precond_get_weights()
+            losses[name] = float(np.mean(l[-min(len(l), 10):]))
+        log(f"[train] round {r + 1}/{rounds}: losses {losses}")
+    for _, ctx in ctxs:
+        ctx.close()
+    return w, counts, losses
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--configs", default=None,
+                    help="comma-separated workloads whose Newton solves give the pairs (e.g. 2,3); "
+                         "trained in rounds, then evaluated on the last one")
     ap.add_argument("--collect-steps", type=int, default=3)
     ap.add_argument("--every", type=int, default=20)
     ap.add_argument("--capacity", type=int, default=120)
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eval-warmup", type=int, default=3)
+    ap.add_argument("--eval-steps", type=int, default=0,
+                    help="after training, time this many steps of the last workload with Jacobi and "
+                         "with the learned preconditioner from the same state")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    import json
     from paper_2602_07853_amd import mpmlite, scenes
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    if a.configs:
+        cfgs = [int(c) for c in a.configs.split(",")]
+        w, counts, losses = corpus(cfgs, a.collect_steps, a.every, a.capacity, a.train_steps, a.lr,
+                                   a.seed, a.rounds, log=log)
+        save_weights(a.out, w)
+        res = dict(pairs=counts, final_losses=losses, train_steps=a.train_steps, rounds=a.rounds)
+        if a.eval_steps > 0:
+            res["eval"] = evaluate(scenes.CONFIGS[cfgs[-1]](), w, a.eval_warmup, a.eval_steps, log=log)
+        print(json.dumps(res), flush=True)
+        return
     sc = scenes.CONFIGS[a.config]()
     ctx = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
                           opts=dict(hv_precision=mpmlite.F32, newton_rtol=1e-6, pcg_rtol=1e-6))
     ctx.precond_set_weights(init_weights(a.seed))
     parts = mpmlite.particles_to_device(sc.particles)
-    log = lambda s: print(s, file=sys.stderr, flush=True)
     n = collect(ctx, sc, parts, a.collect_steps, a.every, a.capacity, log=log)
     log(f"[train] {n} pairs")
     train(ctx, a.train_steps, a.lr, a.seed, log=log)
     save_weights(a.out, ctx.precond_get_weights())
+    if a.eval_steps > 0:
+        print(json.dumps(evaluate(sc, ctx.precond_get_weights(), a.eval_warmup, a.eval_steps, log=log)),
+              flush=True)
 
 
 if __name__ == "__main__":

@@ -186,6 +186,28 @@ def cpu_baseline(sc, cold_counts):
             "oracle_full_step_64": full}
 
 
+def step_error(sc, parts, ctx, t):
+    """Error of one step of `ctx` (its current options) from state `parts`
+    against the FP64 GPU variant of the same step converged to 1e-10."""
+    import torch
+    from paper_2602_07853_amd import mpmlite
+    src = {k: v.clone() for k, v in parts.items()}
+    tight = mpmlite.Context((sc.n,) * 3, sc.dx, sc.materials,
+                            opts=dict(hv_precision=mpmlite.F64, newton_rtol=1e-10, pcg_rtol=1e-10))
+    ref = {k: v.clone() for k, v in src.items()}
+    tight.step(src, ref, sc.dt, sc.gravity, sc.bcs, t)
+    out = {k: v.clone() for k, v in src.items()}
+    ctx.step(src, out, sc.dt, sc.gravity, sc.bcs, t)
+    torch.cuda.synchronize()
+    del tight
+
+    def rel(a, b):
+        return float((a - b).norm() / b.norm().clamp_min(1e-300))
+    res = {"x": rel(out["x"], ref["x"]), "dx": rel(out["x"] - src["x"], ref["x"] - src["x"]),
+           "v": rel(out["v"], ref["v"]), "F": rel(out["F"], ref["F"]), "G": rel(out["G"], ref["G"])}
+    return {k: float(f"{v:.3e}") for k, v in res.items()}
+
+
 def precision_check(sc, parts, ctx, t):
     """Final error of one production step (FP32 products, tolerances 1e-6)
     from the current state, against the FP64 GPU variant of the same step
@@ -226,7 +248,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is not sharded "
-              f"across GPUs in this build.", file=sys.stderr)
+              f"across GPUs.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2602_07853_amd import mpmlite
@@ -429,12 +451,12 @@ def inexact_leg(sc, args, plain_steps_per_s, traj, prec):
     n = args.steps
     sps = n / el
     jp = sum(traj[i][0] for i in range(args.warmup, args.warmup + n)) / n
-    err = precision_check(sc, parts, ctx, t)
+    err = None if args.no_precision_check else step_error(sc, parts, ctx, t)
     out = {"newton_forcing": args.inexact_forcing, "steps_per_s": round(sps, 4), "steps": n,
            "ms_per_step": round(1e3 * el / n, 3), "newton_per_step": round(newton / n, 3),
            "pcg_per_step": round(pcg / n, 2), "vs_exact_newton": round(sps / plain_steps_per_s, 4),
            "exact_pcg_per_step": round(jp, 2), "trajectory_steps": [args.warmup, args.warmup + n - 1],
-           "final_error": err["production_f32"]}
+           "final_error": err}
     print(f"[bench] inexact Newton leg {json.dumps(out)}", file=sys.stderr, flush=True)
     del ctx, parts
     return out
@@ -528,6 +550,8 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
               f"fallbacks {st['fallbacks']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # one more learned step from the state reached, against the FP64 reference
+    err = None if args.no_precision_check else step_error(sc, parts, ctx, t)
     ctx.set_opts(precond=0)
     net = network_rate(ctx, sc)
     n = args.learned_steps
@@ -548,6 +572,7 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
                            "speed_vs_jacobi": round(jm / (host_ms / n), 4),
                            "note": "flexible CG starts from zero; the Jacobi CG from its warm start"},
             "network": net,
+            "final_error": err,
             "plain_pcg_per_step": round(plain_counts[1], 2),
             "training": f"online, energy-norm loss, {args.learned_train_steps} untimed Jacobi steps "
                         "from the workload's initial state, 1 Adam step per 64 CG iterations"}

@@ -8,7 +8,7 @@ reads for its ``traffic`` fields and prints the tables kept under profiles/).
 ``counters``: FETCH_DIR and WRITE_DIR hold the results databases of two
 ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of
 ``python3 -m paper_2602_07853_amd.profile_hv`` (INFO_JSON is the last line it
-printed).  Each counter is scaled by what it reads for the driver's final
+printed).  Each counter is scaled by what it reads for profile_hv's final
 plain device-to-device copy of known size (FETCH_SIZE and WRITE_SIZE are in
 KiB per dispatch), and the per-launch bytes of the fused Hessian-vector
 product and of the CG update kernel are the medians over their launches;
@@ -55,7 +55,7 @@ def counters(fetch_dir, write_dir, info_json, out_json):
         copies = [v for k, v in vals if "copyBuffer" in k]
         if not copies:
             raise SystemExit(f"{cname}: no copy kernel to calibrate with")
-        # the driver's 512 MiB copy is the largest copy dispatch of the run
+        # profile_hv's 512 MiB copy is the largest copy dispatch of the run
         scale = info[key] / (max(copies) * 1024.0)
         res[f"{cname.lower()}_scale"] = scale
         for label, match in (("hv", "k_hv_fused"), ("update", "k_cg_step")):

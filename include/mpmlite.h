@@ -87,9 +87,13 @@ enum { MPL_F32 = 0, MPL_F64 = 1 };
  * matrix-free CG of Sec. 5): the inverse diagonal of H (Jacobi); the
  * inverses of its 3x3 node blocks H_ii = m_i I + sum_c (node block of
  * B_c^T Abar_c B_c), which couple a node's three velocity components
- * (block-Jacobi; single-reduction CG only, MPL_CG_CLASSIC=1 rejects it); or
- * the learned network (see below). */
-enum { MPL_PRECOND_JACOBI = 0, MPL_PRECOND_BLOCK_JACOBI = 1, MPL_PRECOND_LEARNED = 2 };
+ * (block-Jacobi; single-reduction CG only, MPL_CG_CLASSIC=1 rejects it); the
+ * learned network (see below); or one geometric multigrid V-cycle (see
+ * "multigrid" below), the multigrid-preconditioned CG that the paper names
+ * beside plain PCG as an off-the-shelf solver of the same potential (Sec. 7,
+ * the vertex block descent comparison). */
+enum { MPL_PRECOND_JACOBI = 0, MPL_PRECOND_BLOCK_JACOBI = 1, MPL_PRECOND_LEARNED = 2,
+       MPL_PRECOND_MULTIGRID = 3 };
 
 typedef struct {
   double dx;
@@ -168,6 +172,13 @@ typedef struct {
                              its cells of their blocks.  Not combined with
                              MPL_PLASTICITY_FIXED_POINT.  The stats report the sweeps as
                              newton_iters and no CG iterations */
+  int32_t mg_levels;      /* MPL_PRECOND_MULTIGRID: levels of the V-cycle counting the step's
+                             grid, 2..MPL_MG_MAX_LEVELS (0: 4); fewer when a level's cell count
+                             per axis is odd or its half would drop below 4 */
+  int32_t mg_smooth;      /* damped-Jacobi sweeps before and after each coarse correction
+                             (0: 2) */
+  int32_t mg_coarse_sweeps;/* damped-Jacobi sweeps on the coarsest level (0: 4) */
+  double mg_omega;        /* omega_l lambda_l of every level's sweeps, in (0, 2) (0: 1.6) */
 } mpl_solver_opts;
 
 enum { MPL_PLASTICITY_AFTER_SOLVE = 0, MPL_PLASTICITY_FIXED_POINT = 1 };
@@ -368,6 +379,44 @@ enum {
                              * precond = MPL_PRECOND_BLOCK_JACOBI) */
 };
 mpl_status mpl_export_field(mpl_ctx* ctx, int32_t field, double* dense_out);
+
+/* ---- multigrid ----
+ *
+ * Geometric V-cycle on the voxel mesh (the textbook algorithm; the paper
+ * names multigrid-preconditioned CG without defining it, Sec. 7).  Level 0
+ * is the step's grid; level l + 1 halves every axis, its cell (I, J, K) being
+ * the union of the level-l cells (2I + a, 2J + b, 2K + c), a, b, c in {0, 1},
+ * and its nodes the even level-l nodes.  Coarse operator: the same
+ * one-point Q1 product (Sec. 3.3) with the coarse spacing, the coarse cell's
+ * tangent being the sum of its children's (dense 45 values), plus the
+ * lumped coarse mass m_C = P^T m.  P is trilinear interpolation of node
+ * values (weight 1 on a co-located node, 1/2 per axis across an odd offset),
+ * the restriction is P^T, both zero on fixed or massless DOFs; component a of
+ * a coarse node is fixed when the co-located level-l node has mass and that
+ * component fixed.  Smoothing: mg_smooth damped-Jacobi sweeps
+ * x <- x + omega_l D^-1 (b - A x) before (the first from x = 0) and after each
+ * coarse correction, mg_coarse_sweeps on the coarsest level; omega_l =
+ * mg_omega / lambda_l with lambda_l the Rayleigh quotient after 20 power
+ * iterations on D^-1/2 A D^-1/2 from x_0 = +-1 on the free DOFs, the sign of
+ * DOF q = 3 (dense node index of the level) + a being the top bit of
+ * SplitMix64(q) (state (q + 1) * 0x9E3779B97F4A7C15 through the published
+ * finaliser).  The cycle is symmetric; PCG (Hestenes-Stiefel, r and x in
+ * FP64, the cycle in the tangent's precision) uses it as its preconditioner.
+ * The hierarchy is built on first use after each tangent build. */
+#define MPL_MG_MAX_LEVELS 6
+/* One V-cycle z = B r on dense node vectors (FP64, device; [nodes][3]) with
+ * the current tangent (mpl_build_tangent first); uses the solver options'
+ * mg_* fields.  *n_levels (host, may be NULL) receives the level count and
+ * omega (host, MPL_MG_MAX_LEVELS entries, may be NULL) each level's damping. */
+mpl_status mpl_mg_apply(mpl_ctx* ctx, const double* r, double* z, int32_t* n_levels, double* omega);
+/* Dense export of a multigrid level's data (level >= 1; the hierarchy of the
+ * current tangent is built first): field 0 node mass (nodes, 1), 1 fixed
+ * components (nodes, 1; bit a for component a, as MPL_FIELD_FIXED), 2 the
+ * coarse tangent (cells, 81: full symmetric 9x9), 3 the inverse Jacobi
+ * diagonal (nodes, 3).  The level's grid has dims / 2^level cells per axis;
+ * dense_out (device, FP64) holds (dims/2^l + 1)^3 node rows or (dims/2^l)^3
+ * cell rows. */
+mpl_status mpl_mg_export(mpl_ctx* ctx, int32_t level, int32_t field, double* dense_out);
 
 /* ---- learned preconditioner ----
  *

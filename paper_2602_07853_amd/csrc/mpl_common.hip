@@ -309,8 +309,12 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
   if (o->hv_precision != MPL_F32 && o->hv_precision != MPL_F64)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "hv_precision must be MPL_F32 or MPL_F64");
   if (o->precond != MPL_PRECOND_JACOBI && o->precond != MPL_PRECOND_BLOCK_JACOBI &&
-      o->precond != MPL_PRECOND_LEARNED)
+      o->precond != MPL_PRECOND_LEARNED && o->precond != MPL_PRECOND_MULTIGRID)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->mg_levels < 0 || o->mg_levels == 1 || o->mg_levels > MPL_MG_MAX_LEVELS || o->mg_smooth < 0 ||
+      o->mg_smooth > 8 || o->mg_coarse_sweeps < 0 || o->mg_coarse_sweeps > 64 ||
+      !(o->mg_omega >= 0.0 && o->mg_omega < 2.0))
+    return mpl_fail(c, MPL_ERR_INVALID_ARG, "multigrid options out of range");
   if (o->precond == MPL_PRECOND_BLOCK_JACOBI && !c->cg_single)
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "block-Jacobi runs in the single-reduction CG only");
   if (o->time_kernels < 0 || o->time_kernels > 2)
@@ -334,6 +338,10 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
     return mpl_fail(c, MPL_ERR_INVALID_ARG, "solver options out of range");
   c->opts = *o;
   if (c->opts.pcg_check_every <= 0) c->opts.pcg_check_every = 16;
+  if (c->opts.mg_levels == 0) c->opts.mg_levels = 4;
+  if (c->opts.mg_smooth == 0) c->opts.mg_smooth = 2;
+  if (c->opts.mg_coarse_sweeps == 0) c->opts.mg_coarse_sweeps = 4;
+  if (c->opts.mg_omega == 0.0) c->opts.mg_omega = 1.6;
   return MPL_OK;
 }
 
@@ -415,6 +423,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->gal_part};
   for (DevBuf* b : all) free_buf(c, *b);
   nn_destroy(c);
+  mpl_mg_destroy(c);
   for (GraphCache& gc : c->pcg_cache) {
     if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
     if (gc.graph) (void)hipGraphDestroy(gc.graph);

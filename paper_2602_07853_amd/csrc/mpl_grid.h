@@ -184,6 +184,50 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Device flag of a CG solve: 1 converged, 2 breakdown (kernels of later
+// iterations return at once).
+__device__ __forceinline__ bool done_flag(const SolverScalars* s) {
+  return *(volatile const int32_t*)&s->done != 0;
+}
+
+// Assemble (K p)_i for local node l of node block nb: the own partial of the
+// cell block with the same coordinates plus the halo pieces of the cell
+// blocks at -x, -y, -z (faces, edges, corner), summed in a fixed order.
+template <class T>
+__device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* __restrict__ Hhalo,
+                                          const int* __restrict__ n_nbr_cell, int64_t ncell,
+                                          int nb, int l, T* h) {
+  // every load is issued unconditionally (absent sources read slot 0 and
+  // add zero), so the eight sources cost one memory round trip
+  const int* nbr = n_nbr_cell + nb * 8;
+  int o[7], slot[7];
+  bool need[7];
+  halo_sources(l, o, slot, need);
+  T v[8][3];
+  bool use[8];
+  {
+    const int src = nbr[0];
+    use[0] = src >= 0;
+    const int64_t i = use[0] ? (int64_t)src * MPL_BC + l : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[0][a] = Hown[a * ncell + i];
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int src = nbr[o[k]];
+    use[k + 1] = need[k] && src >= 0;
+    const int64_t i = use[k + 1] ? (int64_t)src * MPL_BC + slot[k] : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[k + 1][a] = Hhalo[a * ncell + i];
+  }
+  h[0] = h[1] = h[2] = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (use[k]) h[a] += v[k][a];
+}
+
 }  // namespace mpl
 
 // node flag bits: ACTIVE (the node has mass), FIXED (a boundary condition

@@ -35,6 +35,7 @@ struct DevBuf {
   size_t bytes = 0;
 };
 struct NNState;
+struct MGState;
 
 // Dirichlet boxes of the current step as the centre->node kernel reads them
 // (a per-context device copy, so that contexts on other streams never share it).
@@ -186,6 +187,9 @@ struct mpl_ctx {
 
   // learned preconditioner (allocated on first use)
   NNState* nn = nullptr;
+  // multigrid preconditioner (allocated on first use; mpl_mg.hip)
+  MGState* mg = nullptr;
+  int tangent_serial = 0;  // incremented by every tangent build
 
   // timing
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -207,6 +211,23 @@ struct mpl_ctx {
 
   size_t ncell_alloc() const { return (size_t)n_cblk * MPL_BC; }
   size_t nnode_alloc() const { return (size_t)n_nblk * MPL_BC; }
+};
+
+// Arrays of one level of the block grid as the product, diagonal and vector
+// kernels read them (the step's grid, or a multigrid level).
+struct LevelArrays {
+  int n_cblk = 0, n_nblk = 0;
+  int64_t ncell = 0, nnode = 0;  // allocated slots (blocks x 64)
+  const int* c_nbr_node = nullptr;
+  const int* n_nbr_cell = nullptr;
+  const uint64_t* cmask = nullptr;  // tangent-carrying cells per cell block
+  const int32_t* coff = nullptr;    // their offsets in the compact tangent
+  const void* Abar = nullptr;       // tangent in the solve's precision
+  bool fact = false, mixed = false; // factored (one material) or per-block layout (cfmt)
+  const uint8_t* cfmt = nullptr;
+  const double* mi = nullptr;       // node mass (FP64)
+  const uint8_t* flags = nullptr;   // node flags
+  double inv_dx = 0.0;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -254,6 +275,37 @@ mpl_status mpl_dense_to_block_nodes(mpl_ctx* c, const void* dense, void* block, 
                                     int is_f32);
 mpl_status mpl_block_to_dense_nodes(mpl_ctx* c, const void* block, void* dense, int comps,
                                     int is_f32);
+
+// Product pieces (own and halo, 6 x cells values) of K p on a level, with
+// the level's stored tangent; kernels return at once when s reports a
+// finished solve (s may be null).  With partial, one partial sum of p^T K p
+// per group of four cell blocks goes there.
+template <class T>
+mpl_status mpl_level_hv_pieces(mpl_ctx* c, const LevelArrays& L, const T* p, T* pieces,
+                               const SolverScalars* s, double* partial = nullptr);
+// Inverse Jacobi diagonal of a level's matrix (FP64 and in T) and its node
+// masses in T.
+template <class T>
+mpl_status mpl_level_diag(mpl_ctx* c, const LevelArrays& L, double* D, T* Dt, T* mt);
+// The step grid's arrays as a level (tangent in the precision T).
+template <class T>
+LevelArrays mpl_level0(const mpl_ctx* c);
+// Block maps of a block grid from a dense per-cell-block flag array: compact
+// cell and node block ids, their coordinates, and the counts at
+// totals_dev[0] (cell blocks) and totals_dev[1] (node blocks).  scan needs
+// cell blocks + node blocks + 2 ints.
+mpl_status mpl_block_maps(mpl_ctx* c, const int dims[3], const int cbd[3], const int nbd[3],
+                          int32_t* cflag, int32_t* cmap, int4* ccoord, int32_t* nflag,
+                          int32_t* nmap, int4* ncoord, int32_t* scan, int32_t* totals_dev);
+// Neighbour tables (8 node blocks per cell block, 8 cell blocks per node block).
+mpl_status mpl_block_neighbours(mpl_ctx* c, const int dims[3], const int cbd[3], const int nbd[3],
+                                const int4* ccoord, const int4* ncoord, const int32_t* cmap,
+                                const int32_t* nmap, int32_t* c_nbr_node, int32_t* n_nbr_cell,
+                                int n_cblk, int n_nblk);
+// Multigrid-preconditioned CG on the current tangent (mpl_mg.hip); x0 may be null.
+mpl_status mpl_stage_pcg_mg(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
+                            const double* x0);
+void mpl_mg_destroy(mpl_ctx* c);
 
 // Allocation-free entry point (mpl_noalloc.hip): fetch the device address of
 // the fixed scratch array for the context's device once per device.

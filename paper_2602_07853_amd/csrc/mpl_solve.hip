@@ -22,9 +22,6 @@ using namespace mpl;
 namespace {
 
 
-__device__ __forceinline__ bool done_flag(const SolverScalars* s) {
-  return *(volatile const int32_t*)&s->done != 0;
-}
 
 // G_c(v) = sum over the 8 corners of v_i (x) grad w_ic (Sec. 3.3).
 template <class T>
@@ -888,44 +885,6 @@ __global__ __launch_bounds__(256) void k_hv_fused(const T* __restrict__ p, int64
     __syncthreads();
     if (threadIdx.x == 0 && grp * 4 < n_cblk) partial[grp] = (dsum[0] + dsum[1]) + (dsum[2] + dsum[3]);
   }
-}
-
-// Assemble (K p)_i for local node l of node block nb: the own partial of the
-// cell block with the same coordinates plus the halo pieces of the cell
-// blocks at -x, -y, -z (faces, edges, corner), summed in a fixed order.
-template <class T>
-__device__ __forceinline__ void gather_kp(const T* __restrict__ Hown, const T* __restrict__ Hhalo,
-                                          const int* __restrict__ n_nbr_cell, int64_t ncell,
-                                          int nb, int l, T* h) {
-  // every load is issued unconditionally (absent sources read slot 0 and
-  // add zero), so the eight sources cost one memory round trip
-  const int* nbr = n_nbr_cell + nb * 8;
-  int o[7], slot[7];
-  bool need[7];
-  halo_sources(l, o, slot, need);
-  T v[8][3];
-  bool use[8];
-  {
-    const int src = nbr[0];
-    use[0] = src >= 0;
-    const int64_t i = use[0] ? (int64_t)src * MPL_BC + l : 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[0][a] = Hown[a * ncell + i];
-  }
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int src = nbr[o[k]];
-    use[k + 1] = need[k] && src >= 0;
-    const int64_t i = use[k + 1] ? (int64_t)src * MPL_BC + slot[k] : 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[k + 1][a] = Hhalo[a * ncell + i];
-  }
-  h[0] = h[1] = h[2] = T(0);
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-      if (use[k]) h[a] += v[k][a];
 }
 
 // Stand-alone product: Hu = M u + K u on the free components (0 elsewhere).
@@ -2072,6 +2031,7 @@ mpl_status mpl_stage_tangent(mpl_ctx* c, const double* v, int precision) {
     c->bj_built = true;
   }
   c->tangent_built = true;
+  ++c->tangent_serial;
   c->tangent_precision = precision;
   return MPL_OK;
 }
@@ -2204,6 +2164,77 @@ mpl_status mpl_stage_hv_into(mpl_ctx* c, const void* u, void* Hu, void* pieces, 
   }
   return MPL_OK;
 }
+
+template <class T>
+LevelArrays mpl_level0(const mpl_ctx* c) {
+  LevelArrays L;
+  L.n_cblk = c->n_cblk;
+  L.n_nblk = c->n_nblk;
+  L.ncell = (int64_t)c->ncell_alloc();
+  L.nnode = (int64_t)c->nnode_alloc();
+  L.c_nbr_node = P<int>(c->c_nbr_node);
+  L.n_nbr_cell = P<int>(c->n_nbr_cell);
+  L.cmask = P<uint64_t>(c->cmask);
+  L.coff = P<int32_t>(c->coff);
+  L.Abar = sizeof(T) == 4 ? c->Abar32.p : c->Abar64.p;
+  L.fact = c->tan_factored && sizeof(T) == 4;
+  L.mixed = c->tan_mixed && sizeof(T) == 4;
+  L.cfmt = P<uint8_t>(c->cfmt);
+  L.mi = P<double>(c->mi);
+  L.flags = P<uint8_t>(c->flags);
+  L.inv_dx = c->inv_dx;
+  return L;
+}
+
+template <class T>
+mpl_status mpl_level_hv_pieces(mpl_ctx* c, const LevelArrays& L, const T* p, T* pieces,
+                               const SolverScalars* s, double* partial) {
+  const T inv4 = (T)(0.25 * L.inv_dx);
+  const int grid = (((L.n_cblk + 3) / 4 + 7) / 8) * 8;
+  T* Hown = pieces;
+  T* Hhalo = pieces + 3 * L.ncell;
+  const T* A = (const T*)L.Abar;
+  const uint8_t* fmt = L.mixed ? L.cfmt : nullptr;
+#define MPL_LV_HV(DOT, FACT, MIX)                                                                  \
+  MPL_LAUNCH(c, (k_hv_fused<T, DOT, FACT, MIX>), grid, 256, p, L.nnode, L.c_nbr_node, A, L.cmask, \
+             L.coff, L.ncell, L.n_cblk, inv4, Hown, Hhalo, partial, s, fmt)
+  if (partial) {
+    if (L.fact) MPL_LV_HV(true, true, false);
+    else if (L.mixed) MPL_LV_HV(true, false, true);
+    else MPL_LV_HV(true, false, false);
+  } else {
+    if (L.fact) MPL_LV_HV(false, true, false);
+    else if (L.mixed) MPL_LV_HV(false, false, true);
+    else MPL_LV_HV(false, false, false);
+  }
+#undef MPL_LV_HV
+  return MPL_OK;
+}
+
+template <class T>
+mpl_status mpl_level_diag(mpl_ctx* c, const LevelArrays& L, double* D, T* Dt, T* mt) {
+  const T* A = (const T*)L.Abar;
+  const double inv4 = 0.25 * L.inv_dx;
+  if (L.fact)
+    MPL_LAUNCH(c, (k_diag<T, true, false>), L.n_nblk, 64, A, L.cmask, L.coff, L.mi, L.flags,
+               L.n_nbr_cell, L.nnode, inv4, D, Dt, mt, L.cfmt);
+  else if (L.mixed)
+    MPL_LAUNCH(c, (k_diag<T, false, true>), L.n_nblk, 64, A, L.cmask, L.coff, L.mi, L.flags,
+               L.n_nbr_cell, L.nnode, inv4, D, Dt, mt, L.cfmt);
+  else
+    MPL_LAUNCH(c, (k_diag<T, false, false>), L.n_nblk, 64, A, L.cmask, L.coff, L.mi, L.flags,
+               L.n_nbr_cell, L.nnode, inv4, D, Dt, mt, L.cfmt);
+  return MPL_OK;
+}
+
+template LevelArrays mpl_level0<float>(const mpl_ctx*);
+template LevelArrays mpl_level0<double>(const mpl_ctx*);
+template mpl_status mpl_level_hv_pieces<float>(mpl_ctx*, const LevelArrays&, const float*, float*,
+                                               const SolverScalars*, double*);
+template mpl_status mpl_level_hv_pieces<double>(mpl_ctx*, const LevelArrays&, const double*, double*,
+                                                const SolverScalars*, double*);
+template mpl_status mpl_level_diag<float>(mpl_ctx*, const LevelArrays&, double*, float*, float*);
+template mpl_status mpl_level_diag<double>(mpl_ctx*, const LevelArrays&, double*, double*, double*);
 
 // Runs PCG iterations in chunks of `check` until the device flag reports
 // convergence or breakdown or max_pcg iterations have been launched.  A
@@ -2739,6 +2770,7 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
     if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel, h);
     return pcg_learned<double>(c, b, x, iters, rel, h);
   }
+  if (c->opts.precond == MPL_PRECOND_MULTIGRID) return mpl_stage_pcg_mg(c, b, x, iters, rel, x0);
   // (a warm start applies to the single-reduction Jacobi loop)
   if (!c->cg_single) x0 = nullptr;
   if (c->tangent_precision == MPL_F32) return pcg_impl<float>(c, b, x, iters, rel, h, false, x0);

@@ -14,6 +14,7 @@
 //     a per-block staging slot; a second pass (one wave per block) adds to
 //     each centre the halo slots of the up to 7 blocks at -x/-y/-z in a fixed
 //     order and normalises (no read-modify-write, one launch each).
+#include <algorithm>
 #include <cmath>
 
 #include "mpl_grid.h"
@@ -501,6 +502,42 @@ __global__ __launch_bounds__(64) void k_c2n(GridDev g, const int32_t* __restrict
 }
 
 }  // namespace
+
+static GridDev level_grid(const int dims[3], const int cbd[3], const int nbd[3]) {
+  GridDev g{};
+  for (int a = 0; a < 3; ++a) {
+    g.dims[a] = dims[a];
+    g.cbd[a] = cbd[a];
+    g.nbd[a] = nbd[a];
+  }
+  return g;
+}
+
+mpl_status mpl_block_maps(mpl_ctx* c, const int dims[3], const int cbd[3], const int nbd[3],
+                          int32_t* cflag, int32_t* cmap, int4* ccoord, int32_t* nflag,
+                          int32_t* nmap, int4* ncoord, int32_t* scan, int32_t* totals_dev) {
+  const GridDev g = level_grid(dims, cbd, nbd);
+  const int ncb = cbd[0] * cbd[1] * cbd[2], nnb = nbd[0] * nbd[1] * nbd[2];
+  const int TPB = 256;
+  int32_t* scan_c = scan;
+  int32_t* scan_n = scan + ncb + 1;
+  MPL_TRY(mpl_scan_i32(c, cflag, scan_c, ncb, totals_dev));
+  MPL_LAUNCH(c, k_compact_cells, (ncb + TPB - 1) / TPB, TPB, cflag, scan_c, cmap, ccoord, nflag, g, ncb);
+  MPL_TRY(mpl_scan_i32(c, nflag, scan_n, nnb, totals_dev + 1));
+  MPL_LAUNCH(c, k_compact_nodes, (nnb + TPB - 1) / TPB, TPB, nflag, scan_n, nmap, ncoord, g, nnb);
+  return MPL_OK;
+}
+
+mpl_status mpl_block_neighbours(mpl_ctx* c, const int dims[3], const int cbd[3], const int nbd[3],
+                                const int4* ccoord, const int4* ncoord, const int32_t* cmap,
+                                const int32_t* nmap, int32_t* c_nbr_node, int32_t* n_nbr_cell,
+                                int n_cblk, int n_nblk) {
+  const GridDev g = level_grid(dims, cbd, nbd);
+  const int mx = std::max(n_cblk, n_nblk), TPB = 256;
+  MPL_LAUNCH(c, k_neighbours, (mx + TPB - 1) / TPB, TPB, ccoord, ncoord, cmap, nmap, c_nbr_node,
+             n_nbr_cell, g, n_cblk, n_nblk);
+  return MPL_OK;
+}
 
 mpl_status mpl_stage_unload(mpl_ctx* c, const Parts64* in, double dt, const double* gravity,
                             const mpl_bc* bcs, int n_bcs, double time) {

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpmlite.so")
 
 F32, F64 = 0, 1
-PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_LEARNED = 0, 1, 2
+PRECOND_JACOBI, PRECOND_BLOCK_JACOBI, PRECOND_LEARNED, PRECOND_MULTIGRID = 0, 1, 2, 3
+MG_MAX_LEVELS = 6
 TRANSFER_APIC, TRANSFER_FLIP_PIC = 0, 1
 PLASTICITY_AFTER_SOLVE, PLASTICITY_FIXED_POINT = 0, 1
 NEOHOOKEAN, FIXED_COROTATED, HENCKY = 0, 1, 2
@@ -54,7 +55,8 @@ class _Opts(C.Structure):
                 ("time_kernels", C.c_int32), ("warm_start", C.c_int32), ("transfer", C.c_int32),
                 ("flip_ratio", C.c_double), ("plasticity", C.c_int32), ("plastic_anderson", C.c_int32),
                 ("newton_forcing", C.c_double),
-                ("vbd_sweeps", C.c_int32)]
+                ("vbd_sweeps", C.c_int32), ("mg_levels", C.c_int32), ("mg_smooth", C.c_int32),
+                ("mg_coarse_sweeps", C.c_int32), ("mg_omega", C.c_double)]
 
 
 class _Particles(C.Structure):
@@ -204,7 +206,8 @@ def default_opts(**kw) -> dict:
     o = dict(hv_precision=F32, precond=PRECOND_JACOBI, newton_rtol=1e-6, pcg_rtol=1e-6,
              max_newton=50, max_pcg=20000, max_ls=40, armijo_c=1e-4, pcg_check_every=16,
              time_kernels=0, warm_start=0, transfer=TRANSFER_APIC, flip_ratio=0.0,
-             plasticity=PLASTICITY_AFTER_SOLVE, plastic_anderson=0, newton_forcing=0.0, vbd_sweeps=0)
+             plasticity=PLASTICITY_AFTER_SOLVE, plastic_anderson=0, newton_forcing=0.0, vbd_sweeps=0,
+             mg_levels=0, mg_smooth=0, mg_coarse_sweeps=0, mg_omega=0.0)
     o.update(kw)
     return o
 
@@ -394,6 +397,29 @@ class Context:
         self._check(self._lib.mpl_export_field(self._ctx, int(fid), C.c_void_p(out.data_ptr())),
                     "mpl_export_field")
         return out
+
+    # ------------------------------------------------------------ multigrid
+    def mg_apply(self, r: torch.Tensor):
+        """One V-cycle z = B r (dense FP64 node vectors) with the current
+        tangent; returns (z, level count, per-level damping)."""
+        z = torch.zeros_like(self._check_node_vec(r, "r"))
+        nl = C.c_int32()
+        om = (C.c_double * MG_MAX_LEVELS)()
+        self._check(self._lib.mpl_mg_apply(self._ctx, C.c_void_p(_dptr(r, torch.float64)),
+                                           C.c_void_p(z.data_ptr()), C.byref(nl), om), "mpl_mg_apply")
+        return z, nl.value, [om[i] for i in range(nl.value)]
+
+    def mg_export(self, level: int, field: str) -> torch.Tensor:
+        """Dense FP64 export of multigrid level ``level`` >= 1: ``mass``,
+        ``fixed``, ``abar`` (cells x 81) or ``diag`` (nodes x 3)."""
+        code, kind, comps = dict(mass=(0, "node", 1), fixed=(1, "node", 1), abar=(2, "cell", 81),
+                                 diag=(3, "node", 3))[field]
+        d = [n >> level for n in self.dims]
+        rows = (d[0] + 1) * (d[1] + 1) * (d[2] + 1) if kind == "node" else d[0] * d[1] * d[2]
+        out = torch.zeros((rows, comps), dtype=torch.float64, device="cuda")
+        self._check(self._lib.mpl_mg_export(self._ctx, C.c_int32(level), C.c_int32(code),
+                                            C.c_void_p(out.data_ptr())), "mpl_mg_export")
+        return out if comps > 1 else out[:, 0]
 
     # ------------------------------------------------------------ learned preconditioner
     def precond_param_count(self) -> int:

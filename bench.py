@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--vbd-sweeps", type=int, default=4)
     ap.add_argument("--bj-steps", type=int, default=5,
                     help="timed steps of the block-Jacobi leg, after 3 untimed ones (0 = skip the leg)")
+    ap.add_argument("--mg-steps", type=int, default=5,
+                    help="timed steps of the multigrid-preconditioned CG leg (0: skip)")
+    ap.add_argument("--mg-levels", type=int, default=0, help="V-cycle levels (0: the library's 4)")
+    ap.add_argument("--mg-smooth", type=int, default=0, help="sweeps per side (0: the library's 2)")
     ap.add_argument("--newton-forcing", type=float, default=0.0,
                     help="inexact Newton forcing term for the main run (0: every CG to 1e-6)")
     ap.add_argument("--inexact-forcing", type=float, default=0.1,
@@ -373,7 +377,15 @@ def main():
         inexact = inexact_leg(sc, args, steps_per_s, traj, prec)
     block_jacobi = None
     if args.bj_steps > 0:
-        block_jacobi = block_jacobi_leg(ctx, sc, args, steps_per_s, counts, traj)
+        block_jacobi = precond_leg(ctx, sc, args, steps_per_s, counts, traj, mpmlite.PRECOND_BLOCK_JACOBI,
+                                   "block-Jacobi", args.bj_steps)
+    multigrid = None
+    if args.mg_steps > 0:
+        mg_opts = dict(mg_levels=args.mg_levels, mg_smooth=args.mg_smooth)
+        multigrid = precond_leg(ctx, sc, args, steps_per_s, counts, traj, mpmlite.PRECOND_MULTIGRID,
+                                "multigrid", args.mg_steps, extra_opts=mg_opts)
+        multigrid["options"] = {"levels": args.mg_levels or 4, "smooth": args.mg_smooth or 2,
+                                "coarse_sweeps": 4, "omega_lambda": 1.6}
     learned = None
     if args.learned_steps > 0:
         learned = learned_leg(ctx, sc, parts0, args, steps_per_s, counts, traj)
@@ -411,6 +423,7 @@ def main():
         "cpu_baseline": base,
         "inexact_newton": inexact,
         "block_jacobi": block_jacobi,
+        "multigrid": multigrid,
         "learned": learned,
         "explicit": explicit,
         "vbd": vbd,
@@ -462,17 +475,19 @@ def inexact_leg(sc, args, plain_steps_per_s, traj, prec):
     return out
 
 
-def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untimed=3):
-    """The same workload from its initial state with the 3x3 nodal
-    block-Jacobi preconditioner in the same single-reduction CG and warm
-    start: ``untimed`` steps (the warm start's history fills up), then
-    ``bj_steps`` timed steps.  The CG count falls along the trajectory, so
-    the comparison with Jacobi is also made over the same trajectory steps
-    of the main run (host stage timers on both sides)."""
+def precond_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, precond, label, nsteps, untimed=3,
+                extra_opts=None):
+    """The same workload from its initial state with another preconditioner
+    (3x3 nodal block-Jacobi in the same single-reduction CG, or the
+    multigrid V-cycle in Hestenes-Stiefel PCG), with the same warm start:
+    ``untimed`` steps (the warm start's history fills up), then ``nsteps``
+    timed steps.  The CG count falls along the trajectory, so the comparison
+    with Jacobi is also made over the same trajectory steps of the main run
+    (host stage timers on both sides)."""
     import torch
     from paper_2602_07853_amd import mpmlite
     parts = mpmlite.particles_to_device(sc.particles)
-    ctx.set_opts(time_kernels=0, precond=mpmlite.PRECOND_BLOCK_JACOBI)
+    ctx.set_opts(time_kernels=0, precond=precond, **(extra_opts or {}))
     t = 0.0
     for k in range(untimed):
         ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
@@ -481,18 +496,18 @@ def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untim
     newton = pcg = 0
     host_ms = 0.0
     t0 = time.perf_counter()
-    for k in range(args.bj_steps):
+    for k in range(nsteps):
         st = ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
         t += sc.dt
         newton += st["newton_iters"]
         pcg += st["pcg_iters"]
         host_ms += st["ms_unload"] + st["ms_newton"] + st["ms_load"]
-        print(f"[bench] block-Jacobi step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']}",
-              file=sys.stderr, flush=True)
+        print(f"[bench] {label} step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} "
+              f"ms {st['ms_unload'] + st['ms_newton'] + st['ms_load']:.1f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.set_opts(precond=mpmlite.PRECOND_JACOBI)
-    n = args.bj_steps
+    n = nsteps
     sps = n / el
     out = {"steps_per_s": round(sps, 4), "steps": n, "untimed_steps": untimed,
            "ms_per_step": round(1e3 * el / n, 3), "newton_per_step": round(newton / n, 3),
@@ -500,14 +515,15 @@ def block_jacobi_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, untim
            "jacobi_pcg_per_step": round(plain_counts[1], 2), "same_steps": None}
     window = range(untimed, untimed + n)
     if not all(i in traj for i in window):
-        raise RuntimeError(f"block-Jacobi window {window.start}..{window.stop - 1} lies outside the "
-                           f"main run's {len(traj)} recorded steps; raise --steps or lower --bj-steps")
+        raise RuntimeError(f"{label} window {window.start}..{window.stop - 1} lies outside the "
+                           f"main run's {len(traj)} recorded steps; raise --steps or lower its step count")
     jp = sum(traj[i][0] for i in window) / n
     jm = sum(traj[i][1] for i in window) / n
     bm = host_ms / n
+    key = label.lower().replace("-", "_")
     out["same_steps"] = {"trajectory_steps": [window.start, window.stop - 1],
-                         "jacobi_pcg_per_step": round(jp, 2), "block_jacobi_pcg_per_step": round(pcg / n, 2),
-                         "jacobi_host_ms": round(jm, 2), "block_jacobi_host_ms": round(bm, 2),
+                         "jacobi_pcg_per_step": round(jp, 2), f"{key}_pcg_per_step": round(pcg / n, 2),
+                         "jacobi_host_ms": round(jm, 2), f"{key}_host_ms": round(bm, 2),
                          "speed_vs_jacobi": round(jm / bm, 4)}
     return out
 

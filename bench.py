@@ -535,8 +535,8 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
     ``learned_train_steps`` untimed Jacobi steps, then ``learned_steps`` steps
     are timed with the learned preconditioner and no training.  They are
     compared with the main Jacobi run over the same trajectory steps (host
-    stage timers on both sides); the flexible CG starts each solve from zero,
-    the Jacobi CG from its warm start."""
+    stage timers on both sides); both start each CG from the same kind of
+    warm start (the main run's option)."""
     import torch
     from paper_2602_07853_amd import precond_train
     ctx.precond_set_weights(precond_train.init_weights(0))
@@ -586,7 +586,7 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
                            "jacobi_pcg_per_step": round(jp, 2), "learned_pcg_per_step": round(pcg / n, 2),
                            "jacobi_host_ms": round(jm, 2), "learned_host_ms": round(host_ms / n, 2),
                            "speed_vs_jacobi": round(jm / (host_ms / n), 4),
-                           "note": "flexible CG starts from zero; the Jacobi CG from its warm start"},
+                           "note": f"both CG solvers start from warm_start={args.warm_start}"},
             "network": net,
             "final_error": err,
             "plain_pcg_per_step": round(plain_counts[1], 2),

@@ -227,7 +227,8 @@ enum {
   RED_PCG_INIT = 3,
   RED_FINIT = 4,   // flexible CG: A = b.b, B = sum Dinv b^2
   RED_FCHECK = 5,  // flexible CG: A = r.r, B = sum Dinv r^2 (convergence, stagnation)
-  RED_FBETA = 6    // flexible CG: A = z.r, B = z.q (Polak-Ribiere beta or fallback)
+  RED_FBETA = 6,   // flexible CG: A = z.r, B = z.q (Polak-Ribiere beta or fallback)
+  RED_FINIT_WARM = 7  // flexible CG from x0: A = b.b, B = sum Dinv r^2, C = r.r
 };
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, int na,
@@ -308,6 +309,18 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ a, i
     s->s2 = B;
     s->iters = 0;
     s->done = (A == 0.0) ? 1 : 0;
+    s->fallback = 0;
+    s->fb_new = 0;
+    s->fallbacks = 0;
+    s->nn_off = s->done;
+  } else if (MODE == RED_FINIT_WARM) {
+    // the tolerance stays relative to |b|; stagnation is judged on |r|
+    s->bnorm2 = A;
+    s->rr = C;
+    s->rr_mark = C;
+    s->s2 = B;
+    s->iters = 0;
+    s->done = (A == 0.0 || C == 0.0) ? 1 : 0;
     s->fallback = 0;
     s->fb_new = 0;
     s->fallbacks = 0;
@@ -1520,6 +1533,52 @@ __global__ __launch_bounds__(256) void k_fpcg_init(const double* __restrict__ b,
   }
 }
 
+// Flexible CG from x0: x = x0, r = b - H x0 on the free components (the
+// product's pieces of u0 = x0 in the tangent's precision given); partials of
+// b.b, sum Dinv r^2 and r.r.
+template <class T>
+__global__ __launch_bounds__(256) void k_fpcg_init_warm(const double* __restrict__ b,
+                                                        const double* __restrict__ x0,
+                                                        const T* __restrict__ u0, const T* __restrict__ Hown,
+                                                        const T* __restrict__ Hhalo,
+                                                        const int* __restrict__ n_nbr_cell, int64_t ncell,
+                                                        const T* __restrict__ mi,
+                                                        const double* __restrict__ Dinv,
+                                                        const uint8_t* __restrict__ flags, int64_t nnode,
+                                                        int n_nblk, double* __restrict__ x,
+                                                        double* __restrict__ r, double* __restrict__ pbb,
+                                                        double* __restrict__ ps2, double* __restrict__ prr) {
+  __shared__ double sh[4];
+  const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  double bb = 0.0, s2 = 0.0, rr = 0.0;
+  if (nb < n_nblk) {
+    const int64_t ni = (int64_t)nb * MPL_BC + l;
+    const uint8_t fl = flags[ni];
+    T h[3] = {T(0), T(0), T(0)};
+    if (fl & MPL_NODE_FREE_ALL) gather_kp(Hown, Hhalo, n_nbr_cell, ncell, nb, l, h);
+    const T m = mi[ni];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = a * nnode + ni;
+      const bool fa = mpl_free(fl, a);
+      const double bv = fa ? b[i] : 0.0;
+      const double rv = fa ? bv - (double)(h[a] + m * u0[i]) : 0.0;
+      x[i] = fa ? x0[i] : 0.0;
+      r[i] = rv;
+      bb += bv * bv;
+      s2 += rv * rv * Dinv[i];
+      rr += rv * rv;
+    }
+  }
+  bb = block4_sum(bb, sh);
+  s2 = block4_sum(s2, sh);
+  rr = block4_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    pbb[blockIdx.x] = bb;
+    ps2[blockIdx.x] = s2;
+    prr[blockIdx.x] = rr;
+  }
+}
+
 // partials z.r and z.q (q may be null: first iteration)
 template <class T>
 __global__ __launch_bounds__(256) void k_fpcg_dots(const double* __restrict__ r,
@@ -2473,7 +2532,8 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
 // check, network input, network forward, z.r and z.q, beta, new direction.
 template <class T>
 static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters, double* rel,
-                              const std::function<mpl_status(int)>* hook = nullptr) {
+                              const std::function<mpl_status(int)>* hook = nullptr,
+                              const double* x0 = nullptr) {
   if (!c->nn || !c->nn->ready) return mpl_fail(c, MPL_ERR_STATE, "learned preconditioner has no weights");
   NNState& nn = *c->nn;
   const int64_t ncell = (int64_t)c->ncell_alloc(), nnode = (int64_t)c->nnode_alloc();
@@ -2512,9 +2572,18 @@ static mpl_status pcg_learned(mpl_ctx* c, const double* b, double* x, int* iters
                P<int4>(c->ncoord), nnode, c->n_nblk, net, p, pm, s);
     return MPL_OK;
   };
-  MPL_LAUNCH(c, k_fpcg_init, nwg, 256, b, D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r),
-             pa, pb);
-  MPL_LAUNCH(c, k_reduce<RED_FINIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+  if (x0) {
+    // start from x0 (the q buffer holds x0 in the tangent's precision for its product)
+    MPL_LAUNCH(c, k_cg_prep<T>, (int)((nnode + 255) / 256), 256, x0, P<uint8_t>(c->flags), nnode, q);
+    MPL_TRY(hv_pieces<T>(c, q, false));
+    MPL_LAUNCH(c, k_fpcg_init_warm<T>, nwg, 256, b, x0, (const T*)q, Hown, Hhalo, P<int>(c->n_nbr_cell), ncell,
+               P<T>(c->mt), D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r), pa, pb, pk);
+    MPL_LAUNCH(c, k_reduce<RED_FINIT_WARM>, 1, 1024, pa, nwg, pb, nwg, pk, nwg, s, 0);
+  } else {
+    MPL_LAUNCH(c, k_fpcg_init, nwg, 256, b, D, P<uint8_t>(c->flags), nnode, c->n_nblk, x, P<double>(c->r),
+               pa, pb);
+    MPL_LAUNCH(c, k_reduce<RED_FINIT>, 1, 1024, pa, nwg, pb, nwg, pb, 0, s, 0);
+  }
   MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
   mpl_status st = precondition((const T*)nullptr);
   const int check = std::max(1, c->opts.pcg_check_every);
@@ -2767,8 +2836,8 @@ mpl_status mpl_stage_pcg(mpl_ctx* c, const double* b, double* x, int* iters, dou
   };
   const std::function<mpl_status(int)>* h = online ? &hook : nullptr;
   if (c->opts.precond == MPL_PRECOND_LEARNED) {
-    if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel, h);
-    return pcg_learned<double>(c, b, x, iters, rel, h);
+    if (c->tangent_precision == MPL_F32) return pcg_learned<float>(c, b, x, iters, rel, h, x0);
+    return pcg_learned<double>(c, b, x, iters, rel, h, x0);
   }
   if (c->opts.precond == MPL_PRECOND_MULTIGRID) return mpl_stage_pcg_mg(c, b, x, iters, rel, x0);
   // (a warm start applies to the single-reduction Jacobi loop)

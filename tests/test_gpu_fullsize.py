@@ -118,6 +118,51 @@ def test_energy_gradient_and_hv_full_size(full):
     del A, B, Bo
 
 
+def test_multigrid_full_size(full):
+    """The multigrid V-cycle on the 128^3 workload at full size (FP32, the
+    bench's launch configuration: 4 levels, 2 sweeps per side): level 1's
+    masses, fixed components and tangents, every level's damping, one cycle
+    on a random residual against the oracle's, and the multigrid-PCG solution
+    of the first Newton system against the oracle's product."""
+    from oracle import multigrid as MG
+    from paper_2602_07853_amd import mpmlite
+    sc, ref, ctx, _ = full
+    if not sc.name.startswith("config3"):
+        pytest.skip("the multigrid leg runs on the 128^3 workload")
+    v = ref["vhat"]
+    ctx.set_opts(precond=mpmlite.PRECOND_MULTIGRID, mg_smooth=2, mg_coarse_sweeps=4, pcg_rtol=1e-6)
+    ctx.build_tangent(torch.tensor(v, device="cuda"), 0)
+    A, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
+    levels = MG.hierarchy(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, max_levels=4)
+    print(f"[fullsize] multigrid levels {[lv.grid.n for lv in levels]}", flush=True)
+    lv = levels[1]
+    assert rel(host(ctx.mg_export(1, "mass")), lv.mi) <= 1e-14
+    fixed = host(ctx.mg_export(1, "fixed")).astype(np.uint8)
+    assert np.array_equal(fixed[lv.mi > 0], lv.fixed[lv.mi > 0])
+    e = rel(host(ctx.mg_export(1, "abar")), lv.A)
+    print(f"[fullsize] level-1 tangent rel err {e:.2e}", flush=True)
+    assert e <= 1e-5
+    fr = levels[0].free
+    r = np.random.default_rng(9).normal(size=fr.shape) * fr
+    z, nlev, omega = ctx.mg_apply(torch.tensor(r, device="cuda"))
+    assert nlev == len(levels)
+    assert np.allclose(omega, [l.omega for l in levels], rtol=1e-4, atol=0)
+    e = rel(host(z), MG.vcycle(levels, r, nu=2, nu_coarse=4))
+    print(f"[fullsize] V-cycle rel err {e:.2e}, omega {omega}", flush=True)
+    assert e <= 1e-4
+    _, go, _ = O.energy_grad(ref["grid"], ref["mats"], sc.dt, ref["mi"], ref["vhat"], ref["fixed"],
+                             ref["Vck"], ref["S"], v)
+    b = np.where(fr, -go, 0.0)
+    x, iters, relres = ctx.pcg(torch.tensor(b, device="cuda"))
+    res = b - O.hv(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, host(x))
+    e = np.linalg.norm(res) / np.linalg.norm(b)
+    print(f"[fullsize] multigrid PCG {iters} iterations, residual {relres:.2e} (oracle product {e:.2e})",
+          flush=True)
+    assert relres <= 1e-6 and e <= 2e-5
+    ctx.set_opts(precond=mpmlite.PRECOND_JACOBI)
+    del A, levels
+
+
 def test_load_full_size(full):
     sc, ref, ctx, parts = full
     rng = np.random.default_rng(8)

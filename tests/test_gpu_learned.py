@@ -130,6 +130,39 @@ def test_zero_weights_flexible_cg_matches_jacobi_iterations():
     assert abs(its[LEARNED]["pcg_iters"] - its[0]["pcg_iters"]) <= max(2, its[0]["pcg_iters"] // 20)
 
 
+def test_zero_weights_warm_started_steps_match_jacobi():
+    """With the CG warm start on, the flexible CG starts from the same x0 as
+    the Jacobi CG (r = b - H x0, tolerance still relative to |b|): with zero
+    weights (z = Dinv r) three steps under a moving plate reach the Jacobi
+    steps' particles with about the same CG iterations."""
+    from paper_2602_07853_amd import mpmlite
+    sc = scenes.small_block(n=12, lo=3, hi=9, model=scenes.FIXED_COROTATED, E=7e6, strain=0.0,
+                            plastic=scenes.PLASTIC_VON_MISES, yield_stress=2e3, seed=44,
+                            vel_std=0.05, gravity=(0.0, 0.0, 0.0))
+    sc.bcs.append(dict(kind=scenes.BC_MOVING_BOX, lo=(-1.0, 9 * sc.dx, -1.0), hi=(2.0, 2.0, 2.0),
+                       velocity=(0.0, -0.5, 0.0)))
+    res = {}
+    for precond in (0, LEARNED):
+        ctx = gpu_context(sc, 1, newton_rtol=1e-12, pcg_rtol=1e-10, warm_start=4, precond=precond)
+        if precond == LEARNED:
+            ctx.precond_set_weights(np.zeros(ctx.precond_param_count(), np.float32))
+        dp = mpmlite.particles_to_device(sc.particles)
+        its, fbs = [], []
+        for k in range(3):
+            st = ctx.step(dp, dp, sc.dt, sc.gravity, sc.bcs, k * sc.dt)
+            its.append(st["pcg_iters"])
+            fbs.append(st["fallbacks"])
+        res[precond] = ({key: host(v) for key, v in dp.items()}, its, fbs)
+        print(f"[learned] warm-started steps precond {precond}: CG {its} fallbacks {fbs}", flush=True)
+    (p0, i0, _), (p1, i1, f1) = res[0], res[LEARNED]
+    assert sum(f1) == 0
+    for key in ("x", "v", "F"):
+        assert rel(p1[key], p0[key]) <= 1e-10, key
+    # later steps start warm: the counts stay close to Jacobi's
+    for a, b in zip(i1[1:], i0[1:]):
+        assert abs(a - b) <= max(3, b // 10)
+
+
 def test_collect_pairs_and_train():
     """Pairs recorded during Newton solves satisfy their definition, and
     training on them lowers the loss."""

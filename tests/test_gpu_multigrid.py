@@ -6,10 +6,10 @@ Bars: coarse masses and fixed components exactly as the oracle's
 (restriction of FP64 masses, so within rounding); coarse tangents and
 diagonals within 1e-12 from the FP64 tangent and 1e-5 from the FP32 one
 (which rounds every entry once and, with one material, stores the
-factored form, 2e-6 per cell); one V-cycle within 1e-10 in FP64 and 1e-4
-in FP32, where it chains about fifteen FP32 products and sweeps; the
-damping of every level within 1e-9 (FP64) and 1e-4 (FP32) of the
-oracle's power iteration; solutions within 1e-10 of the oracle's
+factored form, 2e-6 per cell); one V-cycle within 1e-10 in FP64 and 1e-6
+in FP32, where it chains about fifteen FP32 products and sweeps (measured
+1.6e-15 and 9e-8); the damping of every level within 1e-9 (FP64) and 1e-6
+(FP32) of the oracle's power iteration; solutions within 1e-10 of the oracle's
 minimiser, as for Jacobi."""
 import numpy as np
 import pytest
@@ -111,11 +111,11 @@ def test_vcycle_matches_oracle(name, precision):
         z, nlev, omega = ctx.mg_apply(torch.tensor(r, device="cuda"))
         assert nlev == len(levels)
         om_ref = [lv.omega for lv in levels]
-        assert np.allclose(omega, om_ref, rtol=1e-9 if precision == 1 else 1e-4, atol=0)
+        assert np.allclose(omega, om_ref, rtol=1e-9 if precision == 1 else 1e-6, atol=0)
         z_ref = MG.vcycle(levels, r, nu=NU, nu_coarse=NU_COARSE)
         e = rel(host(z), z_ref)
         print(f"  cycle {k}: levels {nlev} omega {omega} rel err {e:.2e}", flush=True)
-        assert e <= (1e-10 if precision == 1 else 1e-4)
+        assert e <= (1e-10 if precision == 1 else 1e-6)
         assert np.all(host(z)[~fr] == 0.0)
 
 

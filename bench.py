@@ -487,7 +487,9 @@ def precond_leg(ctx, sc, args, plain_steps_per_s, plain_counts, traj, precond, l
     import torch
     from paper_2602_07853_amd import mpmlite
     parts = mpmlite.particles_to_device(sc.particles)
-    ctx.set_opts(time_kernels=0, precond=precond, **(extra_opts or {}))
+    # the leg's CG starts build their history from its own steps, as the main run's did
+    ctx.set_opts(warm_start=0)
+    ctx.set_opts(time_kernels=0, precond=precond, warm_start=args.warm_start, **(extra_opts or {}))
     t = 0.0
     for k in range(untimed):
         ctx.step(parts, parts, sc.dt, sc.gravity, sc.bcs, t)
@@ -540,7 +542,9 @@ def learned_leg(ctx, sc, parts, args, plain_steps_per_s, plain_counts, traj):
     import torch
     from paper_2602_07853_amd import precond_train
     ctx.precond_set_weights(precond_train.init_weights(0))
-    ctx.set_opts(time_kernels=0, precond=0)
+    # the leg's CG starts build their history from its own steps, as the main run's did
+    ctx.set_opts(warm_start=0)
+    ctx.set_opts(time_kernels=0, precond=0, warm_start=args.warm_start)
     ctx.precond_online(64, 1, 1e-3)
     t = 0.0
     for k in range(args.learned_train_steps):

@@ -267,7 +267,8 @@ mpl_status mpl_create_with_allocator(const mpl_grid* grid, const mpl_material* m
                                      const mpl_allocator* allocator, mpl_ctx** out);
 void mpl_destroy(mpl_ctx* ctx);
 const char* mpl_last_error(const mpl_ctx* ctx);
-/* Replace the solver options (e.g. tolerances) of an existing context. */
+/* Replace the solver options (e.g. tolerances) of an existing context.  A
+ * change of warm_start empties the CG start histories of the earlier solves. */
 mpl_status mpl_set_opts(mpl_ctx* ctx, const mpl_solver_opts* opts);
 
 /* Alg. 1: one implicit time step.  Unload (Alg. 2), Dirichlet sets and

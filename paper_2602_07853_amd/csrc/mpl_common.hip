@@ -446,7 +446,12 @@ const char* mpl_last_error(const mpl_ctx* c) { return c ? c->last_error.c_str() 
 
 mpl_status mpl_set_opts(mpl_ctx* c, const mpl_solver_opts* o) {
   if (!c || !o) return MPL_ERR_INVALID_ARG;
-  return check_opts(c, o);
+  const int warm_before = c->opts.warm_start;
+  MPL_TRY(check_opts(c, o));
+  // a change of warm-start mode starts the CG start histories afresh
+  if (c->opts.warm_start != warm_before)
+    for (int j = 0; j < mpl_ctx::kWarm; ++j) c->wcount[j] = c->whead[j] = 0;
+  return MPL_OK;
 }
 
 }  // extern "C"

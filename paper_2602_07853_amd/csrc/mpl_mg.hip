@@ -923,6 +923,12 @@ mpl_status estimate_lambdas(mpl_ctx* c, int iters) {
   MPL_HIP(c, hipStreamSynchronize(c->stream));
   for (int l = 0; l < M.nlev; ++l) {
     const double lam = h[4 * l + 1];
+    // exactly 0: the level has no free DOF (its start vector is 0), so its
+    // sweeps have nothing to do; otherwise A is positive definite on it
+    if (lam == 0.0) {
+      M.lev[l].lambda = M.lev[l].omega = 0.0;
+      continue;
+    }
     if (!(lam > 0.0) || !std::isfinite(lam))
       return mpl_fail(c, MPL_ERR_NONFINITE, "multigrid: power iteration gave no positive eigenvalue");
     M.lev[l].lambda = lam;

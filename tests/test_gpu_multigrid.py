@@ -202,3 +202,49 @@ def test_steps_with_multigrid_match_jacobi_steps():
     print(f"[multigrid] steps: jacobi CG {itj}, multigrid CG {itm}", flush=True)
     for key in ("x", "v", "F"):
         assert rel(pm[key], pj[key]) <= (1e-12 if key == "x" else 1e-6)
+
+
+@pytest.mark.parametrize("case", ["one_level", "two_levels"])
+def test_level_counts_match_oracle(case):
+    """A 4^3-cell grid has no coarser level (the cycle is the coarsest
+    level's sweeps alone); mg_levels = 2 stops the 16^3 hierarchy after one
+    coarsening.  Both against the oracle's cycle, FP64."""
+    if case == "one_level":
+        sc = scenes.small_block(n=4, lo=1, hi=3, strain=0.05, model=scenes.FIXED_COROTATED, E=1e6, seed=53)
+        opts, max_levels = {}, 4
+    else:
+        sc = SCENES["stiff_block16"]
+        opts, max_levels = dict(mg_levels=2), 2
+    ref, v = state_at(sc)
+    A, _ = O.tangent(ref["grid"], ref["mats"], sc.dt, ref["Vck"], ref["S"], v, project=True)
+    levels = MG.hierarchy(ref["grid"], ref["mc"], ref["mi"], ref["fixed"], A, max_levels=max_levels)
+    ctx = unloaded(sc, 1, **opts)
+    ctx.build_tangent(torch.tensor(v, device="cuda"), 1)
+    fr = levels[0].free
+    assert fr.any()
+    r = np.random.default_rng(65).normal(size=fr.shape) * fr
+    z, nlev, omega = ctx.mg_apply(torch.tensor(r, device="cuda"))
+    print(f"[multigrid] {case}: levels {nlev} omega {omega}", flush=True)
+    assert nlev == len(levels) == (1 if case == "one_level" else 2)
+    assert rel(host(z), MG.vcycle(levels, r, nu=NU, nu_coarse=NU_COARSE)) <= 1e-10
+
+
+def test_multigrid_entry_point_errors():
+    sc = SCENES["fcr_two_materials"]
+    ctx = unloaded(sc, 1)
+    nn = (sc.n + 1) ** 3
+    r = torch.zeros((nn, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError, match="STATE"):
+        ctx.mg_apply(r)                      # no tangent yet
+    ref = oracle_state(sc)
+    ctx.build_tangent(torch.tensor(ref["vhat"], device="cuda"), 1)
+    z, nlev, _ = ctx.mg_apply(r)             # a zero residual gives a zero correction
+    assert nlev == 2 and float(z.abs().max()) == 0.0
+    for level in (0, nlev):
+        with pytest.raises(RuntimeError, match="INVALID_ARG"):
+            ctx.mg_export(level, "mass")
+    good = dict(mg_levels=0, mg_omega=0.0, mg_smooth=NU)
+    for bad in (dict(mg_levels=1), dict(mg_levels=7), dict(mg_omega=2.0), dict(mg_smooth=-1)):
+        with pytest.raises(RuntimeError, match="INVALID_ARG"):
+            ctx.set_opts(**bad)
+        ctx.set_opts(**good)

@@ -18,10 +18,21 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdint.h>
 
 #define MPL_DEV __host__ __device__ __forceinline__
 
 namespace mpl {
+
+// SplitMix64 (Steele, Lea and Flood 2014) of counter q: the state
+// (q + 1) * golden gamma through the published finaliser (the multigrid
+// power iterations draw their start signs from it).
+MPL_DEV uint64_t splitmix64(uint64_t q) {
+  uint64_t z = (q + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
 
 enum { NEOHOOKEAN = 0, FIXED_COROTATED = 1, HENCKY = 2, WATER = 3 };
 enum { PLASTIC_NONE = 0, PLASTIC_VON_MISES = 1, PLASTIC_DRUCKER_PRAGER = 2 };

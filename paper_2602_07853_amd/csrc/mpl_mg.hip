@@ -71,15 +71,6 @@ struct GeoDev {
   const uint8_t* flags;
 };
 
-// SplitMix64 (Steele, Lea and Flood 2014) of counter q: the state
-// (q + 1) * golden gamma through the published finaliser.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t q) {
-  uint64_t z = (q + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // compact node slot of level node (x, y, z), -1 when outside the level or in
 // an inactive node block
 __device__ __forceinline__ int64_t node_slot(const GeoDev& g, int x, int y, int z) {

@@ -1,7 +1,9 @@
 """Host-side checks of device math helpers compiled for the CPU from the same
 header the kernels use: the symmetric 3x3 inverse behind the block-Jacobi
 preconditioner (inverse within 1e-12 of NumPy's for SPD blocks; indefinite,
-singular and non-finite blocks rejected)."""
+singular and non-finite blocks rejected), and the SplitMix64 generator of the
+multigrid power iterations (bit-exact against the oracle's, whose first
+outputs are pinned to the generator's published ones)."""
 import os
 import shutil
 import subprocess
@@ -63,3 +65,18 @@ def test_sym3_inverse_rejects_non_spd(exe):
     ok, inv = run(exe, blocks)
     assert np.all(ok == 0)
     assert np.all(inv == 0.0)
+
+
+def test_splitmix64_matches_oracle(tmp_path):
+    if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
+        pytest.skip("hipcc not found")
+    from oracle import multigrid as MG
+    out = str(tmp_path / "sm64")
+    subprocess.run([HIPCC, "-O2", "-std=c++17", os.path.join(HERE, "host", "splitmix64_check.cpp"), "-o", out],
+                   check=True, capture_output=True)
+    q = np.concatenate([np.arange(64, dtype=np.uint64),
+                        np.random.default_rng(4).integers(0, 2 ** 40, 200, dtype=np.uint64)])
+    res = subprocess.run([out], input="\n".join(str(int(v)) for v in q) + "\n", capture_output=True,
+                         text=True, check=True)
+    got = [int(line, 16) for line in res.stdout.split()]
+    assert got == [int(v) for v in MG.splitmix64(q)]

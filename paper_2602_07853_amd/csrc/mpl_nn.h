@@ -14,6 +14,7 @@
 struct NNSampleStore;
 struct NNState {
   DevBuf params, grad, adam_m, adam_v, wsw, act, gact, wpart, lpart, tmp;
+  DevBuf csplit;  // FP32 partial sums of 3x3x3 layers split over input-channel chunks
   DevBuf dref;  // device scalar: mean diagonal over free nodes
   NNSampleStore* store = nullptr;
   // device flag: when nonzero the forward kernels return at once (set by the

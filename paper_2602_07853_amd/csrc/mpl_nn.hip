@@ -135,7 +135,11 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x, in
 // channels of the chunk (14 steps per chunk, the last one half empty), and
 // each B operand read from LDS feeds the CT output-channel tiles.  The
 // workgroups stride over the (tile, chunk) items, and the global loads of the
-// next item are issued before the MFMAs of the current one.
+// next item are issued before the MFMAs of the current one.  On small grids
+// the input-channel chunks are split over blockIdx.z: split z sums chunks
+// [z nchunk / nsplit, (z + 1) nchunk / nsplit) and stores its FP32 partial
+// sums to part[z][voxel][channel]; k_conv3_split_reduce then adds the splits
+// in order and applies bias, accumulation and ReLU.
 // Wsw: [chunk][kstep 0..13][CT][64 lanes][8] (swizzle modes 3 and 4).
 namespace lds3 {
 constexpr int HX = 6, HY = 6, HZ = 18, NV = HX * HY * HZ;
@@ -147,7 +151,8 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
                                                    int Ci, const uint16_t* __restrict__ Wsw, int CTT,
                                                    const float* __restrict__ bias,
                                                    uint16_t* __restrict__ y, int ldy, int relu,
-                                                   int accum, const int32_t* __restrict__ skip) {
+                                                   int accum, const int32_t* __restrict__ skip,
+                                                   float* __restrict__ part) {
   // blockIdx.y selects output channels [16 CT y, 16 CT (y + 1)) of the CTT*16
   using namespace lds3;
   if (skip && *skip) return;
@@ -156,7 +161,8 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
   const int nbx = (d.x + 3) >> 2, nby = (d.y + 3) >> 2, nbz = (d.z + 15) >> 4;
   const int ntiles = nbx * nby * nbz;
   const int j = lane & 15, g = lane >> 4;
-  const int nchunk = Ci >> 4;
+  const int nchunk_all = Ci >> 4, nsplit = (int)gridDim.z, zs = (int)blockIdx.z;
+  const int qbeg = zs * nchunk_all / nsplit, qend = (zs + 1) * nchunk_all / nsplit;
   const int ct0 = blockIdx.y * CT;
   uint4 pre[PER];
   auto fetch = [&](int t, int q) {
@@ -179,9 +185,9 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
   for (int st = 0; st < 4; ++st)
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[st][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int t = blockIdx.x, q = 0;
-  if (t >= ntiles) return;
-  fetch(t, 0);
+  int t = blockIdx.x, q = qbeg;
+  if (t >= ntiles || qbeg >= qend) return;
+  fetch(t, qbeg);
   while (true) {
     __syncthreads();  // every wavefront is done reading the previous item's tile
 #pragma unroll
@@ -191,8 +197,8 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
     }
     __syncthreads();
     int tn = t, qn = q + 1;
-    if (qn == nchunk) {
-      qn = 0;
+    if (qn == qend) {
+      qn = qbeg;
       tn = t + (int)gridDim.x;
     }
     if (tn < ntiles) fetch(tn, qn);
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
           acc[st][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop[c], bop, acc[st][c], 0, 0, 0);
       }
     }
-    if (q == nchunk - 1) {
+    if (q == qend - 1) {
       const int bz = t / (nbx * nby), rem = t - bz * nbx * nby;
       const int by = rem / nbx, bx = rem - by * nbx;
       const int ox = bx * 4 + w, oz = bz * 16 + j;
@@ -227,7 +233,12 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
         const int64_t v = ((int64_t)ox * d.y + oy) * d.z + oz;
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-          if (ok) {
+          if (ok && part) {
+            const int o0 = (ct0 + c) * 16 + g * 4;
+            const int64_t nv = (int64_t)d.x * d.y * d.z;
+            *reinterpret_cast<float4*>(part + ((int64_t)zs * nv + v) * (16 * CTT) + o0) =
+                make_float4(acc[st][c][0], acc[st][c][1], acc[st][c][2], acc[st][c][3]);
+          } else if (ok) {
             const int o0 = (ct0 + c) * 16 + g * 4;
             uint16_t* dst = y + v * ldy + o0;
             float r[4];
@@ -250,6 +261,40 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t* __restrict__ 
     t = tn;
     q = qn;
   }
+}
+
+// Sum of the nsplit FP32 partials of a split 3x3x3 layer in split order, then
+// bias, accumulation onto y and ReLU; 4 channels per thread.
+__global__ __launch_bounds__(256) void k_conv3_split_reduce(const float* __restrict__ part, int nsplit,
+                                                            int64_t nv, int co,
+                                                            const float* __restrict__ bias,
+                                                            uint16_t* __restrict__ y, int ldy, int relu,
+                                                            int accum, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = co >> 2;
+  if (i >= nv * q) return;
+  const int64_t v = i / q;
+  const int o0 = (int)(i - v * q) * 4;
+  float4 s = *reinterpret_cast<const float4*>(part + v * co + o0);
+  for (int z = 1; z < nsplit; ++z) {
+    const float4 a = *reinterpret_cast<const float4*>(part + ((int64_t)z * nv + v) * co + o0);
+    s.x += a.x;
+    s.y += a.y;
+    s.z += a.z;
+    s.w += a.w;
+  }
+  uint16_t* dst = y + v * ldy + o0;
+  float r[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float val = r[e] + (bias ? bias[o0 + e] : 0.f);
+    if (accum) val += bf2f(dst[e]);
+    if (relu) val = fmaxf(val, 0.f);
+    r[e] = val;
+  }
+  *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16),
+                                              (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
 }
 
 // ---------------------------------------------------------------- register-blocked 3x3x3 conv
@@ -1001,10 +1046,29 @@ static mpl_status launch_conv3_ct(mpl_ctx* c, View in, Dims3 d, const uint16_t* 
   }
   const int ny = CTT / CT;
   const int64_t ntiles = (int64_t)((d.x + 3) / 4) * ((d.y + 3) / 4) * ((d.z + 15) / 16);
-  const int nwg = (int)std::min<int64_t>(ntiles, std::max(1, resident / ny));
-  hipLaunchKernelGGL((k_conv3_lds<CT>), dim3((unsigned)nwg, ny), dim3(256), 0, c->stream, in.p,
-                     in.ld, d, Ci, wsw, CTT, bias, out.p, out.ld, relu, accum, skip);
+  // grids with fewer than 256 (tile, channel-group) items (the 17^3 level
+  // of the 136^3 box: 200) also split the input-channel chunks, each split
+  // into FP32 partials reduced after; at 34^3 (486 items) the reduction's
+  // traffic cost more than the added workgroups gained
+  const int nchunk = Ci / 16;
+  const int64_t items = std::max<int64_t>(1, ntiles * ny);
+  const int nsplit = items < 256 ? (int)std::min<int64_t>(nchunk, std::max<int64_t>(1, 2048 / items)) : 1;
+  const int nwg = (int)std::min<int64_t>(ntiles, std::max(1, resident / (ny * nsplit)));
+  float* part = nullptr;
+  const int64_t nv = (int64_t)d.x * d.y * d.z;
+  const int co = 16 * CTT;
+  if (nsplit > 1) {
+    MPL_TRY(mpl_ensure(c, nn.csplit, sizeof(float) * (size_t)nsplit * nv * co));
+    part = P<float>(nn.csplit);
+  }
+  hipLaunchKernelGGL((k_conv3_lds<CT>), dim3((unsigned)nwg, ny, nsplit), dim3(256), 0, c->stream, in.p,
+                     in.ld, d, Ci, wsw, CTT, bias, out.p, out.ld, relu, accum, skip, part);
   MPL_HIP(c, hipGetLastError());
+  if (nsplit > 1) {
+    const int64_t n = nv * (co / 4);
+    MPL_LAUNCH(c, k_conv3_split_reduce, (int)((n + 255) / 256), 256, (const float*)part, nsplit, nv, co, bias,
+               out.p, out.ld, relu, accum, skip);
+  }
   return MPL_OK;
 }
 // 3x3x3 stride-1 convolution with Ci input and Co output channels (multiples
@@ -1231,7 +1295,7 @@ void nn_destroy(mpl_ctx* c) {
   if (!c->nn) return;
   NNState& nn = *c->nn;
   DevBuf* all[] = {&nn.params, &nn.grad, &nn.adam_m, &nn.adam_v, &nn.wsw, &nn.act, &nn.gact,
-                   &nn.wpart, &nn.lpart, &nn.tmp, &nn.dref};
+                   &nn.wpart, &nn.lpart, &nn.tmp, &nn.dref, &nn.csplit};
   for (DevBuf* b : all) mpl_dev_free(c, b->p, b->bytes);
   if (nn.store) {
     DevBuf* st[] = {&nn.store->feat, &nn.store->target, &nn.store->mask};

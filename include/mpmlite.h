@@ -408,7 +408,10 @@ mpl_status mpl_export_field(mpl_ctx* ctx, int32_t field, double* dense_out);
 /* One V-cycle z = B r on dense node vectors (FP64, device; [nodes][3]) with
  * the current tangent (mpl_build_tangent first); uses the solver options'
  * mg_* fields.  *n_levels (host, may be NULL) receives the level count and
- * omega (host, MPL_MG_MAX_LEVELS entries, may be NULL) each level's damping. */
+ * omega (host, MPL_MG_MAX_LEVELS entries, may be NULL) each level's damping.
+ * Returns after the context's stream has finished the cycle.  Errors:
+ * MPL_ERR_STATE without a tangent; MPL_ERR_NONFINITE when a level's power
+ * iteration gives a negative or non-finite eigenvalue estimate. */
 mpl_status mpl_mg_apply(mpl_ctx* ctx, const double* r, double* z, int32_t* n_levels, double* omega);
 /* Dense export of a multigrid level's data (level >= 1; the hierarchy of the
  * current tangent is built first): field 0 node mass (nodes, 1), 1 fixed
@@ -416,7 +419,8 @@ mpl_status mpl_mg_apply(mpl_ctx* ctx, const double* r, double* z, int32_t* n_lev
  * coarse tangent (cells, 81: full symmetric 9x9), 3 the inverse Jacobi
  * diagonal (nodes, 3).  The level's grid has dims / 2^level cells per axis;
  * dense_out (device, FP64) holds (dims/2^l + 1)^3 node rows or (dims/2^l)^3
- * cell rows. */
+ * cell rows.  Returns after the copy; MPL_ERR_INVALID_ARG for a level outside
+ * 1 .. n_levels - 1 or an unknown field. */
 mpl_status mpl_mg_export(mpl_ctx* ctx, int32_t level, int32_t field, double* dense_out);
 
 /* ---- learned preconditioner ----

@@ -2913,23 +2913,21 @@ __global__ __launch_bounds__(64) void k_gram(const double* __restrict__ w, const
     if (k < nv && l == 0) part[(int64_t)(ng + k) * n_nblk + nb] = sum;
   }
 }
-// fixed-order sums of the nq rows of k_gram partials (one 1024-thread workgroup)
-__global__ __launch_bounds__(1024) void k_gram_reduce(const double* __restrict__ part, int n, int nq,
+// fixed-order sums of the rows of k_gram partials, one 1024-thread
+// workgroup per row (grid = number of rows)
+__global__ __launch_bounds__(1024) void k_gram_reduce(const double* __restrict__ part, int n,
                                                       double* __restrict__ out) {
   __shared__ double sh[16];
-  const int t = threadIdx.x;
-  for (int q = 0; q < nq; ++q) {
-    double v = 0.0;
-    for (int i = t; i < n; i += 1024) v += part[(int64_t)q * n + i];
-    v = wave_sum(v);
-    if ((t & 63) == 0) sh[t >> 6] = v;
-    __syncthreads();
-    if (t == 0) {
-      double r = 0.0;
-      for (int w = 0; w < 16; ++w) r += sh[w];
-      out[q] = r;
-    }
-    __syncthreads();
+  const int t = threadIdx.x, q = blockIdx.x;
+  double v = 0.0;
+  for (int i = t; i < n; i += 1024) v += part[(int64_t)q * n + i];
+  v = wave_sum(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  if (t == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 16; ++w) r += sh[w];
+    out[q] = r;
   }
 }
 // u = (T) w (block layout, 3 components)
@@ -2993,7 +2991,7 @@ static mpl_status galerkin_start(mpl_ctx* c, const DevBuf* const* hist, int nv, 
   double* sums = part + (size_t)GAL_SUMS * c->n_nblk;
   MPL_LAUNCH(c, k_gram<T>, c->n_nblk, 64, (const double*)w, (const T*)y, b, P<uint8_t>(c->flags), nnode, nv,
              c->n_nblk, part);
-  MPL_LAUNCH(c, k_gram_reduce, 1, 1024, (const double*)part, c->n_nblk, nq, sums);
+  MPL_LAUNCH(c, k_gram_reduce, nq, 1024, (const double*)part, c->n_nblk, sums);
   double h[GAL_SUMS];
   MPL_HIP(c, hipMemcpyAsync(h, sums, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream));
   MPL_HIP(c, hipStreamSynchronize(c->stream));

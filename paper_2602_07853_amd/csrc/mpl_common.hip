@@ -347,7 +347,7 @@ static mpl_status check_opts(mpl_ctx* c, const mpl_solver_opts* o) {
 
 extern "C" {
 
-const char* mpl_version(void) { return "mpmlite-mi355x 0.20 (gfx950)"; }
+const char* mpl_version(void) { return "mpmlite-mi355x 0.21 (gfx950)"; }
 
 mpl_status mpl_create(const mpl_grid* grid, const mpl_material* mats, int32_t n_mats,
                       const mpl_solver_opts* opts, void* hip_stream, mpl_ctx** out) {
@@ -418,7 +418,7 @@ void mpl_destroy(mpl_ctx* c) {
                    &c->vt, &c->dir, &c->r, &c->x, &c->p32, &c->p64, &c->q32, &c->q64, &c->z,
                    &c->D, &c->Bj, &c->Bjt, &c->Aoff, &c->partials, &c->dense_tmp32, &c->dense_tmp64, &c->scal, &c->xstar, &c->ozt, &c->ohz,
                    &c->ogr, &c->cmask, &c->ccnt, &c->coff, &c->Dt, &c->mt, &c->opieces,
-                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->p2c_halo, &c->pstage, &c->cfmt, &c->fcnt, &c->aa_tmp, &c->aa_part, &c->wtmp, &c->warm_x0, &c->gal_w,
+                   &c->cg_u, &c->cg_s, &c->cg_dx, &c->cg_red, &c->p2c_halo, &c->pstage, &c->cfmt, &c->fcnt, &c->aa_tmp, &c->aa_part, &c->wtmp, &c->warm_x0, &c->gal_w,
                    &c->gal_u, &c->gal_y,
                    &c->gal_part};
   for (DevBuf* b : all) free_buf(c, *b);

@@ -173,6 +173,7 @@ struct mpl_ctx {
   DevBuf ozt, ohz, ogr, opieces;
   // single-reduction CG: u = Dinv r and s = running H p (tangent precision)
   DevBuf cg_u, cg_s, cg_dx;
+  DevBuf cg_red;  // its two-level reduction: per-workgroup sums and a ticket counter
   // warm start: the CG solutions of Newton iteration j of the last solves
   // (dense node arrays, so that they survive the change of active blocks),
   // in a ring of kHist per Newton index: whist[j][(whead[j] - k) mod len] is

@@ -1363,51 +1363,52 @@ __global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restric
   }
 }
 
+// Scratch of the two-level CG reduction: per-workgroup sums and the ticket
+// counter (zero between launches).
+#define CG_RED_MAX 64
+struct CgRed {
+  double part[4][CG_RED_MAX];
+  unsigned ticket;
+};
+__global__ void k_cg_red_zero(CgRed* __restrict__ red) {
+  if (threadIdx.x == 0) red->ticket = 0u;
+}
+// workgroups of the two-level reduction for arrays of up to nm entries
+static int cg_red_groups(int nm) { return std::max(1, std::min(CG_RED_MAX, (nm + 255) / 256)); }
+
 // Reduction of the four partial arrays of one single-reduction CG
-// iteration (fixed order), then its scalar logic.  INIT: A = r.u, B = b.b,
-// C = u^T M u, D = u^T K u.  STEP: A = r.u, B = r.r, C, D as in INIT.
+// iteration, then its scalar logic.  INIT: A = r.u, B = b.b, C = u^T M u,
+// D = u^T K u.  STEP: A = r.u, B = r.r, C, D as in INIT.
+// Two levels in one launch of G <= CG_RED_MAX workgroups: workgroup g sums
+// a contiguous range of every array in a fixed order; the workgroup that
+// takes the last ticket (no waiting) sums the G results in workgroup order
+// and runs the scalar logic.  The order depends on the array lengths only,
+// so the sums are reproducible.
 template <bool INIT>
-__global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a,
-                                                    const double* __restrict__ b,
-                                                    const double* __restrict__ c, int n,
-                                                    const double* __restrict__ d, int nd,
-                                                    SolverScalars* __restrict__ s) {
-  __shared__ double sh[4][16];
-  const int t = threadIdx.x;
-  if (!INIT && done_flag(s)) return;
-  // the scalars the tail needs, loaded before the partial sums so that their
-  // latency overlaps the reduction instead of following the barrier
-  double s_alpha = 0.0, s_rz = 0.0, s_tol2 = 0.0;
-  int s_iters = 0;
-  if (!INIT && t == 0) {
-    s_alpha = s->alpha;
-    s_rz = s->rz;
-    s_tol2 = s->tol2;
-    s_iters = s->iters;
-  }
-  // rounds of 8 loads per array and thread, all 32 in flight at once
-  // (indices clamped into range, out-of-range values replaced by zero)
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+__global__ __launch_bounds__(256) void k_reduce_cg(const double* __restrict__ a,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ c, int n,
+                                                   const double* __restrict__ d, int nd,
+                                                   CgRed* __restrict__ red,
+                                                   SolverScalars* __restrict__ s) {
+  __shared__ double sh[4][4];
+  __shared__ int last;
+  const int t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
+  if (!INIT && done_flag(s)) return;  // every workgroup sees the same flag
   const int nm = n > nd ? n : nd;
-  for (int base = t; base < nm; base += 8192) {
-    double v[4][8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int i = base + 1024 * k;
-      const int ia = min(i, n - 1), id = min(i, nd - 1);
-      v[0][k] = (n > 0) ? a[ia] : 0.0;
-      v[1][k] = (n > 0) ? b[ia] : 0.0;
-      v[2][k] = (n > 0) ? c[ia] : 0.0;
-      v[3][k] = (nd > 0) ? d[id] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int i = base + 1024 * k;
-      acc[0] += i < n ? v[0][k] : 0.0;
-      acc[1] += i < n ? v[1][k] : 0.0;
-      acc[2] += i < n ? v[2][k] : 0.0;
-      acc[3] += i < nd ? v[3][k] : 0.0;
-    }
+  const int chunk = (nm + G - 1) / G;
+  const int lo = g * chunk, hi = min(nm, lo + chunk);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = lo + t; i < hi; i += 256) {
+    // the four loads issued together (indices clamped into range, values
+    // past an array's end replaced by zero)
+    const int ia = min(i, n - 1), id = min(i, nd - 1);
+    const double va = n > 0 ? a[ia] : 0.0, vb = n > 0 ? b[ia] : 0.0, vc = n > 0 ? c[ia] : 0.0;
+    const double vd = nd > 0 ? d[id] : 0.0;
+    acc[0] += i < n ? va : 0.0;
+    acc[1] += i < n ? vb : 0.0;
+    acc[2] += i < n ? vc : 0.0;
+    acc[3] += i < nd ? vd : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -1415,14 +1416,29 @@ __global__ __launch_bounds__(1024) void k_reduce_cg(const double* __restrict__ a
     if ((t & 63) == 0) sh[q][t >> 6] = w;
   }
   __syncthreads();
-  if (t != 0) return;
-  double A = 0.0, B = 0.0, C = 0.0, D = 0.0;
-  for (int w = 0; w < 16; ++w) {
-    A += sh[0][w];
-    B += sh[1][w];
-    C += sh[2][w];
-    D += sh[3][w];
+  if (t == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      __hip_atomic_store(&red->part[q][g], ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    // the sums above are visible device-wide before the ticket is taken
+    const unsigned prev = __hip_atomic_fetch_add(&red->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == (unsigned)(G - 1);
   }
+  __syncthreads();
+  if (!last || t >= 64) return;
+  // the last workgroup: one wave sums the G results in workgroup order
+  double v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    v[q] = t < G ? __hip_atomic_load(&red->part[q][t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+  if (t != 0) return;
+  __hip_atomic_store(&red->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next launch
+  const double A = v[0], B = v[1], C = v[2], D = v[3];
+  const double s_alpha = s->alpha, s_rz = s->rz, s_tol2 = s->tol2;
+  const int s_iters = s->iters;
   const double delta = C + D;
   if (INIT) {
     s->alpha_last = 0.0;
@@ -2434,6 +2450,12 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
     T* dx = P<T>(c->cg_dx);
     const int nflush = (int)((3 * nnode + 255) / 256);
     const int ngrp = (c->n_cblk + 3) / 4;
+    const int nred = cg_red_groups(std::max(nwg, ngrp));
+    if (!c->cg_red.p) {
+      MPL_TRY(mpl_ensure(c, c->cg_red, sizeof(CgRed)));
+      MPL_LAUNCH(c, k_cg_red_zero, 1, 64, P<CgRed>(c->cg_red));
+    }
+    CgRed* red = P<CgRed>(c->cg_red);
     // Jacobi (inverse diagonal) or block-Jacobi (inverted node blocks)
     const bool bj = c->opts.precond == MPL_PRECOND_BLOCK_JACOBI;
     if (bj && !c->bj_built) return mpl_fail(c, MPL_ERR_STATE, "block-Jacobi blocks not built with the tangent");
@@ -2452,7 +2474,7 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                  c->n_nblk, x, dx, P<double>(c->r), u, p, sv, pa, pb, pm, s);
     }
     MPL_TRY(hv_pieces<T>(c, u, true));
-    MPL_LAUNCH(c, k_reduce_cg<true>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
+    MPL_LAUNCH(c, k_reduce_cg<true>, nred, 256, pa, pb, pm, nwg, pk, ngrp, red, s);
     MPL_LAUNCH(c, k_set_tol, 1, 1, s, c->opts.pcg_rtol * c->opts.pcg_rtol);
     const int check = std::max(1, c->opts.pcg_check_every);
     auto launch_iteration = [&]() -> mpl_status {
@@ -2468,14 +2490,14 @@ static mpl_status pcg_impl(mpl_ctx* c, const double* b, double* x, int* iters, d
                  pa, pb, pm, s);
       if (e1) MPL_HIP(c, hipEventRecord(e1, c->stream));
       MPL_TRY(hv_pieces<T>(c, u, true));
-      MPL_LAUNCH(c, k_reduce_cg<false>, 1, 1024, pa, pb, pm, nwg, pk, ngrp, s);
+      MPL_LAUNCH(c, k_reduce_cg<false>, nred, 256, pa, pb, pm, nwg, pk, ngrp, red, s);
       return MPL_OK;
     };
     const void* key[24] = {x,           p,           c->r.p,          pre,
                            abar_buf<T>(c).p, c->partials.p, pieces_buf<T>(c).p, c->mt.p,
                            c->flags.p,  c->n_nbr_cell.p, c->c_nbr_node.p, c->scal.p,
                            c->cmask.p,  c->coff.p,   u,               sv,
-                           dx};
+                           dx,          c->cg_red.p};
     const int keyn[8] = {c->n_cblk, c->n_nblk, check, (int)bj, 0, 0, (int)c->tan_factored + 2 * (int)c->tan_mixed, 2};
     // a hook that reads x sees the full solution vector (flushing changes
     // the rounding of x, so it is done only for such hooks)

@@ -34,6 +34,21 @@ MPL_DEV uint64_t splitmix64(uint64_t q) {
   return z ^ (z >> 31);
 }
 
+// Two-level reduction of partial-sum arrays of up to nm entries: the number
+// of workgroups (one per 256 entries, at most gmax) and the contiguous range
+// [lo, hi) of entries that workgroup g of G sums.  The ranges of g = 0..G-1
+// cover [0, nm) in order, each entry once.
+MPL_DEV int red2_groups(int nm, int gmax) {
+  const int g = (nm + 255) / 256;
+  return g < 1 ? 1 : (g > gmax ? gmax : g);
+}
+MPL_DEV void red2_range(int g, int G, int nm, int& lo, int& hi) {
+  const int chunk = (nm + G - 1) / G;
+  const long long l = (long long)g * chunk;
+  lo = l < nm ? (int)l : nm;
+  hi = lo + chunk < nm ? lo + chunk : nm;
+}
+
 enum { NEOHOOKEAN = 0, FIXED_COROTATED = 1, HENCKY = 2, WATER = 3 };
 enum { PLASTIC_NONE = 0, PLASTIC_VON_MISES = 1, PLASTIC_DRUCKER_PRAGER = 2 };
 

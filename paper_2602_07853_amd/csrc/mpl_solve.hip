@@ -1374,7 +1374,7 @@ __global__ void k_cg_red_zero(CgRed* __restrict__ red) {
   if (threadIdx.x == 0) red->ticket = 0u;
 }
 // workgroups of the two-level reduction for arrays of up to nm entries
-static int cg_red_groups(int nm) { return std::max(1, std::min(CG_RED_MAX, (nm + 255) / 256)); }
+static int cg_red_groups(int nm) { return red2_groups(nm, CG_RED_MAX); }
 
 // Reduction of the four partial arrays of one single-reduction CG
 // iteration, then its scalar logic.  INIT: A = r.u, B = b.b, C = u^T M u,
@@ -1395,9 +1395,8 @@ __global__ __launch_bounds__(256) void k_reduce_cg(const double* __restrict__ a,
   __shared__ int last;
   const int t = threadIdx.x, g = blockIdx.x, G = gridDim.x;
   if (!INIT && done_flag(s)) return;  // every workgroup sees the same flag
-  const int nm = n > nd ? n : nd;
-  const int chunk = (nm + G - 1) / G;
-  const int lo = g * chunk, hi = min(nm, lo + chunk);
+  int lo, hi;
+  red2_range(g, G, n > nd ? n : nd, lo, hi);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = lo + t; i < hi; i += 256) {
     // the four loads issued together (indices clamped into range, values

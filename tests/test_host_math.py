@@ -1,9 +1,10 @@
 """Host-side checks of device math helpers compiled for the CPU from the same
 header the kernels use: the symmetric 3x3 inverse behind the block-Jacobi
 preconditioner (inverse within 1e-12 of NumPy's for SPD blocks; indefinite,
-singular and non-finite blocks rejected), and the SplitMix64 generator of the
+singular and non-finite blocks rejected), the SplitMix64 generator of the
 multigrid power iterations (bit-exact against the oracle's, whose first
-outputs are pinned to the generator's published ones)."""
+outputs are pinned to the generator's published ones), and the partition of
+the CG reduction's two-level sum (every entry summed once, in order)."""
 import os
 import shutil
 import subprocess
@@ -80,3 +81,28 @@ def test_splitmix64_matches_oracle(tmp_path):
                          text=True, check=True)
     got = [int(line, 16) for line in res.stdout.split()]
     assert got == [int(v) for v in MG.splitmix64(q)]
+
+
+def test_red2_ranges_cover_every_entry_once(tmp_path):
+    if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
+        pytest.skip("hipcc not found")
+    out = str(tmp_path / "red2")
+    subprocess.run([HIPCC, "-O2", "-std=c++17", os.path.join(HERE, "host", "red2_range_check.cpp"), "-o", out],
+                   check=True, capture_output=True)
+    sizes = [0, 1, 2, 255, 256, 257, 511, 4096, 4353, 13700, 16383, 16384, 16385, 16449, 65536, 100003,
+             2 ** 20 + 7]
+    res = subprocess.run([out], input="\n".join(map(str, sizes)) + "\n", capture_output=True, text=True,
+                         check=True)
+    for nm, line in zip(sizes, res.stdout.strip().splitlines()):
+        v = list(map(int, line.split()))
+        G, ranges = v[0], list(zip(v[1::2], v[2::2]))
+        assert len(ranges) == G
+        assert G == max(1, min(64, -(-nm // 256)))
+        # contiguous, in workgroup order, covering [0, nm) exactly
+        pos = 0
+        for lo, hi in ranges:
+            assert lo == min(pos, nm) and lo <= hi <= nm
+            pos = hi
+        assert pos == nm
+        if nm > 0:
+            assert max(hi - lo for lo, hi in ranges) == -(-nm // G)

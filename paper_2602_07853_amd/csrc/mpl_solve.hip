@@ -1223,8 +1223,11 @@ __global__ __launch_bounds__(256) void k_cg_init_warm(const double* __restrict__
   }
 }
 
+// The FP32 Jacobi variant is held to 80 VGPRs (six waves per SIMD instead of
+// five: more of its loads in flight, no spill); the others keep the
+// compiler's choice, which a cap would spill.
 template <class T, bool BJ>
-__global__ __launch_bounds__(256) void k_cg_step(T* __restrict__ u, T* __restrict__ p, T* __restrict__ sv,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BJ || sizeof(T) == 8) ? 1 : 6))) void k_cg_step(T* __restrict__ u, T* __restrict__ p, T* __restrict__ sv,
                                                  const T* __restrict__ Hown, const T* __restrict__ Hhalo,
                                                  const int* __restrict__ n_nbr_cell, int64_t ncell,
                                                  const T* __restrict__ mi, const T* __restrict__ Dinv,

@@ -1238,7 +1238,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BJ || size
                                                  double* __restrict__ pmu,
                                                  const SolverScalars* __restrict__ s) {
   if (done_flag(s)) return;
-  __shared__ double sh[4];
+  __shared__ double sh3[3][4];
   const int nb = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   const double alpha = s->alpha, beta = s->beta, alpha_last = s->alpha_last;
   const int it = s->iters;
@@ -1356,13 +1356,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BJ || size
       }
     }
   }
-  g = block4_sum(g, sh);
-  rr = block4_sum(rr, sh);
-  mu = block4_sum(mu, sh);
+  // the three workgroup sums behind one barrier (same order as a
+  // workgroup sum of each: waves paired (0+1) + (2+3))
+  g = wave_sum(g);
+  rr = wave_sum(rr);
+  mu = wave_sum(mu);
+  if ((threadIdx.x & 63) == 0) {
+    sh3[0][threadIdx.x >> 6] = g;
+    sh3[1][threadIdx.x >> 6] = rr;
+    sh3[2][threadIdx.x >> 6] = mu;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    pg[blockIdx.x] = g;
-    prr[blockIdx.x] = rr;
-    pmu[blockIdx.x] = mu;
+    pg[blockIdx.x] = (sh3[0][0] + sh3[0][1]) + (sh3[0][2] + sh3[0][3]);
+    prr[blockIdx.x] = (sh3[1][0] + sh3[1][1]) + (sh3[1][2] + sh3[1][3]);
+    pmu[blockIdx.x] = (sh3[2][0] + sh3[2][1]) + (sh3[2][2] + sh3[2][3]);
   }
 }
 
